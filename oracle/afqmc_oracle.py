@@ -1,0 +1,376 @@
+"""Plain FP64 / complex128 CPU oracle of one AFQMC step with a sampled trial.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the product path never does.  It
+shares no code with the HIP library: the only common import is the seeded
+input generator (afqmc_inputs), which holds none of the method's arithmetic.
+
+Each function follows the paper's statement of the method, in its order and
+notation, with numpy's matmul / slogdet / solve / eigh / qr as library steps:
+
+* Sec. II.A, Eqs. H and H_MC: H = sum_s h1 + 1/2 sum_g L_g^2 (the Monte-Carlo
+  form taken as the definition, not normal-ordered).
+* Sec. II.A, Eqs. HS-V and HS: B(x) = e^{-tau T/2} exp(i sqrt(tau) sum_g x_g L_g)
+  e^{-tau T/2}; the factor i is the sqrt(-tau) of Eq. HS-V with real L.
+* Sec. II.B, Eqs. walker_prop, importance_function, shift1 and
+  importance_function_CP: force-bias shift, hybrid weight, phaseless cosine.
+* Sec. II.C, Eq. trial_decomp; Sec. III.A, Eq. Metropolis_sampled_trial: the
+  sampled trial determinant Phi_T(y) = exp(c sum_k y_k A_k) Phi_0.
+* Sec. III.A, Eqs. ratio-update-phi, sign-path, local-obs: overlap-ratio and
+  local-observable estimators over the P tethered paths.
+* Sec. III.A, Eqs. AFQMC_Metro_correction, AFQMC_Metro_constraint_cos and
+  App. B (propagation pseudo-code): Metropolis update of the paths and the
+  hand-off cosine projection.
+
+Array conventions (C order): phi [nw, 2, M, N] complex, y [nw, P, K] float,
+phiT [nw, P, M, N] float, logov [nw, P] complex (log-overlap, summed over the
+two spins; -inf for a singular overlap), theta [nw, P, 2, M, N] complex.
+
+Readings of points the paper leaves open (each is listed in the design notes):
+the energy shift factor exp(tau E_T) in the weight; a fixed-order Taylor
+series for exp(V) in the walker propagator (both sides compute that same
+map); exact exp(U) by eigendecomposition for the trial determinant; the
+frozen normaliser 1/|O_p(phi)| of Eq. Metropolis_sampled_trial taken at the
+pre-move walker; only the phase of the hand-off ratio R applied to W.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import philox
+
+WEIGHT_SEPARATE = 0   # App. B: cosine of Delta-theta, then cosine of Delta-theta_T
+WEIGHT_COMBINED = 1   # one cosine of the summed angle (Sec. III.A, after Eq. AFQMC_Metro_constraint_cos)
+WEIGHT_HALFPLANE = 2  # hand-off by the half-plane rule instead of the cosine
+
+PROPOSAL_PRIOR = 0    # independence sampler from p_T (App. B); Ising: single-spin-flip sweep
+PROPOSAL_RW = 1       # Gaussian random walk y' = y + s eta
+
+
+# ---------------------------------------------------------------------------
+# Derived one-body matrices
+
+def h1_eff(sys) -> np.ndarray:
+    """h1' = h1 + 1/2 sum_g L_g L_g: the one-body part of <1/2 sum_g L_g^2>."""
+    return sys.h1 + 0.5 * np.einsum("gij,gjk->ik", sys.L, sys.L)
+
+
+def exp_sym(Msym: np.ndarray) -> np.ndarray:
+    """exp of a real symmetric matrix by eigendecomposition."""
+    lam, Q = np.linalg.eigh(Msym)
+    return (Q * np.exp(lam)) @ Q.T
+
+
+def half_kinetic(sys, dtau: float) -> np.ndarray:
+    """e^{-tau h1 / 2}: the split one-body factor of B(x) (Eq. HS)."""
+    return exp_sym(-0.5 * dtau * sys.h1)
+
+
+# ---------------------------------------------------------------------------
+# Sampled trial determinant (Eq. trial_decomp / Metropolis_sampled_trial)
+
+def trial_det(sys, y: np.ndarray) -> np.ndarray:
+    """Phi_T(y) = exp(c sum_k y_k A_k) Phi_0 for y [..., K] -> [..., M, N] float."""
+    y = np.asarray(y, dtype=np.float64)
+    U = sys.coupling * np.einsum("...k,kij->...ij", y, sys.A)
+    lam, Q = np.linalg.eigh(U)
+    QtPhi = np.swapaxes(Q, -1, -2) @ sys.phi0
+    return (Q * np.exp(lam)[..., None, :]) @ QtPhi
+
+
+# ---------------------------------------------------------------------------
+# Overlap, log-overlap and Green's function (Eqs. ratio-update-phi, sign-path)
+
+def overlap_matrices(phiT: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """A^s = Phi_T^T Phi^s: phiT [nw,P,M,N], phi [nw,2,M,N] -> [nw,P,2,N,N]."""
+    return np.einsum("wpmi,wsmj->wpsij", phiT, phi)
+
+
+def log_overlap(phiT: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """l_p = sum_s log det(Phi_T(y_p)^T Phi^s) [nw, P] complex; -inf if singular."""
+    sign, logabs = np.linalg.slogdet(overlap_matrices(phiT, phi))
+    sing = np.any(sign == 0, axis=-1)
+    ell = logabs.sum(-1) + 1j * np.angle(sign).sum(-1)
+    ell = np.where(sing, complex(-np.inf, 0.0), ell)
+    return ell
+
+
+def green(phiT: np.ndarray, phi: np.ndarray):
+    """(l, Theta) with Theta^s = Phi^s (Phi_T^T Phi^s)^{-1}; Theta = 0 if singular."""
+    A = overlap_matrices(phiT, phi)
+    ell = log_overlap(phiT, phi)
+    nw, P = ell.shape
+    M, N = phi.shape[-2:]
+    theta = np.zeros((nw, P, 2, M, N), dtype=np.complex128)
+    for w in range(nw):
+        for p in range(P):
+            if not np.isfinite(ell[w, p].real):
+                continue
+            for s in range(2):
+                # Theta A = Phi  <=>  A^T Theta^T = Phi^T
+                theta[w, p, s] = np.linalg.solve(A[w, p, s].T, phi[w, s].T).T
+    return ell, theta
+
+
+def phases(ell: np.ndarray) -> np.ndarray:
+    """S_p = O_p / |O_p| (Eq. sign-path); 0 for a singular sample."""
+    ok = np.isfinite(ell.real)
+    return np.where(ok, np.exp(1j * np.where(ok, ell.imag, 0.0)), 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Per-sample force bias and local energy (Wick's theorem on one determinant pair)
+
+def sample_contraction(sys, phiT: np.ndarray, theta: np.ndarray, ell: np.ndarray,
+                       h1p: Optional[np.ndarray] = None):
+    """Per-sample vb [nw,P,G] and E_p [nw,P] complex.
+
+    f_g^s = Phi_T^T L_g Theta^s;  vb_g = sum_s tr f_g^s = <L_g> (numerator of
+    Eq. shift1 for one path);  E_p = sum_s tr(Phi_T^T h1' Theta^s)
+    + 1/2 sum_g [ vb_g^2 - sum_s tr(f_g^s f_g^s) ].
+    """
+    if h1p is None:
+        h1p = h1_eff(sys)
+    nw, P = ell.shape
+    G = sys.n_chol
+    vb = np.zeros((nw, P, G), dtype=np.complex128)
+    ep = np.zeros((nw, P), dtype=np.complex128)
+    for w in range(nw):
+        ok = np.isfinite(ell[w].real)
+        Y = np.einsum("pmi,gmn->pgin", phiT[w], sys.L)          # Phi_T^T L_g  [P,G,N,M]
+        f = np.einsum("pgim,psmj->pgsij", Y, theta[w])           # [P,G,2,N,N]
+        trf = np.einsum("pgsii->pgs", f)
+        vbw = trf.sum(-1)
+        ex = np.einsum("pgsij,pgsji->p", f, f)
+        e1 = np.einsum("pmi,mn,psni->p", phiT[w], h1p, theta[w])
+        epw = e1 + 0.5 * (vbw ** 2).sum(-1) - 0.5 * ex
+        vb[w] = np.where(ok[:, None], vbw, 0.0)
+        ep[w] = np.where(ok, epw, 0.0)
+    return vb, ep
+
+
+def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: float):
+    """Eq. local-obs over the P paths, then Eq. shift1.
+
+    xbar_g = -i sqrt(tau) sum_p S_p vb_pg / sum_p S_p,  E_L = sum_p S_p E_p / sum_p S_p.
+    The i comes from reading Eq. HS-V's sqrt(-tau) into the propagator with
+    real L_g.  A walker whose phases sum to zero gets xbar = 0 and E_L = 0.
+    """
+    S = phases(ell)
+    den = S.sum(-1)
+    good = den != 0
+    safe = np.where(good, den, 1.0)
+    xbar = -1j * math.sqrt(dtau) * np.einsum("wp,wpg->wg", S, vb) / safe[:, None]
+    eloc = np.einsum("wp,wp->w", S, ep) / safe
+    xbar = np.where(good[:, None], xbar, 0.0)
+    eloc = np.where(good, eloc, 0.0)
+    return xbar, eloc
+
+
+def local_energy(sys, phi, phiT, dtau):
+    """(E_L [nw], xbar [nw,G], E_p [nw,P], vb [nw,P,G], logov [nw,P])."""
+    ell, theta = green(phiT, phi)
+    vb, ep = sample_contraction(sys, phiT, theta, ell)
+    xbar, eloc = walker_estimates(vb, ep, ell, dtau)
+    return eloc, xbar, ep, vb, ell
+
+
+# ---------------------------------------------------------------------------
+# Propagation (Eqs. HS, walker_prop) and hybrid phaseless weight
+
+def taylor_apply(V: np.ndarray, X: np.ndarray, order: int) -> np.ndarray:
+    """sum_{j=0}^{order} V^j X / j!  (V [nw,M,M], X [nw,...,M,N])."""
+    out = X.copy()
+    term = X.copy()
+    for j in range(1, order + 1):
+        term = np.einsum("wik,w...kn->w...in", V, term) / j
+        out = out + term
+    return out
+
+
+def field_matrix(sys, xi: np.ndarray, xbar: np.ndarray, dtau: float) -> np.ndarray:
+    """V = i sqrt(tau) sum_g (xi_g - xbar_g) L_g  -> [nw, M, M] complex."""
+    c = xi.astype(np.complex128) - xbar
+    return 1j * math.sqrt(dtau) * np.einsum("wg,gij->wij", c, sys.L)
+
+
+def propagate_dets(sys, phi, xi, xbar, dtau, n_taylor, Eh=None):
+    """phi' = e^{-tau h1/2} T_n(V) e^{-tau h1/2} phi (both spins)."""
+    if Eh is None:
+        Eh = half_kinetic(sys, dtau)
+    V = field_matrix(sys, xi, xbar, dtau)
+    X = np.einsum("ij,wsjn->wsin", Eh, phi)
+    X = taylor_apply(V, X, n_taylor)
+    return np.einsum("ij,wsjn->wsin", Eh, X)
+
+
+def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
+              e_shift=0.0, weight_mode=WEIGHT_SEPARATE, Eh=None):
+    """One walker move with the hybrid phaseless weight (App. B, step 1).
+
+    Returns (phi', w', ref, logov_new) where logov_new is l_p(phi') at the old
+    paths, and ref is the phase reference the hand-off uses: the numerator
+    num_r = sum_p exp(l'_p - Re l_p) of Eq. ratio-update-phi (separate and
+    half-plane modes) or sum_p S_p (combined-angle mode).
+    """
+    phin = propagate_dets(sys, phi, xi, xbar, dtau, n_taylor, Eh)
+    elln = log_overlap(phiT, phin)
+    ok = np.isfinite(logov.real)
+    okn = np.isfinite(elln.real) & ok
+    diff = np.where(okn, elln, 0.0) - np.where(okn, logov.real, 0.0)
+    num_r = np.where(okn, np.exp(diff), 0.0).sum(-1)
+    S = phases(logov)
+    den = S.sum(-1)
+    alive = (den != 0) & (num_r != 0)
+    r = np.where(alive, num_r / np.where(alive, den, 1.0), 1.0)
+    log_i = (xi * xbar - 0.5 * xbar * xbar).sum(-1) + np.log(r)
+    mag = np.exp(log_i.real + dtau * e_shift)
+    if weight_mode == WEIGHT_COMBINED:
+        wn = w * mag
+        ref = den
+    else:
+        wn = w * mag * np.maximum(0.0, np.cos(np.angle(r)))
+        ref = num_r
+    wn = np.where(alive, wn, 0.0)
+    return phin, wn, ref, elln
+
+
+# ---------------------------------------------------------------------------
+# Metropolis update of the tethered paths (App. B, steps 2 and 3)
+
+def metropolis(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep,
+               proposal=PROPOSAL_PRIOR, rw_step=0.5, weight_mode=WEIGHT_SEPARATE):
+    """Move every path y_p towards P(y; phi) ~ p_T(y) |O(y; phi)| (Eq. PDF-Y).
+
+    Gaussian prior proposal: y' ~ N(0, 1), alpha = |O(y')| / |O(y)|.
+    Gaussian random walk: y' = y + s eta, alpha = |O(y')| N(y') / (|O(y)| N(y)).
+    Ising: one sweep flips y_0 .. y_{K-1} in turn, alpha = |O(y')| / |O(y)|.
+    Accept iff u < alpha.  Then the hand-off projection (Eq.
+    AFQMC_Metro_constraint_cos) with Delta-theta_T = arg sum_p S'_p - arg ref.
+    Returns (y', phiT', logov', w', n_accept [nw]).
+    """
+    y = y.copy()
+    phiT = phiT.copy()
+    logov = logov.copy()
+    nw, P, K = y.shape
+    nacc = np.zeros(nw, dtype=np.int64)
+    for s in range(n_sweep):
+        if sys.hidden_kind == 0:
+            u = philox.accept_uniforms(seed, step, nw, P, K, s)
+            for k in range(K):
+                yp = y.copy()
+                yp[:, :, k] = -yp[:, :, k]
+                phiTp = trial_det(sys, yp)
+                ellp = log_overlap(phiTp, phi)
+                acc = _accept(u[:, :, k], ellp.real - logov.real)
+                y = np.where(acc[..., None], yp, y)
+                phiT = np.where(acc[..., None, None], phiTp, phiT)
+                logov = np.where(acc, ellp, logov)
+                nacc += acc.sum(-1)
+        else:
+            eta = philox.proposal_normals(seed, step, nw, P, K, s)
+            u = philox.accept_uniforms(seed, step, nw, P, 1, s)[:, :, 0]
+            if proposal == PROPOSAL_RW:
+                yp = y + rw_step * eta
+                extra = -0.5 * (yp * yp).sum(-1) + 0.5 * (y * y).sum(-1)
+            else:
+                yp = eta
+                extra = 0.0
+            phiTp = trial_det(sys, yp)
+            ellp = log_overlap(phiTp, phi)
+            acc = _accept(u, ellp.real - logov.real + extra)
+            y = np.where(acc[..., None], yp, y)
+            phiT = np.where(acc[..., None, None], phiTp, phiT)
+            logov = np.where(acc, ellp, logov)
+            nacc += acc.sum(-1)
+    w = handoff(w, logov, ref, weight_mode)
+    return y, phiT, logov, w, nacc
+
+
+def _accept(u: np.ndarray, log_alpha: np.ndarray) -> np.ndarray:
+    """u < alpha with alpha = exp(log_alpha); nan (both singular) rejects."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        la = np.where(np.isnan(log_alpha), -np.inf, log_alpha)
+        return (la >= 0.0) | (u < np.exp(np.minimum(la, 0.0)))
+
+
+def handoff(w, logov_new, ref, weight_mode=WEIGHT_SEPARATE):
+    """W <- W max(0, cos Delta-theta_T), Delta-theta_T = arg sum S' - arg ref."""
+    Sn = phases(logov_new).sum(-1)
+    dth = np.angle(Sn) - np.angle(ref)
+    if weight_mode == WEIGHT_HALFPLANE:
+        wrapped = np.angle(np.exp(1j * dth))
+        fac = np.where(np.abs(wrapped) > 0.5 * np.pi, 0.0, 1.0)
+    else:
+        fac = np.maximum(0.0, np.cos(dth))
+    alive = (Sn != 0) & (ref != 0)
+    return np.where(alive, w * fac, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Re-orthogonalisation and estimator
+
+def reorthogonalize(phi: np.ndarray, logov: Optional[np.ndarray] = None):
+    """Phi^s = Q R with real positive diag(R); Phi^s <- Q; l_p -= sum log R_ii."""
+    nw = phi.shape[0]
+    out = np.empty_like(phi)
+    shift = np.zeros(nw)
+    for w in range(nw):
+        for s in range(2):
+            Q, R = np.linalg.qr(phi[w, s])
+            d = np.diag(R)
+            ph = d / np.abs(d)
+            out[w, s] = Q * ph[None, :]
+            shift[w] += np.log(np.abs(d)).sum()
+    if logov is None:
+        return out, None
+    return out, logov - shift[:, None]
+
+
+def estimator(w: np.ndarray, eloc: np.ndarray):
+    """(sum_k W_k Re E_L,k, sum_k W_k) with exact summation (Eq. mixed_estimator)."""
+    return (math.fsum((w * eloc.real).tolist()), math.fsum(w.tolist()))
+
+
+# ---------------------------------------------------------------------------
+# One whole step (App. B order) for trajectory tests
+
+class State:
+    def __init__(self, phi, w, y, phiT, logov):
+        self.phi, self.w, self.y, self.phiT, self.logov = phi, w, y, phiT, logov
+
+    def copy(self):
+        return State(self.phi.copy(), self.w.copy(), self.y.copy(), self.phiT.copy(),
+                     self.logov.copy())
+
+
+def init_state(sys, nw, P, seed):
+    """phi = Phi_0 for both spins, W = 1, y ~ p_T (stream INIT)."""
+    phi = np.broadcast_to(sys.phi0.astype(np.complex128), (nw, 2, sys.M, sys.N)).copy()
+    y = philox.init_hidden(seed, nw, P, sys.K, sys.hidden_kind)
+    phiT = trial_det(sys, y)
+    logov = log_overlap(phiT, phi)
+    return State(phi, np.ones(nw), y, phiT, logov)
+
+
+def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
+         e_shift=0.0, proposal=PROPOSAL_PRIOR, rw_step=0.5,
+         weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None):
+    """Measure, propagate, move the paths, re-orthogonalise.  Returns (state, record)."""
+    ell, theta = green(st.phiT, st.phi)
+    vb, ep = sample_contraction(sys, st.phiT, theta, ell, h1p)
+    xbar, eloc = walker_estimates(vb, ep, ell, dtau)
+    num, den = estimator(st.w, eloc)
+    xi = philox.field_normals(seed, i, st.phi.shape[0], sys.n_chol)
+    phin, wn, ref, elln = propagate(sys, st.phi, xi, xbar, st.phiT, ell, st.w, dtau,
+                                    n_taylor, e_shift, weight_mode, Eh)
+    y, phiT, logov, w2, nacc = metropolis(sys, phin, st.y, st.phiT, elln, ref, wn, seed, i,
+                                          n_sweep, proposal, rw_step, weight_mode)
+    if n_qr and (i + 1) % n_qr == 0:
+        phin, logov = reorthogonalize(phin, logov)
+    rec = dict(e_num=num, e_den=den, eloc=eloc, xbar=xbar, logov=ell, xi=xi,
+               w_prop=wn, ref=ref, nacc=nacc)
+    return State(phin, w2, y, phiT, logov), rec
