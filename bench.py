@@ -1,0 +1,140 @@
+#!/usr/bin/env python3
+"""Throughput of the sampled-trial AFQMC step on one MI355X.
+
+One step = green -> Cholesky contraction (force bias + local energy) ->
+estimator -> fields -> propagate (V build, Taylor, ratio, weight) ->
+Metropolis sweep of every path with hand-off -> QR every 10 steps, for the
+FP64 workload M=64, N=16 per spin, 256 Cholesky vectors, K=64 Gaussian hidden
+variables, 512 walkers x 8 paths, tau=0.005.  Inputs are synthetic (seeded
+generator, see afqmc_inputs) and resident in HBM before the timed region.
+
+Prints one JSON line.  The roofline object refers to the dominant kernel, the
+Cholesky contraction, timed with HIP events on the library's stream around
+every afqmc_local_energy call of the timed steps; cpu_baseline is the FP64
+numpy oracle on a bounded walker sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s at fixed energy error; contraction TFLOP/s vs MFMA peak"
+PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+
+
+def contraction_flops(M, N, G):
+    """Algorithmic flops of the contraction per (walker, path): the real
+    half-rotation Phi_T^T L_g (2 N M^2), its product with both spins' Theta
+    (2 x 4 M N^2) and tr(f f) (2 x 8 N^2), for each of the G vectors."""
+    return G * (2 * N * M * M + 2 * (4 * M * N * N + 8 * N * N))
+
+
+def cpu_baseline(sys_, run, seed, n_walkers=8):
+    """Time the oracle's whole step on a bounded walker sample (1 BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import afqmc_oracle as O
+    with threadpool_limits(limits=1):
+        st = O.init_state(sys_, n_walkers, run.P, seed)
+        Eh = O.half_kinetic(sys_, run.dtau)
+        h1p = O.h1_eff(sys_)
+        t0 = time.perf_counter()
+        st, _ = O.step(sys_, st, seed, 0, run.dtau, n_taylor=run.n_taylor, n_sweep=run.n_sweep,
+                       n_qr=run.n_qr, Eh=Eh, h1p=h1p)
+        dt = time.perf_counter() - t0
+    return {"value": n_walkers / dt, "unit": "walker-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_walkers} walkers x {run.P} paths, 1 whole step of the same workload "
+                      f"(numpy FP64/complex128, 1 thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on exactly one GPU (one-GPU build); --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import afqmc_inputs as ai
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    if not torch.cuda.is_available():
+        print("no GPU: the HIP path cannot run", file=sys.stderr)
+        sys.exit(1)
+    A.load_library()
+
+    sys_, run = ai.workload(1)
+    nw, P, seed = run.W, run.P, 2001
+    ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw)
+    st = D.init_walkers(ctx, sys_.phi0, nw, seed)
+    est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
+
+    e_shift = 0.0
+    for i in range(args.warmup):
+        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr)
+        if i == 0:
+            torch.cuda.synchronize()
+            e0 = est[0].cpu().numpy()
+            e_shift = float(e0[0] / e0[1])
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        i = args.warmup + k
+        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr,
+               contract_events=evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    contract_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
+    achieved = flops / (contract_ms * 1e-3) / 1e12
+    e = est.cpu().numpy()
+    energies = e[:, 0] / e[:, 1]
+    if not np.all(np.isfinite(energies)):
+        print("non-finite energy in the benchmark run", file=sys.stderr)
+        sys.exit(1)
+
+    out = {
+        "metric": METRIC,
+        "value": nw * args.steps / dt,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
+                               f"-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
+                   "walkers": nw, "paths": P, "M": sys_.M, "N": sys_.N,
+                   "n_chol": sys_.n_chol, "K": sys_.K},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "kernel": "k_contract (+ k_combine) in afqmc_local_energy",
+                     "ms_per_launch": contract_ms, "flops_per_launch": flops},
+        "energy_last": float(energies[-1]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sys_, run, seed)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * afqmc.h -- C ABI of the MI355X (gfx950) hot path of phaseless AFQMC with a
+ * stochastically sampled correlated trial wave function
+ * Psi_T = int dy p_T(y) det Phi_T(y), each walker tethered to P Metropolis
+ * paths over the hidden variables y (Sec. III.A and App. B of the paper).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Hamiltonian (Sec. II.A, Eqs. H and H_MC):  H = sum_s h1 + 1/2 sum_g L_g^2
+ * with real symmetric h1 [M][M] and L_g [M][M]; restricted closed-shell
+ * walkers with N electrons of each spin.
+ * Trial (Sec. II.C, Eq. trial_decomp, m = 1):  Phi_T(y) = exp(c sum_k y_k A_k) Phi_0
+ * with real symmetric generators A_k and hidden variables y_k either Ising
+ * (+-1, uniform prior) or Gaussian (N(0,1) prior).
+ * Propagator (Eqs. HS, walker_prop):  B(x) = e^{-tau h1/2} exp(V) e^{-tau h1/2},
+ * V = i sqrt(tau) sum_g (x_g - xbar_g) L_g, exp(V) applied as the Taylor
+ * series of fixed order n_taylor.
+ *
+ * All array arguments of the per-step calls are DEVICE pointers to
+ * contiguous row-major arrays; "complex" means interleaved (re, im) doubles:
+ *   phi    [nw][2][M][N]    complex  walker determinants (spin up, spin down)
+ *   w      [nw]             double   walker weights
+ *   y      [nw][P][K]       double   hidden variables of the P paths
+ *   phiT   [nw][P][M][N]    double   sampled trial determinants Phi_T(y_p)
+ *   logov  [nw][P]          complex  l_p = sum_s log det(Phi_T(y_p)^T phi^s)
+ *                                    (-inf + 0i marks a singular overlap)
+ *   theta  [nw][P][2][M][N] complex  Theta^s = phi^s (Phi_T^T phi^s)^{-1}
+ * The caller owns every state array and the workspace; the library owns the
+ * device copy of the system made by afqmc_create.  Calls are asynchronous on
+ * the context's stream; they validate arguments on the host and never abort.
+ * Walker k's random numbers depend only on (seed, step, k), so any nw-prefix
+ * of a batch reproduces the same walkers.
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afqmc_ctx_s* afqmc_ctx;
+
+typedef enum {
+  AFQMC_OK = 0,
+  AFQMC_E_INVALID = 1,      /* null pointer, bad enum or parameter value           */
+  AFQMC_E_SHAPE = 2,        /* sizes outside what the kernels support             */
+  AFQMC_E_DEVICE = 3,       /* a HIP runtime call failed                           */
+  AFQMC_E_NOMEM = 4,        /* device allocation in afqmc_create failed            */
+  AFQMC_E_NUMERIC = 5,      /* reserved: non-finite input detected                 */
+  AFQMC_E_UNSUPPORTED = 6,  /* valid request this build does not implement         */
+  AFQMC_E_WORKSPACE = 7     /* no workspace set, or smaller than afqmc_workspace_size */
+} afqmc_status;
+
+enum { AFQMC_HIDDEN_ISING = 0, AFQMC_HIDDEN_GAUSS = 1 };
+
+/* Weight projections (Sec. III.A after Eq. AFQMC_Metro_constraint_cos; App. B):
+ * SEPARATE: |I| max(0, cos dtheta) at the walker move, then max(0, cos dtheta_T)
+ *           at the hand-off (the pseudo-code of App. B);
+ * COMBINED: |I| at the move and one max(0, cos(dtheta + dtheta_T)) at the hand-off;
+ * HALFPLANE: cosine at the move, W = 0 if |dtheta_T| > pi/2 at the hand-off.   */
+enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPLANE = 2 };
+
+/* Metropolis proposals for the paths (Sec. III.A, leapfrog step 2):
+ * PRIOR: independent draw from p_T (App. B); for Ising y one sweep flips
+ *        y_0 .. y_{K-1} in turn.  RW: Gaussian random walk y' = y + rw_step * eta. */
+enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1 };
+
+enum { AFQMC_PREC_FP64 = 0 };
+
+typedef struct {
+  int32_t M;            /* one-particle basis size                         */
+  int32_t N;            /* electrons per spin (n_up = n_dn)                */
+  int32_t n_chol;       /* number of vectors L_g                           */
+  int32_t K;            /* hidden variables per path                       */
+  int32_t P;            /* paths tethered to each walker                   */
+  int32_t hidden_kind;  /* AFQMC_HIDDEN_*                                   */
+  double coupling;      /* c in Phi_T(y) = exp(c sum_k y_k A_k) Phi_0        */
+  const double* h1;     /* HOST [M][M], symmetric                           */
+  const double* L;      /* HOST [n_chol][M][M], each symmetric              */
+  const double* phi0;   /* HOST [M][N]                                      */
+  const double* A;      /* HOST [K][M][M], each symmetric                   */
+  double dtau;          /* time step tau                                    */
+  int32_t n_taylor;     /* Taylor order of exp(V) in the propagator (>= 1)  */
+  int32_t weight_mode;  /* AFQMC_WEIGHT_*                                    */
+  int32_t proposal;     /* AFQMC_PROPOSAL_*                                  */
+  double rw_step;       /* random-walk proposal step                        */
+  int32_t precision;    /* AFQMC_PREC_*                                      */
+} afqmc_system;
+
+/* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and
+ * e^{-tau h1/2} there, and binds the context to `stream` (a hipStream_t, NULL
+ * for the default stream).  Host arrays may be freed on return.
+ * Supported sizes: 1 <= N <= M <= 64, N <= 16, n_chol >= 1, 1 <= K <= 256,
+ * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  Synchronises `stream`. */
+afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afqmc_ctx* out);
+afqmc_status afqmc_destroy(afqmc_ctx ctx);
+/* Text of the last error on this context (static storage owned by ctx). */
+const char* afqmc_last_error(afqmc_ctx ctx);
+afqmc_status afqmc_set_stream(afqmc_ctx ctx, void* stream);
+
+/* Device scratch the per-step calls need for up to nw walkers.  The caller
+ * allocates it (>= 256-byte aligned) and hands it over; calls that overlap on
+ * one context must not share a workspace.  No per-step call allocates.      */
+afqmc_status afqmc_workspace_size(afqmc_ctx ctx, int32_t nw, size_t* bytes);
+afqmc_status afqmc_set_workspace(afqmc_ctx ctx, void* dptr, size_t bytes);
+
+/* Initial paths y ~ p_T (stream INIT of the counter layout below). */
+afqmc_status afqmc_sample_prior(afqmc_ctx ctx, int32_t nw, uint64_t seed, double* y);
+
+/* Phi_T(y_p) = exp(c sum_k y_k A_k) Phi_0 for every path (Sec. II.C, Eq.
+ * trial_decomp; Sec. III.A, Eq. Metropolis_sampled_trial).  y -> phiT. */
+afqmc_status afqmc_trial_build(afqmc_ctx ctx, int32_t nw, const double* y, double* phiT);
+
+/* l_p = sum_s log det(Phi_T(y_p)^T phi^s) with partial-pivoting LU (the
+ * overlaps O_p of Eqs. ratio-update-phi and sign-path, kept as logarithms).
+ * phi, phiT -> logov.  A zero pivot gives l_p = -inf + 0i. */
+afqmc_status afqmc_overlap(afqmc_ctx ctx, int32_t nw, const void* phi, const double* phiT,
+                           void* logov);
+
+/* As afqmc_overlap, plus Theta^s = phi^s (Phi_T^T phi^s)^{-1}, so that the
+ * one-body Green's function of path p is G^s = Theta^s Phi_T^T (Sec. III.A,
+ * Eq. local-obs needs it for every path).  Theta = 0 for a singular path. */
+afqmc_status afqmc_green(afqmc_ctx ctx, int32_t nw, const void* phi, const double* phiT,
+                         void* logov, void* theta);
+
+/* Force bias (Eq. shift1 with Eq. local-obs over the P paths):
+ *   vb_pg = sum_s tr(Phi_T^T L_g Theta^s),  S_p = exp(i Im l_p) (Eq. sign-path),
+ *   xbar_g = -i sqrt(tau) sum_p S_p vb_pg / sum_p S_p.
+ * phiT, theta, logov -> xbar [nw][n_chol] complex; vb_sample [nw][P][n_chol]
+ * complex if non-NULL.  Singular paths (l = -inf) are left out of the sums. */
+afqmc_status afqmc_force_bias(afqmc_ctx ctx, int32_t nw, const double* phiT, const void* theta,
+                              const void* logov, void* xbar, void* vb_sample);
+
+/* Local energy (Eq. local-obs of H, the mixed estimator's E_L of Eq.
+ * mixed_estimator): per path, with f_g^s = Phi_T^T L_g Theta^s,
+ *   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [(sum_s tr f_g^s)^2 - sum_s tr(f_g^s f_g^s)],
+ *   E_L = sum_p S_p E_p / sum_p S_p.
+ * phiT, theta, logov -> eloc [nw] complex; e_sample [nw][P] complex and xbar
+ * [nw][n_chol] complex (the force bias of the same contraction) if non-NULL. */
+afqmc_status afqmc_local_energy(afqmc_ctx ctx, int32_t nw, const double* phiT, const void* theta,
+                                const void* logov, void* eloc, void* e_sample, void* xbar);
+
+/* One walker move with the hybrid phaseless weight (Eqs. walker_prop,
+ * importance_function, importance_function_CP; Eq. ratio-update-phi for the
+ * overlap ratio; App. B step 1):
+ *   phi <- e^{-tau h1/2} T_n(V) e^{-tau h1/2} phi,  V = i sqrt(tau) sum_g (xi_g - xbar_g) L_g
+ *   l'_p = l_p(phi') at the unchanged paths        -> logov_new [nw][P]
+ *   num_r = sum_p exp(l'_p - Re l_p),  r = num_r / sum_p S_p
+ *   W <- W |exp(sum_g (xi_g xbar_g - xbar_g^2/2)) r| e^{tau e_shift} [max(0, cos arg r)]
+ * xi [nw][n_chol] double, xbar [nw][n_chol] complex, logov = l at (phi, paths).
+ * ref [nw] complex receives the hand-off phase reference: num_r, or sum_p S_p
+ * in COMBINED mode.  W = 0 when every path is singular. */
+afqmc_status afqmc_propagate(afqmc_ctx ctx, int32_t nw, void* phi, const double* xi,
+                             const void* xbar, const double* phiT, const void* logov,
+                             double e_shift, double* w, void* ref, void* logov_new);
+
+/* Metropolis update of the paths at the moved walker, then the hand-off
+ * projection (Sec. III.A leapfrog step 2, Eqs. PDF-Y, AFQMC_Metro_correction,
+ * AFQMC_Metro_constraint_cos; App. B steps 2-3).  For each path and each of
+ * n_sweep sweeps a proposal y' is drawn (stream PROPOSAL), Phi_T(y') and
+ * l(y'; phi) are formed, and y' is accepted iff u < alpha (stream ACCEPT),
+ * alpha = |O(y')|/|O(y)| for prior proposals, times N(y')/N(y) for the
+ * random walk.  Accepted paths update y, phiT and logov in place.  Then
+ *   dtheta_T = arg sum_p S'_p - arg ref,  W <- W max(0, cos dtheta_T)
+ * (HALFPLANE: W <- 0 if |dtheta_T| > pi/2).  n_accept [nw] int32 counts
+ * accepted moves per walker (may be NULL). */
+afqmc_status afqmc_metropolis_x(afqmc_ctx ctx, int32_t nw, const void* phi, double* y,
+                                double* phiT, void* logov, const void* ref, double* w,
+                                uint64_t seed, uint64_t step, int32_t n_sweep, int32_t* n_accept);
+
+/* Re-orthonormalise every walker determinant: phi^s = Q R with real positive
+ * diag(R), phi^s <- Q; logov (may be NULL) shifts by -sum_s sum_i log R_ii so
+ * that it stays the log-overlap of the new phi.  Overlap ratios, the force
+ * bias and E_L are unchanged (Eq. WF-imp is invariant under phi -> phi R). */
+afqmc_status afqmc_reorthogonalize(afqmc_ctx ctx, int32_t nw, void* phi, void* logov);
+
+/* Mixed-estimator sums (Eq. mixed_estimator): out[0] = sum_k W_k Re E_L,k,
+ * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2]. */
+afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const void* eloc,
+                             double* out);
+
+/* Counter-based normals: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
+ * counter (i / 4, walker, step, tag << 48 | sweep << 24 | path).  Fills
+ * out [nw][n] with normal i of walker k's stream (tag, sweep 0, path 0), from
+ * Box-Muller pairs of the uniforms (word >> 11) * 2^-53 of words (2j, 2j+1).
+ * tag 1 (FIELD) gives the auxiliary fields xi of step `step`. */
+afqmc_status afqmc_philox_normal(afqmc_ctx ctx, uint64_t seed, uint64_t step, uint32_t tag,
+                                 int32_t nw, int32_t n, double* out);
+
+/* Counter tags of the streams above. */
+enum { AFQMC_TAG_FIELD = 1, AFQMC_TAG_PROPOSAL = 2, AFQMC_TAG_ACCEPT = 3, AFQMC_TAG_INIT = 5 };
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFQMC_H */

@@ -1,0 +1,263 @@
+"""Thin Python binding of libafqmc (the C ABI in include/afqmc.h).
+
+Argument marshalling only: every function below checks the torch tensors it
+is given (device, dtype, contiguity and size, so that no kernel can be handed
+a buffer smaller than its grid assumes) and passes raw device pointers and the
+current HIP stream to the C function of the same name.  There is no fallback:
+if the HIP library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafqmc.so")
+
+HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
+WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE = 0, 1, 2
+PROPOSAL_PRIOR, PROPOSAL_RW = 0, 1
+TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_INIT = 1, 2, 3, 5
+
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
+          5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
+
+
+class afqmc_system(ctypes.Structure):
+    _fields_ = [
+        ("M", c_int32), ("N", c_int32), ("n_chol", c_int32), ("K", c_int32), ("P", c_int32),
+        ("hidden_kind", c_int32), ("coupling", c_double),
+        ("h1", POINTER(c_double)), ("L", POINTER(c_double)), ("phi0", POINTER(c_double)),
+        ("A", POINTER(c_double)),
+        ("dtau", c_double), ("n_taylor", c_int32), ("weight_mode", c_int32),
+        ("proposal", c_int32), ("rw_step", c_double), ("precision", c_int32),
+    ]
+
+
+EXPORTS = {
+    "afqmc_create": (c_int, [POINTER(afqmc_system), c_int, c_void_p, POINTER(c_void_p)]),
+    "afqmc_destroy": (c_int, [c_void_p]),
+    "afqmc_last_error": (c_char_p, [c_void_p]),
+    "afqmc_set_stream": (c_int, [c_void_p, c_void_p]),
+    "afqmc_workspace_size": (c_int, [c_void_p, c_int32, POINTER(c_size_t)]),
+    "afqmc_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "afqmc_sample_prior": (c_int, [c_void_p, c_int32, c_uint64, c_void_p]),
+    "afqmc_trial_build": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "afqmc_overlap": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "afqmc_green": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "afqmc_force_bias": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "afqmc_local_energy": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]),
+    "afqmc_propagate": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_double, c_void_p, c_void_p, c_void_p]),
+    "afqmc_metropolis_x": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_uint64, c_uint64, c_int32, c_void_p]),
+    "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "afqmc_estimator": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "afqmc_philox_normal": (c_int, [c_void_p, c_uint64, c_uint64, c_uint32, c_int32, c_int32,
+                                    c_void_p]),
+}
+
+_lib = None
+
+
+def load_library():
+    """Load libafqmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2505_18519_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class AfqmcError(RuntimeError):
+    pass
+
+
+def _check(ctx, st, what):
+    if st != 0:
+        msg = ""
+        if ctx is not None and ctx.handle:
+            m = load_library().afqmc_last_error(ctx.handle)
+            msg = m.decode() if m else ""
+        raise AfqmcError(f"{what}: {STATUS.get(st, st)} {msg}")
+
+
+def _ptr(t, dtype, numel, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """Owns an afqmc_ctx and its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
+                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0):
+        import numpy as np
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise AfqmcError("no GPU available for libafqmc")
+        self.M, self.N, self.G, self.K, self.P = (int(system.M), int(system.N),
+                                                  int(system.n_chol), int(system.K), int(P))
+        self._host = [np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (system.h1, system.L, system.phi0, system.A)]
+        dp = lambda a: a.ctypes.data_as(POINTER(c_double))
+        self.sys = afqmc_system(self.M, self.N, self.G, self.K, self.P, int(system.hidden_kind),
+                                float(system.coupling), dp(self._host[0]), dp(self._host[1]),
+                                dp(self._host[2]), dp(self._host[3]), float(dtau), int(n_taylor),
+                                int(weight_mode), int(proposal), float(rw_step), 0)
+        self.dtau = float(dtau)
+        self.device = torch.device("cuda", device)
+        self.handle = c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.afqmc_create(ctypes.byref(self.sys), device, _stream(), ctypes.byref(self.handle))
+        if st != 0:
+            self.handle = c_void_p()
+            _check(None, st, "afqmc_create")
+        self.workspace = None
+        self.max_walkers = 0
+        self.reserve(max_walkers)
+
+    def reserve(self, nw):
+        """Make the workspace large enough for nw walkers."""
+        if nw <= self.max_walkers:
+            return
+        n = c_size_t()
+        _check(self, load_library().afqmc_workspace_size(self.handle, int(nw), ctypes.byref(n)),
+               "afqmc_workspace_size")
+        self.workspace = torch.empty(int(n.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(self, load_library().afqmc_set_workspace(self.handle, c_void_p(aligned), int(n.value)),
+               "afqmc_set_workspace")
+        self.max_walkers = nw
+
+    def close(self):
+        if self.handle:
+            load_library().afqmc_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        lib = load_library()
+        lib.afqmc_set_stream(self.handle, _stream())
+        _check(self, getattr(lib, name)(self.handle, *args), name)
+
+
+# --- functions with the C names -------------------------------------------------
+
+def afqmc_sample_prior(ctx, nw, seed, y):
+    ctx._call("afqmc_sample_prior", nw, seed, _ptr(y, torch.float64, nw * ctx.P * ctx.K, "y"))
+
+
+def afqmc_trial_build(ctx, nw, y, phiT):
+    ctx._call("afqmc_trial_build", nw, _ptr(y, torch.float64, nw * ctx.P * ctx.K, "y"),
+              _ptr(phiT, torch.float64, nw * ctx.P * ctx.M * ctx.N, "phiT"))
+
+
+def afqmc_overlap(ctx, nw, phi, phiT, logov):
+    c = ctx
+    c._call("afqmc_overlap", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"))
+
+
+def afqmc_green(ctx, nw, phi, phiT, logov, theta):
+    c = ctx
+    c._call("afqmc_green", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"))
+
+
+def afqmc_force_bias(ctx, nw, phiT, theta, logov, xbar, vb_sample=None):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_force_bias", nw, _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
+            _ptr(vb_sample, torch.complex128, nw * c.P * c.G, "vb_sample", allow_none=True))
+
+
+def afqmc_local_energy(ctx, nw, phiT, theta, logov, eloc, e_sample=None, xbar=None):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_local_energy", nw, _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(eloc, torch.complex128, nw, "eloc"),
+            _ptr(e_sample, torch.complex128, nw * c.P, "e_sample", allow_none=True),
+            _ptr(xbar, torch.complex128, nw * c.G, "xbar", allow_none=True))
+
+
+def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_new):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_propagate", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(xi, torch.float64, nw * c.G, "xi"),
+            _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"), float(e_shift),
+            _ptr(w, torch.float64, nw, "w"), _ptr(ref, torch.complex128, nw, "ref"),
+            _ptr(logov_new, torch.complex128, nw * c.P, "logov_new"))
+
+
+def afqmc_metropolis_x(ctx, nw, phi, y, phiT, logov, ref, w, seed, step, n_sweep, n_accept=None):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_metropolis_x", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(y, torch.float64, nw * c.P * c.K, "y"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(ref, torch.complex128, nw, "ref"), _ptr(w, torch.float64, nw, "w"),
+            int(seed), int(step), int(n_sweep),
+            _ptr(n_accept, torch.int32, nw, "n_accept", allow_none=True))
+
+
+def afqmc_reorthogonalize(ctx, nw, phi, logov=None):
+    c = ctx
+    c._call("afqmc_reorthogonalize", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov", allow_none=True))
+
+
+def afqmc_estimator(ctx, nw, w, eloc, out):
+    ctx._call("afqmc_estimator", nw, _ptr(w, torch.float64, nw, "w"),
+              _ptr(eloc, torch.complex128, nw, "eloc"), _ptr(out, torch.float64, 2, "out"))
+
+
+def afqmc_philox_normal(ctx, seed, step, tag, nw, n, out):
+    ctx._call("afqmc_philox_normal", int(seed), int(step), int(tag), nw, n,
+              _ptr(out, torch.float64, nw * n, "out"))

@@ -1,0 +1,437 @@
+// C ABI entry points of libafqmc: argument checks, context set-up and the
+// kernel sequences of each call.  Every numerical step runs in the gfx950
+// kernels of the k_*.hip files; the host only validates, lays out and launches.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "afqmc_internal.h"
+
+namespace {
+
+afqmc_status fail(afqmc_ctx_s* c, afqmc_status st, const std::string& msg) {
+  if (c != nullptr) c->err = msg;
+  return st;
+}
+
+afqmc_status hip_fail(afqmc_ctx_s* c, hipError_t e, const char* where) {
+  return fail(c, AFQMC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class T>
+hipError_t dev_copy(T** dst, const T* src, size_t n) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_ctx(afqmc_ctx_s* c) {
+  void* ptrs[] = {c->d_h1,      c->d_Lraw,    c->d_Lpad,    c->d_Eh,
+                  c->d_phi0,    c->d_row_ptr, c->d_ent_col, c->d_ent_row,
+                  c->d_ent_kptr, c->d_con_k,  c->d_con_v};
+  for (void* p : ptrs)
+    if (p != nullptr) (void)hipFree(p);
+}
+
+#define CHECK_CTX(c)                                        \
+  do {                                                      \
+    if ((c) == nullptr) return AFQMC_E_INVALID;             \
+    hipError_t se_ = hipSetDevice((c)->device);             \
+    if (se_ != hipSuccess) return hip_fail((c), se_, "hipSetDevice"); \
+  } while (0)
+
+#define CHECK_NW(c, nw)                                                      \
+  do {                                                                       \
+    if ((nw) < 0) return fail((c), AFQMC_E_INVALID, "nw must be >= 0");      \
+  } while (0)
+
+#define REQUIRE(c, p, name)                                                  \
+  do {                                                                       \
+    if ((p) == nullptr) return fail((c), AFQMC_E_INVALID, name " is NULL");  \
+  } while (0)
+
+#define HIPCALL(c, expr, where)                                              \
+  do {                                                                       \
+    hipError_t he_ = (expr);                                                 \
+    if (he_ != hipSuccess) return hip_fail((c), he_, where);                 \
+  } while (0)
+
+afqmc_status need_ws(afqmc_ctx_s* c, int nw, ws_layout* L) {
+  *L = afqmc_ws_layout(c, nw);
+  if (c->ws == nullptr) return fail(c, AFQMC_E_WORKSPACE, "no workspace set (afqmc_set_workspace)");
+  if (c->ws_bytes < L->total)
+    return fail(c, AFQMC_E_WORKSPACE,
+                "workspace too small: " + std::to_string(c->ws_bytes) + " < " +
+                    std::to_string(L->total) + " bytes for nw=" + std::to_string(nw));
+  return AFQMC_OK;
+}
+
+template <class T>
+T* ws_ptr(afqmc_ctx_s* c, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(c->ws) + off);
+}
+
+}  // namespace
+
+ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
+  ws_layout L;
+  const size_t S = (size_t)nw * c->P;
+  size_t off = 0;
+  L.vb = off;
+  off += align256(S * c->G * 16);
+  L.ep = off;
+  off += align256(S * 16);
+  L.vmat = off;
+  off += align256((size_t)nw * c->M * c->M * 16);
+  L.ytry = off;
+  off += align256(S * c->K * 8);
+  L.phiTtry = off;
+  off += align256(S * c->M * c->N * 8);
+  L.ltry = off;
+  off += align256(S * 16);
+  L.acc = off;
+  off += align256((size_t)nw * 4);
+  L.total = off;
+  return L;
+}
+
+extern "C" {
+
+afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afqmc_ctx* out) {
+  if (sys == nullptr || out == nullptr) return AFQMC_E_INVALID;
+  *out = nullptr;
+  if (sys->h1 == nullptr || sys->L == nullptr || sys->phi0 == nullptr || sys->A == nullptr)
+    return AFQMC_E_INVALID;
+  const int M = sys->M, N = sys->N, G = sys->n_chol, K = sys->K, P = sys->P;
+  if (M < 1 || N < 1 || N > M || M > 64 || N > 16 || G < 1 || K < 1 || K > 256 || P < 1 || P > 64)
+    return AFQMC_E_SHAPE;
+  if (sys->hidden_kind != AFQMC_HIDDEN_ISING && sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
+    return AFQMC_E_INVALID;
+  if (sys->weight_mode < 0 || sys->weight_mode > 2) return AFQMC_E_INVALID;
+  if (sys->proposal < 0 || sys->proposal > 1) return AFQMC_E_INVALID;
+  if (sys->precision != AFQMC_PREC_FP64) return AFQMC_E_UNSUPPORTED;
+  if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
+
+  afqmc_ctx_s* c = new (std::nothrow) afqmc_ctx_s();
+  if (c == nullptr) return AFQMC_E_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->M = M;
+  c->N = N;
+  c->G = G;
+  c->K = K;
+  c->P = P;
+  c->MT = ((M + 15) / 16) * 16;
+  c->hidden_kind = sys->hidden_kind;
+  c->coupling = sys->coupling;
+  c->dtau = sys->dtau;
+  c->rw_step = sys->rw_step;
+  c->n_taylor = sys->n_taylor;
+  c->weight_mode = sys->weight_mode;
+  c->proposal = sys->proposal;
+  c->precision = sys->precision;
+
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete c;
+    return AFQMC_E_DEVICE;
+  }
+  // padded L slabs (slab G is filled with h1' on the device)
+  const int MT = c->MT;
+  std::vector<double> Lpad((size_t)(G + 1) * MT * MT, 0.0);
+  for (int gm = 0; gm < G; ++gm)
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j)
+        Lpad[((size_t)gm * MT + i) * MT + j] = sys->L[((size_t)gm * M + i) * M + j];
+  // entry list of sum_k y_k A_k: distinct nonzero (i, j) in row order
+  std::vector<int> row_ptr(M + 1, 0), ent_row, ent_col, ent_kptr(1, 0), con_k;
+  std::vector<double> con_v;
+  for (int i = 0; i < M; ++i) {
+    row_ptr[i] = (int)ent_col.size();
+    for (int j = 0; j < M; ++j) {
+      bool any = false;
+      for (int k = 0; k < K; ++k) {
+        const double v = sys->A[((size_t)k * M + i) * M + j];
+        if (v != 0.0) {
+          con_k.push_back(k);
+          con_v.push_back(v);
+          any = true;
+        }
+      }
+      if (any) {
+        ent_row.push_back(i);
+        ent_col.push_back(j);
+        ent_kptr.push_back((int)con_k.size());
+      }
+    }
+  }
+  row_ptr[M] = (int)ent_col.size();
+  c->n_ent = (int)ent_col.size();
+  c->n_contrib = (int)con_k.size();
+
+  if ((e = dev_copy(&c->d_h1, sys->h1, (size_t)M * M)) != hipSuccess ||
+      (e = dev_copy(&c->d_Lraw, sys->L, (size_t)G * M * M)) != hipSuccess ||
+      (e = dev_copy(&c->d_Lpad, Lpad.data(), Lpad.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_phi0, sys->phi0, (size_t)M * N)) != hipSuccess ||
+      (e = dev_copy(&c->d_row_ptr, row_ptr.data(), row_ptr.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_ent_row, ent_row.data(), ent_row.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_ent_col, ent_col.data(), ent_col.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_ent_kptr, ent_kptr.data(), ent_kptr.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_con_k, con_k.data(), con_k.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_con_v, con_v.data(), con_v.size())) != hipSuccess ||
+      (e = hipMalloc(&c->d_Eh, (size_t)M * M * sizeof(double))) != hipSuccess) {
+    free_ctx(c);
+    delete c;
+    return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
+  }
+  if ((e = launch_setup(c)) != hipSuccess) {
+    free_ctx(c);
+    delete c;
+    return AFQMC_E_DEVICE;
+  }
+  *out = c;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_destroy(afqmc_ctx c) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  delete c;
+  return AFQMC_OK;
+}
+
+const char* afqmc_last_error(afqmc_ctx c) {
+  if (c == nullptr) return "null context";
+  return c->err.c_str();
+}
+
+afqmc_status afqmc_set_stream(afqmc_ctx c, void* stream) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  c->stream = static_cast<hipStream_t>(stream);
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_workspace_size(afqmc_ctx c, int32_t nw, size_t* bytes) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  REQUIRE(c, bytes, "bytes");
+  CHECK_NW(c, nw);
+  *bytes = afqmc_ws_layout(c, nw).total;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_set_workspace(afqmc_ctx c, void* dptr, size_t bytes) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  if (dptr != nullptr && (reinterpret_cast<uintptr_t>(dptr) & 255) != 0)
+    return fail(c, AFQMC_E_INVALID, "workspace must be 256-byte aligned");
+  c->ws = dptr;
+  c->ws_bytes = dptr ? bytes : 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_sample_prior(afqmc_ctx c, int32_t nw, uint64_t seed, double* y) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, y, "y");
+  HIPCALL(c, launch_sample_prior(c, nw, seed, y), "sample_prior");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_trial_build(afqmc_ctx c, int32_t nw, const double* y, double* phiT) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, y, "y");
+  REQUIRE(c, phiT, "phiT");
+  HIPCALL(c, launch_trial_build(c, nw * c->P, y, phiT), "trial_build");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_overlap(afqmc_ctx c, int32_t nw, const void* phi, const double* phiT,
+                           void* logov) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  HIPCALL(c,
+          launch_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
+                         nullptr),
+          "overlap");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_green(afqmc_ctx c, int32_t nw, const void* phi, const double* phiT, void* logov,
+                         void* theta) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, theta, "theta");
+  HIPCALL(c,
+          launch_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
+                         static_cast<double*>(theta)),
+          "green");
+  return AFQMC_OK;
+}
+
+static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, const void* theta,
+                                const void* logov, void* xbar, void* vb_sample, void* eloc,
+                                void* e_sample) {
+  ws_layout L;
+  const bool need = (vb_sample == nullptr) || (e_sample == nullptr);
+  if (need) {
+    afqmc_status st = need_ws(c, nw, &L);
+    if (st != AFQMC_OK) return st;
+  }
+  double* vb = vb_sample ? static_cast<double*>(vb_sample) : ws_ptr<double>(c, L.vb);
+  double* ep = e_sample ? static_cast<double*>(e_sample) : ws_ptr<double>(c, L.ep);
+  HIPCALL(c,
+          launch_contract(c, nw, phiT, static_cast<const double*>(theta),
+                          static_cast<const double*>(logov), vb, ep),
+          "contract");
+  HIPCALL(c,
+          launch_combine(c, nw, vb, ep, static_cast<const double*>(logov),
+                         static_cast<double*>(xbar), static_cast<double*>(eloc)),
+          "combine");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_force_bias(afqmc_ctx c, int32_t nw, const double* phiT, const void* theta,
+                              const void* logov, void* xbar, void* vb_sample) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, theta, "theta");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, xbar, "xbar");
+  return contraction(c, nw, phiT, theta, logov, xbar, vb_sample, nullptr, nullptr);
+}
+
+afqmc_status afqmc_local_energy(afqmc_ctx c, int32_t nw, const double* phiT, const void* theta,
+                                const void* logov, void* eloc, void* e_sample, void* xbar) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, theta, "theta");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, eloc, "eloc");
+  return contraction(c, nw, phiT, theta, logov, xbar, nullptr, eloc, e_sample);
+}
+
+afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* xi, const void* xbar,
+                             const double* phiT, const void* logov, double e_shift, double* w,
+                             void* ref, void* logov_new) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, xi, "xi");
+  REQUIRE(c, xbar, "xbar");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, w, "w");
+  REQUIRE(c, ref, "ref");
+  REQUIRE(c, logov_new, "logov_new");
+  if (!isfinite(e_shift)) return fail(c, AFQMC_E_INVALID, "e_shift must be finite");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  double* vmat = ws_ptr<double>(c, L.vmat);
+  double* ph = static_cast<double*>(phi);
+  HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat), "vbuild");
+  HIPCALL(c, launch_taylor(c, nw, vmat, ph), "taylor");
+  HIPCALL(c, launch_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr),
+          "ratio overlap");
+  HIPCALL(c,
+          launch_weight(c, nw, xi, static_cast<const double*>(xbar),
+                        static_cast<const double*>(logov), static_cast<double*>(logov_new), e_shift,
+                        w, static_cast<double*>(ref)),
+          "weight");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double* y, double* phiT,
+                                void* logov, const void* ref, double* w, uint64_t seed,
+                                uint64_t step, int32_t n_sweep, int32_t* n_accept) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, ref, "ref");
+  REQUIRE(c, w, "w");
+  if (n_sweep < 0) return fail(c, AFQMC_E_INVALID, "n_sweep must be >= 0");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  double* ytry = ws_ptr<double>(c, L.ytry);
+  double* phiTtry = ws_ptr<double>(c, L.phiTtry);
+  double* ltry = ws_ptr<double>(c, L.ltry);
+  int* nacc = n_accept ? n_accept : ws_ptr<int>(c, L.acc);
+  const double* ph = static_cast<const double*>(phi);
+  double* lo = static_cast<double*>(logov);
+  HIPCALL(c, launch_zero_int(c, nw, nacc), "zero");
+  const int nflip = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? c->K : 1;
+  for (int s = 0; s < n_sweep; ++s) {
+    for (int f = 0; f < nflip; ++f) {
+      const int flip_k = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? f : -1;
+      HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k), "proposal");
+      HIPCALL(c, launch_trial_build(c, nw * c->P, ytry, phiTtry), "proposal trial build");
+      HIPCALL(c, launch_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
+      HIPCALL(c, launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, flip_k),
+              "accept");
+    }
+  }
+  HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_reorthogonalize(afqmc_ctx c, int32_t nw, void* phi, void* logov) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  HIPCALL(c, launch_qr(c, nw, static_cast<double*>(phi), static_cast<double*>(logov)), "qr");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_estimator(afqmc_ctx c, int32_t nw, const double* w, const void* eloc,
+                             double* out) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  REQUIRE(c, w, "w");
+  REQUIRE(c, eloc, "eloc");
+  REQUIRE(c, out, "out");
+  HIPCALL(c, launch_estimator(c, nw, w, static_cast<const double*>(eloc), out), "estimator");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_philox_normal(afqmc_ctx c, uint64_t seed, uint64_t step, uint32_t tag, int32_t nw,
+                                 int32_t n, double* out) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (n < 0) return fail(c, AFQMC_E_INVALID, "n must be >= 0");
+  if (tag > 0xFFFF) return fail(c, AFQMC_E_INVALID, "tag must fit in 16 bits");
+  if (nw == 0 || n == 0) return AFQMC_OK;
+  REQUIRE(c, out, "out");
+  HIPCALL(c, launch_philox_normal(c, seed, step, tag, nw, n, out), "philox_normal");
+  return AFQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Device helpers shared by the gfx950 kernels of the AFQMC hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AFQMC_WAVE 64
+
+// ---------------------------------------------------------------------------
+// complex double, interleaved (re, im) in memory
+
+struct cplx {
+  double re, im;
+};
+
+__device__ __forceinline__ cplx cmk(double r, double i) { return cplx{r, i}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+__device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+// a / b with Smith's scaling
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return cplx{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  } else {
+    double r = b.re / b.im, d = b.im + b.re * r;
+    return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+  }
+}
+// a - b * c
+__device__ __forceinline__ cplx cfms(cplx a, cplx b, cplx c) {
+  return cplx{a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};
+}
+// a + b * c
+__device__ __forceinline__ cplx cfma(cplx a, cplx b, cplx c) {
+  return cplx{a.re + b.re * c.re - b.im * c.im, a.im + b.re * c.im + b.im * c.re};
+}
+__device__ __forceinline__ cplx cld(const double* p) { return cplx{p[0], p[1]}; }
+__device__ __forceinline__ void cst(double* p, cplx v) {
+  p[0] = v.re;
+  p[1] = v.im;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 matrix core: D(16x16) += A(16x4) B(4x16).
+// Lane l = 16 g + c (g = l / 16, c = l % 16) supplies A[c][g] and B[g][c] and
+// holds D[4 g + r][c] in element r of the accumulator.
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dx4 mfma_f64(double a, double b, dx4 acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ dx4 dx4_zero() {
+  dx4 z = {0.0, 0.0, 0.0, 0.0};
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// wave-wide reductions (64 lanes)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, AFQMC_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, AFQMC_WAVE));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 256-bit counter, 128-bit key.
+
+struct ph4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ ph4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                             uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  ph4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+__device__ __forceinline__ uint64_t rng_word3(uint32_t tag, uint32_t sweep, uint32_t path) {
+  return ((uint64_t)tag << 48) | ((uint64_t)sweep << 24) | (uint64_t)path;
+}
+
+__device__ __forceinline__ double u01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+// The four normals of one block: Box-Muller on uniform pairs (words 0,1) and (2,3).
+__device__ __forceinline__ void normals4(const ph4& b, double z[4]) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    double ua = u01(b.v[2 * j]), ub = u01(b.v[2 * j + 1]);
+    double r = sqrt(-2.0 * log(1.0 - ua));
+    double s, c;
+    sincos(2.0 * M_PI * ub, &s, &c);
+    z[2 * j] = r * c;
+    z[2 * j + 1] = r * s;
+  }
+}
+
+// normal i of stream (seed, walker, step, w3)
+__device__ __forceinline__ double stream_normal(uint64_t seed, uint64_t walker, uint64_t step,
+                                                uint64_t w3, uint32_t i) {
+  ph4 b = philox4x64_10(i >> 2, walker, step, w3, seed, 0);
+  const bool hi = (i >> 1) & 1;
+  const double ua = u01(hi ? b.v[2] : b.v[0]), ub = u01(hi ? b.v[3] : b.v[1]);
+  const double r = sqrt(-2.0 * log(1.0 - ua));
+  double sn, cs;
+  sincos(2.0 * M_PI * ub, &sn, &cs);
+  return r * ((i & 1) ? sn : cs);
+}
+
+__device__ __forceinline__ double stream_uniform(uint64_t seed, uint64_t walker, uint64_t step,
+                                                 uint64_t w3, uint32_t i) {
+  ph4 b = philox4x64_10(i >> 2, walker, step, w3, seed, 0);
+  const int j = i & 3;
+  const uint64_t x = (j == 0) ? b.v[0] : (j == 1) ? b.v[1] : (j == 2) ? b.v[2] : b.v[3];
+  return u01(x);
+}
+
+__device__ __forceinline__ double neg_inf() { return -__builtin_huge_val(); }

@@ -1,0 +1,270 @@
+// Cholesky-vector contraction: force bias and local energy of every path
+// (Sec. III.A, Eq. local-obs; Eq. shift1; Wick's theorem for <1/2 sum L^2>).
+//
+// Per path p and vector g (both spins s):
+//   Y_g = Phi_T^T L_g (N x M, real, shared by the spins)
+//   f_g^s = Y_g Theta^s (N x N complex)
+//   vb_g = sum_s tr f_g^s,   ex = sum_g sum_s tr(f_g^s f_g^s)
+//   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g vb_g^2 - 1/2 ex
+// h1' rides along as slab g = n_chol of the padded L array, so the one-body
+// term costs one more pass of the same loop.
+//
+// Layout on gfx950: one wavefront per path, CW wavefronts per workgroup.  The
+// path's Phi_T and Theta live in registers as FP64-MFMA B operands for the
+// whole loop over g.  L_g is double-buffered in LDS and shared by the CW
+// wavefronts.  Stage 1 (Y_g^T = L_g Phi_T) leaves Y_g in the accumulator
+// layout, which is exactly the A-operand layout of stage 2 when the
+// contraction index m is visited in the order m = 16 t + 4 g + r, so the two
+// stages chain in registers.  tr(f f) needs f transposed: it goes through a
+// per-wave 8 KB LDS tile.  Nothing of size n_chol x N^2 touches HBM.
+#include "afqmc_internal.h"
+#include "dev_common.h"
+
+namespace {
+
+constexpr int CW = 4;  // wavefronts (paths) per workgroup
+
+template <int MT>
+__global__ void __launch_bounds__(CW * 64)
+k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
+           const double* __restrict__ phiT, const double* __restrict__ theta,
+           const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
+  constexpr int NTILE = MT / 16;
+  constexpr int SLAB = MT * MT;
+  constexpr int NV2 = SLAB / 2;                        // 16-byte vectors per slab
+  constexpr int NQ = (NV2 + CW * 64 - 1) / (CW * 64);  // per thread
+  __shared__ double s_L[2][SLAB];
+  __shared__ double s_f[CW][4][16][17];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int s = blockIdx.x * CW + wave;
+  bool active = s < n_samples;
+  if (active) active = !__builtin_isinf(logov[2 * s]);  // singular paths contribute zero
+
+  // B operands: bT[t][r] = Phi_T[16t+4g+r][c]; bth[sp][ri][t][r] = Theta^sp[16t+4g+r][c]
+  double bT[NTILE][4];
+  double bth[2][2][NTILE][4];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * t + 4 * g + r;
+      const bool ok = active && m < M && c < N;
+      bT[t][r] = ok ? phiT[((size_t)s * M + m) * N + c] : 0.0;
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        const double* src = theta + ((((size_t)s * 2 + sp) * M + m) * N + c) * 2;
+        bth[sp][0][t][r] = ok ? src[0] : 0.0;
+        bth[sp][1][t][r] = ok ? src[1] : 0.0;
+      }
+    }
+
+  // stage slab 0
+  {
+    const double2* src = reinterpret_cast<const double2*>(Lpad);
+    double2* dst = reinterpret_cast<double2*>(s_L[0]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (tid + q * CW * 64 < NV2) dst[tid + q * CW * 64] = src[tid + q * CW * 64];
+  }
+  __syncthreads();
+
+  double vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  double ex_re = 0.0, ex_im = 0.0;
+  double(*sf)[16][17] = s_f[wave];
+
+  for (int gam = 0; gam <= G; ++gam) {
+    const int b = gam & 1;
+    // prefetch the next slab into registers
+    // (loads are unconditional, clamped to the slab, and held in one vector
+    //  value so that they stay in registers)
+    typedef double vpre_t __attribute__((ext_vector_type(2 * NQ)));
+    vpre_t pre;
+    const bool has_next = gam < G;
+    {
+      const double2* src =
+          reinterpret_cast<const double2*>(Lpad + (size_t)(has_next ? gam + 1 : gam) * SLAB);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double2 v = src[min(tid + q * CW * 64, NV2 - 1)];
+        pre[2 * q] = v.x;
+        pre[2 * q + 1] = v.y;
+      }
+    }
+    if (active) {
+      const double* Ls = s_L[b];
+      // stage 1: y1[tp] = (L_g Phi_T)[16tp + 4g + r][c]
+      dx4 y1[NTILE];
+#pragma unroll
+      for (int tp = 0; tp < NTILE; ++tp) y1[tp] = dx4_zero();
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int tp = 0; tp < NTILE; ++tp) {
+            // A[i=c][k=g] = L[16tp+c][16t+4g+r] = L[16t+4g+r][16tp+c] (L symmetric)
+            const double av = Ls[(16 * t + 4 * g + r) * MT + 16 * tp + c];
+            y1[tp] = mfma_f64(av, bT[t][r], y1[tp]);
+          }
+      // stage 2: f[sp][ri] = sum_m Y[c'][m] Theta^sp[m][c]  (rows 4g+r, col c)
+      dx4 f[2][2];
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) f[sp][0] = f[sp][1] = dx4_zero();
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri)
+              f[sp][ri] = mfma_f64(y1[t][r], bth[sp][ri][t][r], f[sp][ri]);
+
+      // diagonal: element (4g+r, c) with c == 4g+r
+      double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (c == 4 * g + r) {
+          d_re = f[0][0][r] + f[1][0][r];
+          d_im = f[0][1][r] + f[1][1][r];
+        }
+      d_re = wave_sum(d_re);
+      d_im = wave_sum(d_im);
+      if (gam < G) {
+        vb2_re += d_re * d_re - d_im * d_im;
+        vb2_im += 2.0 * d_re * d_im;
+        if (lane == 0) {
+          double* o = vb + ((size_t)s * G + gam) * 2;
+          o[0] = d_re;
+          o[1] = d_im;
+        }
+        // exchange: sum_ij f_ij f_ji, transpose through LDS
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sf[2 * sp + ri][4 * g + r][c] = f[sp][ri][r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double tr_ = sf[2 * sp][c][4 * g + r];
+            const double ti_ = sf[2 * sp + 1][c][4 * g + r];
+            const double ar = f[sp][0][r], ai = f[sp][1][r];
+            ex_re += ar * tr_ - ai * ti_;
+            ex_im += ar * ti_ + ai * tr_;
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      } else {
+        e1_re = d_re;
+        e1_im = d_im;
+      }
+    }
+    if (has_next) {
+      double2* dst = reinterpret_cast<double2*>(s_L[b ^ 1]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (tid + q * CW * 64 < NV2) dst[tid + q * CW * 64] = make_double2(pre[2 * q], pre[2 * q + 1]);
+    }
+    __syncthreads();
+  }
+
+  if (s < n_samples) {
+    ex_re = wave_sum(ex_re);
+    ex_im = wave_sum(ex_im);
+    if (lane == 0) {
+      double* o = ep + (size_t)s * 2;
+      if (active) {
+        o[0] = e1_re + 0.5 * vb2_re - 0.5 * ex_re;
+        o[1] = e1_im + 0.5 * vb2_im - 0.5 * ex_im;
+      } else {
+        o[0] = 0.0;
+        o[1] = 0.0;
+      }
+    }
+    if (!active)
+      for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
+  }
+}
+
+// Walker-level estimates over the P paths (Eq. local-obs, then Eq. shift1):
+// S_p = exp(i Im l_p) (0 if singular), xbar_g = -i sqrt(tau) sum S vb / sum S,
+// E_L = sum S E_p / sum S.  One workgroup of 64 threads per walker.
+__global__ void __launch_bounds__(64)
+k_combine(int nw, int P, int G, double sqrt_tau, const double* __restrict__ vb,
+          const double* __restrict__ ep, const double* __restrict__ logov,
+          double* __restrict__ xbar, double* __restrict__ eloc) {
+  __shared__ double s_S[64][2];
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int p = lane; p < P; p += 64) {
+    const double lr = logov[((size_t)w * P + p) * 2], li = logov[((size_t)w * P + p) * 2 + 1];
+    double sr = 0.0, si = 0.0;
+    if (!__builtin_isinf(lr)) sincos(li, &si, &sr);
+    s_S[p][0] = sr;
+    s_S[p][1] = si;
+  }
+  __syncthreads();
+  cplx den = cmk(0.0, 0.0);
+  for (int p = 0; p < P; ++p) den = cadd(den, cmk(s_S[p][0], s_S[p][1]));
+  const bool good = (den.re != 0.0 || den.im != 0.0);
+  if (xbar != nullptr) {
+    for (int gm = lane; gm < G; gm += 64) {
+      cplx num = cmk(0.0, 0.0);
+      for (int p = 0; p < P; ++p)
+        num = cfma(num, cmk(s_S[p][0], s_S[p][1]), cld(vb + (((size_t)w * P + p) * G + gm) * 2));
+      cplx v = good ? cdiv(num, den) : cmk(0.0, 0.0);
+      // -i sqrt(tau) v
+      cst(xbar + ((size_t)w * G + gm) * 2, cmk(sqrt_tau * v.im, -sqrt_tau * v.re));
+    }
+  }
+  if (eloc != nullptr && lane == 0) {
+    cplx num = cmk(0.0, 0.0);
+    for (int p = 0; p < P; ++p)
+      num = cfma(num, cmk(s_S[p][0], s_S[p][1]), cld(ep + ((size_t)w * P + p) * 2));
+    cst(eloc + (size_t)w * 2, good ? cdiv(num, den) : cmk(0.0, 0.0));
+  }
+}
+
+template <int MT>
+hipError_t launch_mt(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                     const double* logov, double* vb, double* ep) {
+  const int n = nw * c->P;
+  dim3 grid((n + CW - 1) / CW), block(CW * 64);
+  hipLaunchKernelGGL(k_contract<MT>, grid, block, 0, c->stream, n, c->M, c->N, c->G, c->d_Lpad,
+                     phiT, theta, logov, vb, ep);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                           const double* logov, double* vb, double* ep) {
+  if (nw <= 0) return hipSuccess;
+  switch (c->MT) {
+    case 32: return launch_mt<32>(c, nw, phiT, theta, logov, vb, ep);
+    case 64: return launch_mt<64>(c, nw, phiT, theta, logov, vb, ep);
+    case 16: return launch_mt<16>(c, nw, phiT, theta, logov, vb, ep);
+    case 48: return launch_mt<48>(c, nw, phiT, theta, logov, vb, ep);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const double* ep,
+                          const double* logov, double* xbar, double* eloc) {
+  if (nw <= 0) return hipSuccess;
+  if (c->P > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_combine, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, sqrt(c->dtau),
+                     vb, ep, logov, xbar, eloc);
+  return hipGetLastError();
+}

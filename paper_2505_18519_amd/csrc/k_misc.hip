@@ -1,0 +1,262 @@
+// Set-up kernels (h1', e^{-tau h1/2}), counter-based random streams, the
+// mixed-estimator sums and walker re-orthonormalisation.
+#include "afqmc_internal.h"
+#include "dev_common.h"
+
+namespace {
+
+// h1' = h1 + 1/2 sum_g L_g L_g into slab G of the padded L array
+__global__ void k_h1_eff(int M, int MT, int G, const double* __restrict__ h1,
+                         const double* __restrict__ L, double* __restrict__ Lpad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int i = e / M, j = e % M;
+  double acc = 0.0;
+  for (int gm = 0; gm < G; ++gm) {
+    const double* Lg = L + (size_t)gm * M * M;
+    double t = 0.0;
+    for (int k = 0; k < M; ++k) t += Lg[i * M + k] * Lg[k * M + j];
+    acc += t;
+  }
+  Lpad[(size_t)G * MT * MT + i * MT + j] = h1[i * M + j] + 0.5 * acc;
+}
+
+// exp(X), X = -tau h1 / 2, by scaling and squaring of a 24-term Taylor series
+// (|X / 2^s|_1 <= 1/4).  One workgroup; three M x M work matrices in global memory.
+__global__ void __launch_bounds__(256)
+k_expm_half(int M, double dtau, const double* __restrict__ h1, double* __restrict__ X,
+            double* __restrict__ T, double* __restrict__ T2, double* __restrict__ E) {
+  __shared__ double s_norm;
+  __shared__ int s_sq;
+  const int tid = threadIdx.x;
+  const int MM = M * M;
+  if (tid == 0) {
+    double nrm = 0.0;
+    for (int j = 0; j < M; ++j) {
+      double cs = 0.0;
+      for (int i = 0; i < M; ++i) cs += fabs(h1[i * M + j]);
+      nrm = fmax(nrm, cs);
+    }
+    nrm *= 0.5 * dtau;
+    int sq = 0;
+    while (nrm > 0.25 && sq < 64) {
+      nrm *= 0.5;
+      ++sq;
+    }
+    s_norm = nrm;
+    s_sq = sq;
+  }
+  __syncthreads();
+  const double scale = -0.5 * dtau * ldexp(1.0, -s_sq);
+  for (int e = tid; e < MM; e += 256) {
+    X[e] = scale * h1[e];
+    T[e] = ((e / M) == (e % M)) ? 1.0 : 0.0;
+    E[e] = T[e];
+  }
+  __syncthreads();
+  for (int j = 1; j <= 24; ++j) {
+    for (int e = tid; e < MM; e += 256) {
+      const int r = e / M, cc = e % M;
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += X[r * M + k] * T[k * M + cc];
+      T2[e] = acc / (double)j;
+    }
+    __syncthreads();
+    for (int e = tid; e < MM; e += 256) {
+      T[e] = T2[e];
+      E[e] += T2[e];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < s_sq; ++q) {
+    for (int e = tid; e < MM; e += 256) {
+      const int r = e / M, cc = e % M;
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += E[r * M + k] * E[k * M + cc];
+      T2[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < MM; e += 256) E[e] = T2[e];
+    __syncthreads();
+  }
+}
+
+__global__ void k_philox_normal(uint64_t seed, uint64_t step, uint64_t w3, int nw, int n,
+                                double* __restrict__ out) {
+  const int nb = (n + 3) / 4;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nw * nb) return;
+  const int w = (int)(idx / nb), b = (int)(idx % nb);
+  ph4 blk = philox4x64_10((uint64_t)b, (uint64_t)w, step, w3, seed, 0);
+  double z[4];
+  normals4(blk, z);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (4 * b + q < n) out[(size_t)w * n + 4 * b + q] = z[q];
+}
+
+__global__ void k_sample_prior(int nw, int P, int K, int hidden_kind, uint64_t seed,
+                               double* __restrict__ y) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nw * P * K) return;
+  const int k = (int)(idx % K);
+  const int p = (int)((idx / K) % P);
+  const int w = (int)(idx / ((size_t)K * P));
+  const uint64_t w3 = rng_word3(AFQMC_TAG_INIT, 0, p);
+  if (hidden_kind == AFQMC_HIDDEN_ISING)
+    y[idx] = (stream_uniform(seed, w, 0, w3, k) < 0.5) ? -1.0 : 1.0;
+  else
+    y[idx] = stream_normal(seed, w, 0, w3, k);
+}
+
+// error-free transformation a + b = s + e
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// out[0] = sum W Re E_L, out[1] = sum W, compensated (sum + error term)
+__global__ void __launch_bounds__(256)
+k_estimator(int nw, const double* __restrict__ w, const double* __restrict__ eloc,
+            double* __restrict__ out) {
+  __shared__ double s_v[4][256];
+  const int tid = threadIdx.x;
+  double n_s = 0.0, n_e = 0.0, d_s = 0.0, d_e = 0.0;
+  for (int k = tid; k < nw; k += 256) {
+    double s, e;
+    two_sum(n_s, w[k] * eloc[2 * (size_t)k], s, e);
+    n_s = s;
+    n_e += e;
+    two_sum(d_s, w[k], s, e);
+    d_s = s;
+    d_e += e;
+  }
+  s_v[0][tid] = n_s;
+  s_v[1][tid] = n_e;
+  s_v[2][tid] = d_s;
+  s_v[3][tid] = d_e;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) {
+      double s, e;
+      two_sum(s_v[0][tid], s_v[0][tid + o], s, e);
+      s_v[0][tid] = s;
+      s_v[1][tid] += s_v[1][tid + o] + e;
+      two_sum(s_v[2][tid], s_v[2][tid + o], s, e);
+      s_v[2][tid] = s;
+      s_v[3][tid] += s_v[3][tid + o] + e;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = s_v[0][0] + s_v[1][0];
+    out[1] = s_v[2][0] + s_v[3][0];
+  }
+}
+
+// Re-orthonormalisation by modified Gram-Schmidt applied twice, one 64-lane
+// workgroup per walker (lane = orbital row; M <= 64, N <= 16).  R_jj is the
+// norm of column j after both projection passes, hence real positive.
+__global__ void __launch_bounds__(64)
+k_qr(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict__ logov) {
+  constexpr int NTQ = 16;
+  const int w = blockIdx.x;
+  const int m = threadIdx.x;
+  double shift = 0.0;
+  for (int sp = 0; sp < 2; ++sp) {
+    double* base = phi + ((size_t)(w * 2 + sp) * M) * N * 2;
+    cplx q[NTQ];
+#pragma unroll
+    for (int j = 0; j < NTQ; ++j)
+      q[j] = (m < M && j < N) ? cmk(base[((size_t)m * N + j) * 2], base[((size_t)m * N + j) * 2 + 1])
+                              : cmk(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < NTQ; ++j) {
+      if (j < N) {
+        cplx v = q[j];
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+          for (int k = 0; k < j; ++k) {
+            // h = q_k^H v
+            double hr = q[k].re * v.re + q[k].im * v.im;
+            double hi = q[k].re * v.im - q[k].im * v.re;
+            hr = wave_sum(hr);
+            hi = wave_sum(hi);
+            v = cfms(v, cmk(hr, hi), q[k]);
+          }
+        const double nrm = sqrt(wave_sum(cabs2(v)));
+        shift += log(nrm);
+        q[j] = cscale(v, 1.0 / nrm);
+      }
+    }
+    if (m < M)
+#pragma unroll
+      for (int j = 0; j < NTQ; ++j)
+        if (j < N) {
+          base[((size_t)m * N + j) * 2] = q[j].re;
+          base[((size_t)m * N + j) * 2 + 1] = q[j].im;
+        }
+  }
+  if (logov != nullptr)
+    for (int p = m; p < P; p += 64) logov[((size_t)w * P + p) * 2] -= shift;
+}
+
+__global__ void k_zero_int(int n, int* __restrict__ p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_setup(afqmc_ctx_s* c) {
+  const int MM = c->M * c->M;
+  hipLaunchKernelGGL(k_h1_eff, dim3((MM + 255) / 256), dim3(256), 0, c->stream, c->M, c->MT, c->G,
+                     c->d_h1, c->d_Lraw, c->d_Lpad);
+  AFQMC_LAUNCH_CHECK();
+  double* tmp = nullptr;
+  hipError_t e = hipMalloc(&tmp, 3 * (size_t)MM * sizeof(double));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_expm_half, dim3(1), dim3(256), 0, c->stream, c->M, c->dtau, c->d_h1, tmp,
+                     tmp + MM, tmp + 2 * MM, c->d_Eh);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  hipFree(tmp);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t step, uint32_t tag,
+                                int nw, int n, double* out) {
+  const size_t total = (size_t)nw * ((n + 3) / 4);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox_normal, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     c->stream, seed, step, ((uint64_t)tag << 48), nw, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y) {
+  const size_t total = (size_t)nw * c->P * c->K;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_prior, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     c->stream, nw, c->P, c->K, c->hidden_kind, seed, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimator(const afqmc_ctx_s* c, int nw, const double* w, const double* eloc,
+                            double* out) {
+  hipLaunchKernelGGL(k_estimator, dim3(1), dim3(256), 0, c->stream, nw, w, eloc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(const afqmc_ctx_s* c, int nw, double* phi, double* logov) {
+  if (nw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qr, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->M, c->N, phi, logov);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, p);
+  return hipGetLastError();
+}

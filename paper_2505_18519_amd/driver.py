@@ -1,0 +1,72 @@
+"""One AFQMC step with a sampled trial, in the order of App. B, through the C ABI.
+
+Holds the composite-walker state (Sec. III.A, Fig. 2): walker determinants and
+weights, the P tethered paths y with their trial determinants Phi_T(y) and
+log-overlaps.  Every arithmetic step runs in libafqmc's kernels; this module
+only allocates the state tensors and sequences the calls on one stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import afqmc as A
+
+
+class Walkers:
+    """Device state of nw composite walkers plus per-step scratch outputs."""
+
+    def __init__(self, ctx: A.Context, nw: int):
+        c, dev = ctx, ctx.device
+        self.nw = nw
+        z = dict(device=dev)
+        self.phi = torch.zeros(nw, 2, c.M, c.N, dtype=torch.complex128, **z)
+        self.w = torch.ones(nw, dtype=torch.float64, **z)
+        self.y = torch.zeros(nw, c.P, c.K, dtype=torch.float64, **z)
+        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=torch.float64, **z)
+        self.logov = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
+        self.logov_new = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
+        self.theta = torch.zeros(nw, c.P, 2, c.M, c.N, dtype=torch.complex128, **z)
+        self.xbar = torch.zeros(nw, c.G, dtype=torch.complex128, **z)
+        self.eloc = torch.zeros(nw, dtype=torch.complex128, **z)
+        self.xi = torch.zeros(nw, c.G, dtype=torch.float64, **z)
+        self.ref = torch.zeros(nw, dtype=torch.complex128, **z)
+        self.nacc = torch.zeros(nw, dtype=torch.int32, **z)
+        ctx.reserve(nw)
+
+
+def init_walkers(ctx: A.Context, phi0, nw: int, seed: int) -> Walkers:
+    """phi = Phi_0 for both spins, W = 1, y ~ p_T, Phi_T(y) and l(y; phi)."""
+    st = Walkers(ctx, nw)
+    p0 = torch.as_tensor(phi0, dtype=torch.complex128, device=ctx.device)
+    st.phi.copy_(p0.expand(nw, 2, ctx.M, ctx.N))
+    A.afqmc_sample_prior(ctx, nw, seed, st.y)
+    A.afqmc_trial_build(ctx, nw, st.y, st.phiT)
+    A.afqmc_overlap(ctx, nw, st.phi, st.phiT, st.logov)
+    return st
+
+
+def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
+         e_shift: float = 0.0, n_sweep: int = 1, n_qr: int = 10, contract_events=None) -> None:
+    """Measure, propagate, move the paths, hand off, re-orthonormalise.
+
+    est_out: device float64 [2] receiving (sum W Re E_L, sum W) at the
+    pre-move state (Eq. mixed_estimator).  contract_events, if given, is a
+    pair of torch.cuda.Event recorded on the current stream around the
+    Cholesky contraction (afqmc_local_energy).
+    """
+    nw = st.nw
+    A.afqmc_green(ctx, nw, st.phi, st.phiT, st.logov, st.theta)
+    if contract_events is not None:
+        contract_events[0].record()
+    A.afqmc_local_energy(ctx, nw, st.phiT, st.theta, st.logov, st.eloc, None, st.xbar)
+    if contract_events is not None:
+        contract_events[1].record()
+    A.afqmc_estimator(ctx, nw, st.w, st.eloc, est_out)
+    A.afqmc_philox_normal(ctx, seed, i, A.TAG_FIELD, nw, ctx.G, st.xi)
+    A.afqmc_propagate(ctx, nw, st.phi, st.xi, st.xbar, st.phiT, st.logov, e_shift, st.w,
+                      st.ref, st.logov_new)
+    A.afqmc_metropolis_x(ctx, nw, st.phi, st.y, st.phiT, st.logov_new, st.ref, st.w, seed, i,
+                         n_sweep, st.nacc)
+    st.logov, st.logov_new = st.logov_new, st.logov
+    if n_qr and (i + 1) % n_qr == 0:
+        A.afqmc_reorthogonalize(ctx, nw, st.phi, st.logov)

@@ -1,0 +1,321 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Same seeded inputs on both sides; tolerances are those of the FP64 path:
+log-overlaps |exp(l - l_ref) - 1| <= 1e-10, force bias normwise 1e-10 per
+walker, energies |E - E_ref| <= 1e-10 max(|E_ref|, 1), determinants
+normwise 1e-10, integer and accept decisions exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import afqmc_inputs as ai
+from oracle import afqmc_oracle as O
+from oracle import philox as PH
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_18519_amd import afqmc as A
+    A.load_library()
+
+
+def dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    # name: (system factory, P, nw)
+    "tiny-ising-M8": (lambda: ai.tiny_ising(), 8, 5),
+    "gauss-M20-N5-ragged": (lambda: ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5), 3, 6),
+    "gauss-M48-N11": (lambda: ai.small_gaussian(M=48, N=11, n_chol=40, K=12, seed=6), 4, 3),
+    "cfg-M64-N16-G256": (lambda: ai.workload(1)[0], 8, 3),
+}
+
+
+def make_ctx(s, P, nw, dtau=0.01, **kw):
+    from paper_2505_18519_amd import afqmc as A
+    return A.Context(s, P, dtau, max_walkers=nw, **kw)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def check_logov(got, ref):
+    ok_ref = np.isfinite(ref.real)
+    assert np.array_equal(np.isfinite(got.real), ok_ref)
+    d = np.abs(np.exp(got[ok_ref] - ref[ok_ref]) - 1.0)
+    assert d.max(initial=0.0) <= TOL, d.max()
+
+
+def state(s, P, nw, seed, spread=0.5):
+    rng = np.random.default_rng(seed)
+    phi = ai.random_walkers(rng, s, nw, spread=spread)
+    y = ai.random_hidden(rng, s, nw, P)
+    return rng, phi, y
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_trial_build_overlap_green(case):
+    _say("case", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, P, nw)
+    rng, phi, y = state(s, P, nw, 1)
+    phiT_ref = O.trial_det(s, y)
+    dy = dev(y)
+    dphiT = torch.zeros(nw, P, s.M, s.N, dtype=torch.float64, device="cuda")
+    A.afqmc_trial_build(ctx, nw, dy, dphiT)
+    torch.cuda.synchronize()
+    assert rel(host(dphiT), phiT_ref) <= 1e-12
+    ell_ref, theta_ref = O.green(phiT_ref, phi)
+    dphi = dev(phi)
+    dl = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    dth = torch.zeros(nw, P, 2, s.M, s.N, dtype=torch.complex128, device="cuda")
+    A.afqmc_green(ctx, nw, dphi, dev(phiT_ref), dl, dth)
+    dl2 = torch.zeros_like(dl)
+    A.afqmc_overlap(ctx, nw, dphi, dev(phiT_ref), dl2)
+    torch.cuda.synchronize()
+    check_logov(host(dl), ell_ref)
+    check_logov(host(dl2), ell_ref)
+    for w in range(nw):
+        for p in range(P):
+            assert rel(host(dth)[w, p], theta_ref[w, p]) <= TOL
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_force_bias_and_local_energy(case):
+    _say("case", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    dtau = 0.01
+    ctx = make_ctx(s, P, nw, dtau=dtau)
+    rng, phi, y = state(s, P, nw, 2)
+    phiT = O.trial_det(s, y)
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, dtau)
+    _, theta = O.green(phiT, phi)
+    dphiT, dth, dl = dev(phiT), dev(theta), dev(ell)
+    G = s.n_chol
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_ep = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, G, dtype=torch.complex128, device="cuda")
+    d_xb2 = torch.zeros(nw, G, dtype=torch.complex128, device="cuda")
+    d_vb = torch.zeros(nw, P, G, dtype=torch.complex128, device="cuda")
+    A.afqmc_local_energy(ctx, nw, dphiT, dth, dl, d_el, d_ep, d_xb)
+    A.afqmc_force_bias(ctx, nw, dphiT, dth, dl, d_xb2, d_vb)
+    torch.cuda.synchronize()
+    g_el, g_ep, g_xb, g_xb2, g_vb = map(host, (d_el, d_ep, d_xb, d_xb2, d_vb))
+    assert np.abs(g_ep - ep).max() <= TOL * max(np.abs(ep).max(), 1)
+    assert np.abs(g_el - eloc).max() <= TOL * max(np.abs(eloc).max(), 1)
+    for w in range(nw):
+        assert rel(g_xb[w], xbar[w]) <= TOL
+        assert rel(g_xb2[w], xbar[w]) <= TOL
+        for p in range(P):
+            assert rel(g_vb[w, p], vb[w, p]) <= TOL
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_propagate(case, mode):
+    _say("case", case, "mode", mode)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    dtau = 0.01
+    ctx = make_ctx(s, P, nw, dtau=dtau, weight_mode=mode)
+    rng, phi, y = state(s, P, nw, 3)
+    phiT = O.trial_det(s, y)
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, dtau)
+    xi = rng.normal(size=(nw, s.n_chol))
+    w0 = rng.uniform(0.5, 1.5, size=nw)
+    e_shift = -1.3
+    phin, wn, ref, elln = O.propagate(s, phi, xi, xbar, phiT, ell, w0, dtau, 10, e_shift, mode)
+    dphi, dw = dev(phi), dev(w0)
+    dref = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    dln = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    A.afqmc_propagate(ctx, nw, dphi, dev(xi), dev(xbar), dev(phiT), dev(ell), e_shift, dw, dref, dln)
+    torch.cuda.synchronize()
+    for w in range(nw):
+        assert rel(host(dphi)[w], phin[w]) <= TOL
+    check_logov(host(dln), elln)
+    assert np.abs(host(dw) - wn).max() <= TOL * np.abs(wn).max()
+    assert np.abs(host(dref) - ref).max() <= TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("proposal", [0, 1])
+def test_metropolis_and_handoff(case, proposal):
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    if s.hidden_kind == 0 and proposal == 1:
+        pytest.skip("random walk is for Gaussian hidden variables")
+    _say("case", case, "proposal", proposal)
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, P, nw, proposal=proposal, rw_step=0.3)
+    rng, phi, y = state(s, P, nw, 4)
+    phiT = O.trial_det(s, y)
+    ell = O.log_overlap(phiT, phi)
+    ref = np.exp(1j * rng.uniform(-0.3, 0.3, size=nw)) * rng.uniform(0.5, 2, size=nw)
+    w0 = rng.uniform(0.5, 1.5, size=nw)
+    seed, stp, nsw = 1234, 7, 2
+    y2, phiT2, ell2, w2, nacc = O.metropolis(s, phi, y, phiT, ell, ref, w0, seed, stp, nsw,
+                                             proposal=proposal, rw_step=0.3)
+    dy, dphiT, dl, dw = dev(y), dev(phiT), dev(ell), dev(w0)
+    dacc = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    A.afqmc_metropolis_x(ctx, nw, dev(phi), dy, dphiT, dl, dev(ref), dw, seed, stp, nsw, dacc)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(dacc), nacc), (host(dacc), nacc)
+    assert np.array_equal(host(dy), y2)
+    assert rel(host(dphiT), phiT2) <= 1e-12
+    check_logov(host(dl), ell2)
+    assert np.abs(host(dw) - w2).max() <= TOL * np.abs(w2).max()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_reorthogonalize(case):
+    _say("case", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, P, nw)
+    rng, phi, y = state(s, P, nw, 5, spread=2.0)
+    phi = phi * 3.0
+    ell = O.log_overlap(O.trial_det(s, y), phi)
+    q, lq = O.reorthogonalize(phi, ell)
+    dphi, dl = dev(phi), dev(ell)
+    A.afqmc_reorthogonalize(ctx, nw, dphi, dl)
+    torch.cuda.synchronize()
+    for w in range(nw):
+        assert rel(host(dphi)[w], q[w]) <= TOL
+    assert np.abs(host(dl).real - lq.real).max() <= TOL * np.abs(lq.real).max()
+
+
+def test_philox_streams_and_prior():
+    _say("philox")
+    s = ai.tiny_ising()
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, 8, 40)
+    out = torch.zeros(37, 61, dtype=torch.float64, device="cuda")
+    A.afqmc_philox_normal(ctx, 99, 5, A.TAG_FIELD, 37, 61, out)
+    dy = torch.zeros(40, 8, s.K, dtype=torch.float64, device="cuda")
+    A.afqmc_sample_prior(ctx, 40, 77, dy)
+    torch.cuda.synchronize()
+    ref = PH.field_normals(99, 5, 37, 61)
+    assert np.abs(host(out) - ref).max() <= 4e-15 * np.abs(ref).max()
+    assert np.array_equal(host(dy), PH.init_hidden(77, 40, 8, s.K, 0))
+    g = ai.small_gaussian()
+    ctx2 = make_ctx(g, 3, 10)
+    dy2 = torch.zeros(10, 3, g.K, dtype=torch.float64, device="cuda")
+    A.afqmc_sample_prior(ctx2, 10, 78, dy2)
+    torch.cuda.synchronize()
+    r2 = PH.init_hidden(78, 10, 3, g.K, 1)
+    assert np.abs(host(dy2) - r2).max() <= 4e-15 * np.abs(r2).max()
+
+
+def test_estimator_sums():
+    _say("estimator")
+    s = ai.tiny_ising()
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, 2, 4)
+    rng = np.random.default_rng(0)
+    nw = 1000
+    w = rng.uniform(0, 2, size=nw)
+    e = rng.normal(size=nw) + 1j * rng.normal(size=nw)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    A.afqmc_estimator(ctx, nw, dev(w), dev(e), out)
+    torch.cuda.synchronize()
+    num, den = O.estimator(w, e)
+    assert abs(host(out)[0] - num) <= 1e-14 * abs(num) + 1e-14
+    assert abs(host(out)[1] - den) <= 1e-14 * den
+
+
+def test_singular_paths_are_excluded():
+    _say("singular")
+    s = ai.tiny_ising()
+    P, nw = 4, 3
+    from paper_2505_18519_amd import afqmc as A
+    ctx = make_ctx(s, P, nw)
+    rng, phi, y = state(s, P, nw, 6)
+    phi[1, 0, :, 0] = 0.0
+    phiT = O.trial_det(s, y)
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, 0.01)
+    dl = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    dth = torch.zeros(nw, P, 2, s.M, s.N, dtype=torch.complex128, device="cuda")
+    A.afqmc_green(ctx, nw, dev(phi), dev(phiT), dl, dth)
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, s.n_chol, dtype=torch.complex128, device="cuda")
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dth, dl, d_el, None, d_xb)
+    torch.cuda.synchronize()
+    g = host(dl)
+    assert np.all(np.isneginf(g[1].real))
+    assert host(d_el)[1] == 0 and np.all(host(d_xb)[1] == 0)
+    assert abs(host(d_el)[0] - eloc[0]) <= TOL * abs(eloc[0])
+
+
+def test_trajectory_tiny_matches_oracle():
+    """30 whole steps (QR every 10) on the tiny Ising workload, identical streams."""
+    _say("trajectory tiny")
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+    s, run = ai.workload(0)
+    nw, P, seed = 16, run.P, 2001
+    ctx = A.Context(s, P, run.dtau, max_walkers=nw)
+    st = D.init_walkers(ctx, s.phi0, nw, seed)
+    ost = O.init_state(s, nw, P, seed)
+    est = torch.zeros(30, 2, dtype=torch.float64, device="cuda")
+    for i in range(30):
+        D.step(ctx, st, seed, i, est[i], e_shift=0.0, n_sweep=1, n_qr=10)
+        ost, rec = O.step(s, ost, seed, i, run.dtau, n_taylor=10, n_sweep=1, n_qr=10)
+        torch.cuda.synchronize()
+        g = host(est[i])
+        assert abs(g[0] / g[1] - rec["e_num"] / rec["e_den"]) <= TOL * abs(rec["e_num"] / rec["e_den"]), i
+        assert abs(g[1] - rec["e_den"]) <= TOL * rec["e_den"], i
+    assert np.array_equal(host(st.y), ost.y)
+    assert np.abs(host(st.w) - ost.w).max() <= TOL * np.abs(ost.w).max()
+
+
+def test_full_size_sampled_walkers():
+    """Green's function and contraction on all 512 x 8 paths of the M=64 workload,
+    with the launch shapes the benchmark times; a sample of walkers is checked."""
+    _say("full size M64")
+    from paper_2505_18519_amd import afqmc as A
+    s, run = ai.workload(1)
+    nw, P = run.W, run.P
+    ctx = A.Context(s, P, run.dtau, max_walkers=nw)
+    rng, phi, y = state(s, P, nw, 8)
+    dy = dev(y)
+    dphiT = torch.zeros(nw, P, s.M, s.N, dtype=torch.float64, device="cuda")
+    A.afqmc_trial_build(ctx, nw, dy, dphiT)
+    dl = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    dth = torch.zeros(nw, P, 2, s.M, s.N, dtype=torch.complex128, device="cuda")
+    A.afqmc_green(ctx, nw, dev(phi), dphiT, dl, dth)
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, s.n_chol, dtype=torch.complex128, device="cuda")
+    A.afqmc_local_energy(ctx, nw, dphiT, dth, dl, d_el, None, d_xb)
+    torch.cuda.synchronize()
+    pick = np.array([0, 1, 200, nw - 1])
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi[pick], O.trial_det(s, y[pick]), run.dtau)
+    check_logov(host(dl)[pick], ell)
+    g_el = host(d_el)[pick]
+    assert np.abs(g_el - eloc).max() <= TOL * np.abs(eloc).max()
+    for k, w in enumerate(pick):
+        assert rel(host(d_xb)[w], xbar[k]) <= TOL
