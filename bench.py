@@ -35,7 +35,7 @@ def contraction_flops(M, N, G):
     return G * (2 * N * M * M + 2 * (4 * M * N * N + 8 * N * N))
 
 
-def cpu_baseline(sys_, run, seed, n_walkers=8):
+def cpu_baseline(sys_, run, seed, n_walkers=48):
     """Time the oracle's whole step on a bounded walker sample (1 BLAS thread)."""
     from threadpoolctl import threadpool_limits
     from oracle import afqmc_oracle as O
@@ -45,7 +45,7 @@ def cpu_baseline(sys_, run, seed, n_walkers=8):
         h1p = O.h1_eff(sys_)
         t0 = time.perf_counter()
         st, _ = O.step(sys_, st, seed, 0, run.dtau, n_taylor=run.n_taylor, n_sweep=run.n_sweep,
-                       n_qr=run.n_qr, Eh=Eh, h1p=h1p)
+                       n_qr=run.n_qr, Eh=Eh, h1p=h1p, xbar_cap=1.0, n_pc=1, w_cap=4.0)
         dt = time.perf_counter() - t0
     return {"value": n_walkers / dt, "unit": "walker-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_walkers} walkers x {run.P} paths, 1 whole step of the same workload "
@@ -76,13 +76,18 @@ def main():
 
     sys_, run = ai.workload(1)
     nw, P, seed = run.W, run.P, 2001
-    ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw)
+    # production loop: force-bias modulus capped at 1 and comb population
+    # control every step with weights capped at 4x the mean (the sampled trial
+    # of this workload has a mean path sign near 0.2 after a few steps)
+    xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
+    ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
 
     e_shift = 0.0
     for i in range(args.warmup):
-        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr)
+        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr,
+               n_pc=n_pc, w_cap=w_cap)
         if i == 0:
             torch.cuda.synchronize()
             e0 = est[0].cpu().numpy()
@@ -95,7 +100,7 @@ def main():
     for k in range(args.steps):
         i = args.warmup + k
         D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr,
-               contract_events=evs[k])
+               contract_events=evs[k], n_pc=n_pc, w_cap=w_cap)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -105,7 +110,10 @@ def main():
     e = est.cpu().numpy()
     energies = e[:, 0] / e[:, 1]
     if not np.all(np.isfinite(energies)):
-        print("non-finite energy in the benchmark run", file=sys.stderr)
+        w = st.w.cpu().numpy()
+        print("non-finite energy in the benchmark run:", e.tolist(), "e_shift", e_shift,
+              "weights: min", w.min(), "max", w.max(), "n_zero", int((w == 0).sum()),
+              "n_nonfinite", int((~np.isfinite(w)).sum()), file=sys.stderr)
         sys.exit(1)
 
     out = {
@@ -124,7 +132,8 @@ def main():
         "config": {"workload": f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
                                f"-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
                    "walkers": nw, "paths": P, "M": sys_.M, "N": sys_.N,
-                   "n_chol": sys_.n_chol, "K": sys_.K},
+                   "n_chol": sys_.n_chol, "K": sys_.K, "xbar_cap": xbar_cap,
+                   "comb_every": n_pc, "weight_cap": w_cap},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
                      "kernel": "k_contract (+ k_combine) in afqmc_local_energy",

@@ -88,6 +88,8 @@ typedef struct {
   int32_t proposal;     /* AFQMC_PROPOSAL_*                                  */
   double rw_step;       /* random-walk proposal step                        */
   int32_t precision;    /* AFQMC_PREC_*                                      */
+  double xbar_cap;      /* > 0: clip |xbar_g| to xbar_cap, phase kept (a common
+                           AFQMC stabilisation the paper does not use); 0: off */
 } afqmc_system;
 
 /* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and
@@ -177,6 +179,19 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx ctx, int32_t nw, const void* phi, doub
  * bias and E_L are unchanged (Eq. WF-imp is invariant under phi -> phi R). */
 afqmc_status afqmc_reorthogonalize(afqmc_ctx ctx, int32_t nw, void* phi, void* logov);
 
+/* Comb population control (branching of the random walk; Sec. II.B speaks of
+ * a branching random walk without fixing the scheme).  With w_cap > 0 each
+ * weight is first clipped to w_cap times the mean weight.  With C_k the
+ * inclusive prefix sums of W and u the uniform of stream (seed, walker 0,
+ * step, tag COMB), new walker j is a copy of old walker
+ *   parent[j] = min{k : C_k > (j + u) sum(W) / nw}
+ * (phi, y, phiT and logov are gathered in place) and every weight becomes
+ * sum(W) / nw.  parent [nw] int32 receives the parents if non-NULL.  A
+ * population whose weights sum to zero is left unchanged. */
+afqmc_status afqmc_population_control(afqmc_ctx ctx, int32_t nw, void* phi, double* w, double* y,
+                                      double* phiT, void* logov, uint64_t seed, uint64_t step,
+                                      double w_cap, int32_t* parent);
+
 /* Mixed-estimator sums (Eq. mixed_estimator): out[0] = sum_k W_k Re E_L,k,
  * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2]. */
 afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const void* eloc,
@@ -191,7 +206,8 @@ afqmc_status afqmc_philox_normal(afqmc_ctx ctx, uint64_t seed, uint64_t step, ui
                                  int32_t nw, int32_t n, double* out);
 
 /* Counter tags of the streams above. */
-enum { AFQMC_TAG_FIELD = 1, AFQMC_TAG_PROPOSAL = 2, AFQMC_TAG_ACCEPT = 3, AFQMC_TAG_INIT = 5 };
+enum { AFQMC_TAG_FIELD = 1, AFQMC_TAG_PROPOSAL = 2, AFQMC_TAG_ACCEPT = 3, AFQMC_TAG_COMB = 4,
+       AFQMC_TAG_INIT = 5 };
 
 #ifdef __cplusplus
 }

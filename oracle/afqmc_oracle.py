@@ -152,12 +152,15 @@ def sample_contraction(sys, phiT: np.ndarray, theta: np.ndarray, ell: np.ndarray
     return vb, ep
 
 
-def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: float):
+def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: float,
+                     xbar_cap: float = 0.0):
     """Eq. local-obs over the P paths, then Eq. shift1.
 
     xbar_g = -i sqrt(tau) sum_p S_p vb_pg / sum_p S_p,  E_L = sum_p S_p E_p / sum_p S_p.
     The i comes from reading Eq. HS-V's sqrt(-tau) into the propagator with
     real L_g.  A walker whose phases sum to zero gets xbar = 0 and E_L = 0.
+    With xbar_cap > 0 each component's modulus is clipped to xbar_cap (phase
+    kept): a stabilisation outside the paper, off by default.
     """
     S = phases(ell)
     den = S.sum(-1)
@@ -167,6 +170,9 @@ def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: floa
     eloc = np.einsum("wp,wp->w", S, ep) / safe
     xbar = np.where(good[:, None], xbar, 0.0)
     eloc = np.where(good, eloc, 0.0)
+    if xbar_cap > 0.0:
+        mag = np.abs(xbar)
+        xbar = np.where(mag > xbar_cap, xbar * (xbar_cap / np.where(mag > 0, mag, 1.0)), xbar)
     return xbar, eloc
 
 
@@ -330,6 +336,30 @@ def reorthogonalize(phi: np.ndarray, logov: Optional[np.ndarray] = None):
     return out, logov - shift[:, None]
 
 
+def comb(w: np.ndarray, seed: int, step: int, w_cap: float = 0.0):
+    """Comb population control (a standard branching step; the paper is silent).
+
+    With w_cap > 0 every weight is first clipped to w_cap times the mean
+    weight.  Then, with u the COMB-stream uniform of this step and C the
+    inclusive prefix sums of W, new walker j copies old walker
+    parent[j] = min{k : C_k > (j + u) sum(W) / nw} and every new weight is
+    sum(W) / nw.  Returns (parent, new weights); an all-zero population is
+    returned unchanged.
+    """
+    w = np.asarray(w, dtype=np.float64).copy()
+    nw = len(w)
+    if w_cap > 0.0:
+        w = np.minimum(w, w_cap * w.sum() / nw)
+    tot = w.sum()
+    if not (tot > 0.0):
+        return np.arange(nw), w
+    u = philox.stream_uniforms(seed, step, [0], [philox.word3(philox.TAG_COMB)], 1)[0, 0, 0]
+    C = np.cumsum(w)
+    t = (np.arange(nw) + u) * (tot / nw)
+    parent = np.minimum(np.searchsorted(C, t, side="right"), nw - 1)
+    return parent, np.full(nw, tot / nw)
+
+
 def estimator(w: np.ndarray, eloc: np.ndarray):
     """(sum_k W_k Re E_L,k, sum_k W_k) with exact summation (Eq. mixed_estimator)."""
     return (math.fsum((w * eloc.real).tolist()), math.fsum(w.tolist()))
@@ -358,11 +388,12 @@ def init_state(sys, nw, P, seed):
 
 def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
          e_shift=0.0, proposal=PROPOSAL_PRIOR, rw_step=0.5,
-         weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None):
-    """Measure, propagate, move the paths, re-orthogonalise.  Returns (state, record)."""
+         weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None, xbar_cap=0.0, n_pc=0, w_cap=0.0):
+    """Measure, propagate, move the paths, re-orthogonalise, and (every n_pc
+    steps, if n_pc > 0) comb the population.  Returns (state, record)."""
     ell, theta = green(st.phiT, st.phi)
     vb, ep = sample_contraction(sys, st.phiT, theta, ell, h1p)
-    xbar, eloc = walker_estimates(vb, ep, ell, dtau)
+    xbar, eloc = walker_estimates(vb, ep, ell, dtau, xbar_cap)
     num, den = estimator(st.w, eloc)
     xi = philox.field_normals(seed, i, st.phi.shape[0], sys.n_chol)
     phin, wn, ref, elln = propagate(sys, st.phi, xi, xbar, st.phiT, ell, st.w, dtau,
@@ -371,6 +402,9 @@ def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
                                           n_sweep, proposal, rw_step, weight_mode)
     if n_qr and (i + 1) % n_qr == 0:
         phin, logov = reorthogonalize(phin, logov)
+    if n_pc and (i + 1) % n_pc == 0:
+        parent, w2 = comb(w2, seed, i, w_cap)
+        phin, y, phiT, logov = phin[parent], y[parent], phiT[parent], logov[parent]
     rec = dict(e_num=num, e_den=den, eloc=eloc, xbar=xbar, logov=ell, xi=xi,
                w_prop=wn, ref=ref, nacc=nacc)
     return State(phin, w2, y, phiT, logov), rec

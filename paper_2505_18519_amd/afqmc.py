@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
 WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE = 0, 1, 2
 PROPOSAL_PRIOR, PROPOSAL_RW = 0, 1
-TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_INIT = 1, 2, 3, 5
+TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
           5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
@@ -34,6 +34,7 @@ class afqmc_system(ctypes.Structure):
         ("A", POINTER(c_double)),
         ("dtau", c_double), ("n_taylor", c_int32), ("weight_mode", c_int32),
         ("proposal", c_int32), ("rw_step", c_double), ("precision", c_int32),
+        ("xbar_cap", c_double),
     ]
 
 
@@ -57,6 +58,8 @@ EXPORTS = {
                                    c_void_p, c_void_p, c_uint64, c_uint64, c_int32, c_void_p]),
     "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_estimator": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "afqmc_population_control": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_uint64, c_uint64, c_double, c_void_p]),
     "afqmc_philox_normal": (c_int, [c_void_p, c_uint64, c_uint64, c_uint32, c_int32, c_int32,
                                     c_void_p]),
 }
@@ -119,7 +122,7 @@ class Context:
     """Owns an afqmc_ctx and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
-                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0):
+                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0, xbar_cap=0.0):
         import numpy as np
         lib = load_library()
         if not torch.cuda.is_available():
@@ -132,7 +135,8 @@ class Context:
         self.sys = afqmc_system(self.M, self.N, self.G, self.K, self.P, int(system.hidden_kind),
                                 float(system.coupling), dp(self._host[0]), dp(self._host[1]),
                                 dp(self._host[2]), dp(self._host[3]), float(dtau), int(n_taylor),
-                                int(weight_mode), int(proposal), float(rw_step), 0)
+                                int(weight_mode), int(proposal), float(rw_step), 0,
+                                float(xbar_cap))
         self.dtau = float(dtau)
         self.device = torch.device("cuda", device)
         self.handle = c_void_p()
@@ -251,6 +255,17 @@ def afqmc_reorthogonalize(ctx, nw, phi, logov=None):
     c = ctx
     c._call("afqmc_reorthogonalize", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
             _ptr(logov, torch.complex128, nw * c.P, "logov", allow_none=True))
+
+
+def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=0.0, parent=None):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_population_control", nw,
+            _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"), _ptr(w, torch.float64, nw, "w"),
+            _ptr(y, torch.float64, nw * c.P * c.K, "y"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"), int(seed), int(step), float(w_cap),
+            _ptr(parent, torch.int32, nw, "parent", allow_none=True))
 
 
 def afqmc_estimator(ctx, nw, w, eloc, out):

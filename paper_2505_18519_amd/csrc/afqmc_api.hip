@@ -97,6 +97,20 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   off += align256(S * 16);
   L.acc = off;
   off += align256((size_t)nw * 4);
+  L.pc_C = off;
+  off += align256((size_t)nw * 8);
+  L.pc_tot = off;
+  off += 256;
+  L.pc_parent = off;
+  off += align256((size_t)nw * 4);
+  L.pc_phi = off;
+  off += align256((size_t)nw * 2 * c->M * c->N * 16);
+  L.pc_y = off;
+  off += align256(S * c->K * 8);
+  L.pc_phiT = off;
+  off += align256(S * c->M * c->N * 8);
+  L.pc_logov = off;
+  off += align256(S * 16);
   L.total = off;
   return L;
 }
@@ -117,6 +131,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if (sys->proposal < 0 || sys->proposal > 1) return AFQMC_E_INVALID;
   if (sys->precision != AFQMC_PREC_FP64) return AFQMC_E_UNSUPPORTED;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
+  if (!(sys->xbar_cap >= 0.0)) return AFQMC_E_INVALID;
 
   afqmc_ctx_s* c = new (std::nothrow) afqmc_ctx_s();
   if (c == nullptr) return AFQMC_E_NOMEM;
@@ -136,6 +151,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   c->weight_mode = sys->weight_mode;
   c->proposal = sys->proposal;
   c->precision = sys->precision;
+  c->xbar_cap = sys->xbar_cap;
 
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) {
@@ -408,6 +424,45 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx c, int32_t nw, void* phi, void* log
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, phi, "phi");
   HIPCALL(c, launch_qr(c, nw, static_cast<double*>(phi), static_cast<double*>(logov)), "qr");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double* w, double* y,
+                                      double* phiT, void* logov, uint64_t seed, uint64_t step,
+                                      double w_cap, int32_t* parent) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, w, "w");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  if (!(w_cap >= 0.0)) return fail(c, AFQMC_E_INVALID, "w_cap must be >= 0");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  int* par = parent ? parent : ws_ptr<int>(c, L.pc_parent);
+  HIPCALL(c,
+          launch_comb(c, nw, w_cap, w, ws_ptr<double>(c, L.pc_C), ws_ptr<double>(c, L.pc_tot), par,
+                      seed, step),
+          "comb");
+  const size_t S = (size_t)c->P;
+  struct {
+    double* state;
+    size_t off, row;
+  } parts[4] = {{static_cast<double*>(phi), L.pc_phi, (size_t)2 * c->M * c->N * 2},
+                {y, L.pc_y, S * c->K},
+                {phiT, L.pc_phiT, S * c->M * c->N},
+                {static_cast<double*>(logov), L.pc_logov, S * 2}};
+  for (auto& pt : parts) {
+    double* tmp = ws_ptr<double>(c, pt.off);
+    HIPCALL(c, launch_gather(c, nw, pt.row, par, pt.state, tmp), "gather");
+    HIPCALL(c,
+            hipMemcpyAsync(pt.state, tmp, (size_t)nw * pt.row * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream),
+            "gather copy");
+  }
   return AFQMC_OK;
 }
 

@@ -14,7 +14,7 @@ struct afqmc_ctx_s {
   hipStream_t stream = nullptr;
   int M = 0, N = 0, G = 0, K = 0, P = 0, hidden_kind = 0;
   int MT = 0;  // M rounded up to a multiple of 16
-  double coupling = 0, dtau = 0, rw_step = 0;
+  double coupling = 0, dtau = 0, rw_step = 0, xbar_cap = 0;
   int n_taylor = 10, weight_mode = 0, proposal = 0, precision = 0;
 
   // device copies owned by the context
@@ -40,7 +40,8 @@ struct afqmc_ctx_s {
 
 // Workspace carve-up for nw walkers (byte offsets, 256-aligned).
 struct ws_layout {
-  size_t vb, ep, vmat, ytry, phiTtry, ltry, acc, total;
+  size_t vb, ep, vmat, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
+      pc_logov, total;
 };
 ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw);
 
@@ -79,3 +80,7 @@ hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t st
                                 int nw, int n, double* out);
 hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y);
 hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
+hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, double* C,
+                       double* tot, int* parent, uint64_t seed, uint64_t step);
+hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
+                         const double* src, double* dst);

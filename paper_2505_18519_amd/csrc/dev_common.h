@@ -48,7 +48,9 @@ __device__ __forceinline__ void cst(double* p, cplx v) {
 // ---------------------------------------------------------------------------
 // FP64 matrix core: D(16x16) += A(16x4) B(4x16).
 // Lane l = 16 g + c (g = l / 16, c = l % 16) supplies A[c][g] and B[g][c] and
-// holds D[4 g + r][c] in element r of the accumulator.
+// holds D[g + 4 r][c] in element r of the accumulator (rows interleaved by 4).
+// A product over m visited as k-steps (t, r) with m = 16 t + 4 r + g therefore
+// takes the accumulator of tile t, element r, directly as its next operand.
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
 

@@ -14,7 +14,7 @@
 // whole loop over g.  L_g is double-buffered in LDS and shared by the CW
 // wavefronts.  Stage 1 (Y_g^T = L_g Phi_T) leaves Y_g in the accumulator
 // layout, which is exactly the A-operand layout of stage 2 when the
-// contraction index m is visited in the order m = 16 t + 4 g + r, so the two
+// contraction index m is visited in the order m = 16 t + 4 r + g, so the two
 // stages chain in registers.  tr(f f) needs f transposed: it goes through a
 // per-wave 8 KB LDS tile.  Nothing of size n_chol x N^2 touches HBM.
 #include "afqmc_internal.h"
@@ -44,14 +44,14 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
   bool active = s < n_samples;
   if (active) active = !__builtin_isinf(logov[2 * s]);  // singular paths contribute zero
 
-  // B operands: bT[t][r] = Phi_T[16t+4g+r][c]; bth[sp][ri][t][r] = Theta^sp[16t+4g+r][c]
+  // B operands: bT[t][r] = Phi_T[16t+4r+g][c]; bth[sp][ri][t][r] = Theta^sp[16t+4r+g][c]
   double bT[NTILE][4];
   double bth[2][2][NTILE][4];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * t + 4 * g + r;
+      const int m = 16 * t + 4 * r + g;
       const bool ok = active && m < M && c < N;
       bT[t][r] = ok ? phiT[((size_t)s * M + m) * N + c] : 0.0;
 #pragma unroll
@@ -96,7 +96,7 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
     }
     if (active) {
       const double* Ls = s_L[b];
-      // stage 1: y1[tp] = (L_g Phi_T)[16tp + 4g + r][c]
+      // stage 1: y1[tp] = (L_g Phi_T)[16tp + 4r + g][c]
       dx4 y1[NTILE];
 #pragma unroll
       for (int tp = 0; tp < NTILE; ++tp) y1[tp] = dx4_zero();
@@ -106,11 +106,11 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int tp = 0; tp < NTILE; ++tp) {
-            // A[i=c][k=g] = L[16tp+c][16t+4g+r] = L[16t+4g+r][16tp+c] (L symmetric)
-            const double av = Ls[(16 * t + 4 * g + r) * MT + 16 * tp + c];
+            // A[i=c][k=g] = L[16tp+c][16t+4r+g] = L[16t+4r+g][16tp+c] (L symmetric)
+            const double av = Ls[(16 * t + 4 * r + g) * MT + 16 * tp + c];
             y1[tp] = mfma_f64(av, bT[t][r], y1[tp]);
           }
-      // stage 2: f[sp][ri] = sum_m Y[c'][m] Theta^sp[m][c]  (rows 4g+r, col c)
+      // stage 2: f[sp][ri] = sum_m Y[c'][m] Theta^sp[m][c]  (rows g+4r, col c)
       dx4 f[2][2];
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) f[sp][0] = f[sp][1] = dx4_zero();
@@ -124,11 +124,11 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
             for (int ri = 0; ri < 2; ++ri)
               f[sp][ri] = mfma_f64(y1[t][r], bth[sp][ri][t][r], f[sp][ri]);
 
-      // diagonal: element (4g+r, c) with c == 4g+r
+      // diagonal: element (g+4r, c) with c == g+4r
       double d_re = 0.0, d_im = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (c == 4 * g + r) {
+        if (c == g + 4 * r) {
           d_re = f[0][0][r] + f[1][0][r];
           d_im = f[0][1][r] + f[1][1][r];
         }
@@ -148,7 +148,7 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
 #pragma unroll
           for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sf[2 * sp + ri][4 * g + r][c] = f[sp][ri][r];
+            for (int r = 0; r < 4; ++r) sf[2 * sp + ri][g + 4 * r][c] = f[sp][ri][r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -156,8 +156,8 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const double tr_ = sf[2 * sp][c][4 * g + r];
-            const double ti_ = sf[2 * sp + 1][c][4 * g + r];
+            const double tr_ = sf[2 * sp][c][g + 4 * r];
+            const double ti_ = sf[2 * sp + 1][c][g + 4 * r];
             const double ar = f[sp][0][r], ai = f[sp][1][r];
             ex_re += ar * tr_ - ai * ti_;
             ex_im += ar * ti_ + ai * tr_;
@@ -201,7 +201,7 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
 // S_p = exp(i Im l_p) (0 if singular), xbar_g = -i sqrt(tau) sum S vb / sum S,
 // E_L = sum S E_p / sum S.  One workgroup of 64 threads per walker.
 __global__ void __launch_bounds__(64)
-k_combine(int nw, int P, int G, double sqrt_tau, const double* __restrict__ vb,
+k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* __restrict__ vb,
           const double* __restrict__ ep, const double* __restrict__ logov,
           double* __restrict__ xbar, double* __restrict__ eloc) {
   __shared__ double s_S[64][2];
@@ -224,8 +224,13 @@ k_combine(int nw, int P, int G, double sqrt_tau, const double* __restrict__ vb,
       for (int p = 0; p < P; ++p)
         num = cfma(num, cmk(s_S[p][0], s_S[p][1]), cld(vb + (((size_t)w * P + p) * G + gm) * 2));
       cplx v = good ? cdiv(num, den) : cmk(0.0, 0.0);
-      // -i sqrt(tau) v
-      cst(xbar + ((size_t)w * G + gm) * 2, cmk(sqrt_tau * v.im, -sqrt_tau * v.re));
+      // -i sqrt(tau) v, modulus optionally clipped to xbar_cap
+      cplx xb = cmk(sqrt_tau * v.im, -sqrt_tau * v.re);
+      if (xbar_cap > 0.0) {
+        const double mag = sqrt(cabs2(xb));
+        if (mag > xbar_cap) xb = cscale(xb, xbar_cap / mag);
+      }
+      cst(xbar + ((size_t)w * G + gm) * 2, xb);
     }
   }
   if (eloc != nullptr && lane == 0) {
@@ -265,6 +270,6 @@ hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const 
   if (nw <= 0) return hipSuccess;
   if (c->P > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_combine, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, sqrt(c->dtau),
-                     vb, ep, logov, xbar, eloc);
+                     c->xbar_cap, vb, ep, logov, xbar, eloc);
   return hipGetLastError();
 }

@@ -35,7 +35,7 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   const double* pT = phiT + (size_t)s * M * N;
   const double* pw = phi + (size_t)w * 2 * M * N * 2;
 
-  // 1. A^s via MFMA: tiles (re up, im up, re dn, im dn); lane holds A[4g+r][c]
+  // 1. A^s via MFMA: tiles (re up, im up, re dn, im dn); lane holds A[g+4r][c]
   dx4 acc[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
 #pragma unroll 4
   for (int q = 0; q < MT / 4; ++q) {
@@ -59,8 +59,8 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      s_lu[wave][sp][4 * g + r][c][0] = acc[2 * sp][r];
-      s_lu[wave][sp][4 * g + r][c][1] = acc[2 * sp + 1][r];
+      s_lu[wave][sp][g + 4 * r][c][0] = acc[2 * sp][r];
+      s_lu[wave][sp][g + 4 * r][c][1] = acc[2 * sp + 1][r];
     }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();

@@ -1,0 +1,107 @@
+// Comb population control: optional weight cap, inclusive prefix sums of W,
+// comb teeth (j + u) sum(W) / nw, parent of each new walker, gather.
+#include <algorithm>
+
+#include "afqmc_internal.h"
+#include "dev_common.h"
+
+namespace {
+
+constexpr int PC_THREADS = 1024;
+
+// One block: W <- min(W, cap * mean W) (cap > 0), C = inclusive prefix sums of
+// W (written to C), tot[0] = sum W.  Each thread scans a contiguous chunk.
+__global__ void __launch_bounds__(PC_THREADS)
+k_comb_scan(int nw, double w_cap, const double* __restrict__ w, double* __restrict__ C,
+            double* __restrict__ tot) {
+  __shared__ double s_part[PC_THREADS];
+  __shared__ double s_mean;
+  const int tid = threadIdx.x;
+  const int chunk = (nw + PC_THREADS - 1) / PC_THREADS;
+  const int b = tid * chunk, e = min(b + chunk, nw);
+  double acc = 0.0;
+  for (int k = b; k < e; ++k) acc += w[k];
+  s_part[tid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int q = 0; q < PC_THREADS; ++q) s += s_part[q];
+    s_mean = s / (double)nw;
+  }
+  __syncthreads();
+  const double cap = (w_cap > 0.0) ? w_cap * s_mean : __builtin_huge_val();
+  acc = 0.0;
+  for (int k = b; k < e; ++k) acc += fmin(w[k], cap);
+  s_part[tid] = acc;
+  __syncthreads();
+  // exclusive offsets of the chunks (Hillis-Steele on the 1024 partial sums)
+  for (int o = 1; o < PC_THREADS; o <<= 1) {
+    const double v = (tid >= o) ? s_part[tid - o] : 0.0;
+    __syncthreads();
+    s_part[tid] += v;
+    __syncthreads();
+  }
+  double run = (tid > 0) ? s_part[tid - 1] : 0.0;
+  for (int k = b; k < e; ++k) {
+    run += fmin(w[k], cap);
+    C[k] = run;
+  }
+  if (tid == PC_THREADS - 1) tot[0] = s_part[PC_THREADS - 1];
+}
+
+// parent[j] = min{k : C_k > (j + u) tot / nw}; new weight tot / nw
+__global__ void k_comb_parent(int nw, uint64_t seed, uint64_t step, const double* __restrict__ C,
+                              const double* __restrict__ tot, int* __restrict__ parent,
+                              double* __restrict__ w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nw) return;
+  const double T = tot[0];
+  if (!(T > 0.0)) {  // dead (or non-finite) population: unchanged
+    parent[j] = j;
+    return;
+  }
+  const double u = stream_uniform(seed, 0, step, rng_word3(AFQMC_TAG_COMB, 0, 0), 0);
+  const double t = ((double)j + u) * (T / (double)nw);
+  int lo = 0, hi = nw - 1;  // first k with C[k] > t, clamped to nw - 1
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] > t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  parent[j] = lo;
+  w[j] = T / (double)nw;
+}
+
+// dst[j] = src[parent[j]] for rows of `row` doubles; block b copies chunk
+// b % nchunk of walker b / nchunk
+__global__ void k_gather_rows(int nw, size_t row, int nchunk, const int* __restrict__ parent,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const int j = blockIdx.x / nchunk;
+  const int ch = blockIdx.x % nchunk;
+  if (j >= nw) return;
+  const size_t base_d = (size_t)j * row, base_s = (size_t)parent[j] * row;
+  for (size_t q = (size_t)ch * blockDim.x + threadIdx.x; q < row; q += (size_t)nchunk * blockDim.x)
+    dst[base_d + q] = src[base_s + q];
+}
+
+}  // namespace
+
+hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, double* C,
+                       double* tot, int* parent, uint64_t seed, uint64_t step) {
+  hipLaunchKernelGGL(k_comb_scan, dim3(1), dim3(PC_THREADS), 0, c->stream, nw, w_cap, w, C, tot);
+  AFQMC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_comb_parent, dim3((nw + 255) / 256), dim3(256), 0, c->stream, nw, seed, step,
+                     C, tot, parent, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
+                         const double* src, double* dst) {
+  if (nw <= 0 || row == 0) return hipSuccess;
+  const int nchunk = (int)std::min<size_t>((row + 255) / 256, 64);
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)(nchunk * nw)), dim3(256), 0, c->stream, nw, row,
+                     nchunk, parent, src, dst);
+  return hipGetLastError();
+}

@@ -90,13 +90,13 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
   const double* V = vmat + (size_t)w * M * M * 2;
   double* ph = phi + (size_t)w * 2 * M * N * 2;
 
-  // A operands: rows 16 wave + c, columns 16t + 4g + r (V, E_h symmetric)
+  // A operands: rows 16 wave + c, columns 16t + 4r + g (V, E_h symmetric)
   double vr[NTILE][4], vi[NTILE][4], nvi[NTILE][4], eh[NTILE][4];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * g + r, col = 16 * wave + c;
+      const int row = 16 * t + 4 * r + g, col = 16 * wave + c;
       const bool ok = row < M && col < M;
       vr[t][r] = ok ? V[((size_t)row * M + col) * 2] : 0.0;
       vi[t][r] = ok ? V[((size_t)row * M + col) * 2 + 1] : 0.0;
@@ -127,7 +127,7 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const double* yb = s_y[src][16 * t + 4 * g + r][16 * ct + c];
+          const double* yb = s_y[src][16 * t + 4 * r + g][16 * ct + c];
           o[ct][0] = mfma_f64(eh[t][r], yb[0], o[ct][0]);
           o[ct][1] = mfma_f64(eh[t][r], yb[1], o[ct][1]);
         }
@@ -137,8 +137,8 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        s_y[dst][16 * wave + 4 * g + r][16 * ct + c][0] = o[ct][0][r];
-        s_y[dst][16 * wave + 4 * g + r][16 * ct + c][1] = o[ct][1][r];
+        s_y[dst][16 * wave + 4 * r + g][16 * ct + c][0] = o[ct][0][r];
+        s_y[dst][16 * wave + 4 * r + g][16 * ct + c][1] = o[ct][1][r];
       }
   };
 
@@ -158,7 +158,7 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const double* yb = s_y[cur][16 * t + 4 * g + r][16 * ct + c];
+          const double* yb = s_y[cur][16 * t + 4 * r + g][16 * ct + c];
           const double yr = yb[0], yi = yb[1];
           acc[ct][0] = mfma_f64(vr[t][r], yr, acc[ct][0]);
           acc[ct][0] = mfma_f64(nvi[t][r], yi, acc[ct][0]);
@@ -183,7 +183,7 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
   for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * wave + 4 * g + r;
+      const int m = 16 * wave + 4 * r + g;
       if (m < M && c < N) {
         double* d = ph + ((size_t)(ct * M + m) * N + c) * 2;
         d[0] = o[ct][0][r];

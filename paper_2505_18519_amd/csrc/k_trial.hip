@@ -5,7 +5,7 @@
 // U = c sum_k y_k A_k is assembled one 16-row tile at a time in LDS from the
 // row-sorted entry list and then held in registers as MFMA A operands.  The
 // Taylor series sum_j U^j Phi_0 / j! is run term by term: with the k index of
-// the product taken in the order (16 t + 4 g + r) the accumulator of one term
+// the product taken in the order (16 t + 4 r + g) the accumulator of one term
 // is, register for register, the B operand of the next, so the series needs
 // no LDS traffic.  Terms are added until max|term| <= 2^-60 max|sum|; when the
 // row-sum norm of U exceeds 8 the series is applied s = ceil(norm / 8) times
@@ -41,7 +41,7 @@ k_trial_build(int n_samples, int M, int N, int K, double coupling, const double*
   if (active)
     for (int k = lane; k < K; k += 64) ys[k] = y[(size_t)s * K + k];
 
-  // U in registers: ua[tp][t][r] = U[16 tp + c][16 t + 4 g + r]
+  // U in registers: ua[tp][t][r] = U[16 tp + c][16 t + 4 r + g]
   double ua[NTILE][NTILE][4];
   double rownorm = 0.0;
 #pragma unroll
@@ -63,7 +63,7 @@ k_trial_build(int n_samples, int M, int N, int K, double coupling, const double*
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        ua[tp][t][r] = tile[c * MT + 16 * t + 4 * g + r];
+        ua[tp][t][r] = tile[c * MT + 16 * t + 4 * r + g];
         rs += fabs(ua[tp][t][r]);
       }
     rs += __shfl_xor(rs, 16, 64);
@@ -88,13 +88,13 @@ k_trial_build(int n_samples, int M, int N, int K, double coupling, const double*
         for (int r = 0; r < 4; ++r) ua[tp][t][r] *= inv;
   }
 
-  // X = Phi_0 in the accumulator layout: x[t][r] = X[16 t + 4 g + r][c]
+  // X = Phi_0 in the accumulator layout: x[t][r] = X[16 t + 4 r + g][c]
   double x[NTILE][4];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int m = 16 * t + 4 * g + r;
+      int m = 16 * t + 4 * r + g;
       x[t][r] = (m < M && c < N) ? phi0[m * N + c] : 0.0;
     }
 
@@ -140,7 +140,7 @@ k_trial_build(int n_samples, int M, int N, int K, double coupling, const double*
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int m = 16 * t + 4 * g + r;
+      int m = 16 * t + 4 * r + g;
       if (m < M && c < N) out[m * N + c] = x[t][r];
     }
 }

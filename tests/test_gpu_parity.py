@@ -185,7 +185,9 @@ def test_metropolis_and_handoff(case, proposal):
     A.afqmc_metropolis_x(ctx, nw, dev(phi), dy, dphiT, dl, dev(ref), dw, seed, stp, nsw, dacc)
     torch.cuda.synchronize()
     assert np.array_equal(host(dacc), nacc), (host(dacc), nacc)
-    assert np.array_equal(host(dy), y2)
+    # accept decisions are exact; accepted Gaussian proposals carry the
+    # device's Box-Muller normals, equal to the oracle's within a few ulp
+    assert np.abs(host(dy) - y2).max() <= 4e-15 * max(np.abs(y2).max(), 1.0)
     assert rel(host(dphiT), phiT2) <= 1e-12
     check_logov(host(dl), ell2)
     assert np.abs(host(dw) - w2).max() <= TOL * np.abs(w2).max()
@@ -289,7 +291,7 @@ def test_trajectory_tiny_matches_oracle():
         g = host(est[i])
         assert abs(g[0] / g[1] - rec["e_num"] / rec["e_den"]) <= TOL * abs(rec["e_num"] / rec["e_den"]), i
         assert abs(g[1] - rec["e_den"]) <= TOL * rec["e_den"], i
-    assert np.array_equal(host(st.y), ost.y)
+    assert np.abs(host(st.y) - ost.y).max() <= 4e-15 * max(np.abs(ost.y).max(), 1.0)
     assert np.abs(host(st.w) - ost.w).max() <= TOL * np.abs(ost.w).max()
 
 
@@ -319,3 +321,49 @@ def test_full_size_sampled_walkers():
     assert np.abs(g_el - eloc).max() <= TOL * np.abs(eloc).max()
     for k, w in enumerate(pick):
         assert rel(host(d_xb)[w], xbar[k]) <= TOL
+
+
+def test_population_control_matches_oracle_comb():
+    _say("population control")
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5)
+    P, nw = 3, 37
+    ctx = make_ctx(s, P, nw)
+    rng, phi, y = state(s, P, nw, 9)
+    phiT = O.trial_det(s, y)
+    ell = O.log_overlap(phiT, phi)
+    w = rng.exponential(size=nw)
+    w[[3, 10]] = 0.0
+    w[5] = 40.0
+    for w_cap in (0.0, 4.0):
+        parent, wn = O.comb(w, 55, 3, w_cap)
+        dphi, dw, dy, dphiT, dl = dev(phi), dev(w), dev(y), dev(phiT), dev(ell)
+        dpar = torch.zeros(nw, dtype=torch.int32, device="cuda")
+        A.afqmc_population_control(ctx, nw, dphi, dw, dy, dphiT, dl, 55, 3, w_cap, dpar)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(dpar), parent)
+        assert np.abs(host(dw) - wn).max() <= 1e-14 * wn.max()
+        assert np.array_equal(host(dphi), phi[parent])
+        assert np.array_equal(host(dy), y[parent])
+        assert np.array_equal(host(dphiT), phiT[parent])
+        assert np.array_equal(host(dl), ell[parent])
+
+
+def test_force_bias_cap():
+    _say("xbar cap")
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5)
+    P, nw, dtau, cap = 3, 6, 0.05, 0.05
+    ctx = make_ctx(s, P, nw, dtau=dtau, xbar_cap=cap)
+    rng, phi, y = state(s, P, nw, 10, spread=1.0)
+    phiT = O.trial_det(s, y)
+    ell, theta = O.green(phiT, phi)
+    vb, ep = O.sample_contraction(s, phiT, theta, ell)
+    xbar, eloc = O.walker_estimates(vb, ep, ell, dtau, xbar_cap=cap)
+    assert np.abs(xbar).max() <= cap * (1 + 1e-12)
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, s.n_chol, dtype=torch.complex128, device="cuda")
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dev(theta), dev(ell), d_el, None, d_xb)
+    torch.cuda.synchronize()
+    for w in range(nw):
+        assert rel(host(d_xb)[w], xbar[w]) <= TOL

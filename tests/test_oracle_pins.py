@@ -461,3 +461,24 @@ def test_estimator_exact_sum():
     e = np.array([1.0, 1.0, 1.0, 1.0]) + 0j
     num, den = O.estimator(np.abs(w), e)
     assert num == math.fsum(np.abs(w))
+
+
+def test_comb_population_control_properties():
+    """The comb keeps the total weight, gives walker k either floor or ceil of
+    nw W_k / sum W copies, none to zero-weight walkers, and with a cap first
+    clips weights to cap x mean."""
+    rng = np.random.default_rng(12)
+    nw = 200
+    w = rng.exponential(size=nw)
+    w[::17] = 0.0
+    for cap in (0.0, 3.0):
+        parent, wn = O.comb(w, 9, 4, cap)
+        wc = np.minimum(w, cap * w.mean()) if cap > 0 else w
+        assert np.allclose(wn, wc.sum() / nw) and math.isclose(wn.sum(), wc.sum(), rel_tol=1e-13)
+        counts = np.bincount(parent, minlength=nw)
+        expect = nw * wc / wc.sum()
+        assert np.all(counts >= np.floor(expect) - 1e-9) and np.all(counts <= np.ceil(expect) + 1e-9)
+        assert np.all(counts[wc == 0] == 0)
+        assert np.all(np.diff(parent) >= 0)
+    p0, w0 = O.comb(np.zeros(5), 1, 1)
+    assert np.array_equal(p0, np.arange(5))
