@@ -187,6 +187,7 @@ def afqmc_sample_prior(ctx, nw, seed, y):
 
 
 def afqmc_trial_build(ctx, nw, y, phiT):
+    ctx.reserve(nw)
     ctx._call("afqmc_trial_build", nw, _ptr(y, torch.float64, nw * ctx.P * ctx.K, "y"),
               _ptr(phiT, torch.float64, nw * ctx.P * ctx.M * ctx.N, "phiT"))
 

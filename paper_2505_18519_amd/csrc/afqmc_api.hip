@@ -32,9 +32,7 @@ hipError_t dev_copy(T** dst, const T* src, size_t n) {
 }
 
 void free_ctx(afqmc_ctx_s* c) {
-  void* ptrs[] = {c->d_h1,      c->d_Lraw,    c->d_Lpad,    c->d_Eh,
-                  c->d_phi0,    c->d_row_ptr, c->d_ent_col, c->d_ent_row,
-                  c->d_ent_kptr, c->d_con_k,  c->d_con_v};
+  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -89,6 +87,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   off += align256(S * 16);
   L.vmat = off;
   off += align256((size_t)nw * c->M * c->M * 16);
+  L.ubuf = off;
+  off += align256(S * c->M * c->M * 8);
   L.ytry = off;
   off += align256(S * c->K * 8);
   L.phiTtry = off;
@@ -165,42 +165,11 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     for (int i = 0; i < M; ++i)
       for (int j = 0; j < M; ++j)
         Lpad[((size_t)gm * MT + i) * MT + j] = sys->L[((size_t)gm * M + i) * M + j];
-  // entry list of sum_k y_k A_k: distinct nonzero (i, j) in row order
-  std::vector<int> row_ptr(M + 1, 0), ent_row, ent_col, ent_kptr(1, 0), con_k;
-  std::vector<double> con_v;
-  for (int i = 0; i < M; ++i) {
-    row_ptr[i] = (int)ent_col.size();
-    for (int j = 0; j < M; ++j) {
-      bool any = false;
-      for (int k = 0; k < K; ++k) {
-        const double v = sys->A[((size_t)k * M + i) * M + j];
-        if (v != 0.0) {
-          con_k.push_back(k);
-          con_v.push_back(v);
-          any = true;
-        }
-      }
-      if (any) {
-        ent_row.push_back(i);
-        ent_col.push_back(j);
-        ent_kptr.push_back((int)con_k.size());
-      }
-    }
-  }
-  row_ptr[M] = (int)ent_col.size();
-  c->n_ent = (int)ent_col.size();
-  c->n_contrib = (int)con_k.size();
-
   if ((e = dev_copy(&c->d_h1, sys->h1, (size_t)M * M)) != hipSuccess ||
       (e = dev_copy(&c->d_Lraw, sys->L, (size_t)G * M * M)) != hipSuccess ||
       (e = dev_copy(&c->d_Lpad, Lpad.data(), Lpad.size())) != hipSuccess ||
       (e = dev_copy(&c->d_phi0, sys->phi0, (size_t)M * N)) != hipSuccess ||
-      (e = dev_copy(&c->d_row_ptr, row_ptr.data(), row_ptr.size())) != hipSuccess ||
-      (e = dev_copy(&c->d_ent_row, ent_row.data(), ent_row.size())) != hipSuccess ||
-      (e = dev_copy(&c->d_ent_col, ent_col.data(), ent_col.size())) != hipSuccess ||
-      (e = dev_copy(&c->d_ent_kptr, ent_kptr.data(), ent_kptr.size())) != hipSuccess ||
-      (e = dev_copy(&c->d_con_k, con_k.data(), con_k.size())) != hipSuccess ||
-      (e = dev_copy(&c->d_con_v, con_v.data(), con_v.size())) != hipSuccess ||
+      (e = dev_copy(&c->d_A, sys->A, (size_t)K * M * M)) != hipSuccess ||
       (e = hipMalloc(&c->d_Eh, (size_t)M * M * sizeof(double))) != hipSuccess) {
     free_ctx(c);
     delete c;
@@ -267,7 +236,10 @@ afqmc_status afqmc_trial_build(afqmc_ctx c, int32_t nw, const double* y, double*
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, y, "y");
   REQUIRE(c, phiT, "phiT");
-  HIPCALL(c, launch_trial_build(c, nw * c->P, y, phiT), "trial_build");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  HIPCALL(c, launch_trial_build(c, nw * c->P, y, phiT, ws_ptr<double>(c, L.ubuf)), "trial_build");
   return AFQMC_OK;
 }
 
@@ -408,7 +380,8 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
     for (int f = 0; f < nflip; ++f) {
       const int flip_k = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? f : -1;
       HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k), "proposal");
-      HIPCALL(c, launch_trial_build(c, nw * c->P, ytry, phiTtry), "proposal trial build");
+      HIPCALL(c, launch_trial_build(c, nw * c->P, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+              "proposal trial build");
       HIPCALL(c, launch_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
       HIPCALL(c, launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, flip_k),
               "accept");

@@ -23,15 +23,7 @@ struct afqmc_ctx_s {
   double* d_Lpad = nullptr;  // [G+1][MT][MT], zero padded; slab G holds h1'
   double* d_Eh = nullptr;    // [M][M] = exp(-tau h1 / 2)
   double* d_phi0 = nullptr;  // [M][N]
-  // trial generators as a row-sorted list of distinct (i, j) entries of
-  // sum_k y_k A_k, each with its (k, value) contributions
-  int n_ent = 0, n_contrib = 0;
-  int* d_row_ptr = nullptr;    // [M+1] first entry of each row
-  int* d_ent_col = nullptr;    // [n_ent]
-  int* d_ent_row = nullptr;    // [n_ent]
-  int* d_ent_kptr = nullptr;   // [n_ent+1]
-  int* d_con_k = nullptr;      // [n_contrib]
-  double* d_con_v = nullptr;   // [n_contrib]
+  double* d_A = nullptr;      // [K][M][M] trial generators (dense)
 
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -40,7 +32,7 @@ struct afqmc_ctx_s {
 
 // Workspace carve-up for nw walkers (byte offsets, 256-aligned).
 struct ws_layout {
-  size_t vb, ep, vmat, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
+  size_t vb, ep, vmat, ubuf, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
       pc_logov, total;
 };
 ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw);
@@ -53,7 +45,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw);
 
 // kernel launchers (each returns the first HIP error it sees)
 hipError_t launch_setup(afqmc_ctx_s* c);
-hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT);
+hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
+                              double* ubuf);
 hipError_t launch_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
                           double* logov, double* theta);
 hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,

@@ -35,6 +35,7 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
   constexpr int NQ = (NV2 + CW * 64 - 1) / (CW * 64);  // per thread
   __shared__ double s_L[2][SLAB];
   __shared__ double s_f[CW][4][16][17];
+  __shared__ double s_dg[CW][16][2][16];  // diagonal partials of 16 vectors
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -75,6 +76,32 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
   double vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
   double ex_re = 0.0, ex_im = 0.0;
   double(*sf)[16][17] = s_f[wave];
+  double(*sdg)[2][16] = s_dg[wave];
+  // lanes holding a diagonal element f[c][c] (c = g + 4 r): r = c / 4 when c % 4 == g
+  const bool diag_lane = (c & 3) == g;
+  // bulk reduction of 16 staged vectors: lane l < 32 sums part l / 16 of vector l % 16
+  auto flush = [&](int g_first, int count) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int gl = lane & 15, part = (lane >> 4) & 1;
+    double v = 0.0;
+    if (lane < 32 && gl < count) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v += sdg[gl][part][q];
+    }
+    const double vi = __shfl_down(v, 16, 64);  // lanes < 16: imaginary part
+    if (lane < 16 && gl < count) {
+      vb2_re += v * v - vi * vi;
+      vb2_im += 2.0 * v * vi;
+      double* o = vb + ((size_t)s * G + g_first + gl) * 2;
+      o[0] = v;
+      o[1] = vi;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
 
   for (int gam = 0; gam <= G; ++gam) {
     const int b = gam & 1;
@@ -124,7 +151,7 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
             for (int ri = 0; ri < 2; ++ri)
               f[sp][ri] = mfma_f64(y1[t][r], bth[sp][ri][t][r], f[sp][ri]);
 
-      // diagonal: element (g+4r, c) with c == g+4r
+      // diagonal: element (g+4r, c) with c == g+4r, summed over the spins
       double d_re = 0.0, d_im = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -132,15 +159,11 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
           d_re = f[0][0][r] + f[1][0][r];
           d_im = f[0][1][r] + f[1][1][r];
         }
-      d_re = wave_sum(d_re);
-      d_im = wave_sum(d_im);
       if (gam < G) {
-        vb2_re += d_re * d_re - d_im * d_im;
-        vb2_im += 2.0 * d_re * d_im;
-        if (lane == 0) {
-          double* o = vb + ((size_t)s * G + gam) * 2;
-          o[0] = d_re;
-          o[1] = d_im;
+        // stage this lane's diagonal element; vb_g = sum over the 16 lanes
+        if (diag_lane) {
+          sdg[gam & 15][0][c] = d_re;
+          sdg[gam & 15][1][c] = d_im;
         }
         // exchange: sum_ij f_ij f_ji, transpose through LDS
 #pragma unroll
@@ -165,9 +188,10 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if ((gam & 15) == 15 || gam == G - 1) flush(gam & ~15, (gam & 15) + 1);
       } else {
-        e1_re = d_re;
-        e1_im = d_im;
+        e1_re = wave_sum(d_re);
+        e1_im = wave_sum(d_im);
       }
     }
     if (has_next) {
@@ -182,6 +206,8 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
   if (s < n_samples) {
     ex_re = wave_sum(ex_re);
     ex_im = wave_sum(ex_im);
+    vb2_re = wave_sum(vb2_re);
+    vb2_im = wave_sum(vb2_im);
     if (lane == 0) {
       double* o = ep + (size_t)s * 2;
       if (active) {

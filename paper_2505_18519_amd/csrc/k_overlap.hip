@@ -7,7 +7,7 @@
 //  2. LU with partial pivoting, one lane per row (lanes 0-15 spin up, 16-31
 //     spin down), pivot rows found by a 16-lane max reduction (largest |a|^2,
 //     lowest row on ties) and broadcast by lane shuffles instead of swapped;
-//     log det = sum log u_kk + i (sum arg u_kk + pi parity(perm));
+//     det = parity(perm) prod u_kk, accumulated as a scaled complex product;
 //  3. optionally Theta^s = phi^s (A^s)^{-1}, one lane per orbital row m:
 //     z U = x, v L = z, Theta[m][perm[k]] = v[k].
 // A zero pivot marks the path singular: l = -inf + 0i and Theta = 0.
@@ -79,7 +79,10 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   bool used = (i >= N) || (lane >= 32);
   int mystep = -1;
   int perm[NT];
-  double logabs = 0.0, argsum = 0.0;
+  // det = prod of pivots, kept as a complex mantissa times 2^pexp so that it
+  // neither overflows nor needs a logarithm per step
+  cplx pprod = cmk(1.0, 0.0);
+  int pexp = 0;
   bool singular = false;
   const int base = lane & ~15;  // first lane of my 16-lane group
 #pragma unroll
@@ -109,8 +112,15 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
         used = true;
         mystep = k;
       }
-      logabs += 0.5 * log(cabs2(piv));
-      argsum += atan2(piv.im, piv.re);
+      pprod = cmul(pprod, piv);
+      {
+        const double mx = fmax(fabs(pprod.re), fabs(pprod.im));
+        if (mx > 0.0 && isfinite(mx)) {
+          const int ex = ilogb(mx);
+          pprod = cscale(pprod, ldexp(1.0, -ex));
+          pexp += ex;
+        }
+      }
       cplx l = cmk(0.0, 0.0);
       if (!used && !singular) {
         l = cdiv(a[k], piv);
@@ -130,7 +140,8 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
 #pragma unroll
     for (int y = x + 1; y < NT; ++y)
       if (y < N && perm[x] > perm[y]) ++inv;
-  argsum += (inv & 1) ? M_PI : 0.0;
+  double logabs = 0.5 * log(cabs2(pprod)) + (double)pexp * M_LN2;
+  double argsum = atan2(pprod.im, pprod.re) + ((inv & 1) ? M_PI : 0.0);
 
   // both spins' results to lane 0 of the wave
   const double la_dn = __shfl(logabs, 16, 64), ar_dn = __shfl(argsum, 16, 64);

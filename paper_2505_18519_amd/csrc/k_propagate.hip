@@ -16,57 +16,46 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // V build: with c = xi - xbar, R = sum_g Re(c_g) L_g and Q = sum_g Im(c_g) L_g,
-// V = sqrt(tau) (-Q + i R).  A (2 nw x G) by (G x M^2) product: each block
-// handles VB_W walkers and VB_E matrix entries; the coefficients sit in LDS.
-constexpr int VB_W = 16;
-constexpr int VB_E = 256;
-constexpr int VB_GC = 128;  // vectors per LDS chunk (32 KB of coefficients)
-
-__global__ void __launch_bounds__(VB_E)
+// V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the FP64
+// matrix cores: each wavefront takes 16 walkers (both Re c and Im c as A
+// operands) and 64 matrix entries; L is read once per 16 walkers.
+__global__ void __launch_bounds__(256)
 k_vbuild(int nw, int G, int MM, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
-  __shared__ double s_c[VB_GC][2 * VB_W];  // (re c, im c) per walker
-  const int w0 = blockIdx.y * VB_W;
-  const int e = blockIdx.x * VB_E + threadIdx.x;
-  double ar[VB_W], ai[VB_W];
-#pragma unroll
-  for (int q = 0; q < VB_W; ++q) ar[q] = ai[q] = 0.0;
-  for (int g0 = 0; g0 < G; g0 += VB_GC) {
-    const int ng = min(VB_GC, G - g0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < ng * VB_W; q += VB_E) {
-      const int gl = q / VB_W, wl = q % VB_W;
-      const int w = w0 + wl, gm = g0 + gl;
-      double cr = 0.0, ci = 0.0;
-      if (w < nw) {
-        cr = xi[(size_t)w * G + gm] - xbar[((size_t)w * G + gm) * 2];
-        ci = -xbar[((size_t)w * G + gm) * 2 + 1];
-      }
-      s_c[gl][wl] = cr;
-      s_c[gl][VB_W + wl] = ci;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int w0 = (blockIdx.y * 4 + wave) * 16;
+  const int e0 = blockIdx.x * 64;
+  if (w0 >= nw) return;
+  dx4 ar[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
+  dx4 ai[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
+  const int wa = w0 + c;
+  for (int k0 = 0; k0 < G; k0 += 4) {
+    const int k = k0 + g;
+    double cr = 0.0, ci = 0.0;
+    if (wa < nw && k < G) {
+      cr = xi[(size_t)wa * G + k] - xbar[((size_t)wa * G + k) * 2];
+      ci = -xbar[((size_t)wa * G + k) * 2 + 1];
     }
-    __syncthreads();
-    if (e < MM) {
-      for (int gl = 0; gl < ng; ++gl) {
-        const double l = L[(size_t)(g0 + gl) * MM + e];
 #pragma unroll
-        for (int q = 0; q < VB_W; ++q) {
-          ar[q] += s_c[gl][q] * l;
-          ai[q] += s_c[gl][VB_W + q] * l;
-        }
-      }
+    for (int et = 0; et < 4; ++et) {
+      const int e = e0 + 16 * et + c;
+      const double b = (k < G && e < MM) ? L[(size_t)k * MM + e] : 0.0;
+      ar[et] = mfma_f64(cr, b, ar[et]);
+      ai[et] = mfma_f64(ci, b, ai[et]);
     }
   }
-  if (e >= MM) return;
 #pragma unroll
-  for (int q = 0; q < VB_W; ++q) {
-    const int w = w0 + q;
-    if (w < nw) {
-      double* o = vmat + ((size_t)w * MM + e) * 2;
-      o[0] = -sqrt_tau * ai[q];
-      o[1] = sqrt_tau * ar[q];
+  for (int et = 0; et < 4; ++et)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int w = w0 + g + 4 * r, e = e0 + 16 * et + c;
+      if (w < nw && e < MM) {
+        double* o = vmat + ((size_t)w * MM + e) * 2;
+        o[0] = -sqrt_tau * ai[et][r];
+        o[1] = sqrt_tau * ar[et][r];
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -261,7 +250,7 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
                          double* vmat) {
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + VB_E - 1) / VB_E, (nw + VB_W - 1) / VB_W), block(VB_E);
+  dim3 grid((MM + 63) / 64, (nw + 63) / 64), block(256);
   hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, sqrt(c->dtau),
                      c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
