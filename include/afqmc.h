@@ -68,7 +68,11 @@ enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPL
  *        y_0 .. y_{K-1} in turn.  RW: Gaussian random walk y' = y + rw_step * eta. */
 enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1 };
 
-enum { AFQMC_PREC_FP64 = 0 };
+/* Precision of the Cholesky contraction (force bias and local energy):
+ * FP64 throughout, or FP32: Phi_T, Theta and L enter the FP32 matrix-core
+ * products with FP32 accumulation over the orbital index; traces, vb_g^2,
+ * the sums over g and every other step of the path stay FP64. */
+enum { AFQMC_PREC_FP64 = 0, AFQMC_PREC_FP32 = 1 };
 
 typedef struct {
   int32_t M;            /* one-particle basis size                         */
@@ -95,8 +99,10 @@ typedef struct {
 /* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and
  * e^{-tau h1/2} there, and binds the context to `stream` (a hipStream_t, NULL
  * for the default stream).  Host arrays may be freed on return.
- * Supported sizes: 1 <= N <= M <= 64, N <= 16, n_chol >= 1, 1 <= K <= 256,
- * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  Synchronises `stream`. */
+ * Supported sizes: 1 <= N <= M <= 128, N <= 32, n_chol >= 1, K >= 1,
+ * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  Systems with M <= 64 and
+ * N <= 16 use register-resident kernels, larger ones workgroup-per-path
+ * kernels.  Synchronises `stream`. */
 afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afqmc_ctx* out);
 afqmc_status afqmc_destroy(afqmc_ctx ctx);
 /* Text of the last error on this context (static storage owned by ctx). */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
 WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE = 0, 1, 2
 PROPOSAL_PRIOR, PROPOSAL_RW = 0, 1
+PREC_FP64, PREC_FP32 = 0, 1
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
@@ -122,7 +123,8 @@ class Context:
     """Owns an afqmc_ctx and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
-                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0, xbar_cap=0.0):
+                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0, xbar_cap=0.0,
+                 precision=PREC_FP64):
         import numpy as np
         lib = load_library()
         if not torch.cuda.is_available():
@@ -135,7 +137,7 @@ class Context:
         self.sys = afqmc_system(self.M, self.N, self.G, self.K, self.P, int(system.hidden_kind),
                                 float(system.coupling), dp(self._host[0]), dp(self._host[1]),
                                 dp(self._host[2]), dp(self._host[3]), float(dtau), int(n_taylor),
-                                int(weight_mode), int(proposal), float(rw_step), 0,
+                                int(weight_mode), int(proposal), float(rw_step), int(precision),
                                 float(xbar_cap))
         self.dtau = float(dtau)
         self.device = torch.device("cuda", device)

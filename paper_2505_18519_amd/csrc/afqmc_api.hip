@@ -32,7 +32,7 @@ hipError_t dev_copy(T** dst, const T* src, size_t n) {
 }
 
 void free_ctx(afqmc_ctx_s* c) {
-  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A};
+  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A, c->d_Lpad32};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -75,6 +75,15 @@ T* ws_ptr(afqmc_ctx_s* c, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(c->ws) + off);
 }
 
+hipError_t do_trial_build(const afqmc_ctx_s* c, int n, const double* y, double* phiT, double* ub) {
+  return c->small ? launch_trial_build(c, n, y, phiT, ub) : launch_trial_build_g(c, n, y, phiT, ub);
+}
+hipError_t do_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
+                      double* logov, double* theta) {
+  return c->small ? launch_overlap(c, nw, phi, phiT, logov, theta)
+                  : launch_overlap_g(c, nw, phi, phiT, logov, theta);
+}
+
 }  // namespace
 
 ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
@@ -89,6 +98,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   off += align256((size_t)nw * c->M * c->M * 16);
   L.ubuf = off;
   off += align256(S * c->M * c->M * 8);
+  L.qrshift = off;
+  off += align256((size_t)nw * 2 * 8);
   L.ytry = off;
   off += align256(S * c->K * 8);
   L.phiTtry = off;
@@ -123,13 +134,14 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if (sys->h1 == nullptr || sys->L == nullptr || sys->phi0 == nullptr || sys->A == nullptr)
     return AFQMC_E_INVALID;
   const int M = sys->M, N = sys->N, G = sys->n_chol, K = sys->K, P = sys->P;
-  if (M < 1 || N < 1 || N > M || M > 64 || N > 16 || G < 1 || K < 1 || K > 256 || P < 1 || P > 64)
+  if (M < 1 || N < 1 || N > M || M > 128 || N > 32 || G < 1 || K < 1 || P < 1 || P > 64)
     return AFQMC_E_SHAPE;
   if (sys->hidden_kind != AFQMC_HIDDEN_ISING && sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
     return AFQMC_E_INVALID;
   if (sys->weight_mode < 0 || sys->weight_mode > 2) return AFQMC_E_INVALID;
   if (sys->proposal < 0 || sys->proposal > 1) return AFQMC_E_INVALID;
-  if (sys->precision != AFQMC_PREC_FP64) return AFQMC_E_UNSUPPORTED;
+  if (sys->precision != AFQMC_PREC_FP64 && sys->precision != AFQMC_PREC_FP32)
+    return AFQMC_E_UNSUPPORTED;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
   if (!(sys->xbar_cap >= 0.0)) return AFQMC_E_INVALID;
 
@@ -143,6 +155,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   c->K = K;
   c->P = P;
   c->MT = ((M + 15) / 16) * 16;
+  c->small = (M <= 64 && N <= 16);
   c->hidden_kind = sys->hidden_kind;
   c->coupling = sys->coupling;
   c->dtau = sys->dtau;
@@ -175,7 +188,13 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     delete c;
     return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
   }
-  if ((e = launch_setup(c)) != hipSuccess) {
+  if ((e = launch_setup(c)) == hipSuccess && c->precision == AFQMC_PREC_FP32) {
+    const size_t n = Lpad.size();
+    if ((e = hipMalloc(&c->d_Lpad32, n * sizeof(float))) == hipSuccess &&
+        (e = launch_to_float(c, n, c->d_Lpad, c->d_Lpad32)) == hipSuccess)
+      e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) {
     free_ctx(c);
     delete c;
     return AFQMC_E_DEVICE;
@@ -239,7 +258,7 @@ afqmc_status afqmc_trial_build(afqmc_ctx c, int32_t nw, const double* y, double*
   ws_layout L;
   afqmc_status st = need_ws(c, nw, &L);
   if (st != AFQMC_OK) return st;
-  HIPCALL(c, launch_trial_build(c, nw * c->P, y, phiT, ws_ptr<double>(c, L.ubuf)), "trial_build");
+  HIPCALL(c, do_trial_build(c, nw * c->P, y, phiT, ws_ptr<double>(c, L.ubuf)), "trial_build");
   return AFQMC_OK;
 }
 
@@ -252,8 +271,8 @@ afqmc_status afqmc_overlap(afqmc_ctx c, int32_t nw, const void* phi, const doubl
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
   HIPCALL(c,
-          launch_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
-                         nullptr),
+          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
+                     nullptr),
           "overlap");
   return AFQMC_OK;
 }
@@ -268,8 +287,8 @@ afqmc_status afqmc_green(afqmc_ctx c, int32_t nw, const void* phi, const double*
   REQUIRE(c, logov, "logov");
   REQUIRE(c, theta, "theta");
   HIPCALL(c,
-          launch_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
-                         static_cast<double*>(theta)),
+          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
+                     static_cast<double*>(theta)),
           "green");
   return AFQMC_OK;
 }
@@ -285,10 +304,16 @@ static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, con
   }
   double* vb = vb_sample ? static_cast<double*>(vb_sample) : ws_ptr<double>(c, L.vb);
   double* ep = e_sample ? static_cast<double*>(e_sample) : ws_ptr<double>(c, L.ep);
-  HIPCALL(c,
-          launch_contract(c, nw, phiT, static_cast<const double*>(theta),
-                          static_cast<const double*>(logov), vb, ep),
-          "contract");
+  if (c->small && c->precision == AFQMC_PREC_FP64)
+    HIPCALL(c,
+            launch_contract(c, nw, phiT, static_cast<const double*>(theta),
+                            static_cast<const double*>(logov), vb, ep),
+            "contract");
+  else
+    HIPCALL(c,
+            launch_contract_g(c, nw, phiT, static_cast<const double*>(theta),
+                              static_cast<const double*>(logov), vb, ep),
+            "contract");
   HIPCALL(c,
           launch_combine(c, nw, vb, ep, static_cast<const double*>(logov),
                          static_cast<double*>(xbar), static_cast<double*>(eloc)),
@@ -341,9 +366,8 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   double* vmat = ws_ptr<double>(c, L.vmat);
   double* ph = static_cast<double*>(phi);
   HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat), "vbuild");
-  HIPCALL(c, launch_taylor(c, nw, vmat, ph), "taylor");
-  HIPCALL(c, launch_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr),
-          "ratio overlap");
+  HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph), "taylor");
+  HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr), "ratio overlap");
   HIPCALL(c,
           launch_weight(c, nw, xi, static_cast<const double*>(xbar),
                         static_cast<const double*>(logov), static_cast<double*>(logov_new), e_shift,
@@ -380,9 +404,9 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
     for (int f = 0; f < nflip; ++f) {
       const int flip_k = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? f : -1;
       HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k), "proposal");
-      HIPCALL(c, launch_trial_build(c, nw * c->P, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+      HIPCALL(c, do_trial_build(c, nw * c->P, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
               "proposal trial build");
-      HIPCALL(c, launch_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
+      HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
       HIPCALL(c, launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, flip_k),
               "accept");
     }
@@ -396,7 +420,17 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx c, int32_t nw, void* phi, void* log
   CHECK_NW(c, nw);
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, phi, "phi");
-  HIPCALL(c, launch_qr(c, nw, static_cast<double*>(phi), static_cast<double*>(logov)), "qr");
+  if (c->small) {
+    HIPCALL(c, launch_qr(c, nw, static_cast<double*>(phi), static_cast<double*>(logov)), "qr");
+  } else {
+    ws_layout L;
+    afqmc_status st = need_ws(c, nw, &L);
+    if (st != AFQMC_OK) return st;
+    HIPCALL(c,
+            launch_qr_g(c, nw, static_cast<double*>(phi), static_cast<double*>(logov),
+                        ws_ptr<double>(c, L.qrshift)),
+            "qr");
+  }
   return AFQMC_OK;
 }
 

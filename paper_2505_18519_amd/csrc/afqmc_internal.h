@@ -24,6 +24,8 @@ struct afqmc_ctx_s {
   double* d_Eh = nullptr;    // [M][M] = exp(-tau h1 / 2)
   double* d_phi0 = nullptr;  // [M][N]
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
+  float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
+  bool small = false;         // M <= 64 and N <= 16: register-resident kernels
 
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -32,7 +34,7 @@ struct afqmc_ctx_s {
 
 // Workspace carve-up for nw walkers (byte offsets, 256-aligned).
 struct ws_layout {
-  size_t vb, ep, vmat, ubuf, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
+  size_t vb, ep, vmat, ubuf, qrshift, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
       pc_logov, total;
 };
 ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw);
@@ -73,6 +75,15 @@ hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t st
                                 int nw, int n, double* out);
 hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y);
 hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
+hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y,
+                                double* phiT, double* ubuf);
+hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
+                            double* logov, double* theta);
+hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                             const double* logov, double* vb, double* ep);
+hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
+hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift);
+hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
 hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, double* C,
                        double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,

@@ -1,0 +1,293 @@
+// Cholesky-vector contraction for larger systems (M <= 128, N <= 32), in FP64
+// or with FP32 matrix-core products (the mixed-precision form).  Same
+// quantities as k_contract (Sec. III.A, Eq. local-obs; Eq. shift1):
+//   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
+//   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
+//
+// Layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16)).
+// Wavefront w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt]
+// in registers for the whole loop over g.  Stage 1 (Y_g^T = L_g Phi_T) is split
+// over all wavefronts by row tile so every element of L_g is read once per
+// path (straight from L2; L is shared by all paths); its result goes through
+// LDS.  Stage 2 gives each wavefront f^s[:, jt]; f is transposed through LDS
+// for tr(f f).  In the FP32 form Phi_T, Theta and L enter the products as
+// FP32 with FP32 accumulation over m; per-vector traces, vb_g^2 and the sums
+// over g are carried in FP64.
+#include "afqmc_internal.h"
+#include "dev_common.h"
+
+namespace {
+
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct mm;
+template <>
+struct mm<double> {
+  typedef dx4 acc_t;
+  __device__ static acc_t zero() { return dx4_zero(); }
+  __device__ static acc_t fma(double a, double b, acc_t c) { return mfma_f64(a, b, c); }
+  // accumulator element r of lane group g holds row g + 4 r (FP64 16x16x4)
+  __device__ static int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct mm<float> {
+  typedef fx4 acc_t;
+  __device__ static acc_t zero() {
+    fx4 z = {0.f, 0.f, 0.f, 0.f};
+    return z;
+  }
+  __device__ static acc_t fma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane group g holds row 4 g + r (FP32 16x16x4)
+  __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+
+template <typename T, int KTMAX, int NTC>
+__global__ void __launch_bounds__(128 * NTC)
+k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ Lpad,
+             const double* __restrict__ phiT, const double* __restrict__ theta,
+             const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
+  typedef mm<T> MM;
+  typedef typename MM::acc_t acc_t;
+  constexpr int NWV = 2 * NTC;             // wavefronts
+  constexpr int NT = 16 * NTC;
+  constexpr int S1MAX = (KTMAX + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  extern __shared__ double smem[];
+  T* sY = reinterpret_cast<T*>(smem);                        // [MT][NT]
+  double* sF = smem + (MT * NT * sizeof(T) + 7) / 8;          // [2][NT][NT+1][2]
+  double* sD = sF + 2 * NT * (NT + 1) * 2;                    // [16][NWV*16][2]
+
+  const int KT = MT / 16;
+  const int s = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int sp = wave & 1, jt = wave >> 1;
+  if (s >= n_samples) return;  // whole block exits together
+  const bool active = !__builtin_isinf(logov[2 * s]);
+
+  // Phi_T B operands for stage 1 (all column tiles), Theta^sp[:, jt] for stage 2
+  T bT[NTC][KTMAX][4];
+  T th[2][KTMAX][4];
+#pragma unroll
+  for (int t = 0; t < KTMAX; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * t + 4 * r + g;
+      const bool okm = active && t < KT && m < M;
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        const int n = 16 * ct + c;
+        bT[ct][t][r] = (okm && n < N) ? (T)phiT[((size_t)s * M + m) * N + n] : (T)0;
+      }
+      const int n = 16 * jt + c;
+      const double* src = theta + ((((size_t)s * 2 + sp) * M + m) * N + n) * 2;
+      th[0][t][r] = (okm && n < N) ? (T)src[0] : (T)0;
+      th[1][t][r] = (okm && n < N) ? (T)src[1] : (T)0;
+    }
+
+  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  const size_t slab = (size_t)MT * MT;
+  for (int gam = 0; gam <= G; ++gam) {
+    const T* Lg = Lpad + (size_t)gam * slab;
+    // stage 1: Y^T tiles (tp, ct) for row tiles tp = wave + NWV q
+    acc_t y1[S1MAX][NTC];
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = MM::zero();
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wave + NWV * q;
+      if (active && tp < KT) {
+#pragma unroll
+        for (int t = 0; t < KTMAX; ++t) {
+          if (t < KT) {
+            T av[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) av[r] = Lg[(size_t)(16 * t + 4 * r + g) * MT + 16 * tp + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = MM::fma(av[r], bT[ct][t][r], y1[q][ct]);
+          }
+        }
+      }
+    }
+    __syncthreads();  // previous vector's stage-2 and transpose reads are done
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wave + NWV * q;
+      if (tp < KT)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sY[(16 * tp + MM::row(g, r)) * NT + 16 * ct + c] = y1[q][ct][r];
+    }
+    __syncthreads();
+    // stage 2: f^sp[it][jt] = sum_m Y^T[m][it cols] Theta^sp[m][jt cols]
+    acc_t f[NTC][2];
+#pragma unroll
+    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = MM::zero();
+    if (active) {
+#pragma unroll
+      for (int t = 0; t < KTMAX; ++t) {
+        if (t < KT) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = 16 * t + 4 * r + g;
+#pragma unroll
+            for (int it = 0; it < NTC; ++it) {
+              const T a = sY[m * NT + 16 * it + c];
+              f[it][0] = MM::fma(a, th[0][t][r], f[it][0]);
+              f[it][1] = MM::fma(a, th[1][t][r], f[it][1]);
+            }
+          }
+        }
+      }
+    }
+    // diagonal of f^sp in tile (jt, jt): element (row(g,r), c) with row == c
+    double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+      if (it == jt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (MM::row(g, r) == c) {
+            d_re = (double)f[it][0][r];
+            d_im = (double)f[it][1][r];
+          }
+    if (gam == G) {
+      d_re = wave_sum(d_re);
+      d_im = wave_sum(d_im);
+      // one-body term: both spins' traces, gathered through LDS below
+      if (lane == 0) {
+        sD[(wave * 16) * 2] = d_re;
+        sD[(wave * 16) * 2 + 1] = d_im;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w = 0; w < NWV; ++w) {
+          e1_re += sD[(w * 16) * 2];
+          e1_im += sD[(w * 16) * 2 + 1];
+        }
+      }
+      break;
+    }
+    // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
+    double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
+        Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
+        Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
+      }
+    {
+      double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
+      if (MM::row(g, 0) == c || MM::row(g, 1) == c || MM::row(g, 2) == c || MM::row(g, 3) == c) {
+        d[0] = d_re;
+        d[1] = d_im;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
+        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
+        ex_re += ar * tr_ - ai * ti_;
+        ex_im += ar * ti_ + ai * tr_;
+      }
+    // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
+    if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
+      const int cnt = (gam & 15) + 1, g0 = gam & ~15;
+      const int gl = lane & 15, part = (lane >> 4) & 1;
+      double v = 0.0;
+      if (lane < 32 && gl < cnt)
+        for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
+      const double vi = __shfl_down(v, 16, 64);
+      if (lane < 16 && gl < cnt) {
+        vb2_re += v * v - vi * vi;
+        vb2_im += 2.0 * v * vi;
+        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
+        o[0] = v;
+        o[1] = vi;
+      }
+    }
+  }
+  // totals: ex from every lane of every wavefront, vb^2 from wavefront 0
+  ex_re = wave_sum(ex_re);
+  ex_im = wave_sum(ex_im);
+  vb2_re = wave_sum(vb2_re);
+  vb2_im = wave_sum(vb2_im);
+  __syncthreads();
+  if (lane == 0) {
+    sD[wave * 4 + 0] = ex_re;
+    sD[wave * 4 + 1] = ex_im;
+    sD[wave * 4 + 2] = vb2_re;
+    sD[wave * 4 + 3] = vb2_im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double xr = 0.0, xi = 0.0;
+    for (int w = 0; w < NWV; ++w) {
+      xr += sD[w * 4 + 0];
+      xi += sD[w * 4 + 1];
+    }
+    const double br = sD[2], bi = sD[3];
+    double* o = ep + (size_t)s * 2;
+    o[0] = active ? e1_re + 0.5 * br - 0.5 * xr : 0.0;
+    o[1] = active ? e1_im + 0.5 * bi - 0.5 * xi : 0.0;
+  }
+  if (!active)
+    for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
+}
+
+size_t lds_bytes(int MT, int NTC, size_t tsize) {
+  const int NT = 16 * NTC, NWV = 2 * NTC;
+  size_t b = ((size_t)MT * NT * tsize + 7) / 8 * 8;
+  b += (size_t)2 * NT * (NT + 1) * 2 * 8;
+  b += (size_t)16 * NWV * 16 * 2 * 8;
+  return b;
+}
+
+template <typename T, int KTMAX, int NTC>
+hipError_t launch_g(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
+                    const double* theta, const double* logov, double* vb, double* ep) {
+  const int n = nw * c->P;
+  const size_t lds = lds_bytes(c->MT, NTC, sizeof(T));
+  auto kern = k_contract_g<T, KTMAX, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(128 * NTC), lds, c->stream, n, c->M, c->N, c->G, c->MT,
+                     L, phiT, theta, logov, vb, ep);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
+                    const double* theta, const double* logov, double* vb, double* ep) {
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_G(KM, NC)                                                            \
+  if (KT <= KM && NTC == NC) return launch_g<T, KM, NC>(c, nw, L, phiT, theta, logov, vb, ep);
+  AFQMC_G(4, 1) AFQMC_G(6, 1) AFQMC_G(8, 1)
+  AFQMC_G(4, 2) AFQMC_G(6, 2) AFQMC_G(8, 2)
+#undef AFQMC_G
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                             const double* logov, double* vb, double* ep) {
+  if (nw <= 0) return hipSuccess;
+  if (c->precision == AFQMC_PREC_FP32)
+    return dispatch<float>(c, nw, c->d_Lpad32, phiT, theta, logov, vb, ep);
+  return dispatch<double>(c, nw, c->d_Lpad, phiT, theta, logov, vb, ep);
+}

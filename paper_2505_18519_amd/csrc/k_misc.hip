@@ -203,6 +203,11 @@ k_qr(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict__
     for (int p = m; p < P; p += 64) logov[((size_t)w * P + p) * 2] -= shift;
 }
 
+__global__ void k_to_float(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
 __global__ void k_zero_int(int n, int* __restrict__ p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -255,8 +260,99 @@ hipError_t launch_qr(const afqmc_ctx_s* c, int nw, double* phi, double* logov) {
   return hipGetLastError();
 }
 
+hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst) {
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, src,
+                     dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Re-orthonormalisation for larger systems (M <= 128, N <= 32): modified
+// Gram-Schmidt applied twice, one 128-thread workgroup per walker and spin,
+// thread = orbital row, the columns in LDS, inner products reduced across the
+// workgroup in LDS.
+namespace {
+
+constexpr int QRG_T = 128;
+
+__global__ void __launch_bounds__(QRG_T)
+k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict__ logshift) {
+  extern __shared__ double sq[];  // [M][N] complex
+  __shared__ double s_red[2][2];
+  const int w = blockIdx.x, sp = blockIdx.y;
+  const int m = threadIdx.x, wave = m >> 6, lane = m & 63;
+  double* base = phi + ((size_t)(w * 2 + sp) * M) * N * 2;
+  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) sq[q] = base[q];
+  __syncthreads();
+  auto block_sum2 = [&](double& a, double& b) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      s_red[wave][0] = a;
+      s_red[wave][1] = b;
+    }
+    __syncthreads();
+    a = s_red[0][0] + s_red[1][0];
+    b = s_red[0][1] + s_red[1][1];
+    __syncthreads();
+  };
+  double shift = 0.0;
+  double* row = sq + (size_t)m * N * 2;
+  const bool own = m < M;
+  for (int j = 0; j < N; ++j) {
+    cplx v = own ? cmk(row[2 * j], row[2 * j + 1]) : cmk(0.0, 0.0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < j; ++k) {
+        const cplx qk = own ? cmk(row[2 * k], row[2 * k + 1]) : cmk(0.0, 0.0);
+        double hr = qk.re * v.re + qk.im * v.im;
+        double hi = qk.re * v.im - qk.im * v.re;
+        block_sum2(hr, hi);
+        v = cfms(v, cmk(hr, hi), qk);
+      }
+    double n2 = cabs2(v), dummy = 0.0;
+    block_sum2(n2, dummy);
+    const double nrm = sqrt(n2);
+    shift += log(nrm);
+    if (own) {
+      row[2 * j] = v.re / nrm;
+      row[2 * j + 1] = v.im / nrm;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) base[q] = sq[q];
+  if (m == 0) logshift[(size_t)w * 2 + sp] = shift;
+}
+
+__global__ void k_apply_shift(int nw, int P, const double* __restrict__ logshift,
+                              double* __restrict__ logov) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw * P) return;
+  const int w = i / P;
+  logov[(size_t)i * 2] -= logshift[(size_t)w * 2] + logshift[(size_t)w * 2 + 1];
+}
+
+}  // namespace
+
+hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift) {
+  if (nw <= 0) return hipSuccess;
+  if (c->M > QRG_T) return hipErrorInvalidValue;
+  const size_t lds = (size_t)c->M * c->N * 2 * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_qr_g, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qr_g, dim3(nw, 2), dim3(QRG_T), lds, c->stream, nw, c->P, c->M, c->N, phi,
+                     shift);
+  AFQMC_LAUNCH_CHECK();
+  if (logov != nullptr) {
+    const int n = nw * c->P;
+    hipLaunchKernelGGL(k_apply_shift, dim3((n + 255) / 256), dim3(256), 0, c->stream, nw, c->P,
+                       shift, logov);
+  }
   return hipGetLastError();
 }

@@ -29,21 +29,53 @@ k_vbuild(int nw, int G, int MM, double sqrt_tau, const double* __restrict__ L,
   if (w0 >= nw) return;
   dx4 ar[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
   dx4 ai[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
-  const int wa = w0 + c;
-  for (int k0 = 0; k0 < G; k0 += 4) {
-    const int k = k0 + g;
-    double cr = 0.0, ci = 0.0;
-    if (wa < nw && k < G) {
-      cr = xi[(size_t)wa * G + k] - xbar[((size_t)wa * G + k) * 2];
-      ci = -xbar[((size_t)wa * G + k) * 2 + 1];
-    }
+  const int wa = min(w0 + c, nw - 1);
+  const bool wok = (w0 + c) < nw;
+  int ec[4];
+  bool eok[4];
 #pragma unroll
-    for (int et = 0; et < 4; ++et) {
-      const int e = e0 + 16 * et + c;
-      const double b = (k < G && e < MM) ? L[(size_t)k * MM + e] : 0.0;
-      ar[et] = mfma_f64(cr, b, ar[et]);
-      ai[et] = mfma_f64(ci, b, ai[et]);
+  for (int et = 0; et < 4; ++et) {
+    const int e = e0 + 16 * et + c;
+    eok[et] = e < MM;
+    ec[et] = min(e, MM - 1);
+  }
+  // batches of KB k-steps, double-buffered: the loads of batch i+1 (clamped
+  // in range, masked after the load) are issued before the MFMAs of batch i
+  constexpr int KB = 4;
+  double cr[2][KB], ci[2][KB], b[2][KB][4];
+  auto load = [&](int k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int k = k0 + 4 * q + g;
+      const int kc = min(k, G - 1);
+      const bool ok = wok && k < G;
+      const double x = xi[(size_t)wa * G + kc];
+      const double br = xbar[((size_t)wa * G + kc) * 2], bi = xbar[((size_t)wa * G + kc) * 2 + 1];
+      cr[buf][q] = ok ? x - br : 0.0;
+      ci[buf][q] = ok ? -bi : 0.0;
+#pragma unroll
+      for (int et = 0; et < 4; ++et) {
+        const double v = L[(size_t)kc * MM + ec[et]];
+        b[buf][q][et] = (k < G && eok[et]) ? v : 0.0;
+      }
     }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+#pragma unroll
+      for (int et = 0; et < 4; ++et) {
+        ar[et] = mfma_f64(cr[buf][q], b[buf][q][et], ar[et]);
+        ai[et] = mfma_f64(ci[buf][q], b[buf][q][et], ai[et]);
+      }
+  };
+  load(0, 0);
+  for (int k0 = 0; k0 < G; k0 += 8 * KB) {
+    if (k0 + 4 * KB < G) load(k0 + 4 * KB, 1);
+    compute(0);
+    if (k0 + 4 * KB >= G) break;
+    if (k0 + 8 * KB < G) load(k0 + 8 * KB, 0);
+    compute(1);
   }
 #pragma unroll
   for (int et = 0; et < 4; ++et)
@@ -274,4 +306,153 @@ hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const d
   hipLaunchKernelGGL(k_weight, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, c->dtau, e_shift,
                      c->weight_mode, xi, xbar, logov, logov_new, w, ref);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Taylor propagator for larger systems (M <= 128, N <= 32): one workgroup per
+// (walker, spin), one wavefront per 16-row tile; V rows as MFMA A operands in
+// registers (V_re and -V_im), e^{-tau h1/2} operands read from L2 at their two
+// uses, the iterate in one LDS tile with two barriers per Horner step.  The imaginary part is accumulated as V_re Y_im - (-V_im) Y_re.
+namespace {
+
+template <int KTMAX, int NTC>
+__global__ void __launch_bounds__(64 * KTMAX)
+k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
+           const double* __restrict__ Eh, double* __restrict__ phi) {
+  constexpr int NT = 16 * NTC;
+  extern __shared__ double smem[];
+  double* sY = smem;                 // [MT][NT][2] iterate
+  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = e^{-tau h1/2} phi
+  const int KT = MT / 16;
+  const int w = blockIdx.x, sp = blockIdx.y;
+  const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const double* V = vmat + (size_t)w * M * M * 2;
+  double* ph = phi + ((size_t)w * 2 + sp) * M * N * 2;
+
+  double vr[KTMAX][4], nvi[KTMAX][4];
+#pragma unroll
+  for (int t = 0; t < KTMAX; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
+      const bool ok = t < KT && row < M && col < M;
+      vr[t][r] = ok ? V[((size_t)row * M + col) * 2] : 0.0;
+      nvi[t][r] = ok ? -V[((size_t)row * M + col) * 2 + 1] : 0.0;
+    }
+  for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
+    const int m = q / NT, n = q % NT;
+    const bool ok = m < M && n < N;
+    sY[2 * q] = ok ? ph[((size_t)m * N + n) * 2] : 0.0;
+    sY[2 * q + 1] = ok ? ph[((size_t)m * N + n) * 2 + 1] : 0.0;
+  }
+  __syncthreads();
+  // o = E_h Y (rows of this tile)
+  auto apply_eh = [&](dx4 (&o)[NTC][2]) {
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) o[ct][0] = o[ct][1] = dx4_zero();
+#pragma unroll
+    for (int t = 0; t < KTMAX; ++t)
+      if (t < KT)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          {
+            const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
+            const double e = (row < M && col < M) ? Eh[row * M + col] : 0.0;
+#pragma unroll
+            for (int ct = 0; ct < NTC; ++ct) {
+              const double* yb = sY + ((16 * t + 4 * r + g) * NT + 16 * ct + c) * 2;
+              o[ct][0] = mfma_f64(e, yb[0], o[ct][0]);
+              o[ct][1] = mfma_f64(e, yb[1], o[ct][1]);
+            }
+          }
+  };
+  auto store = [&](double* dst, const dx4 (&o)[NTC][2]) {
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* d = dst + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+        d[0] = o[ct][0][r];
+        d[1] = o[ct][1][r];
+      }
+  };
+  {
+    dx4 x[NTC][2];
+    apply_eh(x);
+    __syncthreads();
+    store(sY, x);
+    store(sX, x);
+    __syncthreads();
+  }
+  for (int j = n_taylor; j >= 1; --j) {
+    dx4 are[NTC], aim1[NTC], aim2[NTC];
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) are[ct] = aim1[ct] = aim2[ct] = dx4_zero();
+#pragma unroll
+    for (int t = 0; t < KTMAX; ++t)
+      if (t < KT)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct) {
+            const double* yb = sY + ((16 * t + 4 * r + g) * NT + 16 * ct + c) * 2;
+            const double yr = yb[0], yi = yb[1];
+            are[ct] = mfma_f64(vr[t][r], yr, are[ct]);
+            are[ct] = mfma_f64(nvi[t][r], yi, are[ct]);
+            aim1[ct] = mfma_f64(vr[t][r], yi, aim1[ct]);
+            aim2[ct] = mfma_f64(nvi[t][r], yr, aim2[ct]);
+          }
+    const double invj = 1.0 / (double)j;
+    dx4 y[NTC][2];
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* xv = sX + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+        y[ct][0][r] = xv[0] + are[ct][r] * invj;
+        y[ct][1][r] = xv[1] + (aim1[ct][r] - aim2[ct][r]) * invj;
+      }
+    __syncthreads();
+    store(sY, y);
+    __syncthreads();
+  }
+  dx4 o[NTC][2];
+  apply_eh(o);
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + g + 4 * r, n = 16 * ct + c;
+      if (m < M && n < N) {
+        double* d = ph + ((size_t)m * N + n) * 2;
+        d[0] = o[ct][0][r];
+        d[1] = o[ct][1][r];
+      }
+    }
+}
+
+template <int KTMAX, int NTC>
+hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+  const size_t lds = (size_t)2 * c->MT * 16 * NTC * 2 * sizeof(double);
+  auto kern = k_taylor_g<KTMAX, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nw, 2), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N, c->MT,
+                     c->n_taylor, vmat, c->d_Eh, phi);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+  if (nw <= 0) return hipSuccess;
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_P(KM, NC) \
+  if (KT <= KM && NTC == NC) return launch_taylor_g_kt<KM, NC>(c, nw, vmat, phi);
+  AFQMC_P(4, 1) AFQMC_P(6, 1) AFQMC_P(8, 1)
+  AFQMC_P(4, 2) AFQMC_P(6, 2) AFQMC_P(8, 2)
+#undef AFQMC_P
+  return hipErrorInvalidValue;
 }

@@ -28,16 +28,47 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
   const int e0 = blockIdx.x * 64;
   if (s0 >= S) return;
   dx4 acc[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
-  const int sa = s0 + c;
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + g;
-    const double a = (sa < S && k < K) ? y[(size_t)sa * K + k] : 0.0;
+  const int sa = min(s0 + c, S - 1);
+  const bool sok = (s0 + c) < S;
+  int ec[4];
+  bool eok[4];
 #pragma unroll
-    for (int et = 0; et < 4; ++et) {
-      const int e = e0 + 16 * et + c;
-      const double b = (k < K && e < MM) ? A[(size_t)k * MM + e] : 0.0;
-      acc[et] = mfma_f64(a, b, acc[et]);
+  for (int et = 0; et < 4; ++et) {
+    const int e = e0 + 16 * et + c;
+    eok[et] = e < MM;
+    ec[et] = min(e, MM - 1);
+  }
+  // batches of KB k-steps, double-buffered (loads of batch i+1 before the
+  // MFMAs of batch i), loads clamped in range and masked after the load
+  constexpr int KB = 4;
+  double a[2][KB], b[2][KB][4];
+  auto load = [&](int k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int k = k0 + 4 * q + g;
+      const int kc = min(k, K - 1);
+      const double ya = y[(size_t)sa * K + kc];
+      a[buf][q] = (sok && k < K) ? ya : 0.0;
+#pragma unroll
+      for (int et = 0; et < 4; ++et) {
+        const double v = A[(size_t)kc * MM + ec[et]];
+        b[buf][q][et] = (k < K && eok[et]) ? v : 0.0;
+      }
     }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+#pragma unroll
+      for (int et = 0; et < 4; ++et) acc[et] = mfma_f64(a[buf][q], b[buf][q][et], acc[et]);
+  };
+  load(0, 0);
+  for (int k0 = 0; k0 < K; k0 += 8 * KB) {
+    if (k0 + 4 * KB < K) load(k0 + 4 * KB, 1);
+    compute(0);
+    if (k0 + 4 * KB >= K) break;
+    if (k0 + 8 * KB < K) load(k0 + 8 * KB, 0);
+    compute(1);
   }
 #pragma unroll
   for (int et = 0; et < 4; ++et)
@@ -177,4 +208,161 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
     case 64: return launch_mt<64>(c, n_samples, ubuf, phiT);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Larger systems (M <= 128, N <= 32): one workgroup per path, one wavefront per
+// 16-row tile of U (its rows held as MFMA A operands); the Taylor iterate is
+// shared through a double-buffered LDS tile, one barrier per term.
+namespace {
+
+template <int KTMAX, int NTC>
+__global__ void __launch_bounds__(64 * KTMAX)
+k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__ U,
+                 const double* __restrict__ phi0, double* __restrict__ phiT) {
+  constexpr int NT = 16 * NTC;
+  extern __shared__ double smem[];
+  double* sT = smem;                       // [2][MT][NT]
+  double* sred = smem + 2 * MT * NT;       // [KTMAX][2]
+  const int KT = MT / 16;
+  const int s = blockIdx.x;
+  const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  if (s >= n_samples) return;
+  const double* Us = U + (size_t)s * M * M;
+
+  double ua[KTMAX][4];
+  double rs = 0.0;
+#pragma unroll
+  for (int t = 0; t < KTMAX; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
+      ua[t][r] = (t < KT && row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
+      rs += fabs(ua[t][r]);
+    }
+  rs += __shfl_xor(rs, 16, 64);
+  rs += __shfl_xor(rs, 32, 64);
+  rs = wave_max(rs);
+  if (lane == 0) sred[tp * 2] = rs;
+  // Phi_0 into buffer 0 and into the running sum (my rows)
+  for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
+    const int m = q / NT, n = q % NT;
+    sT[q] = (m < M && n < N) ? phi0[m * N + n] : 0.0;
+  }
+  __syncthreads();
+  double rownorm = 0.0;
+  for (int w = 0; w < KT; ++w) rownorm = fmax(rownorm, sred[w * 2]);
+  int nstage = 1;
+  if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
+  if (nstage > 1) {
+    const double inv = 1.0 / nstage;
+#pragma unroll
+    for (int t = 0; t < KTMAX; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ua[t][r] *= inv;
+  }
+  double sm[NTC][4];
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm[ct][r] = sT[(16 * tp + g + 4 * r) * NT + 16 * ct + c];
+  __syncthreads();
+
+  int cur = 0;
+  for (int st = 0; st < nstage; ++st) {
+    if (st > 0) {  // the stage starts from the previous stage's sum
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sT[cur * MT * NT + (16 * tp + g + 4 * r) * NT + 16 * ct + c] = sm[ct][r];
+      __syncthreads();
+    }
+    for (int j = 1; j <= MAX_TERMS; ++j) {
+      const double* Tc = sT + cur * MT * NT;
+      double* Tn = sT + (cur ^ 1) * MT * NT;
+      dx4 acc[NTC];
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) acc[ct] = dx4_zero();
+#pragma unroll
+      for (int t = 0; t < KTMAX; ++t)
+        if (t < KT)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int ct = 0; ct < NTC; ++ct)
+              acc[ct] = mfma_f64(ua[t][r], Tc[(16 * t + 4 * r + g) * NT + 16 * ct + c], acc[ct]);
+      const double invj = 1.0 / (double)j;
+      double tmax = 0.0, smax = 0.0;
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double v = acc[ct][r] * invj;
+          sm[ct][r] += v;
+          Tn[(16 * tp + g + 4 * r) * NT + 16 * ct + c] = v;
+          tmax = fmax(tmax, fabs(v));
+          smax = fmax(smax, fabs(sm[ct][r]));
+        }
+      const bool check = (j & 1) == 0;
+      if (check) {
+        tmax = wave_max(tmax);
+        smax = wave_max(smax);
+        if (lane == 0) {
+          sred[tp * 2] = tmax;
+          sred[tp * 2 + 1] = smax;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+      if (check) {
+        double tm = 0.0, sx = 0.0;
+        for (int w = 0; w < KT; ++w) {
+          tm = fmax(tm, sred[w * 2]);
+          sx = fmax(sx, sred[w * 2 + 1]);
+        }
+        if (tm <= 0x1.0p-60 * sx) break;
+      }
+    }
+  }
+  double* out = phiT + (size_t)s * M * N;
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + g + 4 * r, n = 16 * ct + c;
+      if (m < M && n < N) out[m * N + n] = sm[ct][r];
+    }
+}
+
+template <int KTMAX, int NTC>
+hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+  const int NT = 16 * NTC;
+  const size_t lds = (size_t)(2 * c->MT * NT + 2 * KTMAX) * sizeof(double);
+  auto kern = k_trial_taylor_g<KTMAX, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(64 * (c->MT / 16)), lds, c->stream, n, c->M, c->N, c->MT,
+                     U, c->d_phi0, phiT);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
+                                double* ubuf) {
+  if (n_samples <= 0) return hipSuccess;
+  const int MM = c->M * c->M;
+  dim3 grid((MM + 63) / 64, (n_samples + 63) / 64);
+  hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
+                     c->d_A, ubuf);
+  AFQMC_LAUNCH_CHECK();
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_T(KM, NC) \
+  if (KT <= KM && NTC == NC) return launch_tg<KM, NC>(c, n_samples, ubuf, phiT);
+  AFQMC_T(4, 1) AFQMC_T(6, 1) AFQMC_T(8, 1)
+  AFQMC_T(4, 2) AFQMC_T(6, 2) AFQMC_T(8, 2)
+#undef AFQMC_T
+  return hipErrorInvalidValue;
 }

@@ -46,7 +46,7 @@ def test_host_side_validation(lib):
     h = np.zeros((2, 2))
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     s = A.afqmc_system(200, 4, 8, 4, 2, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 0)
-    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2   # M > 64
+    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2   # M > 128
     s = A.afqmc_system(8, 2, 8, 4, 2, 7, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 0)
     assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 1   # hidden kind
     s = A.afqmc_system(8, 2, 8, 4, 2, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 3)

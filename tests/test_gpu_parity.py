@@ -51,6 +51,10 @@ CASES = {
     "gauss-M20-N5-ragged": (lambda: ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5), 3, 6),
     "gauss-M48-N11": (lambda: ai.small_gaussian(M=48, N=11, n_chol=40, K=12, seed=6), 4, 3),
     "cfg-M64-N16-G256": (lambda: ai.workload(1)[0], 8, 3),
+    # workgroup-per-path kernels (M > 64 or N > 16)
+    "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
+    "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
+    "gauss-M128-N32": (lambda: ai.small_gaussian(M=128, N=32, n_chol=32, K=32, seed=9), 2, 2),
 }
 
 
@@ -367,3 +371,40 @@ def test_force_bias_cap():
     torch.cuda.synchronize()
     for w in range(nw):
         assert rel(host(d_xb)[w], xbar[w]) <= TOL
+
+
+
+MIXED_TOL = 1e-4
+
+
+@pytest.mark.parametrize("case", ["gauss-M20-N5-ragged", "cfg-M64-N16-G256", "gauss-M96-N24",
+                                  "gauss-M128-N32"])
+def test_mixed_precision_contraction(case):
+    """FP32 matrix-core contraction (FP64 traces and sums) against the FP64
+    oracle: per-path vb and E_p, per-walker force bias and E_L within 1e-4."""
+    _say("mixed", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    dtau = 0.01
+    ctx = A.Context(s, P, dtau, max_walkers=nw, precision=A.PREC_FP32)
+    rng, phi, y = state(s, P, nw, 2)
+    phiT = O.trial_det(s, y)
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, dtau)
+    _, theta = O.green(phiT, phi)
+    G = s.n_chol
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_ep = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, G, dtype=torch.complex128, device="cuda")
+    d_vb = torch.zeros(nw, P, G, dtype=torch.complex128, device="cuda")
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dev(theta), dev(ell), d_el, d_ep, d_xb)
+    A.afqmc_force_bias(ctx, nw, dev(phiT), dev(theta), dev(ell), d_xb, d_vb)
+    torch.cuda.synchronize()
+    e_ep = np.abs(host(d_ep) - ep).max() / max(np.abs(ep).max(), 1)
+    e_el = np.abs(host(d_el) - eloc).max() / max(np.abs(eloc).max(), 1)
+    e_xb = max(rel(host(d_xb)[w], xbar[w]) for w in range(nw))
+    e_vb = max(rel(host(d_vb)[w, p], vb[w, p]) for w in range(nw) for p in range(P))
+    _say(f"  errors vs FP64 oracle: E_p {e_ep:.2e} E_L {e_el:.2e} xbar {e_xb:.2e} vb {e_vb:.2e}")
+    for e in (e_ep, e_el, e_xb, e_vb):
+        assert e <= MIXED_TOL
+    # the FP32 products are really in use (FP64 would agree to ~1e-14)
+    assert max(e_ep, e_xb) > 1e-10
