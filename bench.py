@@ -25,7 +25,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s at fixed energy error; contraction TFLOP/s vs MFMA peak"
-PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+
+# name -> (workload index of afqmc_inputs.workload, contraction precision, peak, dtype label)
+WORKLOADS = {
+    "fp64": (1, 0, PEAK_FP64_MFMA, "f64"),
+    "mixed": (2, 1, PEAK_FP32_MFMA, "f32-contraction/f64"),
+    "mixed-fp64": (2, 0, PEAK_FP64_MFMA, "f64"),
+}
 
 
 def contraction_flops(M, N, G):
@@ -58,6 +66,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS))
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU (one-GPU build); --gpus must be 1",
@@ -74,13 +83,15 @@ def main():
         sys.exit(1)
     A.load_library()
 
-    sys_, run = ai.workload(1)
+    widx, precision, peak, dtype = WORKLOADS[args.workload]
+    sys_, run = ai.workload(widx)
     nw, P, seed = run.W, run.P, 2001
     # production loop: force-bias modulus capped at 1 and comb population
     # control every step with weights capped at 4x the mean (the sampled trial
     # of this workload has a mean path sign near 0.2 after a few steps)
     xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
-    ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap)
+    ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap,
+                    precision=precision)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
 
@@ -127,20 +138,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
                                f"-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
                    "walkers": nw, "paths": P, "M": sys_.M, "N": sys_.N,
                    "n_chol": sys_.n_chol, "K": sys_.K, "xbar_cap": xbar_cap,
                    "comb_every": n_pc, "weight_cap": w_cap},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
-                     "kernel": "k_contract (+ k_combine) in afqmc_local_energy",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
+                                else "k_contract_g") + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},
         "energy_last": float(energies[-1]),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(sys_, run, seed)
     print(json.dumps(out))
 

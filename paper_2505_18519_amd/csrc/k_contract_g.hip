@@ -101,16 +101,23 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wave + NWV * q;
       if (active && tp < KT) {
+        // software pipeline: the next k-tile's L operands are fetched before
+        // the current k-tile's MFMAs are issued
+        T av[2][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[0][r] = Lg[(size_t)(4 * r + g) * MT + 16 * tp + c];
 #pragma unroll
         for (int t = 0; t < KTMAX; ++t) {
           if (t < KT) {
-            T av[4];
+            if (t + 1 < KT)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) av[r] = Lg[(size_t)(16 * t + 4 * r + g) * MT + 16 * tp + c];
+              for (int r = 0; r < 4; ++r)
+                av[(t + 1) & 1][r] = Lg[(size_t)(16 * (t + 1) + 4 * r + g) * MT + 16 * tp + c];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-              for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = MM::fma(av[r], bT[ct][t][r], y1[q][ct]);
+              for (int ct = 0; ct < NTC; ++ct)
+                y1[q][ct] = MM::fma(av[t & 1][r], bT[ct][t][r], y1[q][ct]);
           }
         }
       }
