@@ -233,3 +233,29 @@ def random_hidden(rng: np.random.Generator, sys: System, nw: int, P: int) -> np.
 
 def random_fields(rng: np.random.Generator, sys: System, nw: int) -> np.ndarray:
     return rng.normal(size=(nw, sys.n_chol))
+
+
+# --------------------------------------------------------------------------
+# Learned-proposal network parameters.
+
+MLP_HIDDEN = 256
+
+
+def mlp_params(rng: np.random.Generator, M: int, K: int, H: int = MLP_HIDDEN,
+               last_scale: float = 0.0) -> dict:
+    """Initial weights of the proposal network, rounded to float32.
+
+    W1 [M+K][H], W2 [H][H] ~ N(0, 1/fan_in), zero biases; the output layer
+    W3 [H][2K] ~ N(0, last_scale^2 / H) and b3 = 0.  last_scale = 0 makes the
+    network's first proposals exactly the prior N(0, 1).
+    """
+    D = M + K
+    p = {
+        "W1": rng.normal(size=(D, H)) / math.sqrt(D),
+        "b1": np.zeros(H),
+        "W2": rng.normal(size=(H, H)) / math.sqrt(H),
+        "b2": np.zeros(H),
+        "W3": rng.normal(size=(H, 2 * K)) * (last_scale / math.sqrt(H)),
+        "b3": np.zeros(2 * K),
+    }
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
