@@ -65,14 +65,16 @@ enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPL
 
 /* Metropolis proposals for the paths (Sec. III.A, leapfrog step 2):
  * PRIOR: independent draw from p_T (App. B); for Ising y one sweep flips
- *        y_0 .. y_{K-1} in turn.  RW: Gaussian random walk y' = y + rw_step * eta. */
-enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1 };
+ *        y_0 .. y_{K-1} in turn.  RW: Gaussian random walk y' = y + rw_step * eta.
+ * LEARNED (an extension, Gaussian y only): a block move of all K variables from
+ *        the proposal network below (afqmc_mlp_*). */
+enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1, AFQMC_PROPOSAL_LEARNED = 2 };
 
 /* Precision of the Cholesky contraction (force bias and local energy):
  * FP64 throughout, or FP32: Phi_T, Theta and L enter the FP32 matrix-core
  * products with FP32 accumulation over the orbital index; traces, vb_g^2,
  * the sums over g and every other step of the path stay FP64. */
-enum { AFQMC_PREC_FP64 = 0, AFQMC_PREC_FP32 = 1 };
+enum { AFQMC_PREC_FP64 = 0, AFQMC_PREC_FP32 = 1, AFQMC_PREC_BF16 = 2 /* network only */ };
 
 typedef struct {
   int32_t M;            /* one-particle basis size                         */
@@ -100,7 +102,8 @@ typedef struct {
  * e^{-tau h1/2} there, and binds the context to `stream` (a hipStream_t, NULL
  * for the default stream).  Host arrays may be freed on return.
  * Supported sizes: 1 <= N <= M <= 128, N <= 32, n_chol >= 1, K >= 1,
- * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  Systems with M <= 64 and
+ * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  The learned proposal
+ * needs Gaussian hidden variables and K <= 128.  Systems with M <= 64 and
  * N <= 16 use register-resident kernels, larger ones workgroup-per-path
  * kernels.  Synchronises `stream`. */
 afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afqmc_ctx* out);
@@ -171,7 +174,10 @@ afqmc_status afqmc_propagate(afqmc_ctx ctx, int32_t nw, void* phi, const double*
  * n_sweep sweeps a proposal y' is drawn (stream PROPOSAL), Phi_T(y') and
  * l(y'; phi) are formed, and y' is accepted iff u < alpha (stream ACCEPT),
  * alpha = |O(y')|/|O(y)| for prior proposals, times N(y')/N(y) for the
- * random walk.  Accepted paths update y, phiT and logov in place.  Then
+ * random walk, times N(y')q(y|z',y')/(N(y)q(y'|z,y)) for the learned proposal
+ * (z, z' the network features at y and y', see afqmc_mlp_init; with training
+ * on, one Adam step follows each sweep).  Accepted paths update y, phiT and
+ * logov in place.  Then
  *   dtheta_T = arg sum_p S'_p - arg ref,  W <- W max(0, cos dtheta_T)
  * (HALFPLANE: W <- 0 if |dtheta_T| > pi/2).  n_accept [nw] int32 counts
  * accepted moves per walker (may be NULL). */
@@ -210,6 +216,66 @@ afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const v
  * tag 1 (FIELD) gives the auxiliary fields xi of step `step`. */
 afqmc_status afqmc_philox_normal(afqmc_ctx ctx, uint64_t seed, uint64_t step, uint32_t tag,
                                  int32_t nw, int32_t n, double* out);
+
+/* ---- Learned Metropolis proposal (an extension; the paper leaves the proposal
+ * of Sec. III.A leapfrog step 2 open and draws from the prior in App. B) -----
+ *
+ * A perceptron with two hidden layers of AFQMC_MLP_HIDDEN units proposes all K
+ * Gaussian hidden variables of a path at once from the features
+ *   z = [Re diag(G_up + G_dn) (M values), y (K values)]   (D = M + K inputs),
+ *   h1 = tanh(z W1 + b1), h2 = tanh(h1 W2 + b2), o = h2 W3 + b3,
+ *   mu = o[0:K], lv = 4 tanh(o[K:2K] / 4),  y' = mu + exp(lv / 2) eta,
+ * eta from stream PROPOSAL.  The acceptance uses the exact Metropolis-Hastings
+ * ratio with the reverse density at the proposal's own features, so the paths
+ * keep sampling P(y; phi) of Eq. PDF-Y whatever the weights are.  Training
+ * minimises the mean of -log q(y' | z, y) over accepted moves with Adam.
+ * Parameters are one flat array in the order W1 [D][H], b1 [H], W2 [H][H],
+ * b2 [H], W3 [H][2K], b3 [2K] (row-major, H = AFQMC_MLP_HIDDEN).  The context
+ * keeps FP32 master weights and Adam moments; the products run on the matrix
+ * cores in FP32 (AFQMC_PREC_FP32) or BF16 (AFQMC_PREC_BF16, weights and
+ * activations rounded to bfloat16) with FP32 accumulation.  The afqmc_mlp_*
+ * calls need a context created with proposal = AFQMC_PROPOSAL_LEARNED. */
+#define AFQMC_MLP_HIDDEN 256
+
+/* Number of network parameters, D*H + H + H*H + H + 2K*H + 2K (0 on error). */
+int64_t afqmc_mlp_num_params(afqmc_ctx ctx);
+
+/* Loads the parameters (HOST double [n_params], rounded to FP32), resets Adam
+ * (moments 0, step 0) and sets the matrix-core precision and the Adam
+ * hyper-parameters (lr > 0, 0 <= beta1, beta2 < 1, eps > 0).  Training starts
+ * off.  Allocates the network's device state on the first call; synchronises
+ * the stream. */
+afqmc_status afqmc_mlp_init(afqmc_ctx ctx, int32_t precision, const double* params, double lr,
+                            double beta1, double beta2, double eps);
+
+/* Copies the FP32 master parameters to HOST double [n_params]; synchronises. */
+afqmc_status afqmc_mlp_get_params(afqmc_ctx ctx, double* params);
+
+/* Whether afqmc_metropolis_x trains the network after each sweep (0 / 1). */
+afqmc_status afqmc_mlp_set_training(afqmc_ctx ctx, int32_t enabled);
+
+/* Network outputs for n feature rows given as gdiag [n][M] and y [n][K]
+ * (DEVICE double): mu [n][K] and lv [n][K] (DEVICE double).  Needs the
+ * workspace of ceil(n / P) walkers. */
+afqmc_status afqmc_mlp_forward(afqmc_ctx ctx, int32_t n, const double* gdiag, const double* y,
+                               double* mu, double* lv);
+
+/* One training step on n rows: loss = mean over rows with mask[i] != 0 of
+ * -log q(ytarget_i | z_i), z_i = [gdiag_i, y_i], its gradient, then one Adam
+ * step (none if no row is masked in).  gdiag [n][M], y [n][K], ytarget [n][K]
+ * DEVICE double; mask [n] DEVICE int32.  loss: DEVICE double[1] or NULL;
+ * grad: DEVICE double [n_params] (the gradient before the step) or NULL.
+ * Needs the workspace of ceil(n / P) walkers. */
+afqmc_status afqmc_mlp_train_step(afqmc_ctx ctx, int32_t n, const double* gdiag, const double* y,
+                                  const double* ytarget, const int32_t* mask, double* loss,
+                                  double* grad);
+
+/* The network's first input block for every path: as afqmc_overlap, plus
+ * gdiag [nw][P][M] = Re diag(G_up + G_dn) with G^s = Theta^s Phi_T^T (the
+ * diagonal of the one-body Green's function of Eq. local-obs); 0 for a
+ * singular path. */
+afqmc_status afqmc_green_diag(afqmc_ctx ctx, int32_t nw, const void* phi, const double* phiT,
+                              void* logov, double* gdiag);
 
 /* Counter tags of the streams above. */
 enum { AFQMC_TAG_FIELD = 1, AFQMC_TAG_PROPOSAL = 2, AFQMC_TAG_ACCEPT = 3, AFQMC_TAG_COMB = 4,

@@ -123,14 +123,15 @@ def features(gdiag, y):
 
 
 def metropolis_learned(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep, params,
-                       weight_mode=O.WEIGHT_SEPARATE, adam=None):
+                       weight_mode=O.WEIGHT_SEPARATE, adam=None, trace=None):
     """Learned-proposal Metropolis update of the paths, then the hand-off.
 
     One sweep = one block move per path: z = features at (phi, y); draw
     y' = mu + exp(lv / 2) eta with eta from the PROPOSAL stream; Phi_T(y'),
     l(y') and z' = features at (phi, y'); accept iff u < alpha (ACCEPT stream).
     With an Adam optimiser, each sweep then takes one step on the accepted
-    moves.  Returns (y', phiT', logov', w', n_accept, last loss).
+    moves.  Returns (y', phiT', logov', w', n_accept, last loss).  A list
+    passed as `trace` receives (log alpha, u) of every sweep.
     """
     y = y.copy()
     phiT = phiT.copy()
@@ -155,6 +156,8 @@ def metropolis_learned(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep, pa
         la = (ellp.real - logov.real - 0.5 * (ypr * ypr).sum(-1) + 0.5 * (y * y).sum(-1)
               + (lq_r - lq_f).reshape(nw, P))
         acc = O._accept(u, la)
+        if trace is not None:
+            trace.append((la.copy(), u.copy()))
         if adam is not None:
             loss, g = loss_and_grad(params, z, yp, acc.reshape(-1))
             if acc.any():

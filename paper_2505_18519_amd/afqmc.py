@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
 WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE = 0, 1, 2
-PROPOSAL_PRIOR, PROPOSAL_RW = 0, 1
-PREC_FP64, PREC_FP32 = 0, 1
+PROPOSAL_PRIOR, PROPOSAL_RW, PROPOSAL_LEARNED = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+MLP_HIDDEN = 256
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
@@ -63,6 +64,15 @@ EXPORTS = {
                                          c_void_p, c_uint64, c_uint64, c_double, c_void_p]),
     "afqmc_philox_normal": (c_int, [c_void_p, c_uint64, c_uint64, c_uint32, c_int32, c_int32,
                                     c_void_p]),
+    "afqmc_green_diag": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "afqmc_mlp_num_params": (ctypes.c_int64, [c_void_p]),
+    "afqmc_mlp_init": (c_int, [c_void_p, c_int32, POINTER(c_double), c_double, c_double, c_double,
+                               c_double]),
+    "afqmc_mlp_get_params": (c_int, [c_void_p, POINTER(c_double)]),
+    "afqmc_mlp_set_training": (c_int, [c_void_p, c_int32]),
+    "afqmc_mlp_forward": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "afqmc_mlp_train_step": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -279,3 +289,57 @@ def afqmc_estimator(ctx, nw, w, eloc, out):
 def afqmc_philox_normal(ctx, seed, step, tag, nw, n, out):
     ctx._call("afqmc_philox_normal", int(seed), int(step), int(tag), nw, n,
               _ptr(out, torch.float64, nw * n, "out"))
+
+
+def afqmc_green_diag(ctx, nw, phi, phiT, logov, gdiag):
+    c = ctx
+    c._call("afqmc_green_diag", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(gdiag, torch.float64, nw * c.P * c.M, "gdiag"))
+
+
+# --- learned proposal network ---------------------------------------------------
+
+def afqmc_mlp_num_params(ctx):
+    return int(load_library().afqmc_mlp_num_params(ctx.handle))
+
+
+def afqmc_mlp_init(ctx, precision, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """params: host float64 array of afqmc_mlp_num_params(ctx) values."""
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float64).ravel()
+    n = afqmc_mlp_num_params(ctx)
+    if p.size != n:
+        raise ValueError(f"params has {p.size} values, the network has {n}")
+    ctx._call("afqmc_mlp_init", int(precision), p.ctypes.data_as(POINTER(c_double)), float(lr),
+              float(beta1), float(beta2), float(eps))
+
+
+def afqmc_mlp_get_params(ctx):
+    import numpy as np
+    out = np.empty(afqmc_mlp_num_params(ctx), dtype=np.float64)
+    ctx._call("afqmc_mlp_get_params", out.ctypes.data_as(POINTER(c_double)))
+    return out
+
+
+def afqmc_mlp_set_training(ctx, enabled):
+    ctx._call("afqmc_mlp_set_training", 1 if enabled else 0)
+
+
+def afqmc_mlp_forward(ctx, n, gdiag, y, mu, lv):
+    c = ctx
+    c.reserve((n + c.P - 1) // c.P)
+    c._call("afqmc_mlp_forward", n, _ptr(gdiag, torch.float64, n * c.M, "gdiag"),
+            _ptr(y, torch.float64, n * c.K, "y"), _ptr(mu, torch.float64, n * c.K, "mu"),
+            _ptr(lv, torch.float64, n * c.K, "lv"))
+
+
+def afqmc_mlp_train_step(ctx, n, gdiag, y, ytarget, mask, loss=None, grad=None):
+    c = ctx
+    c.reserve((n + c.P - 1) // c.P)
+    c._call("afqmc_mlp_train_step", n, _ptr(gdiag, torch.float64, n * c.M, "gdiag"),
+            _ptr(y, torch.float64, n * c.K, "y"), _ptr(ytarget, torch.float64, n * c.K, "ytarget"),
+            _ptr(mask, torch.int32, n, "mask"),
+            _ptr(loss, torch.float64, 1, "loss", allow_none=True),
+            _ptr(grad, torch.float64, afqmc_mlp_num_params(c), "grad", allow_none=True))

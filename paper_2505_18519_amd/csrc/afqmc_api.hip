@@ -32,10 +32,15 @@ hipError_t dev_copy(T** dst, const T* src, size_t n) {
 }
 
 void free_ctx(afqmc_ctx_s* c) {
-  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A, c->d_Lpad32};
+  auto& m = c->mlp;
+  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A, c->d_Lpad32,
+                  m.master, m.mom1,   m.mom2,   m.w1t,  m.w2t,    m.w3t, m.w2c,
+                  m.w3c,    m.tstep,  m.scal};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
+
+int round16(int x) { return (x + 15) & ~15; }
 
 #define CHECK_CTX(c)                                        \
   do {                                                      \
@@ -79,10 +84,16 @@ hipError_t do_trial_build(const afqmc_ctx_s* c, int n, const double* y, double* 
   return c->small ? launch_trial_build(c, n, y, phiT, ub) : launch_trial_build_g(c, n, y, phiT, ub);
 }
 hipError_t do_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                      double* logov, double* theta) {
-  return c->small ? launch_overlap(c, nw, phi, phiT, logov, theta)
-                  : launch_overlap_g(c, nw, phi, phiT, logov, theta);
+                      double* logov, double* theta, double* gdiag = nullptr) {
+  return c->small ? launch_overlap(c, nw, phi, phiT, logov, theta, gdiag)
+                  : launch_overlap_g(c, nw, phi, phiT, logov, theta, gdiag);
 }
+
+// backward pass, weight gradients, loss reduction and Adam step on the rows
+// whose mask is set; out holds the forward outputs, zT/h1T/h2T its activations
+afqmc_status mlp_train(afqmc_ctx_s* c, const ws_layout& L, int n, const float* out,
+                       const double* ytgt, const int* mask, const void* zT, double* loss,
+                       double* grad);
 
 }  // namespace
 
@@ -122,9 +133,56 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   off += align256(S * c->M * c->N * 8);
   L.pc_logov = off;
   off += align256(S * 16);
+  // learned proposal: sizes for 4-byte product elements (BF16 uses half)
+  const bool ml = c->proposal == AFQMC_PROPOSAL_LEARNED;
+  const size_t Sp = ml ? (size_t)round16((int)S) : 0;
+  const size_t D = (size_t)c->M + c->K, Op = (size_t)round16(2 * c->K), H = AFQMC_MLP_HIDDEN;
+  const size_t np = D * H + H + H * H + H + H * 2 * c->K + 2 * c->K;
+  const size_t nsplit = (Sp + MLP_CHUNK - 1) / MLP_CHUNK;
+  const size_t sizes[] = {ml ? S * c->M * 8 : 0, ml ? S * c->M * 8 : 0, Sp * Op * 4, Sp * Op * 4,
+                          ml ? S * 8 : 0,       ml ? S * 8 : 0,       Sp * 4,      D * Sp * 4,
+                          H * Sp * 4,           H * Sp * 4,           Op * Sp * 4, H * Sp * 4,
+                          H * Sp * 4,           Sp * 8,               nsplit * np * 4,
+                          ml ? (size_t)256 : 0};
+  size_t* dst[] = {&L.gd_cur, &L.gd_try, &L.mlF, &L.mlR, &L.lqf, &L.lqx, &L.mask, &L.zT,
+                   &L.h1T,    &L.h2T,    &L.dOT, &L.dh2T, &L.dh1T, &L.nlq, &L.part, &L.mlio};
+  for (int i = 0; i < 16; ++i) {
+    *dst[i] = off;
+    off += align256(sizes[i]);
+  }
   L.total = off;
   return L;
 }
+
+namespace {
+
+afqmc_status mlp_train(afqmc_ctx_s* c, const ws_layout& L, int n, const float* out,
+                       const double* ytgt, const int* mask, const void* zT, double* loss,
+                       double* grad) {
+  const int Sp = round16(n);
+  void* h1T = ws_ptr<void>(c, L.h1T);
+  void* h2T = ws_ptr<void>(c, L.h2T);
+  void* dOT = ws_ptr<void>(c, L.dOT);
+  void* dh2T = ws_ptr<void>(c, L.dh2T);
+  void* dh1T = ws_ptr<void>(c, L.dh1T);
+  double* nlq = ws_ptr<double>(c, L.nlq);
+  float* part = ws_ptr<float>(c, L.part);
+  HIPCALL(c, launch_mlp_backward(c, n, Sp, out, ytgt, mask, h1T, h2T, dOT, dh2T, dh1T, nlq),
+          "mlp backward");
+  HIPCALL(c, launch_mlp_wgrad(c, Sp, zT, h1T, h2T, dOT, dh2T, dh1T, part), "mlp weight gradients");
+  HIPCALL(c, launch_mlp_reduce(c, n, mask, nlq, loss), "mlp loss");
+  HIPCALL(c, launch_mlp_adam(c, Sp, part, grad), "mlp adam");
+  return AFQMC_OK;
+}
+
+afqmc_status mlp_check(afqmc_ctx_s* c, int n, ws_layout* L) {
+  if (c->proposal != AFQMC_PROPOSAL_LEARNED)
+    return fail(c, AFQMC_E_INVALID, "network calls need proposal = AFQMC_PROPOSAL_LEARNED");
+  if (!c->mlp.ready) return fail(c, AFQMC_E_INVALID, "network not initialised (afqmc_mlp_init)");
+  return need_ws(c, (n + c->P - 1) / c->P, L);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -139,7 +197,10 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if (sys->hidden_kind != AFQMC_HIDDEN_ISING && sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
     return AFQMC_E_INVALID;
   if (sys->weight_mode < 0 || sys->weight_mode > 2) return AFQMC_E_INVALID;
-  if (sys->proposal < 0 || sys->proposal > 1) return AFQMC_E_INVALID;
+  if (sys->proposal < 0 || sys->proposal > 2) return AFQMC_E_INVALID;
+  if (sys->proposal == AFQMC_PROPOSAL_LEARNED &&
+      (sys->hidden_kind != AFQMC_HIDDEN_GAUSS || K > 128))
+    return AFQMC_E_UNSUPPORTED;
   if (sys->precision != AFQMC_PREC_FP64 && sys->precision != AFQMC_PREC_FP32)
     return AFQMC_E_UNSUPPORTED;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
@@ -399,6 +460,43 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
   const double* ph = static_cast<const double*>(phi);
   double* lo = static_cast<double*>(logov);
   HIPCALL(c, launch_zero_int(c, nw, nacc), "zero");
+  if (c->proposal == AFQMC_PROPOSAL_LEARNED) {
+    if (!c->mlp.ready) return fail(c, AFQMC_E_INVALID, "learned proposal needs afqmc_mlp_init");
+    const int n = nw * c->P, Sp = round16(n);
+    double* gdc = ws_ptr<double>(c, L.gd_cur);
+    double* gdt = ws_ptr<double>(c, L.gd_try);
+    float* mlF = ws_ptr<float>(c, L.mlF);
+    float* mlR = ws_ptr<float>(c, L.mlR);
+    double* lqf = ws_ptr<double>(c, L.lqf);
+    double* lqx = ws_ptr<double>(c, L.lqx);
+    int* mask = ws_ptr<int>(c, L.mask);
+    const bool tr = c->mlp.training;
+    void* zT = tr ? ws_ptr<void>(c, L.zT) : nullptr;
+    void* h1T = ws_ptr<void>(c, L.h1T);
+    void* h2T = ws_ptr<void>(c, L.h2T);
+    if (n_sweep > 0)
+      HIPCALL(c, do_overlap(c, nw, ph, phiT, ltry, nullptr, gdc), "green diagonal");
+    for (int s = 0; s < n_sweep; ++s) {
+      HIPCALL(c, launch_mlp_forward(c, n, Sp, gdc, y, mlF, zT, h1T, h2T), "mlp forward");
+      HIPCALL(c, launch_mlp_propose(c, nw, mlF, seed, step, s, ytry, lqf), "mlp propose");
+      HIPCALL(c, do_trial_build(c, n, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+              "proposal trial build");
+      HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr, gdt), "proposal overlap");
+      HIPCALL(c, launch_mlp_forward(c, n, Sp, gdt, ytry, mlR, nullptr, nullptr, nullptr),
+              "mlp reverse forward");
+      HIPCALL(c, launch_mlp_reverse(c, n, mlR, y, ytry, lqf, lqx), "mlp reverse");
+      HIPCALL(c,
+              launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, -1, lqx,
+                            gdc, gdt, mask),
+              "accept");
+      if (tr) {
+        afqmc_status st2 = mlp_train(c, L, n, mlF, ytry, mask, zT, nullptr, nullptr);
+        if (st2 != AFQMC_OK) return st2;
+      }
+    }
+    HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
+    return AFQMC_OK;
+  }
   const int nflip = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? c->K : 1;
   for (int s = 0; s < n_sweep; ++s) {
     for (int f = 0; f < nflip; ++f) {
@@ -493,6 +591,143 @@ afqmc_status afqmc_philox_normal(afqmc_ctx c, uint64_t seed, uint64_t step, uint
   if (nw == 0 || n == 0) return AFQMC_OK;
   REQUIRE(c, out, "out");
   HIPCALL(c, launch_philox_normal(c, seed, step, tag, nw, n, out), "philox_normal");
+  return AFQMC_OK;
+}
+
+int64_t afqmc_mlp_num_params(afqmc_ctx c) {
+  if (c == nullptr || c->proposal != AFQMC_PROPOSAL_LEARNED) return 0;
+  const int64_t D = (int64_t)c->M + c->K, H = AFQMC_MLP_HIDDEN, O = 2 * (int64_t)c->K;
+  return D * H + H + H * H + H + H * O + O;
+}
+
+afqmc_status afqmc_mlp_init(afqmc_ctx c, int32_t precision, const double* params, double lr,
+                            double beta1, double beta2, double eps) {
+  CHECK_CTX(c);
+  if (c->proposal != AFQMC_PROPOSAL_LEARNED)
+    return fail(c, AFQMC_E_INVALID, "network calls need proposal = AFQMC_PROPOSAL_LEARNED");
+  REQUIRE(c, params, "params");
+  if (precision != AFQMC_PREC_FP32 && precision != AFQMC_PREC_BF16)
+    return fail(c, AFQMC_E_UNSUPPORTED, "network precision must be FP32 or BF16");
+  if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(c, AFQMC_E_INVALID, "Adam hyper-parameters out of range");
+  auto& m = c->mlp;
+  const int H = AFQMC_MLP_HIDDEN;
+  m.D = c->M + c->K;
+  m.Dp = round16(m.D);
+  m.O = 2 * c->K;
+  m.Op = round16(m.O);
+  m.np = afqmc_mlp_num_params(c);
+  m.ob1 = (int64_t)m.D * H;
+  m.oW2 = m.ob1 + H;
+  m.ob2 = m.oW2 + (int64_t)H * H;
+  m.oW3 = m.ob2 + H;
+  m.ob3 = m.oW3 + (int64_t)H * m.O;
+  const size_t sz[] = {(size_t)H * m.Dp * 4, (size_t)H * H * 4, (size_t)m.Op * H * 4,
+                       (size_t)H * H * 4, (size_t)H * m.Op * 4};
+  void** cp[] = {&m.w1t, &m.w2t, &m.w3t, &m.w2c, &m.w3c};
+  if (m.master == nullptr) {
+    HIPCALL(c, hipMalloc(&m.master, m.np * sizeof(float)), "mlp alloc");
+    HIPCALL(c, hipMalloc(&m.mom1, m.np * sizeof(float)), "mlp alloc");
+    HIPCALL(c, hipMalloc(&m.mom2, m.np * sizeof(float)), "mlp alloc");
+    for (int i = 0; i < 5; ++i) HIPCALL(c, hipMalloc(cp[i], sz[i]), "mlp alloc");
+    HIPCALL(c, hipMalloc(&m.tstep, 256), "mlp alloc");
+    HIPCALL(c, hipMalloc(&m.scal, 256), "mlp alloc");
+  }
+  m.prec = precision;
+  m.lr = lr;
+  m.beta1 = beta1;
+  m.beta2 = beta2;
+  m.eps = eps;
+  m.training = false;
+  double* src = nullptr;
+  HIPCALL(c, hipMalloc(&src, m.np * sizeof(double)), "mlp alloc");
+  hipError_t e = hipMemcpy(src, params, m.np * sizeof(double), hipMemcpyHostToDevice);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipMemsetAsync(*cp[i], 0, sz[i], c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m.tstep, 0, 256, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m.scal, 0, 256, c->stream);
+  if (e == hipSuccess) e = launch_mlp_setparams(c, src);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(src);
+  if (e != hipSuccess) return hip_fail(c, e, "mlp init");
+  m.ready = true;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_mlp_get_params(afqmc_ctx c, double* params) {
+  CHECK_CTX(c);
+  REQUIRE(c, params, "params");
+  if (!c->mlp.ready) return fail(c, AFQMC_E_INVALID, "network not initialised (afqmc_mlp_init)");
+  std::vector<float> h((size_t)c->mlp.np);
+  HIPCALL(c, hipStreamSynchronize(c->stream), "sync");
+  HIPCALL(c, hipMemcpy(h.data(), c->mlp.master, h.size() * sizeof(float), hipMemcpyDeviceToHost),
+          "mlp params");
+  for (size_t i = 0; i < h.size(); ++i) params[i] = h[i];
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_mlp_set_training(afqmc_ctx c, int32_t enabled) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  if (!c->mlp.ready) return fail(c, AFQMC_E_INVALID, "network not initialised (afqmc_mlp_init)");
+  if (enabled != 0 && enabled != 1) return fail(c, AFQMC_E_INVALID, "enabled must be 0 or 1");
+  c->mlp.training = enabled != 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_mlp_forward(afqmc_ctx c, int32_t n, const double* gdiag, const double* y,
+                               double* mu, double* lv) {
+  CHECK_CTX(c);
+  if (n < 0) return fail(c, AFQMC_E_INVALID, "n must be >= 0");
+  if (n == 0) return AFQMC_OK;
+  REQUIRE(c, gdiag, "gdiag");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, mu, "mu");
+  REQUIRE(c, lv, "lv");
+  ws_layout L;
+  afqmc_status st = mlp_check(c, n, &L);
+  if (st != AFQMC_OK) return st;
+  float* out = ws_ptr<float>(c, L.mlF);
+  HIPCALL(c, launch_mlp_forward(c, n, round16(n), gdiag, y, out, nullptr, nullptr, nullptr),
+          "mlp forward");
+  HIPCALL(c, launch_mlp_outputs(c, n, out, mu, lv), "mlp outputs");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_mlp_train_step(afqmc_ctx c, int32_t n, const double* gdiag, const double* y,
+                                  const double* ytarget, const int32_t* mask, double* loss,
+                                  double* grad) {
+  CHECK_CTX(c);
+  if (n < 0) return fail(c, AFQMC_E_INVALID, "n must be >= 0");
+  if (n == 0) return AFQMC_OK;
+  REQUIRE(c, gdiag, "gdiag");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, ytarget, "ytarget");
+  REQUIRE(c, mask, "mask");
+  ws_layout L;
+  afqmc_status st = mlp_check(c, n, &L);
+  if (st != AFQMC_OK) return st;
+  float* out = ws_ptr<float>(c, L.mlF);
+  void* zT = ws_ptr<void>(c, L.zT);
+  HIPCALL(c,
+          launch_mlp_forward(c, n, round16(n), gdiag, y, out, zT, ws_ptr<void>(c, L.h1T),
+                             ws_ptr<void>(c, L.h2T)),
+          "mlp forward");
+  return mlp_train(c, L, n, out, ytarget, mask, zT, loss, grad);
+}
+
+afqmc_status afqmc_green_diag(afqmc_ctx c, int32_t nw, const void* phi, const double* phiT,
+                              void* logov, double* gdiag) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, gdiag, "gdiag");
+  HIPCALL(c,
+          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
+                     nullptr, gdiag),
+          "green diagonal");
   return AFQMC_OK;
 }
 

@@ -30,13 +30,38 @@ struct afqmc_ctx_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
+
+  // learned proposal network (allocated by afqmc_mlp_init)
+  struct mlp_state {
+    bool ready = false, training = false;
+    int prec = 0;             // AFQMC_PREC_FP32 or AFQMC_PREC_BF16
+    int D = 0, Dp = 0;        // inputs M + K, rounded up to 16
+    int O = 0, Op = 0;        // outputs 2K, rounded up to 16
+    int64_t np = 0;           // parameters
+    int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;  // flat offsets
+    double lr = 1e-3, beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
+    float* master = nullptr;  // [np] FP32 parameters
+    float* mom1 = nullptr;    // [np] Adam first moment
+    float* mom2 = nullptr;    // [np] Adam second moment
+    void* w1t = nullptr;      // [H][Dp]  W1^T in the product type
+    void* w2t = nullptr;      // [H][H]   W2^T
+    void* w3t = nullptr;      // [Op][H]  W3^T
+    void* w2c = nullptr;      // [H][H]   W2
+    void* w3c = nullptr;      // [H][Op]  W3
+    int* tstep = nullptr;     // Adam step counter (device)
+    double* scal = nullptr;   // [4] count, loss, 1/count (device)
+  } mlp;
 };
 
 // Workspace carve-up for nw walkers (byte offsets, 256-aligned).
 struct ws_layout {
   size_t vb, ep, vmat, ubuf, qrshift, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
-      pc_logov, total;
+      pc_logov;
+  // learned proposal (zero-sized unless proposal == LEARNED); Sp = paths rounded up to 16
+  size_t gd_cur, gd_try, mlF, mlR, lqf, lqx, mask, zT, h1T, h2T, dOT, dh2T, dh1T, nlq, part, mlio;
+  size_t total;
 };
+constexpr int MLP_CHUNK = 512;  // samples per split of the weight-gradient sums
 ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw);
 
 #define AFQMC_LAUNCH_CHECK()                                   \
@@ -50,7 +75,7 @@ hipError_t launch_setup(afqmc_ctx_s* c);
 hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
                               double* ubuf);
 hipError_t launch_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                          double* logov, double* theta);
+                          double* logov, double* theta, double* gdiag);
 hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                            const double* logov, double* vb, double* ep);
 hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const double* ep,
@@ -65,7 +90,9 @@ hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double
                            uint64_t seed, uint64_t step, int sweep, int flip_k);
 hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, double* logov,
                          const double* ytry, const double* phiTtry, const double* ltry,
-                         int* nacc, uint64_t seed, uint64_t step, int sweep, int flip_k);
+                         int* nacc, uint64_t seed, uint64_t step, int sweep, int flip_k,
+                         const double* lextra = nullptr, double* gd_cur = nullptr,
+                         const double* gd_try = nullptr, int* mask = nullptr);
 hipError_t launch_handoff(const afqmc_ctx_s* c, int nw, const double* logov, const double* ref,
                           double* w);
 hipError_t launch_qr(const afqmc_ctx_s* c, int nw, double* phi, double* logov);
@@ -78,7 +105,7 @@ hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y,
                                 double* phiT, double* ubuf);
 hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                            double* logov, double* theta);
+                            double* logov, double* theta, double* gdiag);
 hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                              const double* logov, double* vb, double* ep);
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
@@ -88,3 +115,22 @@ hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, do
                        double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
                          const double* src, double* dst);
+
+// learned proposal network (k_mlp.hip); n = feature rows, Sp = n rounded up to 16
+hipError_t launch_mlp_setparams(const afqmc_ctx_s* c, const double* src);
+hipError_t launch_mlp_forward(const afqmc_ctx_s* c, int n, int Sp, const double* gd, const double* y,
+                              float* out, void* zT, void* h1T, void* h2T);
+hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, uint64_t seed,
+                              uint64_t step, int sweep, double* ytry, double* lqf);
+hipError_t launch_mlp_reverse(const afqmc_ctx_s* c, int n, const float* outR, const double* y,
+                              const double* ytry, const double* lqf, double* lqx);
+hipError_t launch_mlp_backward(const afqmc_ctx_s* c, int n, int Sp, const float* out,
+                               const double* ytgt, const int* mask, const void* h1T,
+                               const void* h2T, void* dOT, void* dh2T, void* dh1T, double* nlq);
+hipError_t launch_mlp_wgrad(const afqmc_ctx_s* c, int Sp, const void* zT, const void* h1T,
+                            const void* h2T, const void* dOT, const void* dh2T, const void* dh1T,
+                            float* part);
+hipError_t launch_mlp_reduce(const afqmc_ctx_s* c, int n, const int* mask, const double* nlq,
+                             double* loss);
+hipError_t launch_mlp_adam(const afqmc_ctx_s* c, int Sp, const float* part, double* grad);
+hipError_t launch_mlp_outputs(const afqmc_ctx_s* c, int n, const float* out, double* mu, double* lv);

@@ -6,7 +6,10 @@
 // overlap (det only) at the moved walker -> k_accept.  The paths sample
 // P(y; phi) ~ p_T(y) |O(y; phi)|: prior proposals (App. B) are accepted with
 // |O(y')| / |O(y)|, the Gaussian random walk with |O(y')| N(y') / (|O(y)| N(y)),
-// Ising single-spin flips with |O(y')| / |O(y)|.  Accept iff u < alpha.
+// Ising single-spin flips with |O(y')| / |O(y)|, the learned proposal with
+// |O(y')| N(y') q(y | z') / (|O(y)| N(y) q(y' | z)), whose log ratio of
+// proposal and prior densities arrives precomputed (k_mlp_reverse).
+// Accept iff u < alpha.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -39,7 +42,9 @@ __global__ void __launch_bounds__(64)
 k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __restrict__ y,
          double* __restrict__ phiT, double* __restrict__ logov, const double* __restrict__ ytry,
          const double* __restrict__ phiTtry, const double* __restrict__ ltry,
-         int* __restrict__ nacc, uint64_t seed, uint64_t step, int sweep, int flip_k) {
+         int* __restrict__ nacc, uint64_t seed, uint64_t step, int sweep, int flip_k,
+         const double* __restrict__ lextra, int M, double* __restrict__ gd_cur,
+         const double* __restrict__ gd_try, int* __restrict__ mask) {
   __shared__ int s_acc[64];
   const int w = blockIdx.x;
   const int lane = threadIdx.x;
@@ -60,6 +65,7 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
         }
         la += -0.5 * n_new + 0.5 * n_old;
       }
+      if (lextra != nullptr) la += lextra[wp];
       const uint32_t ui = (hidden_kind == AFQMC_HIDDEN_ISING) ? (uint32_t)flip_k : 0u;
       const double u = stream_uniform(seed, w, step, rng_word3(AFQMC_TAG_ACCEPT, sweep, p), ui);
       if (__builtin_isnan(la)) la = neg_inf();
@@ -68,6 +74,7 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
         logov[wp * 2] = ln;
         logov[wp * 2 + 1] = ltry[wp * 2 + 1];
       }
+      if (mask != nullptr) mask[wp] = acc;
     }
     s_acc[lane] = acc;
     __syncthreads();
@@ -78,6 +85,8 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
       const size_t wp = (size_t)w * P + p0 + q;
       for (int k = lane; k < K; k += 64) y[wp * K + k] = ytry[wp * K + k];
       for (int e = lane; e < MN; e += 64) phiT[wp * MN + e] = phiTtry[wp * MN + e];
+      if (gd_cur != nullptr)
+        for (int e = lane; e < M; e += 64) gd_cur[wp * M + e] = gd_try[wp * M + e];
       ++count;
     }
     __syncthreads();
@@ -134,11 +143,12 @@ hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double
 
 hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, double* logov,
                          const double* ytry, const double* phiTtry, const double* ltry, int* nacc,
-                         uint64_t seed, uint64_t step, int sweep, int flip_k) {
+                         uint64_t seed, uint64_t step, int sweep, int flip_k, const double* lextra,
+                         double* gd_cur, const double* gd_try, int* mask) {
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->M * c->N,
                      c->hidden_kind, c->proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
-                     step, sweep, flip_k);
+                     step, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
   return hipGetLastError();
 }
 

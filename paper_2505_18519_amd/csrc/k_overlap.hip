@@ -9,8 +9,9 @@
 //     lowest row on ties) and broadcast by lane shuffles instead of swapped;
 //     det = parity(perm) prod u_kk, accumulated as a scaled complex product;
 //  3. optionally Theta^s = phi^s (A^s)^{-1}, one lane per orbital row m:
-//     z U = x, v L = z, Theta[m][perm[k]] = v[k].
-// A zero pivot marks the path singular: l = -inf + 0i and Theta = 0.
+//     z U = x, v L = z, Theta[m][perm[k]] = v[k]; and optionally the Green's
+//     function diagonal Re (G_up + G_dn)_mm = Re sum_s sum_n Theta^s_mn Phi_T,mn.
+// A zero pivot marks the path singular: l = -inf + 0i and Theta = 0, diag = 0.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -22,7 +23,8 @@ constexpr int NT = 16;  // N <= 16
 template <int MT>
 __global__ void __launch_bounds__(OV_WAVES * 64)
 k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
-          const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta) {
+          const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta,
+          double* __restrict__ gdiag) {
   __shared__ double s_lu[OV_WAVES][2][NT][NT][2];  // LU rows in pivot order
   __shared__ int s_perm[OV_WAVES][2][NT];
 
@@ -158,11 +160,15 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       o[1] = argsum + ar_dn;
     }
   }
-  if (theta == nullptr) return;
+  if (theta == nullptr && gdiag == nullptr) return;
 
-  double* th = theta + (size_t)s * 2 * M * N * 2;
+  double* th = theta ? theta + (size_t)s * 2 * M * N * 2 : nullptr;
+  double* gd = gdiag ? gdiag + (size_t)s * M : nullptr;
   if (sing_any) {
-    for (int q = lane; q < 2 * M * N * 2; q += 64) th[q] = 0.0;
+    if (th)
+      for (int q = lane; q < 2 * M * N * 2; q += 64) th[q] = 0.0;
+    if (gd)
+      for (int q = lane; q < M; q += 64) gd[q] = 0.0;
     return;
   }
   // LU rows in step order, and the permutation, to LDS
@@ -179,8 +185,9 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
   // 3. Theta rows: lane = orbital row m
-  for (int spin = 0; spin < 2; ++spin) {
-    for (int m0 = 0; m0 < M; m0 += 64) {
+  for (int m0 = 0; m0 < M; m0 += 64) {
+    double gsum = 0.0;
+    for (int spin = 0; spin < 2; ++spin) {
       const int m = m0 + lane;
       if (m < M) {
         cplx x[NT];
@@ -210,39 +217,43 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
             x[j] = acc2;
           }
         }
-        double* dst = th + ((size_t)(spin * M + m) * N) * 2;
+        double* dst = th ? th + ((size_t)(spin * M + m) * N) * 2 : nullptr;
 #pragma unroll
         for (int k = 0; k < NT; ++k)
           if (k < N) {
             const int col = min(max(s_perm[wave][spin][k], 0), N - 1);
-            dst[2 * col] = x[k].re;
-            dst[2 * col + 1] = x[k].im;
+            if (dst) {
+              dst[2 * col] = x[k].re;
+              dst[2 * col + 1] = x[k].im;
+            }
+            gsum = fma(x[k].re, pT[m * N + col], gsum);
           }
       }
     }
+    if (gd && m0 + lane < M) gd[m0 + lane] = gsum;
   }
 }
 
 template <int MT>
 hipError_t launch_mt(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                     double* logov, double* theta) {
+                     double* logov, double* theta, double* gdiag) {
   const int n = nw * c->P;
   dim3 grid((n + OV_WAVES - 1) / OV_WAVES), block(OV_WAVES * 64);
   hipLaunchKernelGGL(k_overlap<MT>, grid, block, 0, c->stream, n, c->P, c->M, c->N, phi, phiT,
-                     logov, theta);
+                     logov, theta, gdiag);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                          double* logov, double* theta) {
+                          double* logov, double* theta, double* gdiag) {
   if (nw <= 0) return hipSuccess;
   switch (c->MT) {
-    case 16: return launch_mt<16>(c, nw, phi, phiT, logov, theta);
-    case 32: return launch_mt<32>(c, nw, phi, phiT, logov, theta);
-    case 48: return launch_mt<48>(c, nw, phi, phiT, logov, theta);
-    case 64: return launch_mt<64>(c, nw, phi, phiT, logov, theta);
+    case 16: return launch_mt<16>(c, nw, phi, phiT, logov, theta, gdiag);
+    case 32: return launch_mt<32>(c, nw, phi, phiT, logov, theta, gdiag);
+    case 48: return launch_mt<48>(c, nw, phi, phiT, logov, theta, gdiag);
+    case 64: return launch_mt<64>(c, nw, phi, phiT, logov, theta, gdiag);
     default: return hipErrorInvalidValue;
   }
 }

@@ -5,8 +5,9 @@
 //  1. A^s = Phi_T^T phi^s on the FP64 matrix cores (NTC x NTC tiles of 16);
 //  2. LU with partial pivoting, one lane per row (N <= 32 lanes), pivot rows
 //     found by a max reduction over the 64 lanes and broadcast by shuffles;
-//  3. optionally Theta^s = phi^s (A^s)^{-1}, lanes over orbital rows m.
-// The two spins' log-determinants are added through LDS.
+//  3. optionally Theta^s = phi^s (A^s)^{-1}, lanes over orbital rows m, and
+//     the Green's function diagonal Re (G_up + G_dn)_mm.
+// The two spins' log-determinants and diagonals are added through LDS.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -15,11 +16,13 @@ namespace {
 template <int NTC>
 __global__ void __launch_bounds__(128)
 k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
-            const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta) {
+            const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta,
+            double* __restrict__ gdiag) {
   constexpr int NT = 16 * NTC;
   __shared__ double s_lu[2][NT][NT + 1][2];
   __shared__ int s_perm[2][NT];
   __shared__ double s_res[2][3];
+  __shared__ double s_gd[128];  // M <= 128
 
   const int s = blockIdx.x;
   const int sp = threadIdx.x >> 6;  // spin of this wavefront
@@ -151,68 +154,82 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
     o[0] = sing_any ? neg_inf() : s_res[0][0] + s_res[1][0];
     o[1] = sing_any ? 0.0 : s_res[0][1] + s_res[1][1];
   }
-  if (theta == nullptr) return;
-  double* th = theta + ((size_t)s * 2 + sp) * M * N * 2;
+  if (theta == nullptr && gdiag == nullptr) return;
+  double* th = theta ? theta + ((size_t)s * 2 + sp) * M * N * 2 : nullptr;
+  double* gd = gdiag ? gdiag + (size_t)s * M : nullptr;
   if (sing_any) {
-    for (int q = lane; q < M * N * 2; q += 64) th[q] = 0.0;
+    if (th)
+      for (int q = lane; q < M * N * 2; q += 64) th[q] = 0.0;
+    if (gd && sp == 0)
+      for (int q = lane; q < M; q += 64) gd[q] = 0.0;
     return;
   }
-  // 3. Theta rows
+  // 3. Theta rows (every lane reaches the barriers; lanes past M idle)
   for (int m0 = 0; m0 < M; m0 += 64) {
     const int m = m0 + lane;
-    if (m >= M) continue;
-    cplx x[NT];
-    const double* src = pw + (size_t)m * N * 2;
+    double gsum = 0.0;
+    if (m < M) {
+      cplx x[NT];
+      const double* src = pw + (size_t)m * N * 2;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) x[j] = (j < N) ? cmk(src[2 * j], src[2 * j + 1]) : cmk(0, 0);
+      for (int j = 0; j < NT; ++j) x[j] = (j < N) ? cmk(src[2 * j], src[2 * j + 1]) : cmk(0, 0);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      if (j < N) {
-        cplx acc2 = x[j];
+      for (int j = 0; j < NT; ++j) {
+        if (j < N) {
+          cplx acc2 = x[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k)
-          acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
-        x[j] = cdiv(acc2, cmk(s_lu[sp][j][j][0], s_lu[sp][j][j][1]));
+          for (int k = 0; k < j; ++k)
+            acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
+          x[j] = cdiv(acc2, cmk(s_lu[sp][j][j][0], s_lu[sp][j][j][1]));
+        }
       }
+#pragma unroll
+      for (int j = NT - 1; j >= 0; --j) {
+        if (j < N) {
+          cplx acc2 = x[j];
+#pragma unroll
+          for (int k = j + 1; k < NT; ++k)
+            if (k < N) acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
+          x[j] = acc2;
+        }
+      }
+      double* dst = th ? th + (size_t)m * N * 2 : nullptr;
+#pragma unroll
+      for (int k = 0; k < NT; ++k)
+        if (k < N) {
+          const int col = min(max(s_perm[sp][k], 0), N - 1);
+          if (dst) {
+            dst[2 * col] = x[k].re;
+            dst[2 * col + 1] = x[k].im;
+          }
+          gsum = fma(x[k].re, pT[m * N + col], gsum);
+        }
+      if (sp == 1) s_gd[m] = gsum;
     }
-#pragma unroll
-    for (int j = NT - 1; j >= 0; --j) {
-      if (j < N) {
-        cplx acc2 = x[j];
-#pragma unroll
-        for (int k = j + 1; k < NT; ++k)
-          if (k < N) acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
-        x[j] = acc2;
-      }
-    }
-    double* dst = th + (size_t)m * N * 2;
-#pragma unroll
-    for (int k = 0; k < NT; ++k)
-      if (k < N) {
-        const int col = min(max(s_perm[sp][k], 0), N - 1);
-        dst[2 * col] = x[k].re;
-        dst[2 * col + 1] = x[k].im;
-      }
+    if (gd == nullptr) continue;  // block-uniform
+    __syncthreads();
+    if (sp == 0 && m < M) gd[m] = gsum + s_gd[m];
+    __syncthreads();
   }
 }
 
 template <int NTC>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                    double* logov, double* theta) {
+                    double* logov, double* theta, double* gdiag) {
   const int n = nw * c->P;
   hipLaunchKernelGGL(k_overlap_g<NTC>, dim3(n), dim3(128), 0, c->stream, n, c->P, c->M, c->N, phi,
-                     phiT, logov, theta);
+                     phiT, logov, theta, gdiag);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
-                            double* logov, double* theta) {
+                            double* logov, double* theta, double* gdiag) {
   if (nw <= 0) return hipSuccess;
   switch ((c->N + 15) / 16) {
-    case 1: return launch_g<1>(c, nw, phi, phiT, logov, theta);
-    case 2: return launch_g<2>(c, nw, phi, phiT, logov, theta);
+    case 1: return launch_g<1>(c, nw, phi, phiT, logov, theta, gdiag);
+    case 2: return launch_g<2>(c, nw, phi, phiT, logov, theta, gdiag);
     default: return hipErrorInvalidValue;
   }
 }

@@ -148,15 +148,20 @@ def test_zero_output_layer_reduces_to_the_prior_proposal():
     assert np.array_equal(a[3], b[3])
 
 
+def _toy():
+    """K = 2 Gaussian-hidden toy whose path density p_T |O| is clearly shifted
+    from the prior (E y_2 = 0.85, E y_2^2 = 1.8 by quadrature)."""
+    return ai.gaussian_system(6, 2, 3, 2, seed=4, coupling=0.15, density=0.6)
+
+
 def test_learned_chain_samples_the_path_density():
     """Detailed balance of the learned proposal on a K = 2 Gaussian toy with a
     state-dependent network: the chains' mean and second moments of y match
     quadrature of p_T(y) |O(y; phi)| (Eq. PDF-Y)."""
-    s = ai.small_gaussian(M=6, N=2, n_chol=3, K=2, seed=4)
-    s.coupling = 0.8
+    s = _toy()
     rng = np.random.default_rng(2)
     phi = ai.random_walkers(rng, s, 1, spread=0.8)
-    P = 96
+    P = 160
     p = ai.mlp_params(np.random.default_rng(3), s.M, s.K, H=12, last_scale=1.5)
     p["b3"][2:] = 0.4          # proposals wider than the prior
     y = rng.normal(size=(1, P, 2))
@@ -188,11 +193,10 @@ def test_learned_chain_with_the_reverse_density_at_the_wrong_state_is_biased():
     """The detailed-balance check above has the power to see a wrong q ratio:
     evaluating the reverse density with the current state's features instead
     of the proposal's biases the sampled moments well beyond 5 sigma."""
-    s = ai.small_gaussian(M=6, N=2, n_chol=3, K=2, seed=4)
-    s.coupling = 0.8
+    s = _toy()
     rng = np.random.default_rng(2)
     phi = ai.random_walkers(rng, s, 1, spread=0.8)
-    P = 96
+    P = 160
     p = ai.mlp_params(np.random.default_rng(3), s.M, s.K, H=12, last_scale=1.5)
     p["b3"][2:] = 0.4
     y = rng.normal(size=(1, P, 2))
