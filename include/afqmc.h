@@ -175,9 +175,14 @@ afqmc_status afqmc_propagate(afqmc_ctx ctx, int32_t nw, void* phi, const double*
  * l(y'; phi) are formed, and y' is accepted iff u < alpha (stream ACCEPT),
  * alpha = |O(y')|/|O(y)| for prior proposals, times N(y')/N(y) for the
  * random walk, times N(y')q(y|z',y')/(N(y)q(y'|z,y)) for the learned proposal
- * (z, z' the network features at y and y', see afqmc_mlp_init; with training
- * on, one Adam step follows each sweep).  Accepted paths update y, phiT and
- * logov in place.  Then
+ * (z, z' the network features at y and y', see afqmc_mlp_init).  With the
+ * learned proposal and rw_step > 0 each sweep is a random-walk move y~ = y +
+ * rw_step eta (stream sweep index 2s) followed by a network move (2s + 1), a
+ * cycle of two exact kernels; with training on, one Adam step on the mean
+ * over all paths of -log q(y | z(y~)) (denoising score matching on the
+ * random-walk pairs) precedes each random-walk accept test.  n_accept counts
+ * both kinds of move.  Accepted paths update y, phiT and logov in place.
+ * Then
  *   dtheta_T = arg sum_p S'_p - arg ref,  W <- W max(0, cos dtheta_T)
  * (HALFPLANE: W <- 0 if |dtheta_T| > pi/2).  n_accept [nw] int32 counts
  * accepted moves per walker (may be NULL). */
@@ -224,11 +229,15 @@ afqmc_status afqmc_philox_normal(afqmc_ctx ctx, uint64_t seed, uint64_t step, ui
  * Gaussian hidden variables of a path at once from the features
  *   z = [Re diag(G_up + G_dn) (M values), y (K values)]   (D = M + K inputs),
  *   h1 = tanh(z W1 + b1), h2 = tanh(h1 W2 + b2), o = h2 W3 + b3,
- *   mu = o[0:K], lv = 4 tanh(o[K:2K] / 4),  y' = mu + exp(lv / 2) eta,
- * eta from stream PROPOSAL.  The acceptance uses the exact Metropolis-Hastings
- * ratio with the reverse density at the proposal's own features, so the paths
- * keep sampling P(y; phi) of Eq. PDF-Y whatever the weights are.  Training
- * minimises the mean of -log q(y' | z, y) over accepted moves with Adam.
+ *   mu = y + o[0:K], lv = 4 tanh(o[K:2K] / 4),  y' = mu + sqrt(2 exp(lv)) eta,
+ * eta from stream PROPOSAL; a zero output layer (W3 = b3 = 0) is the random
+ * walk of step sqrt(2).  The acceptance uses the exact Metropolis-Hastings ratio with
+ * the reverse density at the proposal's own features, so the paths keep
+ * sampling P(y; phi) of Eq. PDF-Y whatever the weights are.  Training (Adam)
+ * makes mu(y~) the denoiser E[y | y~] and exp(lv) the variance Var[y | y~]
+ * of the chains' random-walk moves y~ = y + s eta (see afqmc_metropolis_x):
+ * mu - y is then the drift s^2 grad log p of a Langevin step whose noise
+ * variance is 2 s^2, the proposal above.
  * Parameters are one flat array in the order W1 [D][H], b1 [H], W2 [H][H],
  * b2 [H], W3 [H][2K], b3 [2K] (row-major, H = AFQMC_MLP_HIDDEN).  The context
  * keeps FP32 master weights and Adam moments; the products run on the matrix
@@ -251,12 +260,13 @@ afqmc_status afqmc_mlp_init(afqmc_ctx ctx, int32_t precision, const double* para
 /* Copies the FP32 master parameters to HOST double [n_params]; synchronises. */
 afqmc_status afqmc_mlp_get_params(afqmc_ctx ctx, double* params);
 
-/* Whether afqmc_metropolis_x trains the network after each sweep (0 / 1). */
+/* Whether afqmc_metropolis_x trains the network in each sweep (0 / 1);
+ * training needs rw_step > 0 (AFQMC_E_INVALID otherwise). */
 afqmc_status afqmc_mlp_set_training(afqmc_ctx ctx, int32_t enabled);
 
 /* Network outputs for n feature rows given as gdiag [n][M] and y [n][K]
- * (DEVICE double): mu [n][K] and lv [n][K] (DEVICE double).  Needs the
- * workspace of ceil(n / P) walkers. */
+ * (DEVICE double): mu [n][K] (= y + o) and lv [n][K] (DEVICE double).  Needs
+ * the workspace of ceil(n / P) walkers. */
 afqmc_status afqmc_mlp_forward(afqmc_ctx ctx, int32_t n, const double* gdiag, const double* y,
                                double* mu, double* lv);
 

@@ -133,9 +133,14 @@ class Context:
     """Owns an afqmc_ctx and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
-                 proposal=PROPOSAL_PRIOR, rw_step=0.5, max_walkers=1, device=0, xbar_cap=0.0,
+                 proposal=PROPOSAL_PRIOR, rw_step=None, max_walkers=1, device=0, xbar_cap=0.0,
                  precision=PREC_FP64):
+        """rw_step: the random-walk step (default 0.5 for PROPOSAL_RW); with
+        PROPOSAL_LEARNED a value > 0 cycles random-walk and network moves
+        (default 0: network moves only)."""
         import numpy as np
+        if rw_step is None:
+            rw_step = 0.5 if proposal == PROPOSAL_RW else 0.0
         lib = load_library()
         if not torch.cuda.is_available():
             raise AfqmcError("no GPU available for libafqmc")

@@ -92,8 +92,8 @@ hipError_t do_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const dou
 // backward pass, weight gradients, loss reduction and Adam step on the rows
 // whose mask is set; out holds the forward outputs, zT/h1T/h2T its activations
 afqmc_status mlp_train(afqmc_ctx_s* c, const ws_layout& L, int n, const float* out,
-                       const double* ytgt, const int* mask, const void* zT, double* loss,
-                       double* grad);
+                       const double* yin, const double* ytgt, const int* mask, const void* zT,
+                       double* loss, double* grad);
 
 }  // namespace
 
@@ -140,13 +140,12 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   const size_t np = D * H + H + H * H + H + H * 2 * c->K + 2 * c->K;
   const size_t nsplit = (Sp + MLP_CHUNK - 1) / MLP_CHUNK;
   const size_t sizes[] = {ml ? S * c->M * 8 : 0, ml ? S * c->M * 8 : 0, Sp * Op * 4, Sp * Op * 4,
-                          ml ? S * 8 : 0,       ml ? S * 8 : 0,       Sp * 4,      D * Sp * 4,
-                          H * Sp * 4,           H * Sp * 4,           Op * Sp * 4, H * Sp * 4,
-                          H * Sp * 4,           Sp * 8,               nsplit * np * 4,
-                          ml ? (size_t)256 : 0};
-  size_t* dst[] = {&L.gd_cur, &L.gd_try, &L.mlF, &L.mlR, &L.lqf, &L.lqx, &L.mask, &L.zT,
-                   &L.h1T,    &L.h2T,    &L.dOT, &L.dh2T, &L.dh1T, &L.nlq, &L.part, &L.mlio};
-  for (int i = 0; i < 16; ++i) {
+                          ml ? S * 8 : 0,       ml ? S * 8 : 0,       D * Sp * 4,  H * Sp * 4,
+                          H * Sp * 4,           Op * Sp * 4,          H * Sp * 4,  H * Sp * 4,
+                          Sp * 8,               nsplit * np * 4};
+  size_t* dst[] = {&L.gd_cur, &L.gd_try, &L.mlF,  &L.mlR,  &L.lqf, &L.lqx, &L.zT,
+                   &L.h1T,    &L.h2T,    &L.dOT,  &L.dh2T, &L.dh1T, &L.nlq, &L.part};
+  for (int i = 0; i < 14; ++i) {
     *dst[i] = off;
     off += align256(sizes[i]);
   }
@@ -157,8 +156,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
 namespace {
 
 afqmc_status mlp_train(afqmc_ctx_s* c, const ws_layout& L, int n, const float* out,
-                       const double* ytgt, const int* mask, const void* zT, double* loss,
-                       double* grad) {
+                       const double* yin, const double* ytgt, const int* mask, const void* zT,
+                       double* loss, double* grad) {
   const int Sp = round16(n);
   void* h1T = ws_ptr<void>(c, L.h1T);
   void* h2T = ws_ptr<void>(c, L.h2T);
@@ -167,7 +166,8 @@ afqmc_status mlp_train(afqmc_ctx_s* c, const ws_layout& L, int n, const float* o
   void* dh1T = ws_ptr<void>(c, L.dh1T);
   double* nlq = ws_ptr<double>(c, L.nlq);
   float* part = ws_ptr<float>(c, L.part);
-  HIPCALL(c, launch_mlp_backward(c, n, Sp, out, ytgt, mask, h1T, h2T, dOT, dh2T, dh1T, nlq),
+  HIPCALL(c,
+          launch_mlp_backward(c, n, Sp, out, yin, ytgt, mask, h1T, h2T, dOT, dh2T, dh1T, nlq),
           "mlp backward");
   HIPCALL(c, launch_mlp_wgrad(c, Sp, zT, h1T, h2T, dOT, dh2T, dh1T, part), "mlp weight gradients");
   HIPCALL(c, launch_mlp_reduce(c, n, mask, nlq, loss), "mlp loss");
@@ -469,16 +469,36 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
     float* mlR = ws_ptr<float>(c, L.mlR);
     double* lqf = ws_ptr<double>(c, L.lqf);
     double* lqx = ws_ptr<double>(c, L.lqx);
-    int* mask = ws_ptr<int>(c, L.mask);
     const bool tr = c->mlp.training;
-    void* zT = tr ? ws_ptr<void>(c, L.zT) : nullptr;
+    void* zT = ws_ptr<void>(c, L.zT);
     void* h1T = ws_ptr<void>(c, L.h1T);
     void* h2T = ws_ptr<void>(c, L.h2T);
+    const bool hybrid = c->rw_step > 0.0;
     if (n_sweep > 0)
       HIPCALL(c, do_overlap(c, nw, ph, phiT, ltry, nullptr, gdc), "green diagonal");
     for (int s = 0; s < n_sweep; ++s) {
-      HIPCALL(c, launch_mlp_forward(c, n, Sp, gdc, y, mlF, zT, h1T, h2T), "mlp forward");
-      HIPCALL(c, launch_mlp_propose(c, nw, mlF, seed, step, s, ytry, lqf), "mlp propose");
+      int sl = s;
+      if (hybrid) {  // random-walk move first (stream sweep index 2s), diagonals kept current
+        HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, 2 * s, -1, AFQMC_PROPOSAL_RW),
+                "rw proposal");
+        HIPCALL(c, do_trial_build(c, n, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+                "rw trial build");
+        HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr, gdt), "rw overlap");
+        if (tr) {  // denoising score matching: q(y | z(y~)) on this move's pairs
+          HIPCALL(c, launch_mlp_forward(c, n, Sp, gdt, ytry, mlF, zT, h1T, h2T),
+                  "mlp training forward");
+          afqmc_status st2 = mlp_train(c, L, n, mlF, ytry, y, nullptr, zT, nullptr, nullptr);
+          if (st2 != AFQMC_OK) return st2;
+        }
+        HIPCALL(c,
+                launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, 2 * s, -1,
+                              AFQMC_PROPOSAL_RW, nullptr, gdc, gdt, nullptr),
+                "rw accept");
+        sl = 2 * s + 1;
+      }
+      HIPCALL(c, launch_mlp_forward(c, n, Sp, gdc, y, mlF, nullptr, nullptr, nullptr),
+              "mlp forward");
+      HIPCALL(c, launch_mlp_propose(c, nw, mlF, y, seed, step, sl, ytry, lqf), "mlp propose");
       HIPCALL(c, do_trial_build(c, n, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
               "proposal trial build");
       HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr, gdt), "proposal overlap");
@@ -486,13 +506,9 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
               "mlp reverse forward");
       HIPCALL(c, launch_mlp_reverse(c, n, mlR, y, ytry, lqf, lqx), "mlp reverse");
       HIPCALL(c,
-              launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, -1, lqx,
-                            gdc, gdt, mask),
+              launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, sl, -1,
+                            AFQMC_PROPOSAL_LEARNED, lqx, gdc, gdt, nullptr),
               "accept");
-      if (tr) {
-        afqmc_status st2 = mlp_train(c, L, n, mlF, ytry, mask, zT, nullptr, nullptr);
-        if (st2 != AFQMC_OK) return st2;
-      }
     }
     HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
     return AFQMC_OK;
@@ -501,11 +517,13 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
   for (int s = 0; s < n_sweep; ++s) {
     for (int f = 0; f < nflip; ++f) {
       const int flip_k = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? f : -1;
-      HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k), "proposal");
+      HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k, c->proposal), "proposal");
       HIPCALL(c, do_trial_build(c, nw * c->P, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
               "proposal trial build");
       HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
-      HIPCALL(c, launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, flip_k),
+      HIPCALL(c,
+              launch_accept(c, nw, y, phiT, lo, ytry, phiTtry, ltry, nacc, seed, step, s, flip_k,
+                            c->proposal),
               "accept");
     }
   }
@@ -670,6 +688,8 @@ afqmc_status afqmc_mlp_set_training(afqmc_ctx c, int32_t enabled) {
   if (c == nullptr) return AFQMC_E_INVALID;
   if (!c->mlp.ready) return fail(c, AFQMC_E_INVALID, "network not initialised (afqmc_mlp_init)");
   if (enabled != 0 && enabled != 1) return fail(c, AFQMC_E_INVALID, "enabled must be 0 or 1");
+  if (enabled && !(c->rw_step > 0.0))
+    return fail(c, AFQMC_E_INVALID, "training uses the random-walk moves: needs rw_step > 0");
   c->mlp.training = enabled != 0;
   return AFQMC_OK;
 }
@@ -689,7 +709,7 @@ afqmc_status afqmc_mlp_forward(afqmc_ctx c, int32_t n, const double* gdiag, cons
   float* out = ws_ptr<float>(c, L.mlF);
   HIPCALL(c, launch_mlp_forward(c, n, round16(n), gdiag, y, out, nullptr, nullptr, nullptr),
           "mlp forward");
-  HIPCALL(c, launch_mlp_outputs(c, n, out, mu, lv), "mlp outputs");
+  HIPCALL(c, launch_mlp_outputs(c, n, out, y, mu, lv), "mlp outputs");
   return AFQMC_OK;
 }
 
@@ -712,7 +732,7 @@ afqmc_status afqmc_mlp_train_step(afqmc_ctx c, int32_t n, const double* gdiag, c
           launch_mlp_forward(c, n, round16(n), gdiag, y, out, zT, ws_ptr<void>(c, L.h1T),
                              ws_ptr<void>(c, L.h2T)),
           "mlp forward");
-  return mlp_train(c, L, n, out, ytarget, mask, zT, loss, grad);
+  return mlp_train(c, L, n, out, y, ytarget, mask, zT, loss, grad);
 }
 
 afqmc_status afqmc_green_diag(afqmc_ctx c, int32_t nw, const void* phi, const double* phiT,

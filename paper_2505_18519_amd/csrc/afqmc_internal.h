@@ -58,7 +58,7 @@ struct ws_layout {
   size_t vb, ep, vmat, ubuf, qrshift, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
       pc_logov;
   // learned proposal (zero-sized unless proposal == LEARNED); Sp = paths rounded up to 16
-  size_t gd_cur, gd_try, mlF, mlR, lqf, lqx, mask, zT, h1T, h2T, dOT, dh2T, dh1T, nlq, part, mlio;
+  size_t gd_cur, gd_try, mlF, mlR, lqf, lqx, zT, h1T, h2T, dOT, dh2T, dh1T, nlq, part;
   size_t total;
 };
 constexpr int MLP_CHUNK = 512;  // samples per split of the weight-gradient sums
@@ -86,12 +86,14 @@ hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, doubl
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
                          const double* logov, const double* logov_new, double e_shift, double* w,
                          double* ref);
+// proposal: the kind of move (AFQMC_PROPOSAL_PRIOR or _RW; the learned
+// proposal's random-walk moves pass _RW)
 hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double* ytry,
-                           uint64_t seed, uint64_t step, int sweep, int flip_k);
+                           uint64_t seed, uint64_t step, int sweep, int flip_k, int proposal);
 hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, double* logov,
                          const double* ytry, const double* phiTtry, const double* ltry,
                          int* nacc, uint64_t seed, uint64_t step, int sweep, int flip_k,
-                         const double* lextra = nullptr, double* gd_cur = nullptr,
+                         int proposal, const double* lextra = nullptr, double* gd_cur = nullptr,
                          const double* gd_try = nullptr, int* mask = nullptr);
 hipError_t launch_handoff(const afqmc_ctx_s* c, int nw, const double* logov, const double* ref,
                           double* w);
@@ -120,17 +122,20 @@ hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* pa
 hipError_t launch_mlp_setparams(const afqmc_ctx_s* c, const double* src);
 hipError_t launch_mlp_forward(const afqmc_ctx_s* c, int n, int Sp, const double* gd, const double* y,
                               float* out, void* zT, void* h1T, void* h2T);
-hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, uint64_t seed,
-                              uint64_t step, int sweep, double* ytry, double* lqf);
+hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, const double* y,
+                              uint64_t seed, uint64_t step, int sweep, double* ytry, double* lqf);
 hipError_t launch_mlp_reverse(const afqmc_ctx_s* c, int n, const float* outR, const double* y,
                               const double* ytry, const double* lqf, double* lqx);
+// yin: the y block of the forward pass's input; mask NULL = every row
 hipError_t launch_mlp_backward(const afqmc_ctx_s* c, int n, int Sp, const float* out,
-                               const double* ytgt, const int* mask, const void* h1T,
-                               const void* h2T, void* dOT, void* dh2T, void* dh1T, double* nlq);
+                               const double* yin, const double* ytgt, const int* mask,
+                               const void* h1T, const void* h2T, void* dOT, void* dh2T, void* dh1T,
+                               double* nlq);
 hipError_t launch_mlp_wgrad(const afqmc_ctx_s* c, int Sp, const void* zT, const void* h1T,
                             const void* h2T, const void* dOT, const void* dh2T, const void* dh1T,
                             float* part);
 hipError_t launch_mlp_reduce(const afqmc_ctx_s* c, int n, const int* mask, const double* nlq,
                              double* loss);
 hipError_t launch_mlp_adam(const afqmc_ctx_s* c, int Sp, const float* part, double* grad);
-hipError_t launch_mlp_outputs(const afqmc_ctx_s* c, int n, const float* out, double* mu, double* lv);
+hipError_t launch_mlp_outputs(const afqmc_ctx_s* c, int n, const float* out, const double* y,
+                              double* mu, double* lv);

@@ -131,23 +131,23 @@ k_handoff(int nw, int P, int weight_mode, const double* __restrict__ logov,
 }  // namespace
 
 hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double* ytry,
-                           uint64_t seed, uint64_t step, int sweep, int flip_k) {
+                           uint64_t seed, uint64_t step, int sweep, int flip_k, int proposal) {
   const size_t total = (size_t)nw * c->P * c->K;
   if (total == 0) return hipSuccess;
   const int bs = 256;
   hipLaunchKernelGGL(k_proposal, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, c->stream,
-                     nw, c->P, c->K, c->hidden_kind, c->proposal, c->rw_step, y, ytry, seed, step,
+                     nw, c->P, c->K, c->hidden_kind, proposal, c->rw_step, y, ytry, seed, step,
                      sweep, flip_k);
   return hipGetLastError();
 }
 
 hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, double* logov,
                          const double* ytry, const double* phiTtry, const double* ltry, int* nacc,
-                         uint64_t seed, uint64_t step, int sweep, int flip_k, const double* lextra,
-                         double* gd_cur, const double* gd_try, int* mask) {
+                         uint64_t seed, uint64_t step, int sweep, int flip_k, int proposal,
+                         const double* lextra, double* gd_cur, const double* gd_try, int* mask) {
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->M * c->N,
-                     c->hidden_kind, c->proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
+                     c->hidden_kind, proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
                      step, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
   return hipGetLastError();
 }

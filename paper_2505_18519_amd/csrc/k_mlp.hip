@@ -4,8 +4,12 @@
 // acceptance that keeps the chains exact lives in k_metropolis.hip.
 //
 // Network: z = [Re diag G (M), y (K)] -> h1 = tanh(z W1 + b1) -> h2 =
-// tanh(h1 W2 + b2) -> o = h2 W3 + b3, mu = o[0:K], lv = 4 tanh(o[K:2K] / 4),
-// q(y' | z) = N(mu, diag exp(lv)).  H = 256 hidden units.
+// tanh(h1 W2 + b2) -> o = h2 W3 + b3, mu = y + o[0:K] (a displacement from
+// the input state), lv = 4 tanh(o[K:2K] / 4), q(y' | z) = N(mu, diag exp(lv)).
+// The proposal is N(mu, 2 exp(lv)): trained as the denoiser of the random-walk
+// moves, mu - y is the drift s^2 grad log p of a Langevin step whose noise
+// variance is 2 s^2.  H = 256 hidden units.  The forward pass stores o[0:K]
+// and lv; the kernels that use mu add the input state in FP64.
 //
 // Data layout.
 //  * One wavefront owns 16 samples (the columns of every 16x16 product) and
@@ -99,7 +103,8 @@ __device__ __forceinline__ fx4 fx4_zero() {
 }
 
 // ---------------------------------------------------------------------------
-// Forward pass.  out[s][0:K] = mu, out[s][K:2K] = lv (FP32, row stride Op).
+// Forward pass.  out[s][0:K] = o[0:K] (mu - y), out[s][K:2K] = lv (FP32, row
+// stride Op).
 // TRAIN also stores zT [D][Sp], h1T [H][Sp], h2T [H][Sp] in the product type.
 
 template <class T, bool TRAIN>
@@ -207,12 +212,14 @@ k_mlp_fwd(int n, int Sp, int M, int K, int D, int Dp, int O, int Op,
 }
 
 // ---------------------------------------------------------------------------
-// Proposal y' = mu + exp(lv / 2) eta (eta: stream PROPOSAL) and log q(y' | z).
-// One 64-lane workgroup per path; lane = block of four hidden variables.
+// Proposal y' = mu + sqrt(2 exp(lv)) eta (eta: stream PROPOSAL), mu = y + o,
+// and log q(y' | z).  One 64-lane workgroup per path; lane = block of four
+// hidden variables.
 
 __global__ void __launch_bounds__(64)
-k_mlp_propose(int P, int K, int Op, const float* __restrict__ out, uint64_t seed, uint64_t step,
-              int sweep, double* __restrict__ ytry, double* __restrict__ lqf) {
+k_mlp_propose(int P, int K, int Op, const float* __restrict__ out, const double* __restrict__ y,
+              uint64_t seed, uint64_t step, int sweep, double* __restrict__ ytry,
+              double* __restrict__ lqf) {
   const int wp = blockIdx.x, lane = threadIdx.x;
   const int w = wp / P, p = wp % P;
   const double hl2pi = 0.5 * log(2.0 * M_PI);
@@ -226,7 +233,8 @@ k_mlp_propose(int P, int K, int Op, const float* __restrict__ out, uint64_t seed
     for (int j = 0; j < 4; ++j) {
       const int k = 4 * kb + j;
       if (k < K) {
-        const double mu = out[(size_t)wp * Op + k], lv = out[(size_t)wp * Op + K + k];
+        const double mu = y[(size_t)wp * K + k] + (double)out[(size_t)wp * Op + k];
+        const double lv = out[(size_t)wp * Op + K + k] + M_LN2;   // proposal variance
         const double yv = mu + exp(0.5 * lv) * z[j];
         ytry[(size_t)wp * K + k] = yv;
         const double d = yv - mu;
@@ -239,7 +247,8 @@ k_mlp_propose(int P, int K, int Op, const float* __restrict__ out, uint64_t seed
 }
 
 // lqx = log q(y | z') - log q(y' | z) - |y'|^2 / 2 + |y|^2 / 2 (log of the
-// proposal and prior ratios in the Metropolis-Hastings acceptance)
+// proposal and prior ratios in the Metropolis-Hastings acceptance); the
+// reverse mean is y' + o(z')
 __global__ void __launch_bounds__(64)
 k_mlp_reverse(int K, int Op, const float* __restrict__ outR, const double* __restrict__ y,
               const double* __restrict__ ytry, const double* __restrict__ lqf,
@@ -248,8 +257,9 @@ k_mlp_reverse(int K, int Op, const float* __restrict__ outR, const double* __res
   const double hl2pi = 0.5 * log(2.0 * M_PI);
   double lq = 0.0, nn = 0.0, no = 0.0;
   for (int k = lane; k < K; k += 64) {
-    const double mu = outR[(size_t)wp * Op + k], lv = outR[(size_t)wp * Op + K + k];
     const double yo = y[(size_t)wp * K + k], yn = ytry[(size_t)wp * K + k];
+    const double mu = yn + (double)outR[(size_t)wp * Op + k];
+    const double lv = outR[(size_t)wp * Op + K + k] + M_LN2;
     const double d = yo - mu;
     lq += -0.5 * lv - 0.5 * d * d * exp(-lv) - hl2pi;
     nn += yn * yn;
@@ -263,13 +273,15 @@ k_mlp_reverse(int K, int Op, const float* __restrict__ outR, const double* __res
 
 // ---------------------------------------------------------------------------
 // Backward pass for the loss sum_s mask_s (-log q(ytgt_s | z_s)) (the mean's
-// 1/count is applied in the Adam kernel).  Writes dOT [Op][Sp], dh2T [H][Sp],
+// 1/count is applied in the Adam kernel); yin = the y block of z_s, so that
+// mu = yin + o; mask NULL = every row.  Writes dOT [Op][Sp], dh2T [H][Sp],
 // dh1T [H][Sp] (errors at the pre-activations) and nlq[s] = -log q (masked).
 
 template <class T>
 __global__ void __launch_bounds__(256)
 k_mlp_bwd(int n, int Sp, int K, int O, int Op, const float* __restrict__ out,
-          const double* __restrict__ ytgt, const int* __restrict__ mask, const T* __restrict__ w2c,
+          const double* __restrict__ yin, const double* __restrict__ ytgt,
+          const int* __restrict__ mask, const T* __restrict__ w2c,
           const T* __restrict__ w3c, const T* __restrict__ h1T, const T* __restrict__ h2T,
           T* __restrict__ dOT, T* __restrict__ dh2T, T* __restrict__ dh1T,
           double* __restrict__ nlq) {
@@ -279,7 +291,7 @@ k_mlp_bwd(int n, int Sp, int K, int O, int Op, const float* __restrict__ out,
   const int s0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   if (s0 >= Sp) return;
   const int s = s0 + c;
-  const bool on = s < n && mask[s] != 0;
+  const bool on = s < n && (mask == nullptr || mask[s] != 0);
   const int OQ = Op >> 4;
   const double hl2pi = 0.5 * log(2.0 * M_PI);
 
@@ -296,7 +308,8 @@ k_mlp_bwd(int n, int Sp, int K, int O, int Op, const float* __restrict__ out,
         double gv = 0.0;
         if (on && u < O) {
           const int k = u < K ? u : u - K;
-          const double mu = out[(size_t)s * Op + k], lv = out[(size_t)s * Op + K + k];
+          const double mu = yin[(size_t)s * K + k] + (double)out[(size_t)s * Op + k];
+          const double lv = out[(size_t)s * Op + K + k];
           const double d = ytgt[(size_t)s * K + k] - mu, e = exp(-lv);
           if (u < K) {
             gv = -d * e;
@@ -442,7 +455,7 @@ k_mlp_reduce(int n, const int* __restrict__ mask, const double* __restrict__ nlq
   const int tid = threadIdx.x;
   double cn = 0.0, ls = 0.0;
   for (int s = tid; s < n; s += 256)
-    if (mask[s] != 0) {
+    if (mask == nullptr || mask[s] != 0) {
       cn += 1.0;
       ls += nlq[s];
     }
@@ -536,12 +549,13 @@ k_mlp_adam(mlp_geom m, int nsplit, const float* __restrict__ part, const double*
 }
 
 __global__ void k_mlp_outputs(int n, int K, int Op, const float* __restrict__ out,
-                              double* __restrict__ mu, double* __restrict__ lv) {
+                              const double* __restrict__ y, double* __restrict__ mu,
+                              double* __restrict__ lv) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * K) return;
   const size_t s = idx / K;
   const int k = (int)(idx % K);
-  mu[idx] = out[s * Op + k];
+  mu[idx] = y[idx] + (double)out[s * Op + k];
   lv[idx] = out[s * Op + K + k];
 }
 
@@ -610,11 +624,11 @@ hipError_t launch_mlp_forward(const afqmc_ctx_s* c, int n, int Sp, const double*
                                         : forward_t<float>(c, n, Sp, gd, y, out, zT, h1T, h2T);
 }
 
-hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, uint64_t seed,
-                              uint64_t step, int sweep, double* ytry, double* lqf) {
+hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, const double* y,
+                              uint64_t seed, uint64_t step, int sweep, double* ytry, double* lqf) {
   const int n = nw * c->P;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_propose, dim3(n), dim3(64), 0, c->stream, c->P, c->K, c->mlp.Op, out,
+  hipLaunchKernelGGL(k_mlp_propose, dim3(n), dim3(64), 0, c->stream, c->P, c->K, c->mlp.Op, out, y,
                      seed, step, sweep, ytry, lqf);
   return hipGetLastError();
 }
@@ -628,20 +642,21 @@ hipError_t launch_mlp_reverse(const afqmc_ctx_s* c, int n, const float* outR, co
 }
 
 hipError_t launch_mlp_backward(const afqmc_ctx_s* c, int n, int Sp, const float* out,
-                               const double* ytgt, const int* mask, const void* h1T,
-                               const void* h2T, void* dOT, void* dh2T, void* dh1T, double* nlq) {
+                               const double* yin, const double* ytgt, const int* mask,
+                               const void* h1T, const void* h2T, void* dOT, void* dh2T, void* dh1T,
+                               double* nlq) {
   if (Sp <= 0) return hipSuccess;
   const auto& m = c->mlp;
   const dim3 grid(blocks_of(Sp / 16, 4)), block(256);
   if (m.prec == AFQMC_PREC_BF16)
     hipLaunchKernelGGL(k_mlp_bwd<bf16_t>, grid, block, 0, c->stream, n, Sp, c->K, m.O, m.Op, out,
-                       ytgt, mask, static_cast<const bf16_t*>(m.w2c),
+                       yin, ytgt, mask, static_cast<const bf16_t*>(m.w2c),
                        static_cast<const bf16_t*>(m.w3c), static_cast<const bf16_t*>(h1T),
                        static_cast<const bf16_t*>(h2T), static_cast<bf16_t*>(dOT),
                        static_cast<bf16_t*>(dh2T), static_cast<bf16_t*>(dh1T), nlq);
   else
     hipLaunchKernelGGL(k_mlp_bwd<float>, grid, block, 0, c->stream, n, Sp, c->K, m.O, m.Op, out,
-                       ytgt, mask, static_cast<const float*>(m.w2c),
+                       yin, ytgt, mask, static_cast<const float*>(m.w2c),
                        static_cast<const float*>(m.w3c), static_cast<const float*>(h1T),
                        static_cast<const float*>(h2T), static_cast<float*>(dOT),
                        static_cast<float*>(dh2T), static_cast<float*>(dh1T), nlq);
@@ -705,11 +720,11 @@ hipError_t launch_mlp_adam(const afqmc_ctx_s* c, int Sp, const float* part, doub
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_outputs(const afqmc_ctx_s* c, int n, const float* out, double* mu,
-                              double* lv) {
+hipError_t launch_mlp_outputs(const afqmc_ctx_s* c, int n, const float* out, const double* y,
+                              double* mu, double* lv) {
   const size_t total = (size_t)n * c->K;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_outputs, dim3(blocks_of((int64_t)total, 256)), dim3(256), 0, c->stream,
-                     n, c->K, c->mlp.Op, out, mu, lv);
+                     n, c->K, c->mlp.Op, out, y, mu, lv);
   return hipGetLastError();
 }

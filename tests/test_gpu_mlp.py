@@ -62,9 +62,9 @@ SYSTEMS = {
 }
 
 
-def learned_ctx(s, P, nw, prec, params, lr=1e-3):
+def learned_ctx(s, P, nw, prec, params, lr=1e-3, rw_step=0.0):
     from paper_2505_18519_amd import afqmc as A
-    ctx = A.Context(s, P, 0.01, max_walkers=nw, proposal=A.PROPOSAL_LEARNED)
+    ctx = A.Context(s, P, 0.01, max_walkers=nw, proposal=A.PROPOSAL_LEARNED, rw_step=rw_step)
     A.afqmc_mlp_init(ctx, prec, ML.flatten(params), lr=lr)
     return ctx
 
@@ -240,23 +240,25 @@ def _margins_clear(trace, thr=1e-4):
     return ok.all(-1)
 
 
-def test_learned_metropolis_matches_oracle_fp32():
+@pytest.mark.parametrize("rw_step", [0.0, 0.3])
+def test_learned_metropolis_matches_oracle_fp32(rw_step):
     """Four steps of one sweep each, from the oracle's state on both sides:
     decisions exact (walkers with a decision within 1e-4 of the threshold
-    excepted), y' within FP32-network error, log-overlaps and weights."""
+    excepted), y' within FP32-network error, log-overlaps and weights.
+    rw_step > 0: each sweep is a random-walk move then a network move."""
     from paper_2505_18519_amd import afqmc as A
     s = ai.small_gaussian(M=20, N=5, n_chol=12, K=9, seed=31)
     nw, P = 6, 5
     phi, y, phiT, logov, ref = _paths(s, nw, P, 90)
     p = net(s, 91, last_scale=0.5)
-    ctx = learned_ctx(s, P, nw, A.PREC_FP32, p)
+    ctx = learned_ctx(s, P, nw, A.PREC_FP32, p, rw_step=rw_step)
     w = np.ones(nw)
     total = 0
     for step in range(4):
         _say("learned metropolis step", step)
         tr = []
         yo, pTo, lo, wo, nao, _ = ML.metropolis_learned(s, phi, y, phiT, logov, ref, w, 7, step, 1,
-                                                        p, trace=tr)
+                                                        p, trace=tr, rw_step=rw_step)
         yg, pTg, lg, wg, nag = _gpu_metropolis(ctx, s, phi, y, phiT, logov, ref, w, 7, step, 1)
         keep = _margins_clear(tr)
         assert keep.sum() >= nw - 1
@@ -267,12 +269,13 @@ def test_learned_metropolis_matches_oracle_fp32():
         assert np.allclose(wg[keep], wo[keep], rtol=1e-4, atol=1e-12)
         total += nao.sum()
         y, phiT, logov, w = yo, pTo, lo, wo
-    assert 0 < total < 4 * nw * P
+    assert 0 < total < 4 * nw * P * (2 if rw_step else 1)
 
 
 def test_learned_metropolis_with_training_matches_oracle_fp32():
-    """Two sweeps with one Adam step after each: decisions, paths and the
-    trained parameters against the oracle."""
+    """Two sweeps of (random-walk move, network move) with one Adam step on
+    the random-walk pairs in each: decisions, paths and the trained
+    parameters against the oracle."""
     from paper_2505_18519_amd import afqmc as A
     s = ai.small_gaussian(M=20, N=5, n_chol=12, K=9, seed=31)
     nw, P = 8, 5
@@ -280,12 +283,12 @@ def test_learned_metropolis_with_training_matches_oracle_fp32():
     p = net(s, 93, last_scale=0.5)
     pr = {k: v.copy() for k, v in p.items()}
     opt = ML.Adam(pr)
-    ctx = learned_ctx(s, P, nw, A.PREC_FP32, p)
+    ctx = learned_ctx(s, P, nw, A.PREC_FP32, p, rw_step=0.3)
     A.afqmc_mlp_set_training(ctx, True)
     w = np.ones(nw)
     tr = []
     yo, pTo, lo, wo, nao, _ = ML.metropolis_learned(s, phi, y, phiT, logov, ref, w, 9, 0, 2, pr,
-                                                    adam=opt, trace=tr)
+                                                    adam=opt, trace=tr, rw_step=0.3)
     yg, pTg, lg, wg, nag = _gpu_metropolis(ctx, s, phi, y, phiT, logov, ref, w, 9, 0, 2)
     keep = _margins_clear(tr)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -293,7 +296,7 @@ def test_learned_metropolis_with_training_matches_oracle_fp32():
     _say("training sweeps: accepted", nao.sum(), "clear walkers", keep.sum(), "min margin", mg)
     assert keep.all(), "a marginal decision would change the training set"
     assert np.array_equal(nao, nag)
-    assert 0 < nao.sum() < 2 * nw * P
+    assert 0 < nao.sum() < 4 * nw * P
     assert np.abs(yg - yo).max() < 1e-4
     assert np.abs(np.exp(lg - lo) - 1).max() < 1e-4
     d = np.abs(A.afqmc_mlp_get_params(ctx) - ML.flatten(pr))
@@ -302,12 +305,12 @@ def test_learned_metropolis_with_training_matches_oracle_fp32():
     assert np.abs(A.afqmc_mlp_get_params(ctx) - ML.flatten(p)).max() > 5e-4   # it trained
 
 
-def test_learned_metropolis_zero_output_layer_is_the_prior_step():
-    """BF16 network with W3 = b3 = 0 proposes eta exactly and its q ratio
-    cancels the prior ratio: the decisions and paths of the oracle's prior
-    step, over three sweeps."""
+def test_learned_metropolis_zero_output_layer_is_the_random_walk():
+    """BF16 network with W3 = b3 = 0 proposes y + sqrt(2) eta and its q ratio
+    is 1: the decisions and paths of the oracle's random walk of step
+    sqrt(2), over three sweeps."""
     from paper_2505_18519_amd import afqmc as A
-    s = ai.small_gaussian(M=40, N=8, n_chol=16, K=24, seed=32)
+    s = ai.small_gaussian(M=20, N=5, n_chol=12, K=4, seed=34)
     nw, P = 5, 4
     phi, y, phiT, logov, ref = _paths(s, nw, P, 95)
     p = net(s, 96, last_scale=0.0)
@@ -315,7 +318,8 @@ def test_learned_metropolis_zero_output_layer_is_the_prior_step():
     ctx = learned_ctx(s, P, nw, A.PREC_BF16, p)
     w = np.ones(nw)
     yo, pTo, lo, wo, nao = O.metropolis(s, phi, y, phiT, logov, ref, w, 3, 2, 3,
-                                        proposal=O.PROPOSAL_PRIOR)
+                                        proposal=O.PROPOSAL_RW,
+                                        rw_step=math.exp(0.5 * math.log(2.0)))
     yg, pTg, lg, wg, nag = _gpu_metropolis(ctx, s, phi, y, phiT, logov, ref, w, 3, 2, 3)
     assert np.array_equal(nag, nao)
     assert 0 < nao.sum() < 3 * nw * P
@@ -357,12 +361,13 @@ def test_learned_chain_on_gpu_samples_the_path_density():
     wd = torch.ones(nw, dtype=torch.float64, device="cuda")
     na = torch.zeros(nw, dtype=torch.int32, device="cuda")
     samples, nacc = [], 0
-    for st in range(320):
+    for st in range(500):
         A.afqmc_metropolis_x(ctx, nw, phid, yd, pd, ld, refd, wd, 11, st, 1, na)
-        if st >= 20:
+        if st >= 100:
             samples.append(host(yd).reshape(nw * P, 2))
             nacc += int(host(na).sum())
-    assert 0.1 < nacc / (300 * nw * P) < 0.95
+    _say("acceptance", nacc / (400 * nw * P))
+    assert 0.1 < nacc / (400 * nw * P) < 0.95
     samp = np.stack(samples)
     g = np.linspace(-7, 7, 141)
     Y = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)

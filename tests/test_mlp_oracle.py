@@ -87,7 +87,7 @@ def test_output_transform_bounds_and_zero_layer():
     p["W3"][:] = 0.0
     p["b3"][:] = 0.0
     mu, lv, _ = ML.forward(p, z)
-    assert np.all(mu == 0.0) and np.all(lv == 0.0)
+    assert np.all(mu == z[:, -3:]) and np.all(lv == 0.0)     # mu = y: a random walk
 
 
 def test_adam_closed_forms():
@@ -132,14 +132,16 @@ def _paths(s, nw, P, seed):
     return phi, y, phiT, logov, ref
 
 
-def test_zero_output_layer_reduces_to_the_prior_proposal():
-    """With W3 = b3 = 0 the network proposes N(0, 1), the q ratio cancels the
-    prior ratio, and the learned step makes the prior step's decisions."""
+def test_zero_output_layer_is_the_random_walk():
+    """With W3 = b3 = 0 the network proposes y + sqrt(2) eta: its q ratio is
+    1 and the learned step makes the decisions of the oracle's random walk of
+    step sqrt(2), over three sweeps."""
     s = ai.small_gaussian(M=10, N=3, n_chol=6, K=5, seed=8)
     phi, y, phiT, logov, ref = _paths(s, 3, 6, 9)
     p = ai.mlp_params(np.random.default_rng(1), s.M, s.K, H=16, last_scale=0.0)
     w = np.ones(3)
-    a = O.metropolis(s, phi, y, phiT, logov, ref, w, 11, 4, 3, proposal=O.PROPOSAL_PRIOR)
+    a = O.metropolis(s, phi, y, phiT, logov, ref, w, 11, 4, 3, proposal=O.PROPOSAL_RW,
+                     rw_step=math.exp(0.5 * math.log(2.0)))
     b = ML.metropolis_learned(s, phi, y, phiT, logov, ref, w, 11, 4, 3, p)
     assert np.array_equal(a[4], b[4])
     assert a[4].sum() > 0 and a[4].sum() < 3 * 6 * 3
@@ -154,10 +156,12 @@ def _toy():
     return ai.gaussian_system(6, 2, 3, 2, seed=4, coupling=0.15, density=0.6)
 
 
-def test_learned_chain_samples_the_path_density():
+@pytest.mark.parametrize("rw_step", [0.0, 0.5])
+def test_learned_chain_samples_the_path_density(rw_step):
     """Detailed balance of the learned proposal on a K = 2 Gaussian toy with a
-    state-dependent network: the chains' mean and second moments of y match
-    quadrature of p_T(y) |O(y; phi)| (Eq. PDF-Y)."""
+    state-dependent network (alone, or cycled with random-walk moves): the
+    chains' mean and second moments of y match quadrature of
+    p_T(y) |O(y; phi)| (Eq. PDF-Y)."""
     s = _toy()
     rng = np.random.default_rng(2)
     phi = ai.random_walkers(rng, s, 1, spread=0.8)
@@ -170,11 +174,11 @@ def test_learned_chain_samples_the_path_density():
     acc, nacc = [], 0
     for st in range(260):
         y, phiT, logov, _, na, _ = ML.metropolis_learned(s, phi, y, phiT, logov, np.ones(1, complex),
-                                                         np.ones(1), 5, st, 1, p)
+                                                         np.ones(1), 5, st, 1, p, rw_step=rw_step)
         if st >= 20:
             acc.append(y[0].copy())
             nacc += na[0]
-    assert 0.1 < nacc / (240 * P) < 0.95
+    assert 0.1 < nacc / (240 * P * (2 if rw_step else 1)) < 0.95
     samp = np.stack(acc)                         # [T, P, 2]
     g = np.linspace(-7, 7, 141)
     Y = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
@@ -236,3 +240,44 @@ def test_learned_chain_with_the_reverse_density_at_the_wrong_state_is_biased():
     err = per_chain.std(0, ddof=1) / math.sqrt(P)
     z = (per_chain.mean(0) - ref) / err
     assert np.abs(z).max() > 5.0, z
+
+
+def test_training_learns_the_denoiser_of_the_path_density():
+    """Denoising score matching on the random-walk moves at a fixed walker:
+    the trained network's mean at a noisy point y~ approaches E[y | y~] and
+    exp(lv) approaches Var[y | y~] of p_T(y) |O(y; phi)| smoothed by
+    N(0, s^2) (both by 2-D quadrature) -- Tweedie's formula, the learned
+    Langevin drift."""
+    s = _toy()
+    rng = np.random.default_rng(12)
+    phi = ai.random_walkers(rng, s, 1, spread=0.8)
+    P, sig = 64, 0.8
+    p = ai.mlp_params(np.random.default_rng(13), s.M, s.K, H=16, last_scale=0.0)
+    p["b3"][2:] = 4 * math.atanh(math.log(sig * sig) / 4)      # start as the walk of step sig
+    opt = ML.Adam(p, lr=1e-2)
+    y = rng.normal(size=(1, P, 2))
+    phiT = O.trial_det(s, y)
+    logov = O.log_overlap(phiT, phi)
+    for st in range(400):
+        if st == 250:
+            opt.lr = 2e-3
+        y, phiT, logov, _, _, loss = ML.metropolis_learned(
+            s, phi, y, phiT, logov, np.ones(1, complex), np.ones(1), 21, st, 1, p, adam=opt,
+            rw_step=sig)
+    # probe points from the smoothed density: chain states plus N(0, sig^2)
+    yt = y + sig * rng.normal(size=y.shape)
+    _, gd = ML.green_diag(O.trial_det(s, yt), phi)
+    mu, lv, _ = ML.forward(p, ML.features(gd, yt).reshape(P, -1))
+    g = np.linspace(-7, 7, 141)
+    Y = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    lo = O.log_overlap(O.trial_det(s, Y[None]), phi)[0]
+    dens = np.exp(lo.real - lo.real.max() - 0.5 * (Y * Y).sum(-1))
+    ker = np.exp(-0.5 * ((yt[0][:, None, :] - Y[None]) ** 2).sum(-1) / sig**2) * dens[None]
+    ker /= ker.sum(1, keepdims=True)
+    m_ref = ker @ Y                                              # E[y | y~]
+    v_ref = ker @ (Y * Y) - m_ref**2                             # Var[y | y~]
+    drift = np.abs(m_ref - yt[0]).mean()
+    err = np.abs(mu - m_ref).mean()
+    assert err < 0.2 * drift, (err, drift)
+    assert np.abs(np.exp(lv).mean(0) / v_ref.mean(0) - 1).max() < 0.2, (np.exp(lv).mean(0),
+                                                                      v_ref.mean(0))
