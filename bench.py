@@ -60,13 +60,126 @@ def cpu_baseline(sys_, run, seed, n_walkers=48):
                       f"(numpy FP64/complex128, 1 thread), {dt:.1f} s"}
 
 
+def reblock(x):
+    """Standard error of the mean of a correlated series (Flyvbjerg-Petersen
+    blocking): the largest error over blocking levels with >= 16 blocks."""
+    x = np.asarray(x, dtype=np.float64)
+    best = x.std(ddof=1) / np.sqrt(len(x))
+    while len(x) >= 32:
+        x = 0.5 * (x[0:len(x) // 2 * 2:2] + x[1:len(x) // 2 * 2:2])
+        best = max(best, x.std(ddof=1) / np.sqrt(len(x)))
+    return float(best)
+
+
+def learned_study(args):
+    """Learned-proposal workload (M=96, N=24, 384 vectors, K=128, 2048 walkers x
+    4 paths): the learned/mixed form (BF16 network trained during the warm-up
+    on the random-walk moves, then frozen; FP32-product contraction) against
+    the plain FP64 random-walk form, both whole AFQMC steps from the same
+    walkers and seeds.  Energy errors by reblocking over the timed steps."""
+    import torch
+    import afqmc_inputs as ai
+    from oracle import mlp_oracle as ML
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    sys_, run = ai.workload(4)
+    nw, P, seed = run.W, run.P, 2004
+    xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
+    s_train, rw_step, n_sweep_eq = 0.5, 0.3, 2
+
+    def leg(kind):
+        prec = A.PREC_FP32 if kind == "learned" else A.PREC_FP64
+        common = dict(n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap, precision=prec)
+        if kind == "learned":
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=s_train,
+                            **common)
+            p = ai.mlp_params(np.random.default_rng(8), sys_.M, sys_.K, last_scale=0.0)
+            p["b3"][sys_.K:] = 4 * np.arctanh(np.log(s_train * s_train) / 4)
+            A.afqmc_mlp_init(ctx, A.PREC_BF16, ML.flatten(p), lr=1e-3)
+            A.afqmc_mlp_set_training(ctx, True)
+        else:
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_RW, rw_step=rw_step, **common)
+        st = D.init_walkers(ctx, sys_.phi0, nw, seed)
+        est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
+        e_shift = 0.0
+        for i in range(args.warmup):
+            D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=n_sweep_eq, n_qr=run.n_qr,
+                   n_pc=n_pc, w_cap=w_cap)
+            if i == 0:
+                torch.cuda.synchronize()
+                e0 = est[0].cpu().numpy()
+                e_shift = float(e0[0] / e0[1])
+        if kind == "learned":          # freeze: network moves only from here on
+            trained = A.afqmc_mlp_get_params(ctx)
+            ctx.close()
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=0.0, **common)
+            A.afqmc_mlp_init(ctx, A.PREC_BF16, trained)
+        nacc = torch.zeros(nw, dtype=torch.int64, device="cuda")
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            i = args.warmup + k
+            D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=1, n_qr=run.n_qr,
+                   contract_events=evs[k], n_pc=n_pc, w_cap=w_cap)
+            nacc += st.nacc
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e = est.cpu().numpy()[args.warmup:]
+        en = e[:, 0] / e[:, 1]
+        ctx.close()
+        print(f"{kind}: {1e3 * dt / args.steps:.2f} ms/step, E = {en.mean():.5f} +- "
+              f"{reblock(en):.5f}", file=sys.stderr, flush=True)
+        return {"walker_steps_per_s": nw * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                "contraction_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
+                "acceptance": float(nacc.sum().item()) / (args.steps * nw * P),
+                "energy": float(en.mean()), "energy_err": reblock(en),
+                "finite": bool(np.all(np.isfinite(en)))}
+
+    L = leg("learned")
+    R = leg("rw")
+    if not (L["finite"] and R["finite"]):
+        print("non-finite energy in the learned study", L, R, file=sys.stderr)
+        sys.exit(1)
+    # throughput at equal energy error: steps needed scale with err^2 * steps
+    var_l = L["energy_err"] ** 2 * args.steps
+    var_r = R["energy_err"] ** 2 * args.steps
+    equal_error_ratio = (L["walker_steps_per_s"] / R["walker_steps_per_s"]) * (var_r / var_l)
+    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
+    achieved = flops / (L["contraction_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": L["walker_steps_per_s"],
+        "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": L["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-contraction/bf16-network/f64",
+        "data": "synthetic",
+        "config": {"workload": f"learned-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
+                               f"-W{nw}-P{P}-dtau{run.dtau}",
+                   "network_train_step": s_train, "warmup_sweeps_per_step": n_sweep_eq,
+                   "xbar_cap": xbar_cap, "comb_every": n_pc, "weight_cap": w_cap},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "kernel": "k_contract_g<float> (+ k_combine) in afqmc_local_energy",
+                     "ms_per_launch": L["contraction_ms"], "flops_per_launch": flops},
+        "learned_mixed": L,
+        "random_walk_fp64": R,
+        "equal_error_throughput_ratio": equal_error_ratio,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS) + ["learned"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU (one-GPU build); --gpus must be 1",
@@ -82,6 +195,9 @@ def main():
         print("no GPU: the HIP path cannot run", file=sys.stderr)
         sys.exit(1)
     A.load_library()
+    if args.workload == "learned":
+        learned_study(args)
+        return
 
     widx, precision, peak, dtype = WORKLOADS[args.workload]
     sys_, run = ai.workload(widx)

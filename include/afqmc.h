@@ -203,11 +203,13 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx ctx, int32_t nw, void* phi, void* l
  * step, tag COMB), new walker j is a copy of old walker
  *   parent[j] = min{k : C_k > (j + u) sum(W) / nw}
  * (phi, y, phiT and logov are gathered in place) and every weight becomes
- * sum(W) / nw.  parent [nw] int32 receives the parents if non-NULL.  A
- * population whose weights sum to zero is left unchanged. */
+ * sum(W) / nw, or 1 with normalize = 1 (a common factor of all weights, which
+ * cancels in Eq. mixed_estimator and keeps long runs inside the FP64 range).
+ * parent [nw] int32 receives the parents if non-NULL.  A population whose
+ * weights sum to zero is left unchanged. */
 afqmc_status afqmc_population_control(afqmc_ctx ctx, int32_t nw, void* phi, double* w, double* y,
                                       double* phiT, void* logov, uint64_t seed, uint64_t step,
-                                      double w_cap, int32_t* parent);
+                                      double w_cap, int32_t normalize, int32_t* parent);
 
 /* Mixed-estimator sums (Eq. mixed_estimator): out[0] = sum_k W_k Re E_L,k,
  * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2]. */

@@ -336,15 +336,16 @@ def reorthogonalize(phi: np.ndarray, logov: Optional[np.ndarray] = None):
     return out, logov - shift[:, None]
 
 
-def comb(w: np.ndarray, seed: int, step: int, w_cap: float = 0.0):
+def comb(w: np.ndarray, seed: int, step: int, w_cap: float = 0.0, normalize: bool = False):
     """Comb population control (a standard branching step; the paper is silent).
 
     With w_cap > 0 every weight is first clipped to w_cap times the mean
     weight.  Then, with u the COMB-stream uniform of this step and C the
     inclusive prefix sums of W, new walker j copies old walker
     parent[j] = min{k : C_k > (j + u) sum(W) / nw} and every new weight is
-    sum(W) / nw.  Returns (parent, new weights); an all-zero population is
-    returned unchanged.
+    sum(W) / nw, or 1 with normalize (a common factor, which cancels in the
+    mixed estimator).  Returns (parent, new weights); an all-zero population
+    is returned unchanged.
     """
     w = np.asarray(w, dtype=np.float64).copy()
     nw = len(w)
@@ -357,7 +358,7 @@ def comb(w: np.ndarray, seed: int, step: int, w_cap: float = 0.0):
     C = np.cumsum(w)
     t = (np.arange(nw) + u) * (tot / nw)
     parent = np.minimum(np.searchsorted(C, t, side="right"), nw - 1)
-    return parent, np.full(nw, tot / nw)
+    return parent, np.full(nw, 1.0 if normalize else tot / nw)
 
 
 def estimator(w: np.ndarray, eloc: np.ndarray):
@@ -388,9 +389,11 @@ def init_state(sys, nw, P, seed):
 
 def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
          e_shift=0.0, proposal=PROPOSAL_PRIOR, rw_step=0.5,
-         weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None, xbar_cap=0.0, n_pc=0, w_cap=0.0):
+         weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None, xbar_cap=0.0, n_pc=0, w_cap=0.0,
+         normalize=True):
     """Measure, propagate, move the paths, re-orthogonalise, and (every n_pc
-    steps, if n_pc > 0) comb the population.  Returns (state, record)."""
+    steps, if n_pc > 0) comb the population (weights reset to 1 with
+    normalize).  Returns (state, record)."""
     ell, theta = green(st.phiT, st.phi)
     vb, ep = sample_contraction(sys, st.phiT, theta, ell, h1p)
     xbar, eloc = walker_estimates(vb, ep, ell, dtau, xbar_cap)
@@ -403,7 +406,7 @@ def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
     if n_qr and (i + 1) % n_qr == 0:
         phin, logov = reorthogonalize(phin, logov)
     if n_pc and (i + 1) % n_pc == 0:
-        parent, w2 = comb(w2, seed, i, w_cap)
+        parent, w2 = comb(w2, seed, i, w_cap, normalize)
         phin, y, phiT, logov = phin[parent], y[parent], phiT[parent], logov[parent]
     rec = dict(e_num=num, e_den=den, eloc=eloc, xbar=xbar, logov=ell, xi=xi,
                w_prop=wn, ref=ref, nacc=nacc)

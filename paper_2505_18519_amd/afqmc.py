@@ -61,7 +61,8 @@ EXPORTS = {
     "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_estimator": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "afqmc_population_control": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
-                                         c_void_p, c_uint64, c_uint64, c_double, c_void_p]),
+                                         c_void_p, c_uint64, c_uint64, c_double, c_int32,
+                                         c_void_p]),
     "afqmc_philox_normal": (c_int, [c_void_p, c_uint64, c_uint64, c_uint32, c_int32, c_int32,
                                     c_void_p]),
     "afqmc_green_diag": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -275,7 +276,8 @@ def afqmc_reorthogonalize(ctx, nw, phi, logov=None):
             _ptr(logov, torch.complex128, nw * c.P, "logov", allow_none=True))
 
 
-def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=0.0, parent=None):
+def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=0.0, parent=None,
+                             normalize=False):
     c = ctx
     c.reserve(nw)
     c._call("afqmc_population_control", nw,
@@ -283,7 +285,7 @@ def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
             _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"), int(seed), int(step), float(w_cap),
-            _ptr(parent, torch.int32, nw, "parent", allow_none=True))
+            1 if normalize else 0, _ptr(parent, torch.int32, nw, "parent", allow_none=True))
 
 
 def afqmc_estimator(ctx, nw, w, eloc, out):

@@ -552,7 +552,7 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx c, int32_t nw, void* phi, void* log
 
 afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double* w, double* y,
                                       double* phiT, void* logov, uint64_t seed, uint64_t step,
-                                      double w_cap, int32_t* parent) {
+                                      double w_cap, int32_t normalize, int32_t* parent) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);
   if (nw == 0) return AFQMC_OK;
@@ -562,13 +562,14 @@ afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
   if (!(w_cap >= 0.0)) return fail(c, AFQMC_E_INVALID, "w_cap must be >= 0");
+  if (normalize != 0 && normalize != 1) return fail(c, AFQMC_E_INVALID, "normalize must be 0 or 1");
   ws_layout L;
   afqmc_status st = need_ws(c, nw, &L);
   if (st != AFQMC_OK) return st;
   int* par = parent ? parent : ws_ptr<int>(c, L.pc_parent);
   HIPCALL(c,
-          launch_comb(c, nw, w_cap, w, ws_ptr<double>(c, L.pc_C), ws_ptr<double>(c, L.pc_tot), par,
-                      seed, step),
+          launch_comb(c, nw, w_cap, normalize, w, ws_ptr<double>(c, L.pc_C),
+                      ws_ptr<double>(c, L.pc_tot), par, seed, step),
           "comb");
   const size_t S = (size_t)c->P;
   struct {

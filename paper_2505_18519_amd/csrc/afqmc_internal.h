@@ -113,8 +113,8 @@ hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, c
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
 hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift);
 hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
-hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, double* C,
-                       double* tot, int* parent, uint64_t seed, uint64_t step);
+hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,
+                       double* C, double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
                          const double* src, double* dst);
 

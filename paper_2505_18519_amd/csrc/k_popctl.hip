@@ -49,8 +49,9 @@ k_comb_scan(int nw, double w_cap, const double* __restrict__ w, double* __restri
   if (tid == PC_THREADS - 1) tot[0] = s_part[PC_THREADS - 1];
 }
 
-// parent[j] = min{k : C_k > (j + u) tot / nw}; new weight tot / nw
-__global__ void k_comb_parent(int nw, uint64_t seed, uint64_t step, const double* __restrict__ C,
+// parent[j] = min{k : C_k > (j + u) tot / nw}; new weight tot / nw (1 if normalize)
+__global__ void k_comb_parent(int nw, int normalize, uint64_t seed, uint64_t step,
+                              const double* __restrict__ C,
                               const double* __restrict__ tot, int* __restrict__ parent,
                               double* __restrict__ w) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,7 +72,7 @@ __global__ void k_comb_parent(int nw, uint64_t seed, uint64_t step, const double
       lo = mid + 1;
   }
   parent[j] = lo;
-  w[j] = T / (double)nw;
+  w[j] = normalize ? 1.0 : T / (double)nw;
 }
 
 // dst[j] = src[parent[j]] for rows of `row` doubles; block b copies chunk
@@ -88,11 +89,11 @@ __global__ void k_gather_rows(int nw, size_t row, int nchunk, const int* __restr
 
 }  // namespace
 
-hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, double* w, double* C,
-                       double* tot, int* parent, uint64_t seed, uint64_t step) {
+hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,
+                       double* C, double* tot, int* parent, uint64_t seed, uint64_t step) {
   hipLaunchKernelGGL(k_comb_scan, dim3(1), dim3(PC_THREADS), 0, c->stream, nw, w_cap, w, C, tot);
   AFQMC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_comb_parent, dim3((nw + 255) / 256), dim3(256), 0, c->stream, nw, seed, step,
+  hipLaunchKernelGGL(k_comb_parent, dim3((nw + 255) / 256), dim3(256), 0, c->stream, nw, normalize, seed, step,
                      C, tot, parent, w);
   return hipGetLastError();
 }

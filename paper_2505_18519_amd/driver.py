@@ -47,9 +47,10 @@ def init_walkers(ctx: A.Context, phi0, nw: int, seed: int) -> Walkers:
 
 def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
          e_shift: float = 0.0, n_sweep: int = 1, n_qr: int = 10, contract_events=None,
-         n_pc: int = 0, w_cap: float = 0.0) -> None:
+         n_pc: int = 0, w_cap: float = 0.0, normalize: bool = True) -> None:
     """Measure, propagate, move the paths, hand off, re-orthonormalise, and
-    every n_pc steps (if n_pc > 0) comb the population.
+    every n_pc steps (if n_pc > 0) comb the population (weights reset to 1
+    with normalize, to their mean otherwise).
 
     est_out: device float64 [2] receiving (sum W Re E_L, sum W) at the
     pre-move state (Eq. mixed_estimator).  contract_events, if given, is a
@@ -73,4 +74,5 @@ def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
     if n_qr and (i + 1) % n_qr == 0:
         A.afqmc_reorthogonalize(ctx, nw, st.phi, st.logov)
     if n_pc and (i + 1) % n_pc == 0:
-        A.afqmc_population_control(ctx, nw, st.phi, st.w, st.y, st.phiT, st.logov, seed, i, w_cap)
+        A.afqmc_population_control(ctx, nw, st.phi, st.w, st.y, st.phiT, st.logov, seed, i, w_cap,
+                                   normalize=normalize)

@@ -339,11 +339,12 @@ def test_population_control_matches_oracle_comb():
     w = rng.exponential(size=nw)
     w[[3, 10]] = 0.0
     w[5] = 40.0
-    for w_cap in (0.0, 4.0):
-        parent, wn = O.comb(w, 55, 3, w_cap)
+    for w_cap, norm in ((0.0, False), (4.0, False), (4.0, True)):
+        parent, wn = O.comb(w, 55, 3, w_cap, norm)
         dphi, dw, dy, dphiT, dl = dev(phi), dev(w), dev(y), dev(phiT), dev(ell)
         dpar = torch.zeros(nw, dtype=torch.int32, device="cuda")
-        A.afqmc_population_control(ctx, nw, dphi, dw, dy, dphiT, dl, 55, 3, w_cap, dpar)
+        A.afqmc_population_control(ctx, nw, dphi, dw, dy, dphiT, dl, 55, 3, w_cap, dpar,
+                                   normalize=norm)
         torch.cuda.synchronize()
         assert np.array_equal(host(dpar), parent)
         assert np.abs(host(dw) - wn).max() <= 1e-14 * wn.max()

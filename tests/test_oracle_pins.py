@@ -482,3 +482,7 @@ def test_comb_population_control_properties():
         assert np.all(np.diff(parent) >= 0)
     p0, w0 = O.comb(np.zeros(5), 1, 1)
     assert np.array_equal(p0, np.arange(5))
+    # normalize: the same parents, every weight 1
+    pa, wa = O.comb(w, 9, 4, 3.0)
+    pb, wb = O.comb(w, 9, 4, 3.0, normalize=True)
+    assert np.array_equal(pa, pb) and np.all(wb == 1.0)
