@@ -36,6 +36,25 @@ WORKLOADS = {
 }
 
 
+# HBM bytes per contraction launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
+# the plain-copy calibration (profiles/traffic_k_contract_*.md), valid while the
+# kernel source is the one measured: workload -> (source file, sha256 prefix, bytes)
+TRAFFIC = {
+    "fp64": ("k_contract.hip", "80d1dfe0ae71f6d8", 454600364),
+}
+
+
+def measured_traffic(workload):
+    import hashlib
+    if workload not in TRAFFIC:
+        return None
+    src, sha, nbytes = TRAFFIC[workload]
+    path = os.path.join(ROOT, "paper_2505_18519_amd", "csrc", src)
+    with open(path, "rb") as f:
+        ok = hashlib.sha256(f.read()).hexdigest().startswith(sha)
+    return nbytes if ok else None
+
+
 def contraction_flops(M, N, G):
     """Algorithmic flops of the contraction per (walker, path): the real
     half-rotation Phi_T^T L_g (2 N M^2), its product with both spins' Theta
@@ -180,6 +199,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS) + ["learned"])
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (the plain copy kernel that "
+                         "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU (one-GPU build); --gpus must be 1",
@@ -195,6 +217,15 @@ def main():
         print("no GPU: the HIP path cannot run", file=sys.stderr)
         sys.exit(1)
     A.load_library()
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 5}))
+        return
     if args.workload == "learned":
         learned_study(args)
         return
@@ -262,7 +293,8 @@ def main():
                    "n_chol": sys_.n_chol, "K": sys_.K, "xbar_cap": xbar_cap,
                    "comb_every": n_pc, "weight_cap": w_cap},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload),
                      "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
                                 else "k_contract_g") + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},
