@@ -192,13 +192,96 @@ def learned_study(args):
     print(json.dumps(out))
 
 
+def uneven_study(args):
+    """Uneven batch (32 systems, M in [24, 128], N = M/4, 4M vectors, K = M/2,
+    walkers log-uniform in [64, 1024], 4 paths): aggregate walker-steps/s of the
+    autotuned batch (replays of one captured graph with parallel branches)
+    against the same systems stepped one after another through the per-system
+    calls on one stream."""
+    import torch
+    import afqmc_inputs as ai
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    systems, runs = ai.workload(3)
+    specs = [(s, r.P, r.dtau, dict(xbar_cap=1.0)) for s, r in zip(systems, runs)]
+    walkers = [r.W for r in runs]
+    total_w = sum(walkers)
+    flops = sum(contraction_flops(s.M, s.N, s.n_chol) * r.W * r.P for s, r in zip(systems, runs))
+    seed = 2003
+    t_build = time.perf_counter()
+    b = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=4.0,
+                max_branches=4, autotune=True, history=64)
+    print(f"uneven batch built and tuned in {time.perf_counter() - t_build:.1f} s, cycle "
+          f"{b.cycle} steps", file=sys.stderr, flush=True)
+    n_cycles = max(1, args.steps // b.cycle)
+    b.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(n_cycles)
+    sums, steps = b.estimates()
+    dt = time.perf_counter() - t0
+    n_steps = n_cycles * b.cycle
+    fam, br, ms, nb = b.plan()
+    last = [(int(steps[i]) - 1) % b.history for i in range(b.n)]
+    energies = [float(sums[i, last[i], 0] / sums[i, last[i], 1]) for i in range(b.n)]
+    b.close()
+    print(f"batch: {1e3 * dt / n_steps:.1f} ms/step", file=sys.stderr, flush=True)
+
+    # the same systems one after another on one stream, through the per-system calls
+    seq_steps = 2
+    ctxs, states = [], []
+    for i, (s, P, dtau, kw) in enumerate(specs):
+        ctx = A.Context(s, P, dtau, max_walkers=walkers[i], **kw)
+        ctxs.append(ctx)
+        states.append(D.init_walkers(ctx, s.phi0, walkers[i], seed + i))
+    est = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for i in range(len(specs)):      # warm
+        D.step(ctxs[i], states[i], seed + i, 0, est, n_pc=1, w_cap=4.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(1, 1 + seq_steps):
+        for i in range(len(specs)):
+            D.step(ctxs[i], states[i], seed + i, k, est, n_pc=1, w_cap=4.0)
+    torch.cuda.synchronize()
+    dt_seq = (time.perf_counter() - t1) / seq_steps
+    for c in ctxs:
+        c.close()
+    print(f"sequential: {1e3 * dt_seq:.1f} ms/step", file=sys.stderr, flush=True)
+
+    step_s = dt / n_steps
+    achieved = flops / step_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": total_w / step_s,
+        "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": b.cycle,
+        "ms_per_step": 1e3 * step_s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "uneven-32-systems-M24-128", "systems": len(specs),
+                   "walkers": total_w, "paths": 4, "cycle_steps": b.cycle,
+                   "branches": nb, "families": [int(f) for f in fam]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "kernel": "all systems' contractions per whole step (a lower bound on the "
+                               "contraction kernels' rate: the step's other kernels are included)",
+                     "flops_per_step": flops},
+        "sequential_ms_per_step": 1e3 * dt_seq,
+        "speedup_vs_sequential": dt_seq / step_s,
+        "energies_last_step": energies,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS) + ["learned"])
+    ap.add_argument("--workload", default="fp64",
+                    choices=sorted(WORKLOADS) + ["learned", "uneven"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (the plain copy kernel that "
                          "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -228,6 +311,9 @@ def main():
         return
     if args.workload == "learned":
         learned_study(args)
+        return
+    if args.workload == "uneven":
+        uneven_study(args)
         return
 
     widx, precision, peak, dtype = WORKLOADS[args.workload]

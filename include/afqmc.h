@@ -289,6 +289,61 @@ afqmc_status afqmc_mlp_train_step(afqmc_ctx ctx, int32_t n, const double* gdiag,
 afqmc_status afqmc_green_diag(afqmc_ctx ctx, int32_t nw, const void* phi, const double* phiT,
                               void* logov, double* gdiag);
 
+/* ---- Uneven batching (an extension: many independent systems per launch) --
+ *
+ * A batch advances n_systems independent systems (each an afqmc_system with
+ * its own sizes, within afqmc_create's limits, prior or random-walk
+ * proposals) together.  Each system's walkers start at phi = Phi_0, W = 1,
+ * y ~ p_T (stream INIT, key seed + i), and every step is the App. B step of
+ * the per-system calls: green -> local energy (with x-bar) -> estimator ->
+ * fields (stream FIELD) -> propagate (E_T = 0) -> Metropolis -> QR every
+ * n_qr steps -> comb every n_pc steps with weights reset to 1.  A cycle of
+ * afqmc_batch_cycle() steps of all systems is captured once as one hipGraph
+ * in which each system's kernels run on one of up to max_branches parallel
+ * branches (systems assigned by longest processing time); each system's step
+ * index lives in device memory, so replays advance the random streams.  With
+ * autotune = 1 the batch times, per system, the kernel families that apply
+ * (register-resident for M <= 64 and N <= 16, workgroup-per-path for any
+ * size) and, for the whole cycle, 1, 2 and 4 branches, and keeps the fastest;
+ * those timing steps advance the systems (they are part of the warm-up).
+ * The batch owns all state (one device arena) and its workspaces. */
+typedef struct afqmc_batch_s* afqmc_batch;
+
+typedef struct {
+  uint64_t seed;         /* Philox key of system i: seed + i                         */
+  int32_t n_sweep;       /* Metropolis sweeps per step                               */
+  int32_t n_qr;          /* re-orthonormalise every n_qr steps (0: never)            */
+  int32_t n_pc;          /* comb every n_pc >= 1 steps                                */
+  double w_cap;          /* comb weight cap relative to the mean (0: none)            */
+  int32_t max_branches;  /* 1..4 parallel branches in the step graph                  */
+  int32_t autotune;      /* 0 / 1                                                     */
+  int32_t history;       /* estimator sums kept per system: a ring of `history` steps */
+} afqmc_batch_options;
+
+/* systems, walkers: HOST arrays [n_systems].  Creates contexts, state and the
+ * step graph on `device`; orders itself after `stream` and synchronises it.
+ * Errors: AFQMC_E_INVALID (bad options), the afqmc_create codes of a system. */
+afqmc_status afqmc_batch_create(const afqmc_system* systems, const int32_t* walkers,
+                                int32_t n_systems, const afqmc_batch_options* opt, int device,
+                                void* stream, afqmc_batch* out);
+/* Steps per replay of the step graph (a multiple of n_qr and n_pc, even). */
+int32_t afqmc_batch_cycle(afqmc_batch b);
+/* Launches the step graph n_cycles times after the work already on the
+ * creation stream; that stream waits for the cycles.  Asynchronous. */
+afqmc_status afqmc_batch_run(afqmc_batch b, int32_t n_cycles);
+/* Synchronises and copies, for every system i, the estimator sums of
+ * Eq. mixed_estimator (sum W Re E_L, sum W) of step t to
+ * out[(i * history + t % history) * 2 + {0, 1}] (HOST double), and the steps
+ * done to steps[i] (HOST uint64). */
+afqmc_status afqmc_batch_estimates(afqmc_batch b, double* out, uint64_t* steps);
+/* The tuner's choices (HOST arrays [n_systems], each may be NULL): kernel
+ * family (0 register-resident, 1 workgroup-per-path), branch, the measured
+ * time of one step of the system alone (ms), and the number of branches. */
+afqmc_status afqmc_batch_plan(afqmc_batch b, int32_t* family, int32_t* branch, double* step_ms,
+                              int32_t* n_branches);
+const char* afqmc_batch_last_error(afqmc_batch b);
+afqmc_status afqmc_batch_destroy(afqmc_batch b);
+
 /* Counter tags of the streams above. */
 enum { AFQMC_TAG_FIELD = 1, AFQMC_TAG_PROPOSAL = 2, AFQMC_TAG_ACCEPT = 3, AFQMC_TAG_COMB = 4,
        AFQMC_TAG_INIT = 5 };

@@ -28,6 +28,12 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
           5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
 
 
+class afqmc_batch_options(ctypes.Structure):
+    _fields_ = [("seed", c_uint64), ("n_sweep", c_int32), ("n_qr", c_int32), ("n_pc", c_int32),
+                ("w_cap", c_double), ("max_branches", c_int32), ("autotune", c_int32),
+                ("history", c_int32)]
+
+
 class afqmc_system(ctypes.Structure):
     _fields_ = [
         ("M", c_int32), ("N", c_int32), ("n_chol", c_int32), ("K", c_int32), ("P", c_int32),
@@ -74,6 +80,16 @@ EXPORTS = {
     "afqmc_mlp_forward": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "afqmc_mlp_train_step": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]),
+    "afqmc_batch_create": (c_int, [c_void_p, POINTER(c_int32), c_int32,
+                                   POINTER(afqmc_batch_options), c_int, c_void_p,
+                                   POINTER(c_void_p)]),
+    "afqmc_batch_cycle": (c_int32, [c_void_p]),
+    "afqmc_batch_run": (c_int, [c_void_p, c_int32]),
+    "afqmc_batch_estimates": (c_int, [c_void_p, POINTER(c_double), POINTER(c_uint64)]),
+    "afqmc_batch_plan": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
+                                 POINTER(c_int32)]),
+    "afqmc_batch_last_error": (c_char_p, [c_void_p]),
+    "afqmc_batch_destroy": (c_int, [c_void_p]),
 }
 
 _lib = None
@@ -130,6 +146,22 @@ def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def system_struct(system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
+                  proposal=PROPOSAL_PRIOR, rw_step=None, xbar_cap=0.0, precision=PREC_FP64):
+    """(afqmc_system, host arrays it points into) for a system description."""
+    import numpy as np
+    if rw_step is None:
+        rw_step = 0.5 if proposal == PROPOSAL_RW else 0.0
+    host = [np.ascontiguousarray(a, dtype=np.float64)
+            for a in (system.h1, system.L, system.phi0, system.A)]
+    dp = lambda a: a.ctypes.data_as(POINTER(c_double))
+    st = afqmc_system(int(system.M), int(system.N), int(system.n_chol), int(system.K), int(P),
+                      int(system.hidden_kind), float(system.coupling), dp(host[0]), dp(host[1]),
+                      dp(host[2]), dp(host[3]), float(dtau), int(n_taylor), int(weight_mode),
+                      int(proposal), float(rw_step), int(precision), float(xbar_cap))
+    return st, host
+
+
 class Context:
     """Owns an afqmc_ctx and its workspace (a torch uint8 tensor)."""
 
@@ -139,22 +171,13 @@ class Context:
         """rw_step: the random-walk step (default 0.5 for PROPOSAL_RW); with
         PROPOSAL_LEARNED a value > 0 cycles random-walk and network moves
         (default 0: network moves only)."""
-        import numpy as np
-        if rw_step is None:
-            rw_step = 0.5 if proposal == PROPOSAL_RW else 0.0
         lib = load_library()
         if not torch.cuda.is_available():
             raise AfqmcError("no GPU available for libafqmc")
         self.M, self.N, self.G, self.K, self.P = (int(system.M), int(system.N),
                                                   int(system.n_chol), int(system.K), int(P))
-        self._host = [np.ascontiguousarray(a, dtype=np.float64)
-                      for a in (system.h1, system.L, system.phi0, system.A)]
-        dp = lambda a: a.ctypes.data_as(POINTER(c_double))
-        self.sys = afqmc_system(self.M, self.N, self.G, self.K, self.P, int(system.hidden_kind),
-                                float(system.coupling), dp(self._host[0]), dp(self._host[1]),
-                                dp(self._host[2]), dp(self._host[3]), float(dtau), int(n_taylor),
-                                int(weight_mode), int(proposal), float(rw_step), int(precision),
-                                float(xbar_cap))
+        self.sys, self._host = system_struct(system, P, dtau, n_taylor, weight_mode, proposal,
+                                             rw_step, xbar_cap, precision)
         self.dtau = float(dtau)
         self.device = torch.device("cuda", device)
         self.handle = c_void_p()
@@ -350,3 +373,76 @@ def afqmc_mlp_train_step(ctx, n, gdiag, y, ytarget, mask, loss=None, grad=None):
             _ptr(mask, torch.int32, n, "mask"),
             _ptr(loss, torch.float64, 1, "loss", allow_none=True),
             _ptr(grad, torch.float64, afqmc_mlp_num_params(c), "grad", allow_none=True))
+
+
+# --- uneven batching ---------------------------------------------------------------
+
+class Batch:
+    """Owns an afqmc_batch: systems [(system, P, dtau, kwargs)], walkers per system."""
+
+    def __init__(self, systems, walkers, seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=0.0,
+                 max_branches=4, autotune=True, history=256, device=0):
+        import numpy as np
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise AfqmcError("no GPU available for libafqmc")
+        self.n = len(systems)
+        structs, self._host = [], []
+        for (system, P, dtau, kw) in systems:
+            st, host = system_struct(system, P, dtau, **kw)
+            structs.append(st)
+            self._host.append(host)
+        self._arr = (afqmc_system * self.n)(*structs)
+        self._walkers = (c_int32 * self.n)(*[int(w) for w in walkers])
+        self.history = int(history)
+        self.opt = afqmc_batch_options(int(seed), int(n_sweep), int(n_qr), int(n_pc), float(w_cap),
+                                       int(max_branches), 1 if autotune else 0, self.history)
+        self.handle = c_void_p()
+        with torch.cuda.device(device):
+            rc = lib.afqmc_batch_create(ctypes.cast(self._arr, c_void_p), self._walkers, self.n,
+                                        ctypes.byref(self.opt), device, _stream(),
+                                        ctypes.byref(self.handle))
+        if rc != 0:
+            self.handle = c_void_p()
+            raise AfqmcError(f"afqmc_batch_create: {STATUS.get(rc, rc)}")
+        self.cycle = int(lib.afqmc_batch_cycle(self.handle))
+
+    def _check(self, rc, what):
+        if rc != 0:
+            m = load_library().afqmc_batch_last_error(self.handle)
+            raise AfqmcError(f"{what}: {STATUS.get(rc, rc)} {m.decode() if m else ''}")
+
+    def run(self, n_cycles):
+        self._check(load_library().afqmc_batch_run(self.handle, int(n_cycles)), "afqmc_batch_run")
+
+    def estimates(self):
+        """(sums [n][history][2], steps [n]) for the ring of the last `history` steps."""
+        import numpy as np
+        out = np.zeros((self.n, self.history, 2))
+        steps = np.zeros(self.n, dtype=np.uint64)
+        self._check(load_library().afqmc_batch_estimates(
+            self.handle, out.ctypes.data_as(POINTER(c_double)),
+            steps.ctypes.data_as(POINTER(c_uint64))), "afqmc_batch_estimates")
+        return out, steps
+
+    def plan(self):
+        import numpy as np
+        fam = np.zeros(self.n, dtype=np.int32)
+        br = np.zeros(self.n, dtype=np.int32)
+        ms = np.zeros(self.n)
+        nb = c_int32()
+        self._check(load_library().afqmc_batch_plan(
+            self.handle, fam.ctypes.data_as(POINTER(c_int32)), br.ctypes.data_as(POINTER(c_int32)),
+            ms.ctypes.data_as(POINTER(c_double)), ctypes.byref(nb)), "afqmc_batch_plan")
+        return fam, br, ms, int(nb.value)
+
+    def close(self):
+        if self.handle:
+            load_library().afqmc_batch_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

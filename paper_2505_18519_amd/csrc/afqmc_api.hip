@@ -582,10 +582,7 @@ afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double
   for (auto& pt : parts) {
     double* tmp = ws_ptr<double>(c, pt.off);
     HIPCALL(c, launch_gather(c, nw, pt.row, par, pt.state, tmp), "gather");
-    HIPCALL(c,
-            hipMemcpyAsync(pt.state, tmp, (size_t)nw * pt.row * sizeof(double),
-                           hipMemcpyDeviceToDevice, c->stream),
-            "gather copy");
+    HIPCALL(c, launch_copy(c, (size_t)nw * pt.row, tmp, pt.state), "gather copy");
   }
   return AFQMC_OK;
 }

@@ -27,6 +27,12 @@ struct afqmc_ctx_s {
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
 
+  // Device-resident step counter (set by a batch whose step sequence is a
+  // replayed graph): the kernels that take a step index read *dstep instead,
+  // and the estimator writes its sums to out + 2 * (*dstep % est_cap).
+  const uint64_t* dstep = nullptr;
+  int est_cap = 1;
+
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
@@ -117,6 +123,7 @@ hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize
                        double* C, double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
                          const double* src, double* dst);
+hipError_t launch_copy(const afqmc_ctx_s* c, size_t n, const double* src, double* dst);
 
 // learned proposal network (k_mlp.hip); n = feature rows, Sp = n rounded up to 16
 hipError_t launch_mlp_setparams(const afqmc_ctx_s* c, const double* src);

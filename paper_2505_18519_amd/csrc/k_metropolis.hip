@@ -18,10 +18,12 @@ namespace {
 // y' for every (walker, path): prior draw, random walk, or flip of y_k
 __global__ void k_proposal(int nw, int P, int K, int hidden_kind, int proposal, double rw_step,
                            const double* __restrict__ y, double* __restrict__ ytry, uint64_t seed,
-                           uint64_t step, int sweep, int flip_k) {
+                           uint64_t step, const uint64_t* __restrict__ dstep, int sweep,
+                           int flip_k) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)nw * P * K;
   if (idx >= total) return;
+  if (dstep != nullptr) step = *dstep;
   const int k = (int)(idx % K);
   const size_t wp = idx / K;
   const int p = (int)(wp % P);
@@ -42,10 +44,11 @@ __global__ void __launch_bounds__(64)
 k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __restrict__ y,
          double* __restrict__ phiT, double* __restrict__ logov, const double* __restrict__ ytry,
          const double* __restrict__ phiTtry, const double* __restrict__ ltry,
-         int* __restrict__ nacc, uint64_t seed, uint64_t step, int sweep, int flip_k,
-         const double* __restrict__ lextra, int M, double* __restrict__ gd_cur,
-         const double* __restrict__ gd_try, int* __restrict__ mask) {
+         int* __restrict__ nacc, uint64_t seed, uint64_t step, const uint64_t* __restrict__ dstep,
+         int sweep, int flip_k, const double* __restrict__ lextra, int M,
+         double* __restrict__ gd_cur, const double* __restrict__ gd_try, int* __restrict__ mask) {
   __shared__ int s_acc[64];
+  if (dstep != nullptr) step = *dstep;
   const int w = blockIdx.x;
   const int lane = threadIdx.x;
   int count = 0;
@@ -137,7 +140,7 @@ hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double
   const int bs = 256;
   hipLaunchKernelGGL(k_proposal, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, c->stream,
                      nw, c->P, c->K, c->hidden_kind, proposal, c->rw_step, y, ytry, seed, step,
-                     sweep, flip_k);
+                     c->dstep, sweep, flip_k);
   return hipGetLastError();
 }
 
@@ -148,7 +151,7 @@ hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, 
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->M * c->N,
                      c->hidden_kind, proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
-                     step, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
+                     step, c->dstep, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
   return hipGetLastError();
 }
 

@@ -81,11 +81,12 @@ k_expm_half(int M, double dtau, const double* __restrict__ h1, double* __restric
   }
 }
 
-__global__ void k_philox_normal(uint64_t seed, uint64_t step, uint64_t w3, int nw, int n,
-                                double* __restrict__ out) {
+__global__ void k_philox_normal(uint64_t seed, uint64_t step, const uint64_t* __restrict__ dstep,
+                                uint64_t w3, int nw, int n, double* __restrict__ out) {
   const int nb = (n + 3) / 4;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nw * nb) return;
+  if (dstep != nullptr) step = *dstep;
   const int w = (int)(idx / nb), b = (int)(idx % nb);
   ph4 blk = philox4x64_10((uint64_t)b, (uint64_t)w, step, w3, seed, 0);
   double z[4];
@@ -119,7 +120,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 // out[0] = sum W Re E_L, out[1] = sum W, compensated (sum + error term)
 __global__ void __launch_bounds__(256)
 k_estimator(int nw, const double* __restrict__ w, const double* __restrict__ eloc,
-            double* __restrict__ out) {
+            double* __restrict__ out, const uint64_t* __restrict__ dstep, int cap) {
   __shared__ double s_v[4][256];
   const int tid = threadIdx.x;
   double n_s = 0.0, n_e = 0.0, d_s = 0.0, d_e = 0.0;
@@ -150,8 +151,9 @@ k_estimator(int nw, const double* __restrict__ w, const double* __restrict__ elo
     __syncthreads();
   }
   if (tid == 0) {
-    out[0] = s_v[0][0] + s_v[1][0];
-    out[1] = s_v[2][0] + s_v[3][0];
+    double* o = (dstep != nullptr) ? out + 2 * (size_t)(*dstep % (uint64_t)cap) : out;
+    o[0] = s_v[0][0] + s_v[1][0];
+    o[1] = s_v[2][0] + s_v[3][0];
   }
 }
 
@@ -236,7 +238,7 @@ hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t st
   const size_t total = (size_t)nw * ((n + 3) / 4);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_philox_normal, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     c->stream, seed, step, ((uint64_t)tag << 48), nw, n, out);
+                     c->stream, seed, step, c->dstep, ((uint64_t)tag << 48), nw, n, out);
   return hipGetLastError();
 }
 
@@ -250,7 +252,8 @@ hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, doub
 
 hipError_t launch_estimator(const afqmc_ctx_s* c, int nw, const double* w, const double* eloc,
                             double* out) {
-  hipLaunchKernelGGL(k_estimator, dim3(1), dim3(256), 0, c->stream, nw, w, eloc, out);
+  hipLaunchKernelGGL(k_estimator, dim3(1), dim3(256), 0, c->stream, nw, w, eloc, out, c->dstep,
+                     c->est_cap);
   return hipGetLastError();
 }
 

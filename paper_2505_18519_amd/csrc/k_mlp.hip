@@ -218,9 +218,10 @@ k_mlp_fwd(int n, int Sp, int M, int K, int D, int Dp, int O, int Op,
 
 __global__ void __launch_bounds__(64)
 k_mlp_propose(int P, int K, int Op, const float* __restrict__ out, const double* __restrict__ y,
-              uint64_t seed, uint64_t step, int sweep, double* __restrict__ ytry,
-              double* __restrict__ lqf) {
+              uint64_t seed, uint64_t step, const uint64_t* __restrict__ dstep, int sweep,
+              double* __restrict__ ytry, double* __restrict__ lqf) {
   const int wp = blockIdx.x, lane = threadIdx.x;
+  if (dstep != nullptr) step = *dstep;
   const int w = wp / P, p = wp % P;
   const double hl2pi = 0.5 * log(2.0 * M_PI);
   double lq = 0.0;
@@ -629,7 +630,7 @@ hipError_t launch_mlp_propose(const afqmc_ctx_s* c, int nw, const float* out, co
   const int n = nw * c->P;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_propose, dim3(n), dim3(64), 0, c->stream, c->P, c->K, c->mlp.Op, out, y,
-                     seed, step, sweep, ytry, lqf);
+                     seed, step, c->dstep, sweep, ytry, lqf);
   return hipGetLastError();
 }
 

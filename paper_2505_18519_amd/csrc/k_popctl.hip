@@ -51,7 +51,7 @@ k_comb_scan(int nw, double w_cap, const double* __restrict__ w, double* __restri
 
 // parent[j] = min{k : C_k > (j + u) tot / nw}; new weight tot / nw (1 if normalize)
 __global__ void k_comb_parent(int nw, int normalize, uint64_t seed, uint64_t step,
-                              const double* __restrict__ C,
+                              const uint64_t* __restrict__ dstep, const double* __restrict__ C,
                               const double* __restrict__ tot, int* __restrict__ parent,
                               double* __restrict__ w) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,6 +61,7 @@ __global__ void k_comb_parent(int nw, int normalize, uint64_t seed, uint64_t ste
     parent[j] = j;
     return;
   }
+  if (dstep != nullptr) step = *dstep;
   const double u = stream_uniform(seed, 0, step, rng_word3(AFQMC_TAG_COMB, 0, 0), 0);
   const double t = ((double)j + u) * (T / (double)nw);
   int lo = 0, hi = nw - 1;  // first k with C[k] > t, clamped to nw - 1
@@ -73,6 +74,12 @@ __global__ void k_comb_parent(int nw, int normalize, uint64_t seed, uint64_t ste
   }
   parent[j] = lo;
   w[j] = normalize ? 1.0 : T / (double)nw;
+}
+
+__global__ void k_copy_f64(size_t n, const double* __restrict__ src, double* __restrict__ dst) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    dst[q] = src[q];
 }
 
 // dst[j] = src[parent[j]] for rows of `row` doubles; block b copies chunk
@@ -93,8 +100,8 @@ hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize
                        double* C, double* tot, int* parent, uint64_t seed, uint64_t step) {
   hipLaunchKernelGGL(k_comb_scan, dim3(1), dim3(PC_THREADS), 0, c->stream, nw, w_cap, w, C, tot);
   AFQMC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_comb_parent, dim3((nw + 255) / 256), dim3(256), 0, c->stream, nw, normalize, seed, step,
-                     C, tot, parent, w);
+  hipLaunchKernelGGL(k_comb_parent, dim3((nw + 255) / 256), dim3(256), 0, c->stream, nw,
+                     normalize, seed, step, c->dstep, C, tot, parent, w);
   return hipGetLastError();
 }
 
@@ -104,5 +111,12 @@ hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* pa
   const int nchunk = (int)std::min<size_t>((row + 255) / 256, 64);
   hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)(nchunk * nw)), dim3(256), 0, c->stream, nw, row,
                      nchunk, parent, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const afqmc_ctx_s* c, size_t n, const double* src, double* dst) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_copy_f64, dim3(blocks), dim3(256), 0, c->stream, n, src, dst);
   return hipGetLastError();
 }
