@@ -4,12 +4,15 @@
 //   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
 //   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
 //
-// Layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16)).
-// Wavefront w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt]
-// in registers for the whole loop over g.  Stage 1 (Y_g^T = L_g Phi_T) is split
+// Layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16)),
+// compiled per exact number of 16-row tiles KT = M/16 rounded up.  Wavefront
+// w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt] in
+// registers for the whole loop over g.  Stage 1 (Y_g^T = L_g Phi_T) is split
 // over all wavefronts by row tile so every element of L_g is read once per
-// path (straight from L2; L is shared by all paths); its result goes through
-// LDS.  Stage 2 gives each wavefront f^s[:, jt]; f is transposed through LDS
+// path (straight from L2; L is shared by all paths) through one software
+// pipeline over all (row tile, k tile) steps whose loads run up to three steps
+// ahead and continue into the next vector across the barrier; its result goes
+// through LDS.  Stage 2 gives each wavefront f^s[:, jt]; f is transposed through LDS
 // for tr(f f).  In the FP32 form Phi_T, Theta and L enter the products as
 // FP32 with FP32 accumulation over m; per-vector traces, vb_g^2 and the sums
 // over g are carried in FP64.
@@ -44,22 +47,27 @@ struct mm<float> {
   __device__ static int row(int g, int r) { return 4 * g + r; }
 };
 
-template <typename T, int KTMAX, int NTC>
+template <typename T, int KT, int NTC>
 __global__ void __launch_bounds__(128 * NTC)
 k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ Lpad,
              const double* __restrict__ phiT, const double* __restrict__ theta,
              const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   typedef mm<T> MM;
   typedef typename MM::acc_t acc_t;
+  constexpr int KTMAX = KT;
   constexpr int NWV = 2 * NTC;             // wavefronts
   constexpr int NT = 16 * NTC;
-  constexpr int S1MAX = (KTMAX + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  constexpr int NS = S1MAX * KT;               // stage-1 (row tile, k tile) steps
+  // L operand ring: loads run RING - 1 steps ahead; a depth that divides NS
+  // leaves the next vector's first steps in slots 0 .. RING - 2 (no moves of
+  // registers whose loads are still in flight)
+  constexpr int RING = (NS % 4 == 0) ? 4 : (NS % 3 == 0) ? 3 : 2;
   extern __shared__ double smem[];
   T* sY = reinterpret_cast<T*>(smem);                        // [MT][NT]
   double* sF = smem + (MT * NT * sizeof(T) + 7) / 8;          // [2][NT][NT+1][2]
   double* sD = sF + 2 * NT * (NT + 1) * 2;                    // [16][NWV*16][2]
 
-  const int KT = MT / 16;
   const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
@@ -75,7 +83,7 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = 16 * t + 4 * r + g;
-      const bool okm = active && t < KT && m < M;
+      const bool okm = active && m < M;
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) {
         const int n = 16 * ct + c;
@@ -87,40 +95,62 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
       th[1][t][r] = (okm && n < N) ? (T)src[1] : (T)0;
     }
 
-  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  // stage-1 step k = (q = k / KT, t = k % KT) reads L_g rows 16 t + 4 r + g of
+  // column tile tp(q) = wave + NWV q (row tiles past KT are skipped)
+  auto lrow = [&](const T* Lg, int k, int r) -> T {
+    const int q = k / KT, t = k % KT;
+    const int tp = min(wave + NWV * q, KT - 1);  // clamped: in bounds for every wave
+    return Lg[(size_t)(16 * t + 4 * r + g) * MT + 16 * tp + c];
+  };
+  T av[RING][4];
   const size_t slab = (size_t)MT * MT;
+#pragma unroll
+  for (int k = 0; k < RING - 1; ++k)
+    if (k < NS)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[k][r] = lrow(Lpad, k, r);
+
+  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
   for (int gam = 0; gam <= G; ++gam) {
     const T* Lg = Lpad + (size_t)gam * slab;
-    // stage 1: Y^T tiles (tp, ct) for row tiles tp = wave + NWV q
+    const T* Ln = Lpad + (size_t)min(gam + 1, G) * slab;
+    // stage 1: Y^T tiles (tp, ct), one software pipeline over all steps; the
+    // first RING - 1 steps of the next vector are issued at the end
     acc_t y1[S1MAX][NTC];
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q)
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = MM::zero();
 #pragma unroll
-    for (int q = 0; q < S1MAX; ++q) {
-      const int tp = wave + NWV * q;
-      if (active && tp < KT) {
-        // software pipeline: the next k-tile's L operands are fetched before
-        // the current k-tile's MFMAs are issued
-        T av[2][4];
+    for (int k = 0; k < NS; ++k) {
+      const int q = k / KT, t = k % KT;
+      const int kn = k + RING - 1;
+      if (kn < NS) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) av[0][r] = Lg[(size_t)(4 * r + g) * MT + 16 * tp + c];
+        for (int r = 0; r < 4; ++r) av[kn % RING][r] = lrow(Lg, kn, r);
+      } else {
 #pragma unroll
-        for (int t = 0; t < KTMAX; ++t) {
-          if (t < KT) {
-            if (t + 1 < KT)
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                av[(t + 1) & 1][r] = Lg[(size_t)(16 * (t + 1) + 4 * r + g) * MT + 16 * tp + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-              for (int ct = 0; ct < NTC; ++ct)
-                y1[q][ct] = MM::fma(av[t & 1][r], bT[ct][t][r], y1[q][ct]);
-          }
-        }
+        for (int r = 0; r < 4; ++r) av[kn % RING][r] = lrow(Ln, kn - NS, r);
       }
+      if (active && wave + NWV * q < KT)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct)
+            y1[q][ct] = MM::fma(av[k % RING][r], bT[ct][t][r], y1[q][ct]);
+    }
+    // the ring now holds the next vector's first steps at slots NS % RING ...;
+    // rotate them to slots 0 .. RING - 2 (only when RING does not divide NS)
+    if (NS % RING != 0) {
+      T tmp[RING][4];
+#pragma unroll
+      for (int k = 0; k < RING; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tmp[k][r] = av[(k + NS) % RING][r];
+#pragma unroll
+      for (int k = 0; k < RING; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[k][r] = tmp[k][r];
     }
     __syncthreads();  // previous vector's stage-2 and transpose reads are done
 #pragma unroll
@@ -263,12 +293,12 @@ size_t lds_bytes(int MT, int NTC, size_t tsize) {
   return b;
 }
 
-template <typename T, int KTMAX, int NTC>
+template <typename T, int KT, int NTC>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
                     const double* theta, const double* logov, double* vb, double* ep) {
   const int n = nw * c->P;
   const size_t lds = lds_bytes(c->MT, NTC, sizeof(T));
-  auto kern = k_contract_g<T, KTMAX, NTC>;
+  auto kern = k_contract_g<T, KT, NTC>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -281,10 +311,12 @@ template <typename T>
 hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
                     const double* theta, const double* logov, double* vb, double* ep) {
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_G(KM, NC)                                                            \
-  if (KT <= KM && NTC == NC) return launch_g<T, KM, NC>(c, nw, L, phiT, theta, logov, vb, ep);
-  AFQMC_G(4, 1) AFQMC_G(6, 1) AFQMC_G(8, 1)
-  AFQMC_G(4, 2) AFQMC_G(6, 2) AFQMC_G(8, 2)
+#define AFQMC_G(KK, NC)                                                            \
+  if (KT == KK && NTC == NC) return launch_g<T, KK, NC>(c, nw, L, phiT, theta, logov, vb, ep);
+  AFQMC_G(1, 1) AFQMC_G(2, 1) AFQMC_G(3, 1) AFQMC_G(4, 1)
+  AFQMC_G(5, 1) AFQMC_G(6, 1) AFQMC_G(7, 1) AFQMC_G(8, 1)
+  AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)
+  AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
 #undef AFQMC_G
   return hipErrorInvalidValue;
 }
