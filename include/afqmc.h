@@ -60,8 +60,13 @@ enum { AFQMC_HIDDEN_ISING = 0, AFQMC_HIDDEN_GAUSS = 1 };
  * SEPARATE: |I| max(0, cos dtheta) at the walker move, then max(0, cos dtheta_T)
  *           at the hand-off (the pseudo-code of App. B);
  * COMBINED: |I| at the move and one max(0, cos(dtheta + dtheta_T)) at the hand-off;
- * HALFPLANE: cosine at the move, W = 0 if |dtheta_T| > pi/2 at the hand-off.   */
-enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPLANE = 2 };
+ * HALFPLANE: cosine at the move, W = 0 if |dtheta_T| > pi/2 at the hand-off;
+ * LOCAL: the local-energy formalism (Sec. III.A, after Eq. importance_function_CP):
+ *           |I| = exp(-tau (Re E_L - E_T)) with the walker's E_L of Eq.
+ *           local-obs before the move, times max(0, cos dtheta); hand-off as
+ *           SEPARATE.                                                          */
+enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPLANE = 2,
+       AFQMC_WEIGHT_LOCAL = 3 };
 
 /* Metropolis proposals for the paths (Sec. III.A, leapfrog step 2):
  * PRIOR: independent draw from p_T (App. B); for Ising y one sweep flips
@@ -154,19 +159,22 @@ afqmc_status afqmc_force_bias(afqmc_ctx ctx, int32_t nw, const double* phiT, con
 afqmc_status afqmc_local_energy(afqmc_ctx ctx, int32_t nw, const double* phiT, const void* theta,
                                 const void* logov, void* eloc, void* e_sample, void* xbar);
 
-/* One walker move with the hybrid phaseless weight (Eqs. walker_prop,
+/* One walker move with the phaseless weight (Eqs. walker_prop,
  * importance_function, importance_function_CP; Eq. ratio-update-phi for the
  * overlap ratio; App. B step 1):
  *   phi <- e^{-tau h1/2} T_n(V) e^{-tau h1/2} phi,  V = i sqrt(tau) sum_g (xi_g - xbar_g) L_g
  *   l'_p = l_p(phi') at the unchanged paths        -> logov_new [nw][P]
  *   num_r = sum_p exp(l'_p - Re l_p),  r = num_r / sum_p S_p
- *   W <- W |exp(sum_g (xi_g xbar_g - xbar_g^2/2)) r| e^{tau e_shift} [max(0, cos arg r)]
- * xi [nw][n_chol] double, xbar [nw][n_chol] complex, logov = l at (phi, paths).
+ *   hybrid: W <- W |exp(sum_g (xi_g xbar_g - xbar_g^2/2)) r| e^{tau e_shift} [max(0, cos arg r)]
+ *   LOCAL:  W <- W exp(-tau (Re E_L - e_shift)) max(0, cos arg r)
+ * xi [nw][n_chol] double, xbar [nw][n_chol] complex, logov = l at (phi, paths),
+ * eloc [nw] complex (the pre-move E_L; needed by LOCAL, else may be NULL).
  * ref [nw] complex receives the hand-off phase reference: num_r, or sum_p S_p
  * in COMBINED mode.  W = 0 when every path is singular. */
 afqmc_status afqmc_propagate(afqmc_ctx ctx, int32_t nw, void* phi, const double* xi,
                              const void* xbar, const double* phiT, const void* logov,
-                             double e_shift, double* w, void* ref, void* logov_new);
+                             const void* eloc, double e_shift, double* w, void* ref,
+                             void* logov_new);
 
 /* Metropolis update of the paths at the moved walker, then the hand-off
  * projection (Sec. III.A leapfrog step 2, Eqs. PDF-Y, AFQMC_Metro_correction,

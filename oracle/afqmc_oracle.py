@@ -45,6 +45,7 @@ from . import philox
 WEIGHT_SEPARATE = 0   # App. B: cosine of Delta-theta, then cosine of Delta-theta_T
 WEIGHT_COMBINED = 1   # one cosine of the summed angle (Sec. III.A, after Eq. AFQMC_Metro_constraint_cos)
 WEIGHT_HALFPLANE = 2  # hand-off by the half-plane rule instead of the cosine
+WEIGHT_LOCAL = 3      # local-energy formalism: |I| = exp(-tau (Re E_L - E_T)) (Sec. III.A)
 
 PROPOSAL_PRIOR = 0    # independence sampler from p_T (App. B); Ising: single-spin-flip sweep
 PROPOSAL_RW = 1       # Gaussian random walk y' = y + s eta
@@ -214,8 +215,13 @@ def propagate_dets(sys, phi, xi, xbar, dtau, n_taylor, Eh=None):
 
 
 def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
-              e_shift=0.0, weight_mode=WEIGHT_SEPARATE, Eh=None):
-    """One walker move with the hybrid phaseless weight (App. B, step 1).
+              e_shift=0.0, weight_mode=WEIGHT_SEPARATE, Eh=None, eloc=None):
+    """One walker move with the phaseless weight (App. B, step 1): the hybrid
+    |I| = |exp(sum (xi xbar - xbar^2/2)) r| e^{tau E_T} (Eq. importance_function
+    with the overlap ratio), or in the local-energy formalism (mode
+    WEIGHT_LOCAL, Sec. III.A after Eq. importance_function_CP)
+    |I| = exp(-tau (Re E_L - E_T)) with E_L = eloc at the pre-move walker;
+    both times max(0, cos arg r).
 
     Returns (phi', w', ref, logov_new) where logov_new is l_p(phi') at the old
     paths, and ref is the phase reference the hand-off uses: the numerator
@@ -232,8 +238,11 @@ def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
     den = S.sum(-1)
     alive = (den != 0) & (num_r != 0)
     r = np.where(alive, num_r / np.where(alive, den, 1.0), 1.0)
-    log_i = (xi * xbar - 0.5 * xbar * xbar).sum(-1) + np.log(r)
-    mag = np.exp(log_i.real + dtau * e_shift)
+    if weight_mode == WEIGHT_LOCAL:
+        mag = np.exp(-dtau * (np.asarray(eloc).real - e_shift))
+    else:
+        log_i = (xi * xbar - 0.5 * xbar * xbar).sum(-1) + np.log(r)
+        mag = np.exp(log_i.real + dtau * e_shift)
     if weight_mode == WEIGHT_COMBINED:
         wn = w * mag
         ref = den
@@ -400,7 +409,7 @@ def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
     num, den = estimator(st.w, eloc)
     xi = philox.field_normals(seed, i, st.phi.shape[0], sys.n_chol)
     phin, wn, ref, elln = propagate(sys, st.phi, xi, xbar, st.phiT, ell, st.w, dtau,
-                                    n_taylor, e_shift, weight_mode, Eh)
+                                    n_taylor, e_shift, weight_mode, Eh, eloc)
     y, phiT, logov, w2, nacc = metropolis(sys, phin, st.y, st.phiT, elln, ref, wn, seed, i,
                                           n_sweep, proposal, rw_step, weight_mode)
     if n_qr and (i + 1) % n_qr == 0:

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
-WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE = 0, 1, 2
+WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE, WEIGHT_LOCAL = 0, 1, 2, 3
 PROPOSAL_PRIOR, PROPOSAL_RW, PROPOSAL_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 MLP_HIDDEN = 256
@@ -61,7 +61,7 @@ EXPORTS = {
     "afqmc_local_energy": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
     "afqmc_propagate": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                c_double, c_void_p, c_void_p, c_void_p]),
+                                c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "afqmc_metropolis_x": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_uint64, c_uint64, c_int32, c_void_p]),
     "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
@@ -269,14 +269,15 @@ def afqmc_local_energy(ctx, nw, phiT, theta, logov, eloc, e_sample=None, xbar=No
             _ptr(xbar, torch.complex128, nw * c.G, "xbar", allow_none=True))
 
 
-def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_new):
+def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_new, eloc=None):
     c = ctx
     c.reserve(nw)
     c._call("afqmc_propagate", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
             _ptr(xi, torch.float64, nw * c.G, "xi"),
             _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
             _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
-            _ptr(logov, torch.complex128, nw * c.P, "logov"), float(e_shift),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(eloc, torch.complex128, nw, "eloc", allow_none=True), float(e_shift),
             _ptr(w, torch.float64, nw, "w"), _ptr(ref, torch.complex128, nw, "ref"),
             _ptr(logov_new, torch.complex128, nw * c.P, "logov_new"))
 

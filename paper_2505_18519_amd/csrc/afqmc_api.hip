@@ -196,7 +196,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     return AFQMC_E_SHAPE;
   if (sys->hidden_kind != AFQMC_HIDDEN_ISING && sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
     return AFQMC_E_INVALID;
-  if (sys->weight_mode < 0 || sys->weight_mode > 2) return AFQMC_E_INVALID;
+  if (sys->weight_mode < 0 || sys->weight_mode > 3) return AFQMC_E_INVALID;
   if (sys->proposal < 0 || sys->proposal > 2) return AFQMC_E_INVALID;
   if (sys->proposal == AFQMC_PROPOSAL_LEARNED &&
       (sys->hidden_kind != AFQMC_HIDDEN_GAUSS || K > 128))
@@ -407,8 +407,8 @@ afqmc_status afqmc_local_energy(afqmc_ctx c, int32_t nw, const double* phiT, con
 }
 
 afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* xi, const void* xbar,
-                             const double* phiT, const void* logov, double e_shift, double* w,
-                             void* ref, void* logov_new) {
+                             const double* phiT, const void* logov, const void* eloc,
+                             double e_shift, double* w, void* ref, void* logov_new) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);
   if (nw == 0) return AFQMC_OK;
@@ -421,6 +421,8 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   REQUIRE(c, ref, "ref");
   REQUIRE(c, logov_new, "logov_new");
   if (!isfinite(e_shift)) return fail(c, AFQMC_E_INVALID, "e_shift must be finite");
+  if (c->weight_mode == AFQMC_WEIGHT_LOCAL && eloc == nullptr)
+    return fail(c, AFQMC_E_INVALID, "the local-energy formalism needs eloc");
   ws_layout L;
   afqmc_status st = need_ws(c, nw, &L);
   if (st != AFQMC_OK) return st;
@@ -431,8 +433,8 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr), "ratio overlap");
   HIPCALL(c,
           launch_weight(c, nw, xi, static_cast<const double*>(xbar),
-                        static_cast<const double*>(logov), static_cast<double*>(logov_new), e_shift,
-                        w, static_cast<double*>(ref)),
+                        static_cast<const double*>(logov), static_cast<double*>(logov_new),
+                        static_cast<const double*>(eloc), e_shift, w, static_cast<double*>(ref)),
           "weight");
   return AFQMC_OK;
 }

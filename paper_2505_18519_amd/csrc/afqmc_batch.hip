@@ -120,8 +120,8 @@ afqmc_status one_step(afqmc_batch_s* b, sys_state& sys, hipStream_t st, bool qr,
   BCALL(b, afqmc_estimator(c, nw, sys.w, sys.eloc, sys.est), "estimator");
   BCALL(b, afqmc_philox_normal(c, sys.seed, 0, AFQMC_TAG_FIELD, nw, sys.G, sys.xi), "fields");
   BCALL(b,
-        afqmc_propagate(c, nw, sys.phi, sys.xi, sys.xbar, sys.phiT, sys.logov, 0.0, sys.w, sys.ref,
-                        sys.logov_new),
+        afqmc_propagate(c, nw, sys.phi, sys.xi, sys.xbar, sys.phiT, sys.logov, sys.eloc, 0.0,
+                        sys.w, sys.ref, sys.logov_new),
         "propagate");
   BCALL(b,
         afqmc_metropolis_x(c, nw, sys.phi, sys.y, sys.phiT, sys.logov_new, sys.ref, sys.w, sys.seed,

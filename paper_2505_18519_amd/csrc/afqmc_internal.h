@@ -90,8 +90,8 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
                          double* vmat);
 hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
-                         const double* logov, const double* logov_new, double e_shift, double* w,
-                         double* ref);
+                         const double* logov, const double* logov_new, const double* eloc,
+                         double e_shift, double* w, double* ref);
 // proposal: the kind of move (AFQMC_PROPOSAL_PRIOR or _RW; the learned
 // proposal's random-walk moves pass _RW)
 hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double* ytry,

@@ -214,12 +214,13 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
 }
 
 // ---------------------------------------------------------------------------
-// Hybrid weight with the phaseless cosine; one 64-lane workgroup per walker.
+// Phaseless weight, hybrid or local-energy formalism, with the cosine of the
+// overlap ratio's argument; one 64-lane workgroup per walker.
 __global__ void __launch_bounds__(64)
 k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
          const double* __restrict__ xi, const double* __restrict__ xbar,
          const double* __restrict__ logov, const double* __restrict__ logov_new,
-         double* __restrict__ w, double* __restrict__ ref) {
+         const double* __restrict__ eloc, double* __restrict__ w, double* __restrict__ ref) {
   const int wk = blockIdx.x;
   const int lane = threadIdx.x;
   // sum_g (xi_g xbar_g - xbar_g^2 / 2)
@@ -257,7 +258,9 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
   if (alive) {
     const cplx r = cdiv(num, den);
     const double absr = sqrt(cabs2(r));
-    const double mag = exp(sr + log(absr) + dtau * e_shift);
+    const double mag = (weight_mode == AFQMC_WEIGHT_LOCAL)
+                           ? exp(-dtau * (eloc[2 * (size_t)wk] - e_shift))
+                           : exp(sr + log(absr) + dtau * e_shift);
     if (weight_mode == AFQMC_WEIGHT_COMBINED)
       wn = w[wk] * mag;
     else
@@ -300,11 +303,11 @@ hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, doubl
 }
 
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
-                         const double* logov, const double* logov_new, double e_shift, double* w,
-                         double* ref) {
+                         const double* logov, const double* logov_new, const double* eloc,
+                         double e_shift, double* w, double* ref) {
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_weight, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, c->dtau, e_shift,
-                     c->weight_mode, xi, xbar, logov, logov_new, w, ref);
+                     c->weight_mode, xi, xbar, logov, logov_new, eloc, w, ref);
   return hipGetLastError();
 }
 

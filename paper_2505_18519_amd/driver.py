@@ -67,7 +67,7 @@ def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
     A.afqmc_estimator(ctx, nw, st.w, st.eloc, est_out)
     A.afqmc_philox_normal(ctx, seed, i, A.TAG_FIELD, nw, ctx.G, st.xi)
     A.afqmc_propagate(ctx, nw, st.phi, st.xi, st.xbar, st.phiT, st.logov, e_shift, st.w,
-                      st.ref, st.logov_new)
+                      st.ref, st.logov_new, st.eloc)
     A.afqmc_metropolis_x(ctx, nw, st.phi, st.y, st.phiT, st.logov_new, st.ref, st.w, seed, i,
                          n_sweep, st.nacc)
     st.logov, st.logov_new = st.logov_new, st.logov

@@ -141,7 +141,7 @@ def test_force_bias_and_local_energy(case):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 3])
 def test_propagate(case, mode):
     _say("case", case, "mode", mode)
     s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
@@ -154,11 +154,13 @@ def test_propagate(case, mode):
     xi = rng.normal(size=(nw, s.n_chol))
     w0 = rng.uniform(0.5, 1.5, size=nw)
     e_shift = -1.3
-    phin, wn, ref, elln = O.propagate(s, phi, xi, xbar, phiT, ell, w0, dtau, 10, e_shift, mode)
+    phin, wn, ref, elln = O.propagate(s, phi, xi, xbar, phiT, ell, w0, dtau, 10, e_shift, mode,
+                                      eloc=eloc)
     dphi, dw = dev(phi), dev(w0)
     dref = torch.zeros(nw, dtype=torch.complex128, device="cuda")
     dln = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
-    A.afqmc_propagate(ctx, nw, dphi, dev(xi), dev(xbar), dev(phiT), dev(ell), e_shift, dw, dref, dln)
+    A.afqmc_propagate(ctx, nw, dphi, dev(xi), dev(xbar), dev(phiT), dev(ell), e_shift, dw, dref, dln,
+                      dev(eloc))
     torch.cuda.synchronize()
     for w in range(nw):
         assert rel(host(dphi)[w], phin[w]) <= TOL

@@ -2,7 +2,8 @@
 sides): the tiny Ising workload (M=8, N=2, 16 vectors, K=4, 64 walkers x 8
 paths, tau = 0.01, one sweep per step, comb every step) run on the GPU and by
 the oracle gives mixed-estimator energies (Eq. mixed_estimator) that agree
-within 3 sigma of the combined reblocked errors.  The phaseless bias of the
+within 3 sigma of the combined reblocked errors, with the hybrid weight and
+with the local-energy formalism (Sec. III.A).  The phaseless bias of the
 Jastrow trial against exact diagonalisation is reported, not pinned."""
 import json
 import math
@@ -38,10 +39,10 @@ def reblock(x):
     return best
 
 
-def _gpu_run(s, run, seed):
+def _gpu_run(s, run, seed, mode):
     from paper_2505_18519_amd import afqmc as A
     from paper_2505_18519_amd import driver as D
-    ctx = A.Context(s, run.P, run.dtau, max_walkers=run.W)
+    ctx = A.Context(s, run.P, run.dtau, max_walkers=run.W, weight_mode=mode)
     st = D.init_walkers(ctx, s.phi0, run.W, seed)
     est = torch.zeros(N_STEPS, 2, dtype=torch.float64, device="cuda")
     for i in range(N_STEPS):
@@ -50,12 +51,13 @@ def _gpu_run(s, run, seed):
     return e[:, 0] / e[:, 1]
 
 
-def _oracle_run(s, run, seed):
+def _oracle_run(s, run, seed, mode):
     st = O.init_state(s, run.W, run.P, seed)
     Eh, h1p = O.half_kinetic(s, run.dtau), O.h1_eff(s)
     out = []
     for i in range(N_STEPS):
-        st, rec = O.step(s, st, seed, i, run.dtau, n_qr=10, Eh=Eh, h1p=h1p, n_pc=1, w_cap=4.0)
+        st, rec = O.step(s, st, seed, i, run.dtau, n_qr=10, Eh=Eh, h1p=h1p, n_pc=1, w_cap=4.0,
+                         weight_mode=mode)
         out.append(rec["e_num"] / rec["e_den"])
     return np.array(out)
 
@@ -68,16 +70,17 @@ def _gpu():
     A.load_library()
 
 
-def test_gpu_and_oracle_energies_agree_within_error_bars():
+@pytest.mark.parametrize("mode", [O.WEIGHT_SEPARATE, O.WEIGHT_LOCAL])
+def test_gpu_and_oracle_energies_agree_within_error_bars(mode):
     s, run = ai.workload(0)
     e0 = json.load(open(os.path.join(GOLDEN, "tiny_ising_ed.json")))["E0"]
-    g = np.concatenate([_gpu_run(s, run, seed)[N_EQ:] for seed in (101, 102, 103, 104)])
-    o = np.concatenate([_oracle_run(s, run, seed)[N_EQ:] for seed in (201, 202)])
+    g = np.concatenate([_gpu_run(s, run, seed, mode)[N_EQ:] for seed in (101, 102, 103, 104)])
+    o = np.concatenate([_oracle_run(s, run, seed, mode)[N_EQ:] for seed in (201, 202)])
     # each seed's series is blocked separately, then the means are combined
     eg = [reblock(x) for x in np.split(g, 4)]
     eo = [reblock(x) for x in np.split(o, 2)]
     mg, sg = g.mean(), math.sqrt(sum(e * e for e in eg)) / 4
     mo, so = o.mean(), math.sqrt(sum(e * e for e in eo)) / 2
-    _say(f"GPU {mg:.5f} +- {sg:.5f}  oracle {mo:.5f} +- {so:.5f}  ED {e0:.5f}  "
+    _say(f"weight mode {mode}: GPU {mg:.5f} +- {sg:.5f}  oracle {mo:.5f} +- {so:.5f}  ED {e0:.5f}  "
          f"(phaseless bias of the Jastrow trial: {mg - e0:+.4f})")
     assert abs(mg - mo) < 3 * math.sqrt(sg * sg + so * so)

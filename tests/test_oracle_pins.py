@@ -306,6 +306,14 @@ def test_zero_variance_exact_trial():
         st, rec = O.step(s, st, 3, i, 0.01, e_shift=E0, n_qr=5)
         assert abs(rec["e_num"] / rec["e_den"] - E0) <= 1e-10 * abs(E0)
     assert np.abs(st.w - 1.0).max() <= 1e-10
+    # with E_T = E_0 + d both formalisms grow every weight by exactly e^{tau d}
+    # per step: the hybrid through the overlap ratio e^{-tau E_0}, the
+    # local-energy form through E_L = E_0 (sign and scale of both pinned)
+    for mode in (O.WEIGHT_SEPARATE, O.WEIGHT_LOCAL):
+        st = O.init_state(s, 8, 4, seed=4)
+        for i in range(6):
+            st, rec = O.step(s, st, 4, i, 0.01, e_shift=E0 + 0.7, n_qr=5, weight_mode=mode)
+        assert np.abs(st.w / math.exp(0.01 * 0.7 * 6) - 1.0).max() <= 1e-12, (mode, st.w)
 
 
 # -- Reductions and invariances ---------------------------------------------
