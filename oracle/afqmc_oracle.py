@@ -376,6 +376,94 @@ def estimator(w: np.ndarray, eloc: np.ndarray):
 
 
 # ---------------------------------------------------------------------------
+# Initialisation from the trial and measurement with extra paths (App. B,
+# Initialization and Measurement; Sec. III.A, end of the composite-walker part)
+
+INIT_STEP = 1 << 63      # step indices INIT_STEP + j belong to the initialisation chains
+MEASURE_STEP = 1 << 62   # step indices MEASURE_STEP + i belong to the measurement chains
+
+
+def as_walker(phiT: np.ndarray) -> np.ndarray:
+    """The determinant B_T(Y) phi_T of Eq. Metropolis_sampled_trial as a walker:
+    the same real M x N orbitals for both spins, [n, M, N] -> [n, 2, M, N] complex."""
+    return np.repeat(phiT[:, None], 2, axis=1).astype(np.complex128)
+
+
+def init_metropolis(sys, nw, P, seed, n_pair, n_burn, proposal=PROPOSAL_PRIOR, rw_step=0.5):
+    """Walkers sampled from the trial (App. B, Initialization; Eq. Metropolis).
+
+    The variational Metropolis estimate of Eq. Metropolis samples pairs
+    (Y_k, Y_k') from pi(Y, Y') ~ p_T(Y) p_T(Y') |<phi_T|B_T(Y') B_T(Y)|phi_T>|.
+    pi is symmetric and each of its conditionals is the path density of Eq.
+    PDF-Y with the other member's B_T(.) phi_T as the walker, so a chain of
+    pairs alternates the two conditional Metropolis updates: the partner Y'
+    given the walker B_T(Y_k) phi_T, then Y_k given the walker B_T(Y') phi_T.
+    After n_pair rounds the walker is phi^0_k = B_T(Y_k) phi_T, each of its P
+    paths starts as a copy of the partner (so every pair (Y_k, Y[p]) has the
+    law pi whatever follows) and takes n_burn sweeps at that walker to
+    decorrelate from the others, and W^0_k = Re sum_p S_p (the sum of the pair
+    phases e^{i theta_{p,k}}).  For this trial family the overlaps are squares
+    of real determinants, so W^0_k = P.
+
+    Random streams: Y_k and Y' start from the INIT stream with sweeps 1 and 2;
+    the chains use the Metropolis streams at steps INIT_STEP + 2j (partner)
+    and INIT_STEP + 2j + 1 (walker field), and INIT_STEP + 2 n_pair for the
+    paths' sweeps.  Returns (State, yw [nw, K])."""
+    K, kind = sys.K, sys.hidden_kind
+    ya = philox.init_hidden(seed, nw, 1, K, kind, sweep=1)
+    yb = philox.init_hidden(seed, nw, 1, K, kind, sweep=2)
+    pa, pb = trial_det(sys, ya), trial_det(sys, yb)
+    one, ref = np.ones(nw), np.ones(nw, dtype=np.complex128)
+    for j in range(n_pair):
+        wa = as_walker(pa[:, 0])
+        yb, pb, _, _, _ = metropolis(sys, wa, yb, pb, log_overlap(pb, wa), ref, one, seed,
+                                     INIT_STEP + 2 * j, 1, proposal, rw_step)
+        wb = as_walker(pb[:, 0])
+        ya, pa, _, _, _ = metropolis(sys, wb, ya, pa, log_overlap(pa, wb), ref, one, seed,
+                                     INIT_STEP + 2 * j + 1, 1, proposal, rw_step)
+    phi = as_walker(pa[:, 0])
+    y = np.repeat(yb, P, axis=1)
+    phiT = np.repeat(pb, P, axis=1)
+    y, phiT, logov, _, _ = metropolis(sys, phi, y, phiT, log_overlap(phiT, phi), ref, one, seed,
+                                      INIT_STEP + 2 * n_pair, n_burn, proposal, rw_step)
+    w = phases(logov).sum(-1).real
+    return State(phi, w, y, phiT, logov), ya[:, 0]
+
+
+def extend_paths(y, phiT, logov, P2):
+    """The measurement's P2 paths start from the walker's own: path q copies path q mod P."""
+    idx = np.arange(P2) % y.shape[1]
+    return y[:, idx].copy(), phiT[:, idx].copy(), logov[:, idx].copy()
+
+
+def measure_extra(sys, phi, y, phiT, logov, w, seed, step, P2, n_sweep, dtau,
+                  proposal=PROPOSAL_PRIOR, rw_step=0.5, h1p=None, xbar_cap=0.0):
+    """Mixed estimator with a freshly sampled measurement trial (Sec. III.A, end
+    of the composite-walker part; App. B, Measurement).
+
+    The walker's P paths are extended to P2 (extend_paths) and moved n_sweep
+    sweeps towards p_T |O(.; phi)| at the fixed walker; E'_L is the local
+    energy over the new paths (Eq. local-obs); the walker's weight enters
+    numerator and denominator of Eq. mixed_estimator times the correction
+    factor R_k = sum_q S'_q / sum_p S_p (sign ratios over the new and the
+    current paths).  Returns (sum W Re(R E'_L), sum W Re R, E'_L [nw], R [nw]);
+    a walker whose current sign sum is 0 has R = 0."""
+    y2, phiT2, l2 = extend_paths(y, phiT, logov, P2)
+    nw = phi.shape[0]
+    y2, phiT2, l2, _, _ = metropolis(sys, phi, y2, phiT2, l2, np.ones(nw, dtype=np.complex128),
+                                     np.ones(nw), seed, step, n_sweep, proposal, rw_step)
+    ell2, theta2 = green(phiT2, phi)
+    vb, ep = sample_contraction(sys, phiT2, theta2, ell2, h1p)
+    _, eloc2 = walker_estimates(vb, ep, ell2, dtau, xbar_cap)
+    S = phases(logov).sum(-1)
+    S2 = phases(ell2).sum(-1)
+    R = np.where(S != 0, S2 / np.where(S != 0, S, 1.0), 0.0)
+    num = math.fsum((w * (R * eloc2).real).tolist())
+    den = math.fsum((w * R.real).tolist())
+    return num, den, eloc2, R
+
+
+# ---------------------------------------------------------------------------
 # One whole step (App. B order) for trajectory tests
 
 class State:

@@ -155,9 +155,11 @@ def accept_uniforms(seed: int, step: int, nw: int, P: int, n: int, sweep: int) -
     return stream_uniforms(seed, step, np.arange(nw), w3, n)
 
 
-def init_hidden(seed: int, nw: int, P: int, K: int, hidden_kind: int) -> np.ndarray:
-    """Initial hidden variables drawn from the trial prior p_T, [nw, P, K]."""
-    w3 = [word3(TAG_INIT, 0, p) for p in range(P)]
+def init_hidden(seed: int, nw: int, P: int, K: int, hidden_kind: int, sweep: int = 0) -> np.ndarray:
+    """Initial hidden variables drawn from the trial prior p_T, [nw, P, K].
+    sweep 0: the tethered paths; sweeps 1 and 2: the walker field Y_k and its
+    partner Y' of the initialisation from the trial (one each per walker, P = 1)."""
+    w3 = [word3(TAG_INIT, sweep, p) for p in range(P)]
     if hidden_kind == 0:
         u = stream_uniforms(seed, 0, np.arange(nw), w3, K)
         return np.where(u < 0.5, -1.0, 1.0)
