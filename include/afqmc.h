@@ -193,7 +193,9 @@ afqmc_status afqmc_propagate(afqmc_ctx ctx, int32_t nw, void* phi, const double*
  * Then
  *   dtheta_T = arg sum_p S'_p - arg ref,  W <- W max(0, cos dtheta_T)
  * (HALFPLANE: W <- 0 if |dtheta_T| > pi/2).  n_accept [nw] int32 counts
- * accepted moves per walker (may be NULL). */
+ * accepted moves per walker (may be NULL).  With w = NULL the paths move and
+ * no hand-off is applied (ref may then be NULL too): the form the
+ * initialisation and the measurement chains use. */
 afqmc_status afqmc_metropolis_x(afqmc_ctx ctx, int32_t nw, const void* phi, double* y,
                                 double* phiT, void* logov, const void* ref, double* w,
                                 uint64_t seed, uint64_t step, int32_t n_sweep, int32_t* n_accept);
@@ -223,6 +225,63 @@ afqmc_status afqmc_population_control(afqmc_ctx ctx, int32_t nw, void* phi, doub
  * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2]. */
 afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const void* eloc,
                              double* out);
+
+/* ---- Initialisation from the trial and measurement with extra paths ------- */
+
+/* Step indices of the Metropolis streams reserved for these chains: the
+ * initialisation uses AFQMC_INIT_STEP + j; measurement chains are meant to use
+ * AFQMC_MEASURE_STEP + (step index), apart from the propagation's steps. */
+#define AFQMC_INIT_STEP 0x8000000000000000ull
+#define AFQMC_MEASURE_STEP 0x4000000000000000ull
+
+/* Walkers sampled from the trial (App. B, Initialization; Eq. Metropolis and
+ * Eq. Metropolis_chain): pairs (Y_k, Y') from
+ *   pi(Y, Y') ~ p_T(Y) p_T(Y') |<phi_T|B_T(Y') B_T(Y)|phi_T>|
+ * by n_pair rounds of the two conditional Metropolis updates (each is the
+ * path density of Eq. PDF-Y with the other member's determinant as walker):
+ * the partner Y' at step AFQMC_INIT_STEP + 2j, then Y_k at + 2j + 1, both
+ * with the context's proposal (a learned proposal is replaced by the random
+ * walk of step rw_step, 0.5 if rw_step is 0).  Y_k and Y' start from the
+ * prior (stream INIT, sweeps 1 and 2).  Outputs:
+ *   yw   [nw][K]          the walker fields Y_k
+ *   phi  [nw][2][M][N]    phi^0_k = B_T(Y_k) phi_T = Phi_T(Y_k) for both spins
+ *   y, phiT, logov        P paths per walker, each a copy of the partner Y'
+ *                         moved n_burn sweeps at phi^0_k (step
+ *                         AFQMC_INIT_STEP + 2 n_pair); every walker-path pair
+ *                         then has the law pi
+ *   w    [nw]             W^0_k = Re sum_p S_p (the pair phases summed over
+ *                         the paths; = P for this trial family, whose overlaps
+ *                         are squares of real determinants)
+ * The mixed estimator of this population is the Metropolis estimate of the
+ * trial's variational energy (App. B, Eq. AFQMC_Metropolis_initial).  Uses the
+ * workspace (for nw walkers); all buffers are device memory owned by the
+ * caller and must not overlap. */
+afqmc_status afqmc_init_metropolis(afqmc_ctx ctx, int32_t nw, uint64_t seed, int32_t n_pair,
+                                   int32_t n_burn, double* yw, void* phi, double* y, double* phiT,
+                                   void* logov, double* w);
+
+/* Paths of a measurement trial (Sec. III.A, end of the composite-walker part;
+ * App. B, Measurement): the context's P paths of each walker start from the
+ * walker's p_src current ones, path q copying path q mod p_src:
+ *   y_src [nw][p_src][K], phiT_src [nw][p_src][M][N], logov_src [nw][p_src]
+ *   -> y [nw][P][K], phiT [nw][P][M][N], logov [nw][P] (complex).
+ * Source and destination must not overlap.  Moving them afterwards with
+ * afqmc_metropolis_x (w = NULL) gives the new paths Y'. */
+afqmc_status afqmc_extend_paths(afqmc_ctx ctx, int32_t nw, int32_t p_src, const double* y_src,
+                                const double* phiT_src, const void* logov_src, double* y,
+                                double* phiT, void* logov);
+
+/* Mixed estimator with the measurement trial's correction factor (Sec. III.A,
+ * end of the composite-walker part; App. B, Measurement):
+ *   R_k = sum_q S'_q / sum_p S_p   (new paths: logov [nw][P] of this context;
+ *                                   current: logov_ref [nw][p_ref])
+ *   out[0] = sum_k W_k Re(R_k E'_L,k),  out[1] = sum_k W_k Re R_k
+ * with E'_L (eloc [nw] complex) from the new paths; R_k = 0 when the current
+ * sign sum is 0.  Compensated FP64 sums; out is a DEVICE double[2]; R [nw]
+ * complex receives R_k (may be NULL). */
+afqmc_status afqmc_estimator_corrected(afqmc_ctx ctx, int32_t nw, const double* w,
+                                       const void* eloc, const void* logov, int32_t p_ref,
+                                       const void* logov_ref, double* out, void* R);
 
 /* Counter-based normals: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
  * counter (i / 4, walker, step, tag << 48 | sweep << 24 | path).  Fills

@@ -23,6 +23,7 @@ PROPOSAL_PRIOR, PROPOSAL_RW, PROPOSAL_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 MLP_HIDDEN = 256
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
+INIT_STEP, MEASURE_STEP = 1 << 63, 1 << 62     # AFQMC_INIT_STEP, AFQMC_MEASURE_STEP
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
           5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
@@ -66,6 +67,12 @@ EXPORTS = {
                                    c_void_p, c_void_p, c_uint64, c_uint64, c_int32, c_void_p]),
     "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_estimator": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "afqmc_init_metropolis": (c_int, [c_void_p, c_int32, c_uint64, c_int32, c_int32, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "afqmc_extend_paths": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p]),
+    "afqmc_estimator_corrected": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                                          c_void_p, c_void_p, c_void_p]),
     "afqmc_population_control": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                          c_void_p, c_uint64, c_uint64, c_double, c_int32,
                                          c_void_p]),
@@ -289,7 +296,8 @@ def afqmc_metropolis_x(ctx, nw, phi, y, phiT, logov, ref, w, seed, step, n_sweep
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
             _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
-            _ptr(ref, torch.complex128, nw, "ref"), _ptr(w, torch.float64, nw, "w"),
+            _ptr(ref, torch.complex128, nw, "ref", allow_none=w is None),
+            _ptr(w, torch.float64, nw, "w", allow_none=True),
             int(seed), int(step), int(n_sweep),
             _ptr(n_accept, torch.int32, nw, "n_accept", allow_none=True))
 
@@ -315,6 +323,38 @@ def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=
 def afqmc_estimator(ctx, nw, w, eloc, out):
     ctx._call("afqmc_estimator", nw, _ptr(w, torch.float64, nw, "w"),
               _ptr(eloc, torch.complex128, nw, "eloc"), _ptr(out, torch.float64, 2, "out"))
+
+
+def afqmc_init_metropolis(ctx, nw, seed, n_pair, n_burn, yw, phi, y, phiT, logov, w):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_init_metropolis", nw, int(seed), int(n_pair), int(n_burn),
+            _ptr(yw, torch.float64, nw * c.K, "yw"),
+            _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(y, torch.float64, nw * c.P * c.K, "y"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"), _ptr(w, torch.float64, nw, "w"))
+
+
+def afqmc_extend_paths(ctx, nw, p_src, y_src, phiT_src, logov_src, y, phiT, logov):
+    c = ctx
+    c._call("afqmc_extend_paths", nw, int(p_src),
+            _ptr(y_src, torch.float64, nw * p_src * c.K, "y_src"),
+            _ptr(phiT_src, torch.float64, nw * p_src * c.M * c.N, "phiT_src"),
+            _ptr(logov_src, torch.complex128, nw * p_src, "logov_src"),
+            _ptr(y, torch.float64, nw * c.P * c.K, "y"),
+            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"))
+
+
+def afqmc_estimator_corrected(ctx, nw, w, eloc, logov, p_ref, logov_ref, out, R=None):
+    c = ctx
+    c._call("afqmc_estimator_corrected", nw, _ptr(w, torch.float64, nw, "w"),
+            _ptr(eloc, torch.complex128, nw, "eloc"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"), int(p_ref),
+            _ptr(logov_ref, torch.complex128, nw * p_ref, "logov_ref"),
+            _ptr(out, torch.float64, 2, "out"),
+            _ptr(R, torch.complex128, nw, "R", allow_none=True))
 
 
 def afqmc_philox_normal(ctx, seed, step, tag, nw, n, out):

@@ -149,6 +149,14 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
     *dst[i] = off;
     off += align256(sizes[i]);
   }
+  const size_t MN = (size_t)c->M * c->N;
+  const size_t isz[] = {(size_t)nw * c->K * 8, (size_t)nw * MN * 8, (size_t)nw * MN * 8,
+                        (size_t)nw * 16, (size_t)nw * 16};
+  size_t* idst[] = {&L.in_yb, &L.in_pa, &L.in_pb, &L.in_la, &L.in_lb};
+  for (int i = 0; i < 5; ++i) {
+    *idst[i] = off;
+    off += align256(isz[i]);
+  }
   L.total = off;
   return L;
 }
@@ -449,8 +457,7 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
   REQUIRE(c, y, "y");
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
-  REQUIRE(c, ref, "ref");
-  REQUIRE(c, w, "w");
+  if (w != nullptr) REQUIRE(c, ref, "ref");
   if (n_sweep < 0) return fail(c, AFQMC_E_INVALID, "n_sweep must be >= 0");
   ws_layout L;
   afqmc_status st = need_ws(c, nw, &L);
@@ -512,7 +519,8 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
                             AFQMC_PROPOSAL_LEARNED, lqx, gdc, gdt, nullptr),
               "accept");
     }
-    HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
+    if (w != nullptr)
+      HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
     return AFQMC_OK;
   }
   const int nflip = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? c->K : 1;
@@ -529,7 +537,114 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
               "accept");
     }
   }
-  HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
+  if (w != nullptr)
+    HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
+  return AFQMC_OK;
+}
+
+// Pair chain of the initialisation from the trial: two P = 1 chains whose
+// walker is the other member's determinant; the walker field lives in yw, the
+// partner and both determinants and log-overlaps in the workspace, the
+// complex walker built from either determinant in phi.
+afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32_t n_pair,
+                                   int32_t n_burn, double* yw, void* phi, double* y, double* phiT,
+                                   void* logov, double* w) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, yw, "yw");
+  REQUIRE(c, phi, "phi");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, w, "w");
+  if (n_pair < 0 || n_burn < 0) return fail(c, AFQMC_E_INVALID, "n_pair and n_burn must be >= 0");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  afqmc_ctx_s cp = *c;  // the chains' proposal: a learned one is replaced by the random walk
+  if (cp.proposal == AFQMC_PROPOSAL_LEARNED) {
+    cp.proposal = AFQMC_PROPOSAL_RW;
+    if (!(cp.rw_step > 0.0)) cp.rw_step = 0.5;
+  }
+  afqmc_ctx_s c1 = cp;
+  c1.P = 1;
+  double* yb = ws_ptr<double>(c, L.in_yb);
+  double* pa = ws_ptr<double>(c, L.in_pa);
+  double* pb = ws_ptr<double>(c, L.in_pb);
+  double* la = ws_ptr<double>(c, L.in_la);
+  double* lb = ws_ptr<double>(c, L.in_lb);
+  double* ub = ws_ptr<double>(c, L.ubuf);
+  double* ph = static_cast<double*>(phi);
+  const size_t MN = (size_t)c->M * c->N;
+  auto sub = [&](afqmc_status s2, const afqmc_ctx_s& from) {
+    if (s2 != AFQMC_OK) c->err = from.err;
+    return s2;
+  };
+  HIPCALL(c, launch_sample_prior(&c1, nw, seed, yw, 1), "walker fields");
+  HIPCALL(c, launch_sample_prior(&c1, nw, seed, yb, 2), "partner fields");
+  HIPCALL(c, do_trial_build(&c1, nw, yw, pa, ub), "walker trial build");
+  HIPCALL(c, do_trial_build(&c1, nw, yb, pb, ub), "partner trial build");
+  for (int j = 0; j < n_pair; ++j) {
+    HIPCALL(c, launch_as_walker(c, nw, pa, MN, ph), "walker from field");
+    HIPCALL(c, do_overlap(&c1, nw, ph, pb, lb, nullptr), "partner overlap");
+    st = sub(afqmc_metropolis_x(&c1, nw, ph, yb, pb, lb, nullptr, nullptr, seed,
+                                AFQMC_INIT_STEP + 2 * (uint64_t)j, 1, nullptr), c1);
+    if (st != AFQMC_OK) return st;
+    HIPCALL(c, launch_as_walker(c, nw, pb, MN, ph), "walker from partner");
+    HIPCALL(c, do_overlap(&c1, nw, ph, pa, la, nullptr), "walker-field overlap");
+    st = sub(afqmc_metropolis_x(&c1, nw, ph, yw, pa, la, nullptr, nullptr, seed,
+                                AFQMC_INIT_STEP + 2 * (uint64_t)j + 1, 1, nullptr), c1);
+    if (st != AFQMC_OK) return st;
+  }
+  HIPCALL(c, launch_as_walker(c, nw, pa, MN, ph), "initial walkers");
+  HIPCALL(c, launch_extend_paths(c, nw, 1, c->P, yb, pb, nullptr, y, phiT, nullptr), "paths");
+  HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov), nullptr), "overlap");
+  st = sub(afqmc_metropolis_x(&cp, nw, ph, y, phiT, logov, nullptr, nullptr, seed,
+                              AFQMC_INIT_STEP + 2 * (uint64_t)n_pair, n_burn, nullptr), cp);
+  if (st != AFQMC_OK) return st;
+  HIPCALL(c, launch_sign_sum(c, nw, c->P, static_cast<const double*>(logov), w), "weights");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_extend_paths(afqmc_ctx c, int32_t nw, int32_t p_src, const double* y_src,
+                                const double* phiT_src, const void* logov_src, double* y,
+                                double* phiT, void* logov) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  if (p_src < 1) return fail(c, AFQMC_E_INVALID, "p_src must be >= 1");
+  REQUIRE(c, y_src, "y_src");
+  REQUIRE(c, phiT_src, "phiT_src");
+  REQUIRE(c, logov_src, "logov_src");
+  REQUIRE(c, y, "y");
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  HIPCALL(c,
+          launch_extend_paths(c, nw, p_src, c->P, y_src, phiT_src,
+                              static_cast<const double*>(logov_src), y, phiT,
+                              static_cast<double*>(logov)),
+          "extend_paths");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_estimator_corrected(afqmc_ctx c, int32_t nw, const double* w, const void* eloc,
+                                       const void* logov, int32_t p_ref, const void* logov_ref,
+                                       double* out, void* R) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (p_ref < 1) return fail(c, AFQMC_E_INVALID, "p_ref must be >= 1");
+  REQUIRE(c, w, "w");
+  REQUIRE(c, eloc, "eloc");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, logov_ref, "logov_ref");
+  REQUIRE(c, out, "out");
+  HIPCALL(c,
+          launch_estimator_corrected(c, nw, p_ref, w, static_cast<const double*>(eloc),
+                                     static_cast<const double*>(logov),
+                                     static_cast<const double*>(logov_ref), out,
+                                     static_cast<double*>(R)),
+          "estimator_corrected");
   return AFQMC_OK;
 }
 

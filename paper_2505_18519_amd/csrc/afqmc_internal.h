@@ -65,6 +65,10 @@ struct ws_layout {
       pc_logov;
   // learned proposal (zero-sized unless proposal == LEARNED); Sp = paths rounded up to 16
   size_t gd_cur, gd_try, mlF, mlR, lqf, lqx, zT, h1T, h2T, dOT, dh2T, dh1T, nlq, part;
+  // initialisation from the trial: the partner chain and both P = 1 chains'
+  // determinants and log-overlaps (last, so that the same carve-up for P = 1
+  // or without the network never reaches it)
+  size_t in_yb, in_pa, in_pb, in_la, in_lb;
   size_t total;
 };
 constexpr int MLP_CHUNK = 512;  // samples per split of the weight-gradient sums
@@ -108,7 +112,18 @@ hipError_t launch_estimator(const afqmc_ctx_s* c, int nw, const double* w, const
                             double* out);
 hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t step, uint32_t tag,
                                 int nw, int n, double* out);
-hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y);
+hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y,
+                               int sweep = 0);
+hipError_t launch_estimator_corrected(const afqmc_ctx_s* c, int nw, int Pr, const double* w,
+                                      const double* eloc, const double* logov,
+                                      const double* logov_ref, double* out, double* R);
+// initialisation from the trial and measurement with extra paths (k_init.hip)
+hipError_t launch_as_walker(const afqmc_ctx_s* c, int nw, const double* src, size_t stride,
+                            double* dst);
+hipError_t launch_sign_sum(const afqmc_ctx_s* c, int nw, int P, const double* logov, double* w);
+hipError_t launch_extend_paths(const afqmc_ctx_s* c, int nw, int Ps, int Pd, const double* ys,
+                               const double* ps, const double* ls, double* yd, double* pd,
+                               double* ld);
 hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y,
                                 double* phiT, double* ubuf);

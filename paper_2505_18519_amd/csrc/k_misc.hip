@@ -96,14 +96,14 @@ __global__ void k_philox_normal(uint64_t seed, uint64_t step, const uint64_t* __
     if (4 * b + q < n) out[(size_t)w * n + 4 * b + q] = z[q];
 }
 
-__global__ void k_sample_prior(int nw, int P, int K, int hidden_kind, uint64_t seed,
+__global__ void k_sample_prior(int nw, int P, int K, int hidden_kind, uint64_t seed, int sweep,
                                double* __restrict__ y) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nw * P * K) return;
   const int k = (int)(idx % K);
   const int p = (int)((idx / K) % P);
   const int w = (int)(idx / ((size_t)K * P));
-  const uint64_t w3 = rng_word3(AFQMC_TAG_INIT, 0, p);
+  const uint64_t w3 = rng_word3(AFQMC_TAG_INIT, sweep, p);
   if (hidden_kind == AFQMC_HIDDEN_ISING)
     y[idx] = (stream_uniform(seed, w, 0, w3, k) < 0.5) ? -1.0 : 1.0;
   else
@@ -154,6 +154,70 @@ k_estimator(int nw, const double* __restrict__ w, const double* __restrict__ elo
     double* o = (dstep != nullptr) ? out + 2 * (size_t)(*dstep % (uint64_t)cap) : out;
     o[0] = s_v[0][0] + s_v[1][0];
     o[1] = s_v[2][0] + s_v[3][0];
+  }
+}
+
+// Mixed estimator with a correction factor per walker (measurement with extra
+// paths): R_k = sum_q S'_q / sum_p S_p from the new paths' log-overlaps (P)
+// and the current ones (Pr); out[0] = sum W Re(R E_L), out[1] = sum W Re R,
+// compensated as in k_estimator; R [nw] complex is written when non-null.
+__global__ void __launch_bounds__(256)
+k_estimator_corrected(int nw, int P, int Pr, const double* __restrict__ w,
+                      const double* __restrict__ eloc, const double* __restrict__ logov,
+                      const double* __restrict__ logov_ref, double* __restrict__ out,
+                      double* __restrict__ R) {
+  __shared__ double s_v[4][256];
+  const int tid = threadIdx.x;
+  double n_s = 0.0, n_e = 0.0, d_s = 0.0, d_e = 0.0;
+  for (int k = tid; k < nw; k += 256) {
+    cplx s2 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+    for (int q = 0; q < P; ++q) {
+      const double* l = logov + ((size_t)k * P + q) * 2;
+      if (__builtin_isfinite(l[0])) {
+        double sn, cs;
+        sincos(l[1], &sn, &cs);
+        s2 = cadd(s2, cmk(cs, sn));
+      }
+    }
+    for (int p = 0; p < Pr; ++p) {
+      const double* l = logov_ref + ((size_t)k * Pr + p) * 2;
+      if (__builtin_isfinite(l[0])) {
+        double sn, cs;
+        sincos(l[1], &sn, &cs);
+        s1 = cadd(s1, cmk(cs, sn));
+      }
+    }
+    const cplx r = (s1.re != 0.0 || s1.im != 0.0) ? cdiv(s2, s1) : cmk(0.0, 0.0);
+    if (R != nullptr) cst(R + 2 * (size_t)k, r);
+    const cplx re = cmul(r, cld(eloc + 2 * (size_t)k));
+    double s, e;
+    two_sum(n_s, w[k] * re.re, s, e);
+    n_s = s;
+    n_e += e;
+    two_sum(d_s, w[k] * r.re, s, e);
+    d_s = s;
+    d_e += e;
+  }
+  s_v[0][tid] = n_s;
+  s_v[1][tid] = n_e;
+  s_v[2][tid] = d_s;
+  s_v[3][tid] = d_e;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) {
+      double s, e;
+      two_sum(s_v[0][tid], s_v[0][tid + o], s, e);
+      s_v[0][tid] = s;
+      s_v[1][tid] += s_v[1][tid + o] + e;
+      two_sum(s_v[2][tid], s_v[2][tid + o], s, e);
+      s_v[2][tid] = s;
+      s_v[3][tid] += s_v[3][tid + o] + e;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = s_v[0][0] + s_v[1][0];
+    out[1] = s_v[2][0] + s_v[3][0];
   }
 }
 
@@ -242,11 +306,19 @@ hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t st
   return hipGetLastError();
 }
 
-hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y) {
+hipError_t launch_sample_prior(const afqmc_ctx_s* c, int nw, uint64_t seed, double* y, int sweep) {
   const size_t total = (size_t)nw * c->P * c->K;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sample_prior, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     c->stream, nw, c->P, c->K, c->hidden_kind, seed, y);
+                     c->stream, nw, c->P, c->K, c->hidden_kind, seed, sweep, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimator_corrected(const afqmc_ctx_s* c, int nw, int Pr, const double* w,
+                                      const double* eloc, const double* logov,
+                                      const double* logov_ref, double* out, double* R) {
+  hipLaunchKernelGGL(k_estimator_corrected, dim3(1), dim3(256), 0, c->stream, nw, c->P, Pr, w, eloc,
+                     logov, logov_ref, out, R);
   return hipGetLastError();
 }
 

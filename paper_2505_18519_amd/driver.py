@@ -76,3 +76,50 @@ def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
     if n_pc and (i + 1) % n_pc == 0:
         A.afqmc_population_control(ctx, nw, st.phi, st.w, st.y, st.phiT, st.logov, seed, i, w_cap,
                                    normalize=normalize)
+
+
+def init_walkers_metropolis(ctx: A.Context, nw: int, seed: int, n_pair: int = 10,
+                            n_burn: int = 4) -> Walkers:
+    """Walkers sampled from the trial (App. B, Initialization): phi^0_k =
+    B_T(Y_k) phi_T with P paths each and W^0_k = sum_p S_p, so that the mixed
+    estimate at beta = 0 is the Metropolis estimate of the trial's variational
+    energy.  st.yw holds the walker fields Y_k."""
+    st = Walkers(ctx, nw)
+    st.yw = torch.zeros(nw, ctx.K, dtype=torch.float64, device=ctx.device)
+    A.afqmc_init_metropolis(ctx, nw, seed, n_pair, n_burn, st.yw, st.phi, st.y, st.phiT,
+                            st.logov, st.w)
+    return st
+
+
+class Measurement:
+    """Device buffers of a measurement trial with mctx.P paths per walker
+    (Sec. III.A, end of the composite-walker part; App. B, Measurement).
+    mctx is a context of the same system with the measurement's path count."""
+
+    def __init__(self, mctx: A.Context, nw: int):
+        c, z = mctx, dict(device=mctx.device)
+        self.ctx, self.nw = mctx, nw
+        self.y = torch.zeros(nw, c.P, c.K, dtype=torch.float64, **z)
+        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=torch.float64, **z)
+        self.logov = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
+        self.theta = torch.zeros(nw, c.P, 2, c.M, c.N, dtype=torch.complex128, **z)
+        self.eloc = torch.zeros(nw, dtype=torch.complex128, **z)
+        self.R = torch.zeros(nw, dtype=torch.complex128, **z)
+        mctx.reserve(nw)
+
+
+def measure_extra(m: Measurement, st: Walkers, seed: int, i: int, out: torch.Tensor,
+                  n_sweep: int = 4) -> None:
+    """Mixed estimate at step i with a freshly sampled measurement trial: the
+    walkers' paths extended to m.ctx.P, moved n_sweep sweeps at the current
+    walkers (Metropolis streams at step MEASURE_STEP + i), the local energy
+    over the new paths, and each weight times R_k = sum S' / sum S in both
+    sums.  out: device float64 [2] = (sum W Re(R E'_L), sum W Re R).  Leaves
+    the walkers' own paths untouched."""
+    c, nw, P = m.ctx, st.nw, st.y.shape[1]
+    A.afqmc_extend_paths(c, nw, P, st.y, st.phiT, st.logov, m.y, m.phiT, m.logov)
+    A.afqmc_metropolis_x(c, nw, st.phi, m.y, m.phiT, m.logov, None, None, seed,
+                         A.MEASURE_STEP + i, n_sweep)
+    A.afqmc_green(c, nw, st.phi, m.phiT, m.logov, m.theta)
+    A.afqmc_local_energy(c, nw, m.phiT, m.theta, m.logov, m.eloc, None, None)
+    A.afqmc_estimator_corrected(c, nw, st.w, m.eloc, m.logov, P, st.logov, out, m.R)
