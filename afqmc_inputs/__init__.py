@@ -24,6 +24,14 @@ Phi_0 is the N lowest eigenvectors of h1 (columns; sign fixed so that the
 largest-magnitude entry of each column is positive).  This uses one
 eigendecomposition of the input matrix; it is part of choosing the input
 determinant, not a step of the method.
+
+Multi-slice trials (Sec. II.C, Eqs. trial and trial-AF; Sec. III.B): the
+trial determinant is Phi_T(Y) = F_m X_m ... F_1 X_1 F_0 Phi_0 with
+X_l = T_n(i sqrt(s_l) sum_k y_{l,k} A_k) (the propagator's Taylor map) and
+caller-given real one-body factors F_l.  imaginary_time_trial() fills them for
+Psi_T = e^{-m tau_T H} Phi_0: generators A = the vectors L, s_l = tau_T,
+F_0 = F_m = e^{-tau_T h1 / 2} and e^{-tau_T h1} in between (one
+eigendecomposition of h1, again a choice of input, not a step of the method).
 """
 from __future__ import annotations
 
@@ -35,6 +43,8 @@ import numpy as np
 
 HIDDEN_ISING = 0
 HIDDEN_GAUSS = 1
+TRIAL_JASTROW = 0    # Phi_T(y) = exp(c sum_k y_k A_k) Phi_0
+TRIAL_SLICES = 1     # Phi_T(Y) = F_m X_m ... F_1 X_1 F_0 Phi_0 (complex)
 
 
 @dataclasses.dataclass
@@ -50,8 +60,13 @@ class System:
     h1: np.ndarray         # [M, M]
     L: np.ndarray          # [n_chol, M, M]
     phi0: np.ndarray       # [M, N], orthonormal columns
-    A: np.ndarray          # [K, M, M] symmetric trial generators
+    A: np.ndarray          # [K, M, M] symmetric trial generators ([K / m] for slices)
     name: str = ""
+    trial_kind: int = TRIAL_JASTROW
+    n_slices: int = 0                       # m (TRIAL_SLICES); K = m * len(A)
+    slice_s: Optional[np.ndarray] = None    # [m] s_l in X_l = T_n(i sqrt(s_l) sum_k y A_k)
+    slice_F: Optional[np.ndarray] = None    # [m + 1, M, M] one-body factors F_0 .. F_m
+    trial_taylor: int = 10                  # order n of T_n in X_l
 
 
 @dataclasses.dataclass
@@ -206,6 +221,28 @@ def workload(idx: int):
     raise ValueError(f"no workload {idx}")
 
 
+def imaginary_time_trial(sys: System, m: int, tau_T: float, n_gen: Optional[int] = None,
+                         name: str = "") -> System:
+    """The system with the trial Psi_T = e^{-m tau_T H} Phi_0 in multi-slice
+    form (Sec. III.B with t_j = tau_T, H_T^j = H): generators A = the first
+    n_gen vectors L (all by default), s_l = tau_T, F_0 = F_m = e^{-tau_T h1/2},
+    F_l = e^{-tau_T h1} for 0 < l < m (F_0 = e^{-tau_T h1/2} alone if m = 0).
+    Hidden variables are Gaussian, K = m * n_gen."""
+    n_gen = sys.n_chol if n_gen is None else n_gen
+    lam, Q = np.linalg.eigh(sys.h1)
+    half = (Q * np.exp(-0.5 * tau_T * lam)) @ Q.T
+    full = (Q * np.exp(-tau_T * lam)) @ Q.T
+    F = np.empty((m + 1, sys.M, sys.M))
+    F[0] = half
+    for l in range(1, m + 1):
+        F[l] = half if l == m else full
+    return dataclasses.replace(
+        sys, K=m * n_gen, hidden_kind=HIDDEN_GAUSS, coupling=0.0,
+        A=np.ascontiguousarray(sys.L[:n_gen]), trial_kind=TRIAL_SLICES, n_slices=m,
+        slice_s=np.full(m, float(tau_T)), slice_F=np.ascontiguousarray(F),
+        name=name or f"{sys.name}-itime-m{m}")
+
+
 def small_gaussian(M: int = 16, N: int = 4, n_chol: int = 24, K: int = 8,
                    seed: int = 5) -> System:
     """A small Gaussian-hidden system for fast parity tests."""
@@ -247,7 +284,7 @@ def mlp_params(rng: np.random.Generator, M: int, K: int, H: int = MLP_HIDDEN,
 
     W1 [M+K][H], W2 [H][H] ~ N(0, 1/fan_in), zero biases; the output layer
     W3 [H][2K] ~ N(0, last_scale^2 / H) and b3 = 0.  last_scale = 0 makes the
-    network's first proposals exactly the prior N(0, 1).
+    network's first proposals the random walk of step sqrt(2).
     """
     D = M + K
     p = {

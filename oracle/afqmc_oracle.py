@@ -73,13 +73,43 @@ def half_kinetic(sys, dtau: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Sampled trial determinant (Eq. trial_decomp / Metropolis_sampled_trial)
 
+TRIAL_JASTROW = 0
+TRIAL_SLICES = 1
+
+
 def trial_det(sys, y: np.ndarray) -> np.ndarray:
-    """Phi_T(y) = exp(c sum_k y_k A_k) Phi_0 for y [..., K] -> [..., M, N] float."""
+    """Phi_T(y) = exp(c sum_k y_k A_k) Phi_0 for y [..., K] -> [..., M, N] float,
+    or the multi-slice determinant (trial_det_slices, complex)."""
+    if getattr(sys, "trial_kind", TRIAL_JASTROW) == TRIAL_SLICES:
+        return trial_det_slices(sys, y)
     y = np.asarray(y, dtype=np.float64)
     U = sys.coupling * np.einsum("...k,kij->...ij", y, sys.A)
     lam, Q = np.linalg.eigh(U)
     QtPhi = np.swapaxes(Q, -1, -2) @ sys.phi0
     return (Q * np.exp(lam)[..., None, :]) @ QtPhi
+
+
+def trial_det_slices(sys, y: np.ndarray) -> np.ndarray:
+    """Multi-slice trial determinant (Sec. II.C, Eqs. trial and trial-AF;
+    Sec. III.B; the single-slice VAFQMC form of Eq. VAFQMC is m = 1):
+    the bra <phi_T| prod_l B_T^l(y^l) overlaps a walker as det(Phi_T(Y)^T phi)
+    with Phi_T(Y) = F_m X_m ... F_1 X_1 F_0 Phi_0, where
+    X_l = T_n(i sqrt(s_l) sum_k y_{l,k} A_k) is the same n-term Taylor map as
+    the walker propagator and F_l are the trial's real one-body factors.
+    y [..., m * K_gen] -> [..., M, N] complex; m = 0 gives F_0 Phi_0."""
+    y = np.asarray(y, dtype=np.float64)
+    lead = y.shape[:-1]
+    m = sys.n_slices
+    kg = sys.A.shape[0]
+    yy = y.reshape(-1, m, kg) if m > 0 else np.zeros((int(np.prod(lead)), 0, kg))
+    n = yy.shape[0]
+    X0 = (sys.slice_F[0] @ sys.phi0).astype(np.complex128)
+    X = np.broadcast_to(X0, (n, sys.M, sys.N)).copy()
+    for l in range(m):
+        V = 1j * math.sqrt(sys.slice_s[l]) * np.einsum("nk,kij->nij", yy[:, l], sys.A)
+        X = taylor_apply(V, X, sys.trial_taylor)
+        X = np.einsum("ij,njk->nik", sys.slice_F[l + 1], X)
+    return X.reshape(*lead, sys.M, sys.N)
 
 
 # ---------------------------------------------------------------------------
@@ -409,6 +439,9 @@ def init_metropolis(sys, nw, P, seed, n_pair, n_burn, proposal=PROPOSAL_PRIOR, r
     the chains use the Metropolis streams at steps INIT_STEP + 2j (partner)
     and INIT_STEP + 2j + 1 (walker field), and INIT_STEP + 2 n_pair for the
     paths' sweeps.  Returns (State, yw [nw, K])."""
+    if getattr(sys, "trial_kind", TRIAL_JASTROW) != TRIAL_JASTROW:
+        raise NotImplementedError("the walker B_T(Y) phi_T is built for the real symmetric "
+                                  "trial family only")
     K, kind = sys.K, sys.hidden_kind
     ya = philox.init_hidden(seed, nw, 1, K, kind, sweep=1)
     yb = philox.init_hidden(seed, nw, 1, K, kind, sweep=2)
