@@ -81,6 +81,19 @@ enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1, AFQMC_PROPOSAL_LEARNED =
  * the sums over g and every other step of the path stay FP64. */
 enum { AFQMC_PREC_FP64 = 0, AFQMC_PREC_FP32 = 1, AFQMC_PREC_BF16 = 2 /* network only */ };
 
+/* Trial families (Sec. II.C, Eqs. trial, trial-AF and trial_decomp):
+ * JASTROW: Phi_T(y) = exp(c sum_k y_k A_k) Phi_0, real;
+ * SLICES:  Phi_T(Y) = F_m X_m ... F_1 X_1 F_0 Phi_0 with Y = (y_1 .. y_m),
+ *          X_l = T_n(i sqrt(s_l) sum_k y_{l,k} A_k) (n = trial_taylor, the
+ *          Taylor map of the propagator) and real one-body factors F_l: the
+ *          imaginary-time-evolved trial e^{-m tau_T H} Phi_0 of Sec. III.B and
+ *          the VAFQMC form of Eq. VAFQMC.  Complex: every phiT argument of a
+ *          SLICES context is interleaved complex [..][M][N][2], the overlaps
+ *          stay the bilinear det(Phi_T^T phi).  SLICES needs Gaussian hidden
+ *          variables, a non-learned proposal and (ceil(M/16)) (ceil(N/16)) <= 8,
+ *          and uses the workgroup-per-path kernels at every size. */
+enum { AFQMC_TRIAL_JASTROW = 0, AFQMC_TRIAL_SLICES = 1 };
+
 typedef struct {
   int32_t M;            /* one-particle basis size                         */
   int32_t N;            /* electrons per spin (n_up = n_dn)                */
@@ -92,7 +105,7 @@ typedef struct {
   const double* h1;     /* HOST [M][M], symmetric                           */
   const double* L;      /* HOST [n_chol][M][M], each symmetric              */
   const double* phi0;   /* HOST [M][N]                                      */
-  const double* A;      /* HOST [K][M][M], each symmetric                   */
+  const double* A;      /* HOST [K][M][M] each symmetric ([K/m] for SLICES)  */
   double dtau;          /* time step tau                                    */
   int32_t n_taylor;     /* Taylor order of exp(V) in the propagator (>= 1)  */
   int32_t weight_mode;  /* AFQMC_WEIGHT_*                                    */
@@ -101,6 +114,11 @@ typedef struct {
   int32_t precision;    /* AFQMC_PREC_*                                      */
   double xbar_cap;      /* > 0: clip |xbar_g| to xbar_cap, phase kept (a common
                            AFQMC stabilisation the paper does not use); 0: off */
+  int32_t trial_kind;   /* AFQMC_TRIAL_* (0: JASTROW)                        */
+  int32_t n_slices;     /* SLICES: m >= 1; K = m * (generators in A)         */
+  const double* slice_s;  /* SLICES: HOST [m], s_l >= 0                      */
+  const double* slice_F;  /* SLICES: HOST [m+1][M][M], F_0 .. F_m             */
+  int32_t trial_taylor; /* SLICES: Taylor order n of X_l (>= 1)              */
 } afqmc_system;
 
 /* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and
@@ -127,7 +145,8 @@ afqmc_status afqmc_set_workspace(afqmc_ctx ctx, void* dptr, size_t bytes);
 afqmc_status afqmc_sample_prior(afqmc_ctx ctx, int32_t nw, uint64_t seed, double* y);
 
 /* Phi_T(y_p) = exp(c sum_k y_k A_k) Phi_0 for every path (Sec. II.C, Eq.
- * trial_decomp; Sec. III.A, Eq. Metropolis_sampled_trial).  y -> phiT. */
+ * trial_decomp; Sec. III.A, Eq. Metropolis_sampled_trial), or the multi-slice
+ * product of a SLICES context (complex phiT).  y -> phiT. */
 afqmc_status afqmc_trial_build(afqmc_ctx ctx, int32_t nw, const double* y, double* phiT);
 
 /* l_p = sum_s log det(Phi_T(y_p)^T phi^s) with partial-pivoting LU (the

@@ -24,6 +24,7 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 MLP_HIDDEN = 256
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 INIT_STEP, MEASURE_STEP = 1 << 63, 1 << 62     # AFQMC_INIT_STEP, AFQMC_MEASURE_STEP
+TRIAL_JASTROW, TRIAL_SLICES = 0, 1
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
           5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
@@ -44,6 +45,8 @@ class afqmc_system(ctypes.Structure):
         ("dtau", c_double), ("n_taylor", c_int32), ("weight_mode", c_int32),
         ("proposal", c_int32), ("rw_step", c_double), ("precision", c_int32),
         ("xbar_cap", c_double),
+        ("trial_kind", c_int32), ("n_slices", c_int32), ("slice_s", POINTER(c_double)),
+        ("slice_F", POINTER(c_double)), ("trial_taylor", c_int32),
     ]
 
 
@@ -166,6 +169,14 @@ def system_struct(system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
                       int(system.hidden_kind), float(system.coupling), dp(host[0]), dp(host[1]),
                       dp(host[2]), dp(host[3]), float(dtau), int(n_taylor), int(weight_mode),
                       int(proposal), float(rw_step), int(precision), float(xbar_cap))
+    kind = int(getattr(system, "trial_kind", TRIAL_JASTROW))
+    if kind == TRIAL_SLICES:
+        s_arr = np.ascontiguousarray(system.slice_s, dtype=np.float64)
+        f_arr = np.ascontiguousarray(system.slice_F, dtype=np.float64)
+        host += [s_arr, f_arr]
+        st.trial_kind, st.n_slices = kind, int(system.n_slices)
+        st.slice_s, st.slice_F = dp(s_arr), dp(f_arr)
+        st.trial_taylor = int(system.trial_taylor)
     return st, host
 
 
@@ -185,6 +196,9 @@ class Context:
                                                   int(system.n_chol), int(system.K), int(P))
         self.sys, self._host = system_struct(system, P, dtau, n_taylor, weight_mode, proposal,
                                              rw_step, xbar_cap, precision)
+        # element type of trial determinants: complex for multi-slice trials
+        self.ctrial = int(getattr(system, "trial_kind", TRIAL_JASTROW)) == TRIAL_SLICES
+        self.tdtype = torch.complex128 if self.ctrial else torch.float64
         self.dtau = float(dtau)
         self.device = torch.device("cuda", device)
         self.handle = c_void_p()
@@ -237,20 +251,20 @@ def afqmc_sample_prior(ctx, nw, seed, y):
 def afqmc_trial_build(ctx, nw, y, phiT):
     ctx.reserve(nw)
     ctx._call("afqmc_trial_build", nw, _ptr(y, torch.float64, nw * ctx.P * ctx.K, "y"),
-              _ptr(phiT, torch.float64, nw * ctx.P * ctx.M * ctx.N, "phiT"))
+              _ptr(phiT, ctx.tdtype, nw * ctx.P * ctx.M * ctx.N, "phiT"))
 
 
 def afqmc_overlap(ctx, nw, phi, phiT, logov):
     c = ctx
     c._call("afqmc_overlap", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"))
 
 
 def afqmc_green(ctx, nw, phi, phiT, logov, theta):
     c = ctx
     c._call("afqmc_green", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"))
 
@@ -258,7 +272,7 @@ def afqmc_green(ctx, nw, phi, phiT, logov, theta):
 def afqmc_force_bias(ctx, nw, phiT, theta, logov, xbar, vb_sample=None):
     c = ctx
     c.reserve(nw)
-    c._call("afqmc_force_bias", nw, _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+    c._call("afqmc_force_bias", nw, _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
@@ -268,7 +282,7 @@ def afqmc_force_bias(ctx, nw, phiT, theta, logov, xbar, vb_sample=None):
 def afqmc_local_energy(ctx, nw, phiT, theta, logov, eloc, e_sample=None, xbar=None):
     c = ctx
     c.reserve(nw)
-    c._call("afqmc_local_energy", nw, _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+    c._call("afqmc_local_energy", nw, _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(eloc, torch.complex128, nw, "eloc"),
@@ -282,7 +296,7 @@ def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_
     c._call("afqmc_propagate", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
             _ptr(xi, torch.float64, nw * c.G, "xi"),
             _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(eloc, torch.complex128, nw, "eloc", allow_none=True), float(e_shift),
             _ptr(w, torch.float64, nw, "w"), _ptr(ref, torch.complex128, nw, "ref"),
@@ -294,7 +308,7 @@ def afqmc_metropolis_x(ctx, nw, phi, y, phiT, logov, ref, w, seed, step, n_sweep
     c.reserve(nw)
     c._call("afqmc_metropolis_x", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(ref, torch.complex128, nw, "ref", allow_none=w is None),
             _ptr(w, torch.float64, nw, "w", allow_none=True),
@@ -315,7 +329,7 @@ def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=
     c._call("afqmc_population_control", nw,
             _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"), _ptr(w, torch.float64, nw, "w"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"), int(seed), int(step), float(w_cap),
             1 if normalize else 0, _ptr(parent, torch.int32, nw, "parent", allow_none=True))
 
@@ -332,7 +346,7 @@ def afqmc_init_metropolis(ctx, nw, seed, n_pair, n_burn, yw, phi, y, phiT, logov
             _ptr(yw, torch.float64, nw * c.K, "yw"),
             _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"), _ptr(w, torch.float64, nw, "w"))
 
 
@@ -340,10 +354,10 @@ def afqmc_extend_paths(ctx, nw, p_src, y_src, phiT_src, logov_src, y, phiT, logo
     c = ctx
     c._call("afqmc_extend_paths", nw, int(p_src),
             _ptr(y_src, torch.float64, nw * p_src * c.K, "y_src"),
-            _ptr(phiT_src, torch.float64, nw * p_src * c.M * c.N, "phiT_src"),
+            _ptr(phiT_src, ctx.tdtype, nw * p_src * c.M * c.N, "phiT_src"),
             _ptr(logov_src, torch.complex128, nw * p_src, "logov_src"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"))
 
 
@@ -365,7 +379,7 @@ def afqmc_philox_normal(ctx, seed, step, tag, nw, n, out):
 def afqmc_green_diag(ctx, nw, phi, phiT, logov, gdiag):
     c = ctx
     c._call("afqmc_green_diag", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
-            _ptr(phiT, torch.float64, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(gdiag, torch.float64, nw * c.P * c.M, "gdiag"))
 

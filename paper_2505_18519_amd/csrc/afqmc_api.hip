@@ -34,8 +34,8 @@ hipError_t dev_copy(T** dst, const T* src, size_t n) {
 void free_ctx(afqmc_ctx_s* c) {
   auto& m = c->mlp;
   void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A, c->d_Lpad32,
-                  m.master, m.mom1,   m.mom2,   m.w1t,  m.w2t,    m.w3t, m.w2c,
-                  m.w3c,    m.tstep,  m.scal};
+                  c->d_F,  c->d_phi0c, m.master, m.mom1, m.mom2, m.w1t, m.w2t, m.w3t, m.w2c,
+                  m.w3c,   m.tstep,    m.scal};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -107,14 +107,14 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   off += align256(S * 16);
   L.vmat = off;
   off += align256((size_t)nw * c->M * c->M * 16);
-  L.ubuf = off;
-  off += align256(S * c->M * c->M * 8);
+  L.ubuf = off;  // trial generator sums U (real) or slice matrices V (complex)
+  off += align256(S * c->M * c->M * (c->ctrial ? 16 : 8));
   L.qrshift = off;
   off += align256((size_t)nw * 2 * 8);
   L.ytry = off;
   off += align256(S * c->K * 8);
   L.phiTtry = off;
-  off += align256(S * c->M * c->N * 8);
+  off += align256(S * c->tsz * 8);
   L.ltry = off;
   off += align256(S * 16);
   L.acc = off;
@@ -130,7 +130,7 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   L.pc_y = off;
   off += align256(S * c->K * 8);
   L.pc_phiT = off;
-  off += align256(S * c->M * c->N * 8);
+  off += align256(S * c->tsz * 8);
   L.pc_logov = off;
   off += align256(S * 16);
   // learned proposal: sizes for 4-byte product elements (BF16 uses half)
@@ -213,6 +213,19 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     return AFQMC_E_UNSUPPORTED;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
   if (!(sys->xbar_cap >= 0.0)) return AFQMC_E_INVALID;
+  const bool slices = sys->trial_kind == AFQMC_TRIAL_SLICES;
+  if (sys->trial_kind != AFQMC_TRIAL_JASTROW && !slices) return AFQMC_E_INVALID;
+  if (slices) {
+    const int m = sys->n_slices;
+    if (m < 1 || K % m != 0 || sys->slice_s == nullptr || sys->slice_F == nullptr ||
+        sys->trial_taylor < 1 || sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
+      return AFQMC_E_INVALID;
+    for (int l = 0; l < m; ++l)
+      if (!(sys->slice_s[l] >= 0.0) || !isfinite(sys->slice_s[l])) return AFQMC_E_INVALID;
+    if (sys->proposal == AFQMC_PROPOSAL_LEARNED) return AFQMC_E_UNSUPPORTED;
+    // complex stage-1 operands of the contraction: (M/16) ceil(N/16) <= 8
+    if (((M + 15) / 16) * ((N + 15) / 16) > 8) return AFQMC_E_UNSUPPORTED;
+  }
 
   afqmc_ctx_s* c = new (std::nothrow) afqmc_ctx_s();
   if (c == nullptr) return AFQMC_E_NOMEM;
@@ -224,7 +237,16 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   c->K = K;
   c->P = P;
   c->MT = ((M + 15) / 16) * 16;
-  c->small = (M <= 64 && N <= 16);
+  c->small = (M <= 64 && N <= 16) && !slices;
+  c->trial_kind = sys->trial_kind;
+  c->ctrial = slices;
+  c->tsz = M * N * (slices ? 2 : 1);
+  if (slices) {
+    c->n_slices = sys->n_slices;
+    c->kgen = K / sys->n_slices;
+    c->trial_taylor = sys->trial_taylor;
+    c->slice_s.assign(sys->slice_s, sys->slice_s + sys->n_slices);
+  }
   c->hidden_kind = sys->hidden_kind;
   c->coupling = sys->coupling;
   c->dtau = sys->dtau;
@@ -251,11 +273,21 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
       (e = dev_copy(&c->d_Lraw, sys->L, (size_t)G * M * M)) != hipSuccess ||
       (e = dev_copy(&c->d_Lpad, Lpad.data(), Lpad.size())) != hipSuccess ||
       (e = dev_copy(&c->d_phi0, sys->phi0, (size_t)M * N)) != hipSuccess ||
-      (e = dev_copy(&c->d_A, sys->A, (size_t)K * M * M)) != hipSuccess ||
+      (e = dev_copy(&c->d_A, sys->A, (size_t)(slices ? c->kgen : K) * M * M)) != hipSuccess ||
       (e = hipMalloc(&c->d_Eh, (size_t)M * M * sizeof(double))) != hipSuccess) {
     free_ctx(c);
     delete c;
     return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
+  }
+  if (slices) {  // one-body factors and Phi_0 as the complex input of the first slice
+    std::vector<double> p0c((size_t)M * N * 2, 0.0);
+    for (size_t q = 0; q < (size_t)M * N; ++q) p0c[2 * q] = sys->phi0[q];
+    if ((e = dev_copy(&c->d_F, sys->slice_F, (size_t)(sys->n_slices + 1) * M * M)) != hipSuccess ||
+        (e = dev_copy(&c->d_phi0c, p0c.data(), p0c.size())) != hipSuccess) {
+      free_ctx(c);
+      delete c;
+      return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
+    }
   }
   if ((e = launch_setup(c)) == hipSuccess && c->precision == AFQMC_PREC_FP32) {
     const size_t n = Lpad.size();
@@ -551,6 +583,9 @@ afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32
                                    void* logov, double* w) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);
+  if (c->ctrial)
+    return fail(c, AFQMC_E_UNSUPPORTED,
+                "initialisation from the trial needs the real symmetric trial family");
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, yw, "yw");
   REQUIRE(c, phi, "phi");
@@ -694,7 +729,7 @@ afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double
     size_t off, row;
   } parts[4] = {{static_cast<double*>(phi), L.pc_phi, (size_t)2 * c->M * c->N * 2},
                 {y, L.pc_y, S * c->K},
-                {phiT, L.pc_phiT, S * c->M * c->N},
+                {phiT, L.pc_phiT, S * c->tsz},
                 {static_cast<double*>(logov), L.pc_logov, S * 2}};
   for (auto& pt : parts) {
     double* tmp = ws_ptr<double>(c, pt.off);
@@ -854,6 +889,8 @@ afqmc_status afqmc_green_diag(afqmc_ctx c, int32_t nw, const void* phi, const do
                               void* logov, double* gdiag) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);
+  if (c->ctrial)
+    return fail(c, AFQMC_E_UNSUPPORTED, "the Green's-function diagonal needs a real trial");
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, phi, "phi");
   REQUIRE(c, phiT, "phiT");

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/afqmc.h"
 
@@ -26,6 +27,15 @@ struct afqmc_ctx_s {
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
+
+  // trial family (AFQMC_TRIAL_*); multi-slice trials have complex Phi_T and
+  // always run on the workgroup-per-path kernels
+  int trial_kind = 0, n_slices = 0, kgen = 0, trial_taylor = 10;
+  bool ctrial = false;
+  int tsz = 0;                  // doubles per trial determinant: M N, or 2 M N if complex
+  std::vector<double> slice_s;  // s_l of X_l = T_n(i sqrt(s_l) sum_k y_{l,k} A_k)
+  double* d_F = nullptr;        // [m+1][M][M] one-body factors F_l
+  double* d_phi0c = nullptr;    // [M][N] complex copy of Phi_0
 
   // Device-resident step counter (set by a batch whose step sequence is a
   // replayed graph): the kernels that take a step index read *dstep instead,
@@ -132,6 +142,17 @@ hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, con
 hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                              const double* logov, double* vb, double* ep);
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
+// dst = El T_n(V) Er src for n blocks of `spins` M x N complex matrices (Er may be
+// null); src block (w, sp) at (w * src_ws + sp) M N
+hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
+                               const double* vmat, const double* El, const double* Er,
+                               const double* src, int src_ws, double* dst);
+// vmat[w] = i sqrt_s sum_k y[w * xs + k] Lgen_k  (k < G)
+hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
+                             const double* Lgen, const double* y, double* vmat);
+// multi-slice trial determinants Phi_T(Y) for n paths; vbuf holds n complex M x M
+hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, double* phiT,
+                               double* vbuf);
 hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift);
 hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
 hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,

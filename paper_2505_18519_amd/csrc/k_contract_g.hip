@@ -16,6 +16,11 @@
 // for tr(f f).  In the FP32 form Phi_T, Theta and L enter the products as
 // FP32 with FP32 accumulation over m; per-vector traces, vb_g^2 and the sums
 // over g are carried in FP64.
+//
+// CT (complex trial determinants of multi-slice trials): stage 1 runs on the
+// real M x 2N matrix [Re Phi_T | Im Phi_T], giving Y_a = Re Phi_T^T L_g and
+// Y_b = Im Phi_T^T L_g as extra column tiles that share every L operand; stage
+// 2 forms Y_a Theta and Y_b Theta and combines f = Y_a Theta + i Y_b Theta.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -47,7 +52,7 @@ struct mm<float> {
   __device__ static int row(int g, int r) { return 4 * g + r; }
 };
 
-template <typename T, int KT, int NTC>
+template <typename T, int KT, int NTC, bool CT>
 __global__ void __launch_bounds__(128 * NTC)
 k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ Lpad,
              const double* __restrict__ phiT, const double* __restrict__ theta,
@@ -57,6 +62,8 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
   constexpr int KTMAX = KT;
   constexpr int NWV = 2 * NTC;             // wavefronts
   constexpr int NT = 16 * NTC;
+  constexpr int NTC2 = CT ? 2 * NTC : NTC;     // stage-1 column tiles (re and im parts)
+  constexpr int NT2 = 16 * NTC2;
   constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
   constexpr int NS = S1MAX * KT;               // stage-1 (row tile, k tile) steps
   // L operand ring: loads run RING - 1 steps ahead; a depth that divides NS
@@ -64,8 +71,8 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
   // registers whose loads are still in flight)
   constexpr int RING = (NS % 4 == 0) ? 4 : (NS % 3 == 0) ? 3 : 2;
   extern __shared__ double smem[];
-  T* sY = reinterpret_cast<T*>(smem);                        // [MT][NT]
-  double* sF = smem + (MT * NT * sizeof(T) + 7) / 8;          // [2][NT][NT+1][2]
+  T* sY = reinterpret_cast<T*>(smem);                        // [MT][NT2]
+  double* sF = smem + (MT * NT2 * sizeof(T) + 7) / 8;         // [2][NT][NT+1][2]
   double* sD = sF + 2 * NT * (NT + 1) * 2;                    // [16][NWV*16][2]
 
   const int s = blockIdx.x;
@@ -76,7 +83,7 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
   const bool active = !__builtin_isinf(logov[2 * s]);
 
   // Phi_T B operands for stage 1 (all column tiles), Theta^sp[:, jt] for stage 2
-  T bT[NTC][KTMAX][4];
+  T bT[NTC2][KTMAX][4];
   T th[2][KTMAX][4];
 #pragma unroll
   for (int t = 0; t < KTMAX; ++t)
@@ -85,9 +92,10 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
       const int m = 16 * t + 4 * r + g;
       const bool okm = active && m < M;
 #pragma unroll
-      for (int ct = 0; ct < NTC; ++ct) {
-        const int n = 16 * ct + c;
-        bT[ct][t][r] = (okm && n < N) ? (T)phiT[((size_t)s * M + m) * N + n] : (T)0;
+      for (int ct = 0; ct < NTC2; ++ct) {
+        const int n = 16 * (ct % NTC) + c, part = ct / NTC;
+        const size_t e = ((size_t)s * M + m) * N + n;
+        bT[ct][t][r] = (okm && n < N) ? (T)(CT ? phiT[2 * e + part] : phiT[e]) : (T)0;
       }
       const int n = 16 * jt + c;
       const double* src = theta + ((((size_t)s * 2 + sp) * M + m) * N + n) * 2;
@@ -116,11 +124,11 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
     const T* Ln = Lpad + (size_t)min(gam + 1, G) * slab;
     // stage 1: Y^T tiles (tp, ct), one software pipeline over all steps; the
     // first RING - 1 steps of the next vector are issued at the end
-    acc_t y1[S1MAX][NTC];
+    acc_t y1[S1MAX][NTC2];
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q)
 #pragma unroll
-      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = MM::zero();
+      for (int ct = 0; ct < NTC2; ++ct) y1[q][ct] = MM::zero();
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const int q = k / KT, t = k % KT;
@@ -136,7 +144,7 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int ct = 0; ct < NTC; ++ct)
+          for (int ct = 0; ct < NTC2; ++ct)
             y1[q][ct] = MM::fma(av[k % RING][r], bT[ct][t][r], y1[q][ct]);
     }
     // the ring now holds the next vector's first steps at slots NS % RING ...;
@@ -158,15 +166,15 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
       const int tp = wave + NWV * q;
       if (tp < KT)
 #pragma unroll
-        for (int ct = 0; ct < NTC; ++ct)
+        for (int ct = 0; ct < NTC2; ++ct)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sY[(16 * tp + MM::row(g, r)) * NT + 16 * ct + c] = y1[q][ct][r];
+          for (int r = 0; r < 4; ++r) sY[(16 * tp + MM::row(g, r)) * NT2 + 16 * ct + c] = y1[q][ct][r];
     }
     __syncthreads();
     // stage 2: f^sp[it][jt] = sum_m Y^T[m][it cols] Theta^sp[m][jt cols]
-    acc_t f[NTC][2];
+    acc_t f[NTC2][2];
 #pragma unroll
-    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = MM::zero();
+    for (int it = 0; it < NTC2; ++it) f[it][0] = f[it][1] = MM::zero();
     if (active) {
 #pragma unroll
       for (int t = 0; t < KTMAX; ++t) {
@@ -175,13 +183,22 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
           for (int r = 0; r < 4; ++r) {
             const int m = 16 * t + 4 * r + g;
 #pragma unroll
-            for (int it = 0; it < NTC; ++it) {
-              const T a = sY[m * NT + 16 * it + c];
+            for (int it = 0; it < NTC2; ++it) {
+              const T a = sY[m * NT2 + 16 * it + c];
               f[it][0] = MM::fma(a, th[0][t][r], f[it][0]);
               f[it][1] = MM::fma(a, th[1][t][r], f[it][1]);
             }
           }
         }
+      }
+    }
+    if (CT) {  // f = Y_a Theta + i Y_b Theta
+#pragma unroll
+      for (int it = 0; it < NTC; ++it) {
+        const acc_t fr = f[it][0] - f[it + NTC * (CT ? 1 : 0)][1];
+        const acc_t fi = f[it][1] + f[it + NTC * (CT ? 1 : 0)][0];
+        f[it][0] = fr;
+        f[it][1] = fi;
       }
     }
     // diagonal of f^sp in tile (jt, jt): element (row(g,r), c) with row == c
@@ -285,20 +302,20 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
     for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-size_t lds_bytes(int MT, int NTC, size_t tsize) {
+size_t lds_bytes(int MT, int NTC, size_t tsize, bool ct) {
   const int NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = ((size_t)MT * NT * tsize + 7) / 8 * 8;
+  size_t b = ((size_t)MT * NT * (ct ? 2 : 1) * tsize + 7) / 8 * 8;
   b += (size_t)2 * NT * (NT + 1) * 2 * 8;
   b += (size_t)16 * NWV * 16 * 2 * 8;
   return b;
 }
 
-template <typename T, int KT, int NTC>
+template <typename T, int KT, int NTC, bool CT>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
                     const double* theta, const double* logov, double* vb, double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes(c->MT, NTC, sizeof(T));
-  auto kern = k_contract_g<T, KT, NTC>;
+  const size_t lds = lds_bytes(c->MT, NTC, sizeof(T), CT);
+  auto kern = k_contract_g<T, KT, NTC, CT>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -311,8 +328,17 @@ template <typename T>
 hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
                     const double* theta, const double* logov, double* vb, double* ep) {
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+  if (c->ctrial) {  // complex trials: KT * NTC <= 8 (register budget of the doubled B operands)
+#define AFQMC_GC(KK, NC)                                                                  \
+  if (KT == KK && NTC == NC) return launch_g<T, KK, NC, true>(c, nw, L, phiT, theta, logov, vb, ep);
+    AFQMC_GC(1, 1) AFQMC_GC(2, 1) AFQMC_GC(3, 1) AFQMC_GC(4, 1)
+    AFQMC_GC(5, 1) AFQMC_GC(6, 1) AFQMC_GC(7, 1) AFQMC_GC(8, 1)
+    AFQMC_GC(2, 2) AFQMC_GC(3, 2) AFQMC_GC(4, 2)
+#undef AFQMC_GC
+    return hipErrorInvalidValue;
+  }
 #define AFQMC_G(KK, NC)                                                            \
-  if (KT == KK && NTC == NC) return launch_g<T, KK, NC>(c, nw, L, phiT, theta, logov, vb, ep);
+  if (KT == KK && NTC == NC) return launch_g<T, KK, NC, false>(c, nw, L, phiT, theta, logov, vb, ep);
   AFQMC_G(1, 1) AFQMC_G(2, 1) AFQMC_G(3, 1) AFQMC_G(4, 1)
   AFQMC_G(5, 1) AFQMC_G(6, 1) AFQMC_G(7, 1) AFQMC_G(8, 1)
   AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)

@@ -35,7 +35,7 @@ __global__ void k_sign_sum(int nw, int P, const double* __restrict__ logov,
 }
 
 // Path q of walker w (of Pd) copies path q mod Ps (of Ps): one workgroup per
-// destination path, threads over the M x N trial determinant.
+// destination path, threads over the MN doubles of its trial determinant.
 __global__ void __launch_bounds__(256)
 k_extend_paths(int Ps, int Pd, int K, int MN, const double* __restrict__ ys,
                const double* __restrict__ ps, const double* __restrict__ ls,
@@ -70,6 +70,6 @@ hipError_t launch_extend_paths(const afqmc_ctx_s* c, int nw, int Ps, int Pd, con
                                double* ld) {
   if (nw <= 0 || Pd <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_extend_paths, dim3((unsigned)((size_t)nw * Pd)), dim3(256), 0, c->stream,
-                     Ps, Pd, c->K, c->M * c->N, ys, ps, ls, yd, pd, ld);
+                     Ps, Pd, c->K, c->tsz, ys, ps, ls, yd, pd, ld);
   return hipGetLastError();
 }

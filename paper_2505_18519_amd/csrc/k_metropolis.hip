@@ -149,7 +149,7 @@ hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, 
                          uint64_t seed, uint64_t step, int sweep, int flip_k, int proposal,
                          const double* lextra, double* gd_cur, const double* gd_try, int* mask) {
   if (nw <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->M * c->N,
+  hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->tsz,
                      c->hidden_kind, proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
                      step, c->dstep, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
   return hipGetLastError();

@@ -8,12 +8,15 @@
 //  3. optionally Theta^s = phi^s (A^s)^{-1}, lanes over orbital rows m, and
 //     the Green's function diagonal Re (G_up + G_dn)_mm.
 // The two spins' log-determinants and diagonals are added through LDS.
+// CT: complex trial determinants (multi-slice trials), A^s = Phi_T^T phi^s
+// with both factors complex (no conjugation: the bilinear overlap of Eq.
+// ratio-update-phi); the Green's-function diagonal is then not formed.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
 namespace {
 
-template <int NTC>
+template <int NTC, bool CT>
 __global__ void __launch_bounds__(128)
 k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
             const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta,
@@ -30,7 +33,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   const int g = lane >> 4, c = lane & 15;
   if (s >= n_samples) return;  // whole block
   const int w = s / P;
-  const double* pT = phiT + (size_t)s * M * N;
+  const double* pT = phiT + (size_t)s * M * N * (CT ? 2 : 1);
   const double* pw = phi + ((size_t)w * 2 + sp) * M * N * 2;
 
   // 1. A^sp tiles (it, jt): A[i][j] = sum_m Phi_T[m][i] phi[m][j]
@@ -42,12 +45,18 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   for (int q = 0; q < (M + 3) / 4; ++q) {
     const int m = 4 * q + g;
     const bool okm = m < M;
-    double a[NTC], br[NTC], bi[NTC];
+    double a[NTC], ai[NTC], br[NTC], bi[NTC];
 #pragma unroll
     for (int t = 0; t < NTC; ++t) {
       const int n = 16 * t + c;
       const bool ok = okm && n < N;
-      a[t] = ok ? pT[m * N + n] : 0.0;
+      if (CT) {
+        a[t] = ok ? pT[((size_t)m * N + n) * 2] : 0.0;
+        ai[t] = ok ? pT[((size_t)m * N + n) * 2 + 1] : 0.0;
+      } else {
+        a[t] = ok ? pT[m * N + n] : 0.0;
+        ai[t] = 0.0;
+      }
       br[t] = ok ? pw[((size_t)m * N + n) * 2] : 0.0;
       bi[t] = ok ? pw[((size_t)m * N + n) * 2 + 1] : 0.0;
     }
@@ -57,6 +66,10 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       for (int jt = 0; jt < NTC; ++jt) {
         acc[it][jt][0] = mfma_f64(a[it], br[jt], acc[it][jt][0]);
         acc[it][jt][1] = mfma_f64(a[it], bi[jt], acc[it][jt][1]);
+        if (CT) {
+          acc[it][jt][0] = mfma_f64(-ai[it], bi[jt], acc[it][jt][0]);
+          acc[it][jt][1] = mfma_f64(ai[it], br[jt], acc[it][jt][1]);
+        }
       }
   }
 #pragma unroll
@@ -202,7 +215,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
             dst[2 * col] = x[k].re;
             dst[2 * col + 1] = x[k].im;
           }
-          gsum = fma(x[k].re, pT[m * N + col], gsum);
+          if (!CT) gsum = fma(x[k].re, pT[m * N + col], gsum);
         }
       if (sp == 1) s_gd[m] = gsum;
     }
@@ -217,8 +230,14 @@ template <int NTC>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
                     double* logov, double* theta, double* gdiag) {
   const int n = nw * c->P;
-  hipLaunchKernelGGL(k_overlap_g<NTC>, dim3(n), dim3(128), 0, c->stream, n, c->P, c->M, c->N, phi,
-                     phiT, logov, theta, gdiag);
+  if (c->ctrial) {
+    if (gdiag != nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_overlap_g<NTC, true>), dim3(n), dim3(128), 0, c->stream, n, c->P, c->M,
+                       c->N, phi, phiT, logov, theta, gdiag);
+  } else {
+    hipLaunchKernelGGL((k_overlap_g<NTC, false>), dim3(n), dim3(128), 0, c->stream, n, c->P, c->M,
+                       c->N, phi, phiT, logov, theta, gdiag);
+  }
   return hipGetLastError();
 }
 

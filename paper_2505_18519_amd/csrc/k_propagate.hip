@@ -18,9 +18,11 @@ namespace {
 // V build: with c = xi - xbar, R = sum_g Re(c_g) L_g and Q = sum_g Im(c_g) L_g,
 // V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the FP64
 // matrix cores: each wavefront takes 16 walkers (both Re c and Im c as A
-// operands) and 64 matrix entries; L is read once per 16 walkers.
+// operands) and 64 matrix entries; L is read once per 16 walkers.  Row w of
+// xi starts at w * xs; xbar may be null (c = xi): the trial slices use this
+// with the generators A_k and their block of y.
 __global__ void __launch_bounds__(256)
-k_vbuild(int nw, int G, int MM, double sqrt_tau, const double* __restrict__ L,
+k_vbuild(int nw, int G, int MM, int xs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
@@ -49,8 +51,9 @@ k_vbuild(int nw, int G, int MM, double sqrt_tau, const double* __restrict__ L,
       const int k = k0 + 4 * q + g;
       const int kc = min(k, G - 1);
       const bool ok = wok && k < G;
-      const double x = xi[(size_t)wa * G + kc];
-      const double br = xbar[((size_t)wa * G + kc) * 2], bi = xbar[((size_t)wa * G + kc) * 2 + 1];
+      const double x = xi[(size_t)wa * xs + kc];
+      const double br = xbar ? xbar[((size_t)wa * G + kc) * 2] : 0.0;
+      const double bi = xbar ? xbar[((size_t)wa * G + kc) * 2 + 1] : 0.0;
       cr[buf][q] = ok ? x - br : 0.0;
       ci[buf][q] = ok ? -bi : 0.0;
 #pragma unroll
@@ -286,7 +289,7 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (nw + 63) / 64), block(256);
-  hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, sqrt(c->dtau),
+  hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, c->G, sqrt(c->dtau),
                      c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
 }
@@ -314,24 +317,31 @@ hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const d
 // ---------------------------------------------------------------------------
 // Taylor propagator for larger systems (M <= 128, N <= 32): one workgroup per
 // (walker, spin), one wavefront per 16-row tile; V rows as MFMA A operands in
-// registers (V_re and -V_im), e^{-tau h1/2} operands read from L2 at their two
-// uses, the iterate in one LDS tile with two barriers per Horner step.  The imaginary part is accumulated as V_re Y_im - (-V_im) Y_re.
+// registers (V_re and -V_im), the real one-body factors' operands read from L2
+// at their uses, the iterate in one LDS tile with two barriers per Horner
+// step.  The imaginary part is accumulated as V_re Y_im - (-V_im) Y_re.
+// Computes dst = El T_n(V) Er src per block (Er may be null: identity).  The
+// walker step has El = Er = e^{-tau h1/2}, src = dst, two spins; a trial slice
+// has one M x N block per path and src either the previous slice or, for the
+// first slice, Phi_0 read by every path (src_ws = 0).
 namespace {
 
 template <int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
-k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
-           const double* __restrict__ Eh, double* __restrict__ phi) {
+k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restrict__ vmat,
+           const double* __restrict__ El, const double* __restrict__ Er,
+           const double* src, int src_ws, double* dst) {
   constexpr int NT = 16 * NTC;
   extern __shared__ double smem[];
   double* sY = smem;                 // [MT][NT][2] iterate
-  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = e^{-tau h1/2} phi
+  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = Er src
   const int KT = MT / 16;
   const int w = blockIdx.x, sp = blockIdx.y;
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const double* V = vmat + (size_t)w * M * M * 2;
-  double* ph = phi + ((size_t)w * 2 + sp) * M * N * 2;
+  const double* in = src + ((size_t)w * src_ws + sp) * M * N * 2;
+  double* ph = dst + ((size_t)w * spins + sp) * M * N * 2;
 
   double vr[KTMAX][4], nvi[KTMAX][4];
 #pragma unroll
@@ -346,12 +356,12 @@ k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
   for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
     const int m = q / NT, n = q % NT;
     const bool ok = m < M && n < N;
-    sY[2 * q] = ok ? ph[((size_t)m * N + n) * 2] : 0.0;
-    sY[2 * q + 1] = ok ? ph[((size_t)m * N + n) * 2 + 1] : 0.0;
+    sY[2 * q] = ok ? in[((size_t)m * N + n) * 2] : 0.0;
+    sY[2 * q + 1] = ok ? in[((size_t)m * N + n) * 2 + 1] : 0.0;
   }
   __syncthreads();
-  // o = E_h Y (rows of this tile)
-  auto apply_eh = [&](dx4 (&o)[NTC][2]) {
+  // o = E Y (rows of this tile)
+  auto apply_eh = [&](const double* Eh, dx4 (&o)[NTC][2]) {
 #pragma unroll
     for (int ct = 0; ct < NTC; ++ct) o[ct][0] = o[ct][1] = dx4_zero();
 #pragma unroll
@@ -380,12 +390,15 @@ k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
         d[1] = o[ct][1][r];
       }
   };
-  {
+  if (Er != nullptr) {
     dx4 x[NTC][2];
-    apply_eh(x);
+    apply_eh(Er, x);
     __syncthreads();
     store(sY, x);
     store(sX, x);
+    __syncthreads();
+  } else {
+    for (int q = threadIdx.x; q < 2 * MT * NT; q += blockDim.x) sX[q] = sY[q];
     __syncthreads();
   }
   for (int j = n_taylor; j >= 1; --j) {
@@ -421,7 +434,7 @@ k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
     __syncthreads();
   }
   dx4 o[NTC][2];
-  apply_eh(o);
+  apply_eh(El, o);
 #pragma unroll
   for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
@@ -436,26 +449,45 @@ k_taylor_g(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
 }
 
 template <int KTMAX, int NTC>
-hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
+                              const double* vmat, const double* El, const double* Er,
+                              const double* src, int src_ws, double* dst) {
   const size_t lds = (size_t)2 * c->MT * 16 * NTC * 2 * sizeof(double);
   auto kern = k_taylor_g<KTMAX, NTC>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nw, 2), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N, c->MT,
-                     c->n_taylor, vmat, c->d_Eh, phi);
+  hipLaunchKernelGGL(kern, dim3(n, spins), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N,
+                     c->MT, n_taylor, spins, vmat, El, Er, src, src_ws, dst);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
-  if (nw <= 0) return hipSuccess;
+hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
+                               const double* vmat, const double* El, const double* Er,
+                               const double* src, int src_ws, double* dst) {
+  if (n <= 0) return hipSuccess;
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_P(KM, NC) \
-  if (KT <= KM && NTC == NC) return launch_taylor_g_kt<KM, NC>(c, nw, vmat, phi);
+#define AFQMC_P(KM, NC)                                                                  \
+  if (KT <= KM && NTC == NC)                                                             \
+    return launch_taylor_g_kt<KM, NC>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
   AFQMC_P(4, 1) AFQMC_P(6, 1) AFQMC_P(8, 1)
   AFQMC_P(4, 2) AFQMC_P(6, 2) AFQMC_P(8, 2)
 #undef AFQMC_P
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+  return launch_taylor_g_gen(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
+}
+
+hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
+                             const double* Lgen, const double* y, double* vmat) {
+  if (n <= 0) return hipSuccess;
+  const int MM = c->M * c->M;
+  dim3 grid((MM + 63) / 64, (n + 63) / 64);
+  hipLaunchKernelGGL(k_vbuild, grid, dim3(256), 0, c->stream, n, G, MM, xs, sqrt_s, Lgen, y,
+                     (const double*)nullptr, vmat);
+  return hipGetLastError();
 }

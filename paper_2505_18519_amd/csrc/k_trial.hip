@@ -350,9 +350,31 @@ hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT)
 
 }  // namespace
 
+// Multi-slice trials (Sec. II.C, Eqs. trial and trial-AF; Sec. III.B):
+// Phi_T(Y) = F_m X_m ... F_1 X_1 F_0 Phi_0, X_l = T_n(i sqrt(s_l) sum_k y_{l,k} A_k),
+// slice by slice with the walker propagator's kernels: V_l for every path
+// (k_vbuild over the slice's block of y), then F_l T_n(V_l) [F_0] applied to
+// the running determinant (the first slice reads Phi_0 for every path).
+hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, double* phiT,
+                               double* vbuf) {
+  if (n <= 0) return hipSuccess;
+  const size_t MM = (size_t)c->M * c->M;
+  for (int l = 0; l < c->n_slices; ++l) {
+    hipError_t e = launch_vbuild_gen(c, n, c->kgen, c->K, sqrt(c->slice_s[l]), c->d_A,
+                                     y + (size_t)l * c->kgen, vbuf);
+    if (e != hipSuccess) return e;
+    e = launch_taylor_g_gen(c, n, 1, c->trial_taylor, vbuf, c->d_F + (size_t)(l + 1) * MM,
+                            l == 0 ? c->d_F : nullptr, l == 0 ? c->d_phi0c : phiT,
+                            l == 0 ? 0 : 1, phiT);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
                                 double* ubuf) {
   if (n_samples <= 0) return hipSuccess;
+  if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (n_samples + 63) / 64);
   hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,

@@ -22,7 +22,7 @@ class Walkers:
         self.phi = torch.zeros(nw, 2, c.M, c.N, dtype=torch.complex128, **z)
         self.w = torch.ones(nw, dtype=torch.float64, **z)
         self.y = torch.zeros(nw, c.P, c.K, dtype=torch.float64, **z)
-        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=torch.float64, **z)
+        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=c.tdtype, **z)
         self.logov = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
         self.logov_new = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
         self.theta = torch.zeros(nw, c.P, 2, c.M, c.N, dtype=torch.complex128, **z)
@@ -100,7 +100,7 @@ class Measurement:
         c, z = mctx, dict(device=mctx.device)
         self.ctx, self.nw = mctx, nw
         self.y = torch.zeros(nw, c.P, c.K, dtype=torch.float64, **z)
-        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=torch.float64, **z)
+        self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=c.tdtype, **z)
         self.logov = torch.zeros(nw, c.P, dtype=torch.complex128, **z)
         self.theta = torch.zeros(nw, c.P, 2, c.M, c.N, dtype=torch.complex128, **z)
         self.eloc = torch.zeros(nw, dtype=torch.complex128, **z)
