@@ -15,7 +15,11 @@ distributions given below.  Draw order for one instance, all from
 1. h1 off-diagonal: an (M, M) block of N(0, 0.1^2) normals, strict upper
    triangle kept and mirrored; diagonal = linspace(-2, 2, M).
 2. L: for gamma = 0..n_chol-1, an (M, M) block of N(0,1) normals times
-   0.3/sqrt(gamma+1), upper triangle (with diagonal) kept and mirrored.
+   0.3 sqrt(8/M)/sqrt(gamma+1), upper triangle (with diagonal) kept and
+   mirrored.  The sqrt(8/M) keeps the per-orbital two-body scale
+   sum_gamma sum_j L_ij^2 independent of M (dense random vectors would
+   otherwise make it grow like M: E(Phi_0) ~ +380 at M = 64 with a mean path
+   sign collapsing within ten steps); at M = 8 the factor is exactly 1.
 3. Gaussian trial generators only: for k = 0..K-1, an (M, M) block of uniforms
    (mask: u < density) then an (M, M) block of N(0,1) values; the masked upper
    triangle (with diagonal) is mirrored.
@@ -108,7 +112,7 @@ def make_hamiltonian(rng: np.random.Generator, M: int, n_chol: int):
     h1[np.diag_indices(M)] = np.linspace(-2.0, 2.0, M)
     L = np.empty((n_chol, M, M), dtype=np.float64)
     for g in range(n_chol):
-        b = rng.normal(0.0, 1.0, size=(M, M)) * (0.3 / math.sqrt(g + 1.0))
+        b = rng.normal(0.0, 1.0, size=(M, M)) * (0.3 * math.sqrt(8.0 / M) / math.sqrt(g + 1.0))
         L[g] = _sym_from_upper(b, keep_diag=True)
     return np.ascontiguousarray(h1), np.ascontiguousarray(L)
 
@@ -195,6 +199,8 @@ def workload(idx: int):
     2: mixed precision (M=128, N=32, 512 vectors, K=128), 1024 walkers x 4
     3: 32 uneven systems (M in [24,128], N=M//4, 4M vectors, K=M//2)
     4: learned proposal (M=96, N=24, 384 vectors, K=128), 2048 walkers x 4
+    5: multi-slice trial e^{-2 tau_T H} Phi_0 on the Hamiltonian of workload 1
+       (m=2, tau_T=0.01, all 256 vectors as generators: K=512 Gaussian), 512 x 8
     """
     seed = 1000 + idx
     if idx == 0:
@@ -218,6 +224,10 @@ def workload(idx: int):
     if idx == 4:
         return (gaussian_system(96, 24, 384, 128, seed),
                 RunConfig(W=2048, P=4, dtau=0.005, n_steps=2000, proposal=2))
+    if idx == 5:
+        base = gaussian_system(64, 16, 256, 64, 1001)
+        return (imaginary_time_trial(base, 2, 0.01, name="itime-M64-N16-G256-m2"),
+                RunConfig(W=512, P=8, dtau=0.005, n_steps=2000, proposal=1, rw_step=0.08))
     raise ValueError(f"no workload {idx}")
 
 
@@ -226,14 +236,14 @@ def imaginary_time_trial(sys: System, m: int, tau_T: float, n_gen: Optional[int]
     """The system with the trial Psi_T = e^{-m tau_T H} Phi_0 in multi-slice
     form (Sec. III.B with t_j = tau_T, H_T^j = H): generators A = the first
     n_gen vectors L (all by default), s_l = tau_T, F_0 = F_m = e^{-tau_T h1/2},
-    F_l = e^{-tau_T h1} for 0 < l < m (F_0 = e^{-tau_T h1/2} alone if m = 0).
+    F_l = e^{-tau_T h1} for 0 < l < m (F_0 = identity if m = 0: Psi_T = Phi_0).
     Hidden variables are Gaussian, K = m * n_gen."""
     n_gen = sys.n_chol if n_gen is None else n_gen
     lam, Q = np.linalg.eigh(sys.h1)
     half = (Q * np.exp(-0.5 * tau_T * lam)) @ Q.T
     full = (Q * np.exp(-tau_T * lam)) @ Q.T
     F = np.empty((m + 1, sys.M, sys.M))
-    F[0] = half
+    F[0] = half if m > 0 else np.eye(sys.M)
     for l in range(1, m + 1):
         F[l] = half if l == m else full
     return dataclasses.replace(

@@ -33,6 +33,7 @@ WORKLOADS = {
     "fp64": (1, 0, PEAK_FP64_MFMA, "f64"),
     "mixed": (2, 1, PEAK_FP32_MFMA, "f32-contraction/f64"),
     "mixed-fp64": (2, 0, PEAK_FP64_MFMA, "f64"),
+    "slices": (5, 0, PEAK_FP64_MFMA, "f64"),
 }
 
 
@@ -55,10 +56,14 @@ def measured_traffic(workload):
     return nbytes if ok else None
 
 
-def contraction_flops(M, N, G):
+def contraction_flops(M, N, G, complex_trial=False):
     """Algorithmic flops of the contraction per (walker, path): the real
     half-rotation Phi_T^T L_g (2 N M^2), its product with both spins' Theta
-    (2 x 4 M N^2) and tr(f f) (2 x 8 N^2), for each of the G vectors."""
+    (2 x 4 M N^2) and tr(f f) (2 x 8 N^2), for each of the G vectors.  A
+    complex trial doubles the first two: Re and Im Phi_T^T L_g (4 N M^2), a
+    complex-by-complex product per spin (2 x 8 M N^2)."""
+    if complex_trial:
+        return G * (4 * N * M * M + 2 * (8 * M * N * N + 8 * N * N))
     return G * (2 * N * M * M + 2 * (4 * M * N * N + 8 * N * N))
 
 
@@ -168,6 +173,8 @@ def learned_study(args):
     equal_error_ratio = (L["walker_steps_per_s"] / R["walker_steps_per_s"]) * (var_r / var_l)
     flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
     achieved = flops / (L["contraction_ms"] * 1e-3) / 1e12
+    wname = (sys_.name if ctx.ctrial else
+             f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}")
     out = {
         "metric": METRIC,
         "value": L["walker_steps_per_s"],
@@ -251,6 +258,8 @@ def uneven_study(args):
 
     step_s = dt / n_steps
     achieved = flops / step_s / 1e12
+    wname = (sys_.name if ctx.ctrial else
+             f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}")
     out = {
         "metric": METRIC,
         "value": total_w / step_s,
@@ -324,7 +333,8 @@ def main():
     # of this workload has a mean path sign near 0.2 after a few steps)
     xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
     ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap,
-                    precision=precision)
+                    precision=precision, proposal=run.proposal,
+                    rw_step=run.rw_step if run.proposal == A.PROPOSAL_RW else None)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
 
@@ -349,7 +359,7 @@ def main():
     dt = time.perf_counter() - t0
 
     contract_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
+    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol, ctx.ctrial) * nw * P
     achieved = flops / (contract_ms * 1e-3) / 1e12
     e = est.cpu().numpy()
     energies = e[:, 0] / e[:, 1]
@@ -360,6 +370,8 @@ def main():
               "n_nonfinite", int((~np.isfinite(w)).sum()), file=sys.stderr)
         sys.exit(1)
 
+    wname = (sys_.name if ctx.ctrial else
+             f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}")
     out = {
         "metric": METRIC,
         "value": nw * args.steps / dt,
@@ -373,8 +385,7 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
-                               f"-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
+        "config": {"workload": f"{wname}-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
                    "walkers": nw, "paths": P, "M": sys_.M, "N": sys_.N,
                    "n_chol": sys_.n_chol, "K": sys_.K, "xbar_cap": xbar_cap,
                    "comb_every": n_pc, "weight_cap": w_cap},
@@ -382,9 +393,12 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload),
                      "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
-                                else "k_contract_g") + " (+ k_combine) in afqmc_local_energy",
+                                and not ctx.ctrial else "k_contract_g")
+                               + (" (complex trial)" if ctx.ctrial else "")
+                               + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},
         "energy_last": float(energies[-1]),
+        "acceptance_last_step": float(st.nacc.sum().item()) / (nw * P * run.n_sweep),
     }
     if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(sys_, run, seed)

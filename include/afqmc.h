@@ -241,7 +241,9 @@ afqmc_status afqmc_population_control(afqmc_ctx ctx, int32_t nw, void* phi, doub
                                       double w_cap, int32_t normalize, int32_t* parent);
 
 /* Mixed-estimator sums (Eq. mixed_estimator): out[0] = sum_k W_k Re E_L,k,
- * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2]. */
+ * out[1] = sum_k W_k, compensated FP64 summation; out is a DEVICE double[2].
+ * A walker whose Re E_L is not finite (numerically singular overlaps) is left
+ * out of both sums; afqmc_propagate sets a non-finite new weight to 0. */
 afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const void* eloc,
                              double* out);
 

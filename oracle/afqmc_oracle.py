@@ -279,7 +279,7 @@ def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
     else:
         wn = w * mag * np.maximum(0.0, np.cos(np.angle(r)))
         ref = num_r
-    wn = np.where(alive, wn, 0.0)
+    wn = np.where(alive & np.isfinite(wn), wn, 0.0)   # a non-finite weight kills the walker
     return phin, wn, ref, elln
 
 
@@ -401,8 +401,12 @@ def comb(w: np.ndarray, seed: int, step: int, w_cap: float = 0.0, normalize: boo
 
 
 def estimator(w: np.ndarray, eloc: np.ndarray):
-    """(sum_k W_k Re E_L,k, sum_k W_k) with exact summation (Eq. mixed_estimator)."""
-    return (math.fsum((w * eloc.real).tolist()), math.fsum(w.tolist()))
+    """(sum_k W_k Re E_L,k, sum_k W_k) with exact summation (Eq. mixed_estimator).
+    A walker whose Re E_L is not finite (a numerically singular overlap)
+    contributes to neither sum; its move then gives it W = 0 (propagate)."""
+    ok = np.isfinite(eloc.real)
+    wk = np.where(ok, w, 0.0)
+    return (math.fsum((wk * np.where(ok, eloc.real, 0.0)).tolist()), math.fsum(wk.tolist()))
 
 
 # ---------------------------------------------------------------------------
@@ -491,8 +495,10 @@ def measure_extra(sys, phi, y, phiT, logov, w, seed, step, P2, n_sweep, dtau,
     S = phases(logov).sum(-1)
     S2 = phases(ell2).sum(-1)
     R = np.where(S != 0, S2 / np.where(S != 0, S, 1.0), 0.0)
-    num = math.fsum((w * (R * eloc2).real).tolist())
-    den = math.fsum((w * R.real).tolist())
+    term = (R * eloc2).real
+    ok = np.isfinite(term) & np.isfinite(R.real)   # as in estimator: non-finite walkers drop out
+    num = math.fsum(np.where(ok, w * term, 0.0).tolist())
+    den = math.fsum(np.where(ok, w * R.real, 0.0).tolist())
     return num, den, eloc2, R
 
 

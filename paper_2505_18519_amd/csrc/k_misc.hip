@@ -126,10 +126,12 @@ k_estimator(int nw, const double* __restrict__ w, const double* __restrict__ elo
   double n_s = 0.0, n_e = 0.0, d_s = 0.0, d_e = 0.0;
   for (int k = tid; k < nw; k += 256) {
     double s, e;
-    two_sum(n_s, w[k] * eloc[2 * (size_t)k], s, e);
+    const double el = eloc[2 * (size_t)k];
+    const bool ok = __builtin_isfinite(el);  // a non-finite E_L drops out of both sums
+    two_sum(n_s, ok ? w[k] * el : 0.0, s, e);
     n_s = s;
     n_e += e;
-    two_sum(d_s, w[k], s, e);
+    two_sum(d_s, ok ? w[k] : 0.0, s, e);
     d_s = s;
     d_e += e;
   }
@@ -190,11 +192,12 @@ k_estimator_corrected(int nw, int P, int Pr, const double* __restrict__ w,
     const cplx r = (s1.re != 0.0 || s1.im != 0.0) ? cdiv(s2, s1) : cmk(0.0, 0.0);
     if (R != nullptr) cst(R + 2 * (size_t)k, r);
     const cplx re = cmul(r, cld(eloc + 2 * (size_t)k));
+    const bool ok = __builtin_isfinite(re.re) && __builtin_isfinite(r.re);
     double s, e;
-    two_sum(n_s, w[k] * re.re, s, e);
+    two_sum(n_s, ok ? w[k] * re.re : 0.0, s, e);
     n_s = s;
     n_e += e;
-    two_sum(d_s, w[k] * r.re, s, e);
+    two_sum(d_s, ok ? w[k] * r.re : 0.0, s, e);
     d_s = s;
     d_e += e;
   }

@@ -269,7 +269,7 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
     else
       wn = w[wk] * mag * fmax(0.0, cos(atan2(r.im, r.re)));
   }
-  w[wk] = wn;
+  w[wk] = __builtin_isfinite(wn) ? wn : 0.0;  // a non-finite weight kills the walker
   const cplx rf = (weight_mode == AFQMC_WEIGHT_COMBINED) ? den : num;
   ref[(size_t)wk * 2] = rf.re;
   ref[(size_t)wk * 2 + 1] = rf.im;

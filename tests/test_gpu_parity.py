@@ -254,6 +254,14 @@ def test_estimator_sums():
     num, den = O.estimator(w, e)
     assert abs(host(out)[0] - num) <= 1e-14 * abs(num) + 1e-14
     assert abs(host(out)[1] - den) <= 1e-14 * den
+    # walkers with a non-finite local energy drop out of both sums
+    e[[3, 500]] = [np.nan, np.inf + 0j]
+    A.afqmc_estimator(ctx, nw, dev(w), dev(e), out)
+    torch.cuda.synchronize()
+    num, den = O.estimator(w, e)
+    assert np.isfinite(host(out)).all()
+    assert abs(host(out)[0] - num) <= 1e-14 * abs(num) + 1e-14
+    assert abs(host(out)[1] - den) <= 1e-14 * den
 
 
 def test_singular_paths_are_excluded():

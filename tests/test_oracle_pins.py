@@ -471,6 +471,28 @@ def test_estimator_exact_sum():
     assert num == math.fsum(np.abs(w))
 
 
+def test_non_finite_walkers_drop_out(tiny):
+    """A walker with a non-finite local energy adds nothing to either sum of
+    Eq. mixed_estimator, and a non-finite weight update sets W = 0 while the
+    other walkers' weights are those of the same move without it."""
+    w = np.array([1.0, 2.0, 0.5])
+    e = np.array([-1.0, np.nan, -3.0]) + 0j
+    num, den = O.estimator(w, e)
+    assert num == -1.0 - 1.5 and den == 1.5
+    rng = np.random.default_rng(3)
+    phi = ai.random_walkers(rng, tiny, 3, spread=0.4)
+    y = ai.random_hidden(rng, tiny, 3, 4)
+    phiT = O.trial_det(tiny, y)
+    eloc, xbar, _, _, ell = O.local_energy(tiny, phi, phiT, 0.01)
+    xi = rng.normal(size=(3, tiny.n_chol))
+    _, w_ref, _, _ = O.propagate(tiny, phi, xi, xbar, phiT, ell, np.ones(3), 0.01, 10)
+    xbar_bad = xbar.copy()
+    xbar_bad[1, 0] = np.inf
+    with np.errstate(all="ignore"):
+        _, w_bad, _, _ = O.propagate(tiny, phi, xi, xbar_bad, phiT, ell, np.ones(3), 0.01, 10)
+    assert w_bad[1] == 0.0 and w_bad[0] == w_ref[0] and w_bad[2] == w_ref[2]
+
+
 def test_comb_population_control_properties():
     """The comb keeps the total weight, gives walker k either floor or ceil of
     nw W_k / sum W copies, none to zero-weight walkers, and with a cap first
