@@ -173,8 +173,6 @@ def learned_study(args):
     equal_error_ratio = (L["walker_steps_per_s"] / R["walker_steps_per_s"]) * (var_r / var_l)
     flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
     achieved = flops / (L["contraction_ms"] * 1e-3) / 1e12
-    wname = (sys_.name if ctx.ctrial else
-             f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}")
     out = {
         "metric": METRIC,
         "value": L["walker_steps_per_s"],
@@ -258,8 +256,6 @@ def uneven_study(args):
 
     step_s = dt / n_steps
     achieved = flops / step_s / 1e12
-    wname = (sys_.name if ctx.ctrial else
-             f"gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}")
     out = {
         "metric": METRIC,
         "value": total_w / step_s,
