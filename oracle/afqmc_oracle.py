@@ -503,6 +503,61 @@ def measure_extra(sys, phi, y, phiT, logov, w, seed, step, P2, n_sweep, dtau,
 
 
 # ---------------------------------------------------------------------------
+# Back-propagated one-body density matrix (App. B, Measurement; Eqs.
+# AFQMC_Metropolis_measure and AFQMC_Metropolis_measure2)
+
+def back_propagated_density(sys, phi_mid, hist_xi, hist_xbar, phiT, logov, w, dtau, n_taylor,
+                            Eh=None):
+    """Density matrix with the last h projectors restored: the operator sits
+    between the walker phi_mid saved h steps ago and the measurement step's
+    trial propagated back through those h steps.
+
+    hist_xi [nw, h, G], hist_xbar [nw, h, G]: the fields of the h steps
+    (oldest first) of each walker's line of descent; phiT, logov: the paths
+    and log-overlaps at the measurement step; w: the weights there.  With
+    B_i = e^{-tau h1/2} T_n(V_i) e^{-tau h1/2} (symmetric), the bra
+    <Phi_T(Y_p)| B_h ... B_1 is the determinant Phi~_p = B_1 ... B_h Phi_T(Y_p)
+    (B_h applied first), and per path and spin
+      R_p^s = phi_mid^s (Phi~_p^T phi_mid^s)^{-1} Phi~_p^T,
+      R[i][j] = <Phi~_p| c+_j c_i |phi_mid> / <Phi~_p|phi_mid>;
+    the sampled trial of Eq. Metropolis_sampled_trial weights path p by
+    a_p = <Phi~_p|phi_mid> / |O_p(phi_end)|, so per walker
+      R_k = sum_p a_p (R_p^up + R_p^dn) / sum_p a_p
+    (a common factor of the a_p cancels; singular paths drop out).
+    Returns (sum_k W_k Re R_k [M, M], sum_k W_k, R_k [nw, M, M])."""
+    if Eh is None:
+        Eh = half_kinetic(sys, dtau)
+    nw, h = hist_xi.shape[:2]
+    P = phiT.shape[1]
+    X = phiT.astype(np.complex128).copy()                       # [nw, P, M, N]
+    for i in range(h - 1, -1, -1):
+        V = field_matrix(sys, hist_xi[:, i], hist_xbar[:, i], dtau)
+        X = np.einsum("ij,wpjn->wpin", Eh, X)
+        X = taylor_apply(V, X, n_taylor)
+        X = np.einsum("ij,wpjn->wpin", Eh, X)
+    lt, theta = green(X, phi_mid)                                # <Phi~_p|phi_mid>, Theta
+    la = np.where(np.isfinite(lt.real) & np.isfinite(logov.real), lt - logov.real, -np.inf)
+    shift = np.max(np.where(np.isfinite(la.real), la.real, -np.inf), axis=1, keepdims=True)
+    shift = np.where(np.isfinite(shift), shift, 0.0)
+    a = np.where(np.isfinite(la.real), np.exp(la - shift), 0.0)  # [nw, P]
+    Rk = np.zeros((nw, sys.M, sys.M), dtype=np.complex128)
+    for k in range(nw):
+        den = a[k].sum()
+        if den == 0:
+            continue
+        for p in range(P):
+            if a[k, p] == 0:
+                continue
+            Rp = sum(theta[k, p, s] @ X[k, p].T for s in range(2))
+            Rk[k] += a[k, p] * Rp
+        Rk[k] /= den
+    ok = np.array([np.all(np.isfinite(Rk[k])) for k in range(nw)]) & (np.abs(a).sum(1) > 0)
+    wk = np.where(ok, w, 0.0)
+    num = np.einsum("k,kij->ij", wk, np.where(ok[:, None, None], Rk.real, 0.0))
+    return num, math.fsum(wk.tolist()), Rk
+
+
+# ---------------------------------------------------------------------------
 # One whole step (App. B order) for trajectory tests
 
 class State:
@@ -541,9 +596,10 @@ def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
                                           n_sweep, proposal, rw_step, weight_mode)
     if n_qr and (i + 1) % n_qr == 0:
         phin, logov = reorthogonalize(phin, logov)
+    parent = np.arange(st.phi.shape[0])
     if n_pc and (i + 1) % n_pc == 0:
         parent, w2 = comb(w2, seed, i, w_cap, normalize)
         phin, y, phiT, logov = phin[parent], y[parent], phiT[parent], logov[parent]
     rec = dict(e_num=num, e_den=den, eloc=eloc, xbar=xbar, logov=ell, xi=xi,
-               w_prop=wn, ref=ref, nacc=nacc)
+               w_prop=wn, ref=ref, nacc=nacc, parent=parent)
     return State(phin, w2, y, phiT, logov), rec
