@@ -247,6 +247,47 @@ afqmc_status afqmc_population_control(afqmc_ctx ctx, int32_t nw, void* phi, doub
 afqmc_status afqmc_estimator(afqmc_ctx ctx, int32_t nw, const double* w, const void* eloc,
                              double* out);
 
+/* ---- Back-propagated measurement (App. B, Measurement; Eqs.
+ * AFQMC_Metropolis_measure and AFQMC_Metropolis_measure2) ------------------
+ *
+ * The operator is inserted h steps back along each walker's path: between the
+ * walker phi_mid saved h steps before the measurement and the measurement
+ * step's sampled trial propagated back through the h restored projectors
+ * B_i = e^{-tau h1/2} T_n(V_i) e^{-tau h1/2}, V_i = i sqrt(tau) sum_g
+ * (xi_g - xbar_g) L_g with the fields the walker's line of descent drew.  The
+ * caller keeps the field history [nw][h][G] (afqmc_bp_record after each
+ * afqmc_propagate) and phi_mid, and moves both with the walkers at every comb
+ * (afqmc_gather_rows with the comb's parent array). */
+
+/* hist_xi[w][slot][.] = xi[w][.] (double), hist_xbar[w][slot][.] = xbar[w][.]
+ * (complex); 0 <= slot < h. */
+afqmc_status afqmc_bp_record(afqmc_ctx ctx, int32_t nw, int32_t h, int32_t slot, const double* xi,
+                             const void* xbar, double* hist_xi, void* hist_xbar);
+
+/* One-body density matrix with the last h projectors restored: per walker k
+ * and path p (phiT, logov at the measurement step, complex or real trial),
+ *   Phi~_p = B_1 ... B_h Phi_T(Y_p)          (slot h-1 applied first)
+ *   R_p = sum_s phi_mid^s (Phi~_p^T phi_mid^s)^{-1} Phi~_p^T,
+ *         R_p[i][j] = <Phi~_p| c+_j c_i |phi_mid> / <Phi~_p|phi_mid>
+ *   a_p = <Phi~_p|phi_mid> / |O_p(phi_end)|  (the sampled trial's path weights)
+ *   R_k = sum_p a_p R_p / sum_p a_p          -> rho [nw][M][M] complex
+ *   out[i M + j] = sum_k W_k Re R_k[i][j],  out[M M] = sum_k W_k
+ * over walkers with a live path and finite R_k (compensated FP64 sums).
+ * Scratch owned by the caller: phit_bp [nw][P][M][N] complex, theta_bp
+ * [nw][P][2][M][N] complex, logov_bp [nw][P] complex.  h = 0 gives the
+ * path-weighted mixed estimate.  Uses the workspace; out is DEVICE double[M M + 1]. */
+afqmc_status afqmc_bp_density(afqmc_ctx ctx, int32_t nw, int32_t h, const void* phi_mid,
+                              const double* hist_xi, const void* hist_xbar, const double* phiT,
+                              const void* logov, const double* w, void* phit_bp, void* theta_bp,
+                              void* logov_bp, void* rho, double* out);
+
+/* Device copy of n doubles, and dst[j] = src[parent[j]] for nw rows of `row`
+ * doubles (rows whose parent is outside [0, nw) are left as they are): the
+ * data movement that keeps per-walker buffers in step with the walkers. */
+afqmc_status afqmc_copy(afqmc_ctx ctx, int64_t n, const void* src, void* dst);
+afqmc_status afqmc_gather_rows(afqmc_ctx ctx, int32_t nw, const int32_t* parent, int64_t row,
+                               const void* src, void* dst);
+
 /* ---- Initialisation from the trial and measurement with extra paths ------- */
 
 /* Step indices of the Metropolis streams reserved for these chains: the

@@ -70,6 +70,13 @@ EXPORTS = {
                                    c_void_p, c_void_p, c_uint64, c_uint64, c_int32, c_void_p]),
     "afqmc_reorthogonalize": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_estimator": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "afqmc_copy": (c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p]),
+    "afqmc_gather_rows": (c_int, [c_void_p, c_int32, c_void_p, ctypes.c_int64, c_void_p, c_void_p]),
+    "afqmc_bp_record": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                c_void_p]),
+    "afqmc_bp_density": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p]),
     "afqmc_init_metropolis": (c_int, [c_void_p, c_int32, c_uint64, c_int32, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "afqmc_extend_paths": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
@@ -337,6 +344,53 @@ def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=
 def afqmc_estimator(ctx, nw, w, eloc, out):
     ctx._call("afqmc_estimator", nw, _ptr(w, torch.float64, nw, "w"),
               _ptr(eloc, torch.complex128, nw, "eloc"), _ptr(out, torch.float64, 2, "out"))
+
+
+def _doubles(t):
+    return t.numel() * (2 if t.is_complex() else 1)
+
+
+def afqmc_copy(ctx, src, dst):
+    """dst <- src (same size, device tensors)."""
+    n = _doubles(src)
+    if _doubles(dst) != n:
+        raise ValueError("afqmc_copy: sizes differ")
+    ctx._call("afqmc_copy", n, _ptr(src, src.dtype, src.numel(), "src"),
+              _ptr(dst, dst.dtype, dst.numel(), "dst"))
+
+
+def afqmc_gather_rows(ctx, nw, parent, src, dst):
+    """dst[j] = src[parent[j]] over the leading (walker) dimension."""
+    row = _doubles(src) // nw
+    if _doubles(dst) != row * nw or _doubles(src) != row * nw:
+        raise ValueError("afqmc_gather_rows: sizes differ")
+    ctx._call("afqmc_gather_rows", nw, _ptr(parent, torch.int32, nw, "parent"), row,
+              _ptr(src, src.dtype, src.numel(), "src"), _ptr(dst, dst.dtype, dst.numel(), "dst"))
+
+
+def afqmc_bp_record(ctx, nw, h, slot, xi, xbar, hist_xi, hist_xbar):
+    c = ctx
+    c._call("afqmc_bp_record", nw, int(h), int(slot), _ptr(xi, torch.float64, nw * c.G, "xi"),
+            _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
+            _ptr(hist_xi, torch.float64, nw * h * c.G, "hist_xi"),
+            _ptr(hist_xbar, torch.complex128, nw * h * c.G, "hist_xbar"))
+
+
+def afqmc_bp_density(ctx, nw, h, phi_mid, hist_xi, hist_xbar, phiT, logov, w, phit_bp, theta_bp,
+                     logov_bp, rho, out):
+    c = ctx
+    c.reserve(nw)
+    c._call("afqmc_bp_density", nw, int(h),
+            _ptr(phi_mid, torch.complex128, nw * 2 * c.M * c.N, "phi_mid"),
+            _ptr(hist_xi, torch.float64, nw * h * c.G, "hist_xi", allow_none=h == 0),
+            _ptr(hist_xbar, torch.complex128, nw * h * c.G, "hist_xbar", allow_none=h == 0),
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"), _ptr(w, torch.float64, nw, "w"),
+            _ptr(phit_bp, torch.complex128, nw * c.P * c.M * c.N, "phit_bp"),
+            _ptr(theta_bp, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta_bp"),
+            _ptr(logov_bp, torch.complex128, nw * c.P, "logov_bp"),
+            _ptr(rho, torch.complex128, nw * c.M * c.M, "rho"),
+            _ptr(out, torch.float64, c.M * c.M + 1, "out"))
 
 
 def afqmc_init_metropolis(ctx, nw, seed, n_pair, n_burn, yw, phi, y, phiT, logov, w):

@@ -642,6 +642,111 @@ afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32
   return AFQMC_OK;
 }
 
+afqmc_status afqmc_copy(afqmc_ctx c, int64_t n, const void* src, void* dst) {
+  CHECK_CTX(c);
+  if (n < 0) return fail(c, AFQMC_E_INVALID, "n must be >= 0");
+  if (n == 0) return AFQMC_OK;
+  REQUIRE(c, src, "src");
+  REQUIRE(c, dst, "dst");
+  HIPCALL(c, launch_copy(c, (size_t)n, static_cast<const double*>(src), static_cast<double*>(dst)),
+          "copy");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_gather_rows(afqmc_ctx c, int32_t nw, const int32_t* parent, int64_t row,
+                               const void* src, void* dst) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (row < 0) return fail(c, AFQMC_E_INVALID, "row must be >= 0");
+  if (nw == 0 || row == 0) return AFQMC_OK;
+  REQUIRE(c, parent, "parent");
+  REQUIRE(c, src, "src");
+  REQUIRE(c, dst, "dst");
+  HIPCALL(c,
+          launch_gather(c, nw, (size_t)row, parent, static_cast<const double*>(src),
+                        static_cast<double*>(dst)),
+          "gather_rows");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_bp_record(afqmc_ctx c, int32_t nw, int32_t h, int32_t slot, const double* xi,
+                             const void* xbar, double* hist_xi, void* hist_xbar) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (h < 1 || slot < 0 || slot >= h) return fail(c, AFQMC_E_INVALID, "need 0 <= slot < h");
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, xi, "xi");
+  REQUIRE(c, xbar, "xbar");
+  REQUIRE(c, hist_xi, "hist_xi");
+  REQUIRE(c, hist_xbar, "hist_xbar");
+  HIPCALL(c,
+          launch_bp_record(c, nw, h, slot, xi, static_cast<const double*>(xbar), hist_xi,
+                           static_cast<double*>(hist_xbar)),
+          "bp_record");
+  return AFQMC_OK;
+}
+
+// Back-propagation: the measurement step's path bras through the recorded
+// projectors (most recent first), their overlap with the saved walker on the
+// complex-trial overlap kernel, then the path-weighted density per walker and
+// its weighted sum.
+afqmc_status afqmc_bp_density(afqmc_ctx c, int32_t nw, int32_t h, const void* phi_mid,
+                              const double* hist_xi, const void* hist_xbar, const double* phiT,
+                              const void* logov, const double* w, void* phit_bp, void* theta_bp,
+                              void* logov_bp, void* rho, double* out) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (h < 0) return fail(c, AFQMC_E_INVALID, "h must be >= 0");
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phi_mid, "phi_mid");
+  if (h > 0) {
+    REQUIRE(c, hist_xi, "hist_xi");
+    REQUIRE(c, hist_xbar, "hist_xbar");
+  }
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, w, "w");
+  REQUIRE(c, phit_bp, "phit_bp");
+  REQUIRE(c, theta_bp, "theta_bp");
+  REQUIRE(c, logov_bp, "logov_bp");
+  REQUIRE(c, rho, "rho");
+  REQUIRE(c, out, "out");
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  const size_t n = (size_t)nw * c->P * c->M * c->N;
+  double* X = static_cast<double*>(phit_bp);
+  if (c->ctrial)
+    HIPCALL(c, launch_copy(c, 2 * n, phiT, X), "bp bra copy");
+  else
+    HIPCALL(c, launch_real_to_complex(c, n, phiT, X), "bp bra copy");
+  double* vmat = ws_ptr<double>(c, L.vmat);
+  const int G = c->G;
+  const double* hxb = static_cast<const double*>(hist_xbar);
+  for (int i = h - 1; i >= 0; --i) {
+    HIPCALL(c,
+            launch_vbuild_gen(c, nw, G, h * G, sqrt(c->dtau), c->d_Lraw, hist_xi + (size_t)i * G,
+                              vmat, hxb + (size_t)2 * i * G, h * G),
+            "bp V build");
+    HIPCALL(c, launch_taylor_g_gen(c, nw, c->P, c->n_taylor, vmat, c->d_Eh, c->d_Eh, X, c->P, X),
+            "bp projector");
+  }
+  afqmc_ctx_s cc = *c;  // the back-propagated bras are complex
+  cc.ctrial = true;
+  HIPCALL(c,
+          launch_overlap_g(&cc, nw, static_cast<const double*>(phi_mid), X,
+                           static_cast<double*>(logov_bp), static_cast<double*>(theta_bp), nullptr),
+          "bp overlap");
+  int* okw = ws_ptr<int>(c, L.acc);
+  HIPCALL(c,
+          launch_bp_density(c, nw, static_cast<const double*>(theta_bp), X,
+                            static_cast<const double*>(logov_bp), static_cast<const double*>(logov),
+                            static_cast<double*>(rho), okw),
+          "bp density");
+  HIPCALL(c, launch_bp_reduce(c, nw, w, static_cast<const double*>(rho), okw, out), "bp reduce");
+  return AFQMC_OK;
+}
+
 afqmc_status afqmc_extend_paths(afqmc_ctx c, int32_t nw, int32_t p_src, const double* y_src,
                                 const double* phiT_src, const void* logov_src, double* y,
                                 double* phiT, void* logov) {

@@ -147,9 +147,19 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
 hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
                                const double* vmat, const double* El, const double* Er,
                                const double* src, int src_ws, double* dst);
-// vmat[w] = i sqrt_s sum_k y[w * xs + k] Lgen_k  (k < G)
+// vmat[w] = i sqrt_s sum_k (y[w * xs + k] - xbar[w * xbs + k]) Lgen_k  (k < G;
+// xbar complex, may be null)
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
-                             const double* Lgen, const double* y, double* vmat);
+                             const double* Lgen, const double* y, double* vmat,
+                             const double* xbar = nullptr, int xbs = 0);
+// back-propagation (k_bp.hip)
+hipError_t launch_bp_record(const afqmc_ctx_s* c, int nw, int h, int slot, const double* xi,
+                            const double* xbar, double* hxi, double* hxb);
+hipError_t launch_real_to_complex(const afqmc_ctx_s* c, size_t n, const double* src, double* dst);
+hipError_t launch_bp_density(const afqmc_ctx_s* c, int nw, const double* theta, const double* phit,
+                             const double* lt, const double* lend, double* rho, int* ok);
+hipError_t launch_bp_reduce(const afqmc_ctx_s* c, int nw, const double* w, const double* rho,
+                            const int* ok, double* out);
 // multi-slice trial determinants Phi_T(Y) for n paths; vbuf holds n complex M x M
 hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, double* phiT,
                                double* vbuf);

@@ -89,7 +89,9 @@ __global__ void k_gather_rows(int nw, size_t row, int nchunk, const int* __restr
   const int j = blockIdx.x / nchunk;
   const int ch = blockIdx.x % nchunk;
   if (j >= nw) return;
-  const size_t base_d = (size_t)j * row, base_s = (size_t)parent[j] * row;
+  const int pj = parent[j];
+  if (pj < 0 || pj >= nw) return;  // a parent out of range copies nothing
+  const size_t base_d = (size_t)j * row, base_s = (size_t)pj * row;
   for (size_t q = (size_t)ch * blockDim.x + threadIdx.x; q < row; q += (size_t)nchunk * blockDim.x)
     dst[base_d + q] = src[base_s + q];
 }

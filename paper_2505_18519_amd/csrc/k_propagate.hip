@@ -19,10 +19,11 @@ namespace {
 // V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the FP64
 // matrix cores: each wavefront takes 16 walkers (both Re c and Im c as A
 // operands) and 64 matrix entries; L is read once per 16 walkers.  Row w of
-// xi starts at w * xs; xbar may be null (c = xi): the trial slices use this
-// with the generators A_k and their block of y.
+// xi starts at w * xs and of xbar at w * xbs; xbar may be null (c = xi): the
+// trial slices use this with the generators A_k and their block of y, the
+// back-propagation with a walker's recorded fields.
 __global__ void __launch_bounds__(256)
-k_vbuild(int nw, int G, int MM, int xs, double sqrt_tau, const double* __restrict__ L,
+k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
@@ -52,8 +53,8 @@ k_vbuild(int nw, int G, int MM, int xs, double sqrt_tau, const double* __restric
       const int kc = min(k, G - 1);
       const bool ok = wok && k < G;
       const double x = xi[(size_t)wa * xs + kc];
-      const double br = xbar ? xbar[((size_t)wa * G + kc) * 2] : 0.0;
-      const double bi = xbar ? xbar[((size_t)wa * G + kc) * 2 + 1] : 0.0;
+      const double br = xbar ? xbar[((size_t)wa * xbs + kc) * 2] : 0.0;
+      const double bi = xbar ? xbar[((size_t)wa * xbs + kc) * 2 + 1] : 0.0;
       cr[buf][q] = ok ? x - br : 0.0;
       ci[buf][q] = ok ? -bi : 0.0;
 #pragma unroll
@@ -289,7 +290,7 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (nw + 63) / 64), block(256);
-  hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, c->G, sqrt(c->dtau),
+  hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, c->G, c->G, sqrt(c->dtau),
                      c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
 }
@@ -483,11 +484,12 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
 }
 
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
-                             const double* Lgen, const double* y, double* vmat) {
+                             const double* Lgen, const double* y, double* vmat,
+                             const double* xbar, int xbs) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (n + 63) / 64);
-  hipLaunchKernelGGL(k_vbuild, grid, dim3(256), 0, c->stream, n, G, MM, xs, sqrt_s, Lgen, y,
-                     (const double*)nullptr, vmat);
+  hipLaunchKernelGGL(k_vbuild, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s, Lgen, y,
+                     xbar, vmat);
   return hipGetLastError();
 }

@@ -45,12 +45,69 @@ def init_walkers(ctx: A.Context, phi0, nw: int, seed: int) -> Walkers:
     return st
 
 
+class BackProp:
+    """Field history and saved walkers of a back-propagated measurement (App.
+    B, Measurement): start() saves the walkers, the next h steps record their
+    fields (step(..., bp=...)), and the history follows the walkers through
+    every comb; after the h-th step, density() gives the back-propagated
+    one-body density matrix."""
+
+    def __init__(self, ctx: A.Context, nw: int, h: int):
+        c, z = ctx, dict(device=ctx.device)
+        self.ctx, self.nw, self.h = ctx, nw, h
+        c128, f64 = torch.complex128, torch.float64
+        self.hist_xi = torch.zeros(nw, h, c.G, dtype=f64, **z)
+        self.hist_xbar = torch.zeros(nw, h, c.G, dtype=c128, **z)
+        self.phi_mid = torch.zeros(nw, 2, c.M, c.N, dtype=c128, **z)
+        self._spare = [torch.zeros_like(self.hist_xi), torch.zeros_like(self.hist_xbar),
+                       torch.zeros_like(self.phi_mid)]
+        self.phit_bp = torch.zeros(nw, c.P, c.M, c.N, dtype=c128, **z)
+        self.theta_bp = torch.zeros(nw, c.P, 2, c.M, c.N, dtype=c128, **z)
+        self.logov_bp = torch.zeros(nw, c.P, dtype=c128, **z)
+        self.rho = torch.zeros(nw, c.M, c.M, dtype=c128, **z)
+        self.parent = torch.zeros(nw, dtype=torch.int32, **z)
+        self.slot = -1
+
+    @property
+    def recording(self) -> bool:
+        return 0 <= self.slot < self.h
+
+    @property
+    def ready(self) -> bool:
+        return self.slot == self.h
+
+    def start(self, st: Walkers) -> None:
+        A.afqmc_copy(self.ctx, st.phi, self.phi_mid)
+        self.slot = 0
+
+    def record(self, st: Walkers) -> None:
+        A.afqmc_bp_record(self.ctx, st.nw, self.h, self.slot, st.xi, st.xbar, self.hist_xi,
+                          self.hist_xbar)
+        self.slot += 1
+
+    def follow(self, nw: int) -> None:
+        """Move the history and saved walkers with the comb's parents."""
+        bufs = [self.hist_xi, self.hist_xbar, self.phi_mid]
+        for src, dst in zip(bufs, self._spare):
+            A.afqmc_gather_rows(self.ctx, nw, self.parent, src, dst)
+        self.hist_xi, self.hist_xbar, self.phi_mid, self._spare = (
+            self._spare[0], self._spare[1], self._spare[2], bufs)
+
+    def density(self, st: Walkers, out: torch.Tensor) -> None:
+        """out: device float64 [M*M + 1] = (sum W Re R_k (row-major), sum W)."""
+        A.afqmc_bp_density(self.ctx, st.nw, self.h, self.phi_mid, self.hist_xi, self.hist_xbar,
+                           st.phiT, st.logov, st.w, self.phit_bp, self.theta_bp, self.logov_bp,
+                           self.rho, out)
+
+
 def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
          e_shift: float = 0.0, n_sweep: int = 1, n_qr: int = 10, contract_events=None,
-         n_pc: int = 0, w_cap: float = 0.0, normalize: bool = True) -> None:
+         n_pc: int = 0, w_cap: float = 0.0, normalize: bool = True,
+         bp: "BackProp | None" = None) -> None:
     """Measure, propagate, move the paths, hand off, re-orthonormalise, and
     every n_pc steps (if n_pc > 0) comb the population (weights reset to 1
-    with normalize, to their mean otherwise).
+    with normalize, to their mean otherwise).  With bp recording, the step's
+    fields join its history and the comb moves the history with the walkers.
 
     est_out: device float64 [2] receiving (sum W Re E_L, sum W) at the
     pre-move state (Eq. mixed_estimator).  contract_events, if given, is a
@@ -68,6 +125,9 @@ def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
     A.afqmc_philox_normal(ctx, seed, i, A.TAG_FIELD, nw, ctx.G, st.xi)
     A.afqmc_propagate(ctx, nw, st.phi, st.xi, st.xbar, st.phiT, st.logov, e_shift, st.w,
                       st.ref, st.logov_new, st.eloc)
+    following = bp is not None and bp.recording
+    if following:
+        bp.record(st)
     A.afqmc_metropolis_x(ctx, nw, st.phi, st.y, st.phiT, st.logov_new, st.ref, st.w, seed, i,
                          n_sweep, st.nacc)
     st.logov, st.logov_new = st.logov_new, st.logov
@@ -75,7 +135,9 @@ def step(ctx: A.Context, st: Walkers, seed: int, i: int, est_out: torch.Tensor,
         A.afqmc_reorthogonalize(ctx, nw, st.phi, st.logov)
     if n_pc and (i + 1) % n_pc == 0:
         A.afqmc_population_control(ctx, nw, st.phi, st.w, st.y, st.phiT, st.logov, seed, i, w_cap,
-                                   normalize=normalize)
+                                   parent=bp.parent if following else None, normalize=normalize)
+        if following:
+            bp.follow(nw)
 
 
 def init_walkers_metropolis(ctx: A.Context, nw: int, seed: int, n_pair: int = 10,
