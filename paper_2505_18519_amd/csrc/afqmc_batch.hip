@@ -312,8 +312,9 @@ afqmc_status build(afqmc_batch_s* b, const afqmc_system* systems, const int32_t*
     sys.can_small = sys.c->small;
     sys.family = sys.c->small ? 0 : 1;
     const size_t nw = sys.nw, M = sys.M, N = sys.N, P = sys.P, K = sys.K, G = sys.G;
+    const size_t tsz = (size_t)sys.c->tsz;  // doubles per trial determinant (complex: 2 M N)
     arena += al256(nw * 2 * M * N * 16) + al256(nw * 8) + al256(nw * P * K * 8) +
-             al256(nw * P * M * N * 8) + 2 * al256(nw * P * 16) + al256(nw * P * 2 * M * N * 16) +
+             al256(nw * P * tsz * 8) + 2 * al256(nw * P * 16) + al256(nw * P * 2 * M * N * 16) +
              al256(nw * G * 16) + al256(nw * 16) + al256(nw * G * 8) + al256(nw * 16) +
              al256(nw * 4) + al256((size_t)H * 16);
     size_t wsz = 0;
@@ -338,7 +339,7 @@ afqmc_status build(afqmc_batch_s* b, const afqmc_system* systems, const int32_t*
     sys.phi = (double*)take(nw * 2 * M * N * 16);
     sys.w = (double*)take(nw * 8);
     sys.y = (double*)take(nw * P * K * 8);
-    sys.phiT = (double*)take(nw * P * M * N * 8);
+    sys.phiT = (double*)take(nw * P * (size_t)sys.c->tsz * 8);
     sys.logov = (double*)take(nw * P * 16);
     sys.logov_new = (double*)take(nw * P * 16);
     sys.theta = (double*)take(nw * P * 2 * M * N * 16);

@@ -296,8 +296,8 @@ hipError_t launch_setup(afqmc_ctx_s* c) {
                      tmp + MM, tmp + 2 * MM, c->d_Eh);
   e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(c->stream);
-  hipFree(tmp);
-  return e != hipSuccess ? e : e2;
+  const hipError_t e3 = hipFree(tmp);
+  return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
 }
 
 hipError_t launch_philox_normal(const afqmc_ctx_s* c, uint64_t seed, uint64_t step, uint32_t tag,

@@ -21,7 +21,9 @@ namespace {
 // operands) and 64 matrix entries; L is read once per 16 walkers.  Row w of
 // xi starts at w * xs and of xbar at w * xbs; xbar may be null (c = xi): the
 // trial slices use this with the generators A_k and their block of y, the
-// back-propagation with a walker's recorded fields.
+// back-propagation with a walker's recorded fields.  XB = false (no xbar):
+// Q = 0 and only the R products run.
+template <bool XB>
 __global__ void __launch_bounds__(256)
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
@@ -53,8 +55,8 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
       const int kc = min(k, G - 1);
       const bool ok = wok && k < G;
       const double x = xi[(size_t)wa * xs + kc];
-      const double br = xbar ? xbar[((size_t)wa * xbs + kc) * 2] : 0.0;
-      const double bi = xbar ? xbar[((size_t)wa * xbs + kc) * 2 + 1] : 0.0;
+      const double br = XB ? xbar[((size_t)wa * xbs + kc) * 2] : 0.0;
+      const double bi = XB ? xbar[((size_t)wa * xbs + kc) * 2 + 1] : 0.0;
       cr[buf][q] = ok ? x - br : 0.0;
       ci[buf][q] = ok ? -bi : 0.0;
 #pragma unroll
@@ -70,7 +72,7 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
 #pragma unroll
       for (int et = 0; et < 4; ++et) {
         ar[et] = mfma_f64(cr[buf][q], b[buf][q][et], ar[et]);
-        ai[et] = mfma_f64(ci[buf][q], b[buf][q][et], ai[et]);
+        if (XB) ai[et] = mfma_f64(ci[buf][q], b[buf][q][et], ai[et]);
       }
   };
   load(0, 0);
@@ -290,8 +292,8 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (nw + 63) / 64), block(256);
-  hipLaunchKernelGGL(k_vbuild, grid, block, 0, c->stream, nw, c->G, MM, c->G, c->G, sqrt(c->dtau),
-                     c->d_Lraw, xi, xbar, vmat);
+  hipLaunchKernelGGL(k_vbuild<true>, grid, block, 0, c->stream, nw, c->G, MM, c->G, c->G,
+                     sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
 }
 
@@ -489,7 +491,11 @@ hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double 
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (n + 63) / 64);
-  hipLaunchKernelGGL(k_vbuild, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s, Lgen, y,
-                     xbar, vmat);
+  if (xbar != nullptr)
+    hipLaunchKernelGGL(k_vbuild<true>, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s,
+                       Lgen, y, xbar, vmat);
+  else
+    hipLaunchKernelGGL(k_vbuild<false>, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s,
+                       Lgen, y, xbar, vmat);
   return hipGetLastError();
 }

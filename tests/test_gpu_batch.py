@@ -1,5 +1,6 @@
 """Uneven batching through the C ABI: a batch of systems of different size,
-stepped by replays of one captured graph with parallel branches, gives every
+stepped by replays of one captured graph with parallel branches (real and
+complex trial families side by side), gives every
 system exactly the per-step estimates of that system run alone through the
 per-system calls with the same seed (the same kernels on the same inputs), and
 the autotuned batch runs and reports a valid plan."""
@@ -33,6 +34,8 @@ SYSTEMS = [
     (lambda: ai.small_gaussian(M=48, N=11, n_chol=40, K=12, seed=72), 3, 9, True),
     (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=73), 2, 5, False),
     (lambda: ai.tiny_ising(), 8, 16, False),
+    # a multi-slice (complex) trial: trial determinants twice the size
+    (lambda: ai.imaginary_time_trial(ai.tiny_ising(), 2, 0.05), 4, 12, True),
 ]
 DTAU, XCAP, WCAP, SEED = 0.01, 1.0, 4.0, 900
 
