@@ -197,6 +197,138 @@ def learned_study(args):
     print(json.dumps(out))
 
 
+def scan_study(args):
+    """Cost of one step against the number of tethered paths P and of
+    Metropolis sweeps (the synthetic analogue of the paper's statement that the
+    cost grows linearly with P and with the sweeps): the FP64 workload's
+    Hamiltonian and walker count, P in {1, 2, 4, 8, 16} at one sweep and
+    n_sweep in {1, 2, 4} at P = 8, each timed over the same number of steps."""
+    import torch
+    import afqmc_inputs as ai
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    sys_, run = ai.workload(1)
+    nw, seed = run.W, 2001
+    rows = []
+    for P, ns in [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (8, 2), (8, 4)]:
+        ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=1.0)
+        st = D.init_walkers(ctx, sys_.phi0, nw, seed)
+        est = torch.zeros(2, dtype=torch.float64, device="cuda")
+        for i in range(args.warmup):
+            D.step(ctx, st, seed, i, est, n_sweep=ns, n_qr=run.n_qr, n_pc=1, w_cap=4.0)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            D.step(ctx, st, seed, args.warmup + k, est, n_sweep=ns, n_qr=run.n_qr,
+                   contract_events=evs[k], n_pc=1, w_cap=4.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        rows.append({"P": P, "n_sweep": ns, "ms_per_step": 1e3 * dt / args.steps,
+                     "walker_steps_per_s": nw * args.steps / dt, "contraction_ms": cms})
+        print(f"P={P} n_sweep={ns}: {1e3 * dt / args.steps:.3f} ms/step (contraction {cms:.3f} ms)",
+              file=sys.stderr, flush=True)
+        ctx.close()
+    one = [r for r in rows if r["n_sweep"] == 1]
+    slope, icept = np.polyfit([r["P"] for r in one], [r["ms_per_step"] for r in one], 1)
+    ref = next(r for r in rows if r["P"] == 8 and r["n_sweep"] == 1)
+    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * 8
+    achieved = flops / (ref["contraction_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": ref["walker_steps_per_s"], "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ref["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"scan-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}-W{nw}",
+                   "walkers": nw},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "kernel": "k_contract (+ k_combine) in afqmc_local_energy, P = 8",
+                     "ms_per_launch": ref["contraction_ms"], "flops_per_launch": flops},
+        "scan": rows,
+        "linear_fit_ms_per_step_vs_P": {"slope_ms": float(slope), "intercept_ms": float(icept)},
+    }
+    print(json.dumps(out))
+
+
+def mixed_study(args):
+    """The mixed-precision form at fixed energy error on the FP64 workload's
+    system (M=64, N=16, 256 vectors, K=64, 512 walkers x 8 paths) with the
+    random-walk proposal (step 0.3), where long runs are stable: FP32-product
+    contraction and the all-FP64 form run the same steps from the same
+    walkers and seeds; energies reblocked over the timed steps, their
+    difference against the combined error bar, and the throughput of the
+    mixed form at the FP64 form's energy error.  (The mixed workload's own
+    system, M=128 with K=128, loses its path-sign average within a few tens
+    of steps, so its energies carry no usable error bar.)"""
+    import torch
+    import afqmc_inputs as ai
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    sys_, run = ai.workload(1)
+    nw, P, seed = run.W, run.P, 2002
+
+    def leg(prec):
+        ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=1.0,
+                        precision=prec, proposal=A.PROPOSAL_RW, rw_step=0.3)
+        st = D.init_walkers(ctx, sys_.phi0, nw, seed)
+        est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
+        for i in range(args.warmup):
+            D.step(ctx, st, seed, i, est[i], n_qr=run.n_qr, n_pc=1, w_cap=4.0)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            i = args.warmup + k
+            D.step(ctx, st, seed, i, est[i], n_qr=run.n_qr, contract_events=evs[k], n_pc=1,
+                   w_cap=4.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e = est.cpu().numpy()[args.warmup:]
+        en = e[:, 0] / e[:, 1]
+        ctx.close()
+        print(f"precision {prec}: {1e3 * dt / args.steps:.2f} ms/step, E = {en.mean():.6f} +- "
+              f"{reblock(en):.6f}", file=sys.stderr, flush=True)
+        return {"walker_steps_per_s": nw * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                "contraction_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
+                "energy": float(en.mean()), "energy_err": reblock(en),
+                "max_step_energy_difference": None, "series": en}
+
+    F32 = leg(A.PREC_FP32)
+    F64 = leg(A.PREC_FP64)
+    dmax = float(np.max(np.abs(F32["series"] - F64["series"])))
+    for d in (F32, F64):
+        d["max_step_energy_difference"] = dmax
+        del d["series"]
+    comb = float(np.hypot(F32["energy_err"], F64["energy_err"]))
+    ratio = (F32["walker_steps_per_s"] / F64["walker_steps_per_s"]) * (
+        (F64["energy_err"] ** 2) / max(F32["energy_err"] ** 2, 1e-300))
+    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
+    achieved = flops / (F32["contraction_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": F32["walker_steps_per_s"], "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": F32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-contraction/f64", "data": "synthetic",
+        "config": {"workload": f"mixed-vs-fp64-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}"
+                               f"-K{sys_.K}-W{nw}-P{P}-dtau{run.dtau}-rw0.3", "walkers": nw,
+                   "paths": P},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "kernel": "k_contract_g<float> (+ k_combine) in afqmc_local_energy",
+                     "ms_per_launch": F32["contraction_ms"], "flops_per_launch": flops},
+        "fp32_products": F32, "fp64": F64,
+        "energy_difference": F32["energy"] - F64["energy"], "combined_error": comb,
+        "equal_error_throughput_ratio": ratio,
+    }
+    print(json.dumps(out))
+
+
 def uneven_study(args):
     """Uneven batch (32 systems, M in [24, 128], N = M/4, 4M vectors, K = M/2,
     walkers log-uniform in [64, 1024], 4 paths): aggregate walker-steps/s of the
@@ -286,7 +418,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fp64",
-                    choices=sorted(WORKLOADS) + ["learned", "uneven"])
+                    choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "mixed-study"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (the plain copy kernel that "
                          "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -319,6 +451,12 @@ def main():
         return
     if args.workload == "uneven":
         uneven_study(args)
+        return
+    if args.workload == "scan":
+        scan_study(args)
+        return
+    if args.workload == "mixed-study":
+        mixed_study(args)
         return
 
     widx, precision, peak, dtype = WORKLOADS[args.workload]
