@@ -126,9 +126,13 @@ typedef struct {
  * for the default stream).  Host arrays may be freed on return.
  * Supported sizes: 1 <= N <= M <= 128, N <= 32, n_chol >= 1, K >= 1,
  * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  The learned proposal
- * needs Gaussian hidden variables and K <= 128.  Systems with M <= 64 and
- * N <= 16 use register-resident kernels, larger ones workgroup-per-path
- * kernels.  Synchronises `stream`. */
+ * needs Gaussian hidden variables and K <= 128.  Real-trial systems with
+ * M <= 64 and N <= 16 use register-resident kernels, larger ones (and every
+ * multi-slice trial) workgroup-per-path kernels.  Multi-slice trials need
+ * ceil(M/16) ceil(N/16) <= 8 (AFQMC_E_UNSUPPORTED otherwise), Gaussian hidden
+ * variables and a non-learned proposal.  Invalid arguments (missing arrays,
+ * non-finite dtau or coupling, an unknown mode) return AFQMC_E_INVALID.
+ * Synchronises `stream`. */
 afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afqmc_ctx* out);
 afqmc_status afqmc_destroy(afqmc_ctx ctx);
 /* Text of the last error on this context (static storage owned by ctx). */
