@@ -41,7 +41,7 @@ WORKLOADS = {
 # the plain-copy calibration (profiles/traffic_k_contract_*.md), valid while the
 # kernel source is the one measured: workload -> (source file, sha256 prefix, bytes)
 TRAFFIC = {
-    "fp64": ("k_contract.hip", "80d1dfe0ae71f6d8", 454600364),
+    "fp64": ("k_contract.hip", "84a10461fe9f869b", 454528640),
 }
 
 

@@ -12,17 +12,26 @@
 // Layout on gfx950: one wavefront per path, CW wavefronts per workgroup.  The
 // path's Phi_T and Theta live in registers as FP64-MFMA B operands for the
 // whole loop over g.  L_g is double-buffered in LDS and shared by the CW
-// wavefronts.  Stage 1 (Y_g^T = L_g Phi_T) leaves Y_g in the accumulator
-// layout, which is exactly the A-operand layout of stage 2 when the
-// contraction index m is visited in the order m = 16 t + 4 r + g, so the two
-// stages chain in registers.  tr(f f) needs f transposed: it goes through a
-// per-wave 8 KB LDS tile.  Nothing of size n_chol x N^2 touches HBM.
+// wavefronts; each slab goes from global memory straight into LDS
+// (global_load_lds, 16 bytes per lane), issued once the current slab's
+// stage-1 reads are out, so no registers hold it in flight.  Stage 1
+// (Y_g^T = L_g Phi_T) leaves Y_g in the accumulator layout, which is exactly
+// the A-operand layout of stage 2 when the contraction index m is visited in
+// the order m = 16 t + 4 r + g, so the two stages chain in registers; its A
+// operands are read from LDS one step ahead.  tr(f f) needs f transposed: it
+// goes through a per-wave LDS tile, and that tail of vector g - 1 is issued
+// ahead of stage 1 of vector g, so its LDS traffic overlaps the matrix core.
+// Nothing of size n_chol x N^2 touches HBM.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
 namespace {
 
 constexpr int CW = 4;  // wavefronts (paths) per workgroup
+constexpr int FL = 16;  // vectors per flush of the staged diagonals
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
 template <int MT>
 __global__ void __launch_bounds__(CW * 64)
@@ -31,11 +40,11 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
            const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   constexpr int NTILE = MT / 16;
   constexpr int SLAB = MT * MT;
-  constexpr int NV2 = SLAB / 2;                        // 16-byte vectors per slab
-  constexpr int NQ = (NV2 + CW * 64 - 1) / (CW * 64);  // per thread
-  __shared__ double s_L[2][SLAB];
+  constexpr int NCH = SLAB / 128;  // 1 KB chunks of a slab: 64 lanes x 16 bytes
+  constexpr int KS = 4 * NTILE;    // steps of the contraction index in stage 1
+  __shared__ __attribute__((aligned(16))) double s_L[2][SLAB];
   __shared__ double s_f[CW][4][16][17];
-  __shared__ double s_dg[CW][16][2][16];  // diagonal partials of 16 vectors
+  __shared__ double s_dg[CW][FL][2][17];  // diagonal partials; column 16 takes the other lanes
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -44,6 +53,16 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
   const int s = blockIdx.x * CW + wave;
   bool active = s < n_samples;
   if (active) active = !__builtin_isinf(logov[2 * s]);  // singular paths contribute zero
+
+  // slab copies go from global memory straight into LDS; wave w takes chunks w, w + CW, ...
+  auto copy_slab = [&](int slab, int buf) {
+    const double* src = Lpad + (size_t)slab * SLAB;
+#pragma unroll
+    for (int k = wave; k < NCH; k += CW)
+      __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 128 + lane * 2),
+                                       (lds_ptr_t)(s_L[buf] + k * 128), 16, 0, 0);
+  };
+  copy_slab(0, 0);
 
   // B operands: bT[t][r] = Phi_T[16t+4r+g][c]; bth[sp][ri][t][r] = Theta^sp[16t+4r+g][c]
   double bT[NTILE][4];
@@ -63,35 +82,98 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
       }
     }
 
-  // stage slab 0
-  {
-    const double2* src = reinterpret_cast<const double2*>(Lpad);
-    double2* dst = reinterpret_cast<double2*>(s_L[0]);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (tid + q * CW * 64 < NV2) dst[tid + q * CW * 64] = src[tid + q * CW * 64];
-  }
-  __syncthreads();
-
-  double vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
-  double ex_re = 0.0, ex_im = 0.0;
+  double vb2_re = 0.0, vb2_im = 0.0, ex_re = 0.0, ex_im = 0.0;
   double(*sf)[16][17] = s_f[wave];
-  double(*sdg)[2][16] = s_dg[wave];
+  double(*sdg)[2][17] = s_dg[wave];
   // lanes holding a diagonal element f[c][c] (c = g + 4 r): r = c / 4 when c % 4 == g
-  const bool diag_lane = (c & 3) == g;
-  // bulk reduction of 16 staged vectors: lane l < 32 sums part l / 16 of vector l % 16
+  const int dcol = ((c & 3) == g) ? c : 16;
+
+  // stage 1: y1[tp] = (L_g Phi_T)[16tp + 4r + g][c], A operands read one step ahead
+  auto stage1 = [&](const double* Ls, dx4 (&y1)[NTILE]) {
+#pragma unroll
+    for (int tp = 0; tp < NTILE; ++tp) y1[tp] = dx4_zero();
+    double ac[NTILE], an[NTILE];
+#pragma unroll
+    for (int tp = 0; tp < NTILE; ++tp) ac[tp] = Ls[g * MT + 16 * tp + c];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      if (k + 1 < KS) {
+#pragma unroll
+        for (int tp = 0; tp < NTILE; ++tp) an[tp] = Ls[(4 * (k + 1) + g) * MT + 16 * tp + c];
+      }
+      // A[c][g] = L[16tp+c][16t+4r+g] = L[16t+4r+g][16tp+c] (L symmetric), k = 4t + r
+#pragma unroll
+      for (int tp = 0; tp < NTILE; ++tp) y1[tp] = mfma_f64(ac[tp], bT[k >> 2][k & 3], y1[tp]);
+      if (k + 1 < KS) {
+#pragma unroll
+        for (int tp = 0; tp < NTILE; ++tp) ac[tp] = an[tp];
+      }
+    }
+  };
+  // stage 2: f[sp][ri] = sum_m Y[c'][m] Theta^sp[m][c]  (rows g+4r, col c)
+  auto stage2 = [&](const dx4 (&y1)[NTILE], dx4 (&f)[2][2]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) f[sp][0] = f[sp][1] = dx4_zero();
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) f[sp][ri] = mfma_f64(y1[t][r], bth[sp][ri][t][r], f[sp][ri]);
+  };
+  // diagonal of f summed over the spins, in the lanes that hold one (0 elsewhere)
+  auto diag = [&](const dx4 (&f)[2][2], double& d_re, double& d_im) {
+    d_re = 0.0;
+    d_im = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (c == g + 4 * r) {
+        d_re = f[0][0][r] + f[1][0][r];
+        d_im = f[0][1][r] + f[1][1][r];
+      }
+  };
+  // tail of vector gv: stage its diagonal for vb_gv and add sum_ij f_ij f_ji to ex.  The
+  // transpose goes through this wave's LDS tile.  LDS operations of one wavefront execute in
+  // order, so the reads see the writes without a wait in between; the wave barrier only
+  // keeps the compiler from moving the reads above the writes.
+  auto tail = [&](const dx4 (&f)[2][2], int gv) {
+    double d_re, d_im;
+    diag(f, d_re, d_im);
+    sdg[gv % FL][0][dcol] = d_re;
+    sdg[gv % FL][1][dcol] = d_im;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sf[2 * sp + ri][g + 4 * r][c] = f[sp][ri][r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double tr_ = sf[2 * sp][c][g + 4 * r];
+        const double ti_ = sf[2 * sp + 1][c][g + 4 * r];
+        const double ar = f[sp][0][r], ai = f[sp][1][r];
+        ex_re += ar * tr_ - ai * ti_;
+        ex_im += ar * ti_ + ai * tr_;
+      }
+  };
+  // bulk reduction of FL staged vectors: lane l < 2 FL sums part l / FL of vector l % FL
   auto flush = [&](int g_first, int count) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int gl = lane & 15, part = (lane >> 4) & 1;
+    const int gl = lane % FL, part = (lane / FL) & 1;
     double v = 0.0;
-    if (lane < 32 && gl < count) {
+    if (lane < 2 * FL && gl < count) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) v += sdg[gl][part][q];
     }
-    const double vi = __shfl_down(v, 16, 64);  // lanes < 16: imaginary part
-    if (lane < 16 && gl < count) {
+    const double vi = __shfl_down(v, FL, 64);  // lanes < FL: imaginary part
+    if (lane < FL && gl < count) {
       vb2_re += v * v - vi * vi;
       vb2_im += 2.0 * v * vi;
       double* o = vb + ((size_t)s * G + g_first + gl) * 2;
@@ -103,107 +185,48 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   };
 
-  for (int gam = 0; gam <= G; ++gam) {
-    const int b = gam & 1;
-    // prefetch the next slab into registers
-    // (loads are unconditional, clamped to the slab, and held in one vector
-    //  value so that they stay in registers)
-    typedef double vpre_t __attribute__((ext_vector_type(2 * NQ)));
-    vpre_t pre;
-    const bool has_next = gam < G;
-    {
-      const double2* src =
-          reinterpret_cast<const double2*>(Lpad + (size_t)(has_next ? gam + 1 : gam) * SLAB);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const double2 v = src[min(tid + q * CW * 64, NV2 - 1)];
-        pre[2 * q] = v.x;
-        pre[2 * q + 1] = v.y;
-      }
-    }
-    if (active) {
-      const double* Ls = s_L[b];
-      // stage 1: y1[tp] = (L_g Phi_T)[16tp + 4r + g][c]
-      dx4 y1[NTILE];
-#pragma unroll
-      for (int tp = 0; tp < NTILE; ++tp) y1[tp] = dx4_zero();
-#pragma unroll
-      for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int tp = 0; tp < NTILE; ++tp) {
-            // A[i=c][k=g] = L[16tp+c][16t+4r+g] = L[16t+4r+g][16tp+c] (L symmetric)
-            const double av = Ls[(16 * t + 4 * r + g) * MT + 16 * tp + c];
-            y1[tp] = mfma_f64(av, bT[t][r], y1[tp]);
-          }
-      // stage 2: f[sp][ri] = sum_m Y[c'][m] Theta^sp[m][c]  (rows g+4r, col c)
-      dx4 f[2][2];
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp) f[sp][0] = f[sp][1] = dx4_zero();
-#pragma unroll
-      for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri)
-              f[sp][ri] = mfma_f64(y1[t][r], bth[sp][ri][t][r], f[sp][ri]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
+  __syncthreads();
+  // vector 0: both stages; its tail runs during stage 1 of vector 1
+  dx4 f[2][2];
+  if (active) {
+    dx4 y1[NTILE];
+    stage1(s_L[0], y1);
+    copy_slab(G > 0 ? 1 : 0, 1);
+    stage2(y1, f);
+  } else {
+    copy_slab(G > 0 ? 1 : 0, 1);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
 
-      // diagonal: element (g+4r, c) with c == g+4r, summed over the spins
-      double d_re = 0.0, d_im = 0.0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (c == g + 4 * r) {
-          d_re = f[0][0][r] + f[1][0][r];
-          d_im = f[0][1][r] + f[1][1][r];
-        }
-      if (gam < G) {
-        // stage this lane's diagonal element; vb_g = sum over the 16 lanes
-        if (diag_lane) {
-          sdg[gam & 15][0][c] = d_re;
-          sdg[gam & 15][1][c] = d_im;
-        }
-        // exchange: sum_ij f_ij f_ji, transpose through LDS
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sf[2 * sp + ri][g + 4 * r][c] = f[sp][ri][r];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double tr_ = sf[2 * sp][c][g + 4 * r];
-            const double ti_ = sf[2 * sp + 1][c][g + 4 * r];
-            const double ar = f[sp][0][r], ai = f[sp][1][r];
-            ex_re += ar * tr_ - ai * ti_;
-            ex_im += ar * ti_ + ai * tr_;
-          }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if ((gam & 15) == 15 || gam == G - 1) flush(gam & ~15, (gam & 15) + 1);
-      } else {
-        e1_re = wave_sum(d_re);
-        e1_im = wave_sum(d_im);
-      }
+  // slab gam is in buffer gam & 1; slab G is h1', whose diagonal gives the one-body term
+  for (int gam = 1; gam <= G; ++gam) {
+    const int b = gam & 1;
+    const int nxt = gam < G ? gam + 1 : gam;  // the last copy repeats a slab no one reads
+    if (active) {
+      dx4 y1[NTILE];
+      tail(f, gam - 1);
+      stage1(s_L[b], y1);
+      // buffer b ^ 1 was last read in the previous iteration, which the barrier closed
+      copy_slab(nxt, b ^ 1);
+      stage2(y1, f);
+      if ((gam - 1) % FL == FL - 1 || gam == G) flush(gam - 1 - (gam - 1) % FL, (gam - 1) % FL + 1);
+    } else {
+      copy_slab(nxt, b ^ 1);
     }
-    if (has_next) {
-      double2* dst = reinterpret_cast<double2*>(s_L[b ^ 1]);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (tid + q * CW * 64 < NV2) dst[tid + q * CW * 64] = make_double2(pre[2 * q], pre[2 * q + 1]);
-    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
     __syncthreads();
   }
 
   if (s < n_samples) {
+    double e1_re = 0.0, e1_im = 0.0;
+    if (active) {
+      double d_re, d_im;
+      diag(f, d_re, d_im);
+      e1_re = wave_sum(d_re);
+      e1_im = wave_sum(d_im);
+    }
     ex_re = wave_sum(ex_re);
     ex_im = wave_sum(ex_im);
     vb2_re = wave_sum(vb2_re);

@@ -129,3 +129,56 @@ def test_bp_trajectory_follows_the_comb(sysname):
     assert np.abs(g[:-1].reshape(s.M, s.M) - num).max() <= 1e-9 * np.abs(num).max()
     assert abs(g[-1] - den) <= 1e-9 * den
     assert np.abs(host(bp.rho) - Rk).max() <= 1e-9 * np.abs(Rk).max()
+
+
+def test_entry_points_reject_bad_arguments_and_accept_empty_calls():
+    """Argument errors are reported (AfqmcError), never faults; nw = 0 is a no-op."""
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+    s = ai.tiny_ising()
+    ctx = A.Context(s, 4, 0.01, max_walkers=4)
+    bp = D.BackProp(ctx, 4, 3)
+    xi = torch.zeros(4, s.n_chol, dtype=torch.float64, device="cuda")
+    xb = torch.zeros(4, s.n_chol, dtype=torch.complex128, device="cuda")
+    with pytest.raises(A.AfqmcError):           # slot outside [0, h)
+        A.afqmc_bp_record(ctx, 4, 3, 3, xi, xb, bp.hist_xi, bp.hist_xbar)
+    with pytest.raises(A.AfqmcError):           # h < 1
+        A._check(ctx, A.load_library().afqmc_bp_record(ctx.handle, 4, 0, 0, None, None, None,
+                                                        None), "bp_record")
+    with pytest.raises(A.AfqmcError):           # negative history length
+        A._check(ctx, A.load_library().afqmc_bp_density(ctx.handle, 4, -1, None, None, None, None,
+                                                         None, None, None, None, None, None,
+                                                         None), "bp_density")
+    with pytest.raises(A.AfqmcError):           # p_src < 1
+        A._check(ctx, A.load_library().afqmc_extend_paths(ctx.handle, 4, 0, None, None, None,
+                                                           None, None, None), "extend_paths")
+    with pytest.raises(A.AfqmcError):           # negative copy length
+        A._check(ctx, A.load_library().afqmc_copy(ctx.handle, -1, None, None), "copy")
+    # empty calls succeed without touching their (absent) arrays
+    lib = A.load_library()
+    assert lib.afqmc_bp_record(ctx.handle, 0, 3, 0, None, None, None, None) == 0
+    assert lib.afqmc_bp_density(ctx.handle, 0, 2, None, None, None, None, None, None, None, None,
+                                None, None, None) == 0
+    assert lib.afqmc_gather_rows(ctx.handle, 0, None, 8, None, None) == 0
+    assert lib.afqmc_gather_rows(ctx.handle, 4, None, 0, None, None) == 0
+    assert lib.afqmc_copy(ctx.handle, 0, None, None) == 0
+    assert lib.afqmc_init_metropolis(ctx.handle, 0, 1, 2, 2, None, None, None, None, None,
+                                     None) == 0
+    assert lib.afqmc_extend_paths(ctx.handle, 0, 1, None, None, None, None, None, None) == 0
+    # the corrected estimator always writes its two sums, so it needs its arrays even at nw = 0
+    assert lib.afqmc_estimator_corrected(ctx.handle, 0, None, None, None, 1, None, None,
+                                         None) == 1
+    one = torch.ones(8, dtype=torch.float64, device="cuda")
+    onec = torch.ones(8, dtype=torch.complex128, device="cuda")
+    out = torch.full((2,), 7.0, dtype=torch.float64, device="cuda")
+    A.afqmc_estimator_corrected(ctx, 0, one, onec, onec, 1, onec, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), [0.0, 0.0])
+    # gather with a parent out of range copies nothing for that row
+    src = torch.arange(12, dtype=torch.float64, device="cuda").reshape(4, 3)
+    dst = torch.full((4, 3), -1.0, dtype=torch.float64, device="cuda")
+    par = torch.tensor([3, 7, -2, 0], dtype=torch.int32, device="cuda")
+    A.afqmc_gather_rows(ctx, 4, par, src, dst)
+    torch.cuda.synchronize()
+    ref = np.array([[9, 10, 11], [-1, -1, -1], [-1, -1, -1], [0, 1, 2]], dtype=float)
+    assert np.array_equal(host(dst), ref)
