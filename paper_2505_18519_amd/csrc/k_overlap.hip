@@ -8,9 +8,14 @@
 //     spin down), pivot rows found by a 16-lane max reduction (largest |a|^2,
 //     lowest row on ties) and broadcast by lane shuffles instead of swapped;
 //     det = parity(perm) prod u_kk, accumulated as a scaled complex product;
-//  3. optionally Theta^s = phi^s (A^s)^{-1}, one lane per orbital row m:
-//     z U = x, v L = z, Theta[m][perm[k]] = v[k]; and optionally the Green's
-//     function diagonal Re (G_up + G_dn)_mm = Re sum_s sum_n Theta^s_mn Phi_T,mn.
+//  3. optionally Theta^s = phi^s (A^s)^{-1}: lanes (spin, j) solve the unit rows
+//     e_j X^s = e_j (A^s)^{-1} with the factors (z U = e_j, v L = z,
+//     X[j][perm[k]] = v[k]), X^s replaces the factors in LDS, and
+//     Theta^s = phi^s X^s runs on the matrix cores (four real products per
+//     spin), stored as whole 16-byte complex entries along each row;
+//     with the Green's function diagonal Re (G_up + G_dn)_mm =
+//     Re sum_s sum_n Theta^s_mn Phi_T,mn requested, one lane per orbital row m
+//     solves x (A^s)^{-1} for its row of phi instead.
 // A zero pivot marks the path singular: l = -inf + 0i and Theta = 0, diag = 0.
 #include "afqmc_internal.h"
 #include "dev_common.h"
@@ -21,7 +26,7 @@ constexpr int OV_WAVES = 4;
 constexpr int NT = 16;  // N <= 16
 
 template <int MT>
-__global__ void __launch_bounds__(OV_WAVES * 64)
+__global__ void __launch_bounds__(OV_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
           const double* __restrict__ phiT, double* __restrict__ logov, double* __restrict__ theta,
           double* __restrict__ gdiag) {
@@ -184,7 +189,100 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
-  // 3. Theta rows: lane = orbital row m
+  if (gdiag == nullptr) {
+    // 3. X^s = (A^s)^{-1}: lane (spin, j) < 32 solves e_j X = e_j A^{-1} with the
+    //    factors (z U = e_j, v L = z, X[j][perm[k]] = v[k]); rows j >= N stay zero
+    const int jr = c, spn = (lane >> 4) & 1;
+    const bool solver = lane < 32 && jr < N;
+    cplx x[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) x[j] = cmk(j == jr ? 1.0 : 0.0, 0.0);
+    if (solver) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        if (j < N) {
+          cplx acc2 = x[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k)
+            acc2 = cfms(acc2, x[k], cmk(s_lu[wave][spn][k][j][0], s_lu[wave][spn][k][j][1]));
+          x[j] = cdiv(acc2, cmk(s_lu[wave][spn][j][j][0], s_lu[wave][spn][j][j][1]));
+        }
+      }
+#pragma unroll
+      for (int j = NT - 1; j >= 0; --j) {
+        if (j < N) {
+          cplx acc2 = x[j];
+#pragma unroll
+          for (int k = j + 1; k < NT; ++k)
+            if (k < N)
+              acc2 = cfms(acc2, x[k], cmk(s_lu[wave][spn][k][j][0], s_lu[wave][spn][k][j][1]));
+          x[j] = acc2;
+        }
+      }
+    }
+    int pcol[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) pcol[k] = min(max(s_perm[wave][spn][k], 0), NT - 1);
+    // every lane of the wave has issued its factor reads: X replaces the factors in LDS
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < 32) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {  // unused columns first, then the solved row
+        s_lu[wave][spn][jr][k][0] = 0.0;
+        s_lu[wave][spn][jr][k][1] = 0.0;
+      }
+      if (solver) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+          if (k < N) {
+            s_lu[wave][spn][jr][pcol[k]][0] = x[k].re;
+            s_lu[wave][spn][jr][pcol[k]][1] = x[k].im;
+          }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // 4. Theta^s = phi^s X^s on the matrix cores: A[c][g] = phi[16t + c][4q + g],
+    //    B[g][c] = X[4q + g][c]; the lane holds Theta[16t + g + 4r][c]
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin) {
+      double xr[4], xi[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xr[q] = s_lu[wave][spin][4 * q + g][c][0];
+        xi[q] = s_lu[wave][spin][4 * q + g][c][1];
+      }
+#pragma unroll
+      for (int t = 0; t < MT / 16; ++t) {
+        dx4 tr = dx4_zero(), ti = dx4_zero();
+        const int m = 16 * t + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n = 4 * q + g;
+          double2 v = make_double2(0.0, 0.0);
+          if (m < M && n < N)
+            v = *reinterpret_cast<const double2*>(pw + ((size_t)(spin * M + m) * N + n) * 2);
+          tr = mfma_f64(v.x, xr[q], tr);
+          tr = mfma_f64(-v.y, xi[q], tr);
+          ti = mfma_f64(v.x, xi[q], ti);
+          ti = mfma_f64(v.y, xr[q], ti);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mo = 16 * t + g + 4 * r;
+          if (mo < M && c < N)
+            *reinterpret_cast<double2*>(th + ((size_t)(spin * M + mo) * N + c) * 2) =
+                make_double2(tr[r], ti[r]);
+        }
+      }
+    }
+    return;
+  }
+
+  // 3. Theta rows with the Green's function diagonal: lane = orbital row m
   for (int m0 = 0; m0 < M; m0 += 64) {
     double gsum = 0.0;
     for (int spin = 0; spin < 2; ++spin) {

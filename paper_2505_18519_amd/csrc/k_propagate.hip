@@ -24,7 +24,7 @@ namespace {
 // back-propagation with a walker's recorded fields.  XB = false (no xbar):
 // Q = 0 and only the R products run.
 template <bool XB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
