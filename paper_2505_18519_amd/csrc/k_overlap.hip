@@ -5,8 +5,9 @@
 //  1. A^s = Phi_T^T phi^s (N x N complex) on the FP64 matrix cores, operands
 //     read straight from HBM (real trial times the re / im parts of phi);
 //  2. LU with partial pivoting, one lane per row (lanes 0-15 spin up, 16-31
-//     spin down), pivot rows found by a 16-lane max reduction (largest |a|^2,
-//     lowest row on ties) and broadcast by lane shuffles instead of swapped;
+//     spin down), pivot rows found by a 16-lane max reduction over DPP moves
+//     (largest |a|^2, lowest row on ties) and broadcast by lane shuffles
+//     instead of swapped;
 //     det = parity(perm) prod u_kk, accumulated as a scaled complex product;
 //  3. optionally Theta^s = phi^s (A^s)^{-1}: lanes (spin, j) solve the unit rows
 //     e_j X^s = e_j (A^s)^{-1} with the factors (z U = e_j, v L = z,
@@ -24,6 +25,20 @@ namespace {
 
 constexpr int OV_WAVES = 4;
 constexpr int NT = 16;  // N <= 16
+
+// value of the lane that DPP control CTRL selects within this lane's 16-lane row
+// (0xB1: lane xor 1, 0x4E: lane xor 2, 0x141: mirrored within 8, 0x140: mirrored within 16)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffLL));
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 template <int MT>
 __global__ void __launch_bounds__(OV_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
@@ -101,15 +116,18 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       double v = used ? -1.0 : cabs2(a[k]);
       if (!used && !(v >= 0.0)) v = 0.0;
       int idx = used ? 1000 : i;
-#pragma unroll
-      for (int o = 8; o >= 1; o >>= 1) {
-        double v2 = __shfl_xor(v, o, 64);
-        int i2 = __shfl_xor(idx, o, 64);
+      // across the 16-lane row with DPP moves (VALU latency, no LDS round trip):
+      // partner lane xor 1, xor 2, then the mirrored quad, then the mirrored half
+      auto take = [&](double v2, int i2) {
         if (v2 > v || (v2 == v && i2 < idx)) {
           v = v2;
           idx = i2;
         }
-      }
+      };
+      take(dpp_f64<0xB1>(v), dpp_i32<0xB1>(idx));
+      take(dpp_f64<0x4E>(v), dpp_i32<0x4E>(idx));
+      take(dpp_f64<0x141>(v), dpp_i32<0x141>(idx));
+      take(dpp_f64<0x140>(v), dpp_i32<0x140>(idx));
       const int prow = idx;  // uniform within the group
       perm[k] = prow;
       const int src = base + (prow & 15);

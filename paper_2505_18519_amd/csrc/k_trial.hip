@@ -18,18 +18,30 @@ namespace {
 constexpr int TB_WAVES = 4;
 constexpr int MAX_TERMS = 128;
 
-// U[s][e] = c sum_k y[s][k] A[k][e]; block = 4 wavefronts x 16 paths, 64 entries
-__global__ void __launch_bounds__(256)
+// U[s][e] = c sum_k y[s][k] A[k][e]; block = 4 wavefronts x UB_PT * 16 paths, 64 entries.
+// Each wavefront keeps UB_PT path tiles x 4 entry tiles of accumulators, so every
+// generator entry it loads feeds UB_PT products and every y entry four.
+constexpr int UB_PT = 2;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
          const double* __restrict__ A, double* __restrict__ U) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
-  const int s0 = (blockIdx.y * 4 + wave) * 16;
+  const int s0 = (blockIdx.y * 4 + wave) * 16 * UB_PT;
   const int e0 = blockIdx.x * 64;
   if (s0 >= S) return;
-  dx4 acc[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
-  const int sa = min(s0 + c, S - 1);
-  const bool sok = (s0 + c) < S;
+  dx4 acc[UB_PT][4];
+#pragma unroll
+  for (int pt = 0; pt < UB_PT; ++pt)
+#pragma unroll
+    for (int et = 0; et < 4; ++et) acc[pt][et] = dx4_zero();
+  int sa[UB_PT];
+  bool sok[UB_PT];
+#pragma unroll
+  for (int pt = 0; pt < UB_PT; ++pt) {
+    sa[pt] = min(s0 + 16 * pt + c, S - 1);
+    sok[pt] = (s0 + 16 * pt + c) < S;
+  }
   int ec[4];
   bool eok[4];
 #pragma unroll
@@ -41,14 +53,17 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
   // batches of KB k-steps, double-buffered (loads of batch i+1 before the
   // MFMAs of batch i), loads clamped in range and masked after the load
   constexpr int KB = 4;
-  double a[2][KB], b[2][KB][4];
+  double a[2][KB][UB_PT], b[2][KB][4];
   auto load = [&](int k0, int buf) {
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const int k = k0 + 4 * q + g;
       const int kc = min(k, K - 1);
-      const double ya = y[(size_t)sa * K + kc];
-      a[buf][q] = (sok && k < K) ? ya : 0.0;
+#pragma unroll
+      for (int pt = 0; pt < UB_PT; ++pt) {
+        const double ya = y[(size_t)sa[pt] * K + kc];
+        a[buf][q][pt] = (sok[pt] && k < K) ? ya : 0.0;
+      }
 #pragma unroll
       for (int et = 0; et < 4; ++et) {
         const double v = A[(size_t)kc * MM + ec[et]];
@@ -60,7 +75,10 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
 #pragma unroll
     for (int q = 0; q < KB; ++q)
 #pragma unroll
-      for (int et = 0; et < 4; ++et) acc[et] = mfma_f64(a[buf][q], b[buf][q][et], acc[et]);
+      for (int pt = 0; pt < UB_PT; ++pt)
+#pragma unroll
+        for (int et = 0; et < 4; ++et)
+          acc[pt][et] = mfma_f64(a[buf][q][pt], b[buf][q][et], acc[pt][et]);
   };
   load(0, 0);
   for (int k0 = 0; k0 < K; k0 += 8 * KB) {
@@ -71,12 +89,14 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
     compute(1);
   }
 #pragma unroll
-  for (int et = 0; et < 4; ++et)
+  for (int pt = 0; pt < UB_PT; ++pt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int s = s0 + g + 4 * r, e = e0 + 16 * et + c;
-      if (s < S && e < MM) U[(size_t)s * MM + e] = coupling * acc[et][r];
-    }
+    for (int et = 0; et < 4; ++et)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = s0 + 16 * pt + g + 4 * r, e = e0 + 16 * et + c;
+        if (s < S && e < MM) U[(size_t)s * MM + e] = coupling * acc[pt][et][r];
+      }
 }
 
 template <int MT>
@@ -197,7 +217,7 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
                               double* ubuf) {
   if (n_samples <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (n_samples + 63) / 64);
+  dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
   hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
                      c->d_A, ubuf);
   AFQMC_LAUNCH_CHECK();
@@ -376,7 +396,7 @@ hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const doubl
   if (n_samples <= 0) return hipSuccess;
   if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
   const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (n_samples + 63) / 64);
+  dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
   hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
                      c->d_A, ubuf);
   AFQMC_LAUNCH_CHECK();
