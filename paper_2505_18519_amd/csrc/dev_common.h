@@ -77,6 +77,37 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// value of the lane that DPP control CTRL selects within this lane's 16-lane row
+// (0xB1: lane xor 1, 0x4E: lane xor 2, 0x141: mirrored within 8, 0x140: mirrored within 16)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffLL));
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// wave_max for code where all 64 lanes are active: DPP moves within each 16-lane
+// row, then the four row results by readlane; no LDS round trips.  fmax ignores
+// NaN and is order-independent, so the result equals wave_max's.
+__device__ __forceinline__ double wave_max_full(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 256-bit counter, 128-bit key.
 

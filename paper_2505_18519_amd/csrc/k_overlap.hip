@@ -26,20 +26,6 @@ namespace {
 constexpr int OV_WAVES = 4;
 constexpr int NT = 16;  // N <= 16
 
-// value of the lane that DPP control CTRL selects within this lane's 16-lane row
-// (0xB1: lane xor 1, 0x4E: lane xor 2, 0x141: mirrored within 8, 0x140: mirrored within 16)
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffLL));
-  const int hi = dpp_i32<CTRL>((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 template <int MT>
 __global__ void __launch_bounds__(OV_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,

@@ -130,7 +130,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
     rs += __shfl_xor(rs, 32, 64);
     rownorm = fmax(rownorm, rs);
   }
-  rownorm = wave_max(rownorm);
+  rownorm = wave_max_full(rownorm);
   // a non-finite U gives a non-finite Phi_T after one stage; the stage count
   // is bounded so that every wavefront finishes
   int nstage = 1;
@@ -187,8 +187,8 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
           tmax = fmax(tmax, fabs(term[t][r]));
           smax = fmax(smax, fabs(sum[t][r]));
         }
-      tmax = wave_max(tmax);
-      smax = wave_max(smax);
+      tmax = wave_max_full(tmax);
+      smax = wave_max_full(smax);
       if (tmax <= 0x1.0p-60 * smax) break;
     }
   }
@@ -263,7 +263,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
     }
   rs += __shfl_xor(rs, 16, 64);
   rs += __shfl_xor(rs, 32, 64);
-  rs = wave_max(rs);
+  rs = wave_max_full(rs);
   if (lane == 0) sred[tp * 2] = rs;
   // Phi_0 into buffer 0 and into the running sum (my rows)
   for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
@@ -326,8 +326,8 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
         }
       const bool check = (j & 1) == 0;
       if (check) {
-        tmax = wave_max(tmax);
-        smax = wave_max(smax);
+        tmax = wave_max_full(tmax);
+        smax = wave_max_full(smax);
         if (lane == 0) {
           sred[tp * 2] = tmax;
           sred[tp * 2 + 1] = smax;
