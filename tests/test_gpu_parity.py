@@ -51,6 +51,11 @@ CASES = {
     "gauss-M20-N5-ragged": (lambda: ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5), 3, 6),
     "gauss-M48-N11": (lambda: ai.small_gaussian(M=48, N=11, n_chol=40, K=12, seed=6), 4, 3),
     "cfg-M64-N16-G256": (lambda: ai.workload(1)[0], 8, 3),
+    # edge shapes of the wavefront-per-path kernels: a single Cholesky vector and a
+    # single path; 17 vectors (one flush of 16 staged diagonals plus a ragged one)
+    # with 15 paths (a last workgroup with idle wavefronts)
+    "gauss-M32-N8-G1-P1": (lambda: ai.small_gaussian(M=32, N=8, n_chol=1, K=4, seed=10), 1, 4),
+    "gauss-M64-N16-G17-P5": (lambda: ai.small_gaussian(M=64, N=16, n_chol=17, K=8, seed=11), 5, 3),
     # workgroup-per-path kernels (M > 64 or N > 16)
     "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
     "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
