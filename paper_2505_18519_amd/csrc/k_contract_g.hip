@@ -17,6 +17,13 @@
 // FP32 with FP32 accumulation over m; per-vector traces, vb_g^2 and the sums
 // over g are carried in FP64.
 //
+// PR (real trials, FP64 products, 16 < N <= 24): stage 2 takes the vectors in
+// pairs.  Y_g^T and Y_g+1^T share one LDS tile as columns [0, N) and [N, 2N),
+// so f holds the rows of both vectors in 2N <= 48 = three row tiles instead of
+// two tiles per vector (at N = 24 a third fewer stage-2 products); the
+// transpose, the staged diagonals and the flushes follow the pair, and the
+// h1' slab may close a pair or stand alone.
+//
 // CT (complex trial determinants of multi-slice trials): stage 1 runs on the
 // real M x 2N matrix [Re Phi_T | Im Phi_T], giving Y_a = Re Phi_T^T L_g and
 // Y_b = Im Phi_T^T L_g as extra column tiles that share every L operand; stage
@@ -52,7 +59,7 @@ struct mm<float> {
   __device__ static int row(int g, int r) { return 4 * g + r; }
 };
 
-template <typename T, int KT, int NTC, bool CT>
+template <typename T, int KT, int NTC, bool CT, bool PR>
 __global__ void __launch_bounds__(128 * NTC)
 k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ Lpad,
              const double* __restrict__ phiT, const double* __restrict__ theta,
@@ -70,10 +77,18 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
   // leaves the next vector's first steps in slots 0 .. RING - 2 (no moves of
   // registers whose loads are still in flight)
   constexpr int RING = (NS % 4 == 0) ? 4 : (NS % 3 == 0) ? 3 : 2;
+  // PR (pairs, real trials with 16 < N <= 24): vectors are taken two at a time in
+  // stage 2; the rows of Y_g and Y_g+1 stack to 2N <= 48 = three row tiles
+  // instead of two tiles each, and f holds both vectors' rows.
+  static_assert(!PR || (!CT && NTC == 2), "pairs: real trials, 16 < N <= 24");
+  constexpr int SYW = PR ? 48 : NT2;  // columns of sY
+  constexpr int FR = PR ? 48 : NT;    // rows of f staged for the transpose
+  constexpr int FT = PR ? 3 : NTC2;   // row tiles of f
   extern __shared__ double smem[];
-  T* sY = reinterpret_cast<T*>(smem);                        // [MT][NT2]
-  double* sF = smem + (MT * NT2 * sizeof(T) + 7) / 8;         // [2][NT][NT+1][2]
-  double* sD = sF + 2 * NT * (NT + 1) * 2;                    // [16][NWV*16][2]
+  T* sY = reinterpret_cast<T*>(smem);                        // [MT][SYW]
+  double* sF = smem + (MT * SYW * sizeof(T) + 7) / 8;         // [2][FR][NT+1][2]
+  double* sD = sF + 2 * FR * (NT + 1) * 2;                    // [16][NWV*16][2]
+  double* sE = sD + 16 * NWV * 16 * 2;                        // [NWV][2]
 
   const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -119,7 +134,11 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
       for (int r = 0; r < 4; ++r) av[k][r] = lrow(Lpad, k, r);
 
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  if (PR) {  // columns 2N .. 47 of sY are never written
+    for (int q = threadIdx.x; q < MT * SYW; q += blockDim.x) sY[q] = (T)0;
+  }
   for (int gam = 0; gam <= G; ++gam) {
+    const int hv = PR ? (gam & 1) : 0;  // half of the pair this vector fills
     const T* Lg = Lpad + (size_t)gam * slab;
     const T* Ln = Lpad + (size_t)min(gam + 1, G) * slab;
     // stage 1: Y^T tiles (tp, ct), one software pipeline over all steps; the
@@ -160,7 +179,9 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
 #pragma unroll
         for (int r = 0; r < 4; ++r) av[k][r] = tmp[k][r];
     }
-    __syncthreads();  // previous vector's stage-2 and transpose reads are done
+    // previous vector's (pair's) stage-2 and transpose reads are done; the
+    // second vector of a pair writes the other half, which that barrier freed
+    if (hv == 0) __syncthreads();
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wave + NWV * q;
@@ -168,13 +189,21 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
 #pragma unroll
         for (int ct = 0; ct < NTC2; ++ct)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sY[(16 * tp + MM::row(g, r)) * NT2 + 16 * ct + c] = y1[q][ct][r];
+          for (int r = 0; r < 4; ++r) {
+            if (PR) {
+              if (16 * ct + c < N)
+                sY[(16 * tp + MM::row(g, r)) * SYW + hv * N + 16 * ct + c] = y1[q][ct][r];
+            } else {
+              sY[(16 * tp + MM::row(g, r)) * NT2 + 16 * ct + c] = y1[q][ct][r];
+            }
+          }
     }
+    if (PR && hv == 0 && gam < G) continue;  // stage 2 waits for the pair
     __syncthreads();
     // stage 2: f^sp[it][jt] = sum_m Y^T[m][it cols] Theta^sp[m][jt cols]
-    acc_t f[NTC2][2];
+    acc_t f[FT][2];
 #pragma unroll
-    for (int it = 0; it < NTC2; ++it) f[it][0] = f[it][1] = MM::zero();
+    for (int it = 0; it < FT; ++it) f[it][0] = f[it][1] = MM::zero();
     if (active) {
 #pragma unroll
       for (int t = 0; t < KTMAX; ++t) {
@@ -183,8 +212,8 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
           for (int r = 0; r < 4; ++r) {
             const int m = 16 * t + 4 * r + g;
 #pragma unroll
-            for (int it = 0; it < NTC2; ++it) {
-              const T a = sY[m * NT2 + 16 * it + c];
+            for (int it = 0; it < FT; ++it) {
+              const T a = sY[m * SYW + 16 * it + c];
               f[it][0] = MM::fma(a, th[0][t][r], f[it][0]);
               f[it][1] = MM::fma(a, th[1][t][r], f[it][1]);
             }
@@ -201,76 +230,169 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
         f[it][1] = fi;
       }
     }
-    // diagonal of f^sp in tile (jt, jt): element (row(g,r), c) with row == c
-    double d_re = 0.0, d_im = 0.0;
+    if constexpr (PR) {
+      // the group holds vectors g0v .. gam (gam = g0v + hv); the h1' slab G may be either
+      const int g0v = gam - hv;
+      const int j = 16 * jt + c;
+      // stage f^sp[:, jt] (both halves) for the transpose
+      double* Fs = sF + (size_t)sp * FR * (NT + 1) * 2;
 #pragma unroll
-    for (int it = 0; it < NTC; ++it)
-      if (it == jt)
+      for (int it = 0; it < FT; ++it)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (MM::row(g, r) == c) {
-            d_re = (double)f[it][0][r];
-            d_im = (double)f[it][1][r];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + MM::row(g, r);
+          Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
+          Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
+        }
+      // diagonal element (h N + j, j) of half h, held by one of the four lane groups
+      double dr[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+      for (int it = 0; it < FT; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + MM::row(g, r);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (j < N && i == h * N + j) {
+              dr[h][0] = (double)f[it][0][r];
+              dr[h][1] = (double)f[it][1][r];
+            }
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h > hv) break;
+        const int gv = g0v + h;
+        if (gv < G) {  // staged for vb_gv: the sum over the lane groups to lane group 0
+          double d0 = dr[h][0], d1 = dr[h][1];
+          d0 += __shfl_xor(d0, 16, 64);
+          d1 += __shfl_xor(d1, 16, 64);
+          d0 += __shfl_xor(d0, 32, 64);
+          d1 += __shfl_xor(d1, 32, 64);
+          if (g == 0) {
+            double* d = sD + ((size_t)(gv & 15) * NWV * 16 + wave * 16 + c) * 2;
+            d[0] = d0;
+            d[1] = d1;
           }
-    if (gam == G) {
-      d_re = wave_sum(d_re);
-      d_im = wave_sum(d_im);
-      // one-body term: both spins' traces, gathered through LDS below
-      if (lane == 0) {
-        sD[(wave * 16) * 2] = d_re;
-        sD[(wave * 16) * 2 + 1] = d_im;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int w = 0; w < NWV; ++w) {
-          e1_re += sD[(w * 16) * 2];
-          e1_im += sD[(w * 16) * 2 + 1];
+        } else {  // h1': this wavefront's part of the one-body trace
+          const double e0 = wave_sum(dr[h][0]), e1 = wave_sum(dr[h][1]);
+          if (lane == 0) {
+            sE[wave * 2] = e0;
+            sE[wave * 2 + 1] = e1;
+          }
         }
       }
-      break;
-    }
-    // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
-    double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
-#pragma unroll
-    for (int it = 0; it < NTC; ++it)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
-        Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
-        Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
+      __syncthreads();
+      if (gam == G && threadIdx.x == 0) {
+        for (int w = 0; w < NWV; ++w) {
+          e1_re += sE[w * 2];
+          e1_im += sE[w * 2 + 1];
+        }
       }
-    {
-      double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
-      if (MM::row(g, 0) == c || MM::row(g, 1) == c || MM::row(g, 2) == c || MM::row(g, 3) == c) {
-        d[0] = d_re;
-        d[1] = d_im;
-      }
-    }
-    __syncthreads();
+      // exchange of the regular halves: sum_ij f_ij f_ji, f_ji at row h N + j, column i - h N
 #pragma unroll
-    for (int it = 0; it < NTC; ++it)
+      for (int it = 0; it < FT; ++it)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
-        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
-        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
-        ex_re += ar * tr_ - ai * ti_;
-        ex_im += ar * ti_ + ai * tr_;
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + MM::row(g, r);
+          const int h = i >= N ? 1 : 0, il = i - h * N;
+          if (i < 2 * N && j < N && h <= hv && g0v + h < G) {
+            const double* src = Fs + ((h * N + j) * (NT + 1) + il) * 2;
+            const double tr_ = src[0], ti_ = src[1];
+            const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
+            ex_re += ar * tr_ - ai * ti_;
+            ex_im += ar * ti_ + ai * tr_;
+          }
+        }
+      // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
+      const int glast = min(gam, G - 1);  // last regular vector of the group
+      if (g0v < G && ((glast & 15) == 15 || glast == G - 1) && wave == 0) {
+        const int cnt = (glast & 15) + 1, gb = glast & ~15;
+        const int gl = lane & 15, part = (lane >> 4) & 1;
+        double v = 0.0;
+        if (lane < 32 && gl < cnt)
+          for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
+        const double vi = __shfl_down(v, 16, 64);
+        if (lane < 16 && gl < cnt) {
+          vb2_re += v * v - vi * vi;
+          vb2_im += 2.0 * v * vi;
+          double* o = vb + ((size_t)s * G + gb + gl) * 2;
+          o[0] = v;
+          o[1] = vi;
+        }
       }
-    // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
-    if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
-      const int cnt = (gam & 15) + 1, g0 = gam & ~15;
-      const int gl = lane & 15, part = (lane >> 4) & 1;
-      double v = 0.0;
-      if (lane < 32 && gl < cnt)
-        for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
-      const double vi = __shfl_down(v, 16, 64);
-      if (lane < 16 && gl < cnt) {
-        vb2_re += v * v - vi * vi;
-        vb2_im += 2.0 * v * vi;
-        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
-        o[0] = v;
-        o[1] = vi;
+      if (gam == G) break;
+    } else {
+      // diagonal of f^sp in tile (jt, jt): element (row(g,r), c) with row == c
+      double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+      for (int it = 0; it < NTC; ++it)
+        if (it == jt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (MM::row(g, r) == c) {
+              d_re = (double)f[it][0][r];
+              d_im = (double)f[it][1][r];
+            }
+      if (gam == G) {
+        d_re = wave_sum(d_re);
+        d_im = wave_sum(d_im);
+        // one-body term: both spins' traces, gathered through LDS below
+        if (lane == 0) {
+          sD[(wave * 16) * 2] = d_re;
+          sD[(wave * 16) * 2 + 1] = d_im;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          for (int w = 0; w < NWV; ++w) {
+            e1_re += sD[(w * 16) * 2];
+            e1_im += sD[(w * 16) * 2 + 1];
+          }
+        }
+        break;
+      }
+      // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
+      double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
+#pragma unroll
+      for (int it = 0; it < NTC; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
+          Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
+          Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
+        }
+      {
+        double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
+        if (MM::row(g, 0) == c || MM::row(g, 1) == c || MM::row(g, 2) == c || MM::row(g, 3) == c) {
+          d[0] = d_re;
+          d[1] = d_im;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < NTC; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + MM::row(g, r), j = 16 * jt + c;
+          const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+          const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
+          ex_re += ar * tr_ - ai * ti_;
+          ex_im += ar * ti_ + ai * tr_;
+        }
+      // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
+      if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
+        const int cnt = (gam & 15) + 1, g0 = gam & ~15;
+        const int gl = lane & 15, part = (lane >> 4) & 1;
+        double v = 0.0;
+        if (lane < 32 && gl < cnt)
+          for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
+        const double vi = __shfl_down(v, 16, 64);
+        if (lane < 16 && gl < cnt) {
+          vb2_re += v * v - vi * vi;
+          vb2_im += 2.0 * v * vi;
+          double* o = vb + ((size_t)s * G + g0 + gl) * 2;
+          o[0] = v;
+          o[1] = vi;
+        }
       }
     }
   }
@@ -302,20 +424,22 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
     for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-size_t lds_bytes(int MT, int NTC, size_t tsize, bool ct) {
+size_t lds_bytes(int MT, int NTC, size_t tsize, bool ct, bool pr) {
   const int NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = ((size_t)MT * NT * (ct ? 2 : 1) * tsize + 7) / 8 * 8;
-  b += (size_t)2 * NT * (NT + 1) * 2 * 8;
+  const int syw = pr ? 48 : NT * (ct ? 2 : 1), fr = pr ? 48 : NT;
+  size_t b = ((size_t)MT * syw * tsize + 7) / 8 * 8;
+  b += (size_t)2 * fr * (NT + 1) * 2 * 8;
   b += (size_t)16 * NWV * 16 * 2 * 8;
+  b += (size_t)NWV * 2 * 8;
   return b;
 }
 
-template <typename T, int KT, int NTC, bool CT>
+template <typename T, int KT, int NTC, bool CT, bool PR = false>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT,
                     const double* theta, const double* logov, double* vb, double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes(c->MT, NTC, sizeof(T), CT);
-  auto kern = k_contract_g<T, KT, NTC, CT>;
+  const size_t lds = lds_bytes(c->MT, NTC, sizeof(T), CT, PR);
+  auto kern = k_contract_g<T, KT, NTC, CT, PR>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -336,6 +460,18 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
     AFQMC_GC(2, 2) AFQMC_GC(3, 2) AFQMC_GC(4, 2)
 #undef AFQMC_GC
     return hipErrorInvalidValue;
+  }
+  // 16 < N <= 24, FP64 products: vectors in pairs (2N rows in three tiles; measured at
+  // M = 96, N = 24: 86.9 -> 82.3 ms).  The FP32 form was slower in pairs (54.5 -> 56.4 ms)
+  // and the FP64 form spills at KT = 8, so those keep one vector at a time.
+  if constexpr (sizeof(T) == 8) {
+    if (NTC == 2 && c->N <= 24 && KT <= 7) {
+#define AFQMC_GP(KK)                                                                       \
+  if (KT == KK) return launch_g<T, KK, 2, false, true>(c, nw, L, phiT, theta, logov, vb, ep);
+      AFQMC_GP(2) AFQMC_GP(3) AFQMC_GP(4) AFQMC_GP(5) AFQMC_GP(6) AFQMC_GP(7)
+#undef AFQMC_GP
+      return hipErrorInvalidValue;
+    }
   }
 #define AFQMC_G(KK, NC)                                                            \
   if (KT == KK && NTC == NC) return launch_g<T, KK, NC, false>(c, nw, L, phiT, theta, logov, vb, ep);
