@@ -27,12 +27,17 @@ sys.path.insert(0, ROOT)
 METRIC = "walker-steps/s at fixed energy error; contraction TFLOP/s vs MFMA peak"
 PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix
 
 # name -> (workload index of afqmc_inputs.workload, contraction precision, peak, dtype label)
 WORKLOADS = {
     "fp64": (1, 0, PEAK_FP64_MFMA, "f64"),
     "mixed": (2, 1, PEAK_FP32_MFMA, "f32-contraction/f64"),
     "mixed-fp64": (2, 0, PEAK_FP64_MFMA, "f64"),
+    # BF16 products: roofline against the dense BF16 peak with the algorithmic flops
+    # (the split form executes three products per algorithmic one)
+    "mixed-bf16x3": (2, 3, PEAK_BF16_MFMA, "bf16x3-contraction/f64"),
+    "mixed-bf16": (2, 2, PEAK_BF16_MFMA, "bf16-contraction/f64"),
     "slices": (5, 0, PEAK_FP64_MFMA, "f64"),
 }
 
@@ -255,11 +260,11 @@ def scan_study(args):
 
 
 def mixed_study(args):
-    """The mixed-precision form at fixed energy error on the FP64 workload's
+    """The mixed-precision forms at fixed energy error on the FP64 workload's
     system (M=64, N=16, 256 vectors, K=64, 512 walkers x 8 paths) with the
-    random-walk proposal (step 0.3), where long runs are stable: FP32-product
-    contraction and the all-FP64 form run the same steps from the same
-    walkers and seeds; energies reblocked over the timed steps, their
+    random-walk proposal (step 0.3), where long runs are stable: the FP32,
+    split-BF16 and BF16 contractions and the all-FP64 form run the same steps
+    from the same walkers and seeds; energies reblocked over the timed steps, their
     difference against the combined error bar, and the throughput of the
     mixed form at the FP64 form's energy error.  (The mixed workload's own
     system, M=128 with K=128, loses its path-sign average within a few tens
@@ -300,14 +305,24 @@ def mixed_study(args):
                 "max_step_energy_difference": None, "series": en}
 
     F32 = leg(A.PREC_FP32)
+    B3 = leg(A.PREC_BF16X3)
+    B1 = leg(A.PREC_BF16)
     F64 = leg(A.PREC_FP64)
-    dmax = float(np.max(np.abs(F32["series"] - F64["series"])))
-    for d in (F32, F64):
-        d["max_step_energy_difference"] = dmax
+
+    def versus_fp64(d):
+        d["max_step_energy_difference"] = float(np.max(np.abs(d["series"] - F64["series"])))
+        d["energy_difference"] = d["energy"] - F64["energy"]
+        d["combined_error"] = float(np.hypot(d["energy_err"], F64["energy_err"]))
+        d["equal_error_throughput_ratio"] = (d["walker_steps_per_s"] / F64["walker_steps_per_s"]) * (
+            (F64["energy_err"] ** 2) / max(d["energy_err"] ** 2, 1e-300))
+
+    for d in (F32, B3, B1):
+        versus_fp64(d)
+    for d in (F32, B3, B1, F64):
         del d["series"]
-    comb = float(np.hypot(F32["energy_err"], F64["energy_err"]))
-    ratio = (F32["walker_steps_per_s"] / F64["walker_steps_per_s"]) * (
-        (F64["energy_err"] ** 2) / max(F32["energy_err"] ** 2, 1e-300))
+    F64["max_step_energy_difference"] = F32["max_step_energy_difference"]
+    comb = F32["combined_error"]
+    ratio = F32["equal_error_throughput_ratio"]
     flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
     achieved = flops / (F32["contraction_ms"] * 1e-3) / 1e12
     out = {
@@ -322,7 +337,7 @@ def mixed_study(args):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
                      "kernel": "k_contract_g<float> (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": F32["contraction_ms"], "flops_per_launch": flops},
-        "fp32_products": F32, "fp64": F64,
+        "fp32_products": F32, "bf16x3_products": B3, "bf16_products": B1, "fp64": F64,
         "energy_difference": F32["energy"] - F64["energy"], "combined_error": comb,
         "equal_error_throughput_ratio": ratio,
     }
@@ -527,7 +542,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload),
                      "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
-                                and not ctx.ctrial else "k_contract_g")
+                                and not ctx.ctrial else
+                                "k_contract_bf" if precision in (2, 3) else "k_contract_g")
                                + (" (complex trial)" if ctx.ctrial else "")
                                + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},

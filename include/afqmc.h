@@ -76,10 +76,21 @@ enum { AFQMC_WEIGHT_SEPARATE = 0, AFQMC_WEIGHT_COMBINED = 1, AFQMC_WEIGHT_HALFPL
 enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1, AFQMC_PROPOSAL_LEARNED = 2 };
 
 /* Precision of the Cholesky contraction (force bias and local energy):
- * FP64 throughout, or FP32: Phi_T, Theta and L enter the FP32 matrix-core
- * products with FP32 accumulation over the orbital index; traces, vb_g^2,
- * the sums over g and every other step of the path stay FP64. */
-enum { AFQMC_PREC_FP64 = 0, AFQMC_PREC_FP32 = 1, AFQMC_PREC_BF16 = 2 /* network only */ };
+ * FP64 throughout; FP32: Phi_T, Theta and L enter the FP32 matrix-core
+ * products with FP32 accumulation over the orbital index; BF16: the same
+ * products with bfloat16 operands (one product per pair, about 3 significant
+ * digits); BF16X3 (split bfloat16): each operand x carried as hi = bf16(x) and
+ * lo = bf16(x - hi), each product as hi*hi + hi*lo + lo*hi (close to FP32
+ * accuracy).  In every form the traces, vb_g^2, the sums over g and every
+ * other step of the path stay FP64.  BF16 and BF16X3 need the real trial
+ * family (AFQMC_E_UNSUPPORTED otherwise).  The proposal network's own
+ * precision is set separately (afqmc_mlp_init: FP32 or BF16). */
+enum {
+  AFQMC_PREC_FP64 = 0,
+  AFQMC_PREC_FP32 = 1,
+  AFQMC_PREC_BF16 = 2,
+  AFQMC_PREC_BF16X3 = 3
+};
 
 /* Trial families (Sec. II.C, Eqs. trial, trial-AF and trial_decomp):
  * JASTROW: Phi_T(y) = exp(c sum_k y_k A_k) Phi_0, real;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 HIDDEN_ISING, HIDDEN_GAUSS = 0, 1
 WEIGHT_SEPARATE, WEIGHT_COMBINED, WEIGHT_HALFPLANE, WEIGHT_LOCAL = 0, 1, 2, 3
 PROPOSAL_PRIOR, PROPOSAL_RW, PROPOSAL_LEARNED = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2, 3
 MLP_HIDDEN = 256
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 INIT_STEP, MEASURE_STEP = 1 << 63, 1 << 62     # AFQMC_INIT_STEP, AFQMC_MEASURE_STEP

@@ -33,9 +33,9 @@ hipError_t dev_copy(T** dst, const T* src, size_t n) {
 
 void free_ctx(afqmc_ctx_s* c) {
   auto& m = c->mlp;
-  void* ptrs[] = {c->d_h1, c->d_Lraw, c->d_Lpad, c->d_Eh, c->d_phi0, c->d_A, c->d_Lpad32,
-                  c->d_F,  c->d_phi0c, m.master, m.mom1, m.mom2, m.w1t, m.w2t, m.w3t, m.w2c,
-                  m.w3c,   m.tstep,    m.scal};
+  void* ptrs[] = {c->d_h1,  c->d_Lraw, c->d_Lpad,  c->d_Eh,   c->d_phi0, c->d_A,   c->d_Lpad32,
+                  c->d_Lbf, c->d_Lbf_lo, c->d_F,    c->d_phi0c, m.master,  m.mom1,   m.mom2,
+                  m.w1t,    m.w2t,     m.w3t,       m.w2c,      m.w3c,     m.tstep,  m.scal};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -209,8 +209,8 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if (sys->proposal == AFQMC_PROPOSAL_LEARNED &&
       (sys->hidden_kind != AFQMC_HIDDEN_GAUSS || K > 128))
     return AFQMC_E_UNSUPPORTED;
-  if (sys->precision != AFQMC_PREC_FP64 && sys->precision != AFQMC_PREC_FP32)
-    return AFQMC_E_UNSUPPORTED;
+  if (sys->precision < AFQMC_PREC_FP64 || sys->precision > AFQMC_PREC_BF16X3)
+    return AFQMC_E_INVALID;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
   if (!(sys->xbar_cap >= 0.0)) return AFQMC_E_INVALID;
   const bool slices = sys->trial_kind == AFQMC_TRIAL_SLICES;
@@ -223,6 +223,9 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     for (int l = 0; l < m; ++l)
       if (!(sys->slice_s[l] >= 0.0) || !isfinite(sys->slice_s[l])) return AFQMC_E_INVALID;
     if (sys->proposal == AFQMC_PROPOSAL_LEARNED) return AFQMC_E_UNSUPPORTED;
+    // the BF16 contraction takes real trial determinants only
+    if (sys->precision == AFQMC_PREC_BF16 || sys->precision == AFQMC_PREC_BF16X3)
+      return AFQMC_E_UNSUPPORTED;
     // complex stage-1 operands of the contraction: (M/16) ceil(N/16) <= 8
     if (((M + 15) / 16) * ((N + 15) / 16) > 8) return AFQMC_E_UNSUPPORTED;
   }
@@ -293,6 +296,15 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     const size_t n = Lpad.size();
     if ((e = hipMalloc(&c->d_Lpad32, n * sizeof(float))) == hipSuccess &&
         (e = launch_to_float(c, n, c->d_Lpad, c->d_Lpad32)) == hipSuccess)
+      e = hipStreamSynchronize(c->stream);
+  }
+  if (e == hipSuccess &&
+      (c->precision == AFQMC_PREC_BF16 || c->precision == AFQMC_PREC_BF16X3)) {
+    const size_t n = Lpad.size();
+    const bool x3 = c->precision == AFQMC_PREC_BF16X3;
+    if ((e = hipMalloc(&c->d_Lbf, n * sizeof(unsigned short))) == hipSuccess &&
+        (!x3 || (e = hipMalloc(&c->d_Lbf_lo, n * sizeof(unsigned short))) == hipSuccess) &&
+        (e = launch_to_bf16(c, n, c->d_Lpad, c->d_Lbf, c->d_Lbf_lo)) == hipSuccess)
       e = hipStreamSynchronize(c->stream);
   }
   if (e != hipSuccess) {
@@ -409,6 +421,11 @@ static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, con
     HIPCALL(c,
             launch_contract(c, nw, phiT, static_cast<const double*>(theta),
                             static_cast<const double*>(logov), vb, ep),
+            "contract");
+  else if (c->precision == AFQMC_PREC_BF16 || c->precision == AFQMC_PREC_BF16X3)
+    HIPCALL(c,
+            launch_contract_bf(c, nw, phiT, static_cast<const double*>(theta),
+                               static_cast<const double*>(logov), vb, ep),
             "contract");
   else
     HIPCALL(c,

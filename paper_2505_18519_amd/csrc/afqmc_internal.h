@@ -26,6 +26,8 @@ struct afqmc_ctx_s {
   double* d_phi0 = nullptr;  // [M][N]
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
+  unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad (BF16 contraction)
+  unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf (split-BF16 contraction)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
 
   // trial family (AFQMC_TRIAL_*); multi-slice trials have complex Phi_T and
@@ -165,6 +167,10 @@ hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, dou
                                double* vbuf);
 hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift);
 hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
+hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
+                              const double* theta, const double* logov, double* vb, double* ep);
+hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
+                          unsigned short* lo);
 hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,
                        double* C, double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,

@@ -1,0 +1,360 @@
+// Cholesky-vector contraction with BF16 matrix-core products and FP32
+// accumulation (the mixed-precision forms AFQMC_PREC_BF16 and
+// AFQMC_PREC_BF16X3).  Same quantities as k_contract (Sec. III.A, Eq.
+// local-obs; Eq. shift1):
+//   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
+//   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
+//
+// Products: v_mfma_f32_16x16x16bf16_1k, lane (g, c) supplying A[c][4g + j] and
+// B[4g + j][c] (j = 0..3, four consecutive k values) and holding D[4g + r][c].
+// X3 (split BF16): every operand x is carried as x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi), and a product a b as a_hi b_hi + a_hi b_lo + a_lo b_hi
+// (three products; the dropped a_lo b_lo is below 2^-16 relative), which
+// brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
+//
+// Layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16));
+// wavefront w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt]
+// as BF16 B operands in registers for the whole loop over g, and Phi_T
+// (all column tiles) as the stage-1 B operands.  Stage 1 (Y_g^T = L_g Phi_T)
+// is split over the wavefronts by row tile; each reads its rows of the BF16
+// copy of L_g (eight contiguous bytes per lane) one vector ahead, so the loads
+// of vector g + 1 are in flight during stage 2 of vector g.  Y_g^T is rounded
+// to BF16 once, as stage 1 leaves it, and stored in LDS in the accumulator
+// layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a column in
+// one lane); f is transposed through LDS for tr(f f); traces, vb_g^2 and the
+// sums over g are FP64.
+#include "afqmc_internal.h"
+#include "dev_common.h"
+
+namespace {
+
+typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef short sx4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+// hi / lo BF16 pair of a value: hi = bf16(x), lo = bf16(x - hi)
+struct bsplit {
+  sx4 hi, lo;
+};
+template <bool X3>
+__device__ __forceinline__ bsplit split4(float a, float b, float c, float d) {
+  bsplit s;
+  const unsigned short h0 = f2bf(a), h1 = f2bf(b), h2 = f2bf(c), h3 = f2bf(d);
+  s.hi = sx4{(short)h0, (short)h1, (short)h2, (short)h3};
+  if (X3) {
+    s.lo = sx4{(short)f2bf(a - bf2f(h0)), (short)f2bf(b - bf2f(h1)), (short)f2bf(c - bf2f(h2)),
+               (short)f2bf(d - bf2f(h3))};
+  } else {
+    s.lo = sx4{0, 0, 0, 0};
+  }
+  return s;
+}
+
+template <bool X3>
+__device__ __forceinline__ fx4 mma(const bsplit& a, const bsplit& b, fx4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, acc, 0, 0, 0);
+  if (X3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ fx4 fx4_zero() {
+  fx4 z = {0.f, 0.f, 0.f, 0.f};
+  return z;
+}
+
+template <int KT, int NTC, bool X3>
+__global__ void __launch_bounds__(128 * NTC)
+k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* __restrict__ Lhi,
+              const unsigned short* __restrict__ Llo, const double* __restrict__ phiT,
+              const double* __restrict__ theta, const double* __restrict__ logov,
+              double* __restrict__ vb, double* __restrict__ ep) {
+  constexpr int NWV = 2 * NTC;                 // wavefronts
+  constexpr int NT = 16 * NTC;
+  constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  extern __shared__ double smem[];
+  // Y^T as BF16 (hi, and lo for X3) in the accumulator layout: entry (mq, n) holds
+  // rows 4 mq .. 4 mq + 3 of column n, i.e. one stage-2 A operand
+  sx4* sYh = reinterpret_cast<sx4*>(smem);                    // [MT/4][NT]
+  sx4* sYl = sYh + (MT / 4) * NT;                             // [MT/4][NT] (X3)
+  double* sF = smem + (size_t)(MT / 4) * NT * (X3 ? 2 : 1);    // [2][NT][NT+1][2]
+  double* sD = sF + 2 * NT * (NT + 1) * 2;                     // [16][NWV*16][2]
+  double* sE = sD + 16 * NWV * 16 * 2;                         // [NWV][2]
+
+  const int s = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int sp = wave & 1, jt = wave >> 1;
+  if (s >= n_samples) return;  // whole block exits together
+  const bool active = !__builtin_isinf(logov[2 * s]);
+
+  // B operands: bT[ct][t] = Phi_T[16t + 4g + j][16ct + c]; th[ri][t] = Theta^sp[16t + 4g + j][16jt + c]
+  bsplit bT[NTC][KT], th[2][KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    float v[NTC][4], w[2][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = 16 * t + 4 * g + j;
+      const bool okm = active && m < M;
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        const int n = 16 * ct + c;
+        v[ct][j] = (okm && n < N) ? (float)phiT[((size_t)s * M + m) * N + n] : 0.f;
+      }
+      const int n = 16 * jt + c;
+      const double* src = theta + ((((size_t)s * 2 + sp) * M + m) * N + n) * 2;
+      w[0][j] = (okm && n < N) ? (float)src[0] : 0.f;
+      w[1][j] = (okm && n < N) ? (float)src[1] : 0.f;
+    }
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<X3>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<X3>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
+  }
+
+  // stage-1 A operands of row tile tp = wave + NWV q: L[16tp + c][16t + 4g .. +3]
+  // (row tiles past KT are clamped in range and their products skipped)
+  const size_t slab = (size_t)MT * MT;
+  auto loadA = [&](int gam, bsplit (&a)[S1MAX][KT]) {
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = min(wave + NWV * q, KT - 1);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const size_t o = (size_t)gam * slab + (size_t)(16 * tp + c) * MT + 16 * t + 4 * g;
+        a[q][t].hi = *reinterpret_cast<const sx4*>(Lhi + o);
+        if (X3) a[q][t].lo = *reinterpret_cast<const sx4*>(Llo + o);
+        else a[q][t].lo = sx4{0, 0, 0, 0};
+      }
+    }
+  };
+  bsplit aL[S1MAX][KT];
+  loadA(0, aL);
+
+  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  for (int gam = 0; gam <= G; ++gam) {
+    // stage 1: Y^T tiles (tp, ct)
+    fx4 y1[S1MAX][NTC];
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = fx4_zero();
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q)
+      if (active && wave + NWV * q < KT)
+#pragma unroll
+        for (int t = 0; t < KT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<X3>(aL[q][t], bT[ct][t], y1[q][ct]);
+    // the next vector's L rows, in flight during the rest of this one
+    if (gam < G) loadA(gam + 1, aL);
+    __syncthreads();  // previous vector's stage-2 and transpose reads are done
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wave + NWV * q;
+      if (tp < KT)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct) {
+          const fx4 v = y1[q][ct];
+          const bsplit b = split4<X3>(v[0], v[1], v[2], v[3]);
+          const int o = (4 * tp + g) * NT + 16 * ct + c;
+          sYh[o] = b.hi;
+          if (X3) sYl[o] = b.lo;
+        }
+    }
+    __syncthreads();
+    // stage 2: f^sp[it][jt] = sum_m Y[it rows][m] Theta^sp[m][jt cols];
+    // A[c][4g + j] = Y^T[16t + 4g + j][16it + c]
+    fx4 f[NTC][2];
+#pragma unroll
+    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
+    if (active) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int it = 0; it < NTC; ++it) {
+          const int o = (4 * t + g) * NT + 16 * it + c;
+          bsplit a;
+          a.hi = sYh[o];
+          a.lo = X3 ? sYl[o] : sx4{0, 0, 0, 0};
+          f[it][0] = mma<X3>(a, th[0][t], f[it][0]);
+          f[it][1] = mma<X3>(a, th[1][t], f[it][1]);
+        }
+    }
+    // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
+    double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+      if (it == jt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * g + r == c) {
+            d_re = (double)f[it][0][r];
+            d_im = (double)f[it][1][r];
+          }
+    if (gam == G) {  // h1': both spins' one-body traces through LDS
+      d_re = wave_sum(d_re);
+      d_im = wave_sum(d_im);
+      if (lane == 0) {
+        sE[wave * 2] = d_re;
+        sE[wave * 2 + 1] = d_im;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w = 0; w < NWV; ++w) {
+          e1_re += sE[w * 2];
+          e1_im += sE[w * 2 + 1];
+        }
+      }
+      break;
+    }
+    // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
+    double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
+        Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
+        Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
+      }
+    if (g == (c >> 2)) {  // the lane group holding row c of tile jt
+      double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
+      d[0] = d_re;
+      d[1] = d_im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
+        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
+        ex_re += ar * tr_ - ai * ti_;
+        ex_im += ar * ti_ + ai * tr_;
+      }
+    // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
+    if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
+      const int cnt = (gam & 15) + 1, g0 = gam & ~15;
+      const int gl = lane & 15, part = (lane >> 4) & 1;
+      double v = 0.0;
+      if (lane < 32 && gl < cnt)
+        for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
+      const double vi = __shfl_down(v, 16, 64);
+      if (lane < 16 && gl < cnt) {
+        vb2_re += v * v - vi * vi;
+        vb2_im += 2.0 * v * vi;
+        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
+        o[0] = v;
+        o[1] = vi;
+      }
+    }
+  }
+  // totals: ex from every lane of every wavefront, vb^2 from wavefront 0
+  ex_re = wave_sum(ex_re);
+  ex_im = wave_sum(ex_im);
+  vb2_re = wave_sum(vb2_re);
+  vb2_im = wave_sum(vb2_im);
+  __syncthreads();
+  if (lane == 0) {
+    sD[wave * 4 + 0] = ex_re;
+    sD[wave * 4 + 1] = ex_im;
+    sD[wave * 4 + 2] = vb2_re;
+    sD[wave * 4 + 3] = vb2_im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double xr = 0.0, xi = 0.0;
+    for (int w = 0; w < NWV; ++w) {
+      xr += sD[w * 4 + 0];
+      xi += sD[w * 4 + 1];
+    }
+    const double br = sD[2], bi = sD[3];
+    double* o = ep + (size_t)s * 2;
+    o[0] = active ? e1_re + 0.5 * br - 0.5 * xr : 0.0;
+    o[1] = active ? e1_im + 0.5 * bi - 0.5 * xi : 0.0;
+  }
+  if (!active)
+    for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
+}
+
+size_t lds_bytes(int MT, int NTC, bool x3) {
+  const int NT = 16 * NTC, NWV = 2 * NTC;
+  size_t b = (size_t)(MT / 4) * NT * 8 * (x3 ? 2 : 1);
+  b += (size_t)2 * NT * (NT + 1) * 2 * 8;
+  b += (size_t)16 * NWV * 16 * 2 * 8;
+  b += (size_t)NWV * 2 * 8;
+  return b;
+}
+
+template <int KT, int NTC, bool X3>
+hipError_t launch_bf(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                     const double* logov, double* vb, double* ep) {
+  const int n = nw * c->P;
+  const size_t lds = lds_bytes(c->MT, NTC, X3);
+  auto kern = k_contract_bf<KT, NTC, X3>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(128 * NTC), lds, c->stream, n, c->M, c->N, c->G, c->MT,
+                     c->d_Lbf, c->d_Lbf_lo, phiT, theta, logov, vb, ep);
+  return hipGetLastError();
+}
+
+template <bool X3>
+hipError_t dispatch(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                    const double* logov, double* vb, double* ep) {
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_B(KK, NC) \
+  if (KT == KK && NTC == NC) return launch_bf<KK, NC, X3>(c, nw, phiT, theta, logov, vb, ep);
+  AFQMC_B(1, 1) AFQMC_B(2, 1) AFQMC_B(3, 1) AFQMC_B(4, 1)
+  AFQMC_B(5, 1) AFQMC_B(6, 1) AFQMC_B(7, 1) AFQMC_B(8, 1)
+  AFQMC_B(2, 2) AFQMC_B(3, 2) AFQMC_B(4, 2)
+  AFQMC_B(5, 2) AFQMC_B(6, 2) AFQMC_B(7, 2) AFQMC_B(8, 2)
+#undef AFQMC_B
+  return hipErrorInvalidValue;
+}
+
+// L (double) -> BF16 hi and, when lo is given, lo = bf16(L - hi)
+__global__ void k_to_bf16(size_t n, const double* __restrict__ src, unsigned short* __restrict__ hi,
+                          unsigned short* __restrict__ lo) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = (float)src[i];
+  const unsigned short h = f2bf(x);
+  hi[i] = h;
+  if (lo != nullptr) lo[i] = f2bf(x - bf2f(h));
+}
+
+}  // namespace
+
+hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
+                              const double* theta, const double* logov, double* vb, double* ep) {
+  if (nw <= 0) return hipSuccess;
+  if (c->d_Lbf == nullptr) return hipErrorInvalidValue;
+  if (c->precision == AFQMC_PREC_BF16X3) {
+    if (c->d_Lbf_lo == nullptr) return hipErrorInvalidValue;
+    return dispatch<true>(c, nw, phiT, theta, logov, vb, ep);
+  }
+  return dispatch<false>(c, nw, phiT, theta, logov, vb, ep);
+}
+
+hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
+                          unsigned short* lo) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, src,
+                     hi, lo);
+  return hipGetLastError();
+}

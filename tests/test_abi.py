@@ -49,8 +49,8 @@ def test_host_side_validation(lib):
     assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2   # M > 128
     s = A.afqmc_system(8, 2, 8, 4, 2, 7, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 0)
     assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 1   # hidden kind
-    s = A.afqmc_system(8, 2, 8, 4, 2, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 3)
-    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 6   # precision
+    s = A.afqmc_system(8, 2, 8, 4, 2, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 4)
+    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 1   # precision
     assert lib.afqmc_destroy(None) == 1
     assert lib.afqmc_green(None, 1, None, None, None, None) == 1
 

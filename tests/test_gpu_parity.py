@@ -314,6 +314,9 @@ def test_trajectory_tiny_matches_oracle():
     assert np.abs(host(st.w) - ost.w).max() <= TOL * np.abs(ost.w).max()
 
 
+# plain BF16 products (8 significant bits) are reported, not held to the mixed bar
+BF16_TOL = 5e-2
+
 FULL = {
     # name: (workload index, contraction precision, tolerance)
     "M64-N16-G256-512x8-fp64": (1, 0, TOL),
@@ -321,6 +324,9 @@ FULL = {
     "M128-N32-G512-1024x4-fp32": (2, 1, 1e-4),
     "M96-N24-G384-2048x4-fp64": (4, 0, TOL),
     "M96-N24-G384-2048x4-fp32": (4, 1, 1e-4),
+    "M128-N32-G512-1024x4-bf16x3": (2, 3, 1e-4),
+    "M96-N24-G384-2048x4-bf16x3": (4, 3, 1e-4),
+    "M128-N32-G512-1024x4-bf16": (2, 2, BF16_TOL),
 }
 
 
@@ -423,18 +429,22 @@ def test_force_bias_cap():
 
 
 MIXED_TOL = 1e-4
+MIXED = {"fp32": (1, MIXED_TOL), "bf16x3": (3, MIXED_TOL), "bf16": (2, BF16_TOL)}
 
 
-@pytest.mark.parametrize("case", ["gauss-M20-N5-ragged", "cfg-M64-N16-G256", "gauss-M96-N24",
-                                  "gauss-M128-N32"])
-def test_mixed_precision_contraction(case):
-    """FP32 matrix-core contraction (FP64 traces and sums) against the FP64
-    oracle: per-path vb and E_p, per-walker force bias and E_L within 1e-4."""
-    _say("mixed", case)
+@pytest.mark.parametrize("prec", list(MIXED))
+@pytest.mark.parametrize("case", ["gauss-M20-N5-ragged", "cfg-M64-N16-G256", "gauss-M72-N20-ragged",
+                                  "gauss-M96-N24", "gauss-M128-N32"])
+def test_mixed_precision_contraction(case, prec):
+    """FP32, split-BF16 and BF16 matrix-core contractions (FP64 traces and
+    sums) against the FP64 oracle: per-path vb and E_p, per-walker force bias
+    and E_L within 1e-4 (FP32, split BF16) or the plain-BF16 bound."""
+    _say("mixed", case, prec)
     s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
     from paper_2505_18519_amd import afqmc as A
     dtau = 0.01
-    ctx = A.Context(s, P, dtau, max_walkers=nw, precision=A.PREC_FP32)
+    code, bound = MIXED[prec]
+    ctx = A.Context(s, P, dtau, max_walkers=nw, precision=code)
     rng, phi, y = state(s, P, nw, 2)
     phiT = O.trial_det(s, y)
     eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, dtau)
@@ -453,6 +463,16 @@ def test_mixed_precision_contraction(case):
     e_vb = max(rel(host(d_vb)[w, p], vb[w, p]) for w in range(nw) for p in range(P))
     _say(f"  errors vs FP64 oracle: E_p {e_ep:.2e} E_L {e_el:.2e} xbar {e_xb:.2e} vb {e_vb:.2e}")
     for e in (e_ep, e_el, e_xb, e_vb):
-        assert e <= MIXED_TOL
-    # the FP32 products are really in use (FP64 would agree to ~1e-14)
+        assert e <= bound
+    # the reduced-precision products are really in use (FP64 would agree to ~1e-14)
     assert max(e_ep, e_xb) > 1e-10
+
+
+def test_bf16_contraction_needs_real_trials():
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.imaginary_time_trial(ai.tiny_ising(), 1, 0.05)
+    for prec in (A.PREC_BF16, A.PREC_BF16X3):
+        with pytest.raises(A.AfqmcError):
+            A.Context(s, 4, 0.01, precision=prec)
+    with pytest.raises(A.AfqmcError):
+        A.Context(ai.tiny_ising(), 4, 0.01, precision=4)
