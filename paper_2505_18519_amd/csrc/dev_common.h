@@ -77,6 +77,13 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// x where ok, +0 elsewhere, as a bit mask: a load whose value feeds this stays
+// unconditional (a select or branch would let the compiler move the load into a
+// branch and wait for it there)
+__device__ __forceinline__ double keep_if(double x, bool ok) {
+  return __longlong_as_double(__double_as_longlong(x) & (ok ? ~0LL : 0LL));
+}
+
 // value of the lane that DPP control CTRL selects within this lane's 16-lane row
 // (0xB1: lane xor 1, 0x4E: lane xor 2, 0x141: mirrored within 8, 0x140: mirrored within 16)
 template <int CTRL>

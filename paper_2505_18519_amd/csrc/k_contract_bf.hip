@@ -85,9 +85,12 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
   extern __shared__ double smem[];
   // Y^T as BF16 (hi, and lo for X3) in the accumulator layout: entry (mq, n) holds
   // rows 4 mq .. 4 mq + 3 of column n, i.e. one stage-2 A operand
-  sx4* sYh = reinterpret_cast<sx4*>(smem);                    // [MT/4][NT]
-  sx4* sYl = sYh + (MT / 4) * NT;                             // [MT/4][NT] (X3)
-  double* sF = smem + (size_t)(MT / 4) * NT * (X3 ? 2 : 1);    // [2][NT][NT+1][2]
+  // Two buffers (vector parity): vector g + 1 writes the buffer vector g - 1 was
+  // read from, which the barriers of vector g have closed, so stage 1 needs no
+  // barrier of its own.
+  sx4* sYh = reinterpret_cast<sx4*>(smem);                    // [2][MT/4][NT]
+  sx4* sYl = sYh + 2 * (MT / 4) * NT;                         // [2][MT/4][NT] (X3)
+  double* sF = smem + (size_t)2 * (MT / 4) * NT * (X3 ? 2 : 1);  // [2][NT][NT+1][2]
   double* sD = sF + 2 * NT * (NT + 1) * 2;                     // [16][NWV*16][2]
   double* sE = sD + 16 * NWV * 16 * 2;                         // [NWV][2]
 
@@ -100,6 +103,8 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
 
   // B operands: bT[ct][t] = Phi_T[16t + 4g + j][16ct + c]; th[ri][t] = Theta^sp[16t + 4g + j][16jt + c]
   bsplit bT[NTC][KT], th[2][KT];
+  // loads are clamped in range and unconditional (masked afterwards), so that
+  // they are all in flight together rather than one branch at a time
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     float v[NTC][4], w[2][4];
@@ -107,15 +112,18 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
     for (int j = 0; j < 4; ++j) {
       const int m = 16 * t + 4 * g + j;
       const bool okm = active && m < M;
+      const int mc = min(m, M - 1);
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) {
         const int n = 16 * ct + c;
-        v[ct][j] = (okm && n < N) ? (float)phiT[((size_t)s * M + m) * N + n] : 0.f;
+        const double x = phiT[((size_t)s * M + mc) * N + min(n, N - 1)];
+        v[ct][j] = (float)keep_if(x, okm && n < N);
       }
       const int n = 16 * jt + c;
-      const double* src = theta + ((((size_t)s * 2 + sp) * M + m) * N + n) * 2;
-      w[0][j] = (okm && n < N) ? (float)src[0] : 0.f;
-      w[1][j] = (okm && n < N) ? (float)src[1] : 0.f;
+      const double2 x2 = *reinterpret_cast<const double2*>(
+          theta + ((((size_t)s * 2 + sp) * M + mc) * N + min(n, N - 1)) * 2);
+      w[0][j] = (float)keep_if(x2.x, okm && n < N);
+      w[1][j] = (float)keep_if(x2.y, okm && n < N);
     }
 #pragma unroll
     for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<X3>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
@@ -159,7 +167,7 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
           for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<X3>(aL[q][t], bT[ct][t], y1[q][ct]);
     // the next vector's L rows, in flight during the rest of this one
     if (gam < G) loadA(gam + 1, aL);
-    __syncthreads();  // previous vector's stage-2 and transpose reads are done
+    const int yb = (gam & 1) * (MT / 4) * NT;  // this vector's Y^T buffer
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wave + NWV * q;
@@ -169,8 +177,8 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
           const fx4 v = y1[q][ct];
           const bsplit b = split4<X3>(v[0], v[1], v[2], v[3]);
           const int o = (4 * tp + g) * NT + 16 * ct + c;
-          sYh[o] = b.hi;
-          if (X3) sYl[o] = b.lo;
+          sYh[yb + o] = b.hi;
+          if (X3) sYl[yb + o] = b.lo;
         }
     }
     __syncthreads();
@@ -180,17 +188,30 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
 #pragma unroll
     for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
     if (active) {
-#pragma unroll
-      for (int t = 0; t < KT; ++t)
+      // A operands of k tile t read one tile ahead
+      auto rdA = [&](int t, bsplit (&a)[NTC]) {
 #pragma unroll
         for (int it = 0; it < NTC; ++it) {
-          const int o = (4 * t + g) * NT + 16 * it + c;
-          bsplit a;
-          a.hi = sYh[o];
-          a.lo = X3 ? sYl[o] : sx4{0, 0, 0, 0};
-          f[it][0] = mma<X3>(a, th[0][t], f[it][0]);
-          f[it][1] = mma<X3>(a, th[1][t], f[it][1]);
+          const int o = yb + (4 * t + g) * NT + 16 * it + c;
+          a[it].hi = sYh[o];
+          a[it].lo = X3 ? sYl[o] : sx4{0, 0, 0, 0};
         }
+      };
+      bsplit ac[NTC], an[NTC];
+      rdA(0, ac);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        if (t + 1 < KT) rdA(t + 1, an);
+#pragma unroll
+        for (int it = 0; it < NTC; ++it) {
+          f[it][0] = mma<X3>(ac[it], th[0][t], f[it][0]);
+          f[it][1] = mma<X3>(ac[it], th[1][t], f[it][1]);
+        }
+        if (t + 1 < KT) {
+#pragma unroll
+          for (int it = 0; it < NTC; ++it) ac[it] = an[it];
+        }
+      }
     }
     // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
     double d_re = 0.0, d_im = 0.0;
@@ -292,7 +313,7 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
 
 size_t lds_bytes(int MT, int NTC, bool x3) {
   const int NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = (size_t)(MT / 4) * NT * 8 * (x3 ? 2 : 1);
+  size_t b = (size_t)2 * (MT / 4) * NT * 8 * (x3 ? 2 : 1);
   b += (size_t)2 * NT * (NT + 1) * 2 * 8;
   b += (size_t)16 * NWV * 16 * 2 * 8;
   b += (size_t)NWV * 2 * 8;

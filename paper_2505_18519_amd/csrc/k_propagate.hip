@@ -57,12 +57,12 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
       const double x = xi[(size_t)wa * xs + kc];
       const double br = XB ? xbar[((size_t)wa * xbs + kc) * 2] : 0.0;
       const double bi = XB ? xbar[((size_t)wa * xbs + kc) * 2 + 1] : 0.0;
-      cr[buf][q] = ok ? x - br : 0.0;
-      ci[buf][q] = ok ? -bi : 0.0;
+      cr[buf][q] = keep_if(x - br, ok);
+      ci[buf][q] = keep_if(-bi, ok);
 #pragma unroll
       for (int et = 0; et < 4; ++et) {
         const double v = L[(size_t)kc * MM + ec[et]];
-        b[buf][q][et] = (k < G && eok[et]) ? v : 0.0;
+        b[buf][q][et] = keep_if(v, k < G && eok[et]);
       }
     }
   };
@@ -353,14 +353,19 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
       const bool ok = t < KT && row < M && col < M;
-      vr[t][r] = ok ? V[((size_t)row * M + col) * 2] : 0.0;
-      nvi[t][r] = ok ? -V[((size_t)row * M + col) * 2 + 1] : 0.0;
+      // clamped, unconditional loads masked afterwards: all in flight together
+      const double2 v = *reinterpret_cast<const double2*>(
+          V + ((size_t)min(row, M - 1) * M + min(col, M - 1)) * 2);
+      vr[t][r] = keep_if(v.x, ok);
+      nvi[t][r] = keep_if(-v.y, ok);
     }
   for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
     const int m = q / NT, n = q % NT;
     const bool ok = m < M && n < N;
-    sY[2 * q] = ok ? in[((size_t)m * N + n) * 2] : 0.0;
-    sY[2 * q + 1] = ok ? in[((size_t)m * N + n) * 2 + 1] : 0.0;
+    const double2 v = *reinterpret_cast<const double2*>(
+        in + ((size_t)min(m, M - 1) * N + min(n, N - 1)) * 2);
+    sY[2 * q] = keep_if(v.x, ok);
+    sY[2 * q + 1] = keep_if(v.y, ok);
   }
   __syncthreads();
   // o = E Y (rows of this tile)
@@ -374,7 +379,8 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
         for (int r = 0; r < 4; ++r)
           {
             const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
-            const double e = (row < M && col < M) ? Eh[row * M + col] : 0.0;
+            const double e =
+                keep_if(Eh[min(row, M - 1) * M + min(col, M - 1)], row < M && col < M);
 #pragma unroll
             for (int ct = 0; ct < NTC; ++ct) {
               const double* yb = sY + ((16 * t + 4 * r + g) * NT + 16 * ct + c) * 2;

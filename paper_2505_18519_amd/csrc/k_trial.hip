@@ -62,12 +62,12 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
 #pragma unroll
       for (int pt = 0; pt < UB_PT; ++pt) {
         const double ya = y[(size_t)sa[pt] * K + kc];
-        a[buf][q][pt] = (sok[pt] && k < K) ? ya : 0.0;
+        a[buf][q][pt] = keep_if(ya, sok[pt] && k < K);
       }
 #pragma unroll
       for (int et = 0; et < 4; ++et) {
         const double v = A[(size_t)kc * MM + ec[et]];
-        b[buf][q][et] = (k < K && eok[et]) ? v : 0.0;
+        b[buf][q][et] = keep_if(v, k < K && eok[et]);
       }
     }
   };
