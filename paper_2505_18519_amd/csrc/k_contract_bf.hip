@@ -311,6 +311,295 @@ k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* 
     for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Plain BF16 with BCP paths per workgroup sharing each L slab: the slab of vector
+// g + 1 goes from global memory straight into LDS (global_load_lds) during
+// vector g, already in A-operand order ([row tile][k tile][lane][4]: one 8-byte
+// LDS read per product, consecutive lanes on consecutive words), so every L
+// byte crosses L2 once per workgroup instead of once per path.  Per path the
+// layout is that of k_contract_bf; f is staged for the transpose in FP32 (its
+// products are FP32) and the diagonals flush every BFL vectors.
+constexpr int BCP = 2;  // paths per workgroup
+constexpr int BFL = 8;  // vectors per flush of the staged diagonals
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+template <int KT, int NTC>
+__global__ void __launch_bounds__(128 * NTC * BCP)
+k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restrict__ Lop,
+               const double* __restrict__ phiT, const double* __restrict__ theta,
+               const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
+  constexpr int MT = 16 * KT;
+  constexpr int NWV = 2 * NTC;                 // wavefronts per path
+  constexpr int NWT = NWV * BCP;               // wavefronts per workgroup
+  constexpr int NT = 16 * NTC;
+  constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  constexpr int SLAB = MT * MT;                // BF16 entries per slab
+  constexpr int NU = SLAB / 8;                 // 16-byte units per slab
+  constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
+  constexpr int YT = (MT / 4) * NT;            // sx4 entries of one Y^T tile
+  extern __shared__ double smem[];
+  sx4* sL = reinterpret_cast<sx4*>(smem);                                  // [2][SLAB/4]
+  sx4* sY = sL + 2 * (SLAB / 4);                                           // [BCP][2][YT]
+  float* sF = reinterpret_cast<float*>(sY + BCP * 2 * YT);                 // [BCP][2][NT][NT+1][2]
+  double* sD = reinterpret_cast<double*>(sF + BCP * 2 * NT * (NT + 1) * 2);  // [BCP][BFL][NWV*16][2]
+  double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
+  double* sT = sE + BCP * NWV * 2;                                         // [NWT][4]
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int pw = wave / NWV, wv = wave % NWV;  // path of the workgroup, wavefront of the path
+  const int sp = wv & 1, jt = wv >> 1;
+  const int s = blockIdx.x * BCP + pw;
+  const bool valid = s < n_samples;            // every wavefront takes part in the barriers
+  const int sc = valid ? s : n_samples - 1;
+  const bool active = valid && !__builtin_isinf(logov[2 * sc]);
+
+  auto copy_slab = [&](int slab, int buf) {
+    const unsigned short* src = Lop + (size_t)slab * SLAB;
+    char* dst = reinterpret_cast<char*>(sL + buf * (SLAB / 4));
+    for (int k = wave; k < NCH; k += NWT)
+      if (k * 64 + lane < NU)  // lanes past a partial last chunk copy nothing
+        __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 512 + lane * 8),
+                                         (lds_ptr_t)(dst + k * 1024), 16, 0, 0);
+  };
+  copy_slab(0, 0);
+
+  // B operands (bit-masked unconditional loads)
+  bsplit bT[NTC][KT], th[2][KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    float v[NTC][4], w[2][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = 16 * t + 4 * g + j;
+      const bool okm = active && m < M;
+      const int mc = min(m, M - 1);
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        const int n = 16 * ct + c;
+        const double x = phiT[((size_t)sc * M + mc) * N + min(n, N - 1)];
+        v[ct][j] = (float)keep_if(x, okm && n < N);
+      }
+      const int n = 16 * jt + c;
+      const double2 x2 = *reinterpret_cast<const double2*>(
+          theta + ((((size_t)sc * 2 + sp) * M + mc) * N + min(n, N - 1)) * 2);
+      w[0][j] = (float)keep_if(x2.x, okm && n < N);
+      w[1][j] = (float)keep_if(x2.y, okm && n < N);
+    }
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<false>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<false>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
+  __syncthreads();
+
+  sx4* Yp = sY + pw * 2 * YT;
+  float* Fp = sF + (size_t)pw * 2 * NT * (NT + 1) * 2;
+  double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
+  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  for (int gam = 0; gam <= G; ++gam) {
+    const int b = gam & 1;
+    // stage 1: Y^T tiles (tp, ct) from the shared slab
+    fx4 y1[S1MAX][NTC];
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = fx4_zero();
+    const sx4* Ls = sL + b * (SLAB / 4);
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wv + NWV * q;
+      if (active && tp < KT)
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+          bsplit a;
+          a.hi = Ls[(tp * KT + t) * 64 + lane];
+          a.lo = sx4{0, 0, 0, 0};
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<false>(a, bT[ct][t], y1[q][ct]);
+        }
+    }
+    // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
+    if (gam < G) copy_slab(gam + 1, b ^ 1);
+    sx4* Yb = Yp + b * YT;
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wv + NWV * q;
+      if (tp < KT)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct) {
+          const fx4 v = y1[q][ct];
+          Yb[(4 * tp + g) * NT + 16 * ct + c] = split4<false>(v[0], v[1], v[2], v[3]).hi;
+        }
+    }
+    __syncthreads();
+    // stage 2: f^sp[it][jt], A[c][4g + j] = Y^T[16t + 4g + j][16it + c]
+    fx4 f[NTC][2];
+#pragma unroll
+    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
+    if (active) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int it = 0; it < NTC; ++it) {
+          bsplit a;
+          a.hi = Yb[(4 * t + g) * NT + 16 * it + c];
+          a.lo = sx4{0, 0, 0, 0};
+          f[it][0] = mma<false>(a, th[0][t], f[it][0]);
+          f[it][1] = mma<false>(a, th[1][t], f[it][1]);
+        }
+    }
+    // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
+    double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+      if (it == jt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * g + r == c) {
+            d_re = (double)f[it][0][r];
+            d_im = (double)f[it][1][r];
+          }
+    if (gam == G) {  // h1': the path's one-body traces through LDS
+      d_re = wave_sum(d_re);
+      d_im = wave_sum(d_im);
+      if (lane == 0) {
+        sE[wave * 2] = d_re;
+        sE[wave * 2 + 1] = d_im;
+      }
+      __syncthreads();
+      if (wv == 0 && lane == 0) {
+        for (int w = 0; w < NWV; ++w) {
+          e1_re += sE[(pw * NWV + w) * 2];
+          e1_im += sE[(pw * NWV + w) * 2 + 1];
+        }
+      }
+      break;
+    }
+    // stage f^sp[:, jt] for the transpose, and the diagonal partials
+    float* Fs = Fp + (size_t)sp * NT * (NT + 1) * 2;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
+        Fs[(i * (NT + 1) + j) * 2] = f[it][0][r];
+        Fs[(i * (NT + 1) + j) * 2 + 1] = f[it][1][r];
+      }
+    if (g == (c >> 2)) {
+      double* d = Dp + ((size_t)(gam % BFL) * NWV * 16 + wv * 16 + c) * 2;
+      d[0] = d_re;
+      d[1] = d_im;
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
+        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
+        ex_re += ar * tr_ - ai * ti_;
+        ex_im += ar * ti_ + ai * tr_;
+      }
+    // every BFL vectors: wavefront 0 of each path reduces its staged diagonals to vb_g
+    if ((gam % BFL == BFL - 1 || gam == G - 1) && wv == 0 && valid) {
+      const int cnt = gam % BFL + 1, g0 = gam - gam % BFL;
+      const int gl = lane % BFL, part = (lane / BFL) & 1;
+      double v = 0.0;
+      if (lane < 2 * BFL && gl < cnt)
+        for (int q = 0; q < NWV * 16; ++q) v += Dp[((size_t)gl * NWV * 16 + q) * 2 + part];
+      const double vi = __shfl_down(v, BFL, 64);
+      if (lane < BFL && gl < cnt) {
+        vb2_re += v * v - vi * vi;
+        vb2_im += 2.0 * v * vi;
+        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
+        o[0] = v;
+        o[1] = vi;
+      }
+    }
+  }
+  // totals per path: ex from every lane of its wavefronts, vb^2 from its wavefront 0
+  ex_re = wave_sum(ex_re);
+  ex_im = wave_sum(ex_im);
+  vb2_re = wave_sum(vb2_re);
+  vb2_im = wave_sum(vb2_im);
+  if (lane == 0) {
+    sT[wave * 4 + 0] = ex_re;
+    sT[wave * 4 + 1] = ex_im;
+    sT[wave * 4 + 2] = vb2_re;
+    sT[wave * 4 + 3] = vb2_im;
+  }
+  __syncthreads();
+  if (valid && wv == 0 && lane == 0) {
+    double xr = 0.0, xi = 0.0;
+    for (int w = 0; w < NWV; ++w) {
+      xr += sT[(pw * NWV + w) * 4 + 0];
+      xi += sT[(pw * NWV + w) * 4 + 1];
+    }
+    const double br = sT[pw * NWV * 4 + 2], bi = sT[pw * NWV * 4 + 3];
+    double* o = ep + (size_t)s * 2;
+    o[0] = active ? e1_re + 0.5 * br - 0.5 * xr : 0.0;
+    o[1] = active ? e1_im + 0.5 * bi - 0.5 * xi : 0.0;
+  }
+  if (valid && !active && wv == 0)
+    for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
+}
+
+size_t lds_bytes_s(int KT, int NTC) {
+  const int MT = 16 * KT, NT = 16 * NTC, NWV = 2 * NTC;
+  size_t b = (size_t)2 * MT * MT * 2;                 // slabs
+  b += (size_t)BCP * 2 * (MT / 4) * NT * 8;           // Y^T tiles
+  b += (size_t)BCP * 2 * NT * (NT + 1) * 2 * 4;       // f (FP32)
+  b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
+  b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
+  return b;
+}
+
+template <int KT, int NTC>
+hipError_t launch_bfs(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                      const double* logov, double* vb, double* ep) {
+  const int n = nw * c->P;
+  const size_t lds = lds_bytes_s(KT, NTC);
+  auto kern = k_contract_bfs<KT, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((n + BCP - 1) / BCP), dim3(128 * NTC * BCP), lds, c->stream, n,
+                     c->M, c->N, c->G, c->d_Lbf, phiT, theta, logov, vb, ep);
+  return hipGetLastError();
+}
+
+hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
+                      const double* logov, double* vb, double* ep) {
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_BS(KK, NC) \
+  if (KT == KK && NTC == NC) return launch_bfs<KK, NC>(c, nw, phiT, theta, logov, vb, ep);
+  AFQMC_BS(1, 1) AFQMC_BS(2, 1) AFQMC_BS(3, 1) AFQMC_BS(4, 1)
+  AFQMC_BS(5, 1) AFQMC_BS(6, 1) AFQMC_BS(7, 1) AFQMC_BS(8, 1)
+  AFQMC_BS(2, 2) AFQMC_BS(3, 2) AFQMC_BS(4, 2)
+  AFQMC_BS(5, 2) AFQMC_BS(6, 2) AFQMC_BS(7, 2) AFQMC_BS(8, 2)
+#undef AFQMC_BS
+  return hipErrorInvalidValue;
+}
+
+// L (double, row-major slabs) -> BF16 in A-operand order [slab][tp][t][g][c][j] =
+// L[slab][16 tp + c][16 t + 4 g + j]
+__global__ void k_to_bf16_op(size_t n, int MT, const double* __restrict__ src,
+                             unsigned short* __restrict__ dst) {
+  const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int KT = MT / 16;
+  const size_t slab = o / ((size_t)MT * MT);
+  const int r = (int)(o % ((size_t)MT * MT));
+  const int j = r & 3, cc = (r >> 2) & 15, gg = (r >> 6) & 3, t = (r >> 8) % KT, tp = (r >> 8) / KT;
+  dst[o] = f2bf((float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + 16 * t + 4 * gg + j]);
+}
+
 size_t lds_bytes(int MT, int NTC, bool x3) {
   const int NT = 16 * NTC, NWV = 2 * NTC;
   size_t b = (size_t)2 * (MT / 4) * NT * 8 * (x3 ? 2 : 1);
@@ -369,12 +658,17 @@ hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
     if (c->d_Lbf_lo == nullptr) return hipErrorInvalidValue;
     return dispatch<true>(c, nw, phiT, theta, logov, vb, ep);
   }
-  return dispatch<false>(c, nw, phiT, theta, logov, vb, ep);
+  return dispatch_s(c, nw, phiT, theta, logov, vb, ep);
 }
 
 hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
                           unsigned short* lo) {
   if (n == 0) return hipSuccess;
+  if (c->precision == AFQMC_PREC_BF16) {  // plain BF16: the shared-slab kernel's operand order
+    hipLaunchKernelGGL(k_to_bf16_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                       c->MT, src, hi);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, src,
                      hi, lo);
   return hipGetLastError();
