@@ -12,7 +12,11 @@
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
 // brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
 //
-// Layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16));
+// k_contract_bf (used for the split form; one path per workgroup) and
+// k_contract_bfs (plain BF16; two paths per workgroup sharing each L slab
+// through LDS, described at its definition).
+//
+// k_contract_bf layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16));
 // wavefront w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt]
 // as BF16 B operands in registers for the whole loop over g, and Phi_T
 // (all column tiles) as the stage-1 B operands.  Stage 1 (Y_g^T = L_g Phi_T)
