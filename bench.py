@@ -543,7 +543,7 @@ def main():
                      "traffic": measured_traffic(args.workload),
                      "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
                                 and not ctx.ctrial else
-                                "k_contract_bf" if precision in (2, 3) else "k_contract_g")
+                                "k_contract_bfs" if precision in (2, 3) else "k_contract_g")
                                + (" (complex trial)" if ctx.ctrial else "")
                                + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},

@@ -26,8 +26,8 @@ struct afqmc_ctx_s {
   double* d_phi0 = nullptr;  // [M][N]
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
-  unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad (BF16 contraction)
-  unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf (split-BF16 contraction)
+  unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad, A-operand order (BF16 contractions)
+  unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf, same order (split BF16)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
 
   // trial family (AFQMC_TRIAL_*); multi-slice trials have complex Phi_T and

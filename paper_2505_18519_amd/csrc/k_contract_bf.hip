@@ -12,21 +12,17 @@
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
 // brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
 //
-// k_contract_bf (used for the split form; one path per workgroup) and
-// k_contract_bfs (plain BF16; two paths per workgroup sharing each L slab
-// through LDS, described at its definition).
-//
-// k_contract_bf layout: one workgroup per path with 2 * NTC wavefronts (NTC = ceil(N/16));
-// wavefront w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt]
-// as BF16 B operands in registers for the whole loop over g, and Phi_T
-// (all column tiles) as the stage-1 B operands.  Stage 1 (Y_g^T = L_g Phi_T)
-// is split over the wavefronts by row tile; each reads its rows of the BF16
-// copy of L_g (eight contiguous bytes per lane) one vector ahead, so the loads
-// of vector g + 1 are in flight during stage 2 of vector g.  Y_g^T is rounded
-// to BF16 once, as stage 1 leaves it, and stored in LDS in the accumulator
-// layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a column in
-// one lane); f is transposed through LDS for tr(f f); traces, vb_g^2 and the
-// sums over g are FP64.
+// k_contract_bfs serves both forms: BCP paths per workgroup share each L slab
+// through LDS.  Per path, 2 * NTC wavefronts (NTC = ceil(N/16)); wavefront
+// w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt] as BF16 B
+// operands in registers for the whole loop over g, and Phi_T (all column
+// tiles) as the stage-1 B operands.  Stage 1 (Y_g^T = L_g Phi_T) is split over
+// the path's wavefronts by row tile, its A operands read from the shared slab.
+// Y_g^T is rounded to BF16 once, as stage 1 leaves it, and stored in LDS in the
+// accumulator layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a
+// column in one lane); f is transposed through LDS for tr(f f); traces, vb_g^2
+// and the sums over g are FP64.
+
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -77,262 +73,25 @@ __device__ __forceinline__ fx4 fx4_zero() {
   return z;
 }
 
-template <int KT, int NTC, bool X3>
-__global__ void __launch_bounds__(128 * NTC)
-k_contract_bf(int n_samples, int M, int N, int G, int MT, const unsigned short* __restrict__ Lhi,
-              const unsigned short* __restrict__ Llo, const double* __restrict__ phiT,
-              const double* __restrict__ theta, const double* __restrict__ logov,
-              double* __restrict__ vb, double* __restrict__ ep) {
-  constexpr int NWV = 2 * NTC;                 // wavefronts
-  constexpr int NT = 16 * NTC;
-  constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
-  extern __shared__ double smem[];
-  // Y^T as BF16 (hi, and lo for X3) in the accumulator layout: entry (mq, n) holds
-  // rows 4 mq .. 4 mq + 3 of column n, i.e. one stage-2 A operand
-  // Two buffers (vector parity): vector g + 1 writes the buffer vector g - 1 was
-  // read from, which the barriers of vector g have closed, so stage 1 needs no
-  // barrier of its own.
-  sx4* sYh = reinterpret_cast<sx4*>(smem);                    // [2][MT/4][NT]
-  sx4* sYl = sYh + 2 * (MT / 4) * NT;                         // [2][MT/4][NT] (X3)
-  double* sF = smem + (size_t)2 * (MT / 4) * NT * (X3 ? 2 : 1);  // [2][NT][NT+1][2]
-  double* sD = sF + 2 * NT * (NT + 1) * 2;                     // [16][NWV*16][2]
-  double* sE = sD + 16 * NWV * 16 * 2;                         // [NWV][2]
-
-  const int s = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, c = lane & 15;
-  const int sp = wave & 1, jt = wave >> 1;
-  if (s >= n_samples) return;  // whole block exits together
-  const bool active = !__builtin_isinf(logov[2 * s]);
-
-  // B operands: bT[ct][t] = Phi_T[16t + 4g + j][16ct + c]; th[ri][t] = Theta^sp[16t + 4g + j][16jt + c]
-  bsplit bT[NTC][KT], th[2][KT];
-  // loads are clamped in range and unconditional (masked afterwards), so that
-  // they are all in flight together rather than one branch at a time
-#pragma unroll
-  for (int t = 0; t < KT; ++t) {
-    float v[NTC][4], w[2][4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = 16 * t + 4 * g + j;
-      const bool okm = active && m < M;
-      const int mc = min(m, M - 1);
-#pragma unroll
-      for (int ct = 0; ct < NTC; ++ct) {
-        const int n = 16 * ct + c;
-        const double x = phiT[((size_t)s * M + mc) * N + min(n, N - 1)];
-        v[ct][j] = (float)keep_if(x, okm && n < N);
-      }
-      const int n = 16 * jt + c;
-      const double2 x2 = *reinterpret_cast<const double2*>(
-          theta + ((((size_t)s * 2 + sp) * M + mc) * N + min(n, N - 1)) * 2);
-      w[0][j] = (float)keep_if(x2.x, okm && n < N);
-      w[1][j] = (float)keep_if(x2.y, okm && n < N);
-    }
-#pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<X3>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
-#pragma unroll
-    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<X3>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
-  }
-
-  // stage-1 A operands of row tile tp = wave + NWV q: L[16tp + c][16t + 4g .. +3]
-  // (row tiles past KT are clamped in range and their products skipped)
-  const size_t slab = (size_t)MT * MT;
-  auto loadA = [&](int gam, bsplit (&a)[S1MAX][KT]) {
-#pragma unroll
-    for (int q = 0; q < S1MAX; ++q) {
-      const int tp = min(wave + NWV * q, KT - 1);
-#pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const size_t o = (size_t)gam * slab + (size_t)(16 * tp + c) * MT + 16 * t + 4 * g;
-        a[q][t].hi = *reinterpret_cast<const sx4*>(Lhi + o);
-        if (X3) a[q][t].lo = *reinterpret_cast<const sx4*>(Llo + o);
-        else a[q][t].lo = sx4{0, 0, 0, 0};
-      }
-    }
-  };
-  bsplit aL[S1MAX][KT];
-  loadA(0, aL);
-
-  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
-  for (int gam = 0; gam <= G; ++gam) {
-    // stage 1: Y^T tiles (tp, ct)
-    fx4 y1[S1MAX][NTC];
-#pragma unroll
-    for (int q = 0; q < S1MAX; ++q)
-#pragma unroll
-      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = fx4_zero();
-#pragma unroll
-    for (int q = 0; q < S1MAX; ++q)
-      if (active && wave + NWV * q < KT)
-#pragma unroll
-        for (int t = 0; t < KT; ++t)
-#pragma unroll
-          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<X3>(aL[q][t], bT[ct][t], y1[q][ct]);
-    // the next vector's L rows, in flight during the rest of this one
-    if (gam < G) loadA(gam + 1, aL);
-    const int yb = (gam & 1) * (MT / 4) * NT;  // this vector's Y^T buffer
-#pragma unroll
-    for (int q = 0; q < S1MAX; ++q) {
-      const int tp = wave + NWV * q;
-      if (tp < KT)
-#pragma unroll
-        for (int ct = 0; ct < NTC; ++ct) {
-          const fx4 v = y1[q][ct];
-          const bsplit b = split4<X3>(v[0], v[1], v[2], v[3]);
-          const int o = (4 * tp + g) * NT + 16 * ct + c;
-          sYh[yb + o] = b.hi;
-          if (X3) sYl[yb + o] = b.lo;
-        }
-    }
-    __syncthreads();
-    // stage 2: f^sp[it][jt] = sum_m Y[it rows][m] Theta^sp[m][jt cols];
-    // A[c][4g + j] = Y^T[16t + 4g + j][16it + c]
-    fx4 f[NTC][2];
-#pragma unroll
-    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
-    if (active) {
-      // A operands of k tile t read one tile ahead
-      auto rdA = [&](int t, bsplit (&a)[NTC]) {
-#pragma unroll
-        for (int it = 0; it < NTC; ++it) {
-          const int o = yb + (4 * t + g) * NT + 16 * it + c;
-          a[it].hi = sYh[o];
-          a[it].lo = X3 ? sYl[o] : sx4{0, 0, 0, 0};
-        }
-      };
-      bsplit ac[NTC], an[NTC];
-      rdA(0, ac);
-#pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        if (t + 1 < KT) rdA(t + 1, an);
-#pragma unroll
-        for (int it = 0; it < NTC; ++it) {
-          f[it][0] = mma<X3>(ac[it], th[0][t], f[it][0]);
-          f[it][1] = mma<X3>(ac[it], th[1][t], f[it][1]);
-        }
-        if (t + 1 < KT) {
-#pragma unroll
-          for (int it = 0; it < NTC; ++it) ac[it] = an[it];
-        }
-      }
-    }
-    // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
-    double d_re = 0.0, d_im = 0.0;
-#pragma unroll
-    for (int it = 0; it < NTC; ++it)
-      if (it == jt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * g + r == c) {
-            d_re = (double)f[it][0][r];
-            d_im = (double)f[it][1][r];
-          }
-    if (gam == G) {  // h1': both spins' one-body traces through LDS
-      d_re = wave_sum(d_re);
-      d_im = wave_sum(d_im);
-      if (lane == 0) {
-        sE[wave * 2] = d_re;
-        sE[wave * 2 + 1] = d_im;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int w = 0; w < NWV; ++w) {
-          e1_re += sE[w * 2];
-          e1_im += sE[w * 2 + 1];
-        }
-      }
-      break;
-    }
-    // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
-    double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
-#pragma unroll
-    for (int it = 0; it < NTC; ++it)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
-        Fs[(i * (NT + 1) + j) * 2] = (double)f[it][0][r];
-        Fs[(i * (NT + 1) + j) * 2 + 1] = (double)f[it][1][r];
-      }
-    if (g == (c >> 2)) {  // the lane group holding row c of tile jt
-      double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
-      d[0] = d_re;
-      d[1] = d_im;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < NTC; ++it)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
-        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
-        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
-        ex_re += ar * tr_ - ai * ti_;
-        ex_im += ar * ti_ + ai * tr_;
-      }
-    // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
-    if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
-      const int cnt = (gam & 15) + 1, g0 = gam & ~15;
-      const int gl = lane & 15, part = (lane >> 4) & 1;
-      double v = 0.0;
-      if (lane < 32 && gl < cnt)
-        for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
-      const double vi = __shfl_down(v, 16, 64);
-      if (lane < 16 && gl < cnt) {
-        vb2_re += v * v - vi * vi;
-        vb2_im += 2.0 * v * vi;
-        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
-        o[0] = v;
-        o[1] = vi;
-      }
-    }
-  }
-  // totals: ex from every lane of every wavefront, vb^2 from wavefront 0
-  ex_re = wave_sum(ex_re);
-  ex_im = wave_sum(ex_im);
-  vb2_re = wave_sum(vb2_re);
-  vb2_im = wave_sum(vb2_im);
-  __syncthreads();
-  if (lane == 0) {
-    sD[wave * 4 + 0] = ex_re;
-    sD[wave * 4 + 1] = ex_im;
-    sD[wave * 4 + 2] = vb2_re;
-    sD[wave * 4 + 3] = vb2_im;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double xr = 0.0, xi = 0.0;
-    for (int w = 0; w < NWV; ++w) {
-      xr += sD[w * 4 + 0];
-      xi += sD[w * 4 + 1];
-    }
-    const double br = sD[2], bi = sD[3];
-    double* o = ep + (size_t)s * 2;
-    o[0] = active ? e1_re + 0.5 * br - 0.5 * xr : 0.0;
-    o[1] = active ? e1_im + 0.5 * bi - 0.5 * xi : 0.0;
-  }
-  if (!active)
-    for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
-}
-
 // ---------------------------------------------------------------------------
-// Plain BF16 with BCP paths per workgroup sharing each L slab: the slab of vector
-// g + 1 goes from global memory straight into LDS (global_load_lds) during
-// vector g, already in A-operand order ([row tile][k tile][lane][4]: one 8-byte
-// LDS read per product, consecutive lanes on consecutive words), so every L
-// byte crosses L2 once per workgroup instead of once per path.  Per path the
-// layout is that of k_contract_bf; f is staged for the transpose in FP32 (its
-// products are FP32) and the diagonals flush every BFL vectors.
+// BCP paths per workgroup sharing each L slab: the slab of vector g + 1 goes
+// from global memory straight into LDS (global_load_lds) during vector g,
+// already in A-operand order ([row tile][k tile][lane][4]: one 8-byte LDS read
+// per product, consecutive lanes on consecutive words), so every L byte crosses
+// L2 once per workgroup instead of once per path.  f is staged for the
+// transpose in FP32 (its products are FP32) and the diagonals flush every BFL
+// vectors.
 constexpr int BCP = 2;  // paths per workgroup
 constexpr int BFL = 8;  // vectors per flush of the staged diagonals
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
-template <int KT, int NTC>
+template <int KT, int NTC, bool X3>
 __global__ void __launch_bounds__(128 * NTC * BCP)
 k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restrict__ Lop,
-               const double* __restrict__ phiT, const double* __restrict__ theta,
+               const unsigned short* __restrict__ Lop_lo, const double* __restrict__ phiT,
+               const double* __restrict__ theta,
                const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   constexpr int MT = 16 * KT;
   constexpr int NWV = 2 * NTC;                 // wavefronts per path
@@ -343,10 +102,15 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
   constexpr int NU = SLAB / 8;                 // 16-byte units per slab
   constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
   constexpr int YT = (MT / 4) * NT;            // sx4 entries of one Y^T tile
+  // plain BF16: slabs and Y^T tiles double-buffered (the next slab loads during
+  // the whole vector); split BF16 (hi and lo of each): single buffers, the next
+  // slab loading from the barrier after stage 1 on, so that LDS still fits
+  constexpr int NB = X3 ? 1 : 2;               // buffers
+  constexpr int NP = X3 ? 2 : 1;               // parts (hi, lo)
   extern __shared__ double smem[];
-  sx4* sL = reinterpret_cast<sx4*>(smem);                                  // [2][SLAB/4]
-  sx4* sY = sL + 2 * (SLAB / 4);                                           // [BCP][2][YT]
-  float* sF = reinterpret_cast<float*>(sY + BCP * 2 * YT);                 // [BCP][2][NT][NT+1][2]
+  sx4* sL = reinterpret_cast<sx4*>(smem);                                  // [NB][NP][SLAB/4]
+  sx4* sY = sL + NB * NP * (SLAB / 4);                                     // [BCP][NB][NP][YT]
+  float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][2][NT][NT+1][2]
   double* sD = reinterpret_cast<double*>(sF + BCP * 2 * NT * (NT + 1) * 2);  // [BCP][BFL][NWV*16][2]
   double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
   double* sT = sE + BCP * NWV * 2;                                         // [NWT][4]
@@ -361,12 +125,15 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
   const bool active = valid && !__builtin_isinf(logov[2 * sc]);
 
   auto copy_slab = [&](int slab, int buf) {
-    const unsigned short* src = Lop + (size_t)slab * SLAB;
-    char* dst = reinterpret_cast<char*>(sL + buf * (SLAB / 4));
-    for (int k = wave; k < NCH; k += NWT)
-      if (k * 64 + lane < NU)  // lanes past a partial last chunk copy nothing
-        __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 512 + lane * 8),
-                                         (lds_ptr_t)(dst + k * 1024), 16, 0, 0);
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      const unsigned short* src = (part ? Lop_lo : Lop) + (size_t)slab * SLAB;
+      char* dst = reinterpret_cast<char*>(sL + (buf * NP + part) * (SLAB / 4));
+      for (int k = wave; k < NCH; k += NWT)
+        if (k * 64 + lane < NU)  // lanes past a partial last chunk copy nothing
+          __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 512 + lane * 8),
+                                           (lds_ptr_t)(dst + k * 1024), 16, 0, 0);
+    }
   };
   copy_slab(0, 0);
 
@@ -393,26 +160,26 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
       w[1][j] = (float)keep_if(x2.y, okm && n < N);
     }
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<false>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
+    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<X3>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<false>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
+    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<X3>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
-  sx4* Yp = sY + pw * 2 * YT;
+  sx4* Yp = sY + pw * NB * NP * YT;
   float* Fp = sF + (size_t)pw * 2 * NT * (NT + 1) * 2;
   double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
   for (int gam = 0; gam <= G; ++gam) {
-    const int b = gam & 1;
+    const int b = NB == 2 ? (gam & 1) : 0;
     // stage 1: Y^T tiles (tp, ct) from the shared slab
     fx4 y1[S1MAX][NTC];
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q)
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = fx4_zero();
-    const sx4* Ls = sL + b * (SLAB / 4);
+    const sx4* Ls = sL + b * NP * (SLAB / 4);
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -421,14 +188,14 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
         for (int t = 0; t < KT; ++t) {
           bsplit a;
           a.hi = Ls[(tp * KT + t) * 64 + lane];
-          a.lo = sx4{0, 0, 0, 0};
+          a.lo = X3 ? Ls[SLAB / 4 + (tp * KT + t) * 64 + lane] : sx4{0, 0, 0, 0};
 #pragma unroll
-          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<false>(a, bT[ct][t], y1[q][ct]);
+          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<X3>(a, bT[ct][t], y1[q][ct]);
         }
     }
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
-    if (gam < G) copy_slab(gam + 1, b ^ 1);
-    sx4* Yb = Yp + b * YT;
+    if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
+    sx4* Yb = Yp + b * NP * YT;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -436,10 +203,14 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
 #pragma unroll
         for (int ct = 0; ct < NTC; ++ct) {
           const fx4 v = y1[q][ct];
-          Yb[(4 * tp + g) * NT + 16 * ct + c] = split4<false>(v[0], v[1], v[2], v[3]).hi;
+          const bsplit yv = split4<X3>(v[0], v[1], v[2], v[3]);
+          Yb[(4 * tp + g) * NT + 16 * ct + c] = yv.hi;
+          if (X3) Yb[YT + (4 * tp + g) * NT + 16 * ct + c] = yv.lo;
         }
     }
     __syncthreads();
+    // single buffers: every stage-1 read of this slab is done, the next one can load
+    if (NB == 1 && gam < G) copy_slab(gam + 1, 0);
     // stage 2: f^sp[it][jt], A[c][4g + j] = Y^T[16t + 4g + j][16it + c]
     fx4 f[NTC][2];
 #pragma unroll
@@ -451,9 +222,9 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
         for (int it = 0; it < NTC; ++it) {
           bsplit a;
           a.hi = Yb[(4 * t + g) * NT + 16 * it + c];
-          a.lo = sx4{0, 0, 0, 0};
-          f[it][0] = mma<false>(a, th[0][t], f[it][0]);
-          f[it][1] = mma<false>(a, th[1][t], f[it][1]);
+          a.lo = X3 ? Yb[YT + (4 * t + g) * NT + 16 * it + c] : sx4{0, 0, 0, 0};
+          f[it][0] = mma<X3>(a, th[0][t], f[it][0]);
+          f[it][1] = mma<X3>(a, th[1][t], f[it][1]);
         }
     }
     // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
@@ -554,35 +325,37 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
     for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-size_t lds_bytes_s(int KT, int NTC) {
+size_t lds_bytes_s(int KT, int NTC, bool x3) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = (size_t)2 * MT * MT * 2;                 // slabs
-  b += (size_t)BCP * 2 * (MT / 4) * NT * 8;           // Y^T tiles
+  const int nbp = 2;                                  // buffers x parts: 2 x 1 or 1 x 2
+  size_t b = (size_t)nbp * MT * MT * 2;               // slabs
+  b += (size_t)BCP * nbp * (MT / 4) * NT * 8;         // Y^T tiles
   b += (size_t)BCP * 2 * NT * (NT + 1) * 2 * 4;       // f (FP32)
   b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
   b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
   return b;
 }
 
-template <int KT, int NTC>
+template <int KT, int NTC, bool X3>
 hipError_t launch_bfs(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                       const double* logov, double* vb, double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes_s(KT, NTC);
-  auto kern = k_contract_bfs<KT, NTC>;
+  const size_t lds = lds_bytes_s(KT, NTC, X3);
+  auto kern = k_contract_bfs<KT, NTC, X3>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((n + BCP - 1) / BCP), dim3(128 * NTC * BCP), lds, c->stream, n,
-                     c->M, c->N, c->G, c->d_Lbf, phiT, theta, logov, vb, ep);
+                     c->M, c->N, c->G, c->d_Lbf, c->d_Lbf_lo, phiT, theta, logov, vb, ep);
   return hipGetLastError();
 }
 
+template <bool X3>
 hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                       const double* logov, double* vb, double* ep) {
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
 #define AFQMC_BS(KK, NC) \
-  if (KT == KK && NTC == NC) return launch_bfs<KK, NC>(c, nw, phiT, theta, logov, vb, ep);
+  if (KT == KK && NTC == NC) return launch_bfs<KK, NC, X3>(c, nw, phiT, theta, logov, vb, ep);
   AFQMC_BS(1, 1) AFQMC_BS(2, 1) AFQMC_BS(3, 1) AFQMC_BS(4, 1)
   AFQMC_BS(5, 1) AFQMC_BS(6, 1) AFQMC_BS(7, 1) AFQMC_BS(8, 1)
   AFQMC_BS(2, 2) AFQMC_BS(3, 2) AFQMC_BS(4, 2)
@@ -592,64 +365,19 @@ hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const double* phiT, const do
 }
 
 // L (double, row-major slabs) -> BF16 in A-operand order [slab][tp][t][g][c][j] =
-// L[slab][16 tp + c][16 t + 4 g + j]
+// L[slab][16 tp + c][16 t + 4 g + j]; with lo given, also lo = bf16(L - hi) in that order
 __global__ void k_to_bf16_op(size_t n, int MT, const double* __restrict__ src,
-                             unsigned short* __restrict__ dst) {
+                             unsigned short* __restrict__ dst, unsigned short* __restrict__ lo) {
   const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
   const int KT = MT / 16;
   const size_t slab = o / ((size_t)MT * MT);
   const int r = (int)(o % ((size_t)MT * MT));
   const int j = r & 3, cc = (r >> 2) & 15, gg = (r >> 6) & 3, t = (r >> 8) % KT, tp = (r >> 8) / KT;
-  dst[o] = f2bf((float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + 16 * t + 4 * gg + j]);
-}
-
-size_t lds_bytes(int MT, int NTC, bool x3) {
-  const int NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = (size_t)2 * (MT / 4) * NT * 8 * (x3 ? 2 : 1);
-  b += (size_t)2 * NT * (NT + 1) * 2 * 8;
-  b += (size_t)16 * NWV * 16 * 2 * 8;
-  b += (size_t)NWV * 2 * 8;
-  return b;
-}
-
-template <int KT, int NTC, bool X3>
-hipError_t launch_bf(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
-                     const double* logov, double* vb, double* ep) {
-  const int n = nw * c->P;
-  const size_t lds = lds_bytes(c->MT, NTC, X3);
-  auto kern = k_contract_bf<KT, NTC, X3>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n), dim3(128 * NTC), lds, c->stream, n, c->M, c->N, c->G, c->MT,
-                     c->d_Lbf, c->d_Lbf_lo, phiT, theta, logov, vb, ep);
-  return hipGetLastError();
-}
-
-template <bool X3>
-hipError_t dispatch(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
-                    const double* logov, double* vb, double* ep) {
-  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_B(KK, NC) \
-  if (KT == KK && NTC == NC) return launch_bf<KK, NC, X3>(c, nw, phiT, theta, logov, vb, ep);
-  AFQMC_B(1, 1) AFQMC_B(2, 1) AFQMC_B(3, 1) AFQMC_B(4, 1)
-  AFQMC_B(5, 1) AFQMC_B(6, 1) AFQMC_B(7, 1) AFQMC_B(8, 1)
-  AFQMC_B(2, 2) AFQMC_B(3, 2) AFQMC_B(4, 2)
-  AFQMC_B(5, 2) AFQMC_B(6, 2) AFQMC_B(7, 2) AFQMC_B(8, 2)
-#undef AFQMC_B
-  return hipErrorInvalidValue;
-}
-
-// L (double) -> BF16 hi and, when lo is given, lo = bf16(L - hi)
-__global__ void k_to_bf16(size_t n, const double* __restrict__ src, unsigned short* __restrict__ hi,
-                          unsigned short* __restrict__ lo) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float x = (float)src[i];
+  const float x = (float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + 16 * t + 4 * gg + j];
   const unsigned short h = f2bf(x);
-  hi[i] = h;
-  if (lo != nullptr) lo[i] = f2bf(x - bf2f(h));
+  dst[o] = h;
+  if (lo != nullptr) lo[o] = f2bf(x - bf2f(h));
 }
 
 }  // namespace
@@ -660,20 +388,16 @@ hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
   if (c->d_Lbf == nullptr) return hipErrorInvalidValue;
   if (c->precision == AFQMC_PREC_BF16X3) {
     if (c->d_Lbf_lo == nullptr) return hipErrorInvalidValue;
-    return dispatch<true>(c, nw, phiT, theta, logov, vb, ep);
+    return dispatch_s<true>(c, nw, phiT, theta, logov, vb, ep);
   }
-  return dispatch_s(c, nw, phiT, theta, logov, vb, ep);
+  return dispatch_s<false>(c, nw, phiT, theta, logov, vb, ep);
 }
 
 hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
                           unsigned short* lo) {
   if (n == 0) return hipSuccess;
-  if (c->precision == AFQMC_PREC_BF16) {  // plain BF16: the shared-slab kernel's operand order
-    hipLaunchKernelGGL(k_to_bf16_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
-                       c->MT, src, hi);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, src,
-                     hi, lo);
+  // the shared-slab kernels' A-operand order (lo only for the split form)
+  hipLaunchKernelGGL(k_to_bf16_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                     c->MT, src, hi, lo);
   return hipGetLastError();
 }
