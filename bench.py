@@ -193,7 +193,7 @@ def learned_study(args):
                    "xbar_cap": xbar_cap, "comb_every": n_pc, "weight_cap": w_cap},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "kernel": "k_contract_g<float> (+ k_combine) in afqmc_local_energy",
+                     "kernel": "k_contract_sh, FP32 products (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": L["contraction_ms"], "flops_per_launch": flops},
         "learned_mixed": L,
         "random_walk_fp64": R,
@@ -335,7 +335,7 @@ def mixed_study(args):
                    "paths": P},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "kernel": "k_contract_g<float> (+ k_combine) in afqmc_local_energy",
+                     "kernel": "k_contract_sh, FP32 products (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": F32["contraction_ms"], "flops_per_launch": flops},
         "fp32_products": F32, "bf16x3_products": B3, "bf16_products": B1, "fp64": F64,
         "energy_difference": F32["energy"] - F64["energy"], "combined_error": comb,
@@ -543,7 +543,8 @@ def main():
                      "traffic": measured_traffic(args.workload),
                      "kernel": ("k_contract" if sys_.M <= 64 and sys_.N <= 16 and precision == 0
                                 and not ctx.ctrial else
-                                "k_contract_bfs" if precision in (2, 3) else "k_contract_g")
+                                "k_contract_sh" if precision in (1, 2, 3) and not ctx.ctrial
+                                else "k_contract_g")
                                + (" (complex trial)" if ctx.ctrial else "")
                                + " (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": contract_ms, "flops_per_launch": flops},

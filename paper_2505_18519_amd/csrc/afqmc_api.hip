@@ -295,7 +295,8 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if ((e = launch_setup(c)) == hipSuccess && c->precision == AFQMC_PREC_FP32) {
     const size_t n = Lpad.size();
     if ((e = hipMalloc(&c->d_Lpad32, n * sizeof(float))) == hipSuccess &&
-        (e = launch_to_float(c, n, c->d_Lpad, c->d_Lpad32)) == hipSuccess)
+        (e = c->ctrial ? launch_to_float(c, n, c->d_Lpad, c->d_Lpad32)
+                       : launch_to_f32_op(c, n, c->d_Lpad, c->d_Lpad32)) == hipSuccess)
       e = hipStreamSynchronize(c->stream);
   }
   if (e == hipSuccess &&
@@ -422,9 +423,9 @@ static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, con
             launch_contract(c, nw, phiT, static_cast<const double*>(theta),
                             static_cast<const double*>(logov), vb, ep),
             "contract");
-  else if (c->precision == AFQMC_PREC_BF16 || c->precision == AFQMC_PREC_BF16X3)
+  else if (c->precision != AFQMC_PREC_FP64 && !c->ctrial)
     HIPCALL(c,
-            launch_contract_bf(c, nw, phiT, static_cast<const double*>(theta),
+            launch_contract_sh(c, nw, phiT, static_cast<const double*>(theta),
                                static_cast<const double*>(logov), vb, ep),
             "contract");
   else

@@ -25,7 +25,7 @@ struct afqmc_ctx_s {
   double* d_Eh = nullptr;    // [M][M] = exp(-tau h1 / 2)
   double* d_phi0 = nullptr;  // [M][N]
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
-  float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad (mixed-precision contraction)
+  float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad: A-operand order, row-major with ctrial
   unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad, A-operand order (BF16 contractions)
   unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf, same order (split BF16)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
@@ -167,10 +167,12 @@ hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, dou
                                double* vbuf);
 hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift);
 hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
-hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
+// FP32 (real trial), split-BF16 and BF16 contractions, two paths per workgroup
+hipError_t launch_contract_sh(const afqmc_ctx_s* c, int nw, const double* phiT,
                               const double* theta, const double* logov, double* vb, double* ep);
 hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
                           unsigned short* lo);
+hipError_t launch_to_f32_op(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
 hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,
                        double* C, double* tot, int* parent, uint64_t seed, uint64_t step);
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,

@@ -1,5 +1,6 @@
 // Cholesky-vector contraction for larger systems (M <= 128, N <= 32), in FP64
-// or with FP32 matrix-core products (the mixed-precision form).  Same
+// or, for complex (multi-slice) trials, with FP32 matrix-core products (real
+// trials with FP32 products run k_contract_sh).  Same
 // quantities as k_contract (Sec. III.A, Eq. local-obs; Eq. shift1):
 //   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
 //   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
@@ -480,10 +481,10 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
 #undef AFQMC_GC
     return hipErrorInvalidValue;
   }
-  // 16 < N <= 24, FP64 products: vectors in pairs (2N rows in three tiles; measured at
-  // M = 96, N = 24: 86.9 -> 82.3 ms).  The FP32 form was slower in pairs (54.5 -> 56.4 ms)
-  // and the FP64 form spills at KT = 8, so those keep one vector at a time.
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8) {  // real trials with FP32 products run k_contract_sh
+    // 16 < N <= 24: vectors in pairs (2N rows in three tiles; measured at M = 96,
+    // N = 24: 86.9 -> 82.3 ms); the kernel spills at KT = 8, which keeps one vector
+    // at a time
     if (NTC == 2 && c->N <= 24 && KT <= 7) {
 #define AFQMC_GP(KK)                                                                       \
   if (KT == KK) return launch_g<T, KK, 2, false, true>(c, nw, L, phiT, theta, logov, vb, ep);
@@ -491,14 +492,14 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
 #undef AFQMC_GP
       return hipErrorInvalidValue;
     }
-  }
 #define AFQMC_G(KK, NC)                                                            \
   if (KT == KK && NTC == NC) return launch_g<T, KK, NC, false>(c, nw, L, phiT, theta, logov, vb, ep);
-  AFQMC_G(1, 1) AFQMC_G(2, 1) AFQMC_G(3, 1) AFQMC_G(4, 1)
-  AFQMC_G(5, 1) AFQMC_G(6, 1) AFQMC_G(7, 1) AFQMC_G(8, 1)
-  AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)
-  AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
+    AFQMC_G(1, 1) AFQMC_G(2, 1) AFQMC_G(3, 1) AFQMC_G(4, 1)
+    AFQMC_G(5, 1) AFQMC_G(6, 1) AFQMC_G(7, 1) AFQMC_G(8, 1)
+    AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)
+    AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
 #undef AFQMC_G
+  }
   return hipErrorInvalidValue;
 }
 
@@ -507,7 +508,7 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
 hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                              const double* logov, double* vb, double* ep) {
   if (nw <= 0) return hipSuccess;
-  if (c->precision == AFQMC_PREC_FP32)
+  if (c->precision == AFQMC_PREC_FP32)  // complex trials (real ones run k_contract_sh)
     return dispatch<float>(c, nw, c->d_Lpad32, phiT, theta, logov, vb, ep);
   return dispatch<double>(c, nw, c->d_Lpad, phiT, theta, logov, vb, ep);
 }

@@ -1,27 +1,30 @@
-// Cholesky-vector contraction with BF16 matrix-core products and FP32
-// accumulation (the mixed-precision forms AFQMC_PREC_BF16 and
-// AFQMC_PREC_BF16X3).  Same quantities as k_contract (Sec. III.A, Eq.
-// local-obs; Eq. shift1):
+// Cholesky-vector contraction with reduced-precision matrix-core products and
+// FP32 accumulation: FP32, split BF16 and BF16 (AFQMC_PREC_FP32 with a real
+// trial, AFQMC_PREC_BF16X3, AFQMC_PREC_BF16).  Same quantities as k_contract
+// (Sec. III.A, Eq. local-obs; Eq. shift1):
 //   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
 //   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
 //
-// Products: v_mfma_f32_16x16x16bf16_1k, lane (g, c) supplying A[c][4g + j] and
-// B[4g + j][c] (j = 0..3, four consecutive k values) and holding D[4g + r][c].
-// X3 (split BF16): every operand x is carried as x_hi = bf16(x) and
+// Products: lane (g, c) supplies A[c][4g + j] and B[4g + j][c] (j = 0..3, four
+// consecutive k values) and holds D[4g + r][c] -- one v_mfma_f32_16x16x16bf16_1k
+// for BF16, four v_mfma_f32_16x16x4f32 (the j-th on k = 4g + j) for FP32.
+// Split BF16: every operand x is carried as x_hi = bf16(x) and
 // x_lo = bf16(x - x_hi), and a product a b as a_hi b_hi + a_hi b_lo + a_lo b_hi
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
 // brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
 //
-// k_contract_bfs serves both forms: BCP paths per workgroup share each L slab
-// through LDS.  Per path, 2 * NTC wavefronts (NTC = ceil(N/16)); wavefront
-// w = (spin s = w % 2, column tile jt = w / 2) keeps Theta^s[:, jt] as BF16 B
-// operands in registers for the whole loop over g, and Phi_T (all column
-// tiles) as the stage-1 B operands.  Stage 1 (Y_g^T = L_g Phi_T) is split over
-// the path's wavefronts by row tile, its A operands read from the shared slab.
-// Y_g^T is rounded to BF16 once, as stage 1 leaves it, and stored in LDS in the
-// accumulator layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a
-// column in one lane); f is transposed through LDS for tr(f f); traces, vb_g^2
-// and the sums over g are FP64.
+// k_contract_sh: BCP paths per workgroup share each L slab through LDS.  Per
+// path, 2 * NTC wavefronts (NTC = ceil(N/16)); wavefront w = (spin s = w % 2,
+// column tile jt = w / 2) keeps Theta^s[:, jt] as B operands in registers for
+// the whole loop over g, and Phi_T (all column tiles) as the stage-1 B
+// operands.  Stage 1 (Y_g^T = L_g Phi_T) is split over the path's wavefronts by
+// row tile, its A operands read from the shared slab.  Y_g^T is rounded to the
+// operand form once, as stage 1 leaves it, and stored in LDS in the accumulator
+// layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a column in
+// one lane); f is transposed through LDS for tr(f f); traces, vb_g^2 and the
+// sums over g are FP64.
+
+#include <type_traits>
 
 #include "afqmc_internal.h"
 #include "dev_common.h"
@@ -73,6 +76,49 @@ __device__ __forceinline__ fx4 fx4_zero() {
   return z;
 }
 
+// Operand forms of the contraction.  An operand is what one lane supplies to a
+// 16 x 16 x 16 product: four consecutive k values (4g .. 4g+3) of one row or
+// column, as NP parts of type V.  FP32 runs the product as four
+// v_mfma_f32_16x16x4f32, the j-th taking k = 4g + j, so its lane layout is
+// the BF16 one with float4 in place of four BF16 values.
+enum { FM_BF16 = 0, FM_BF16X3 = 1, FM_FP32 = 2 };
+template <int FM>
+struct Form {
+  static constexpr bool X3 = FM == FM_BF16X3;
+  static constexpr bool F32 = FM == FM_FP32;
+  static constexpr int NP = X3 ? 2 : 1;             // parts: hi (and lo)
+  static constexpr int NB = FM == FM_BF16 ? 2 : 1;  // slab and Y^T buffers
+  typedef typename std::conditional<F32, fx4, sx4>::type V;
+  struct Op {
+    V p[NP];
+  };
+  __device__ __forceinline__ static Op make(float a, float b, float c, float d) {
+    Op o;
+    if constexpr (F32) {
+      o.p[0] = fx4{a, b, c, d};
+    } else {
+      const bsplit s = split4<X3>(a, b, c, d);
+      o.p[0] = s.hi;
+      if constexpr (X3) o.p[NP - 1] = s.lo;
+    }
+    return o;
+  }
+  __device__ __forceinline__ static fx4 mma(const Op& a, const Op& b, fx4 acc) {
+    if constexpr (F32) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.p[0][j], b.p[0][j], acc, 0, 0, 0);
+    } else {
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[0], b.p[0], acc, 0, 0, 0);
+      if constexpr (X3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[0], b.p[NP - 1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[NP - 1], b.p[0], acc, 0, 0, 0);
+      }
+    }
+    return acc;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // BCP paths per workgroup sharing each L slab: the slab of vector g + 1 goes
 // from global memory straight into LDS (global_load_lds) during vector g,
@@ -87,10 +133,10 @@ constexpr int BFL = 8;  // vectors per flush of the staged diagonals
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
-template <int KT, int NTC, bool X3>
+template <int KT, int NTC, int FM>
 __global__ void __launch_bounds__(128 * NTC * BCP)
-k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restrict__ Lop,
-               const unsigned short* __restrict__ Lop_lo, const double* __restrict__ phiT,
+k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
+               const void* __restrict__ Lop_lo, const double* __restrict__ phiT,
                const double* __restrict__ theta,
                const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   constexpr int MT = 16 * KT;
@@ -98,18 +144,23 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
   constexpr int NWT = NWV * BCP;               // wavefronts per workgroup
   constexpr int NT = 16 * NTC;
   constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
-  constexpr int SLAB = MT * MT;                // BF16 entries per slab
-  constexpr int NU = SLAB / 8;                 // 16-byte units per slab
+  typedef Form<FM> Fm;
+  typedef typename Fm::V V;
+  typedef typename Fm::Op Op;
+  constexpr int SLAB = MT * MT;                // entries per slab
+  constexpr int SV = SLAB / 4;                 // operands (V) per slab part
+  constexpr int NU = SV * (int)sizeof(V) / 16; // 16-byte units per slab part
   constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
-  constexpr int YT = (MT / 4) * NT;            // sx4 entries of one Y^T tile
+  constexpr int YT = (MT / 4) * NT;            // operands of one Y^T tile part
   // plain BF16: slabs and Y^T tiles double-buffered (the next slab loads during
-  // the whole vector); split BF16 (hi and lo of each): single buffers, the next
-  // slab loading from the barrier after stage 1 on, so that LDS still fits
-  constexpr int NB = X3 ? 1 : 2;               // buffers
-  constexpr int NP = X3 ? 2 : 1;               // parts (hi, lo)
+  // the whole vector); split BF16 (hi and lo of each) and FP32 (twice the
+  // bytes): single buffers, the next slab loading from the barrier after stage 1
+  // on, so that LDS still fits
+  constexpr int NB = Fm::NB;                   // buffers
+  constexpr int NP = Fm::NP;                   // parts (hi, lo)
   extern __shared__ double smem[];
-  sx4* sL = reinterpret_cast<sx4*>(smem);                                  // [NB][NP][SLAB/4]
-  sx4* sY = sL + NB * NP * (SLAB / 4);                                     // [BCP][NB][NP][YT]
+  V* sL = reinterpret_cast<V*>(smem);                                      // [NB][NP][SV]
+  V* sY = sL + NB * NP * SV;                                               // [BCP][NB][NP][YT]
   float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][2][NT][NT+1][2]
   double* sD = reinterpret_cast<double*>(sF + BCP * 2 * NT * (NT + 1) * 2);  // [BCP][BFL][NWV*16][2]
   double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
@@ -127,18 +178,19 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
   auto copy_slab = [&](int slab, int buf) {
 #pragma unroll
     for (int part = 0; part < NP; ++part) {
-      const unsigned short* src = (part ? Lop_lo : Lop) + (size_t)slab * SLAB;
-      char* dst = reinterpret_cast<char*>(sL + (buf * NP + part) * (SLAB / 4));
+      const char* src = reinterpret_cast<const char*>(part ? Lop_lo : Lop) +
+                        (size_t)slab * SV * sizeof(V);
+      char* dst = reinterpret_cast<char*>(sL + (buf * NP + part) * SV);
       for (int k = wave; k < NCH; k += NWT)
         if (k * 64 + lane < NU)  // lanes past a partial last chunk copy nothing
-          __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 512 + lane * 8),
+          __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + k * 1024 + lane * 16),
                                            (lds_ptr_t)(dst + k * 1024), 16, 0, 0);
     }
   };
   copy_slab(0, 0);
 
   // B operands (bit-masked unconditional loads)
-  bsplit bT[NTC][KT], th[2][KT];
+  Op bT[NTC][KT], th[2][KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     float v[NTC][4], w[2][4];
@@ -160,14 +212,14 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
       w[1][j] = (float)keep_if(x2.y, okm && n < N);
     }
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = split4<X3>(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
+    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = Fm::make(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri) th[ri][t] = split4<X3>(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
+    for (int ri = 0; ri < 2; ++ri) th[ri][t] = Fm::make(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
-  sx4* Yp = sY + pw * NB * NP * YT;
+  V* Yp = sY + pw * NB * NP * YT;
   float* Fp = sF + (size_t)pw * 2 * NT * (NT + 1) * 2;
   double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
@@ -179,23 +231,23 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
     for (int q = 0; q < S1MAX; ++q)
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = fx4_zero();
-    const sx4* Ls = sL + b * NP * (SLAB / 4);
+    const V* Ls = sL + b * NP * SV;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
       if (active && tp < KT)
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
-          bsplit a;
-          a.hi = Ls[(tp * KT + t) * 64 + lane];
-          a.lo = X3 ? Ls[SLAB / 4 + (tp * KT + t) * 64 + lane] : sx4{0, 0, 0, 0};
+          Op a;
 #pragma unroll
-          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = mma<X3>(a, bT[ct][t], y1[q][ct]);
+          for (int part = 0; part < NP; ++part) a.p[part] = Ls[part * SV + (tp * KT + t) * 64 + lane];
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = Fm::mma(a, bT[ct][t], y1[q][ct]);
         }
     }
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
     if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
-    sx4* Yb = Yp + b * NP * YT;
+    V* Yb = Yp + b * NP * YT;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -203,9 +255,9 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
 #pragma unroll
         for (int ct = 0; ct < NTC; ++ct) {
           const fx4 v = y1[q][ct];
-          const bsplit yv = split4<X3>(v[0], v[1], v[2], v[3]);
-          Yb[(4 * tp + g) * NT + 16 * ct + c] = yv.hi;
-          if (X3) Yb[YT + (4 * tp + g) * NT + 16 * ct + c] = yv.lo;
+          const Op yv = Fm::make(v[0], v[1], v[2], v[3]);
+#pragma unroll
+          for (int part = 0; part < NP; ++part) Yb[part * YT + (4 * tp + g) * NT + 16 * ct + c] = yv.p[part];
         }
     }
     __syncthreads();
@@ -220,11 +272,11 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
       for (int t = 0; t < KT; ++t)
 #pragma unroll
         for (int it = 0; it < NTC; ++it) {
-          bsplit a;
-          a.hi = Yb[(4 * t + g) * NT + 16 * it + c];
-          a.lo = X3 ? Yb[YT + (4 * t + g) * NT + 16 * it + c] : sx4{0, 0, 0, 0};
-          f[it][0] = mma<X3>(a, th[0][t], f[it][0]);
-          f[it][1] = mma<X3>(a, th[1][t], f[it][1]);
+          Op a;
+#pragma unroll
+          for (int part = 0; part < NP; ++part) a.p[part] = Yb[part * YT + (4 * t + g) * NT + 16 * it + c];
+          f[it][0] = Fm::mma(a, th[0][t], f[it][0]);
+          f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
         }
     }
     // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
@@ -325,37 +377,41 @@ k_contract_bfs(int n_samples, int M, int N, int G, const unsigned short* __restr
     for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-size_t lds_bytes_s(int KT, int NTC, bool x3) {
+// the same for every form: buffers x parts x bytes per entry = 2 x 1 x 2 (BF16),
+// 1 x 2 x 2 (split BF16) or 1 x 1 x 4 (FP32)
+size_t lds_bytes_s(int KT, int NTC) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = 2 * NTC;
-  const int nbp = 2;                                  // buffers x parts: 2 x 1 or 1 x 2
-  size_t b = (size_t)nbp * MT * MT * 2;               // slabs
-  b += (size_t)BCP * nbp * (MT / 4) * NT * 8;         // Y^T tiles
+  size_t b = (size_t)4 * MT * MT;                     // slabs
+  b += (size_t)BCP * (MT / 4) * NT * 16;              // Y^T tiles
   b += (size_t)BCP * 2 * NT * (NT + 1) * 2 * 4;       // f (FP32)
   b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
   b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
   return b;
 }
 
-template <int KT, int NTC, bool X3>
-hipError_t launch_bfs(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
-                      const double* logov, double* vb, double* ep) {
+template <int KT, int NTC, int FM>
+hipError_t launch_sh(const afqmc_ctx_s* c, int nw, const void* L, const void* L_lo,
+                      const double* phiT, const double* theta, const double* logov, double* vb,
+                      double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes_s(KT, NTC, X3);
-  auto kern = k_contract_bfs<KT, NTC, X3>;
+  const size_t lds = lds_bytes_s(KT, NTC);
+  auto kern = k_contract_sh<KT, NTC, FM>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((n + BCP - 1) / BCP), dim3(128 * NTC * BCP), lds, c->stream, n,
-                     c->M, c->N, c->G, c->d_Lbf, c->d_Lbf_lo, phiT, theta, logov, vb, ep);
+                     c->M, c->N, c->G, L, L_lo, phiT, theta, logov, vb, ep);
   return hipGetLastError();
 }
 
-template <bool X3>
-hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
-                      const double* logov, double* vb, double* ep) {
+template <int FM>
+hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const void* L, const void* L_lo,
+                      const double* phiT, const double* theta, const double* logov, double* vb,
+                      double* ep) {
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_BS(KK, NC) \
-  if (KT == KK && NTC == NC) return launch_bfs<KK, NC, X3>(c, nw, phiT, theta, logov, vb, ep);
+#define AFQMC_BS(KK, NC)    \
+  if (KT == KK && NTC == NC) \
+    return launch_sh<KK, NC, FM>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
   AFQMC_BS(1, 1) AFQMC_BS(2, 1) AFQMC_BS(3, 1) AFQMC_BS(4, 1)
   AFQMC_BS(5, 1) AFQMC_BS(6, 1) AFQMC_BS(7, 1) AFQMC_BS(8, 1)
   AFQMC_BS(2, 2) AFQMC_BS(3, 2) AFQMC_BS(4, 2)
@@ -380,17 +436,37 @@ __global__ void k_to_bf16_op(size_t n, int MT, const double* __restrict__ src,
   if (lo != nullptr) lo[o] = f2bf(x - bf2f(h));
 }
 
+// the same order in FP32
+__global__ void k_to_f32_op(size_t n, int MT, const double* __restrict__ src,
+                            float* __restrict__ dst) {
+  const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int KT = MT / 16;
+  const size_t slab = o / ((size_t)MT * MT);
+  const int r = (int)(o % ((size_t)MT * MT));
+  const int j = r & 3, cc = (r >> 2) & 15, gg = (r >> 6) & 3, t = (r >> 8) % KT, tp = (r >> 8) / KT;
+  dst[o] = (float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + 16 * t + 4 * gg + j];
+}
+
 }  // namespace
 
-hipError_t launch_contract_bf(const afqmc_ctx_s* c, int nw, const double* phiT,
+hipError_t launch_contract_sh(const afqmc_ctx_s* c, int nw, const double* phiT,
                               const double* theta, const double* logov, double* vb, double* ep) {
   if (nw <= 0) return hipSuccess;
-  if (c->d_Lbf == nullptr) return hipErrorInvalidValue;
-  if (c->precision == AFQMC_PREC_BF16X3) {
-    if (c->d_Lbf_lo == nullptr) return hipErrorInvalidValue;
-    return dispatch_s<true>(c, nw, phiT, theta, logov, vb, ep);
+  if (c->ctrial) return hipErrorInvalidValue;  // real trial determinants only
+  switch (c->precision) {
+    case AFQMC_PREC_FP32:
+      if (c->d_Lpad32 == nullptr) return hipErrorInvalidValue;
+      return dispatch_s<FM_FP32>(c, nw, c->d_Lpad32, nullptr, phiT, theta, logov, vb, ep);
+    case AFQMC_PREC_BF16X3:
+      if (c->d_Lbf == nullptr || c->d_Lbf_lo == nullptr) return hipErrorInvalidValue;
+      return dispatch_s<FM_BF16X3>(c, nw, c->d_Lbf, c->d_Lbf_lo, phiT, theta, logov, vb, ep);
+    case AFQMC_PREC_BF16:
+      if (c->d_Lbf == nullptr) return hipErrorInvalidValue;
+      return dispatch_s<FM_BF16>(c, nw, c->d_Lbf, nullptr, phiT, theta, logov, vb, ep);
+    default:
+      return hipErrorInvalidValue;
   }
-  return dispatch_s<false>(c, nw, phiT, theta, logov, vb, ep);
 }
 
 hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, unsigned short* hi,
@@ -399,5 +475,12 @@ hipError_t launch_to_bf16(const afqmc_ctx_s* c, size_t n, const double* src, uns
   // the shared-slab kernels' A-operand order (lo only for the split form)
   hipLaunchKernelGGL(k_to_bf16_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
                      c->MT, src, hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32_op(const afqmc_ctx_s* c, size_t n, const double* src, float* dst) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                     c->MT, src, dst);
   return hipGetLastError();
 }
