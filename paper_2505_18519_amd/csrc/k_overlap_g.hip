@@ -2,11 +2,18 @@
 // M <= 128); same quantities and conventions as k_overlap (Sec. III.A, Eqs.
 // ratio-update-phi and sign-path).  One workgroup of two wavefronts per path,
 // wavefront s handling spin s:
-//  1. A^s = Phi_T^T phi^s on the FP64 matrix cores (NTC x NTC tiles of 16);
-//  2. LU with partial pivoting, one lane per row (N <= 32 lanes), pivot rows
-//     found by a max reduction over the 64 lanes and broadcast by shuffles;
-//  3. optionally Theta^s = phi^s (A^s)^{-1}, lanes over orbital rows m, and
-//     the Green's function diagonal Re (G_up + G_dn)_mm.
+//  1. A^s = Phi_T^T phi^s on the FP64 matrix cores (NTC x NTC tiles of 16),
+//     operand loads clamped and bit-masked so that four k steps are in flight;
+//  2. LU with partial pivoting, one lane per row (N <= 32 lanes): the pivot
+//     (largest |a|^2, lowest row on ties) by DPP moves within the two 16-lane
+//     rows and one comparison of their results, the pivot row broadcast by
+//     readlane (the pivot is uniform over the wavefront);
+//  3. optionally Theta^s = phi^s (A^s)^{-1}: lanes j < N solve the unit rows
+//     e_j X^s = e_j (A^s)^{-1} with the factors, X^s replaces the factors in
+//     LDS, and Theta^s = phi^s X^s runs on the matrix cores (four real products
+//     per tile), stored as whole 16-byte complex entries along each row; with
+//     the Green's function diagonal Re (G_up + G_dn)_mm requested, lanes over
+//     orbital rows m solve x (A^s)^{-1} for their rows of phi instead.
 // The two spins' log-determinants and diagonals are added through LDS.
 // CT: complex trial determinants (multi-slice trials), A^s = Phi_T^T phi^s
 // with both factors complex (no conjugation: the bilinear overlap of Eq.
@@ -42,23 +49,28 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   for (int it = 0; it < NTC; ++it)
 #pragma unroll
     for (int jt = 0; jt < NTC; ++jt) acc[it][jt][0] = acc[it][jt][1] = dx4_zero();
+#pragma unroll 4
   for (int q = 0; q < (M + 3) / 4; ++q) {
     const int m = 4 * q + g;
     const bool okm = m < M;
+    const int mc = min(m, M - 1);
     double a[NTC], ai[NTC], br[NTC], bi[NTC];
 #pragma unroll
     for (int t = 0; t < NTC; ++t) {
       const int n = 16 * t + c;
       const bool ok = okm && n < N;
+      const size_t e = (size_t)mc * N + min(n, N - 1);
       if (CT) {
-        a[t] = ok ? pT[((size_t)m * N + n) * 2] : 0.0;
-        ai[t] = ok ? pT[((size_t)m * N + n) * 2 + 1] : 0.0;
+        const double2 v = *reinterpret_cast<const double2*>(pT + e * 2);
+        a[t] = keep_if(v.x, ok);
+        ai[t] = keep_if(v.y, ok);
       } else {
-        a[t] = ok ? pT[m * N + n] : 0.0;
+        a[t] = keep_if(pT[e], ok);
         ai[t] = 0.0;
       }
-      br[t] = ok ? pw[((size_t)m * N + n) * 2] : 0.0;
-      bi[t] = ok ? pw[((size_t)m * N + n) * 2 + 1] : 0.0;
+      const double2 x = *reinterpret_cast<const double2*>(pw + e * 2);
+      br[t] = keep_if(x.x, ok);
+      bi[t] = keep_if(x.y, ok);
     }
 #pragma unroll
     for (int it = 0; it < NTC; ++it)
@@ -100,22 +112,31 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   for (int k = 0; k < NT; ++k) {
     perm[k] = 0;
     if (k < N) {
+      // NaN entries count as zero so that the order is total and every lane
+      // agrees on the pivot
       double v = used ? -1.0 : cabs2(a[k]);
       if (!used && !(v >= 0.0)) v = 0.0;
       int idx = used ? 1000 : i;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        const double v2 = __shfl_xor(v, o, 64);
-        const int i2 = __shfl_xor(idx, o, 64);
+      auto take = [&](double v2, int i2) {
         if (v2 > v || (v2 == v && i2 < idx)) {
           v = v2;
           idx = i2;
         }
-      }
-      const int prow = idx;
+      };
+      // within each 16-lane row: lane xor 1, xor 2, mirrored quad, mirrored half
+      take(dpp_f64<0xB1>(v), dpp_i32<0xB1>(idx));
+      take(dpp_f64<0x4E>(v), dpp_i32<0x4E>(idx));
+      take(dpp_f64<0x141>(v), dpp_i32<0x141>(idx));
+      take(dpp_f64<0x140>(v), dpp_i32<0x140>(idx));
+      // rows 0 and 1 hold the N <= 32 matrix rows; lanes 32-63 are all used
+      const double v16 = readlane_f64(v, 16);
+      const int i16 = __builtin_amdgcn_readlane(idx, 16);
+      v = readlane_f64(v, 0);
+      idx = __builtin_amdgcn_readlane(idx, 0);
+      take(v16, i16);
+      const int prow = idx;  // uniform over the wavefront
       perm[k] = prow;
-      const int src = prow & 63;
-      const cplx piv = cmk(__shfl(a[k].re, src, 64), __shfl(a[k].im, src, 64));
+      const cplx piv = cmk(readlane_f64(a[k].re, prow), readlane_f64(a[k].im, prow));
       if (!(v > 0.0)) singular = true;
       if (i == prow && !used) {
         used = true;
@@ -135,7 +156,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       }
 #pragma unroll
       for (int j = k + 1; j < NT; ++j) {
-        const cplx pj = cmk(__shfl(a[j].re, src, 64), __shfl(a[j].im, src, 64));
+        const cplx pj = cmk(readlane_f64(a[j].re, prow), readlane_f64(a[j].im, prow));
         if (!used && !singular) a[j] = cfms(a[j], l, pj);
       }
     }
@@ -177,7 +198,108 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       for (int q = lane; q < M; q += 64) gd[q] = 0.0;
     return;
   }
-  // 3. Theta rows (every lane reaches the barriers; lanes past M idle)
+  if (gdiag == nullptr) {
+    // 3. X = (A^sp)^{-1}: lane j < N solves e_j X = e_j A^{-1} with the factors
+    //    (z U = e_j, v L = z, X[j][perm[k]] = v[k]); rows j >= N stay zero
+    const int jr = lane;
+    const bool solver = jr < N;
+    cplx x[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) x[j] = cmk(j == jr ? 1.0 : 0.0, 0.0);
+    if (solver) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        if (j < N) {
+          cplx acc2 = x[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k)
+            acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
+          x[j] = cdiv(acc2, cmk(s_lu[sp][j][j][0], s_lu[sp][j][j][1]));
+        }
+      }
+#pragma unroll
+      for (int j = NT - 1; j >= 0; --j) {
+        if (j < N) {
+          cplx acc2 = x[j];
+#pragma unroll
+          for (int k = j + 1; k < NT; ++k)
+            if (k < N) acc2 = cfms(acc2, x[k], cmk(s_lu[sp][k][j][0], s_lu[sp][k][j][1]));
+          x[j] = acc2;
+        }
+      }
+    }
+    int pcol[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) pcol[k] = min(max(s_perm[sp][k], 0), NT - 1);
+    // every lane of the wavefront has issued its factor reads: X replaces them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < NT) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {  // unused columns first, then the solved row
+        s_lu[sp][jr][k][0] = 0.0;
+        s_lu[sp][jr][k][1] = 0.0;
+      }
+      if (solver) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+          if (k < N) {
+            s_lu[sp][jr][pcol[k]][0] = x[k].re;
+            s_lu[sp][jr][pcol[k]][1] = x[k].im;
+          }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // 4. Theta^sp = phi^sp X on the matrix cores: A[c][g] = phi[16t + c][4q + g],
+    //    B[g][c] = X[4q + g][16ct + c]; the lane holds Theta[16t + g + 4r][16ct + c]
+    double xr[NT / 4][NTC], xi[NT / 4][NTC];
+#pragma unroll
+    for (int q = 0; q < NT / 4; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        xr[q][ct] = s_lu[sp][4 * q + g][16 * ct + c][0];
+        xi[q][ct] = s_lu[sp][4 * q + g][16 * ct + c][1];
+      }
+    for (int t = 0; t < (M + 15) / 16; ++t) {
+      const int m = 16 * t + c;
+      const int mc = min(m, M - 1);
+      double2 v[NT / 4];
+#pragma unroll
+      for (int q = 0; q < NT / 4; ++q) {
+        const int n = 4 * q + g;
+        const double2 e =
+            *reinterpret_cast<const double2*>(pw + ((size_t)mc * N + min(n, N - 1)) * 2);
+        const bool ok = m < M && n < N;
+        v[q] = make_double2(keep_if(e.x, ok), keep_if(e.y, ok));
+      }
+      dx4 tr[NTC], ti[NTC];
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) tr[ct] = ti[ct] = dx4_zero();
+#pragma unroll
+      for (int q = 0; q < NT / 4; ++q)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct) {
+          tr[ct] = mfma_f64(v[q].x, xr[q][ct], tr[ct]);
+          tr[ct] = mfma_f64(-v[q].y, xi[q][ct], tr[ct]);
+          ti[ct] = mfma_f64(v[q].x, xi[q][ct], ti[ct]);
+          ti[ct] = mfma_f64(v[q].y, xr[q][ct], ti[ct]);
+        }
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mo = 16 * t + g + 4 * r, col = 16 * ct + c;
+          if (mo < M && col < N)
+            *reinterpret_cast<double2*>(th + ((size_t)mo * N + col) * 2) =
+                make_double2(tr[ct][r], ti[ct][r]);
+        }
+    }
+    return;
+  }
+  // 3. Theta rows with the diagonal (every lane reaches the barriers; lanes past M idle)
   for (int m0 = 0; m0 < M; m0 += 64) {
     const int m = m0 + lane;
     double gsum = 0.0;
