@@ -84,9 +84,12 @@ def cpu_baseline(sys_, run, seed, n_walkers=48):
         st, _ = O.step(sys_, st, seed, 0, run.dtau, n_taylor=run.n_taylor, n_sweep=run.n_sweep,
                        n_qr=run.n_qr, Eh=Eh, h1p=h1p, xbar_cap=1.0, n_pc=1, w_cap=4.0)
         dt = time.perf_counter() - t0
+    flops = n_walkers * run.P * contraction_flops(sys_.M, sys_.N, sys_.n_chol)
     return {"value": n_walkers / dt, "unit": "walker-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_walkers} walkers x {run.P} paths, 1 whole step of the same workload "
-                      f"(numpy FP64/complex128, 1 thread), {dt:.1f} s"}
+                      f"(numpy FP64/complex128, 1 thread), {dt:.1f} s",
+            "gflops": flops / dt / 1e9,
+            "gflops_counts": "the contraction's algorithmic flops over the whole step's time"}
 
 
 def reblock(x):
