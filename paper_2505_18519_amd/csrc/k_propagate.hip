@@ -17,29 +17,41 @@ namespace {
 // ---------------------------------------------------------------------------
 // V build: with c = xi - xbar, R = sum_g Re(c_g) L_g and Q = sum_g Im(c_g) L_g,
 // V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the FP64
-// matrix cores: each wavefront takes 16 walkers (both Re c and Im c as A
-// operands) and 64 matrix entries; L is read once per 16 walkers.  Row w of
+// matrix cores: each wavefront takes VB_WT tiles of 16 walkers (both Re c and
+// Im c as A operands) and VB_ET tiles of 16 matrix entries, so every L entry it
+// loads feeds the products of 16 VB_WT walkers; L is read once per 16 VB_WT
+// walkers, and the four wavefronts of a workgroup share their L entries.  Row w of
 // xi starts at w * xs and of xbar at w * xbs; xbar may be null (c = xi): the
 // trial slices use this with the generators A_k and their block of y, the
 // back-propagation with a walker's recorded fields.  XB = false (no xbar):
 // Q = 0 and only the R products run.
+constexpr int VB_WT = 2;  // walker tiles per wavefront
+constexpr int VB_ET = 2;  // entry tiles per wavefront
 template <bool XB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
-  const int w0 = (blockIdx.y * 4 + wave) * 16;
-  const int e0 = blockIdx.x * 64;
+  const int w0 = (blockIdx.y * 4 + wave) * 16 * VB_WT;
+  const int e0 = blockIdx.x * 16 * VB_ET;
   if (w0 >= nw) return;
-  dx4 ar[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
-  dx4 ai[4] = {dx4_zero(), dx4_zero(), dx4_zero(), dx4_zero()};
-  const int wa = min(w0 + c, nw - 1);
-  const bool wok = (w0 + c) < nw;
-  int ec[4];
-  bool eok[4];
+  dx4 ar[VB_WT][VB_ET], ai[VB_WT][VB_ET];
 #pragma unroll
-  for (int et = 0; et < 4; ++et) {
+  for (int wt = 0; wt < VB_WT; ++wt)
+#pragma unroll
+    for (int et = 0; et < VB_ET; ++et) ar[wt][et] = ai[wt][et] = dx4_zero();
+  int wa[VB_WT];
+  bool wok[VB_WT];
+#pragma unroll
+  for (int wt = 0; wt < VB_WT; ++wt) {
+    wa[wt] = min(w0 + 16 * wt + c, nw - 1);
+    wok[wt] = (w0 + 16 * wt + c) < nw;
+  }
+  int ec[VB_ET];
+  bool eok[VB_ET];
+#pragma unroll
+  for (int et = 0; et < VB_ET; ++et) {
     const int e = e0 + 16 * et + c;
     eok[et] = e < MM;
     ec[et] = min(e, MM - 1);
@@ -47,20 +59,23 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
   // batches of KB k-steps, double-buffered: the loads of batch i+1 (clamped
   // in range, masked after the load) are issued before the MFMAs of batch i
   constexpr int KB = 4;
-  double cr[2][KB], ci[2][KB], b[2][KB][4];
+  double cr[2][KB][VB_WT], ci[2][KB][VB_WT], b[2][KB][VB_ET];
   auto load = [&](int k0, int buf) {
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const int k = k0 + 4 * q + g;
       const int kc = min(k, G - 1);
-      const bool ok = wok && k < G;
-      const double x = xi[(size_t)wa * xs + kc];
-      const double br = XB ? xbar[((size_t)wa * xbs + kc) * 2] : 0.0;
-      const double bi = XB ? xbar[((size_t)wa * xbs + kc) * 2 + 1] : 0.0;
-      cr[buf][q] = keep_if(x - br, ok);
-      ci[buf][q] = keep_if(-bi, ok);
 #pragma unroll
-      for (int et = 0; et < 4; ++et) {
+      for (int wt = 0; wt < VB_WT; ++wt) {
+        const bool ok = wok[wt] && k < G;
+        const double x = xi[(size_t)wa[wt] * xs + kc];
+        const double br = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2] : 0.0;
+        const double bi = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2 + 1] : 0.0;
+        cr[buf][q][wt] = keep_if(x - br, ok);
+        ci[buf][q][wt] = keep_if(-bi, ok);
+      }
+#pragma unroll
+      for (int et = 0; et < VB_ET; ++et) {
         const double v = L[(size_t)kc * MM + ec[et]];
         b[buf][q][et] = keep_if(v, k < G && eok[et]);
       }
@@ -70,10 +85,12 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
 #pragma unroll
     for (int q = 0; q < KB; ++q)
 #pragma unroll
-      for (int et = 0; et < 4; ++et) {
-        ar[et] = mfma_f64(cr[buf][q], b[buf][q][et], ar[et]);
-        if (XB) ai[et] = mfma_f64(ci[buf][q], b[buf][q][et], ai[et]);
-      }
+      for (int wt = 0; wt < VB_WT; ++wt)
+#pragma unroll
+        for (int et = 0; et < VB_ET; ++et) {
+          ar[wt][et] = mfma_f64(cr[buf][q][wt], b[buf][q][et], ar[wt][et]);
+          if (XB) ai[wt][et] = mfma_f64(ci[buf][q][wt], b[buf][q][et], ai[wt][et]);
+        }
   };
   load(0, 0);
   for (int k0 = 0; k0 < G; k0 += 8 * KB) {
@@ -84,16 +101,18 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
     compute(1);
   }
 #pragma unroll
-  for (int et = 0; et < 4; ++et)
+  for (int wt = 0; wt < VB_WT; ++wt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int w = w0 + g + 4 * r, e = e0 + 16 * et + c;
-      if (w < nw && e < MM) {
-        double* o = vmat + ((size_t)w * MM + e) * 2;
-        o[0] = -sqrt_tau * ai[et][r];
-        o[1] = sqrt_tau * ar[et][r];
+    for (int et = 0; et < VB_ET; ++et)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int w = w0 + 16 * wt + g + 4 * r, e = e0 + 16 * et + c;
+        if (w < nw && e < MM) {
+          double* o = vmat + ((size_t)w * MM + e) * 2;
+          o[0] = -sqrt_tau * ai[wt][et][r];
+          o[1] = sqrt_tau * ar[wt][et][r];
+        }
       }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -291,7 +310,8 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
                          double* vmat) {
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (nw + 63) / 64), block(256);
+  dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (nw + 64 * VB_WT - 1) / (64 * VB_WT)),
+      block(256);
   hipLaunchKernelGGL(k_vbuild<true>, grid, block, 0, c->stream, nw, c->G, MM, c->G, c->G,
                      sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
@@ -496,7 +516,7 @@ hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double 
                              const double* xbar, int xbs) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (n + 63) / 64);
+  dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (n + 64 * VB_WT - 1) / (64 * VB_WT));
   if (xbar != nullptr)
     hipLaunchKernelGGL(k_vbuild<true>, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s,
                        Lgen, y, xbar, vmat);
