@@ -7,9 +7,12 @@
 //   operands and runs the Taylor series sum_j U^j Phi_0 / j!.  With the k
 //   index of the product visited as 16 t + 4 r + g, the accumulator of one
 //   term is, register for register, the B operand of the next, so the series
-//   needs no LDS traffic.  Terms are added until max|term| <= 2^-60 max|sum|
+//   needs no LDS traffic.  Terms are added until max|term| <= 2^-56 max|sum|
 //   (checked every second term); when the row-sum norm of U exceeds 16 the
-//   series is applied s = ceil(norm / 16) times to U / s.
+//   series is applied s = ceil(norm / 16) times to U / s.  Each later term is
+//   at most ||U / s||_inf / (j + 1) <= 16 / 29 of the one before once the
+//   terms have passed their peak, so the dropped tail is below 1.3 * 2^-56
+//   max|sum|, a sixth of an ulp of the largest entry.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -189,7 +192,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
         }
       tmax = wave_max_full(tmax);
       smax = wave_max_full(smax);
-      if (tmax <= 0x1.0p-60 * smax) break;
+      if (tmax <= 0x1.0p-56 * smax) break;
     }
   }
 
@@ -341,7 +344,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
           tm = fmax(tm, sred[w * 2]);
           sx = fmax(sx, sred[w * 2 + 1]);
         }
-        if (tm <= 0x1.0p-60 * sx) break;
+        if (tm <= 0x1.0p-56 * sx) break;
       }
     }
   }
