@@ -64,3 +64,24 @@ def test_binding_rejects_host_tensors():
     from paper_2505_18519_amd import afqmc as A
     with pytest.raises(ValueError):
         A._ptr(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "x")
+
+
+def test_binding_constants_match_the_header():
+    """Every AFQMC_* enumerator of include/afqmc.h has the binding constant of
+    the same name (prefix dropped) and value."""
+    import re
+    from paper_2505_18519_amd import afqmc as A
+    text = open(HEADER).read()
+    found = dict((k, int(v)) for k, v in re.findall(r"\bAFQMC_([A-Z0-9_]+)\s*=\s*(\d+)", text))
+    checked = 0
+    for name, value in found.items():
+        if name in ("OK",) or name.startswith("E_"):
+            continue
+        assert hasattr(A, name), name
+        assert getattr(A, name) == value, (name, getattr(A, name), value)
+        checked += 1
+    assert checked >= 18
+    defines = dict((k, int(v, 0)) for k, v in
+                   re.findall(r"#define AFQMC_([A-Z0-9_]+) (0x[0-9a-fA-F]+|\d+)", text))
+    for name in ("MLP_HIDDEN", "INIT_STEP", "MEASURE_STEP"):
+        assert getattr(A, name) == defines[name], name
