@@ -56,6 +56,10 @@ CASES = {
     # with 15 paths (a last workgroup with idle wavefronts)
     "gauss-M32-N8-G1-P1": (lambda: ai.small_gaussian(M=32, N=8, n_chol=1, K=4, seed=10), 1, 4),
     "gauss-M64-N16-G17-P5": (lambda: ai.small_gaussian(M=64, N=16, n_chol=17, K=8, seed=11), 5, 3),
+    # one electron per spin: 1 x 1 overlaps in a single tile of rows (M = 3) and in
+    # the workgroup-per-path kernels just past M = 64
+    "gauss-M3-N1": (lambda: ai.small_gaussian(M=3, N=1, n_chol=5, K=2, seed=12), 2, 3),
+    "gauss-M70-N1": (lambda: ai.small_gaussian(M=70, N=1, n_chol=9, K=4, seed=13), 3, 2),
     # workgroup-per-path kernels (M > 64 or N > 16)
     "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
     "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
