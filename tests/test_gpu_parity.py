@@ -60,6 +60,9 @@ CASES = {
     # the workgroup-per-path kernels just past M = 64
     "gauss-M3-N1": (lambda: ai.small_gaussian(M=3, N=1, n_chol=5, K=2, seed=12), 2, 3),
     "gauss-M70-N1": (lambda: ai.small_gaussian(M=70, N=1, n_chol=9, K=4, seed=13), 3, 2),
+    # every orbital occupied (N = M) in both kernel families
+    "gauss-M16-N16": (lambda: ai.small_gaussian(M=16, N=16, n_chol=6, K=4, seed=14), 2, 3),
+    "gauss-M32-N32": (lambda: ai.small_gaussian(M=32, N=32, n_chol=6, K=4, seed=15), 2, 2),
     # workgroup-per-path kernels (M > 64 or N > 16)
     "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
     "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
