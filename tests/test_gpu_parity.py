@@ -448,8 +448,9 @@ MIXED = {"fp32": (1, MIXED_TOL), "bf16x3": (3, MIXED_TOL), "bf16": (2, BF16_TOL)
 
 
 @pytest.mark.parametrize("prec", list(MIXED))
-@pytest.mark.parametrize("case", ["tiny-ising-M8", "gauss-M20-N5-ragged", "gauss-M48-N11",
-                                  "cfg-M64-N16-G256", "gauss-M72-N20-ragged", "gauss-M96-N24",
+@pytest.mark.parametrize("case", ["tiny-ising-M8", "gauss-M3-N1", "gauss-M20-N5-ragged",
+                                  "gauss-M32-N32", "gauss-M48-N11", "cfg-M64-N16-G256",
+                                  "gauss-M70-N1", "gauss-M72-N20-ragged", "gauss-M96-N24",
                                   "gauss-M128-N32"])
 def test_mixed_precision_contraction(case, prec):
     """FP32, split-BF16 and BF16 matrix-core contractions (FP64 traces and
