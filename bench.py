@@ -111,7 +111,6 @@ def learned_study(args):
     walkers and seeds.  Energy errors by reblocking over the timed steps."""
     import torch
     import afqmc_inputs as ai
-    from oracle import mlp_oracle as ML
     from paper_2505_18519_amd import afqmc as A
     from paper_2505_18519_amd import driver as D
 
@@ -128,7 +127,7 @@ def learned_study(args):
                             **common)
             p = ai.mlp_params(np.random.default_rng(8), sys_.M, sys_.K, last_scale=0.0)
             p["b3"][sys_.K:] = 4 * np.arctanh(np.log(s_train * s_train) / 4)
-            A.afqmc_mlp_init(ctx, A.PREC_BF16, ML.flatten(p), lr=1e-3)
+            A.afqmc_mlp_init(ctx, A.PREC_BF16, A.mlp_pack(p), lr=1e-3)
             A.afqmc_mlp_set_training(ctx, True)
         else:
             ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_RW, rw_step=rw_step, **common)

@@ -28,6 +28,7 @@
  * The caller owns every state array and the workspace; the library owns the
  * device copy of the system made by afqmc_create.  Calls are asynchronous on
  * the context's stream; they validate arguments on the host and never abort.
+ * Non-finite results are data, flagged per walker (see "Numerical events").
  * Walker k's random numbers depend only on (seed, step, k), so any nw-prefix
  * of a batch reproduces the same walkers.
  */
@@ -49,7 +50,8 @@ typedef enum {
   AFQMC_E_SHAPE = 2,        /* sizes outside what the kernels support             */
   AFQMC_E_DEVICE = 3,       /* a HIP runtime call failed                           */
   AFQMC_E_NOMEM = 4,        /* device allocation in afqmc_create failed            */
-  AFQMC_E_NUMERIC = 5,      /* reserved: non-finite input detected                 */
+  AFQMC_E_NUMERIC = 5,      /* a kernel produced a non-finite E_L, force bias or weight
+                               (afqmc_numeric_flags; per-step calls with the check on) */
   AFQMC_E_UNSUPPORTED = 6,  /* valid request this build does not implement         */
   AFQMC_E_WORKSPACE = 7     /* no workspace set, or smaller than afqmc_workspace_size */
 } afqmc_status;
@@ -155,6 +157,44 @@ afqmc_status afqmc_set_stream(afqmc_ctx ctx, void* stream);
  * one context must not share a workspace.  No per-step call allocates.      */
 afqmc_status afqmc_workspace_size(afqmc_ctx ctx, int32_t nw, size_t* bytes);
 afqmc_status afqmc_set_workspace(afqmc_ctx ctx, void* dptr, size_t bytes);
+
+/* ---- Numerical events --------------------------------------------------------
+ * A walker whose local energy, force bias or weight comes out non-finite (for
+ * instance from a NaN or Inf in its inputs, or an overlap too ill-conditioned
+ * for FP64) is kept as data: its E_L leaves the estimator sums and its weight
+ * is set to 0, so one such walker never turns a population estimate into NaN.
+ * The kernels that write E_L, the force bias and W also OR these bits into a
+ * per-walker int32 flag word, flags[k], held in the first 4 nw bytes of the
+ * workspace:
+ *   AFQMC_NUMERIC_ELOC     E_L non-finite             (afqmc_local_energy)
+ *   AFQMC_NUMERIC_XBAR     a force-bias component     (afqmc_local_energy,
+ *                          non-finite                  afqmc_force_bias)
+ *   AFQMC_NUMERIC_WEIGHT   the move's weight update   (afqmc_propagate)
+ *                          non-finite (W set to 0)
+ *   AFQMC_NUMERIC_HANDOFF  the hand-off's sign sum,   (afqmc_metropolis_x)
+ *                          reference or weight non-finite (W set to 0)
+ * Flags accumulate until afqmc_numeric_flags reads and clears them, or until
+ * afqmc_set_workspace installs a new workspace (whose flags start clear).  A
+ * call made with no workspace set (afqmc_local_energy or afqmc_force_bias
+ * with every per-path output given) records no flags. */
+enum { AFQMC_NUMERIC_ELOC = 1, AFQMC_NUMERIC_XBAR = 2, AFQMC_NUMERIC_WEIGHT = 4,
+       AFQMC_NUMERIC_HANDOFF = 8 };
+
+/* Synchronises the context's stream, copies the flag words of walkers
+ * 0 .. nw-1 to flags (HOST int32 [nw], may be NULL), stores the number of
+ * flagged walkers in *n_flagged (may be NULL), and clears those words.
+ * Returns AFQMC_E_NUMERIC if any of them was set (the text of
+ * afqmc_last_error names the count and the first walker), AFQMC_OK if none
+ * was, AFQMC_E_WORKSPACE without a workspace for nw walkers. */
+afqmc_status afqmc_numeric_flags(afqmc_ctx ctx, int32_t nw, int32_t* flags, int32_t* n_flagged);
+
+/* on = 1: afqmc_local_energy, afqmc_force_bias, afqmc_propagate and
+ * afqmc_metropolis_x clear the flags of their nw walkers first, synchronise
+ * the stream after their kernels, and return AFQMC_E_NUMERIC if one of those
+ * walkers was flagged (their outputs are written as always; the flags stay
+ * for afqmc_numeric_flags).  on = 0 (the default): those calls stay
+ * asynchronous and never report numerical events themselves. */
+afqmc_status afqmc_set_numeric_check(afqmc_ctx ctx, int32_t on);
 
 /* Initial paths y ~ p_T (stream INIT of the counter layout below). */
 afqmc_status afqmc_sample_prior(afqmc_ctx ctx, int32_t nw, uint64_t seed, double* y);

@@ -147,9 +147,12 @@ def green(phiT: np.ndarray, phi: np.ndarray):
 
 
 def phases(ell: np.ndarray) -> np.ndarray:
-    """S_p = O_p / |O_p| (Eq. sign-path); 0 for a singular sample."""
-    ok = np.isfinite(ell.real)
-    return np.where(ok, np.exp(1j * np.where(ok, ell.imag, 0.0)), 0.0)
+    """S_p = O_p / |O_p| (Eq. sign-path); 0 for a singular sample (l = -inf).
+    A NaN log-overlap (an overlap matrix with a non-finite entry) gives a NaN
+    phase, so the walker's estimates and weight come out non-finite."""
+    sing = np.isneginf(ell.real)
+    with np.errstate(invalid="ignore"):
+        return np.where(sing, 0.0, np.exp(1j * np.where(sing, 0.0, ell.imag)))
 
 
 # ---------------------------------------------------------------------------
@@ -170,7 +173,7 @@ def sample_contraction(sys, phiT: np.ndarray, theta: np.ndarray, ell: np.ndarray
     vb = np.zeros((nw, P, G), dtype=np.complex128)
     ep = np.zeros((nw, P), dtype=np.complex128)
     for w in range(nw):
-        ok = np.isfinite(ell[w].real)
+        ok = ~np.isneginf(ell[w].real)
         Y = np.einsum("pmi,gmn->pgin", phiT[w], sys.L)          # Phi_T^T L_g  [P,G,N,M]
         f = np.einsum("pgim,psmj->pgsij", Y, theta[w])           # [P,G,2,N,N]
         trf = np.einsum("pgsii->pgs", f)
@@ -260,10 +263,11 @@ def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
     """
     phin = propagate_dets(sys, phi, xi, xbar, dtau, n_taylor, Eh)
     elln = log_overlap(phiT, phin)
-    ok = np.isfinite(logov.real)
-    okn = np.isfinite(elln.real) & ok
-    diff = np.where(okn, elln, 0.0) - np.where(okn, logov.real, 0.0)
-    num_r = np.where(okn, np.exp(diff), 0.0).sum(-1)
+    ok = ~np.isneginf(logov.real)
+    okn = ~np.isneginf(elln.real) & ok
+    with np.errstate(invalid="ignore"):
+        diff = np.where(okn, elln, 0.0) - np.where(okn, logov.real, 0.0)
+        num_r = np.where(okn, np.exp(diff), 0.0).sum(-1)
     S = phases(logov)
     den = S.sum(-1)
     alive = (den != 0) & (num_r != 0)
@@ -343,16 +347,20 @@ def _accept(u: np.ndarray, log_alpha: np.ndarray) -> np.ndarray:
 
 
 def handoff(w, logov_new, ref, weight_mode=WEIGHT_SEPARATE):
-    """W <- W max(0, cos Delta-theta_T), Delta-theta_T = arg sum S' - arg ref."""
+    """W <- W max(0, cos Delta-theta_T), Delta-theta_T = arg sum S' - arg ref.
+    A non-finite reference or weight gives W = 0, as a non-finite weight
+    update does in propagate."""
     Sn = phases(logov_new).sum(-1)
-    dth = np.angle(Sn) - np.angle(ref)
-    if weight_mode == WEIGHT_HALFPLANE:
-        wrapped = np.angle(np.exp(1j * dth))
-        fac = np.where(np.abs(wrapped) > 0.5 * np.pi, 0.0, 1.0)
-    else:
-        fac = np.maximum(0.0, np.cos(dth))
-    alive = (Sn != 0) & (ref != 0)
-    return np.where(alive, w * fac, 0.0)
+    with np.errstate(invalid="ignore"):
+        dth = np.angle(Sn) - np.angle(ref)
+        if weight_mode == WEIGHT_HALFPLANE:
+            wrapped = np.angle(np.exp(1j * dth))
+            fac = np.where(np.abs(wrapped) > 0.5 * np.pi, 0.0, 1.0)
+        else:
+            fac = np.maximum(0.0, np.cos(dth))
+        wn = w * fac
+    alive = (Sn != 0) & (ref != 0) & np.isfinite(Sn) & np.isfinite(ref) & np.isfinite(wn)
+    return np.where(alive, wn, 0.0)
 
 
 # ---------------------------------------------------------------------------

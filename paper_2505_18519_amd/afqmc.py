@@ -25,6 +25,8 @@ MLP_HIDDEN = 256
 TAG_FIELD, TAG_PROPOSAL, TAG_ACCEPT, TAG_COMB, TAG_INIT = 1, 2, 3, 4, 5
 INIT_STEP, MEASURE_STEP = 1 << 63, 1 << 62     # AFQMC_INIT_STEP, AFQMC_MEASURE_STEP
 TRIAL_JASTROW, TRIAL_SLICES = 0, 1
+NUMERIC_ELOC, NUMERIC_XBAR, NUMERIC_WEIGHT, NUMERIC_HANDOFF = 1, 2, 4, 8
+E_NUMERIC = 5
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_NOMEM",
           5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_WORKSPACE"}
@@ -58,6 +60,8 @@ EXPORTS = {
     "afqmc_workspace_size": (c_int, [c_void_p, c_int32, POINTER(c_size_t)]),
     "afqmc_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
     "afqmc_sample_prior": (c_int, [c_void_p, c_int32, c_uint64, c_void_p]),
+    "afqmc_numeric_flags": (c_int, [c_void_p, c_int32, c_void_p, POINTER(c_int32)]),
+    "afqmc_set_numeric_check": (c_int, [c_void_p, c_int32]),
     "afqmc_trial_build": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_overlap": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "afqmc_green": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -129,7 +133,9 @@ def load_library():
 
 
 class AfqmcError(RuntimeError):
-    pass
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 def _check(ctx, st, what):
@@ -138,7 +144,7 @@ def _check(ctx, st, what):
         if ctx is not None and ctx.handle:
             m = load_library().afqmc_last_error(ctx.handle)
             msg = m.decode() if m else ""
-        raise AfqmcError(f"{what}: {STATUS.get(st, st)} {msg}")
+        raise AfqmcError(f"{what}: {STATUS.get(st, st)} {msg}", st)
 
 
 def _ptr(t, dtype, numel, name, allow_none=False):
@@ -250,6 +256,25 @@ class Context:
 
 
 # --- functions with the C names -------------------------------------------------
+
+def afqmc_numeric_flags(ctx, nw):
+    """(flags [nw] int32 numpy array, number flagged); reads and clears the
+    flag words (AFQMC_E_NUMERIC is reported by the count, not raised)."""
+    import numpy as np
+    flags = np.zeros(max(int(nw), 1), dtype=np.int32)
+    n = c_int32(0)
+    lib = load_library()
+    lib.afqmc_set_stream(ctx.handle, _stream())
+    st = lib.afqmc_numeric_flags(ctx.handle, int(nw), flags.ctypes.data_as(c_void_p),
+                                 ctypes.byref(n))
+    if st not in (0, E_NUMERIC):
+        _check(ctx, st, "afqmc_numeric_flags")
+    return flags[:int(nw)], int(n.value)
+
+
+def afqmc_set_numeric_check(ctx, on):
+    ctx._call("afqmc_set_numeric_check", 1 if on else 0)
+
 
 def afqmc_sample_prior(ctx, nw, seed, y):
     ctx._call("afqmc_sample_prior", nw, seed, _ptr(y, torch.float64, nw * ctx.P * ctx.K, "y"))
@@ -444,9 +469,24 @@ def afqmc_mlp_num_params(ctx):
     return int(load_library().afqmc_mlp_num_params(ctx.handle))
 
 
-def afqmc_mlp_init(ctx, precision, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
-    """params: host float64 array of afqmc_mlp_num_params(ctx) values."""
+MLP_PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def mlp_pack(params):
+    """The flat parameter array of afqmc_mlp_init from a dict of the six
+    network arrays: W1 [D][H], b1 [H], W2 [H][H], b2 [H], W3 [H][2K], b3 [2K],
+    each row-major, concatenated in that order (the layout afqmc.h states)."""
     import numpy as np
+    return np.concatenate([np.asarray(params[k], dtype=np.float64).ravel()
+                           for k in MLP_PARAM_ORDER])
+
+
+def afqmc_mlp_init(ctx, precision, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """params: host float64 array of afqmc_mlp_num_params(ctx) values, or a
+    dict of the six arrays (packed by mlp_pack)."""
+    import numpy as np
+    if isinstance(params, dict):
+        params = mlp_pack(params)
     p = np.ascontiguousarray(params, dtype=np.float64).ravel()
     n = afqmc_mlp_num_params(ctx)
     if p.size != n:

@@ -80,6 +80,57 @@ T* ws_ptr(afqmc_ctx_s* c, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(c->ws) + off);
 }
 
+// The numerical-event flag words of walkers [0, nw) (the workspace's first
+// 4 nw bytes), null if no workspace that large is set.  Words not yet known
+// to be clear are cleared first, on the stream, by a fill kernel; with the
+// numeric check on, all nw are cleared so that the call reports only its own.
+int* flag_words(afqmc_ctx_s* c, int nw, hipError_t* e) {
+  *e = hipSuccess;
+  if (c->ws == nullptr || c->ws_bytes < align256((size_t)nw * 4)) return nullptr;
+  int* f = static_cast<int*>(c->ws);
+  const int from = c->numeric_check ? 0 : c->flags_clear;
+  if (nw > from) {
+    *e = launch_zero_int(c, nw - from, f + from);
+    if (*e != hipSuccess) return nullptr;
+  }
+  c->flags_clear = std::max(c->flags_clear, nw);
+  return f;
+}
+
+// Copies the flag words of walkers [0, nw) to host (synchronising the
+// stream) and counts the flagged ones.
+hipError_t read_flags(afqmc_ctx_s* c, int nw, std::vector<int32_t>* out, int* n_bad, int* first) {
+  out->assign((size_t)nw, 0);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && nw > 0)
+    e = hipMemcpy(out->data(), c->ws, (size_t)nw * 4, hipMemcpyDeviceToHost);
+  *n_bad = 0;
+  *first = -1;
+  for (int k = 0; k < nw && e == hipSuccess; ++k)
+    if ((*out)[k] != 0) {
+      if (*first < 0) *first = k;
+      ++*n_bad;
+    }
+  return e;
+}
+
+afqmc_status numeric_report(afqmc_ctx_s* c, int n_bad, int first, int bits) {
+  return fail(c, AFQMC_E_NUMERIC,
+              std::to_string(n_bad) + " walker(s) with a non-finite result; first: walker " +
+                  std::to_string(first) + ", flag bits " + std::to_string(bits));
+}
+
+// With the numeric check on, the end of a per-step call: synchronise and
+// report the walkers this call flagged.
+afqmc_status numeric_check_end(afqmc_ctx_s* c, int nw, const int* f) {
+  if (!c->numeric_check || f == nullptr) return AFQMC_OK;
+  std::vector<int32_t> h;
+  int n_bad = 0, first = -1;
+  hipError_t e = read_flags(c, nw, &h, &n_bad, &first);
+  if (e != hipSuccess) return hip_fail(c, e, "numeric check");
+  return n_bad ? numeric_report(c, n_bad, first, h[first]) : AFQMC_OK;
+}
+
 hipError_t do_trial_build(const afqmc_ctx_s* c, int n, const double* y, double* phiT, double* ub) {
   return c->small ? launch_trial_build(c, n, y, phiT, ub) : launch_trial_build_g(c, n, y, phiT, ub);
 }
@@ -101,6 +152,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
   ws_layout L;
   const size_t S = (size_t)nw * c->P;
   size_t off = 0;
+  L.flags = off;
+  off += align256((size_t)nw * 4);
   L.vb = off;
   off += align256(S * c->G * 16);
   L.ep = off;
@@ -351,6 +404,39 @@ afqmc_status afqmc_set_workspace(afqmc_ctx c, void* dptr, size_t bytes) {
     return fail(c, AFQMC_E_INVALID, "workspace must be 256-byte aligned");
   c->ws = dptr;
   c->ws_bytes = dptr ? bytes : 0;
+  c->flags_clear = 0;  // a new workspace's flag words are cleared at first use
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_numeric_flags(afqmc_ctx c, int32_t nw, int32_t* flags, int32_t* n_flagged) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (n_flagged != nullptr) *n_flagged = 0;
+  if (c->ws == nullptr || c->ws_bytes < align256((size_t)nw * 4))
+    return fail(c, AFQMC_E_WORKSPACE, "no workspace for the flags of nw walkers");
+  if (nw == 0) return AFQMC_OK;
+  hipError_t e;
+  if (nw > c->flags_clear) {  // words not written since the workspace was set
+    HIPCALL(c, launch_zero_int(c, nw - c->flags_clear, static_cast<int*>(c->ws) + c->flags_clear),
+            "numeric flags");
+    c->flags_clear = nw;
+  }
+  std::vector<int32_t> h;
+  int n_bad = 0, first = -1;
+  e = read_flags(c, nw, &h, &n_bad, &first);
+  if (e != hipSuccess) return hip_fail(c, e, "numeric flags");
+  if (flags != nullptr) memcpy(flags, h.data(), (size_t)nw * 4);
+  if (n_flagged != nullptr) *n_flagged = n_bad;
+  if (n_bad == 0) return AFQMC_OK;
+  HIPCALL(c, launch_zero_int(c, nw, static_cast<int*>(c->ws)), "numeric flags");
+  HIPCALL(c, hipStreamSynchronize(c->stream), "numeric flags");
+  return numeric_report(c, n_bad, first, h[first]);
+}
+
+afqmc_status afqmc_set_numeric_check(afqmc_ctx c, int32_t on) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  if (on != 0 && on != 1) return fail(c, AFQMC_E_INVALID, "on must be 0 or 1");
+  c->numeric_check = on == 1;
   return AFQMC_OK;
 }
 
@@ -433,11 +519,14 @@ static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, con
             launch_contract_g(c, nw, phiT, static_cast<const double*>(theta),
                               static_cast<const double*>(logov), vb, ep),
             "contract");
+  hipError_t fe;
+  int* flags = flag_words(c, nw, &fe);
+  HIPCALL(c, fe, "flags");
   HIPCALL(c,
           launch_combine(c, nw, vb, ep, static_cast<const double*>(logov),
-                         static_cast<double*>(xbar), static_cast<double*>(eloc)),
+                         static_cast<double*>(xbar), static_cast<double*>(eloc), flags),
           "combine");
-  return AFQMC_OK;
+  return numeric_check_end(c, nw, flags);
 }
 
 afqmc_status afqmc_force_bias(afqmc_ctx c, int32_t nw, const double* phiT, const void* theta,
@@ -489,12 +578,16 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat), "vbuild");
   HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph), "taylor");
   HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr), "ratio overlap");
+  hipError_t fe;
+  int* flags = flag_words(c, nw, &fe);
+  HIPCALL(c, fe, "flags");
   HIPCALL(c,
           launch_weight(c, nw, xi, static_cast<const double*>(xbar),
                         static_cast<const double*>(logov), static_cast<double*>(logov_new),
-                        static_cast<const double*>(eloc), e_shift, w, static_cast<double*>(ref)),
+                        static_cast<const double*>(eloc), e_shift, w, static_cast<double*>(ref),
+                        flags),
           "weight");
-  return AFQMC_OK;
+  return numeric_check_end(c, nw, flags);
 }
 
 afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double* y, double* phiT,
@@ -569,9 +662,12 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
                             AFQMC_PROPOSAL_LEARNED, lqx, gdc, gdt, nullptr),
               "accept");
     }
-    if (w != nullptr)
-      HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
-    return AFQMC_OK;
+    if (w == nullptr) return AFQMC_OK;
+    hipError_t fe;
+    int* flags = flag_words(c, nw, &fe);
+    HIPCALL(c, fe, "flags");
+    HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w, flags), "handoff");
+    return numeric_check_end(c, nw, flags);
   }
   const int nflip = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? c->K : 1;
   for (int s = 0; s < n_sweep; ++s) {
@@ -587,9 +683,12 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
               "accept");
     }
   }
-  if (w != nullptr)
-    HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w), "handoff");
-  return AFQMC_OK;
+  if (w == nullptr) return AFQMC_OK;
+  hipError_t fe;
+  int* flags = flag_words(c, nw, &fe);
+  HIPCALL(c, fe, "flags");
+  HIPCALL(c, launch_handoff(c, nw, lo, static_cast<const double*>(ref), w, flags), "handoff");
+  return numeric_check_end(c, nw, flags);
 }
 
 // Pair chain of the initialisation from the trial: two P = 1 chains whose

@@ -48,6 +48,10 @@ struct afqmc_ctx_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
+  // numerical-event flags: one int32 per walker at the start of the workspace;
+  // the first flags_clear of them are known to be zero (host bookkeeping)
+  int flags_clear = 0;
+  bool numeric_check = false;  // per-step calls synchronise and report AFQMC_E_NUMERIC
 
   // learned proposal network (allocated by afqmc_mlp_init)
   struct mlp_state {
@@ -73,6 +77,7 @@ struct afqmc_ctx_s {
 
 // Workspace carve-up for nw walkers (byte offsets, 256-aligned).
 struct ws_layout {
+  size_t flags;  // [nw] int32 numerical-event flags (AFQMC_NUMERIC_*), always at offset 0
   size_t vb, ep, vmat, ubuf, qrshift, ytry, phiTtry, ltry, acc, pc_C, pc_tot, pc_parent, pc_phi, pc_y, pc_phiT,
       pc_logov;
   // learned proposal (zero-sized unless proposal == LEARNED); Sp = paths rounded up to 16
@@ -100,14 +105,16 @@ hipError_t launch_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const
                           double* logov, double* theta, double* gdiag);
 hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
                            const double* logov, double* vb, double* ep);
+// flags (may be null): per-walker AFQMC_NUMERIC_* bits OR-ed in where a
+// kernel finds a non-finite result
 hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const double* ep,
-                          const double* logov, double* xbar, double* eloc);
+                          const double* logov, double* xbar, double* eloc, int* flags);
 hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
                          double* vmat);
 hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
                          const double* logov, const double* logov_new, const double* eloc,
-                         double e_shift, double* w, double* ref);
+                         double e_shift, double* w, double* ref, int* flags);
 // proposal: the kind of move (AFQMC_PROPOSAL_PRIOR or _RW; the learned
 // proposal's random-walk moves pass _RW)
 hipError_t launch_proposal(const afqmc_ctx_s* c, int nw, const double* y, double* ytry,
@@ -118,7 +125,7 @@ hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, 
                          int proposal, const double* lextra = nullptr, double* gd_cur = nullptr,
                          const double* gd_try = nullptr, int* mask = nullptr);
 hipError_t launch_handoff(const afqmc_ctx_s* c, int nw, const double* logov, const double* ref,
-                          double* w);
+                          double* w, int* flags);
 hipError_t launch_qr(const afqmc_ctx_s* c, int nw, double* phi, double* logov);
 hipError_t launch_estimator(const afqmc_ctx_s* c, int nw, const double* w, const double* eloc,
                             double* out);

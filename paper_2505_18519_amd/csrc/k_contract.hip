@@ -248,11 +248,12 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
 
 // Walker-level estimates over the P paths (Eq. local-obs, then Eq. shift1):
 // S_p = exp(i Im l_p) (0 if singular), xbar_g = -i sqrt(tau) sum S vb / sum S,
-// E_L = sum S E_p / sum S.  One workgroup of 64 threads per walker.
+// E_L = sum S E_p / sum S.  One workgroup of 64 threads per walker.  A
+// non-finite E_L or force-bias component sets the walker's flag bits.
 __global__ void __launch_bounds__(64)
 k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* __restrict__ vb,
           const double* __restrict__ ep, const double* __restrict__ logov,
-          double* __restrict__ xbar, double* __restrict__ eloc) {
+          double* __restrict__ xbar, double* __restrict__ eloc, int* __restrict__ flags) {
   __shared__ double s_S[64][2];
   const int w = blockIdx.x;
   const int lane = threadIdx.x;
@@ -267,6 +268,7 @@ k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* 
   cplx den = cmk(0.0, 0.0);
   for (int p = 0; p < P; ++p) den = cadd(den, cmk(s_S[p][0], s_S[p][1]));
   const bool good = (den.re != 0.0 || den.im != 0.0);
+  bool bad_xb = false;
   if (xbar != nullptr) {
     for (int gm = lane; gm < G; gm += 64) {
       cplx num = cmk(0.0, 0.0);
@@ -280,14 +282,21 @@ k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* 
         if (mag > xbar_cap) xb = cscale(xb, xbar_cap / mag);
       }
       cst(xbar + ((size_t)w * G + gm) * 2, xb);
+      bad_xb |= !(__builtin_isfinite(xb.re) && __builtin_isfinite(xb.im));
     }
   }
-  if (eloc != nullptr && lane == 0) {
+  const bool any_bad_xb = __ballot(bad_xb) != 0;
+  if (lane != 0) return;
+  int bits = any_bad_xb ? AFQMC_NUMERIC_XBAR : 0;
+  if (eloc != nullptr) {
     cplx num = cmk(0.0, 0.0);
     for (int p = 0; p < P; ++p)
       num = cfma(num, cmk(s_S[p][0], s_S[p][1]), cld(ep + ((size_t)w * P + p) * 2));
-    cst(eloc + (size_t)w * 2, good ? cdiv(num, den) : cmk(0.0, 0.0));
+    const cplx el = good ? cdiv(num, den) : cmk(0.0, 0.0);
+    cst(eloc + (size_t)w * 2, el);
+    if (!(__builtin_isfinite(el.re) && __builtin_isfinite(el.im))) bits |= AFQMC_NUMERIC_ELOC;
   }
+  if (bits != 0 && flags != nullptr) flags[w] |= bits;
 }
 
 template <int MT>
@@ -315,10 +324,10 @@ hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, con
 }
 
 hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const double* ep,
-                          const double* logov, double* xbar, double* eloc) {
+                          const double* logov, double* xbar, double* eloc, int* flags) {
   if (nw <= 0) return hipSuccess;
   if (c->P > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_combine, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, sqrt(c->dtau),
-                     c->xbar_cap, vb, ep, logov, xbar, eloc);
+                     c->xbar_cap, vb, ep, logov, xbar, eloc, flags);
   return hipGetLastError();
 }

@@ -97,10 +97,11 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
   if (lane == 0 && nacc != nullptr) nacc[w] += count;
 }
 
-// W <- W max(0, cos(arg sum_p S'_p - arg ref)), or the half-plane rule
+// W <- W max(0, cos(arg sum_p S'_p - arg ref)), or the half-plane rule; a
+// non-finite sign sum, reference or weight sets W = 0 and the walker's flag
 __global__ void __launch_bounds__(64)
 k_handoff(int nw, int P, int weight_mode, const double* __restrict__ logov,
-          const double* __restrict__ ref, double* __restrict__ w) {
+          const double* __restrict__ ref, double* __restrict__ w, int* __restrict__ flags) {
   const int wk = blockIdx.x;
   const int lane = threadIdx.x;
   double sr = 0.0, si = 0.0;
@@ -117,7 +118,9 @@ k_handoff(int nw, int P, int weight_mode, const double* __restrict__ logov,
   si = wave_sum(si);
   if (lane != 0) return;
   const double rr = ref[(size_t)wk * 2], ri = ref[(size_t)wk * 2 + 1];
-  const bool alive = (sr != 0.0 || si != 0.0) && (rr != 0.0 || ri != 0.0);
+  const bool finite = __builtin_isfinite(sr) && __builtin_isfinite(si) &&
+                      __builtin_isfinite(rr) && __builtin_isfinite(ri);
+  const bool alive = finite && (sr != 0.0 || si != 0.0) && (rr != 0.0 || ri != 0.0);
   double fac = 0.0;
   if (alive) {
     const double dth = atan2(si, sr) - atan2(ri, rr);
@@ -128,7 +131,10 @@ k_handoff(int nw, int P, int weight_mode, const double* __restrict__ logov,
       fac = fmax(0.0, cos(dth));
     }
   }
-  w[wk] = w[wk] * fac;
+  const double wn = w[wk] * fac;
+  const bool ok = finite && __builtin_isfinite(wn);
+  w[wk] = ok ? wn : 0.0;
+  if (!ok && flags != nullptr) flags[wk] |= AFQMC_NUMERIC_HANDOFF;
 }
 
 }  // namespace
@@ -156,9 +162,9 @@ hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, 
 }
 
 hipError_t launch_handoff(const afqmc_ctx_s* c, int nw, const double* logov, const double* ref,
-                          double* w) {
+                          double* w, int* flags) {
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_handoff, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->weight_mode, logov,
-                     ref, w);
+                     ref, w, flags);
   return hipGetLastError();
 }

@@ -18,6 +18,7 @@
 //     Re sum_s sum_n Theta^s_mn Phi_T,mn requested, one lane per orbital row m
 //     solves x (A^s)^{-1} for its row of phi instead.
 // A zero pivot marks the path singular: l = -inf + 0i and Theta = 0, diag = 0.
+// A non-finite overlap entry gives l = NaN + NaN i (Theta and diag 0).
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -85,6 +86,15 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
   bool used = (i >= N) || (lane >= 32);
+  // a non-finite entry of either spin's overlap matrix makes l NaN (a
+  // numerical event, not a singular path)
+  bool nonfinite = false;
+  if (!used) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+      if (k < N) nonfinite |= !(isfinite(a[k].re) && isfinite(a[k].im));
+  }
+  const bool nf_any = __ballot(nonfinite) != 0;
   int mystep = -1;
   int perm[NT];
   // det = prod of pivots, kept as a complex mantissa times 2^pexp so that it
@@ -161,7 +171,10 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   const bool sing_any = sing_up || sing_dn;
   if (lane == 0) {
     double* o = logov + (size_t)s * 2;
-    if (sing_any) {
+    if (nf_any) {
+      o[0] = __builtin_nan("");
+      o[1] = __builtin_nan("");
+    } else if (sing_any) {
       o[0] = neg_inf();
       o[1] = 0.0;
     } else {
@@ -173,7 +186,7 @@ k_overlap(int n_samples, int P, int M, int N, const double* __restrict__ phi,
 
   double* th = theta ? theta + (size_t)s * 2 * M * N * 2 : nullptr;
   double* gd = gdiag ? gdiag + (size_t)s * M : nullptr;
-  if (sing_any) {
+  if (sing_any || nf_any) {
     if (th)
       for (int q = lane; q < 2 * M * N * 2; q += 64) th[q] = 0.0;
     if (gd)

@@ -14,7 +14,9 @@
 //     per tile), stored as whole 16-byte complex entries along each row; with
 //     the Green's function diagonal Re (G_up + G_dn)_mm requested, lanes over
 //     orbital rows m solve x (A^s)^{-1} for their rows of phi instead.
-// The two spins' log-determinants and diagonals are added through LDS.
+// The two spins' log-determinants and diagonals are added through LDS.  A
+// zero pivot gives l = -inf + 0i, a non-finite overlap entry l = NaN + NaN i
+// (Theta and the diagonal 0 in both cases).
 // CT: complex trial determinants (multi-slice trials), A^s = Phi_T^T phi^s
 // with both factors complex (no conjugation: the bilinear overlap of Eq.
 // ratio-update-phi); the Green's-function diagonal is then not formed.
@@ -103,6 +105,15 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
     a[j] = (i < NT) ? cmk(s_lu[sp][i][j][0], s_lu[sp][i][j][1]) : cmk(0.0, 0.0);
   __syncthreads();
   bool used = i >= N;
+  // a non-finite entry of either spin's overlap matrix makes l NaN (a
+  // numerical event, not a singular path)
+  bool nonfinite = false;
+  if (!used) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      if (j < N) nonfinite |= !(isfinite(a[j].re) && isfinite(a[j].im));
+  }
+  nonfinite = __ballot(nonfinite) != 0;
   int mystep = -1;
   int perm[NT];
   cplx pprod = cmk(1.0, 0.0);
@@ -170,7 +181,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   if (lane == 0) {
     s_res[sp][0] = 0.5 * log(cabs2(pprod)) + (double)pexp * M_LN2;
     s_res[sp][1] = atan2(pprod.im, pprod.re) + ((inv & 1) ? M_PI : 0.0);
-    s_res[sp][2] = singular ? 1.0 : 0.0;
+    s_res[sp][2] = nonfinite ? 2.0 : singular ? 1.0 : 0.0;
   }
   // LU rows in step order, permutation
   if (i < N && mystep >= 0) {
@@ -183,10 +194,12 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   }
   __syncthreads();
   const bool sing_any = s_res[0][2] != 0.0 || s_res[1][2] != 0.0;
+  const bool nf_any = s_res[0][2] == 2.0 || s_res[1][2] == 2.0;
   if (threadIdx.x == 0) {
     double* o = logov + (size_t)s * 2;
-    o[0] = sing_any ? neg_inf() : s_res[0][0] + s_res[1][0];
-    o[1] = sing_any ? 0.0 : s_res[0][1] + s_res[1][1];
+    const double nan = __builtin_nan("");
+    o[0] = nf_any ? nan : sing_any ? neg_inf() : s_res[0][0] + s_res[1][0];
+    o[1] = nf_any ? nan : sing_any ? 0.0 : s_res[0][1] + s_res[1][1];
   }
   if (theta == nullptr && gdiag == nullptr) return;
   double* th = theta ? theta + ((size_t)s * 2 + sp) * M * N * 2 : nullptr;

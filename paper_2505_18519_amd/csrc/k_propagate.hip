@@ -245,7 +245,8 @@ __global__ void __launch_bounds__(64)
 k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
          const double* __restrict__ xi, const double* __restrict__ xbar,
          const double* __restrict__ logov, const double* __restrict__ logov_new,
-         const double* __restrict__ eloc, double* __restrict__ w, double* __restrict__ ref) {
+         const double* __restrict__ eloc, double* __restrict__ w, double* __restrict__ ref,
+         int* __restrict__ flags) {
   const int wk = blockIdx.x;
   const int lane = threadIdx.x;
   // sum_g (xi_g xbar_g - xbar_g^2 / 2)
@@ -291,7 +292,9 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
     else
       wn = w[wk] * mag * fmax(0.0, cos(atan2(r.im, r.re)));
   }
-  w[wk] = __builtin_isfinite(wn) ? wn : 0.0;  // a non-finite weight kills the walker
+  const bool finite = __builtin_isfinite(wn);
+  w[wk] = finite ? wn : 0.0;  // a non-finite weight kills the walker, and is flagged
+  if (!finite && flags != nullptr) flags[wk] |= AFQMC_NUMERIC_WEIGHT;
   const cplx rf = (weight_mode == AFQMC_WEIGHT_COMBINED) ? den : num;
   ref[(size_t)wk * 2] = rf.re;
   ref[(size_t)wk * 2 + 1] = rf.im;
@@ -330,10 +333,10 @@ hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, doubl
 
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
                          const double* logov, const double* logov_new, const double* eloc,
-                         double e_shift, double* w, double* ref) {
+                         double e_shift, double* w, double* ref, int* flags) {
   if (nw <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_weight, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, c->dtau, e_shift,
-                     c->weight_mode, xi, xbar, logov, logov_new, eloc, w, ref);
+                     c->weight_mode, xi, xbar, logov, logov_new, eloc, w, ref, flags);
   return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ def test_force_bias_and_local_energy(case):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("mode", [0, 1, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_propagate(case, mode):
     _say("case", case, "mode", mode)
     s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
@@ -183,21 +183,27 @@ def test_propagate(case, mode):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("proposal", [0, 1])
-def test_metropolis_and_handoff(case, proposal):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_metropolis_and_handoff(case, proposal, mode):
+    """Metropolis moves of the paths, then the hand-off projection of the
+    weight mode: the cosine (SEPARATE, COMBINED) or the half-plane rule.  For
+    modes 1 and 2 the reference phases span the whole circle, so walkers on
+    both sides of the half-plane boundary occur."""
     s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
     if s.hidden_kind == 0 and proposal == 1:
         pytest.skip("random walk is for Gaussian hidden variables")
-    _say("case", case, "proposal", proposal)
+    _say("case", case, "proposal", proposal, "mode", mode)
     from paper_2505_18519_amd import afqmc as A
-    ctx = make_ctx(s, P, nw, proposal=proposal, rw_step=0.3)
+    ctx = make_ctx(s, P, nw, proposal=proposal, rw_step=0.3, weight_mode=mode)
     rng, phi, y = state(s, P, nw, 4)
     phiT = O.trial_det(s, y)
     ell = O.log_overlap(phiT, phi)
-    ref = np.exp(1j * rng.uniform(-0.3, 0.3, size=nw)) * rng.uniform(0.5, 2, size=nw)
+    spread = 0.3 if mode == 0 else math.pi
+    ref = np.exp(1j * rng.uniform(-spread, spread, size=nw)) * rng.uniform(0.5, 2, size=nw)
     w0 = rng.uniform(0.5, 1.5, size=nw)
     seed, stp, nsw = 1234, 7, 2
     y2, phiT2, ell2, w2, nacc = O.metropolis(s, phi, y, phiT, ell, ref, w0, seed, stp, nsw,
-                                             proposal=proposal, rw_step=0.3)
+                                             proposal=proposal, rw_step=0.3, weight_mode=mode)
     dy, dphiT, dl, dw = dev(y), dev(phiT), dev(ell), dev(w0)
     dacc = torch.zeros(nw, dtype=torch.int32, device="cuda")
     A.afqmc_metropolis_x(ctx, nw, dev(phi), dy, dphiT, dl, dev(ref), dw, seed, stp, nsw, dacc)
@@ -208,7 +214,33 @@ def test_metropolis_and_handoff(case, proposal):
     assert np.abs(host(dy) - y2).max() <= 4e-15 * max(np.abs(y2).max(), 1.0)
     assert rel(host(dphiT), phiT2) <= 1e-12
     check_logov(host(dl), ell2)
-    assert np.abs(host(dw) - w2).max() <= TOL * np.abs(w2).max()
+    assert np.array_equal(host(dw) == 0.0, w2 == 0.0)
+    assert np.abs(host(dw) - w2).max() <= TOL * max(np.abs(w2).max(), 1e-300)
+
+
+def test_half_plane_handoff_both_outcomes():
+    """Half-plane hand-off over many walkers whose reference phases span the
+    circle: the kept set and the weights equal the oracle's exactly, and both
+    outcomes occur."""
+    _say("half-plane hand-off")
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5)
+    P, nw = 4, 96
+    ctx = make_ctx(s, P, nw, proposal=A.PROPOSAL_RW, rw_step=0.3,
+                   weight_mode=A.WEIGHT_HALFPLANE)
+    rng, phi, y = state(s, P, nw, 14)
+    phiT = O.trial_det(s, y)
+    ell = O.log_overlap(phiT, phi)
+    ref = np.exp(1j * rng.uniform(-math.pi, math.pi, size=nw))
+    w0 = rng.uniform(0.5, 1.5, size=nw)
+    _, _, _, w2, _ = O.metropolis(s, phi, y, phiT, ell, ref, w0, 99, 3, 1,
+                                  proposal=O.PROPOSAL_RW, rw_step=0.3,
+                                  weight_mode=O.WEIGHT_HALFPLANE)
+    dw = dev(w0)
+    A.afqmc_metropolis_x(ctx, nw, dev(phi), dev(y), dev(phiT), dev(ell), dev(ref), dw, 99, 3, 1)
+    torch.cuda.synchronize()
+    assert 20 < (w2 > 0).sum() < nw - 20
+    assert np.array_equal(host(dw), w2)
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -307,26 +339,49 @@ def test_singular_paths_are_excluded(case, prec):
         assert rel(host(d_xb)[w], xbar[w]) <= bound
 
 
-def test_trajectory_tiny_matches_oracle():
-    """30 whole steps (QR every 10) on the tiny Ising workload, identical streams."""
-    _say("trajectory tiny")
+TRAJ = {
+    # name: (system factory, P, walkers, tau, proposal, rw step)
+    "tiny-ising": (lambda: ai.workload(0)[0], 8, 16, 0.01, 0, 0.0),
+    "gauss-M20-rw": (lambda: ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5), 4, 12, 0.01,
+                     1, 0.3),
+    "gauss-M72-prior": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 6,
+                        0.005, 0, 0.0),
+}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("name", list(TRAJ))
+def test_trajectory_matches_oracle(name, mode):
+    """30 whole steps (QR every 10) in every weight formalism, identical
+    streams: per-step estimator sums, then paths and weights, against the
+    oracle's steps.  The local-energy formalism (mode 3) runs with the
+    shift E_T at the first step's energy, as production runs do."""
+    _say("trajectory", name, "mode", mode)
     from paper_2505_18519_amd import afqmc as A
     from paper_2505_18519_amd import driver as D
-    s, run = ai.workload(0)
-    nw, P, seed = 16, run.P, 2001
-    ctx = A.Context(s, P, run.dtau, max_walkers=nw)
+    fac, P, nw, dtau, prop, rw = TRAJ[name]
+    s = fac()
+    seed = 2001
+    ctx = A.Context(s, P, dtau, max_walkers=nw, weight_mode=mode, proposal=prop, rw_step=rw)
     st = D.init_walkers(ctx, s.phi0, nw, seed)
     ost = O.init_state(s, nw, P, seed)
     est = torch.zeros(30, 2, dtype=torch.float64, device="cuda")
+    e_shift = 0.0
     for i in range(30):
-        D.step(ctx, st, seed, i, est[i], e_shift=0.0, n_sweep=1, n_qr=10)
-        ost, rec = O.step(s, ost, seed, i, run.dtau, n_taylor=10, n_sweep=1, n_qr=10)
+        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=1, n_qr=10)
+        ost, rec = O.step(s, ost, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
+                          e_shift=e_shift, proposal=prop, rw_step=rw, weight_mode=mode)
         torch.cuda.synchronize()
         g = host(est[i])
-        assert abs(g[0] / g[1] - rec["e_num"] / rec["e_den"]) <= TOL * abs(rec["e_num"] / rec["e_den"]), i
+        e_ref = rec["e_num"] / rec["e_den"]
+        assert abs(g[0] / g[1] - e_ref) <= TOL * max(abs(e_ref), 1.0), (i, g, e_ref)
         assert abs(g[1] - rec["e_den"]) <= TOL * rec["e_den"], i
-    assert np.abs(host(st.y) - ost.y).max() <= 4e-15 * max(np.abs(ost.y).max(), 1.0)
-    assert np.abs(host(st.w) - ost.w).max() <= TOL * np.abs(ost.w).max()
+        if i == 0 and mode == 3:
+            e_shift = e_ref
+    assert np.abs(host(st.y) - ost.y).max() <= 1e-12 * max(np.abs(ost.y).max(), 1.0)
+    gw = host(st.w)
+    assert np.array_equal(gw == 0.0, ost.w == 0.0)
+    assert np.abs(gw - ost.w).max() <= TOL * np.abs(ost.w).max()
 
 
 # plain BF16 products (8 significant bits) are reported, not held to the mixed bar

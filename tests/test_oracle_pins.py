@@ -282,6 +282,106 @@ def test_gaussian_random_walk_detailed_balance():
     assert np.all(np.abs(samp.mean(0) - mean_ref) < 5 * err), (samp.mean(0), mean_ref, err)
 
 
+def _quadrature_moments(s, phi, a, b, half=8.0, n=161):
+    """Mean and second moment per coordinate of the 2-D density
+    exp(a Re l(y; phi) - b |y|^2 / 2) on a grid, with their standard deviations."""
+    g = np.linspace(-half, half, n)
+    Y = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    lo = O.log_overlap(O.trial_det(s, Y[None]), phi)[0].real
+    dens = np.exp(a * (lo - lo.max()) - 0.5 * b * (Y * Y).sum(-1))
+    dens /= dens.sum()
+    m1 = (dens[:, None] * Y).sum(0)
+    m2 = (dens[:, None] * Y ** 2).sum(0)
+    m4 = (dens[:, None] * Y ** 4).sum(0)
+    return m1, m2, np.sqrt(m2 - m1 ** 2), np.sqrt(m4 - m2 ** 2)
+
+
+def test_gaussian_prior_proposal_detailed_balance():
+    """The independence sampler of App. B (Propagation, step 2; Sec. III.A,
+    leapfrog step 2): y' drawn from the prior N(0, 1), accepted with
+    min{1, |O(y')| / |O(y)|}, must leave p_T(y) |O(y; phi)| = N(y) |O(y; phi)|
+    of Eq. PDF-Y invariant.  On a K = 2 toy the chain's first and second
+    moments match 2-D quadrature of that density, and they are far from the
+    densities a plausible slip would sample instead: an extra prior ratio
+    N(y')/N(y) in alpha (density N^2 |O|), the inverted ratio (N / |O|), or
+    the squared ratio (N |O|^2)."""
+    s = ai.small_gaussian(M=6, N=2, n_chol=3, K=2, seed=4)
+    s.coupling = 1.5
+    rng = np.random.default_rng(2)
+    phi = ai.random_walkers(rng, s, 1, spread=1.5)
+    P = 128
+    y = rng.normal(size=(1, P, 2))
+    phiT = O.trial_det(s, y)
+    logov = O.log_overlap(phiT, phi)
+    acc, n_acc = [], 0
+    for st in range(300):
+        y, phiT, logov, _, nacc = O.metropolis(s, phi, y, phiT, logov, np.ones(1, complex),
+                                               np.ones(1), 5, st, 1,
+                                               proposal=O.PROPOSAL_PRIOR)
+        n_acc += int(nacc[0])
+        if st >= 30:
+            acc.append(y[0].copy())
+    samp = np.concatenate(acc)
+    assert 0.2 < n_acc / (300 * P) < 0.99          # the test exercises rejections
+    n_eff = len(samp) / 20                          # autocorrelation allowance of 20
+
+    def zscores(a, b):
+        m1, m2, sd1, sd2 = _quadrature_moments(s, phi, a, b)
+        z1 = (samp.mean(0) - m1) / (sd1 / math.sqrt(n_eff))
+        z2 = ((samp ** 2).mean(0) - m2) / (sd2 / math.sqrt(n_eff))
+        return np.abs(np.concatenate([z1, z2]))
+
+    assert zscores(1.0, 1.0).max() < 4.0, zscores(1.0, 1.0)
+    for a, b in ((1.0, 2.0), (-1.0, 1.0), (2.0, 1.0)):
+        assert zscores(a, b).max() > 5.0, (a, b, zscores(a, b))
+
+
+def test_handoff_half_plane_and_cosine_closed_forms():
+    """Hand-off projection (Sec. III.A, after Eq. AFQMC_Metro_constraint_cos;
+    App. B step 3): with the angle dtheta_T = arg sum_p S'_p - arg ref,
+    the cosine rule multiplies W by max(0, cos dtheta_T) and the half-plane
+    rule keeps W exactly when the new sign sum lies within pi/2 of the
+    reference.  Both are checked against the inner-product form
+    cos dtheta_T = Re(a conj(b)) / (|a| |b|) (a = sum S', b = ref), which holds
+    for any branch of arg, and on single-path cases whose answer is plain."""
+    pi = math.pi
+    # one path of phase theta against a reference of phase phi0 and modulus 2.5
+    cases = [(0.49 * pi, 0.0, True), (0.51 * pi, 0.0, False), (-0.51 * pi, 0.0, False),
+             (1.6 * pi, 0.0, True), (-1.6 * pi, 0.0, True), (pi, 0.0, False),
+             (0.9 * pi, -0.9 * pi, True), (0.2 * pi, 0.75 * pi, False), (0.0, 0.0, True)]
+    for th, ph, kept in cases:
+        logov = np.array([[0.3 + 1j * th]])
+        ref = np.array([2.5 * np.exp(1j * ph)])
+        w = np.array([1.7])
+        w_hp = O.handoff(w, logov, ref, O.WEIGHT_HALFPLANE)
+        w_cos = O.handoff(w, logov, ref, O.WEIGHT_SEPARATE)
+        assert w_hp[0] == (1.7 if kept else 0.0), (th, ph)
+        assert abs(w_cos[0] - 1.7 * max(0.0, math.cos(th - ph))) <= 1e-15, (th, ph)
+        assert (w_cos[0] > 0.0) == kept
+    # many walkers, P = 5 paths with one singular path, arbitrary phases
+    rng = np.random.default_rng(11)
+    nw, P = 400, 5
+    logov = rng.normal(size=(nw, P)) + 1j * rng.uniform(-8, 8, size=(nw, P))
+    logov[:, 2] = complex(-np.inf, 0.0)
+    ref = rng.normal(size=nw) + 1j * rng.normal(size=nw)
+    w = rng.uniform(0.5, 2.0, size=nw)
+    a = np.exp(1j * logov[:, [0, 1, 3, 4]].imag).sum(-1)
+    inner = (a * np.conj(ref)).real / (np.abs(a) * np.abs(ref))
+    w_hp = O.handoff(w, logov, ref, O.WEIGHT_HALFPLANE)
+    w_cos = O.handoff(w, logov, ref, O.WEIGHT_SEPARATE)
+    w_comb = O.handoff(w, logov, ref, O.WEIGHT_COMBINED)
+    assert np.array_equal(w_hp, np.where(inner > 0, w, 0.0))
+    assert np.abs(w_cos - w * np.maximum(inner, 0.0)).max() <= 1e-13
+    assert np.array_equal(w_comb, w_cos)           # the same projection, another reference
+    assert 100 < (w_hp > 0).sum() < 300            # both outcomes occur
+    # a walker whose new paths are all singular, or whose reference is 0, dies
+    logov[7] = complex(-np.inf, 0.0)
+    ref[9] = 0.0
+    for mode in (O.WEIGHT_HALFPLANE, O.WEIGHT_SEPARATE):
+        out = O.handoff(w, logov, ref, mode)
+        assert out[7] == 0.0 and out[9] == 0.0
+
+
 # -- Exactly solvable: zero-variance trial ----------------------------------
 
 def test_zero_variance_exact_trial():
