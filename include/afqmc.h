@@ -233,6 +233,25 @@ afqmc_status afqmc_force_bias(afqmc_ctx ctx, int32_t nw, const double* phiT, con
 afqmc_status afqmc_local_energy(afqmc_ctx ctx, int32_t nw, const double* phiT, const void* theta,
                                 const void* logov, void* eloc, void* e_sample, void* xbar);
 
+/* For callers that cannot allocate device memory -- code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the local
+ * energy of afqmc_local_energy (same arguments, same kernels, same results),
+ * with its per-path scratch -- vb [nw][P][n_chol] complex and, when e_sample
+ * is NULL, E_p [nw][P] complex -- in a fixed device array of
+ * AFQMC_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the workspace.  It needs no workspace,
+ * allocates nothing and records no numerical-event flags (those live in the
+ * workspace).  Returns AFQMC_E_SHAPE if its scratch, 16 nw P n_chol bytes plus
+ * 16 nw P without e_sample (each rounded up to 256), exceeds that size.  Every
+ * call on one GPU shares that GPU's array and leaves its contents behind (no
+ * entry needs to start at zero: the call writes each one it reads), so calls
+ * that overlap on one GPU -- two streams, two contexts, two threads -- race
+ * and must be ordered by the caller. */
+#define AFQMC_STATIC_SCRATCH_BYTES (64u << 20)
+afqmc_status afqmc_local_energy_static(afqmc_ctx ctx, int32_t nw, const double* phiT,
+                                       const void* theta, const void* logov, void* eloc,
+                                       void* e_sample, void* xbar);
+
 /* One walker move with the phaseless weight (Eqs. walker_prop,
  * importance_function, importance_function_CP; Eq. ratio-update-phi for the
  * overlap ratio; App. B step 1):

@@ -68,6 +68,8 @@ EXPORTS = {
     "afqmc_force_bias": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "afqmc_local_energy": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "afqmc_local_energy_static": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p]),
     "afqmc_propagate": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "afqmc_metropolis_x": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -315,6 +317,22 @@ def afqmc_local_energy(ctx, nw, phiT, theta, logov, eloc, e_sample=None, xbar=No
     c = ctx
     c.reserve(nw)
     c._call("afqmc_local_energy", nw, _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
+            _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
+            _ptr(logov, torch.complex128, nw * c.P, "logov"),
+            _ptr(eloc, torch.complex128, nw, "eloc"),
+            _ptr(e_sample, torch.complex128, nw * c.P, "e_sample", allow_none=True),
+            _ptr(xbar, torch.complex128, nw * c.G, "xbar", allow_none=True))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20   # AFQMC_STATIC_SCRATCH_BYTES
+
+
+def afqmc_local_energy_static(ctx, nw, phiT, theta, logov, eloc, e_sample=None, xbar=None):
+    """afqmc_local_energy with its scratch in the library's fixed per-GPU
+    array: no workspace is reserved and nothing is allocated."""
+    c = ctx
+    c._call("afqmc_local_energy_static", nw,
+            _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(eloc, torch.complex128, nw, "eloc"),

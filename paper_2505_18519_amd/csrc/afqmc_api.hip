@@ -5,12 +5,39 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "afqmc_internal.h"
 
+// Fixed per-GPU scratch of the entry point that allocates nothing
+// (afqmc_local_energy_static).  In host code this name is only a stand-in for
+// the symbol: every host use goes through the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[AFQMC_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The address of `device`'s scratch array, looked up once per device with that
+// device current (afqmc_create calls this after hipSetDevice(device)).
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 afqmc_status fail(afqmc_ctx_s* c, afqmc_status st, const std::string& msg) {
   if (c != nullptr) c->err = msg;
@@ -314,6 +341,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   c->xbar_cap = sys->xbar_cap;
 
   hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = scratch_address(device, &c->d_scratch);
   if (e != hipSuccess) {
     delete c;
     return AFQMC_E_DEVICE;
@@ -493,6 +521,25 @@ afqmc_status afqmc_green(afqmc_ctx c, int32_t nw, const void* phi, const double*
   return AFQMC_OK;
 }
 
+// The contraction kernel of the context's family and precision into per-path
+// vb and ep, then the walker-level combination.
+static hipError_t contraction_kernels(afqmc_ctx c, int32_t nw, const double* phiT,
+                                      const void* theta, const void* logov, void* xbar, double* vb,
+                                      void* eloc, double* ep, int* flags) {
+  const double* th = static_cast<const double*>(theta);
+  const double* lo = static_cast<const double*>(logov);
+  hipError_t e;
+  if (c->small && c->precision == AFQMC_PREC_FP64)
+    e = launch_contract(c, nw, phiT, th, lo, vb, ep);
+  else if (c->precision != AFQMC_PREC_FP64 && !c->ctrial)
+    e = launch_contract_sh(c, nw, phiT, th, lo, vb, ep);
+  else
+    e = launch_contract_g(c, nw, phiT, th, lo, vb, ep);
+  if (e != hipSuccess) return e;
+  return launch_combine(c, nw, vb, ep, lo, static_cast<double*>(xbar),
+                        static_cast<double*>(eloc), flags);
+}
+
 static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, const void* theta,
                                 const void* logov, void* xbar, void* vb_sample, void* eloc,
                                 void* e_sample) {
@@ -504,28 +551,11 @@ static afqmc_status contraction(afqmc_ctx c, int32_t nw, const double* phiT, con
   }
   double* vb = vb_sample ? static_cast<double*>(vb_sample) : ws_ptr<double>(c, L.vb);
   double* ep = e_sample ? static_cast<double*>(e_sample) : ws_ptr<double>(c, L.ep);
-  if (c->small && c->precision == AFQMC_PREC_FP64)
-    HIPCALL(c,
-            launch_contract(c, nw, phiT, static_cast<const double*>(theta),
-                            static_cast<const double*>(logov), vb, ep),
-            "contract");
-  else if (c->precision != AFQMC_PREC_FP64 && !c->ctrial)
-    HIPCALL(c,
-            launch_contract_sh(c, nw, phiT, static_cast<const double*>(theta),
-                               static_cast<const double*>(logov), vb, ep),
-            "contract");
-  else
-    HIPCALL(c,
-            launch_contract_g(c, nw, phiT, static_cast<const double*>(theta),
-                              static_cast<const double*>(logov), vb, ep),
-            "contract");
   hipError_t fe;
   int* flags = flag_words(c, nw, &fe);
   HIPCALL(c, fe, "flags");
-  HIPCALL(c,
-          launch_combine(c, nw, vb, ep, static_cast<const double*>(logov),
-                         static_cast<double*>(xbar), static_cast<double*>(eloc), flags),
-          "combine");
+  HIPCALL(c, contraction_kernels(c, nw, phiT, theta, logov, xbar, vb, eloc, ep, flags),
+          "contraction");
   return numeric_check_end(c, nw, flags);
 }
 
@@ -551,6 +581,34 @@ afqmc_status afqmc_local_energy(afqmc_ctx c, int32_t nw, const double* phiT, con
   REQUIRE(c, logov, "logov");
   REQUIRE(c, eloc, "eloc");
   return contraction(c, nw, phiT, theta, logov, xbar, nullptr, eloc, e_sample);
+}
+
+afqmc_status afqmc_local_energy_static(afqmc_ctx c, int32_t nw, const double* phiT,
+                                       const void* theta, const void* logov, void* eloc,
+                                       void* e_sample, void* xbar) {
+  CHECK_CTX(c);
+  CHECK_NW(c, nw);
+  if (nw == 0) return AFQMC_OK;
+  REQUIRE(c, phiT, "phiT");
+  REQUIRE(c, theta, "theta");
+  REQUIRE(c, logov, "logov");
+  REQUIRE(c, eloc, "eloc");
+  if (c->d_scratch == nullptr) return fail(c, AFQMC_E_DEVICE, "no scratch address for this device");
+  // vb [nw][P][G] complex, then (unless the caller takes E_p) ep [nw][P] complex
+  const size_t S = (size_t)nw * c->P;
+  const size_t vb_bytes = align256(S * c->G * 16);
+  const size_t need = vb_bytes + (e_sample ? 0 : align256(S * 16));
+  if (need > (size_t)AFQMC_STATIC_SCRATCH_BYTES)
+    return fail(c, AFQMC_E_SHAPE,
+                "afqmc_local_energy_static needs " + std::to_string(need) +
+                    " bytes of scratch for nw=" + std::to_string(nw) + ", more than the fixed " +
+                    std::to_string((size_t)AFQMC_STATIC_SCRATCH_BYTES));
+  unsigned char* base = static_cast<unsigned char*>(c->d_scratch);
+  double* vb = reinterpret_cast<double*>(base);
+  double* ep = e_sample ? static_cast<double*>(e_sample) : reinterpret_cast<double*>(base + vb_bytes);
+  HIPCALL(c, contraction_kernels(c, nw, phiT, theta, logov, xbar, vb, eloc, ep, nullptr),
+          "static contraction");
+  return AFQMC_OK;
 }
 
 afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* xi, const void* xbar,

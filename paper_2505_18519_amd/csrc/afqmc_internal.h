@@ -47,6 +47,8 @@ struct afqmc_ctx_s {
 
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device address of this GPU's fixed scratch array (afqmc_local_energy_static)
+  void* d_scratch = nullptr;
   std::string err;
   // numerical-event flags: one int32 per walker at the start of the workspace;
   // the first flags_clear of them are known to be zero (host bookkeeping)

@@ -85,3 +85,5 @@ def test_binding_constants_match_the_header():
                    re.findall(r"#define AFQMC_([A-Z0-9_]+) (0x[0-9a-fA-F]+|\d+)", text))
     for name in ("MLP_HIDDEN", "INIT_STEP", "MEASURE_STEP"):
         assert getattr(A, name) == defines[name], name
+    m = re.search(r"#define AFQMC_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and A.STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
