@@ -3,15 +3,18 @@
 
 One step = green -> Cholesky contraction (force bias + local energy) ->
 estimator -> fields -> propagate (V build, Taylor, ratio, weight) ->
-Metropolis sweep of every path with hand-off -> QR every 10 steps, for the
-FP64 workload M=64, N=16 per spin, 256 Cholesky vectors, K=64 Gaussian hidden
-variables, 512 walkers x 8 paths, tau=0.005.  Inputs are synthetic (seeded
-generator, see afqmc_inputs) and resident in HBM before the timed region.
+Metropolis sweep of every path with hand-off -> QR every 10 steps -> comb,
+for the FP64 workload M=64, N=16 per spin, 256 Cholesky vectors, K=64
+Gaussian hidden variables, 512 walkers x 8 paths, tau=0.005, random-walk
+proposal of step 0.3 (the FP64 random-walk form whose energy error fixes the
+reference error bar).  Inputs are synthetic (seeded generator, see
+afqmc_inputs) and resident in HBM before the timed region.
 
 Prints one JSON line.  The roofline object refers to the dominant kernel, the
 Cholesky contraction, timed with HIP events on the library's stream around
 every afqmc_local_energy call of the timed steps; cpu_baseline is the FP64
-numpy oracle on a bounded walker sample of the same workload.
+numpy oracle on a bounded walker sample of the same workload, run as
+independent walker chunks in parallel processes on the host's cores.
 """
 import argparse
 import json
@@ -32,6 +35,7 @@ PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix
 # name -> (workload index of afqmc_inputs.workload, contraction precision, peak, dtype label)
 WORKLOADS = {
     "fp64": (1, 0, PEAK_FP64_MFMA, "f64"),
+    "fp64-prior": (1, 0, PEAK_FP64_MFMA, "f64"),
     "mixed": (2, 1, PEAK_FP32_MFMA, "f32-contraction/f64"),
     "mixed-fp64": (2, 0, PEAK_FP64_MFMA, "f64"),
     # BF16 products: roofline against the dense BF16 peak with the algorithmic flops
@@ -47,7 +51,20 @@ WORKLOADS = {
 # kernel source is the one measured: workload -> (source file, sha256 prefix, bytes)
 TRAFFIC = {
     "fp64": ("k_contract.hip", "84a10461fe9f869b", 454528640),
+    "fp64-prior": ("k_contract.hip", "84a10461fe9f869b", 454528640),
 }
+
+# Proposal of each per-step workload: the default FP64 leg runs the random walk
+# of step 0.3 (the form the fixed energy error is defined on); "fp64-prior" the
+# paper's independence sampler from p_T.  Others keep their RunConfig's.
+RW_STEP_FP64 = 0.3
+PROPOSAL_OVERRIDE = {"fp64": (1, RW_STEP_FP64), "fp64-prior": (0, None)}
+
+# The departures of the synthetic inputs and run loop from the configurations
+# as written, stated beside every figure of the per-step workloads.
+L_SCALE = "0.3*sqrt(8/M)/sqrt(g+1)"
+L_SCALE_NOTE = ("the configurations write 0.3/sqrt(g+1); the extra sqrt(8/M) keeps the "
+                "two-body scale per orbital independent of M (exactly 1 at M = 8)")
 
 
 def measured_traffic(workload):
@@ -72,24 +89,64 @@ def contraction_flops(M, N, G, complex_trial=False):
     return G * (2 * N * M * M + 2 * (4 * M * N * N + 8 * N * N))
 
 
-def cpu_baseline(sys_, run, seed, n_walkers=48):
-    """Time the oracle's whole step on a bounded walker sample (1 BLAS thread)."""
+def _oracle_chunk(args):
+    """One host process of the CPU baseline: the oracle's whole steps on its own
+    walker chunk (one BLAS thread), one untimed step first.  Returns the time
+    of the timed steps."""
+    widx, n_walkers, seed, n_steps, proposal, rw_step, n_pc = args
     from threadpoolctl import threadpool_limits
+    import afqmc_inputs as ai
     from oracle import afqmc_oracle as O
+    sys_, run = ai.workload(widx)
     with threadpool_limits(limits=1):
         st = O.init_state(sys_, n_walkers, run.P, seed)
         Eh = O.half_kinetic(sys_, run.dtau)
         h1p = O.h1_eff(sys_)
+        kw = dict(n_taylor=run.n_taylor, n_sweep=run.n_sweep, n_qr=run.n_qr, Eh=Eh, h1p=h1p,
+                  proposal=proposal, rw_step=rw_step, n_pc=n_pc)
+        st, _ = O.step(sys_, st, seed, 0, run.dtau, **kw)
         t0 = time.perf_counter()
-        st, _ = O.step(sys_, st, seed, 0, run.dtau, n_taylor=run.n_taylor, n_sweep=run.n_sweep,
-                       n_qr=run.n_qr, Eh=Eh, h1p=h1p, xbar_cap=1.0, n_pc=1, w_cap=4.0)
-        dt = time.perf_counter() - t0
-    flops = n_walkers * run.P * contraction_flops(sys_.M, sys_.N, sys_.n_chol)
-    return {"value": n_walkers / dt, "unit": "walker-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_walkers} walkers x {run.P} paths, 1 whole step of the same workload "
-                      f"(numpy FP64/complex128, 1 thread), {dt:.1f} s",
+        for i in range(1, 1 + n_steps):
+            st, _ = O.step(sys_, st, seed, i, run.dtau, **kw)
+        return time.perf_counter() - t0
+
+
+def host_cores():
+    """CPU threads this process may use, at most 16 (one GPU's share of a box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(widx, seed, proposal, rw_step, n_pc, per_core=4, n_steps=2):
+    """Time the oracle's whole steps on a bounded walker sample: per_core
+    walkers (all paths) on each host core, as independent chunks in separate
+    processes (walkers are independent within a step; each chunk combs its own
+    walkers), one untimed step, then n_steps timed steps."""
+    import multiprocessing as mp
+    import afqmc_inputs as ai
+    sys_, run = ai.workload(widx)
+    cores = host_cores()
+    jobs = [(widx, per_core, seed + 7919 * c, n_steps, proposal, rw_step, n_pc)
+            for c in range(cores)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_chunk, jobs)
+    wall = time.perf_counter() - t0
+    dt = max(times)
+    n_walkers = per_core * cores
+    flops = n_walkers * n_steps * run.P * contraction_flops(sys_.M, sys_.N, sys_.n_chol)
+    return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n_walkers} walkers x {run.P} paths ({per_core} per process on {cores} "
+                      f"processes, one BLAS thread each), {n_steps} whole steps of the same "
+                      f"workload after one untimed step (numpy FP64/complex128); slowest "
+                      f"process {dt:.1f} s, {sum(times):.1f} s of CPU work, pool {wall:.1f} s",
             "gflops": flops / dt / 1e9,
-            "gflops_counts": "the contraction's algorithmic flops over the whole step's time"}
+            "gflops_counts": "the contraction's algorithmic flops over the whole steps' time"}
 
 
 def reblock(x):
@@ -450,6 +507,14 @@ def main():
     from paper_2505_18519_amd import afqmc as A
     from paper_2505_18519_amd import driver as D
 
+    # the CPU baseline runs first, in processes started before anything here
+    # touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "fp64" and not args.copy_calibration:
+        prop, rws = PROPOSAL_OVERRIDE["fp64"]
+        cpu = cpu_baseline(1, 2001, prop, rws, 1)
+        print(f"cpu baseline: {cpu['value']:.2f} walker-steps/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
     if not torch.cuda.is_available():
         print("no GPU: the HIP path cannot run", file=sys.stderr)
         sys.exit(1)
@@ -479,13 +544,17 @@ def main():
     widx, precision, peak, dtype = WORKLOADS[args.workload]
     sys_, run = ai.workload(widx)
     nw, P, seed = run.W, run.P, 2001
-    # production loop: force-bias modulus capped at 1 and comb population
-    # control every step with weights capped at 4x the mean (the sampled trial
-    # of this workload has a mean path sign near 0.2 after a few steps)
-    xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
+    proposal, rw_step = PROPOSAL_OVERRIDE.get(
+        args.workload, (run.proposal, run.rw_step if run.proposal == A.PROPOSAL_RW else None))
+    # population control: comb every step with the weights reset to 1 (a common
+    # factor of all weights, which cancels in the mixed estimator); the FP64
+    # legs use no force-bias or weight cap, the M = 128 and slices legs keep a
+    # force-bias modulus cap of 1 and a weight cap of 4x the mean (their
+    # path-sign averages fall within a few tens of steps)
+    capped = args.workload not in ("fp64", "fp64-prior")
+    xbar_cap, n_pc, w_cap = (1.0, 1, 4.0) if capped else (0.0, 1, 0.0)
     ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap,
-                    precision=precision, proposal=run.proposal,
-                    rw_step=run.rw_step if run.proposal == A.PROPOSAL_RW else None)
+                    precision=precision, proposal=proposal, rw_step=rw_step)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
 
@@ -536,10 +605,15 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"{wname}-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}",
+        "config": {"workload": f"{wname}-W{nw}-P{P}-dtau{run.dtau}-qr{run.n_qr}-"
+                               + (f"rw{rw_step}" if proposal == A.PROPOSAL_RW else "prior"),
                    "walkers": nw, "paths": P, "M": sys_.M, "N": sys_.N,
-                   "n_chol": sys_.n_chol, "K": sys_.K, "xbar_cap": xbar_cap,
-                   "comb_every": n_pc, "weight_cap": w_cap},
+                   "n_chol": sys_.n_chol, "K": sys_.K,
+                   "proposal": "random walk" if proposal == A.PROPOSAL_RW else "prior",
+                   "rw_step": rw_step if proposal == A.PROPOSAL_RW else None,
+                   "L_scale": L_SCALE, "L_scale_note": L_SCALE_NOTE,
+                   "xbar_cap": xbar_cap, "comb_every": n_pc, "comb_weights_reset_to": 1.0,
+                   "weight_cap": w_cap},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload),
@@ -553,8 +627,8 @@ def main():
         "energy_last": float(energies[-1]),
         "acceptance_last_step": float(st.nacc.sum().item()) / (nw * P * run.n_sweep),
     }
-    if not args.no_cpu_baseline and args.workload == "fp64":
-        out["cpu_baseline"] = cpu_baseline(sys_, run, seed)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -593,6 +593,29 @@ def test_non_finite_walkers_drop_out(tiny):
     assert w_bad[1] == 0.0 and w_bad[0] == w_ref[0] and w_bad[2] == w_ref[2]
 
 
+def test_force_bias_cap_keeps_phase_and_clips_modulus(tiny):
+    """The force-bias cap (a stabilisation outside the paper, off unless asked
+    for): each capped component is the uncapped one times a positive factor
+    <= 1, equal to it where |xbar_g| <= cap and of modulus exactly cap
+    elsewhere; the local energy is untouched."""
+    rng = np.random.default_rng(21)
+    phi = ai.random_walkers(rng, tiny, 5, spread=1.5)
+    y = ai.random_hidden(rng, tiny, 5, 6)
+    phiT = O.trial_det(tiny, y)
+    ell, theta = O.green(phiT, phi)
+    vb, ep = O.sample_contraction(tiny, phiT, theta, ell)
+    x0, e0 = O.walker_estimates(vb, ep, ell, 0.05)
+    cap = float(np.median(np.abs(x0)))
+    x1, e1 = O.walker_estimates(vb, ep, ell, 0.05, xbar_cap=cap)
+    assert np.array_equal(e0, e1)
+    big = np.abs(x0) > cap
+    assert 0 < big.sum() < big.size
+    assert np.array_equal(x1[~big], x0[~big])
+    ratio = x1[big] / x0[big]
+    assert np.abs(ratio.imag).max() <= 1e-15 and np.all((ratio.real > 0) & (ratio.real < 1))
+    assert np.abs(np.abs(x1[big]) - cap).max() <= 1e-15 * cap
+
+
 def test_comb_population_control_properties():
     """The comb keeps the total weight, gives walker k either floor or ceil of
     nw W_k / sum W copies, none to zero-weight walkers, and with a cap first
