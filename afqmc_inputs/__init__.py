@@ -197,7 +197,7 @@ def workload(idx: int):
     0: tiny Ising Jastrow (M=8, N=2, 16 vectors, K=4), 64 walkers x 8 samples
     1: FP64 (M=64, N=16, 256 vectors, K=64 Gaussian), 512 walkers x 8 samples
     2: mixed precision (M=128, N=32, 512 vectors, K=128), 1024 walkers x 4
-    3: 32 uneven systems (M in [24,128], N=M//4, 4M vectors, K=M//2)
+    3: 32 uneven systems (M in [24,160], N=M//4, 4M vectors, K=M//2)
     4: learned proposal (M=96, N=24, 384 vectors, K=128), 2048 walkers x 4
     5: multi-slice trial e^{-2 tau_T H} Phi_0 on the Hamiltonian of workload 1
        (m=2, tau_T=0.01, all 256 vectors as generators: K=512 Gaussian), 512 x 8
@@ -213,7 +213,7 @@ def workload(idx: int):
                 RunConfig(W=1024, P=4, dtau=0.005, n_steps=2000))
     if idx == 3:
         rng = np.random.default_rng(seed)
-        Ms = rng.integers(24, 129, size=32)      # the kernels take M <= 128
+        Ms = rng.integers(24, 161, size=32)
         Ws = np.rint(np.exp(rng.uniform(math.log(64), math.log(1024), size=32))).astype(int)
         systems, runs = [], []
         for s, (M, W) in enumerate(zip(Ms, Ws)):

@@ -404,11 +404,12 @@ def mixed_study(args):
 
 
 def uneven_study(args):
-    """Uneven batch (32 systems, M in [24, 128], N = M/4, 4M vectors, K = M/2,
+    """Uneven batch (32 systems, M in [24, 160], N = M/4, 4M vectors, K = M/2,
     walkers log-uniform in [64, 1024], 4 paths): aggregate walker-steps/s of the
     autotuned batch (replays of one captured graph with parallel branches)
     against the same systems stepped one after another through the per-system
-    calls on one stream."""
+    calls on one stream, and per-system agreement: a batch with the default
+    kernel families against each system alone, estimator sums step by step."""
     import torch
     import afqmc_inputs as ai
     from paper_2505_18519_amd import afqmc as A
@@ -428,37 +429,49 @@ def uneven_study(args):
     n_cycles = max(1, args.steps // b.cycle)
     b.run(1)
     torch.cuda.synchronize()
+    _, steps0 = b.estimates()
     t0 = time.perf_counter()
     b.run(n_cycles)
     sums, steps = b.estimates()
     dt = time.perf_counter() - t0
     n_steps = n_cycles * b.cycle
     fam, br, ms, nb = b.plan()
-    last = [(int(steps[i]) - 1) % b.history for i in range(b.n)]
-    energies = [float(sums[i, last[i], 0] / sums[i, last[i], 1]) for i in range(b.n)]
+    energies = []
+    for i in range(b.n):     # mean and spread of the per-step energies of the timed steps
+        idx = [t % b.history for t in range(int(steps0[i]), int(steps[i]))][-b.history:]
+        e = sums[i, idx, 0] / sums[i, idx, 1]
+        energies.append({"M": systems[i].M, "N": systems[i].N, "walkers": walkers[i],
+                         "energy": float(np.mean(e)),
+                         "energy_err": float(np.std(e, ddof=1) / np.sqrt(len(e)))})
     b.close()
     print(f"batch: {1e3 * dt / n_steps:.1f} ms/step", file=sys.stderr, flush=True)
 
-    # the same systems one after another on one stream, through the per-system calls
-    seq_steps = 2
-    ctxs, states = [], []
+    # agreement: a batch with each system's default kernel family (no tuner)
+    # and each system alone through the per-system calls, same seeds, 20 steps
+    n_check = 20
+    bv = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=4.0,
+                 max_branches=4, autotune=False, history=64)
+    bv.run(n_check // bv.cycle)
+    vsums, _ = bv.estimates()
+    bv.close()
+    agree, seq_ms = [], 0.0
     for i, (s, P, dtau, kw) in enumerate(specs):
         ctx = A.Context(s, P, dtau, max_walkers=walkers[i], **kw)
-        ctxs.append(ctx)
-        states.append(D.init_walkers(ctx, s.phi0, walkers[i], seed + i))
-    est = torch.zeros(2, dtype=torch.float64, device="cuda")
-    for i in range(len(specs)):      # warm
-        D.step(ctxs[i], states[i], seed + i, 0, est, n_pc=1, w_cap=4.0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for k in range(1, 1 + seq_steps):
-        for i in range(len(specs)):
-            D.step(ctxs[i], states[i], seed + i, k, est, n_pc=1, w_cap=4.0)
-    torch.cuda.synchronize()
-    dt_seq = (time.perf_counter() - t1) / seq_steps
-    for c in ctxs:
-        c.close()
-    print(f"sequential: {1e3 * dt_seq:.1f} ms/step", file=sys.stderr, flush=True)
+        st = D.init_walkers(ctx, s.phi0, walkers[i], seed + i)
+        est = torch.zeros(n_check, 2, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(n_check):
+            D.step(ctx, st, seed + i, k, est[k], n_pc=1, w_cap=4.0)
+        torch.cuda.synchronize()
+        seq_ms += 1e3 * (time.perf_counter() - t1) / n_check
+        ref = est.cpu().numpy()
+        got = vsums[i, :n_check]
+        scale = np.maximum(np.abs(ref), 1e-300)
+        agree.append(float(np.max(np.abs(got - ref) / scale)))
+        ctx.close()
+    print(f"sequential: {seq_ms:.1f} ms/step; per-system max relative difference of the "
+          f"estimator sums, batch vs alone: {max(agree):.1e}", file=sys.stderr, flush=True)
 
     step_s = dt / n_steps
     achieved = flops / step_s / 1e12
@@ -470,17 +483,24 @@ def uneven_study(args):
         "ms_per_step": 1e3 * step_s,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "uneven-32-systems-M24-128", "systems": len(specs),
+        "config": {"workload": "uneven-32-systems-M24-160", "systems": len(specs),
+                   "M_range": [min(s.M for s in systems), max(s.M for s in systems)],
                    "walkers": total_w, "paths": 4, "cycle_steps": b.cycle,
-                   "branches": nb, "families": [int(f) for f in fam]},
+                   "branches": nb, "families": [int(f) for f in fam],
+                   "L_scale": L_SCALE, "xbar_cap": 1.0, "comb_every": 1, "weight_cap": 4.0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
                      "kernel": "all systems' contractions per whole step (a lower bound on the "
                                "contraction kernels' rate: the step's other kernels are included)",
                      "flops_per_step": flops},
-        "sequential_ms_per_step": 1e3 * dt_seq,
-        "speedup_vs_sequential": dt_seq / step_s,
-        "energies_last_step": energies,
+        "sequential_ms_per_step": seq_ms,
+        "speedup_vs_sequential": seq_ms * 1e-3 / step_s,
+        "per_system_agreement": {
+            "what": f"max relative difference of the per-step estimator sums over {n_check} "
+                    "steps, batch (default kernel families) vs each system alone through the "
+                    "per-system calls; 0 = bit-identical",
+            "max": max(agree), "per_system": agree},
+        "per_system_energies": energies,
     }
     print(json.dumps(out))
 

@@ -137,9 +137,11 @@ typedef struct {
 /* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and
  * e^{-tau h1/2} there, and binds the context to `stream` (a hipStream_t, NULL
  * for the default stream).  Host arrays may be freed on return.
- * Supported sizes: 1 <= N <= M <= 128, N <= 32, n_chol >= 1, K >= 1,
- * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  The learned proposal
- * needs Gaussian hidden variables and K <= 128.  Real-trial systems with
+ * Supported sizes: 1 <= N <= M <= 160, N <= 40, n_chol >= 1, K >= 1,
+ * 1 <= P <= 64; other sizes return AFQMC_E_SHAPE.  Past M = 128 or N = 32
+ * only the FP64 contraction and the prior and random-walk proposals are
+ * built (AFQMC_E_UNSUPPORTED otherwise).  The learned proposal needs
+ * Gaussian hidden variables and K <= 128.  Real-trial systems with
  * M <= 64 and N <= 16 use register-resident kernels, larger ones (and every
  * multi-slice trial) workgroup-per-path kernels.  Multi-slice trials need
  * ceil(M/16) ceil(N/16) <= 8 (AFQMC_E_UNSUPPORTED otherwise), Gaussian hidden

@@ -280,8 +280,13 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   if (sys->h1 == nullptr || sys->L == nullptr || sys->phi0 == nullptr || sys->A == nullptr)
     return AFQMC_E_INVALID;
   const int M = sys->M, N = sys->N, G = sys->n_chol, K = sys->K, P = sys->P;
-  if (M < 1 || N < 1 || N > M || M > 128 || N > 32 || G < 1 || K < 1 || P < 1 || P > 64)
+  if (M < 1 || N < 1 || N > M || M > 160 || N > 40 || G < 1 || K < 1 || P < 1 || P > 64)
     return AFQMC_E_SHAPE;
+  // past M = 128 or N = 32 only the FP64 contraction and the non-learned
+  // proposals are built
+  const bool big = M > 128 || N > 32;
+  if (big && (sys->precision != AFQMC_PREC_FP64 || sys->proposal == AFQMC_PROPOSAL_LEARNED))
+    return AFQMC_E_UNSUPPORTED;
   if (sys->hidden_kind != AFQMC_HIDDEN_ISING && sys->hidden_kind != AFQMC_HIDDEN_GAUSS)
     return AFQMC_E_INVALID;
   if (sys->weight_mode < 0 || sys->weight_mode > 3) return AFQMC_E_INVALID;

@@ -498,6 +498,9 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
     AFQMC_G(5, 1) AFQMC_G(6, 1) AFQMC_G(7, 1) AFQMC_G(8, 1)
     AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)
     AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
+    AFQMC_G(9, 1) AFQMC_G(10, 1) AFQMC_G(9, 2) AFQMC_G(10, 2)
+    AFQMC_G(3, 3) AFQMC_G(4, 3) AFQMC_G(5, 3) AFQMC_G(6, 3)
+    AFQMC_G(7, 3) AFQMC_G(8, 3) AFQMC_G(9, 3) AFQMC_G(10, 3)
 #undef AFQMC_G
   }
   return hipErrorInvalidValue;

@@ -351,18 +351,18 @@ hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Re-orthonormalisation for larger systems (M <= 128, N <= 32): modified
-// Gram-Schmidt applied twice, one 128-thread workgroup per walker and spin,
-// thread = orbital row, the columns in LDS, inner products reduced across the
-// workgroup in LDS.
+// Re-orthonormalisation for larger systems (M <= 160, N <= 40): modified
+// Gram-Schmidt applied twice, one workgroup of QW wavefronts (64 QW >= M) per
+// walker and spin, thread = orbital row, the columns in LDS, inner products
+// reduced across the workgroup in LDS.
 namespace {
 
-constexpr int QRG_T = 128;
-
-__global__ void __launch_bounds__(QRG_T)
+template <int QW>
+__global__ void __launch_bounds__(64 * QW)
 k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict__ logshift) {
+  constexpr int QRG_T = 64 * QW;
   extern __shared__ double sq[];  // [M][N] complex
-  __shared__ double s_red[2][2];
+  __shared__ double s_red[QW][2];
   const int w = blockIdx.x, sp = blockIdx.y;
   const int m = threadIdx.x, wave = m >> 6, lane = m & 63;
   double* base = phi + ((size_t)(w * 2 + sp) * M) * N * 2;
@@ -376,8 +376,13 @@ k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict
       s_red[wave][1] = b;
     }
     __syncthreads();
-    a = s_red[0][0] + s_red[1][0];
-    b = s_red[0][1] + s_red[1][1];
+    a = 0.0;
+    b = 0.0;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      a += s_red[q][0];
+      b += s_red[q][1];
+    }
     __syncthreads();
   };
   double shift = 0.0;
@@ -417,16 +422,27 @@ __global__ void k_apply_shift(int nw, int P, const double* __restrict__ logshift
 
 }  // namespace
 
+namespace {
+
+template <int QW>
+hipError_t launch_qr_gw(const afqmc_ctx_s* c, int nw, double* phi, double* shift) {
+  const size_t lds = (size_t)c->M * c->N * 2 * sizeof(double);
+  auto kern = k_qr_g<QW>;
+  hipError_t e =
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nw, 2), dim3(64 * QW), lds, c->stream, nw, c->P, c->M, c->N, phi,
+                     shift);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_qr_g(const afqmc_ctx_s* c, int nw, double* phi, double* logov, double* shift) {
   if (nw <= 0) return hipSuccess;
-  if (c->M > QRG_T) return hipErrorInvalidValue;
-  const size_t lds = (size_t)c->M * c->N * 2 * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_qr_g, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  if (c->M > 192) return hipErrorInvalidValue;
+  hipError_t e = c->M <= 128 ? launch_qr_gw<2>(c, nw, phi, shift) : launch_qr_gw<3>(c, nw, phi, shift);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_qr_g, dim3(nw, 2), dim3(QRG_T), lds, c->stream, nw, c->P, c->M, c->N, phi,
-                     shift);
-  AFQMC_LAUNCH_CHECK();
   if (logov != nullptr) {
     const int n = nw * c->P;
     hipLaunchKernelGGL(k_apply_shift, dim3((n + 255) / 256), dim3(256), 0, c->stream, nw, c->P,

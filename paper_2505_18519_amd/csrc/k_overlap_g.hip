@@ -1,12 +1,12 @@
-// Overlap, log-determinant and Green's function for larger systems (N <= 32,
-// M <= 128); same quantities and conventions as k_overlap (Sec. III.A, Eqs.
+// Overlap, log-determinant and Green's function for larger systems (N <= 40,
+// M <= 160); same quantities and conventions as k_overlap (Sec. III.A, Eqs.
 // ratio-update-phi and sign-path).  One workgroup of two wavefronts per path,
 // wavefront s handling spin s:
 //  1. A^s = Phi_T^T phi^s on the FP64 matrix cores (NTC x NTC tiles of 16),
 //     operand loads clamped and bit-masked so that four k steps are in flight;
-//  2. LU with partial pivoting, one lane per row (N <= 32 lanes): the pivot
-//     (largest |a|^2, lowest row on ties) by DPP moves within the two 16-lane
-//     rows and one comparison of their results, the pivot row broadcast by
+//  2. LU with partial pivoting, one lane per row (N <= 40 lanes): the pivot
+//     (largest |a|^2, lowest row on ties) by DPP moves within each 16-lane
+//     row and a comparison of the rows' results, the pivot row broadcast by
 //     readlane (the pivot is uniform over the wavefront);
 //  3. optionally Theta^s = phi^s (A^s)^{-1}: lanes j < N solve the unit rows
 //     e_j X^s = e_j (A^s)^{-1} with the factors, X^s replaces the factors in
@@ -34,7 +34,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   __shared__ double s_lu[2][NT][NT + 1][2];
   __shared__ int s_perm[2][NT];
   __shared__ double s_res[2][3];
-  __shared__ double s_gd[128];  // M <= 128
+  __shared__ double s_gd[160];  // M <= 160
 
   const int s = blockIdx.x;
   const int sp = threadIdx.x >> 6;  // spin of this wavefront
@@ -139,12 +139,16 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       take(dpp_f64<0x4E>(v), dpp_i32<0x4E>(idx));
       take(dpp_f64<0x141>(v), dpp_i32<0x141>(idx));
       take(dpp_f64<0x140>(v), dpp_i32<0x140>(idx));
-      // rows 0 and 1 hold the N <= 32 matrix rows; lanes 32-63 are all used
+      // rows 0 .. NTC-1 hold the N <= 16 NTC matrix rows; the lanes past 16 NTC
+      // are all used
       const double v16 = readlane_f64(v, 16);
       const int i16 = __builtin_amdgcn_readlane(idx, 16);
+      const double v32 = NTC > 2 ? readlane_f64(v, 32) : -1.0;
+      const int i32 = NTC > 2 ? __builtin_amdgcn_readlane(idx, 32) : 1000;
       v = readlane_f64(v, 0);
       idx = __builtin_amdgcn_readlane(idx, 0);
       take(v16, i16);
+      if (NTC > 2) take(v32, i32);
       const int prow = idx;  // uniform over the wavefront
       perm[k] = prow;
       const cplx piv = cmk(readlane_f64(a[k].re, prow), readlane_f64(a[k].im, prow));
@@ -384,6 +388,7 @@ hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, con
   switch ((c->N + 15) / 16) {
     case 1: return launch_g<1>(c, nw, phi, phiT, logov, theta, gdiag);
     case 2: return launch_g<2>(c, nw, phi, phiT, logov, theta, gdiag);
+    case 3: return launch_g<3>(c, nw, phi, phiT, logov, theta, gdiag);
     default: return hipErrorInvalidValue;
   }
 }

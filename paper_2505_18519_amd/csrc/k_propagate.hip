@@ -341,18 +341,20 @@ hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const d
 }
 
 // ---------------------------------------------------------------------------
-// Taylor propagator for larger systems (M <= 128, N <= 32): one workgroup per
+// Taylor propagator for larger systems (M <= 160, N <= 40): one workgroup per
 // (walker, spin), one wavefront per 16-row tile; V rows as MFMA A operands in
 // registers (V_re and -V_im), the real one-body factors' operands read from L2
 // at their uses, the iterate in one LDS tile with two barriers per Horner
-// step.  The imaginary part is accumulated as V_re Y_im - (-V_im) Y_re.
+// step, and X (the start of the Horner recursion) in a second LDS tile, or in
+// registers (each wavefront its own rows) when two tiles exceed the LDS.  The
+// imaginary part is accumulated as V_re Y_im - (-V_im) Y_re.
 // Computes dst = El T_n(V) Er src per block (Er may be null: identity).  The
 // walker step has El = Er = e^{-tau h1/2}, src = dst, two spins; a trial slice
 // has one M x N block per path and src either the previous slice or, for the
 // first slice, Phi_0 read by every path (src_ws = 0).
 namespace {
 
-template <int KTMAX, int NTC>
+template <int KTMAX, int NTC, bool XR>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restrict__ vmat,
            const double* __restrict__ El, const double* __restrict__ Er,
@@ -360,7 +362,7 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
   constexpr int NT = 16 * NTC;
   extern __shared__ double smem[];
   double* sY = smem;                 // [MT][NT][2] iterate
-  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = Er src
+  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = Er src (unless XR)
   const int KT = MT / 16;
   const int w = blockIdx.x, sp = blockIdx.y;
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -422,13 +424,24 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
         d[1] = o[ct][1][r];
       }
   };
+  // X = Er src: a second LDS tile, or (XR, when two tiles do not fit in LDS)
+  // registers, each wavefront holding its own rows in the accumulator layout
+  dx4 x[NTC][2];
   if (Er != nullptr) {
-    dx4 x[NTC][2];
     apply_eh(Er, x);
     __syncthreads();
     store(sY, x);
-    store(sX, x);
+    if (!XR) store(sX, x);
     __syncthreads();
+  } else if (XR) {
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* d = sY + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+        x[ct][0][r] = d[0];
+        x[ct][1][r] = d[1];
+      }
   } else {
     for (int q = threadIdx.x; q < 2 * MT * NT; q += blockDim.x) sX[q] = sY[q];
     __syncthreads();
@@ -457,9 +470,17 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double* xv = sX + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
-        y[ct][0][r] = xv[0] + are[ct][r] * invj;
-        y[ct][1][r] = xv[1] + (aim1[ct][r] - aim2[ct][r]) * invj;
+        double xr_, xi_;
+        if (XR) {
+          xr_ = x[ct][0][r];
+          xi_ = x[ct][1][r];
+        } else {
+          const double* xv = sX + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+          xr_ = xv[0];
+          xi_ = xv[1];
+        }
+        y[ct][0][r] = xr_ + are[ct][r] * invj;
+        y[ct][1][r] = xi_ + (aim1[ct][r] - aim2[ct][r]) * invj;
       }
     __syncthreads();
     store(sY, y);
@@ -480,12 +501,16 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     }
 }
 
+constexpr size_t kMaxLds = 160 * 1024;
+
 template <int KTMAX, int NTC>
 hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
                               const double* vmat, const double* El, const double* Er,
                               const double* src, int src_ws, double* dst) {
-  const size_t lds = (size_t)2 * c->MT * 16 * NTC * 2 * sizeof(double);
-  auto kern = k_taylor_g<KTMAX, NTC>;
+  const size_t tile = (size_t)c->MT * 16 * NTC * 2 * sizeof(double);
+  const bool xr = 2 * tile > kMaxLds;
+  const size_t lds = xr ? tile : 2 * tile;
+  auto kern = xr ? k_taylor_g<KTMAX, NTC, true> : k_taylor_g<KTMAX, NTC, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -504,8 +529,9 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
 #define AFQMC_P(KM, NC)                                                                  \
   if (KT <= KM && NTC == NC)                                                             \
     return launch_taylor_g_kt<KM, NC>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
-  AFQMC_P(4, 1) AFQMC_P(6, 1) AFQMC_P(8, 1)
-  AFQMC_P(4, 2) AFQMC_P(6, 2) AFQMC_P(8, 2)
+  AFQMC_P(4, 1) AFQMC_P(6, 1) AFQMC_P(8, 1) AFQMC_P(10, 1)
+  AFQMC_P(4, 2) AFQMC_P(6, 2) AFQMC_P(8, 2) AFQMC_P(10, 2)
+  AFQMC_P(4, 3) AFQMC_P(6, 3) AFQMC_P(8, 3) AFQMC_P(10, 3)
 #undef AFQMC_P
   return hipErrorInvalidValue;
 }

@@ -234,7 +234,7 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Larger systems (M <= 128, N <= 32): one workgroup per path, one wavefront per
+// Larger systems (M <= 160, N <= 40): one workgroup per path, one wavefront per
 // 16-row tile of U (its rows held as MFMA A operands); the Taylor iterate is
 // shared through a double-buffered LDS tile, one barrier per term.
 namespace {
@@ -406,8 +406,9 @@ hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const doubl
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
 #define AFQMC_T(KM, NC) \
   if (KT <= KM && NTC == NC) return launch_tg<KM, NC>(c, n_samples, ubuf, phiT);
-  AFQMC_T(4, 1) AFQMC_T(6, 1) AFQMC_T(8, 1)
-  AFQMC_T(4, 2) AFQMC_T(6, 2) AFQMC_T(8, 2)
+  AFQMC_T(4, 1) AFQMC_T(6, 1) AFQMC_T(8, 1) AFQMC_T(10, 1)
+  AFQMC_T(4, 2) AFQMC_T(6, 2) AFQMC_T(8, 2) AFQMC_T(10, 2)
+  AFQMC_T(4, 3) AFQMC_T(6, 3) AFQMC_T(8, 3) AFQMC_T(10, 3)
 #undef AFQMC_T
   return hipErrorInvalidValue;
 }

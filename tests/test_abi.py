@@ -46,8 +46,8 @@ def test_host_side_validation(lib):
     h = np.zeros((2, 2))
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     s = A.afqmc_system(200, 4, 8, 4, 2, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 0)
-    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2   # M > 128
-    for M, N, P in ((64, 33, 2), (8, 9, 2), (0, 1, 2), (8, 2, 65), (8, 2, 0)):  # N > 32, N > M, ...
+    assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2   # M > 160
+    for M, N, P in ((64, 41, 2), (8, 9, 2), (0, 1, 2), (8, 2, 65), (8, 2, 0)):  # N > 40, N > M, ...
         s = A.afqmc_system(M, N, 8, 4, P, 1, 0.1, dp(h), dp(h), dp(h), dp(h), 0.01, 10, 0, 0, 0.5, 0)
         assert lib.afqmc_create(ctypes.byref(s), 0, None, ctypes.byref(out)) == 2, (M, N, P)
         assert not out.value

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import afqmc_inputs as ai
+from oracle import afqmc_oracle as O
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -112,3 +113,50 @@ def test_autotuned_batch_runs_and_reports_its_plan():
     assert np.all(np.isfinite(den)) and np.all(den >= 0) and (den > 0).sum() >= b.n - 1
     assert np.all(np.isfinite(num[den > 0] / den[den > 0]))
     b.close()
+
+
+ORACLE_SYSTEMS = [
+    # (system, P, walkers, proposal): an uneven set that spans both kernel
+    # families, Ising and Gaussian hidden variables, the prior and the random
+    # walk, and a system past M = 128 and N = 32 (nine row tiles, three column
+    # tiles), as the uneven batches of M in [24, 160] hold
+    (lambda: ai.tiny_ising(), 4, 6, 0),
+    (lambda: ai.small_gaussian(M=24, N=6, n_chol=12, K=12, seed=81), 3, 5, 1),
+    (lambda: ai.small_gaussian(M=70, N=17, n_chol=20, K=16, seed=82), 2, 4, 0),
+    (lambda: ai.small_gaussian(M=136, N=34, n_chol=16, K=24, seed=83), 2, 3, 1),
+]
+
+
+def test_batch_matches_the_oracle_step_for_step():
+    """Each system of a batch (graph replays on two branches) against the
+    oracle's whole steps from the same seed: the estimator sums of Eq.
+    mixed_estimator at every one of 20 steps to 1e-9 relative (the comb, QR
+    every 10 steps and the hand-off included), which also fixes the weights,
+    since every comb draws its parents from them."""
+    from paper_2505_18519_amd import afqmc as A
+    specs, walkers = [], []
+    for mk, P, nw, prop in ORACLE_SYSTEMS:
+        s = mk()
+        kw = dict(xbar_cap=XCAP)
+        if prop == 1:
+            kw.update(proposal=A.PROPOSAL_RW, rw_step=0.3)
+        specs.append((s, P, DTAU, kw))
+        walkers.append(nw)
+    b = A.Batch(specs, walkers, seed=SEED, n_sweep=1, n_qr=10, n_pc=1, w_cap=WCAP,
+                max_branches=2, autotune=False, history=64)
+    b.run(2)
+    sums, steps = b.estimates()
+    b.close()
+    assert np.all(steps == 20)
+    for i, ((s, P, _, kw), nw) in enumerate(zip(specs, walkers)):
+        _say("oracle batch system", s.name, "P", P, "walkers", nw)
+        prop = ORACLE_SYSTEMS[i][3]
+        st = O.init_state(s, nw, P, SEED + i)
+        for t in range(20):
+            st, rec = O.step(s, st, SEED + i, t, DTAU, n_taylor=10, n_sweep=1, n_qr=10,
+                             proposal=prop, rw_step=0.3, xbar_cap=XCAP, n_pc=1, w_cap=WCAP,
+                             normalize=True)
+            num, den = sums[i, t]
+            assert abs(den - rec["e_den"]) <= 1e-9 * rec["e_den"], (s.name, t)
+            assert abs(num - rec["e_num"]) <= 1e-9 * max(abs(rec["e_num"]), rec["e_den"]), \
+                (s.name, t, num, rec["e_num"])

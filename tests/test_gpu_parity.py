@@ -67,6 +67,11 @@ CASES = {
     "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
     "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
     "gauss-M128-N32": (lambda: ai.small_gaussian(M=128, N=32, n_chol=32, K=32, seed=9), 2, 2),
+    # past M = 128 and N = 32 (the uneven batches' largest systems): nine and ten
+    # row tiles, three column tiles, ragged
+    "gauss-M136-N34": (lambda: ai.small_gaussian(M=136, N=34, n_chol=24, K=40, seed=16), 2, 2),
+    "gauss-M150-N20": (lambda: ai.small_gaussian(M=150, N=20, n_chol=20, K=24, seed=17), 3, 2),
+    "gauss-M160-N40": (lambda: ai.small_gaussian(M=160, N=40, n_chol=24, K=40, seed=18), 2, 2),
 }
 
 
@@ -538,6 +543,19 @@ def test_mixed_precision_contraction(case, prec):
         assert e <= bound
     # the reduced-precision products are really in use (FP64 would agree to ~1e-14)
     assert max(e_ep, e_xb) > 1e-10
+
+
+def test_large_systems_take_the_fp64_contraction_and_plain_proposals():
+    """Past M = 128 or N = 32 only the FP64 contraction and the prior and
+    random-walk proposals are built; the rest is refused, not run."""
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=136, N=34, n_chol=4, K=8, seed=16)
+    A.Context(s, 2, 0.01, proposal=A.PROPOSAL_RW).close()
+    for kw in (dict(precision=A.PREC_FP32), dict(precision=A.PREC_BF16X3),
+               dict(proposal=A.PROPOSAL_LEARNED)):
+        with pytest.raises(A.AfqmcError) as ei:
+            A.Context(s, 2, 0.01, **kw)
+        assert ei.value.status == 6, kw
 
 
 def test_bf16_contraction_needs_real_trials():

@@ -70,6 +70,9 @@ def test_uneven_batch_recipe():
     systems, runs = ai.workload(3)
     assert len(systems) == len(runs) == 32
     for s, r in zip(systems, runs):
-        assert 24 <= s.M <= 128 and s.N == s.M // 4
+        assert 24 <= s.M <= 160 and s.N == s.M // 4
         assert s.n_chol == 4 * s.M and s.K == s.M // 2
         assert 64 <= r.W <= 1024 and r.P == 4
+    # the draw spans the configured range: systems past M = 128 and N = 32 occur
+    assert max(s.M for s in systems) > 150 and min(s.M for s in systems) < 30
+    assert any(s.N > 32 for s in systems)
