@@ -63,6 +63,37 @@ __device__ __forceinline__ dx4 dx4_zero() {
   return z;
 }
 
+// FP32 matrix core, v_mfma_f32_16x16x4f32: the same operand lanes as the FP64
+// product (A[c][g], B[g][c]) but D[4 g + r][c] in element r.  MM<T> gives both
+// forms one interface: a product over m visited as k-steps (t, r) with
+// m = 16 t + MM<T>::row(g, r) takes the accumulator of tile t, element r,
+// directly as its next operand, in either precision.
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MM;
+template <>
+struct MM<double> {
+  typedef dx4 acc_t;
+  __device__ __forceinline__ static acc_t zero() { return dx4_zero(); }
+  __device__ __forceinline__ static acc_t fma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct MM<float> {
+  typedef fx4 acc_t;
+  __device__ __forceinline__ static acc_t zero() {
+    fx4 z = {0.f, 0.f, 0.f, 0.f};
+    return z;
+  }
+  __device__ __forceinline__ static acc_t fma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+};
+
 // ---------------------------------------------------------------------------
 // wave-wide reductions (64 lanes)
 

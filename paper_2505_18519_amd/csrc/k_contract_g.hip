@@ -34,7 +34,6 @@
 
 namespace {
 
-typedef float fx4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct mm;

@@ -31,7 +31,6 @@
 
 namespace {
 
-typedef float fx4 __attribute__((ext_vector_type(4)));
 typedef short sx4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest even (NaN kept quiet)

@@ -38,7 +38,6 @@ constexpr int H = AFQMC_MLP_HIDDEN;
 constexpr int HT = H / 16;
 constexpr float LVMAX = 4.0f;
 
-typedef float fx4 __attribute__((ext_vector_type(4)));
 typedef short sx4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16_t;
 

@@ -25,22 +25,26 @@ namespace {
 // trial slices use this with the generators A_k and their block of y, the
 // back-propagation with a walker's recorded fields.  XB = false (no xbar):
 // Q = 0 and only the R products run.
+// With T = float (mixed-precision contexts with real trials) the products run
+// on v_mfma_f32_16x16x4f32: c and L rounded to FP32, FP32 accumulation over g.
 constexpr int VB_WT = 2;  // walker tiles per wavefront
 constexpr int VB_ET = 2;  // entry tiles per wavefront
-template <bool XB>
+template <typename T, bool XB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
+  typedef ::MM<T> mm;  // (the parameter MM is the number of matrix entries)
+  typedef typename mm::acc_t acc_t;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const int w0 = (blockIdx.y * 4 + wave) * 16 * VB_WT;
   const int e0 = blockIdx.x * 16 * VB_ET;
   if (w0 >= nw) return;
-  dx4 ar[VB_WT][VB_ET], ai[VB_WT][VB_ET];
+  acc_t ar[VB_WT][VB_ET], ai[VB_WT][VB_ET];
 #pragma unroll
   for (int wt = 0; wt < VB_WT; ++wt)
 #pragma unroll
-    for (int et = 0; et < VB_ET; ++et) ar[wt][et] = ai[wt][et] = dx4_zero();
+    for (int et = 0; et < VB_ET; ++et) ar[wt][et] = ai[wt][et] = mm::zero();
   int wa[VB_WT];
   bool wok[VB_WT];
 #pragma unroll
@@ -59,7 +63,7 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
   // batches of KB k-steps, double-buffered: the loads of batch i+1 (clamped
   // in range, masked after the load) are issued before the MFMAs of batch i
   constexpr int KB = 4;
-  double cr[2][KB][VB_WT], ci[2][KB][VB_WT], b[2][KB][VB_ET];
+  T cr[2][KB][VB_WT], ci[2][KB][VB_WT], b[2][KB][VB_ET];
   auto load = [&](int k0, int buf) {
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
@@ -71,13 +75,13 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
         const double x = xi[(size_t)wa[wt] * xs + kc];
         const double br = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2] : 0.0;
         const double bi = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2 + 1] : 0.0;
-        cr[buf][q][wt] = keep_if(x - br, ok);
-        ci[buf][q][wt] = keep_if(-bi, ok);
+        cr[buf][q][wt] = (T)keep_if(x - br, ok);
+        ci[buf][q][wt] = (T)keep_if(-bi, ok);
       }
 #pragma unroll
       for (int et = 0; et < VB_ET; ++et) {
         const double v = L[(size_t)kc * MM + ec[et]];
-        b[buf][q][et] = keep_if(v, k < G && eok[et]);
+        b[buf][q][et] = (T)keep_if(v, k < G && eok[et]);
       }
     }
   };
@@ -88,8 +92,8 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
       for (int wt = 0; wt < VB_WT; ++wt)
 #pragma unroll
         for (int et = 0; et < VB_ET; ++et) {
-          ar[wt][et] = mfma_f64(cr[buf][q][wt], b[buf][q][et], ar[wt][et]);
-          if (XB) ai[wt][et] = mfma_f64(ci[buf][q][wt], b[buf][q][et], ai[wt][et]);
+          ar[wt][et] = mm::fma(cr[buf][q][wt], b[buf][q][et], ar[wt][et]);
+          if (XB) ai[wt][et] = mm::fma(ci[buf][q][wt], b[buf][q][et], ai[wt][et]);
         }
   };
   load(0, 0);
@@ -106,11 +110,11 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
     for (int et = 0; et < VB_ET; ++et)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int w = w0 + 16 * wt + g + 4 * r, e = e0 + 16 * et + c;
+        const int w = w0 + 16 * wt + mm::row(g, r), e = e0 + 16 * et + c;
         if (w < nw && e < MM) {
           double* o = vmat + ((size_t)w * MM + e) * 2;
-          o[0] = -sqrt_tau * ai[wt][et][r];
-          o[1] = sqrt_tau * ar[wt][et][r];
+          o[0] = -sqrt_tau * (double)ai[wt][et][r];
+          o[1] = sqrt_tau * (double)ar[wt][et][r];
         }
       }
 }
@@ -121,13 +125,17 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
 // of V (and of e^{-tau h1/2}) in registers as FP64-MFMA A operands; the
 // iterate Y is shared through a double-buffered LDS tile.  Horner form:
 // Y = X; for j = n..1: Y = X + V Y / j.
-template <int MT>
+// T = float (mixed-precision contexts with real trials): V, E_h and the
+// iterate rounded to FP32, v_mfma_f32_16x16x4f32 products.
+template <typename T, int MT>
 __global__ void __launch_bounds__(MT * 4)
 k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
          const double* __restrict__ Eh, double* __restrict__ phi) {
+  typedef MM<T> mm;
+  typedef typename mm::acc_t acc_t;
   constexpr int NTILE = MT / 16;
   constexpr int NC = 32;  // 2 spins x 16 columns
-  __shared__ double s_y[2][MT][NC][2];
+  __shared__ T s_y[2][MT][NC][2];
 
   const int w = blockIdx.x;
   const int wave = threadIdx.x >> 6;  // my row tile
@@ -136,18 +144,18 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
   const double* V = vmat + (size_t)w * M * M * 2;
   double* ph = phi + (size_t)w * 2 * M * N * 2;
 
-  // A operands: rows 16 wave + c, columns 16t + 4r + g (V, E_h symmetric)
-  double vr[NTILE][4], vi[NTILE][4], nvi[NTILE][4], eh[NTILE][4];
+  // A operands: rows 16 wave + c, columns 16t + k(g, r) (V, E_h symmetric)
+  T vr[NTILE][4], vi[NTILE][4], nvi[NTILE][4], eh[NTILE][4];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * r + g, col = 16 * wave + c;
+      const int row = 16 * t + mm::row(g, r), col = 16 * wave + c;
       const bool ok = row < M && col < M;
-      vr[t][r] = ok ? V[((size_t)row * M + col) * 2] : 0.0;
-      vi[t][r] = ok ? V[((size_t)row * M + col) * 2 + 1] : 0.0;
+      vr[t][r] = (T)(ok ? V[((size_t)row * M + col) * 2] : 0.0);
+      vi[t][r] = (T)(ok ? V[((size_t)row * M + col) * 2 + 1] : 0.0);
       nvi[t][r] = -vi[t][r];
-      eh[t][r] = ok ? Eh[row * M + col] : 0.0;
+      eh[t][r] = (T)(ok ? Eh[row * M + col] : 0.0);
     }
   // phi -> LDS buffer 0 (columns: spin * 16 + n)
   for (int q = threadIdx.x; q < MT * NC; q += MT * 4) {
@@ -158,60 +166,60 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
       re = src[0];
       im = src[1];
     }
-    s_y[0][m][col][0] = re;
-    s_y[0][m][col][1] = im;
+    s_y[0][m][col][0] = (T)re;
+    s_y[0][m][col][1] = (T)im;
   }
   __syncthreads();
 
   // real-symmetric product with eh: out rows of this tile from buffer `src`
-  auto apply_eh = [&](int src, dx4 (&o)[2][2]) {
+  auto apply_eh = [&](int src, acc_t (&o)[2][2]) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) o[ct][0] = o[ct][1] = dx4_zero();
+    for (int ct = 0; ct < 2; ++ct) o[ct][0] = o[ct][1] = mm::zero();
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const double* yb = s_y[src][16 * t + 4 * r + g][16 * ct + c];
-          o[ct][0] = mfma_f64(eh[t][r], yb[0], o[ct][0]);
-          o[ct][1] = mfma_f64(eh[t][r], yb[1], o[ct][1]);
+          const T* yb = s_y[src][16 * t + mm::row(g, r)][16 * ct + c];
+          o[ct][0] = mm::fma(eh[t][r], yb[0], o[ct][0]);
+          o[ct][1] = mm::fma(eh[t][r], yb[1], o[ct][1]);
         }
   };
-  auto store_rows = [&](int dst, const dx4 (&o)[2][2]) {
+  auto store_rows = [&](int dst, const acc_t (&o)[2][2]) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        s_y[dst][16 * wave + 4 * r + g][16 * ct + c][0] = o[ct][0][r];
-        s_y[dst][16 * wave + 4 * r + g][16 * ct + c][1] = o[ct][1][r];
+        s_y[dst][16 * wave + mm::row(g, r)][16 * ct + c][0] = o[ct][0][r];
+        s_y[dst][16 * wave + mm::row(g, r)][16 * ct + c][1] = o[ct][1][r];
       }
   };
 
   // X = E_h phi (kept in registers, rows of this tile) -> buffer 1
-  dx4 x[2][2];
+  acc_t x[2][2];
   apply_eh(0, x);
   store_rows(1, x);
   __syncthreads();
   int cur = 1;
   for (int j = n_taylor; j >= 1; --j) {
-    dx4 acc[2][2];
+    acc_t acc[2][2];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) acc[ct][0] = acc[ct][1] = dx4_zero();
+    for (int ct = 0; ct < 2; ++ct) acc[ct][0] = acc[ct][1] = mm::zero();
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const double* yb = s_y[cur][16 * t + 4 * r + g][16 * ct + c];
-          const double yr = yb[0], yi = yb[1];
-          acc[ct][0] = mfma_f64(vr[t][r], yr, acc[ct][0]);
-          acc[ct][0] = mfma_f64(nvi[t][r], yi, acc[ct][0]);
-          acc[ct][1] = mfma_f64(vr[t][r], yi, acc[ct][1]);
-          acc[ct][1] = mfma_f64(vi[t][r], yr, acc[ct][1]);
+          const T* yb = s_y[cur][16 * t + mm::row(g, r)][16 * ct + c];
+          const T yr = yb[0], yi = yb[1];
+          acc[ct][0] = mm::fma(vr[t][r], yr, acc[ct][0]);
+          acc[ct][0] = mm::fma(nvi[t][r], yi, acc[ct][0]);
+          acc[ct][1] = mm::fma(vr[t][r], yi, acc[ct][1]);
+          acc[ct][1] = mm::fma(vi[t][r], yr, acc[ct][1]);
         }
-    const double invj = 1.0 / (double)j;
+    const T invj = (T)(1.0 / (double)j);
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -223,17 +231,17 @@ k_taylor(int M, int N, int n_taylor, const double* __restrict__ vmat,
     cur ^= 1;
   }
   // phi' = E_h Y
-  dx4 o[2][2];
+  acc_t o[2][2];
   apply_eh(cur, o);
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * wave + 4 * r + g;
+      const int m = 16 * wave + mm::row(g, r);
       if (m < M && c < N) {
         double* d = ph + ((size_t)(ct * M + m) * N + c) * 2;
-        d[0] = o[ct][0][r];
-        d[1] = o[ct][1][r];
+        d[0] = (double)o[ct][0][r];
+        d[1] = (double)o[ct][1][r];
       }
     }
 }
@@ -300,10 +308,17 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
   ref[(size_t)wk * 2 + 1] = rf.im;
 }
 
+// reduced-precision walker propagation: mixed-precision contexts with real trials
+bool prop_f32(const afqmc_ctx_s* c) { return c->precision != AFQMC_PREC_FP64 && !c->ctrial; }
+
 template <int MT>
 hipError_t launch_taylor_mt(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
-  hipLaunchKernelGGL(k_taylor<MT>, dim3(nw), dim3(MT * 4), 0, c->stream, c->M, c->N, c->n_taylor,
-                     vmat, c->d_Eh, phi);
+  if (prop_f32(c))
+    hipLaunchKernelGGL((k_taylor<float, MT>), dim3(nw), dim3(MT * 4), 0, c->stream, c->M, c->N,
+                       c->n_taylor, vmat, c->d_Eh, phi);
+  else
+    hipLaunchKernelGGL((k_taylor<double, MT>), dim3(nw), dim3(MT * 4), 0, c->stream, c->M, c->N,
+                       c->n_taylor, vmat, c->d_Eh, phi);
   return hipGetLastError();
 }
 
@@ -315,8 +330,12 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
   const int MM = c->M * c->M;
   dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (nw + 64 * VB_WT - 1) / (64 * VB_WT)),
       block(256);
-  hipLaunchKernelGGL(k_vbuild<true>, grid, block, 0, c->stream, nw, c->G, MM, c->G, c->G,
-                     sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
+  if (prop_f32(c))
+    hipLaunchKernelGGL((k_vbuild<float, true>), grid, block, 0, c->stream, nw, c->G, MM, c->G,
+                       c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
+  else
+    hipLaunchKernelGGL((k_vbuild<double, true>), grid, block, 0, c->stream, nw, c->G, MM, c->G,
+                       c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
   return hipGetLastError();
 }
 
@@ -354,15 +373,17 @@ hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const d
 // first slice, Phi_0 read by every path (src_ws = 0).
 namespace {
 
-template <int KTMAX, int NTC, bool XR>
+template <typename T, int KTMAX, int NTC, bool XR>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restrict__ vmat,
            const double* __restrict__ El, const double* __restrict__ Er,
            const double* src, int src_ws, double* dst) {
+  typedef MM<T> mm;
+  typedef typename mm::acc_t acc_t;
   constexpr int NT = 16 * NTC;
   extern __shared__ double smem[];
-  double* sY = smem;                 // [MT][NT][2] iterate
-  double* sX = smem + MT * NT * 2;   // [MT][NT][2] X = Er src (unless XR)
+  T* sY = reinterpret_cast<T*>(smem);  // [MT][NT][2] iterate
+  T* sX = sY + MT * NT * 2;            // [MT][NT][2] X = Er src (unless XR)
   const int KT = MT / 16;
   const int w = blockIdx.x, sp = blockIdx.y;
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -371,62 +392,62 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
   const double* in = src + ((size_t)w * src_ws + sp) * M * N * 2;
   double* ph = dst + ((size_t)w * spins + sp) * M * N * 2;
 
-  double vr[KTMAX][4], nvi[KTMAX][4];
+  T vr[KTMAX][4], nvi[KTMAX][4];
 #pragma unroll
   for (int t = 0; t < KTMAX; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
+      const int row = 16 * t + mm::row(g, r), col = 16 * tp + c;
       const bool ok = t < KT && row < M && col < M;
       // clamped, unconditional loads masked afterwards: all in flight together
       const double2 v = *reinterpret_cast<const double2*>(
           V + ((size_t)min(row, M - 1) * M + min(col, M - 1)) * 2);
-      vr[t][r] = keep_if(v.x, ok);
-      nvi[t][r] = keep_if(-v.y, ok);
+      vr[t][r] = (T)keep_if(v.x, ok);
+      nvi[t][r] = (T)keep_if(-v.y, ok);
     }
   for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
     const int m = q / NT, n = q % NT;
     const bool ok = m < M && n < N;
     const double2 v = *reinterpret_cast<const double2*>(
         in + ((size_t)min(m, M - 1) * N + min(n, N - 1)) * 2);
-    sY[2 * q] = keep_if(v.x, ok);
-    sY[2 * q + 1] = keep_if(v.y, ok);
+    sY[2 * q] = (T)keep_if(v.x, ok);
+    sY[2 * q + 1] = (T)keep_if(v.y, ok);
   }
   __syncthreads();
   // o = E Y (rows of this tile)
-  auto apply_eh = [&](const double* Eh, dx4 (&o)[NTC][2]) {
+  auto apply_eh = [&](const double* Eh, acc_t (&o)[NTC][2]) {
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) o[ct][0] = o[ct][1] = dx4_zero();
+    for (int ct = 0; ct < NTC; ++ct) o[ct][0] = o[ct][1] = mm::zero();
 #pragma unroll
     for (int t = 0; t < KTMAX; ++t)
       if (t < KT)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           {
-            const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
-            const double e =
-                keep_if(Eh[min(row, M - 1) * M + min(col, M - 1)], row < M && col < M);
+            const int row = 16 * t + mm::row(g, r), col = 16 * tp + c;
+            const T e =
+                (T)keep_if(Eh[min(row, M - 1) * M + min(col, M - 1)], row < M && col < M);
 #pragma unroll
             for (int ct = 0; ct < NTC; ++ct) {
-              const double* yb = sY + ((16 * t + 4 * r + g) * NT + 16 * ct + c) * 2;
-              o[ct][0] = mfma_f64(e, yb[0], o[ct][0]);
-              o[ct][1] = mfma_f64(e, yb[1], o[ct][1]);
+              const T* yb = sY + ((16 * t + mm::row(g, r)) * NT + 16 * ct + c) * 2;
+              o[ct][0] = mm::fma(e, yb[0], o[ct][0]);
+              o[ct][1] = mm::fma(e, yb[1], o[ct][1]);
             }
           }
   };
-  auto store = [&](double* dst, const dx4 (&o)[NTC][2]) {
+  auto store = [&](T* dst, const acc_t (&o)[NTC][2]) {
 #pragma unroll
     for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double* d = dst + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+        T* d = dst + ((16 * tp + mm::row(g, r)) * NT + 16 * ct + c) * 2;
         d[0] = o[ct][0][r];
         d[1] = o[ct][1][r];
       }
   };
   // X = Er src: a second LDS tile, or (XR, when two tiles do not fit in LDS)
   // registers, each wavefront holding its own rows in the accumulator layout
-  dx4 x[NTC][2];
+  acc_t x[NTC][2];
   if (Er != nullptr) {
     apply_eh(Er, x);
     __syncthreads();
@@ -438,7 +459,7 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double* d = sY + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+        const T* d = sY + ((16 * tp + mm::row(g, r)) * NT + 16 * ct + c) * 2;
         x[ct][0][r] = d[0];
         x[ct][1][r] = d[1];
       }
@@ -447,9 +468,9 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     __syncthreads();
   }
   for (int j = n_taylor; j >= 1; --j) {
-    dx4 are[NTC], aim1[NTC], aim2[NTC];
+    acc_t are[NTC], aim1[NTC], aim2[NTC];
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) are[ct] = aim1[ct] = aim2[ct] = dx4_zero();
+    for (int ct = 0; ct < NTC; ++ct) are[ct] = aim1[ct] = aim2[ct] = mm::zero();
 #pragma unroll
     for (int t = 0; t < KTMAX; ++t)
       if (t < KT)
@@ -457,25 +478,25 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int ct = 0; ct < NTC; ++ct) {
-            const double* yb = sY + ((16 * t + 4 * r + g) * NT + 16 * ct + c) * 2;
-            const double yr = yb[0], yi = yb[1];
-            are[ct] = mfma_f64(vr[t][r], yr, are[ct]);
-            are[ct] = mfma_f64(nvi[t][r], yi, are[ct]);
-            aim1[ct] = mfma_f64(vr[t][r], yi, aim1[ct]);
-            aim2[ct] = mfma_f64(nvi[t][r], yr, aim2[ct]);
+            const T* yb = sY + ((16 * t + mm::row(g, r)) * NT + 16 * ct + c) * 2;
+            const T yr = yb[0], yi = yb[1];
+            are[ct] = mm::fma(vr[t][r], yr, are[ct]);
+            are[ct] = mm::fma(nvi[t][r], yi, are[ct]);
+            aim1[ct] = mm::fma(vr[t][r], yi, aim1[ct]);
+            aim2[ct] = mm::fma(nvi[t][r], yr, aim2[ct]);
           }
-    const double invj = 1.0 / (double)j;
-    dx4 y[NTC][2];
+    const T invj = (T)(1.0 / (double)j);
+    acc_t y[NTC][2];
 #pragma unroll
     for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double xr_, xi_;
+        T xr_, xi_;
         if (XR) {
           xr_ = x[ct][0][r];
           xi_ = x[ct][1][r];
         } else {
-          const double* xv = sX + ((16 * tp + g + 4 * r) * NT + 16 * ct + c) * 2;
+          const T* xv = sX + ((16 * tp + mm::row(g, r)) * NT + 16 * ct + c) * 2;
           xr_ = xv[0];
           xi_ = xv[1];
         }
@@ -486,31 +507,31 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     store(sY, y);
     __syncthreads();
   }
-  dx4 o[NTC][2];
+  acc_t o[NTC][2];
   apply_eh(El, o);
 #pragma unroll
   for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * tp + g + 4 * r, n = 16 * ct + c;
+      const int m = 16 * tp + mm::row(g, r), n = 16 * ct + c;
       if (m < M && n < N) {
         double* d = ph + ((size_t)m * N + n) * 2;
-        d[0] = o[ct][0][r];
-        d[1] = o[ct][1][r];
+        d[0] = (double)o[ct][0][r];
+        d[1] = (double)o[ct][1][r];
       }
     }
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-template <int KTMAX, int NTC>
+template <typename T, int KTMAX, int NTC>
 hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
                               const double* vmat, const double* El, const double* Er,
                               const double* src, int src_ws, double* dst) {
-  const size_t tile = (size_t)c->MT * 16 * NTC * 2 * sizeof(double);
+  const size_t tile = (size_t)c->MT * 16 * NTC * 2 * sizeof(T);
   const bool xr = 2 * tile > kMaxLds;
   const size_t lds = xr ? tile : 2 * tile;
-  auto kern = xr ? k_taylor_g<KTMAX, NTC, true> : k_taylor_g<KTMAX, NTC, false>;
+  auto kern = xr ? k_taylor_g<T, KTMAX, NTC, true> : k_taylor_g<T, KTMAX, NTC, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -521,14 +542,17 @@ hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int n, int spins, int n_tayl
 
 }  // namespace
 
-hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
-                               const double* vmat, const double* El, const double* Er,
-                               const double* src, int src_ws, double* dst) {
+namespace {
+
+template <typename T>
+hipError_t taylor_g_dispatch(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
+                             const double* vmat, const double* El, const double* Er,
+                             const double* src, int src_ws, double* dst) {
   if (n <= 0) return hipSuccess;
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_P(KM, NC)                                                                  \
-  if (KT <= KM && NTC == NC)                                                             \
-    return launch_taylor_g_kt<KM, NC>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
+#define AFQMC_P(KM, NC)                                                                        \
+  if (KT <= KM && NTC == NC)                                                                   \
+    return launch_taylor_g_kt<T, KM, NC>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
   AFQMC_P(4, 1) AFQMC_P(6, 1) AFQMC_P(8, 1) AFQMC_P(10, 1)
   AFQMC_P(4, 2) AFQMC_P(6, 2) AFQMC_P(8, 2) AFQMC_P(10, 2)
   AFQMC_P(4, 3) AFQMC_P(6, 3) AFQMC_P(8, 3) AFQMC_P(10, 3)
@@ -536,8 +560,18 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
   return hipErrorInvalidValue;
 }
 
+}  // namespace
+
+hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_taylor,
+                               const double* vmat, const double* El, const double* Er,
+                               const double* src, int src_ws, double* dst) {
+  return taylor_g_dispatch<double>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
+}
+
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
-  return launch_taylor_g_gen(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
+  if (prop_f32(c))
+    return taylor_g_dispatch<float>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
+  return taylor_g_dispatch<double>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
 }
 
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
@@ -547,10 +581,10 @@ hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double 
   const int MM = c->M * c->M;
   dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (n + 64 * VB_WT - 1) / (64 * VB_WT));
   if (xbar != nullptr)
-    hipLaunchKernelGGL(k_vbuild<true>, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s,
-                       Lgen, y, xbar, vmat);
+    hipLaunchKernelGGL((k_vbuild<double, true>), grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs,
+                       sqrt_s, Lgen, y, xbar, vmat);
   else
-    hipLaunchKernelGGL(k_vbuild<false>, grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs, sqrt_s,
-                       Lgen, y, xbar, vmat);
+    hipLaunchKernelGGL((k_vbuild<double, false>), grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs,
+                       sqrt_s, Lgen, y, xbar, vmat);
   return hipGetLastError();
 }

@@ -13,6 +13,10 @@
 //   at most ||U / s||_inf / (j + 1) <= 16 / 29 of the one before once the
 //   terms have passed their peak, so the dropped tail is below 1.3 * 2^-56
 //   max|sum|, a sixth of an ulp of the largest entry.
+// Mixed-precision contexts (any precision but FP64) run both Taylor kernels
+// with FP32 products (v_mfma_f32_16x16x4f32: U and the terms rounded to FP32,
+// FP32 accumulation within a product, the running sum kept in FP64) and stop
+// at max|term| <= 2^-26 max|sum|, a quarter of an FP32 ulp.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -102,10 +106,18 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
       }
 }
 
-template <int MT>
+// stop once max|term| <= this fraction of max|sum|
+template <typename T>
+__device__ __forceinline__ constexpr double stop_ratio() {
+  return sizeof(T) == 8 ? 0x1.0p-56 : 0x1.0p-26;
+}
+
+template <typename T, int MT>
 __global__ void __launch_bounds__(TB_WAVES * 64, 2)
 k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
                const double* __restrict__ phi0, double* __restrict__ phiT) {
+  typedef MM<T> mm;
+  typedef typename mm::acc_t acc_t;
   constexpr int NTILE = MT / 16;  // row tiles
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -114,8 +126,9 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
   if (s >= n_samples) return;  // no block-level barriers in this kernel
   const double* Us = U + (size_t)s * M * M;
 
-  // ua[tp][t][r] = U[16 tp + c][16 t + 4 r + g] = U[16 t + 4 r + g][16 tp + c]
-  double ua[NTILE][NTILE][4];
+  // ua[tp][t][r] = U[16 tp + c][16 t + k(g, r)] = U[16 t + k(g, r)][16 tp + c],
+  // k(g, r) = mm::row(g, r)
+  T ua[NTILE][NTILE][4];
   double rownorm = 0.0;
 #pragma unroll
   for (int tp = 0; tp < NTILE; ++tp) {
@@ -124,9 +137,10 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
-        ua[tp][t][r] = (row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
-        rs += fabs(ua[tp][t][r]);
+        const int row = 16 * t + mm::row(g, r), col = 16 * tp + c;
+        const double u = (row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
+        ua[tp][t][r] = (T)u;
+        rs += fabs(u);
       }
     // row 16 tp + c of U: its entries are spread over the four lane groups
     rs += __shfl_xor(rs, 16, 64);
@@ -139,7 +153,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
   int nstage = 1;
   if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
   if (nstage > 1) {
-    const double inv = 1.0 / nstage;
+    const T inv = (T)(1.0 / nstage);
 #pragma unroll
     for (int tp = 0; tp < NTILE; ++tp)
 #pragma unroll
@@ -148,13 +162,14 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
         for (int r = 0; r < 4; ++r) ua[tp][t][r] *= inv;
   }
 
-  // sum = Phi_0 in the accumulator layout: sum[t][r] = X[16 t + 4 r + g][c]
-  double sum[NTILE][4], term[NTILE][4];
+  // sum = Phi_0 in the accumulator layout: sum[t][r] = X[16 t + k(g, r)][c]
+  double sum[NTILE][4];
+  T term[NTILE][4];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * t + 4 * r + g;
+      const int m = 16 * t + mm::row(g, r);
       sum[t][r] = (m < M && c < N) ? phi0[m * N + c] : 0.0;
     }
 
@@ -162,24 +177,24 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) term[t][r] = sum[t][r];
+      for (int r = 0; r < 4; ++r) term[t][r] = (T)sum[t][r];
     for (int j = 1; j <= MAX_TERMS; ++j) {
-      dx4 acc[NTILE];
+      acc_t acc[NTILE];
 #pragma unroll
-      for (int tp = 0; tp < NTILE; ++tp) acc[tp] = dx4_zero();
+      for (int tp = 0; tp < NTILE; ++tp) acc[tp] = mm::zero();
 #pragma unroll
       for (int t = 0; t < NTILE; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int tp = 0; tp < NTILE; ++tp) acc[tp] = mfma_f64(ua[tp][t][r], term[t][r], acc[tp]);
-      const double invj = 1.0 / (double)j;
+          for (int tp = 0; tp < NTILE; ++tp) acc[tp] = mm::fma(ua[tp][t][r], term[t][r], acc[tp]);
+      const T invj = (T)(1.0 / (double)j);
 #pragma unroll
       for (int t = 0; t < NTILE; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           term[t][r] = acc[t][r] * invj;
-          sum[t][r] += term[t][r];
+          sum[t][r] += (double)term[t][r];
         }
       if (j & 1) continue;
       double tmax = 0.0, smax = 0.0;
@@ -187,12 +202,12 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
       for (int t = 0; t < NTILE; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          tmax = fmax(tmax, fabs(term[t][r]));
+          tmax = fmax(tmax, fabs((double)term[t][r]));
           smax = fmax(smax, fabs(sum[t][r]));
         }
       tmax = wave_max_full(tmax);
       smax = wave_max_full(smax);
-      if (tmax <= 0x1.0p-56 * smax) break;
+      if (tmax <= stop_ratio<T>() * smax) break;
     }
   }
 
@@ -201,7 +216,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * t + 4 * r + g;
+      const int m = 16 * t + mm::row(g, r);
       if (m < M && c < N) out[m * N + c] = sum[t][r];
     }
 }
@@ -209,8 +224,12 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
 template <int MT>
 hipError_t launch_mt(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
   dim3 grid((n + TB_WAVES - 1) / TB_WAVES), block(TB_WAVES * 64);
-  hipLaunchKernelGGL(k_trial_taylor<MT>, grid, block, 0, c->stream, n, c->M, c->N, U, c->d_phi0,
-                     phiT);
+  if (c->precision != AFQMC_PREC_FP64)
+    hipLaunchKernelGGL((k_trial_taylor<float, MT>), grid, block, 0, c->stream, n, c->M, c->N, U,
+                       c->d_phi0, phiT);
+  else
+    hipLaunchKernelGGL((k_trial_taylor<double, MT>), grid, block, 0, c->stream, n, c->M, c->N, U,
+                       c->d_phi0, phiT);
   return hipGetLastError();
 }
 
@@ -239,14 +258,16 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
 // shared through a double-buffered LDS tile, one barrier per term.
 namespace {
 
-template <int KTMAX, int NTC>
+template <typename T, int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__ U,
                  const double* __restrict__ phi0, double* __restrict__ phiT) {
+  typedef MM<T> mm;
+  typedef typename mm::acc_t acc_t;
   constexpr int NT = 16 * NTC;
   extern __shared__ double smem[];
-  double* sT = smem;                       // [2][MT][NT]
-  double* sred = smem + 2 * MT * NT;       // [KTMAX][2]
+  T* sT = reinterpret_cast<T*>(smem);                           // [2][MT][NT]
+  double* sred = smem + (2 * MT * NT * sizeof(T) + 7) / 8;      // [KTMAX][2]
   const int KT = MT / 16;
   const int s = blockIdx.x;
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -254,15 +275,17 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
   if (s >= n_samples) return;
   const double* Us = U + (size_t)s * M * M;
 
-  double ua[KTMAX][4];
+  // ua[t][r] = U[16 tp + c][16 t + k(g, r)], k(g, r) = mm::row(g, r)
+  T ua[KTMAX][4];
   double rs = 0.0;
 #pragma unroll
   for (int t = 0; t < KTMAX; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * r + g, col = 16 * tp + c;
-      ua[t][r] = (t < KT && row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
-      rs += fabs(ua[t][r]);
+      const int row = 16 * t + mm::row(g, r), col = 16 * tp + c;
+      const double u = (t < KT && row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
+      ua[t][r] = (T)u;
+      rs += fabs(u);
     }
   rs += __shfl_xor(rs, 16, 64);
   rs += __shfl_xor(rs, 32, 64);
@@ -271,7 +294,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
   // Phi_0 into buffer 0 and into the running sum (my rows)
   for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
     const int m = q / NT, n = q % NT;
-    sT[q] = (m < M && n < N) ? phi0[m * N + n] : 0.0;
+    sT[q] = (T)((m < M && n < N) ? phi0[m * N + n] : 0.0);
   }
   __syncthreads();
   double rownorm = 0.0;
@@ -279,7 +302,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
   int nstage = 1;
   if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
   if (nstage > 1) {
-    const double inv = 1.0 / nstage;
+    const T inv = (T)(1.0 / nstage);
 #pragma unroll
     for (int t = 0; t < KTMAX; ++t)
 #pragma unroll
@@ -289,7 +312,10 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
 #pragma unroll
   for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sm[ct][r] = sT[(16 * tp + g + 4 * r) * NT + 16 * ct + c];
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + mm::row(g, r), n = 16 * ct + c;
+      sm[ct][r] = (m < M && n < N) ? phi0[m * N + n] : 0.0;
+    }
   __syncthreads();
 
   int cur = 0;
@@ -298,15 +324,16 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sT[cur * MT * NT + (16 * tp + g + 4 * r) * NT + 16 * ct + c] = sm[ct][r];
+        for (int r = 0; r < 4; ++r)
+          sT[cur * MT * NT + (16 * tp + mm::row(g, r)) * NT + 16 * ct + c] = (T)sm[ct][r];
       __syncthreads();
     }
     for (int j = 1; j <= MAX_TERMS; ++j) {
-      const double* Tc = sT + cur * MT * NT;
-      double* Tn = sT + (cur ^ 1) * MT * NT;
-      dx4 acc[NTC];
+      const T* Tc = sT + cur * MT * NT;
+      T* Tn = sT + (cur ^ 1) * MT * NT;
+      acc_t acc[NTC];
 #pragma unroll
-      for (int ct = 0; ct < NTC; ++ct) acc[ct] = dx4_zero();
+      for (int ct = 0; ct < NTC; ++ct) acc[ct] = mm::zero();
 #pragma unroll
       for (int t = 0; t < KTMAX; ++t)
         if (t < KT)
@@ -314,17 +341,17 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
           for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int ct = 0; ct < NTC; ++ct)
-              acc[ct] = mfma_f64(ua[t][r], Tc[(16 * t + 4 * r + g) * NT + 16 * ct + c], acc[ct]);
-      const double invj = 1.0 / (double)j;
+              acc[ct] = mm::fma(ua[t][r], Tc[(16 * t + mm::row(g, r)) * NT + 16 * ct + c], acc[ct]);
+      const T invj = (T)(1.0 / (double)j);
       double tmax = 0.0, smax = 0.0;
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double v = acc[ct][r] * invj;
-          sm[ct][r] += v;
-          Tn[(16 * tp + g + 4 * r) * NT + 16 * ct + c] = v;
-          tmax = fmax(tmax, fabs(v));
+          const T v = acc[ct][r] * invj;
+          sm[ct][r] += (double)v;
+          Tn[(16 * tp + mm::row(g, r)) * NT + 16 * ct + c] = v;
+          tmax = fmax(tmax, fabs((double)v));
           smax = fmax(smax, fabs(sm[ct][r]));
         }
       const bool check = (j & 1) == 0;
@@ -344,7 +371,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
           tm = fmax(tm, sred[w * 2]);
           sx = fmax(sx, sred[w * 2 + 1]);
         }
-        if (tm <= 0x1.0p-56 * sx) break;
+        if (tm <= stop_ratio<T>() * sx) break;
       }
     }
   }
@@ -353,22 +380,28 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
   for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = 16 * tp + g + 4 * r, n = 16 * ct + c;
+      const int m = 16 * tp + mm::row(g, r), n = 16 * ct + c;
       if (m < M && n < N) out[m * N + n] = sm[ct][r];
     }
 }
 
-template <int KTMAX, int NTC>
-hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+template <typename T, int KTMAX, int NTC>
+hipError_t launch_tgt(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
   const int NT = 16 * NTC;
-  const size_t lds = (size_t)(2 * c->MT * NT + 2 * KTMAX) * sizeof(double);
-  auto kern = k_trial_taylor_g<KTMAX, NTC>;
+  const size_t lds = ((2 * (size_t)c->MT * NT * sizeof(T) + 7) / 8 + 2 * KTMAX) * sizeof(double);
+  auto kern = k_trial_taylor_g<T, KTMAX, NTC>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(n), dim3(64 * (c->MT / 16)), lds, c->stream, n, c->M, c->N, c->MT,
                      U, c->d_phi0, phiT);
   return hipGetLastError();
+}
+
+template <int KTMAX, int NTC>
+hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+  return c->precision != AFQMC_PREC_FP64 ? launch_tgt<float, KTMAX, NTC>(c, n, U, phiT)
+                                         : launch_tgt<double, KTMAX, NTC>(c, n, U, phiT);
 }
 
 }  // namespace
