@@ -36,12 +36,15 @@ PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix
 WORKLOADS = {
     "fp64": (1, 0, PEAK_FP64_MFMA, "f64"),
     "fp64-prior": (1, 0, PEAK_FP64_MFMA, "f64"),
-    "mixed": (2, 1, PEAK_FP32_MFMA, "f32-contraction/f64"),
+    # mixed forms: the contraction's products in the named type, the trial series,
+    # V build and propagation on FP32 products, complex64 walkers, LU / log-det /
+    # Theta / QR / sums in FP64
+    "mixed": (2, 1, PEAK_FP32_MFMA, "f32-products/c64-walkers/f64-lu"),
     "mixed-fp64": (2, 0, PEAK_FP64_MFMA, "f64"),
     # BF16 products: roofline against the dense BF16 peak with the algorithmic flops
     # (the split form executes three products per algorithmic one)
-    "mixed-bf16x3": (2, 3, PEAK_BF16_MFMA, "bf16x3-contraction/f64"),
-    "mixed-bf16": (2, 2, PEAK_BF16_MFMA, "bf16-contraction/f64"),
+    "mixed-bf16x3": (2, 3, PEAK_BF16_MFMA, "bf16x3-contraction/f32-products/c64-walkers/f64-lu"),
+    "mixed-bf16": (2, 2, PEAK_BF16_MFMA, "bf16-contraction/f32-products/c64-walkers/f64-lu"),
     "slices": (5, 0, PEAK_FP64_MFMA, "f64"),
 }
 
@@ -573,8 +576,9 @@ def main():
     # path-sign averages fall within a few tens of steps)
     capped = args.workload not in ("fp64", "fp64-prior")
     xbar_cap, n_pc, w_cap = (1.0, 1, 4.0) if capped else (0.0, 1, 0.0)
+    c64 = precision != 0 and getattr(sys_, "trial_kind", 0) == 0
     ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap,
-                    precision=precision, proposal=proposal, rw_step=rw_step)
+                    precision=precision, proposal=proposal, rw_step=rw_step, walker_c64=c64)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
 
@@ -633,7 +637,7 @@ def main():
                    "rw_step": rw_step if proposal == A.PROPOSAL_RW else None,
                    "L_scale": L_SCALE, "L_scale_note": L_SCALE_NOTE,
                    "xbar_cap": xbar_cap, "comb_every": n_pc, "comb_weights_reset_to": 1.0,
-                   "weight_cap": w_cap},
+                   "weight_cap": w_cap, "walkers_complex64": c64},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload),

@@ -132,6 +132,13 @@ typedef struct {
   const double* slice_s;  /* SLICES: HOST [m], s_l >= 0                      */
   const double* slice_F;  /* SLICES: HOST [m+1][M][M], F_0 .. F_m             */
   int32_t trial_taylor; /* SLICES: Taylor order n of X_l (>= 1)              */
+  int32_t walker_c64;   /* 1: every phi argument (walkers) is complex64, [nw][2][M][N]
+                           interleaved FLOAT pairs: the calls widen it to FP64 in
+                           the workspace and round the moved or re-orthonormalised
+                           walkers back to complex64.  Needs a reduced-precision
+                           contraction (precision != FP64) and the real trial
+                           family; not with afqmc_init_metropolis, the
+                           back-propagation calls or batches. 0: complex128. */
 } afqmc_system;
 
 /* Copies the system to device `device`, derives h1' = h1 + 1/2 sum_g L_g^2 and

@@ -49,6 +49,7 @@ class afqmc_system(ctypes.Structure):
         ("xbar_cap", c_double),
         ("trial_kind", c_int32), ("n_slices", c_int32), ("slice_s", POINTER(c_double)),
         ("slice_F", POINTER(c_double)), ("trial_taylor", c_int32),
+        ("walker_c64", c_int32),
     ]
 
 
@@ -172,7 +173,8 @@ def _stream():
 
 
 def system_struct(system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
-                  proposal=PROPOSAL_PRIOR, rw_step=None, xbar_cap=0.0, precision=PREC_FP64):
+                  proposal=PROPOSAL_PRIOR, rw_step=None, xbar_cap=0.0, precision=PREC_FP64,
+                  walker_c64=False):
     """(afqmc_system, host arrays it points into) for a system description."""
     import numpy as np
     if rw_step is None:
@@ -184,6 +186,7 @@ def system_struct(system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
                       int(system.hidden_kind), float(system.coupling), dp(host[0]), dp(host[1]),
                       dp(host[2]), dp(host[3]), float(dtau), int(n_taylor), int(weight_mode),
                       int(proposal), float(rw_step), int(precision), float(xbar_cap))
+    st.walker_c64 = 1 if walker_c64 else 0
     kind = int(getattr(system, "trial_kind", TRIAL_JASTROW))
     if kind == TRIAL_SLICES:
         s_arr = np.ascontiguousarray(system.slice_s, dtype=np.float64)
@@ -200,17 +203,20 @@ class Context:
 
     def __init__(self, system, P, dtau, n_taylor=10, weight_mode=WEIGHT_SEPARATE,
                  proposal=PROPOSAL_PRIOR, rw_step=None, max_walkers=1, device=0, xbar_cap=0.0,
-                 precision=PREC_FP64):
+                 precision=PREC_FP64, walker_c64=False):
         """rw_step: the random-walk step (default 0.5 for PROPOSAL_RW); with
         PROPOSAL_LEARNED a value > 0 cycles random-walk and network moves
-        (default 0: network moves only)."""
+        (default 0: network moves only).  walker_c64: walkers (every phi
+        argument) are complex64 tensors."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise AfqmcError("no GPU available for libafqmc")
         self.M, self.N, self.G, self.K, self.P = (int(system.M), int(system.N),
                                                   int(system.n_chol), int(system.K), int(P))
         self.sys, self._host = system_struct(system, P, dtau, n_taylor, weight_mode, proposal,
-                                             rw_step, xbar_cap, precision)
+                                             rw_step, xbar_cap, precision, walker_c64)
+        # element type of the walker determinants phi
+        self.pdtype = torch.complex64 if walker_c64 else torch.complex128
         # element type of trial determinants: complex for multi-slice trials
         self.ctrial = int(getattr(system, "trial_kind", TRIAL_JASTROW)) == TRIAL_SLICES
         self.tdtype = torch.complex128 if self.ctrial else torch.float64
@@ -290,14 +296,14 @@ def afqmc_trial_build(ctx, nw, y, phiT):
 
 def afqmc_overlap(ctx, nw, phi, phiT, logov):
     c = ctx
-    c._call("afqmc_overlap", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_overlap", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"))
 
 
 def afqmc_green(ctx, nw, phi, phiT, logov, theta):
     c = ctx
-    c._call("afqmc_green", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_green", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(theta, torch.complex128, nw * c.P * 2 * c.M * c.N, "theta"))
@@ -343,7 +349,7 @@ def afqmc_local_energy_static(ctx, nw, phiT, theta, logov, eloc, e_sample=None, 
 def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_new, eloc=None):
     c = ctx
     c.reserve(nw)
-    c._call("afqmc_propagate", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_propagate", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(xi, torch.float64, nw * c.G, "xi"),
             _ptr(xbar, torch.complex128, nw * c.G, "xbar"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
@@ -356,7 +362,7 @@ def afqmc_propagate(ctx, nw, phi, xi, xbar, phiT, logov, e_shift, w, ref, logov_
 def afqmc_metropolis_x(ctx, nw, phi, y, phiT, logov, ref, w, seed, step, n_sweep, n_accept=None):
     c = ctx
     c.reserve(nw)
-    c._call("afqmc_metropolis_x", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_metropolis_x", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
@@ -368,7 +374,7 @@ def afqmc_metropolis_x(ctx, nw, phi, y, phiT, logov, ref, w, seed, step, n_sweep
 
 def afqmc_reorthogonalize(ctx, nw, phi, logov=None):
     c = ctx
-    c._call("afqmc_reorthogonalize", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_reorthogonalize", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(logov, torch.complex128, nw * c.P, "logov", allow_none=True))
 
 
@@ -377,7 +383,7 @@ def afqmc_population_control(ctx, nw, phi, w, y, phiT, logov, seed, step, w_cap=
     c = ctx
     c.reserve(nw)
     c._call("afqmc_population_control", nw,
-            _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"), _ptr(w, torch.float64, nw, "w"),
+            _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"), _ptr(w, torch.float64, nw, "w"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"), int(seed), int(step), float(w_cap),
@@ -441,7 +447,7 @@ def afqmc_init_metropolis(ctx, nw, seed, n_pair, n_burn, yw, phi, y, phiT, logov
     c.reserve(nw)
     c._call("afqmc_init_metropolis", nw, int(seed), int(n_pair), int(n_burn),
             _ptr(yw, torch.float64, nw * c.K, "yw"),
-            _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+            _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(y, torch.float64, nw * c.P * c.K, "y"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"), _ptr(w, torch.float64, nw, "w"))
@@ -475,7 +481,7 @@ def afqmc_philox_normal(ctx, seed, step, tag, nw, n, out):
 
 def afqmc_green_diag(ctx, nw, phi, phiT, logov, gdiag):
     c = ctx
-    c._call("afqmc_green_diag", nw, _ptr(phi, torch.complex128, nw * 2 * c.M * c.N, "phi"),
+    c._call("afqmc_green_diag", nw, _ptr(phi, c.pdtype, nw * 2 * c.M * c.N, "phi"),
             _ptr(phiT, ctx.tdtype, nw * c.P * c.M * c.N, "phiT"),
             _ptr(logov, torch.complex128, nw * c.P, "logov"),
             _ptr(gdiag, torch.float64, nw * c.P * c.M, "gdiag"))

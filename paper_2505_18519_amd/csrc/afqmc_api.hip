@@ -107,6 +107,38 @@ T* ws_ptr(afqmc_ctx_s* c, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(c->ws) + off);
 }
 
+// Walkers of a complex64 context: their FP64 copy in the workspace (widened
+// exactly), on which every kernel runs; after a move or re-orthonormalisation
+// the copy is rounded back into the caller's complex64 array.  complex128
+// contexts use the caller's array directly.
+afqmc_status phi_in(afqmc_ctx_s* c, int nw, const void* phi, double** out) {
+  if (!c->c64) {
+    *out = const_cast<double*>(static_cast<const double*>(phi));
+    return AFQMC_OK;
+  }
+  ws_layout L;
+  afqmc_status st = need_ws(c, nw, &L);
+  if (st != AFQMC_OK) return st;
+  double* d = ws_ptr<double>(c, L.phi128);
+  HIPCALL(c, launch_phi_widen(c, (size_t)nw * 2 * c->M * c->N, static_cast<const float*>(phi), d),
+          "widen walkers");
+  *out = d;
+  return AFQMC_OK;
+}
+
+afqmc_status phi_out(afqmc_ctx_s* c, int nw, const double* w128, void* phi) {
+  if (!c->c64) return AFQMC_OK;
+  HIPCALL(c, launch_phi_narrow(c, (size_t)nw * 2 * c->M * c->N, w128, static_cast<float*>(phi)),
+          "round walkers");
+  return AFQMC_OK;
+}
+
+#define PHI_IN(c, nw, phi, out)                     \
+  do {                                              \
+    afqmc_status pst_ = phi_in((c), (nw), (phi), (out)); \
+    if (pst_ != AFQMC_OK) return pst_;              \
+  } while (0)
+
 // The numerical-event flag words of walkers [0, nw) (the workspace's first
 // 4 nw bytes), null if no workspace that large is set.  Words not yet known
 // to be clear are cleared first, on the stream, by a fill kernel; with the
@@ -237,6 +269,8 @@ ws_layout afqmc_ws_layout(const afqmc_ctx_s* c, int nw) {
     *idst[i] = off;
     off += align256(isz[i]);
   }
+  L.phi128 = off;
+  off += c->c64 ? align256((size_t)nw * 2 * MN * 16) : 0;
   L.total = off;
   return L;
 }
@@ -298,6 +332,10 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     return AFQMC_E_INVALID;
   if (sys->n_taylor < 1 || !(sys->dtau > 0.0) || !isfinite(sys->coupling)) return AFQMC_E_INVALID;
   if (!(sys->xbar_cap >= 0.0)) return AFQMC_E_INVALID;
+  if (sys->walker_c64 != 0 && sys->walker_c64 != 1) return AFQMC_E_INVALID;
+  if (sys->walker_c64 == 1 &&
+      (sys->precision == AFQMC_PREC_FP64 || sys->trial_kind != AFQMC_TRIAL_JASTROW))
+    return AFQMC_E_UNSUPPORTED;
   const bool slices = sys->trial_kind == AFQMC_TRIAL_SLICES;
   if (sys->trial_kind != AFQMC_TRIAL_JASTROW && !slices) return AFQMC_E_INVALID;
   if (slices) {
@@ -344,6 +382,7 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   c->proposal = sys->proposal;
   c->precision = sys->precision;
   c->xbar_cap = sys->xbar_cap;
+  c->c64 = sys->walker_c64 == 1;
 
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = scratch_address(device, &c->d_scratch);
@@ -503,10 +542,9 @@ afqmc_status afqmc_overlap(afqmc_ctx c, int32_t nw, const void* phi, const doubl
   REQUIRE(c, phi, "phi");
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
-  HIPCALL(c,
-          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
-                     nullptr),
-          "overlap");
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
+  HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov), nullptr), "overlap");
   return AFQMC_OK;
 }
 
@@ -519,9 +557,10 @@ afqmc_status afqmc_green(afqmc_ctx c, int32_t nw, const void* phi, const double*
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
   REQUIRE(c, theta, "theta");
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
   HIPCALL(c,
-          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
-                     static_cast<double*>(theta)),
+          do_overlap(c, nw, ph, phiT, static_cast<double*>(logov), static_cast<double*>(theta)),
           "green");
   return AFQMC_OK;
 }
@@ -637,9 +676,13 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   afqmc_status st = need_ws(c, nw, &L);
   if (st != AFQMC_OK) return st;
   double* vmat = ws_ptr<double>(c, L.vmat);
-  double* ph = static_cast<double*>(phi);
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
   HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat), "vbuild");
   HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph), "taylor");
+  st = phi_out(c, nw, ph, phi);
+  if (st != AFQMC_OK) return st;
+  if (c->c64) PHI_IN(c, nw, phi, &ph);  // the ratio is that of the stored (rounded) walkers
   HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov_new), nullptr), "ratio overlap");
   hipError_t fe;
   int* flags = flag_words(c, nw, &fe);
@@ -672,7 +715,8 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
   double* phiTtry = ws_ptr<double>(c, L.phiTtry);
   double* ltry = ws_ptr<double>(c, L.ltry);
   int* nacc = n_accept ? n_accept : ws_ptr<int>(c, L.acc);
-  const double* ph = static_cast<const double*>(phi);
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
   double* lo = static_cast<double*>(logov);
   HIPCALL(c, launch_zero_int(c, nw, nacc), "zero");
   if (c->proposal == AFQMC_PROPOSAL_LEARNED) {
@@ -766,6 +810,8 @@ afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32
   if (c->ctrial)
     return fail(c, AFQMC_E_UNSUPPORTED,
                 "initialisation from the trial needs the real symmetric trial family");
+  if (c->c64)
+    return fail(c, AFQMC_E_UNSUPPORTED, "initialisation from the trial needs complex128 walkers");
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, yw, "yw");
   REQUIRE(c, phi, "phi");
@@ -876,6 +922,8 @@ afqmc_status afqmc_bp_density(afqmc_ctx c, int32_t nw, int32_t h, const void* ph
                               void* logov_bp, void* rho, double* out) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);
+  if (c->c64)
+    return fail(c, AFQMC_E_UNSUPPORTED, "back-propagation needs complex128 walkers");
   if (h < 0) return fail(c, AFQMC_E_INVALID, "h must be >= 0");
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, phi_mid, "phi_mid");
@@ -973,18 +1021,18 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx c, int32_t nw, void* phi, void* log
   CHECK_NW(c, nw);
   if (nw == 0) return AFQMC_OK;
   REQUIRE(c, phi, "phi");
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
   if (c->small) {
-    HIPCALL(c, launch_qr(c, nw, static_cast<double*>(phi), static_cast<double*>(logov)), "qr");
+    HIPCALL(c, launch_qr(c, nw, ph, static_cast<double*>(logov)), "qr");
   } else {
     ws_layout L;
     afqmc_status st = need_ws(c, nw, &L);
     if (st != AFQMC_OK) return st;
-    HIPCALL(c,
-            launch_qr_g(c, nw, static_cast<double*>(phi), static_cast<double*>(logov),
-                        ws_ptr<double>(c, L.qrshift)),
+    HIPCALL(c, launch_qr_g(c, nw, ph, static_cast<double*>(logov), ws_ptr<double>(c, L.qrshift)),
             "qr");
   }
-  return AFQMC_OK;
+  return phi_out(c, nw, ph, phi);
 }
 
 afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double* w, double* y,
@@ -1012,7 +1060,8 @@ afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double
   struct {
     double* state;
     size_t off, row;
-  } parts[4] = {{static_cast<double*>(phi), L.pc_phi, (size_t)2 * c->M * c->N * 2},
+  // a walker's row: 2 M N complex entries, 16 bytes each, or 8 if complex64
+  } parts[4] = {{static_cast<double*>(phi), L.pc_phi, (size_t)2 * c->M * c->N * (c->c64 ? 1 : 2)},
                 {y, L.pc_y, S * c->K},
                 {phiT, L.pc_phiT, S * c->tsz},
                 {static_cast<double*>(logov), L.pc_logov, S * 2}};
@@ -1181,9 +1230,9 @@ afqmc_status afqmc_green_diag(afqmc_ctx c, int32_t nw, const void* phi, const do
   REQUIRE(c, phiT, "phiT");
   REQUIRE(c, logov, "logov");
   REQUIRE(c, gdiag, "gdiag");
-  HIPCALL(c,
-          do_overlap(c, nw, static_cast<const double*>(phi), phiT, static_cast<double*>(logov),
-                     nullptr, gdiag),
+  double* ph;
+  PHI_IN(c, nw, phi, &ph);
+  HIPCALL(c, do_overlap(c, nw, ph, phiT, static_cast<double*>(logov), nullptr, gdiag),
           "green diagonal");
   return AFQMC_OK;
 }

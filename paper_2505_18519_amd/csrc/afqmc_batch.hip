@@ -396,8 +396,10 @@ afqmc_status afqmc_batch_create(const afqmc_system* systems, const int32_t* walk
     return AFQMC_E_INVALID;
   *out = nullptr;
   if (n_systems < 1) return AFQMC_E_INVALID;
-  for (int i = 0; i < n_systems; ++i)
+  for (int i = 0; i < n_systems; ++i) {
     if (walkers[i] < 1) return AFQMC_E_INVALID;
+    if (systems[i].walker_c64 != 0) return AFQMC_E_UNSUPPORTED;  // the arena holds complex128
+  }
   if (opt->n_sweep < 0 || opt->n_qr < 0 || opt->n_pc < 1 || !(opt->w_cap >= 0.0) ||
       opt->max_branches < 1 || opt->max_branches > 4 || opt->history < 1 ||
       (opt->autotune != 0 && opt->autotune != 1))

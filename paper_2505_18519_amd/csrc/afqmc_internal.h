@@ -29,6 +29,7 @@ struct afqmc_ctx_s {
   unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad, A-operand order (BF16 contractions)
   unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf, same order (split BF16)
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
+  bool c64 = false;           // walkers stored as complex64 (widened in the workspace)
 
   // trial family (AFQMC_TRIAL_*); multi-slice trials have complex Phi_T and
   // always run on the workgroup-per-path kernels
@@ -88,6 +89,7 @@ struct ws_layout {
   // determinants and log-overlaps (last, so that the same carve-up for P = 1
   // or without the network never reaches it)
   size_t in_yb, in_pa, in_pb, in_la, in_lb;
+  size_t phi128;  // complex64 walkers: their FP64 copy [nw][2][M][N] complex (else 0 bytes)
   size_t total;
 };
 constexpr int MLP_CHUNK = 512;  // samples per split of the weight-gradient sums
@@ -146,6 +148,9 @@ hipError_t launch_extend_paths(const afqmc_ctx_s* c, int nw, int Ps, int Pd, con
                                const double* ps, const double* ls, double* yd, double* pd,
                                double* ld);
 hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
+// complex64 <-> complex128 walker copies, n complex entries
+hipError_t launch_phi_widen(const afqmc_ctx_s* c, size_t n, const float* src, double* dst);
+hipError_t launch_phi_narrow(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y,
                                 double* phiT, double* ubuf);
 hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,

@@ -1,5 +1,7 @@
 // Set-up kernels (h1', e^{-tau h1/2}), counter-based random streams, the
 // mixed-estimator sums and walker re-orthonormalisation.
+#include <algorithm>
+
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -341,6 +343,42 @@ hipError_t launch_qr(const afqmc_ctx_s* c, int nw, double* phi, double* logov) {
 hipError_t launch_to_float(const afqmc_ctx_s* c, size_t n, const double* src, float* dst) {
   hipLaunchKernelGGL(k_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, src,
                      dst);
+  return hipGetLastError();
+}
+
+namespace {
+
+// complex64 walkers: exact widening to complex128, rounding to nearest back
+__global__ void k_phi_widen(size_t n, const float2* __restrict__ src, double2* __restrict__ dst) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = src[q];
+    dst[q] = make_double2((double)v.x, (double)v.y);
+  }
+}
+__global__ void k_phi_narrow(size_t n, const double2* __restrict__ src, float2* __restrict__ dst) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = src[q];
+    dst[q] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_phi_widen(const afqmc_ctx_s* c, size_t n, const float* src, double* dst) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_phi_widen, dim3(blocks), dim3(256), 0, c->stream, n,
+                     reinterpret_cast<const float2*>(src), reinterpret_cast<double2*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_narrow(const afqmc_ctx_s* c, size_t n, const double* src, float* dst) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_phi_narrow, dim3(blocks), dim3(256), 0, c->stream, n,
+                     reinterpret_cast<const double2*>(src), reinterpret_cast<float2*>(dst));
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ class Walkers:
         c, dev = ctx, ctx.device
         self.nw = nw
         z = dict(device=dev)
-        self.phi = torch.zeros(nw, 2, c.M, c.N, dtype=torch.complex128, **z)
+        self.phi = torch.zeros(nw, 2, c.M, c.N, dtype=c.pdtype, **z)
         self.w = torch.ones(nw, dtype=torch.float64, **z)
         self.y = torch.zeros(nw, c.P, c.K, dtype=torch.float64, **z)
         self.phiT = torch.zeros(nw, c.P, c.M, c.N, dtype=c.tdtype, **z)
@@ -37,7 +37,7 @@ class Walkers:
 def init_walkers(ctx: A.Context, phi0, nw: int, seed: int) -> Walkers:
     """phi = Phi_0 for both spins, W = 1, y ~ p_T, Phi_T(y) and l(y; phi)."""
     st = Walkers(ctx, nw)
-    p0 = torch.as_tensor(phi0, dtype=torch.complex128, device=ctx.device)
+    p0 = torch.as_tensor(phi0, dtype=ctx.pdtype, device=ctx.device)
     st.phi.copy_(p0.expand(nw, 2, ctx.M, ctx.N))
     A.afqmc_sample_prior(ctx, nw, seed, st.y)
     A.afqmc_trial_build(ctx, nw, st.y, st.phiT)

@@ -615,3 +615,85 @@ def test_bf16_contraction_needs_real_trials():
             A.Context(s, 4, 0.01, precision=prec)
     with pytest.raises(A.AfqmcError):
         A.Context(ai.tiny_ising(), 4, 0.01, precision=4)
+
+
+@pytest.mark.parametrize("case", ["gauss-M20-N5-ragged", "cfg-M64-N16-G256", "gauss-M72-N20-ragged",
+                                  "gauss-M128-N32"])
+def test_complex64_walkers(case):
+    """Walkers stored as complex64 (mixed-precision contexts): the calls widen
+    them exactly, so overlaps and Theta equal the oracle's for the stored
+    walkers to the FP64 bound; a move returns walkers within 1e-5 of the FP64
+    oracle (FP32 products plus rounding to complex64) whose stored log-overlaps
+    are the FP64 LU of the rounded walkers; QR returns the rounded FP64 QR;
+    the comb copies rows bit for bit."""
+    _say("complex64 walkers", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    dtau = 0.01
+    ctx = A.Context(s, P, dtau, max_walkers=nw, precision=A.PREC_FP32, walker_c64=True)
+    rng, phi, y = state(s, P, nw, 11, spread=1.0)
+    phi64 = phi.astype(np.complex64)
+    phi_w = phi64.astype(np.complex128)                 # what the library works on
+    phiT = O.trial_det(s, y)
+    ell_ref, theta_ref = O.green(phiT, phi_w)
+    dl = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    dth = torch.zeros(nw, P, 2, s.M, s.N, dtype=torch.complex128, device="cuda")
+    dphi = dev(phi64)
+    assert dphi.dtype == torch.complex64
+    A.afqmc_green(ctx, nw, dphi, dev(phiT), dl, dth)
+    torch.cuda.synchronize()
+    check_logov(host(dl), ell_ref)
+    for w in range(nw):
+        for p in range(P):
+            assert rel(host(dth)[w, p], theta_ref[w, p]) <= TOL
+    # a move
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi_w, phiT, dtau)
+    xi = rng.normal(size=(nw, s.n_chol))
+    w0 = rng.uniform(0.5, 1.5, size=nw)
+    phin, wn, ref, elln = O.propagate(s, phi_w, xi, xbar, phiT, ell, w0, dtau, 10, -1.3)
+    dw = dev(w0)
+    dref = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    dln = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    A.afqmc_propagate(ctx, nw, dphi, dev(xi), dev(xbar), dev(phiT), dev(ell), -1.3, dw, dref, dln)
+    torch.cuda.synchronize()
+    g_phi = host(dphi).astype(np.complex128)
+    e_phi = max(rel(g_phi[w], phin[w]) for w in range(nw))
+    check_logov(host(dln), O.log_overlap(phiT, g_phi))
+    e_w = np.abs(host(dw) - wn).max() / np.abs(wn).max()
+    _say(f"  errors vs FP64 oracle: phi' {e_phi:.2e}  W {e_w:.2e}")
+    assert e_phi <= MIXED_PROP_TOL and e_w <= MIXED_TOL
+    # re-orthonormalisation of the stored walkers
+    q_ref, lq_ref = O.reorthogonalize(g_phi, ell)
+    dl2 = dev(ell)
+    A.afqmc_reorthogonalize(ctx, nw, dphi, dl2)
+    torch.cuda.synchronize()
+    g_q = host(dphi)
+    assert g_q.dtype == np.complex64
+    for w in range(nw):
+        assert rel(g_q[w].astype(np.complex128), q_ref[w]) <= 2e-7
+    assert np.abs(host(dl2).real - lq_ref.real).max() <= TOL * np.abs(lq_ref.real).max()
+    # the comb moves complex64 rows
+    wts = rng.exponential(size=nw)
+    parent, _ = O.comb(wts, 3, 1)
+    before = host(dphi).copy()
+    A.afqmc_population_control(ctx, nw, dphi, dev(wts), dev(y), dev(phiT), dev(ell), 3, 1, 0.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(dphi), before[parent])
+
+
+def test_complex64_walkers_need_a_mixed_context():
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5)
+    with pytest.raises(A.AfqmcError) as ei:
+        A.Context(s, 2, 0.01, walker_c64=True)          # FP64 contraction
+    assert ei.value.status == 6
+    ctx = A.Context(s, 2, 0.01, max_walkers=2, precision=A.PREC_BF16X3, walker_c64=True)
+    z = dict(device="cuda")
+    with pytest.raises(A.AfqmcError) as ei:
+        A.afqmc_init_metropolis(ctx, 2, 1, 1, 1, torch.zeros(2, s.K, dtype=torch.float64, **z),
+                                torch.zeros(2, 2, s.M, s.N, dtype=torch.complex64, **z),
+                                torch.zeros(2, 2, s.K, dtype=torch.float64, **z),
+                                torch.zeros(2, 2, s.M, s.N, dtype=torch.float64, **z),
+                                torch.zeros(2, 2, dtype=torch.complex128, **z),
+                                torch.zeros(2, dtype=torch.float64, **z))
+    assert ei.value.status == 6
