@@ -426,7 +426,8 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
   }
   if (e == hipSuccess &&
       (c->precision == AFQMC_PREC_BF16 || c->precision == AFQMC_PREC_BF16X3)) {
-    const size_t n = Lpad.size();
+    // slabs of MT rows by the k extent padded to whole 32-wide blocks
+    const size_t n = (size_t)(G + 1) * MT * ((MT + 31) / 32 * 32);
     const bool x3 = c->precision == AFQMC_PREC_BF16X3;
     if ((e = hipMalloc(&c->d_Lbf, n * sizeof(unsigned short))) == hipSuccess &&
         (!x3 || (e = hipMalloc(&c->d_Lbf_lo, n * sizeof(unsigned short))) == hipSuccess) &&

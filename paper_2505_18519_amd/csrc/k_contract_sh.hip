@@ -5,9 +5,13 @@
 //   Y_g = Phi_T^T L_g,  f_g^s = Y_g Theta^s,  vb_g = sum_s tr f_g^s,
 //   E_p = sum_s tr(Phi_T^T h1' Theta^s) + 1/2 sum_g [vb_g^2 - sum_s tr(f_g^s f_g^s)].
 //
-// Products: lane (g, c) supplies A[c][4g + j] and B[4g + j][c] (j = 0..3, four
-// consecutive k values) and holds D[4g + r][c] -- one v_mfma_f32_16x16x16bf16_1k
-// for BF16, four v_mfma_f32_16x16x4f32 (the j-th on k = 4g + j) for FP32.
+// Products: lane (g, c) supplies KV consecutive k values of one row of A and
+// one column of B and holds D[4g + r][c].  BF16 (and split BF16): one
+// v_mfma_f32_16x16x32_bf16 per 32-wide k block, KV = 8 (k = 32 u + 8 g + j);
+// FP32: four v_mfma_f32_16x16x4f32 per 16-wide k block, KV = 4 (k = 16 u +
+// 4 g + j, the j-th product on the j-th value).  A and B take the same lane
+// layout of k, so the product is the contraction over k whatever order the
+// matrix core visits the block in.
 // Split BF16: every operand x is carried as x_hi = bf16(x) and
 // x_lo = bf16(x - x_hi), and a product a b as a_hi b_hi + a_hi b_lo + a_lo b_hi
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
@@ -21,8 +25,9 @@
 // row tile, its A operands read from the shared slab.  Y_g^T is rounded to the
 // operand form once, as stage 1 leaves it, and stored in LDS in the accumulator
 // layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a column in
-// one lane); f is transposed through LDS for tr(f f); traces, vb_g^2 and the
-// sums over g are FP64.
+// one lane); f is transposed through LDS for tr(f f).  Each lane's eight
+// products of FP32 entries of f for tr(f f) are summed in FP32 per vector;
+// the traces, the sums over lanes, vb_g^2 and the sums over g are FP64.
 
 #include <type_traits>
 
@@ -32,8 +37,14 @@
 namespace {
 
 typedef short sx4 __attribute__((ext_vector_type(4)));
+typedef short sx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bfx8 __attribute__((ext_vector_type(8)));
 
-// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+typedef __bf16 bfx2 __attribute__((ext_vector_type(2)));
+typedef float fx2 __attribute__((ext_vector_type(2)));
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet): the host-side
+// set-up conversion of the slabs
 __device__ __forceinline__ unsigned short f2bf(float f) {
   unsigned u = __float_as_uint(f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
@@ -42,44 +53,24 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-// hi / lo BF16 pair of a value: hi = bf16(x), lo = bf16(x - hi)
-struct bsplit {
-  sx4 hi, lo;
-};
-template <bool X3>
-__device__ __forceinline__ bsplit split4(float a, float b, float c, float d) {
-  bsplit s;
-  const unsigned short h0 = f2bf(a), h1 = f2bf(b), h2 = f2bf(c), h3 = f2bf(d);
-  s.hi = sx4{(short)h0, (short)h1, (short)h2, (short)h3};
-  if (X3) {
-    s.lo = sx4{(short)f2bf(a - bf2f(h0)), (short)f2bf(b - bf2f(h1)), (short)f2bf(c - bf2f(h2)),
-               (short)f2bf(d - bf2f(h3))};
-  } else {
-    s.lo = sx4{0, 0, 0, 0};
-  }
-  return s;
+// two floats -> two bfloat16 (round to nearest even, one v_cvt_pk_bf16_f32 on
+// gfx950), as the low and high halves of a 32-bit word
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(fx2{a, b}, bfx2));
 }
-
-template <bool X3>
-__device__ __forceinline__ fx4 mma(const bsplit& a, const bsplit& b, fx4 acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, acc, 0, 0, 0);
-  if (X3) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, acc, 0, 0, 0);
-  }
-  return acc;
-}
+__device__ __forceinline__ float bf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
 __device__ __forceinline__ fx4 fx4_zero() {
   fx4 z = {0.f, 0.f, 0.f, 0.f};
   return z;
 }
 
-// Operand forms of the contraction.  An operand is what one lane supplies to a
-// 16 x 16 x 16 product: four consecutive k values (4g .. 4g+3) of one row or
-// column, as NP parts of type V.  FP32 runs the product as four
-// v_mfma_f32_16x16x4f32, the j-th taking k = 4g + j, so its lane layout is
-// the BF16 one with float4 in place of four BF16 values.
+// Operand forms of the contraction.  An operand is what one lane supplies to
+// one k block: KV consecutive k values of one row or column, as NP parts of
+// type V (FP32: float4; BF16: eight BF16 values).  The Y^T tile is kept in
+// LDS in 4-row groups of type V4 (the accumulator layout of stage 1), two of
+// which make one BF16 operand.
 enum { FM_BF16 = 0, FM_BF16X3 = 1, FM_FP32 = 2 };
 template <int FM>
 struct Form {
@@ -87,20 +78,46 @@ struct Form {
   static constexpr bool F32 = FM == FM_FP32;
   static constexpr int NP = X3 ? 2 : 1;             // parts: hi (and lo)
   static constexpr int NB = FM == FM_BF16 ? 2 : 1;  // slab and Y^T buffers
-  typedef typename std::conditional<F32, fx4, sx4>::type V;
+  static constexpr int KV = F32 ? 4 : 8;            // k values per lane and block
+  static constexpr int KB = 4 * KV;                 // k per block
+  typedef typename std::conditional<F32, fx4, sx8>::type V;
+  typedef typename std::conditional<F32, fx4, sx4>::type V4;
   struct Op {
     V p[NP];
   };
-  __device__ __forceinline__ static Op make(float a, float b, float c, float d) {
-    Op o;
+  struct Op4 {
+    V4 p[NP];
+  };
+  // hi (and lo) parts of four values
+  __device__ __forceinline__ static Op4 make4(float a, float b, float c, float d) {
+    Op4 o;
     if constexpr (F32) {
       o.p[0] = fx4{a, b, c, d};
     } else {
-      const bsplit s = split4<X3>(a, b, c, d);
-      o.p[0] = s.hi;
-      if constexpr (X3) o.p[NP - 1] = s.lo;
+      const unsigned h01 = pk_bf16(a, b), h23 = pk_bf16(c, d);
+      o.p[0] = __builtin_bit_cast(sx4, (unsigned long long)h01 | ((unsigned long long)h23 << 32));
+      if constexpr (X3) {
+        const unsigned l01 = pk_bf16(a - bf_lo(h01), b - bf_hi(h01));
+        const unsigned l23 = pk_bf16(c - bf_lo(h23), d - bf_hi(h23));
+        o.p[NP - 1] =
+            __builtin_bit_cast(sx4, (unsigned long long)l01 | ((unsigned long long)l23 << 32));
+      }
     }
     return o;
+  }
+  __device__ __forceinline__ static Op make(const float (&x)[KV]) {
+    Op o;
+    if constexpr (F32) {
+      o.p[0] = fx4{x[0], x[1], x[2], x[3]};
+    } else {
+      const Op4 a = make4(x[0], x[1], x[2], x[3]), b = make4(x[4], x[5], x[6], x[7]);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) o.p[part] = join(a.p[part], b.p[part]);
+    }
+    return o;
+  }
+  __device__ __forceinline__ static sx8 join(sx4 a, sx4 b) {
+    return sx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
   }
   __device__ __forceinline__ static fx4 mma(const Op& a, const Op& b, fx4 acc) {
     if constexpr (F32) {
@@ -108,10 +125,15 @@ struct Form {
       for (int j = 0; j < 4; ++j)
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.p[0][j], b.p[0][j], acc, 0, 0, 0);
     } else {
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[0], b.p[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bfx8, a.p[0]),
+                                                    __builtin_bit_cast(bfx8, b.p[0]), acc, 0, 0, 0);
       if constexpr (X3) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[0], b.p[NP - 1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.p[NP - 1], b.p[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bfx8, a.p[0]),
+                                                      __builtin_bit_cast(bfx8, b.p[NP - 1]), acc, 0,
+                                                      0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bfx8, a.p[NP - 1]),
+                                                      __builtin_bit_cast(bfx8, b.p[0]), acc, 0, 0,
+                                                      0);
       }
     }
     return acc;
@@ -145,12 +167,15 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
   typedef Form<FM> Fm;
   typedef typename Fm::V V;
+  typedef typename Fm::V4 V4;
   typedef typename Fm::Op Op;
-  constexpr int SLAB = MT * MT;                // entries per slab
-  constexpr int SV = SLAB / 4;                 // operands (V) per slab part
+  constexpr int KV = Fm::KV, KB = Fm::KB;
+  constexpr int KBN = (MT + KB - 1) / KB;      // k blocks (a BF16 block pads an odd KT)
+  constexpr int MTP = KB * KBN;                // k extent, padded
+  constexpr int SV = KT * KBN * 64;            // operands (V) per slab part
   constexpr int NU = SV * (int)sizeof(V) / 16; // 16-byte units per slab part
   constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
-  constexpr int YT = (MT / 4) * NT;            // operands of one Y^T tile part
+  constexpr int YT = (MTP / 4) * NT;           // 4-row groups (V4) of one Y^T tile part
   // plain BF16: slabs and Y^T tiles double-buffered (the next slab loads during
   // the whole vector); split BF16 (hi and lo of each) and FP32 (twice the
   // bytes): single buffers, the next slab loading from the barrier after stage 1
@@ -159,7 +184,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   constexpr int NP = Fm::NP;                   // parts (hi, lo)
   extern __shared__ double smem[];
   V* sL = reinterpret_cast<V*>(smem);                                      // [NB][NP][SV]
-  V* sY = sL + NB * NP * SV;                                               // [BCP][NB][NP][YT]
+  V4* sY = reinterpret_cast<V4*>(sL + NB * NP * SV);                       // [BCP][NB][NP][YT]
   float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][2][NT][NT+1][2]
   double* sD = reinterpret_cast<double*>(sF + BCP * 2 * NT * (NT + 1) * 2);  // [BCP][BFL][NWV*16][2]
   double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
@@ -187,15 +212,25 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     }
   };
   copy_slab(0, 0);
+  if (MTP > MT) {  // the Y^T rows of a padded k block are never written: zero them once
+    for (int q = threadIdx.x; q < BCP * NB * NP * ((MTP - MT) / 4) * NT; q += blockDim.x) {
+      const int per = ((MTP - MT) / 4) * NT;
+      const int tile = q / per, e = q % per;
+      V4 z;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[i] = 0;
+      sY[(size_t)tile * YT + (MT / 4) * NT + e] = z;
+    }
+  }
 
-  // B operands (bit-masked unconditional loads)
-  Op bT[NTC][KT], th[2][KT];
+  // B operands (bit-masked unconditional loads): k = KB u + KV g + j
+  Op bT[NTC][KBN], th[2][KBN];
 #pragma unroll
-  for (int t = 0; t < KT; ++t) {
-    float v[NTC][4], w[2][4];
+  for (int t = 0; t < KBN; ++t) {
+    float v[NTC][KV], w[2][KV];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = 16 * t + 4 * g + j;
+    for (int j = 0; j < KV; ++j) {
+      const int m = KB * t + KV * g + j;
       const bool okm = active && m < M;
       const int mc = min(m, M - 1);
 #pragma unroll
@@ -211,14 +246,14 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
       w[1][j] = (float)keep_if(x2.y, okm && n < N);
     }
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = Fm::make(v[ct][0], v[ct][1], v[ct][2], v[ct][3]);
+    for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = Fm::make(v[ct]);
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri) th[ri][t] = Fm::make(w[ri][0], w[ri][1], w[ri][2], w[ri][3]);
+    for (int ri = 0; ri < 2; ++ri) th[ri][t] = Fm::make(w[ri]);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
-  V* Yp = sY + pw * NB * NP * YT;
+  V4* Yp = sY + pw * NB * NP * YT;
   float* Fp = sF + (size_t)pw * 2 * NT * (NT + 1) * 2;
   double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
@@ -236,17 +271,17 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
       const int tp = wv + NWV * q;
       if (active && tp < KT)
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
+        for (int t = 0; t < KBN; ++t) {
           Op a;
 #pragma unroll
-          for (int part = 0; part < NP; ++part) a.p[part] = Ls[part * SV + (tp * KT + t) * 64 + lane];
+          for (int part = 0; part < NP; ++part) a.p[part] = Ls[part * SV + (tp * KBN + t) * 64 + lane];
 #pragma unroll
           for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = Fm::mma(a, bT[ct][t], y1[q][ct]);
         }
     }
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
     if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
-    V* Yb = Yp + b * NP * YT;
+    V4* Yb = Yp + b * NP * YT;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -254,7 +289,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
         for (int ct = 0; ct < NTC; ++ct) {
           const fx4 v = y1[q][ct];
-          const Op yv = Fm::make(v[0], v[1], v[2], v[3]);
+          const typename Fm::Op4 yv = Fm::make4(v[0], v[1], v[2], v[3]);
 #pragma unroll
           for (int part = 0; part < NP; ++part) Yb[part * YT + (4 * tp + g) * NT + 16 * ct + c] = yv.p[part];
         }
@@ -262,18 +297,26 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     __syncthreads();
     // single buffers: every stage-1 read of this slab is done, the next one can load
     if (NB == 1 && gam < G) copy_slab(gam + 1, 0);
-    // stage 2: f^sp[it][jt], A[c][4g + j] = Y^T[16t + 4g + j][16it + c]
+    // stage 2: f^sp[it][jt], A[c][KV g + j] = Y^T[KB t + KV g + j][16it + c]: the
+    // 4-row group (KB t + KV g) / 4, and for BF16 the next one too
     fx4 f[NTC][2];
 #pragma unroll
     for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
     if (active) {
 #pragma unroll
-      for (int t = 0; t < KT; ++t)
+      for (int t = 0; t < KBN; ++t)
 #pragma unroll
         for (int it = 0; it < NTC; ++it) {
           Op a;
+          const int grp = (KB * t + KV * g) / 4;
 #pragma unroll
-          for (int part = 0; part < NP; ++part) a.p[part] = Yb[part * YT + (4 * t + g) * NT + 16 * it + c];
+          for (int part = 0; part < NP; ++part) {
+            const V4* yg = Yb + part * YT + grp * NT + 16 * it + c;
+            if constexpr (Fm::F32)
+              a.p[part] = yg[0];
+            else
+              a.p[part] = Fm::join(yg[0], yg[NT]);
+          }
           f[it][0] = Fm::mma(a, th[0][t], f[it][0]);
           f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
         }
@@ -322,16 +365,23 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     }
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
     __syncthreads();
+    // this lane's share of tr(f f) for the vector: its eight FP32 products of
+    // FP32 entries summed in FP32, the sum over lanes and vectors in FP64
+    float xr = 0.f, xi = 0.f;
 #pragma unroll
     for (int it = 0; it < NTC; ++it)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
-        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
-        const double ar = (double)f[it][0][r], ai = (double)f[it][1][r];
-        ex_re += ar * tr_ - ai * ti_;
-        ex_im += ar * ti_ + ai * tr_;
+        const float tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const float ar = f[it][0][r], ai = f[it][1][r];
+        xr = fmaf(ar, tr_, xr);
+        xr = fmaf(-ai, ti_, xr);
+        xi = fmaf(ar, ti_, xi);
+        xi = fmaf(ai, tr_, xi);
       }
+    ex_re += (double)xr;
+    ex_im += (double)xi;
     // every BFL vectors: wavefront 0 of each path reduces its staged diagonals to vb_g
     if ((gam % BFL == BFL - 1 || gam == G - 1) && wv == 0 && valid) {
       const int cnt = gam % BFL + 1, g0 = gam - gam % BFL;
@@ -376,12 +426,13 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-// the same for every form: buffers x parts x bytes per entry = 2 x 1 x 2 (BF16),
-// 1 x 2 x 2 (split BF16) or 1 x 1 x 4 (FP32)
-size_t lds_bytes_s(int KT, int NTC) {
+// buffers x parts x bytes per entry = 2 x 1 x 2 (BF16), 1 x 2 x 2 (split BF16)
+// or 1 x 1 x 4 (FP32), over MT x MTP entries (MTP: k padded to whole blocks)
+size_t lds_bytes_s(int KT, int NTC, int FM) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = 2 * NTC;
-  size_t b = (size_t)4 * MT * MT;                     // slabs
-  b += (size_t)BCP * (MT / 4) * NT * 16;              // Y^T tiles
+  const int KB = FM == FM_FP32 ? 16 : 32, MTP = (MT + KB - 1) / KB * KB;
+  size_t b = (size_t)4 * MT * MTP;                    // slabs
+  b += (size_t)BCP * (MTP / 4) * NT * 16;             // Y^T tiles
   b += (size_t)BCP * 2 * NT * (NT + 1) * 2 * 4;       // f (FP32)
   b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
   b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
@@ -393,7 +444,7 @@ hipError_t launch_sh(const afqmc_ctx_s* c, int nw, const void* L, const void* L_
                       const double* phiT, const double* theta, const double* logov, double* vb,
                       double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes_s(KT, NTC);
+  const size_t lds = lds_bytes_s(KT, NTC, FM);
   auto kern = k_contract_sh<KT, NTC, FM>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -419,17 +470,20 @@ hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const void* L, const void* L
   return hipErrorInvalidValue;
 }
 
-// L (double, row-major slabs) -> BF16 in A-operand order [slab][tp][t][g][c][j] =
-// L[slab][16 tp + c][16 t + 4 g + j]; with lo given, also lo = bf16(L - hi) in that order
+// L (double, row-major slabs) -> BF16 in A-operand order [slab][tp][u][g][c][j] =
+// L[slab][16 tp + c][32 u + 8 g + j] (0 for k = 32 u + 8 g + j >= MT, the padding of
+// the last 32-wide block); with lo given, also lo = bf16(L - hi) in that order.
+// n = slabs x MT x MTP.
 __global__ void k_to_bf16_op(size_t n, int MT, const double* __restrict__ src,
                              unsigned short* __restrict__ dst, unsigned short* __restrict__ lo) {
   const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
-  const int KT = MT / 16;
-  const size_t slab = o / ((size_t)MT * MT);
-  const int r = (int)(o % ((size_t)MT * MT));
-  const int j = r & 3, cc = (r >> 2) & 15, gg = (r >> 6) & 3, t = (r >> 8) % KT, tp = (r >> 8) / KT;
-  const float x = (float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + 16 * t + 4 * gg + j];
+  const int KBN = (MT + 31) / 32, MTP = 32 * KBN;
+  const size_t slab = o / ((size_t)MT * MTP);
+  const int r = (int)(o % ((size_t)MT * MTP));
+  const int j = r & 7, cc = (r >> 3) & 15, gg = (r >> 7) & 3, u = (r >> 9) % KBN, tp = (r >> 9) / KBN;
+  const int k = 32 * u + 8 * gg + j;
+  const float x = k < MT ? (float)src[slab * MT * MT + (size_t)(16 * tp + cc) * MT + k] : 0.f;
   const unsigned short h = f2bf(x);
   dst[o] = h;
   if (lo != nullptr) lo[o] = f2bf(x - bf2f(h));
