@@ -53,8 +53,8 @@ WORKLOADS = {
 # the plain-copy calibration (profiles/traffic_k_contract_*.md), valid while the
 # kernel source is the one measured: workload -> (source file, sha256 prefix, bytes)
 TRAFFIC = {
-    "fp64": ("k_contract.hip", "84a10461fe9f869b", 454528640),
-    "fp64-prior": ("k_contract.hip", "84a10461fe9f869b", 454528640),
+    "fp64": ("k_contract.hip", "e96e7653420b4e6b", 454536192),
+    "fp64-prior": ("k_contract.hip", "e96e7653420b4e6b", 454536192),
 }
 
 # Proposal of each per-step workload: the default FP64 leg runs the random walk
