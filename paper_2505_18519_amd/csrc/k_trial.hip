@@ -7,16 +7,17 @@
 //   operands and runs the Taylor series sum_j U^j Phi_0 / j!.  With the k
 //   index of the product visited as 16 t + 4 r + g, the accumulator of one
 //   term is, register for register, the B operand of the next, so the series
-//   needs no LDS traffic.  Terms are added until max|term| <= 2^-56 max|sum|
-//   (checked every second term); when the row-sum norm of U exceeds 16 the
-//   series is applied s = ceil(norm / 16) times to U / s.  Each later term is
-//   at most ||U / s||_inf / (j + 1) <= 16 / 29 of the one before once the
-//   terms have passed their peak, so the dropped tail is below 1.3 * 2^-56
-//   max|sum|, a sixth of an ulp of the largest entry.
+//   needs no LDS traffic.  When the row-sum norm of U exceeds 16 the series
+//   is applied s = ceil(norm / 16) times to U / s.  Every entry of term j + 1
+//   is at most r / (j + 1) times the largest entry of term j (r = ||U / s||_inf),
+//   so after term j the whole dropped tail is bounded by max|term_j| times
+//   (r / (j + 1)) / (1 - r / (j + 2)) once j + 2 > r; the series stops (checked
+//   every second term) when that bound is below 2^-56 max|sum|, a quarter of
+//   an ulp of the largest entry.
 // Mixed-precision contexts (any precision but FP64) run both Taylor kernels
 // with FP32 products (v_mfma_f32_16x16x4f32: U and the terms rounded to FP32,
 // FP32 accumulation within a product, the running sum kept in FP64) and stop
-// at max|term| <= 2^-26 max|sum|, a quarter of an FP32 ulp.
+// when the tail bound is below 2^-26 max|sum|, a quarter of an FP32 ulp.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
@@ -106,10 +107,20 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
       }
 }
 
-// stop once max|term| <= this fraction of max|sum|
+// the dropped tail may be at most this fraction of max|sum|
 template <typename T>
 __device__ __forceinline__ constexpr double stop_ratio() {
   return sizeof(T) == 8 ? 0x1.0p-56 : 0x1.0p-26;
+}
+
+// Stop test after term j of exp(V) X with r = ||V||_inf: the tail
+// sum_{i>j} V^i X / i! has entries at most tmax * q / (1 - r / (j + 2)),
+// q = r / (j + 1), when j + 2 > r (no bound before that).
+template <typename T>
+__device__ __forceinline__ bool series_done(double tmax, double smax, double r, int j) {
+  const double nxt = (double)(j + 2);
+  if (!(nxt > r)) return false;
+  return tmax * (r / (double)(j + 1)) <= stop_ratio<T>() * smax * (1.0 - r / nxt);
 }
 
 template <typename T, int MT>
@@ -152,6 +163,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
   // is bounded so that every wavefront finishes
   int nstage = 1;
   if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
+  const double rn = rownorm / nstage;
   if (nstage > 1) {
     const T inv = (T)(1.0 / nstage);
 #pragma unroll
@@ -207,7 +219,7 @@ k_trial_taylor(int n_samples, int M, int N, const double* __restrict__ U,
         }
       tmax = wave_max_full(tmax);
       smax = wave_max_full(smax);
-      if (tmax <= stop_ratio<T>() * smax) break;
+      if (series_done<T>(tmax, smax, rn, j)) break;
     }
   }
 
@@ -301,6 +313,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
   for (int w = 0; w < KT; ++w) rownorm = fmax(rownorm, sred[w * 2]);
   int nstage = 1;
   if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
+  const double rn = rownorm / nstage;
   if (nstage > 1) {
     const T inv = (T)(1.0 / nstage);
 #pragma unroll
@@ -371,7 +384,7 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
           tm = fmax(tm, sred[w * 2]);
           sx = fmax(sx, sred[w * 2 + 1]);
         }
-        if (tm <= stop_ratio<T>() * sx) break;
+        if (series_done<T>(tm, sx, rn, j)) break;
       }
     }
   }
