@@ -174,8 +174,10 @@ def sample_contraction(sys, phiT: np.ndarray, theta: np.ndarray, ell: np.ndarray
     ep = np.zeros((nw, P), dtype=np.complex128)
     for w in range(nw):
         ok = ~np.isneginf(ell[w].real)
-        Y = np.einsum("pmi,gmn->pgin", phiT[w], sys.L)          # Phi_T^T L_g  [P,G,N,M]
-        f = np.einsum("pgim,psmj->pgsij", Y, theta[w])           # [P,G,2,N,N]
+        # Phi_T^T L_g [P,G,N,M] and f = Y Theta^s [P,G,2,N,N], both as library
+        # products (einsum's BLAS path, batched matmul)
+        Y = np.einsum("pmi,gmn->pgin", phiT[w], sys.L, optimize=True)
+        f = np.matmul(Y[:, :, None], theta[w][:, None])
         trf = np.einsum("pgsii->pgs", f)
         vbw = trf.sum(-1)
         ex = np.einsum("pgsij,pgsji->p", f, f)
@@ -187,14 +189,16 @@ def sample_contraction(sys, phiT: np.ndarray, theta: np.ndarray, ell: np.ndarray
 
 
 def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: float,
-                     xbar_cap: float = 0.0):
+                     xbar_cap: float = 0.0, eloc_cap=None):
     """Eq. local-obs over the P paths, then Eq. shift1.
 
     xbar_g = -i sqrt(tau) sum_p S_p vb_pg / sum_p S_p,  E_L = sum_p S_p E_p / sum_p S_p.
     The i comes from reading Eq. HS-V's sqrt(-tau) into the propagator with
     real L_g.  A walker whose phases sum to zero gets xbar = 0 and E_L = 0.
     With xbar_cap > 0 each component's modulus is clipped to xbar_cap (phase
-    kept): a stabilisation outside the paper, off by default.
+    kept); with eloc_cap = (E_T, d), d > 0, a finite Re E_L is clipped to
+    [E_T - d, E_T + d] (Im E_L kept).  Both are stabilisations outside the
+    paper (the usual phaseless-AFQMC caps), off by default.
     """
     S = phases(ell)
     den = S.sum(-1)
@@ -207,6 +211,10 @@ def walker_estimates(vb: np.ndarray, ep: np.ndarray, ell: np.ndarray, dtau: floa
     if xbar_cap > 0.0:
         mag = np.abs(xbar)
         xbar = np.where(mag > xbar_cap, xbar * (xbar_cap / np.where(mag > 0, mag, 1.0)), xbar)
+    if eloc_cap is not None and eloc_cap[1] > 0.0:
+        lo, hi = eloc_cap[0] - eloc_cap[1], eloc_cap[0] + eloc_cap[1]
+        fin = np.isfinite(eloc.real) & np.isfinite(eloc.imag)
+        eloc = np.where(fin, np.minimum(np.maximum(eloc.real, lo), hi) + 1j * eloc.imag, eloc)
     return xbar, eloc
 
 
@@ -291,7 +299,7 @@ def propagate(sys, phi, xi, xbar, phiT, logov, w, dtau, n_taylor,
 # Metropolis update of the tethered paths (App. B, steps 2 and 3)
 
 def metropolis(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep,
-               proposal=PROPOSAL_PRIOR, rw_step=0.5, weight_mode=WEIGHT_SEPARATE):
+               proposal=PROPOSAL_PRIOR, rw_step=0.5, weight_mode=WEIGHT_SEPARATE, w0=0):
     """Move every path y_p towards P(y; phi) ~ p_T(y) |O(y; phi)| (Eq. PDF-Y).
 
     Gaussian prior proposal: y' ~ N(0, 1), alpha = |O(y')| / |O(y)|.
@@ -299,7 +307,8 @@ def metropolis(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep,
     Ising: one sweep flips y_0 .. y_{K-1} in turn, alpha = |O(y')| / |O(y)|.
     Accept iff u < alpha.  Then the hand-off projection (Eq.
     AFQMC_Metro_constraint_cos) with Delta-theta_T = arg sum_p S'_p - arg ref.
-    Returns (y', phiT', logov', w', n_accept [nw]).
+    Returns (y', phiT', logov', w', n_accept [nw]).  w0: population index of
+    the first walker (selects the walkers' random streams).
     """
     y = y.copy()
     phiT = phiT.copy()
@@ -308,7 +317,7 @@ def metropolis(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep,
     nacc = np.zeros(nw, dtype=np.int64)
     for s in range(n_sweep):
         if sys.hidden_kind == 0:
-            u = philox.accept_uniforms(seed, step, nw, P, K, s)
+            u = philox.accept_uniforms(seed, step, nw, P, K, s, w0)
             for k in range(K):
                 yp = y.copy()
                 yp[:, :, k] = -yp[:, :, k]
@@ -320,8 +329,8 @@ def metropolis(sys, phi, y, phiT, logov, ref, w, seed, step, n_sweep,
                 logov = np.where(acc, ellp, logov)
                 nacc += acc.sum(-1)
         else:
-            eta = philox.proposal_normals(seed, step, nw, P, K, s)
-            u = philox.accept_uniforms(seed, step, nw, P, 1, s)[:, :, 0]
+            eta = philox.proposal_normals(seed, step, nw, P, K, s, w0)
+            u = philox.accept_uniforms(seed, step, nw, P, 1, s, w0)[:, :, 0]
             if proposal == PROPOSAL_RW:
                 yp = y + rw_step * eta
                 extra = -0.5 * (yp * yp).sum(-1) + 0.5 * (y * y).sum(-1)
@@ -589,19 +598,20 @@ def init_state(sys, nw, P, seed):
 def step(sys, st: State, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
          e_shift=0.0, proposal=PROPOSAL_PRIOR, rw_step=0.5,
          weight_mode=WEIGHT_SEPARATE, Eh=None, h1p=None, xbar_cap=0.0, n_pc=0, w_cap=0.0,
-         normalize=True):
+         normalize=True, eloc_cap=None, w0=0):
     """Measure, propagate, move the paths, re-orthogonalise, and (every n_pc
     steps, if n_pc > 0) comb the population (weights reset to 1 with
-    normalize).  Returns (state, record)."""
+    normalize).  w0: index of the first walker of st in the population (the
+    random streams are per walker index).  Returns (state, record)."""
     ell, theta = green(st.phiT, st.phi)
     vb, ep = sample_contraction(sys, st.phiT, theta, ell, h1p)
-    xbar, eloc = walker_estimates(vb, ep, ell, dtau, xbar_cap)
+    xbar, eloc = walker_estimates(vb, ep, ell, dtau, xbar_cap, eloc_cap)
     num, den = estimator(st.w, eloc)
-    xi = philox.field_normals(seed, i, st.phi.shape[0], sys.n_chol)
+    xi = philox.field_normals(seed, i, st.phi.shape[0], sys.n_chol, w0)
     phin, wn, ref, elln = propagate(sys, st.phi, xi, xbar, st.phiT, ell, st.w, dtau,
                                     n_taylor, e_shift, weight_mode, Eh, eloc)
     y, phiT, logov, w2, nacc = metropolis(sys, phin, st.y, st.phiT, elln, ref, wn, seed, i,
-                                          n_sweep, proposal, rw_step, weight_mode)
+                                          n_sweep, proposal, rw_step, weight_mode, w0)
     if n_qr and (i + 1) % n_qr == 0:
         phin, logov = reorthogonalize(phin, logov)
     parent = np.arange(st.phi.shape[0])

@@ -138,21 +138,26 @@ def stream_uniforms(seed: int, step: int, walkers, w3s, n: int) -> np.ndarray:
 
 # Named streams --------------------------------------------------------------
 
-def field_normals(seed: int, step: int, nw: int, n_chol: int) -> np.ndarray:
-    """Auxiliary fields xi [nw, n_chol] for one propagation step."""
-    return stream_normals(seed, step, np.arange(nw), [word3(TAG_FIELD)], n_chol)[:, 0, :]
+def field_normals(seed: int, step: int, nw: int, n_chol: int, w0: int = 0) -> np.ndarray:
+    """Auxiliary fields xi [nw, n_chol] of walkers w0 .. w0 + nw - 1 for one
+    propagation step."""
+    return stream_normals(seed, step, np.arange(w0, w0 + nw), [word3(TAG_FIELD)], n_chol)[:, 0, :]
 
 
-def proposal_normals(seed: int, step: int, nw: int, P: int, n: int, sweep: int) -> np.ndarray:
-    """Normals [nw, P, n] for the hidden-variable proposal of one sweep."""
+def proposal_normals(seed: int, step: int, nw: int, P: int, n: int, sweep: int,
+                     w0: int = 0) -> np.ndarray:
+    """Normals [nw, P, n] for the hidden-variable proposal of one sweep
+    (walkers w0 .. w0 + nw - 1)."""
     w3 = [word3(TAG_PROPOSAL, sweep, p) for p in range(P)]
-    return stream_normals(seed, step, np.arange(nw), w3, n)
+    return stream_normals(seed, step, np.arange(w0, w0 + nw), w3, n)
 
 
-def accept_uniforms(seed: int, step: int, nw: int, P: int, n: int, sweep: int) -> np.ndarray:
-    """Uniforms [nw, P, n] for the Metropolis accept tests of one sweep."""
+def accept_uniforms(seed: int, step: int, nw: int, P: int, n: int, sweep: int,
+                    w0: int = 0) -> np.ndarray:
+    """Uniforms [nw, P, n] for the Metropolis accept tests of one sweep
+    (walkers w0 .. w0 + nw - 1)."""
     w3 = [word3(TAG_ACCEPT, sweep, p) for p in range(P)]
-    return stream_uniforms(seed, step, np.arange(nw), w3, n)
+    return stream_uniforms(seed, step, np.arange(w0, w0 + nw), w3, n)
 
 
 def init_hidden(seed: int, nw: int, P: int, K: int, hidden_kind: int, sweep: int = 0) -> np.ndarray:

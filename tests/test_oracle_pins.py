@@ -616,6 +616,79 @@ def test_force_bias_cap_keeps_phase_and_clips_modulus(tiny):
     assert np.abs(np.abs(x1[big]) - cap).max() <= 1e-15 * cap
 
 
+def test_local_energy_cap_clips_the_real_part_only(tiny):
+    """The local-energy cap (a stabilisation outside the paper, off unless
+    asked for): Re E_L inside [E_T - d, E_T + d] is unchanged bit for bit, a
+    value outside becomes the nearest bound exactly, Im E_L and the force bias
+    are untouched, the map is monotone, and an unbounded width is the identity.
+    In the local-energy weight the cap bounds the per-step factor
+    exp(-tau (Re E_L - E_T)) to [e^{-tau d}, e^{tau d}]."""
+    rng = np.random.default_rng(23)
+    phi = ai.random_walkers(rng, tiny, 9, spread=1.5)
+    y = ai.random_hidden(rng, tiny, 9, 6)
+    phiT = O.trial_det(tiny, y)
+    ell, theta = O.green(phiT, phi)
+    vb, ep = O.sample_contraction(tiny, phiT, theta, ell)
+    x0, e0 = O.walker_estimates(vb, ep, ell, 0.05)
+    et = float(np.median(e0.real))
+    d = 0.5 * float(np.std(e0.real))
+    x1, e1 = O.walker_estimates(vb, ep, ell, 0.05, eloc_cap=(et, d))
+    assert np.array_equal(x0, x1) and np.array_equal(e0.imag, e1.imag)
+    inside = np.abs(e0.real - et) <= d
+    assert 0 < inside.sum() < inside.size
+    assert np.array_equal(e1.real[inside], e0.real[inside])
+    assert np.all(e1.real[(e0.real > et + d)] == et + d)
+    assert np.all(e1.real[(e0.real < et - d)] == et - d)
+    order = np.argsort(e0.real, kind="stable")
+    assert np.all(np.diff(e1.real[order]) >= 0.0)
+    _, e2 = O.walker_estimates(vb, ep, ell, 0.05, eloc_cap=(et, 1e300))
+    assert np.array_equal(e2, e0)
+    _, e3 = O.walker_estimates(vb, ep, ell, 0.05, eloc_cap=(et, 0.0))
+    assert np.array_equal(e3, e0)
+    # the weight factor of the local-energy formalism is then bounded
+    tau, nw = 0.01, phi.shape[0]
+    xi = np.random.default_rng(5).standard_normal((nw, tiny.n_chol))
+    w = np.ones(nw)
+    _, wn, _, _ = O.propagate(tiny, phi, xi, x1, phiT, ell, w, tau, 10, e_shift=et,
+                              weight_mode=O.WEIGHT_LOCAL, eloc=e1)
+    assert np.all(wn <= np.exp(tau * d) * (1 + 1e-15))
+    live = wn > 0
+    assert np.all(wn[live] <= np.exp(tau * d) * (1 + 1e-15))
+    # with no cap the same walkers' factors leave that band
+    _, wu, _, _ = O.propagate(tiny, phi, xi, x0, phiT, ell, w, tau, 10, e_shift=et,
+                              weight_mode=O.WEIGHT_LOCAL, eloc=e0)
+    mag_c = np.exp(-tau * (e1.real - et))
+    mag_u = np.exp(-tau * (e0.real - et))
+    assert mag_c.max() <= np.exp(tau * d) * (1 + 1e-15) < mag_u.max()
+    assert np.allclose(wn / np.where(wu > 0, wu, 1.0), np.where(wu > 0, mag_c / mag_u, 1.0),
+                       rtol=1e-12, atol=0)
+
+
+def test_walker_chunks_step_like_the_whole_population(tiny):
+    """A step of walkers w0 .. w0 + n - 1 taken alone, with w0 naming their
+    place in the population, equals their rows of the whole population's step
+    (without the comb, which couples walkers): the random streams belong to
+    the walker index, so a population can be stepped in chunks."""
+    nw, P, seed = 6, 4, 31
+    st = O.init_state(tiny, nw, P, seed)
+    kw = dict(dtau=0.01, weight_mode=O.WEIGHT_LOCAL, xbar_cap=1.0, eloc_cap=(-3.0, 2.0))
+    for i in range(3):
+        whole, rec = O.step(tiny, st, seed, i, **kw)
+        parts = []
+        for a, b in ((0, 2), (2, 6)):
+            sub = O.State(st.phi[a:b], st.w[a:b], st.y[a:b], st.phiT[a:b], st.logov[a:b])
+            parts.append(O.step(tiny, sub, seed, i, w0=a, **kw)[0])
+        for name in ("phi", "w", "y", "phiT", "logov"):
+            joined = np.concatenate([getattr(q, name) for q in parts])
+            assert np.array_equal(joined, getattr(whole, name)), (i, name)
+        st = whole
+    # a wrong offset gives other streams
+    sub = O.State(st.phi[2:6], st.w[2:6], st.y[2:6], st.phiT[2:6], st.logov[2:6])
+    other = O.step(tiny, sub, seed, 3, w0=0, **kw)[0]
+    ref = O.step(tiny, sub, seed, 3, w0=2, **kw)[0]
+    assert not np.array_equal(other.y, ref.y)
+
+
 def test_comb_population_control_properties():
     """The comb keeps the total weight, gives walker k either floor or ceil of
     nw W_k / sum W copies, none to zero-weight walkers, and with a cap first
