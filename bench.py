@@ -7,8 +7,9 @@ Metropolis sweep of every path with hand-off -> QR every 10 steps -> comb,
 for the FP64 workload M=64, N=16 per spin, 256 Cholesky vectors, K=64
 Gaussian hidden variables, 512 walkers x 8 paths, tau=0.005, random-walk
 proposal of step 0.3 (the FP64 random-walk form whose energy error fixes the
-reference error bar).  Inputs are synthetic (seeded generator, see
-afqmc_inputs) and resident in HBM before the timed region.
+reference error bar), in the stabilised form (local-energy weights, force-bias
+and local-energy caps, see STABLE).  Inputs are synthetic (seeded generator,
+see afqmc_inputs) and resident in HBM before the timed region.
 
 Prints one JSON line.  The roofline object refers to the dominant kernel, the
 Cholesky contraction, timed with HIP events on the library's stream around
@@ -63,6 +64,27 @@ TRAFFIC = {
 RW_STEP_FP64 = 0.3
 PROPOSAL_OVERRIDE = {"fp64": (1, RW_STEP_FP64), "fp64-prior": (0, None)}
 
+# The stabilised form of the runs (a reading outside the paper, which states no
+# stabilisation): the hybrid weight's overlap-ratio estimator sum_p O_p(phi') /
+# |O_p(phi)| / sum_p S_p has a denominator that approaches zero as the paths'
+# phases spread, so a few walkers take the whole weight and the comb collapses
+# the population; local-energy weights with the usual caps keep the runs
+# stationary.  Stated beside every figure of the per-step workloads.
+STABLE = {"weights": "local energy", "xbar_cap": 1.0,
+          "eloc_cap": "Re E_L within E_T +- sqrt(2/tau)",
+          "e_t_schedule": "0 and no cap for steps 0..19, then the mixed estimate of the last "
+                          "<= 100 steps, refreshed after step 19 and every 100 steps",
+          "comb_every": 1, "comb_weights_reset_to": 1.0, "weight_cap": 0.0}
+
+
+def oracle_form(proposal, rw_step, n_pc, dtau):
+    """Keyword arguments of the oracle's step for the stabilised form (the
+    CPU baseline's E_L cap sits at 0: its cost does not depend on the centre)."""
+    import math
+    return dict(proposal=proposal, rw_step=rw_step, n_pc=n_pc, weight_mode=3,
+                xbar_cap=STABLE["xbar_cap"], eloc_cap=(0.0, math.sqrt(2.0 / dtau)))
+
+
 # The departures of the synthetic inputs and run loop from the configurations
 # as written, stated beside every figure of the per-step workloads.
 L_SCALE = "0.3*sqrt(8/M)/sqrt(g+1)"
@@ -96,7 +118,7 @@ def _oracle_chunk(args):
     """One host process of the CPU baseline: the oracle's whole steps on its own
     walker chunk (one BLAS thread), one untimed step first.  Returns the time
     of the timed steps."""
-    widx, n_walkers, seed, n_steps, proposal, rw_step, n_pc = args
+    widx, n_walkers, seed, n_steps, form = args
     from threadpoolctl import threadpool_limits
     import afqmc_inputs as ai
     from oracle import afqmc_oracle as O
@@ -106,7 +128,7 @@ def _oracle_chunk(args):
         Eh = O.half_kinetic(sys_, run.dtau)
         h1p = O.h1_eff(sys_)
         kw = dict(n_taylor=run.n_taylor, n_sweep=run.n_sweep, n_qr=run.n_qr, Eh=Eh, h1p=h1p,
-                  proposal=proposal, rw_step=rw_step, n_pc=n_pc)
+                  **form)
         st, _ = O.step(sys_, st, seed, 0, run.dtau, **kw)
         t0 = time.perf_counter()
         for i in range(1, 1 + n_steps):
@@ -123,17 +145,17 @@ def host_cores():
     return max(1, min(n, 16))
 
 
-def cpu_baseline(widx, seed, proposal, rw_step, n_pc, per_core=4, n_steps=2):
+def cpu_baseline(widx, seed, form, per_core=4, n_steps=6):
     """Time the oracle's whole steps on a bounded walker sample: per_core
     walkers (all paths) on each host core, as independent chunks in separate
     processes (walkers are independent within a step; each chunk combs its own
-    walkers), one untimed step, then n_steps timed steps."""
+    walkers), one untimed step, then n_steps timed steps.  form: the oracle
+    step's keyword arguments of the run's form (proposal, weights, caps)."""
     import multiprocessing as mp
     import afqmc_inputs as ai
     sys_, run = ai.workload(widx)
     cores = host_cores()
-    jobs = [(widx, per_core, seed + 7919 * c, n_steps, proposal, rw_step, n_pc)
-            for c in range(cores)]
+    jobs = [(widx, per_core, seed + 7919 * c, n_steps, form) for c in range(cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -406,6 +428,124 @@ def mixed_study(args):
     print(json.dumps(out))
 
 
+def fixed_error_study(args):
+    """Walker-steps/s at fixed energy error on the FP64 workload's system (M=64,
+    N=16, 256 vectors, K=64, 512 walkers x 8 paths, tau = 0.005), every form in
+    the stabilised form (STABLE): the FP64 random-walk form, which fixes the
+    error eps, and the mixed-precision forms (FP32, split-BF16 and BF16
+    contraction products with FP32 trial series and propagation and complex64
+    walkers) and the learned proposal (BF16 network trained on the GPU during
+    the warm-up, then frozen; FP32 products).  Each form runs n_seeds
+    independent runs of warmup + steps steps; a run's energy is its mixed
+    estimate over the measured steps; sigma is the spread of those energies
+    over the seeds (sample standard deviation); eps is the FP64 random-walk
+    form's sigma; a form's time to eps is T (sigma / eps)^2 with T the wall
+    time of one run's measured steps, and its walker-steps/s at fixed error is
+    walkers x measured steps / time to eps.  Mean energies are compared with
+    the FP64 form's within their combined errors."""
+    import torch
+    import afqmc_inputs as ai
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+
+    sys_, run = ai.workload(1)
+    nw, P = run.W, run.P
+    n_seeds, n_eq, n_meas = args.seeds, args.warmup, args.steps
+    s_train = 0.5
+
+    def one(form, seed):
+        prec = {"fp64": A.PREC_FP64, "fp32": A.PREC_FP32, "bf16x3": A.PREC_BF16X3,
+                "bf16": A.PREC_BF16, "learned": A.PREC_FP32}[form]
+        common = dict(n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=STABLE["xbar_cap"],
+                      precision=prec, walker_c64=form in ("fp32", "bf16x3", "bf16"),
+                      weight_mode=A.WEIGHT_LOCAL)
+        if form == "learned":
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=s_train,
+                            **common)
+            p = ai.mlp_params(np.random.default_rng(8), sys_.M, sys_.K, last_scale=0.0)
+            p["b3"][sys_.K:] = 4 * np.arctanh(np.log(s_train * s_train) / 4)
+            A.afqmc_mlp_init(ctx, A.PREC_BF16, A.mlp_pack(p), lr=1e-3)
+            A.afqmc_mlp_set_training(ctx, True)
+        else:
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_RW, rw_step=RW_STEP_FP64,
+                            **common)
+        st = D.init_walkers(ctx, sys_.phi0, nw, seed)
+        est = torch.zeros(n_eq + n_meas, 2, dtype=torch.float64, device="cuda")
+        ref = D.EnergyReference(ctx)
+        for i in range(n_eq):
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_qr=run.n_qr, n_pc=1)
+            ref.update(i, est)
+        if form == "learned":  # freeze: network moves only from here on
+            trained = A.afqmc_mlp_get_params(ctx)
+            ctx.close()
+            ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=0.0,
+                            **common)
+            A.afqmc_mlp_init(ctx, A.PREC_BF16, trained)
+            ref.attach(ctx)
+        nacc = torch.zeros(nw, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_eq, n_eq + n_meas):
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_qr=run.n_qr, n_pc=1)
+            ref.update(i, est)
+            nacc += st.nacc
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        e = est[n_eq:].cpu().numpy()
+        en = float(e[:, 0].sum() / e[:, 1].sum())
+        return {"energy": en, "seconds": dt, "reblocked": reblock(e[:, 0] / e[:, 1]),
+                "acceptance": float(nacc.sum().item()) / (n_meas * nw * P),
+                "finite": bool(np.all(np.isfinite(e)))}
+
+    forms = ["fp64", "fp32", "bf16x3", "bf16", "learned"]
+    res = {}
+    for form in forms:
+        runs = []
+        for k in range(n_seeds):
+            r = one(form, 7001 + 97 * k)
+            runs.append(r)
+            print(f"{form} seed {k}: E = {r['energy']:.4f} (reblocked +- {r['reblocked']:.4f}), "
+                  f"{1e3 * r['seconds'] / n_meas:.2f} ms/step, acceptance {r['acceptance']:.3f}",
+                  file=sys.stderr, flush=True)
+        en = np.array([r["energy"] for r in runs])
+        T = float(np.mean([r["seconds"] for r in runs]))
+        res[form] = {"energies": en.tolist(), "energy": float(en.mean()),
+                     "sigma_run": float(en.std(ddof=1)),
+                     "error_of_mean": float(en.std(ddof=1) / np.sqrt(n_seeds)),
+                     "reblocked_sigma_run_mean": float(np.mean([r["reblocked"] for r in runs])),
+                     "seconds_per_run": T, "ms_per_step": 1e3 * T / n_meas,
+                     "walker_steps_per_s": nw * n_meas / T,
+                     "acceptance": float(np.mean([r["acceptance"] for r in runs])),
+                     "finite": all(r["finite"] for r in runs)}
+    eps = res["fp64"]["sigma_run"]
+    for form in forms:
+        d = res[form]
+        d["time_to_eps_s"] = d["seconds_per_run"] * (d["sigma_run"] / eps) ** 2
+        d["walker_steps_per_s_at_eps"] = nw * n_meas / d["time_to_eps_s"]
+        d["vs_fp64_at_eps"] = d["walker_steps_per_s_at_eps"] / res["fp64"]["walker_steps_per_s_at_eps"]
+        diff = d["energy"] - res["fp64"]["energy"]
+        comb = float(np.hypot(d["error_of_mean"], res["fp64"]["error_of_mean"]))
+        d["energy_difference_vs_fp64"] = diff
+        d["combined_error"] = comb
+        d["agrees_within_3_sigma"] = bool(abs(diff) <= 3 * comb)
+    best = max((f for f in forms if f != "fp64"), key=lambda f: res[f]["walker_steps_per_s_at_eps"])
+    out = {
+        "metric": METRIC, "value": res[best]["walker_steps_per_s_at_eps"], "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": n_meas, "warmup": n_eq,
+        "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "mixed (see forms)", "data": "synthetic",
+        "config": {"workload": f"fixed-error-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
+                               f"-W{nw}-P{P}-dtau{run.dtau}", "walkers": nw, "paths": P,
+                   "seeds_per_form": n_seeds, "rw_step": RW_STEP_FP64,
+                   "network_train_step": s_train, "L_scale": L_SCALE, **STABLE},
+        "value_form": best,
+        "eps": eps,
+        "forms": res,
+    }
+    print(json.dumps(out))
+
+
 def uneven_study(args):
     """Uneven batch (32 systems, M in [24, 160], N = M/4, 4M vectors, K = M/2,
     walkers log-uniform in [64, 1024], 4 paths): aggregate walker-steps/s of the
@@ -515,7 +655,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fp64",
-                    choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "mixed-study"])
+                    choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "mixed-study",
+                                                 "fixed-error"])
+    ap.add_argument("--seeds", type=int, default=6,
+                    help="independent runs per form (fixed-error workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (the plain copy kernel that "
                          "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -535,7 +678,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and args.workload == "fp64" and not args.copy_calibration:
         prop, rws = PROPOSAL_OVERRIDE["fp64"]
-        cpu = cpu_baseline(1, 2001, prop, rws, 1)
+        cpu = cpu_baseline(1, 2001, oracle_form(prop, rws, 1, ai.workload(1)[1].dtau))
         print(f"cpu baseline: {cpu['value']:.2f} walker-steps/s on {cpu['cores']} cores",
               file=sys.stderr, flush=True)
     if not torch.cuda.is_available():
@@ -563,33 +706,32 @@ def main():
     if args.workload == "mixed-study":
         mixed_study(args)
         return
+    if args.workload == "fixed-error":
+        fixed_error_study(args)
+        return
 
     widx, precision, peak, dtype = WORKLOADS[args.workload]
     sys_, run = ai.workload(widx)
     nw, P, seed = run.W, run.P, 2001
     proposal, rw_step = PROPOSAL_OVERRIDE.get(
         args.workload, (run.proposal, run.rw_step if run.proposal == A.PROPOSAL_RW else None))
-    # population control: comb every step with the weights reset to 1 (a common
-    # factor of all weights, which cancels in the mixed estimator); the FP64
-    # legs use no force-bias or weight cap, the M = 128 and slices legs keep a
-    # force-bias modulus cap of 1 and a weight cap of 4x the mean (their
-    # path-sign averages fall within a few tens of steps)
-    capped = args.workload not in ("fp64", "fp64-prior")
-    xbar_cap, n_pc, w_cap = (1.0, 1, 4.0) if capped else (0.0, 1, 0.0)
+    # the stabilised form of every per-step leg: local-energy weights, force-bias
+    # modulus capped at 1, Re E_L capped at E_T +- sqrt(2 / tau) with the E_T
+    # schedule of driver.EnergyReference, comb every step with the weights reset
+    # to 1 (a common factor, which cancels in the mixed estimator)
+    xbar_cap, n_pc, w_cap = STABLE["xbar_cap"], STABLE["comb_every"], 0.0
     c64 = precision != 0 and getattr(sys_, "trial_kind", 0) == 0
     ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap,
-                    precision=precision, proposal=proposal, rw_step=rw_step, walker_c64=c64)
+                    precision=precision, proposal=proposal, rw_step=rw_step, walker_c64=c64,
+                    weight_mode=A.WEIGHT_LOCAL)
     st = D.init_walkers(ctx, sys_.phi0, nw, seed)
     est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
+    ref = D.EnergyReference(ctx)
 
-    e_shift = 0.0
     for i in range(args.warmup):
-        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr,
-               n_pc=n_pc, w_cap=w_cap)
-        if i == 0:
-            torch.cuda.synchronize()
-            e0 = est[0].cpu().numpy()
-            e_shift = float(e0[0] / e0[1])
+        D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=run.n_sweep,
+               n_qr=run.n_qr, n_pc=n_pc, w_cap=w_cap)
+        ref.update(i, est)
     torch.cuda.synchronize()
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -597,8 +739,9 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         i = args.warmup + k
-        D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=run.n_sweep, n_qr=run.n_qr,
-               contract_events=evs[k], n_pc=n_pc, w_cap=w_cap)
+        D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=run.n_sweep,
+               n_qr=run.n_qr, contract_events=evs[k], n_pc=n_pc, w_cap=w_cap)
+        ref.update(i, est)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -609,7 +752,7 @@ def main():
     energies = e[:, 0] / e[:, 1]
     if not np.all(np.isfinite(energies)):
         w = st.w.cpu().numpy()
-        print("non-finite energy in the benchmark run:", e.tolist(), "e_shift", e_shift,
+        print("non-finite energy in the benchmark run:", e.tolist(), "e_shift", ref.e_shift,
               "weights: min", w.min(), "max", w.max(), "n_zero", int((w == 0).sum()),
               "n_nonfinite", int((~np.isfinite(w)).sum()), file=sys.stderr)
         sys.exit(1)
@@ -635,9 +778,8 @@ def main():
                    "n_chol": sys_.n_chol, "K": sys_.K,
                    "proposal": "random walk" if proposal == A.PROPOSAL_RW else "prior",
                    "rw_step": rw_step if proposal == A.PROPOSAL_RW else None,
-                   "L_scale": L_SCALE, "L_scale_note": L_SCALE_NOTE,
-                   "xbar_cap": xbar_cap, "comb_every": n_pc, "comb_weights_reset_to": 1.0,
-                   "weight_cap": w_cap, "walkers_complex64": c64},
+                   "L_scale": L_SCALE, "L_scale_note": L_SCALE_NOTE, **STABLE,
+                   "walkers_complex64": c64},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload),

@@ -205,6 +205,19 @@ afqmc_status afqmc_numeric_flags(afqmc_ctx ctx, int32_t nw, int32_t* flags, int3
  * asynchronous and never report numerical events themselves. */
 afqmc_status afqmc_set_numeric_check(afqmc_ctx ctx, int32_t on);
 
+/* Local-energy cap (a stabilisation the paper does not state; the usual
+ * phaseless-AFQMC practice of clipping E_L at E_T +- sqrt(2 / tau)): with
+ * half_width > 0, every walker's E_L that afqmc_local_energy (and its
+ * static variant) writes has its real part clipped to
+ * [center - half_width, center + half_width] before it reaches the caller,
+ * the estimator or the local-energy weight; the imaginary part, the per-path
+ * E_p and non-finite values (which set AFQMC_NUMERIC_ELOC) are not changed.
+ * half_width = 0 (the default) turns it off.  The setting belongs to the
+ * context and holds for every later call until changed; centre and width
+ * must be finite and width >= 0 (AFQMC_E_INVALID otherwise, setting
+ * unchanged). */
+afqmc_status afqmc_set_eloc_cap(afqmc_ctx ctx, double center, double half_width);
+
 /* Initial paths y ~ p_T (stream INIT of the counter layout below). */
 afqmc_status afqmc_sample_prior(afqmc_ctx ctx, int32_t nw, uint64_t seed, double* y);
 

@@ -63,6 +63,7 @@ EXPORTS = {
     "afqmc_sample_prior": (c_int, [c_void_p, c_int32, c_uint64, c_void_p]),
     "afqmc_numeric_flags": (c_int, [c_void_p, c_int32, c_void_p, POINTER(c_int32)]),
     "afqmc_set_numeric_check": (c_int, [c_void_p, c_int32]),
+    "afqmc_set_eloc_cap": (c_int, [c_void_p, c_double, c_double]),
     "afqmc_trial_build": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_overlap": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "afqmc_green": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -282,6 +283,12 @@ def afqmc_numeric_flags(ctx, nw):
 
 def afqmc_set_numeric_check(ctx, on):
     ctx._call("afqmc_set_numeric_check", 1 if on else 0)
+
+
+def afqmc_set_eloc_cap(ctx, center, half_width):
+    """Clip Re E_L to [center - half_width, center + half_width] in every
+    later local-energy call of ctx (half_width = 0: off)."""
+    ctx._call("afqmc_set_eloc_cap", float(center), float(half_width))
 
 
 def afqmc_sample_prior(ctx, nw, seed, y):

@@ -513,6 +513,15 @@ afqmc_status afqmc_set_numeric_check(afqmc_ctx c, int32_t on) {
   return AFQMC_OK;
 }
 
+afqmc_status afqmc_set_eloc_cap(afqmc_ctx c, double center, double half_width) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  if (!(half_width >= 0.0) || !__builtin_isfinite(half_width) || !__builtin_isfinite(center))
+    return fail(c, AFQMC_E_INVALID, "the local-energy cap needs a finite centre and a finite width >= 0");
+  c->ecap_center = center;
+  c->ecap_half = half_width;
+  return AFQMC_OK;
+}
+
 afqmc_status afqmc_sample_prior(afqmc_ctx c, int32_t nw, uint64_t seed, double* y) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);

@@ -16,6 +16,8 @@ struct afqmc_ctx_s {
   int M = 0, N = 0, G = 0, K = 0, P = 0, hidden_kind = 0;
   int MT = 0;  // M rounded up to a multiple of 16
   double coupling = 0, dtau = 0, rw_step = 0, xbar_cap = 0;
+  // Re E_L clipped to [ecap_center - ecap_half, ecap_center + ecap_half] when ecap_half > 0
+  double ecap_center = 0, ecap_half = 0;
   int n_taylor = 10, weight_mode = 0, proposal = 0, precision = 0;
 
   // device copies owned by the context

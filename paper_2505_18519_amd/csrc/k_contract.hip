@@ -249,9 +249,11 @@ k_contract(int n_samples, int M, int N, int G, const double* __restrict__ Lpad,
 // Walker-level estimates over the P paths (Eq. local-obs, then Eq. shift1):
 // S_p = exp(i Im l_p) (0 if singular), xbar_g = -i sqrt(tau) sum S vb / sum S,
 // E_L = sum S E_p / sum S.  One workgroup of 64 threads per walker.  A
-// non-finite E_L or force-bias component sets the walker's flag bits.
+// non-finite E_L or force-bias component sets the walker's flag bits.  With
+// ecap_half > 0 a finite Re E_L is clipped to [ecap_lo, ecap_hi] (Im E_L kept).
 __global__ void __launch_bounds__(64)
-k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* __restrict__ vb,
+k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, double ecap_half,
+          double ecap_lo, double ecap_hi, const double* __restrict__ vb,
           const double* __restrict__ ep, const double* __restrict__ logov,
           double* __restrict__ xbar, double* __restrict__ eloc, int* __restrict__ flags) {
   __shared__ double s_S[64][2];
@@ -292,9 +294,10 @@ k_combine(int nw, int P, int G, double sqrt_tau, double xbar_cap, const double* 
     cplx num = cmk(0.0, 0.0);
     for (int p = 0; p < P; ++p)
       num = cfma(num, cmk(s_S[p][0], s_S[p][1]), cld(ep + ((size_t)w * P + p) * 2));
-    const cplx el = good ? cdiv(num, den) : cmk(0.0, 0.0);
-    cst(eloc + (size_t)w * 2, el);
+    cplx el = good ? cdiv(num, den) : cmk(0.0, 0.0);
     if (!(__builtin_isfinite(el.re) && __builtin_isfinite(el.im))) bits |= AFQMC_NUMERIC_ELOC;
+    else if (ecap_half > 0.0) el.re = fmin(fmax(el.re, ecap_lo), ecap_hi);
+    cst(eloc + (size_t)w * 2, el);
   }
   if (bits != 0 && flags != nullptr) flags[w] |= bits;
 }
@@ -328,6 +331,7 @@ hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const 
   if (nw <= 0) return hipSuccess;
   if (c->P > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_combine, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->G, sqrt(c->dtau),
-                     c->xbar_cap, vb, ep, logov, xbar, eloc, flags);
+                     c->xbar_cap, c->ecap_half, c->ecap_center - c->ecap_half,
+                     c->ecap_center + c->ecap_half, vb, ep, logov, xbar, eloc, flags);
   return hipGetLastError();
 }

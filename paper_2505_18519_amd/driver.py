@@ -185,3 +185,42 @@ def measure_extra(m: Measurement, st: Walkers, seed: int, i: int, out: torch.Ten
     A.afqmc_green(c, nw, st.phi, m.phiT, m.logov, m.theta)
     A.afqmc_local_energy(c, nw, m.phiT, m.theta, m.logov, m.eloc, None, None)
     A.afqmc_estimator_corrected(c, nw, st.w, m.eloc, m.logov, P, st.logov, out, m.R)
+
+
+class EnergyReference:
+    """Trial energy E_T of a long run and the local-energy cap around it.
+
+    Steps 0..19 run without the cap and with E_T = 0.  After step 19, and
+    after every step i with (i + 1) % 100 == 0 from step 99 on, E_T becomes
+    the mixed estimate over the last (at most) 100 steps, sum num / sum den
+    of est[max(0, i - 99) .. i]; from then on the context clips Re E_L to
+    E_T +- width (afqmc_set_eloc_cap; width = sqrt(2 / tau) by default, the
+    usual phaseless-AFQMC cap) and e_shift = E_T enters the weights.  The
+    schedule reads the estimator sums back to the host only at those steps.
+    """
+
+    def __init__(self, ctx: A.Context, width: "float | None" = None):
+        import math
+        self.ctx = ctx
+        self.width = math.sqrt(2.0 / ctx.dtau) if width is None else float(width)
+        self.e_t = None
+
+    @property
+    def e_shift(self) -> float:
+        return 0.0 if self.e_t is None else self.e_t
+
+    def attach(self, ctx: A.Context) -> None:
+        """Carry E_T and the cap over to another context of the same run."""
+        self.ctx = ctx
+        if self.e_t is not None:
+            A.afqmc_set_eloc_cap(ctx, self.e_t, self.width)
+
+    def update(self, i: int, est: torch.Tensor) -> None:
+        """After step i; est: device float64 [>= i + 1, 2] of the run's sums."""
+        if not (i == 19 or (i >= 99 and (i + 1) % 100 == 0)):
+            return
+        seg = est[max(0, i - 99):i + 1].sum(0).cpu()
+        num, den = float(seg[0]), float(seg[1])
+        if den > 0.0 and num == num:
+            self.e_t = num / den
+            A.afqmc_set_eloc_cap(self.ctx, self.e_t, self.width)

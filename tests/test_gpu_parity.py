@@ -510,6 +510,90 @@ def test_force_bias_cap():
 
 
 
+def test_local_energy_cap():
+    """Re E_L clipped to E_T +- d in the context (afqmc_set_eloc_cap) against
+    the oracle's capped walker estimates, with a window narrow enough that
+    walkers fall on both sides of it; Im E_L, the force bias and the per-path
+    E_p are unchanged; width 0 turns the cap off again."""
+    _say("eloc cap")
+    from paper_2505_18519_amd import afqmc as A
+    s = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5)
+    P, nw, dtau = 3, 12, 0.05
+    ctx = make_ctx(s, P, nw, dtau=dtau)
+    rng, phi, y = state(s, P, nw, 12, spread=1.5)
+    phiT = O.trial_det(s, y)
+    ell, theta = O.green(phiT, phi)
+    vb, ep = O.sample_contraction(s, phiT, theta, ell)
+    _, e0 = O.walker_estimates(vb, ep, ell, dtau)
+    et, d = float(np.median(e0.real)), 0.4 * float(np.std(e0.real))
+    xbar, eloc = O.walker_estimates(vb, ep, ell, dtau, eloc_cap=(et, d))
+    inside = np.abs(e0.real - et) <= d
+    assert 0 < inside.sum() < nw
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_ep = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, s.n_chol, dtype=torch.complex128, device="cuda")
+    A.afqmc_set_eloc_cap(ctx, et, d)
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dev(theta), dev(ell), d_el, d_ep, d_xb)
+    torch.cuda.synchronize()
+    g = host(d_el)
+    assert np.abs(g - eloc).max() <= TOL * max(np.abs(eloc).max(), 1.0)
+    assert np.all(g.real[~inside] == eloc.real[~inside])  # the bounds themselves
+    assert np.abs(host(d_ep) - ep).max() <= TOL * max(np.abs(ep).max(), 1.0)
+    for w in range(nw):
+        assert rel(host(d_xb)[w], xbar[w]) <= TOL
+    A.afqmc_set_eloc_cap(ctx, et, 0.0)
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dev(theta), dev(ell), d_el, None, None)
+    torch.cuda.synchronize()
+    assert np.abs(host(d_el) - e0).max() <= TOL * max(np.abs(e0).max(), 1.0)
+    with pytest.raises(A.AfqmcError):
+        A.afqmc_set_eloc_cap(ctx, et, -1.0)
+    with pytest.raises(A.AfqmcError):
+        A.afqmc_set_eloc_cap(ctx, float("nan"), 1.0)
+
+
+@pytest.mark.parametrize("name", ["gauss-M20-rw", "cfg-M64-rw"])
+def test_stabilised_trajectory_matches_oracle(name):
+    """40 whole steps of the stabilised local-energy form (force-bias modulus
+    capped at 1, Re E_L capped around E_T, comb every step with weights reset
+    to 1): E_T and a deliberately narrow cap window are set after steps 4 and
+    19 from the run's own estimates, so that walkers are clipped; per-step
+    estimator sums, then paths and weights, against the oracle's steps."""
+    _say("stabilised trajectory", name)
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+    if name == "gauss-M20-rw":
+        s, P, nw, dtau = ai.small_gaussian(M=20, N=5, n_chol=24, K=8, seed=5), 4, 12, 0.01
+    else:
+        s, P, nw, dtau = ai.workload(1)[0], 8, 6, 0.005
+    seed, width = 2003, 0.3
+    ctx = A.Context(s, P, dtau, max_walkers=nw, weight_mode=3, proposal=1, rw_step=0.3,
+                    xbar_cap=1.0)
+    st = D.init_walkers(ctx, s.phi0, nw, seed)
+    ost = O.init_state(s, nw, P, seed)
+    est = torch.zeros(40, 2, dtype=torch.float64, device="cuda")
+    e_t, clipped = None, 0
+    for i in range(40):
+        cap = None if e_t is None else (e_t, width)
+        D.step(ctx, st, seed, i, est[i], e_shift=e_t or 0.0, n_sweep=1, n_qr=10, n_pc=1)
+        ost, rec = O.step(s, ost, seed, i, dtau, n_taylor=10, n_sweep=1, n_qr=10,
+                          e_shift=e_t or 0.0, proposal=1, rw_step=0.3, weight_mode=3,
+                          xbar_cap=1.0, n_pc=1, eloc_cap=cap)
+        torch.cuda.synchronize()
+        g = host(est[i])
+        e_ref = rec["e_num"] / rec["e_den"]
+        assert abs(g[0] / g[1] - e_ref) <= TOL * max(abs(e_ref), 1.0), (i, g, e_ref)
+        assert abs(g[1] - rec["e_den"]) <= TOL * rec["e_den"], i
+        if cap is not None:
+            clipped += int(np.sum(np.abs(rec["eloc"].real - e_t) >= width * (1 - 1e-12)))
+        if i in (4, 19):
+            e_t = e_ref
+            A.afqmc_set_eloc_cap(ctx, e_t, width)
+    assert clipped > 0
+    assert np.abs(host(st.y) - ost.y).max() <= 1e-12 * max(np.abs(ost.y).max(), 1.0)
+    gw = host(st.w)
+    assert np.abs(gw - ost.w).max() <= TOL * np.abs(ost.w).max()
+
+
 MIXED_TOL = 1e-4
 MIXED = {"fp32": (1, MIXED_TOL), "bf16x3": (3, MIXED_TOL), "bf16": (2, BF16_TOL)}
 # FP32-product trial series and walker propagation (mixed-precision contexts):
