@@ -443,6 +443,272 @@ k_contract_g(int n_samples, int M, int N, int G, int MT, const T* __restrict__ L
     for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// k_contract_gs: the FP64 contraction of real trials for shapes whose operands
+// do not fit in registers (three column tiles, N > 32: a wavefront would need
+// Phi_T for every column tile and its Theta^s[:, jt] at once, past the 256
+// registers of two wavefronts per SIMD).  Same workgroup layout, LDS tiles and
+// tail as k_contract_g, but no operand stays in registers across vectors: every
+// stage-1 step loads its L rows and Phi_T entries, every stage-2 step its
+// Theta entries, from global memory (L2: Phi_T and Theta are reused by every
+// vector of the path, L by every path), one 16-wide k tile ahead of the
+// products, and the first tile of the next vector (and of the next stage 2)
+// ahead of the barriers.  Stage 1 visits the k tiles in the outer loop so that
+// each Phi_T entry feeds the wavefront's row tiles together.
+template <int KT, int NTC>
+__global__ void __launch_bounds__(128 * NTC)
+k_contract_gs(int n_samples, int M, int N, int G, int MT, const double* __restrict__ Lpad,
+              const double* __restrict__ phiT, const double* __restrict__ theta,
+              const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
+  constexpr int NWV = 2 * NTC;                 // wavefronts
+  constexpr int NT = 16 * NTC;
+  constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
+  extern __shared__ double smem[];
+  double* sY = smem;                           // [MT][NT]
+  double* sF = sY + MT * NT;                   // [2][NT][NT+1][2]
+  double* sD = sF + 2 * NT * (NT + 1) * 2;     // [16][NWV*16][2]
+
+  const int s = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int sp = wave & 1, jt = wave >> 1;
+  if (s >= n_samples) return;  // whole block exits together
+  const bool active = !__builtin_isinf(logov[2 * s]);
+  const size_t slab = (size_t)MT * MT;
+
+  // stage-1 operands of k tile t: L rows 16 t + 4 r + g of the wavefront's row
+  // tiles (clamped in range; tiles past KT are never used) and Phi_T entries
+  // (0 outside M x N or for an inactive path)
+  struct S1 {
+    double a[S1MAX][4];
+    double b[NTC][4];
+  };
+  auto load1 = [&](const double* Lg, int t, S1& o) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * t + 4 * r + g;
+#pragma unroll
+      for (int q = 0; q < S1MAX; ++q) {
+        const int tp = min(wave + NWV * q, KT - 1);
+        o.a[q][r] = Lg[(size_t)m * MT + 16 * tp + c];
+      }
+      // clamped addresses and bit-masked values: unconditional loads, in flight together
+      const bool okm = active && m < M;
+      const int mc = min(m, M - 1);
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        const int n = 16 * ct + c;
+        o.b[ct][r] = keep_if(phiT[((size_t)s * M + mc) * N + min(n, N - 1)], okm && n < N);
+      }
+    }
+  };
+  // stage-2 operands of k tile t: Theta^sp[16 t + 4 r + g][16 jt + c]
+  struct S2 {
+    double re[4], im[4];
+  };
+  auto load2 = [&](int t, S2& o) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * t + 4 * r + g, n = 16 * jt + c;
+      const bool ok = active && m < M && n < N;
+      const double2 x = *reinterpret_cast<const double2*>(
+          theta + ((((size_t)s * 2 + sp) * M + min(m, M - 1)) * N + min(n, N - 1)) * 2);
+      o.re[r] = keep_if(x.x, ok);
+      o.im[r] = keep_if(x.y, ok);
+    }
+  };
+
+  S1 p1[2];
+  S2 p2[2];
+  load1(Lpad, 0, p1[0]);
+  load2(0, p2[0]);
+  double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
+  for (int gam = 0; gam <= G; ++gam) {
+    const double* Lg = Lpad + (size_t)gam * slab;
+    const double* Ln = Lpad + (size_t)min(gam + 1, G) * slab;
+    // stage 1: Y^T tiles (tp, ct) of the wavefront's row tiles
+    dx4 y1[S1MAX][NTC];
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = dx4_zero();
+    // products of tile t from `cur` while `nxt` receives tile t + 1 (or the
+    // next vector's first); tiles in pairs through the two buffers
+    auto step1 = [&](int t, S1& cur, S1& nxt) {
+      if (t + 1 < KT) load1(Lg, t + 1, nxt);
+      else load1(Ln, 0, nxt);
+      if (active)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < S1MAX; ++q)
+            if (wave + NWV * q < KT)
+#pragma unroll
+              for (int ct = 0; ct < NTC; ++ct)
+                y1[q][ct] = mfma_f64(cur.a[q][r], cur.b[ct][r], y1[q][ct]);
+    };
+#pragma unroll 1
+    for (int t = 0; t + 1 < KT; t += 2) {
+      step1(t, p1[0], p1[1]);
+      step1(t + 1, p1[1], p1[0]);
+    }
+    if (KT & 1) {  // the last tile; the next vector's first then moves to slot 0
+      step1(KT - 1, p1[0], p1[1]);
+      p1[0] = p1[1];
+    }
+    __syncthreads();  // the previous vector's stage-2 and transpose reads are done
+#pragma unroll
+    for (int q = 0; q < S1MAX; ++q) {
+      const int tp = wave + NWV * q;
+      if (tp < KT)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sY[(16 * tp + g + 4 * r) * NT + 16 * ct + c] = y1[q][ct][r];
+    }
+    __syncthreads();
+    // stage 2: f^sp[it][jt] = sum_m Y^T[m][it cols] Theta^sp[m][jt cols]
+    dx4 f[NTC][2];
+#pragma unroll
+    for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = dx4_zero();
+    auto step2 = [&](int t, S2& cur, S2& nxt) {
+      load2(t + 1 < KT ? t + 1 : 0, nxt);  // or the next vector's first tile
+      if (active)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = 16 * t + 4 * r + g;
+#pragma unroll
+          for (int it = 0; it < NTC; ++it) {
+            const double a = sY[m * NT + 16 * it + c];
+            f[it][0] = mfma_f64(a, cur.re[r], f[it][0]);
+            f[it][1] = mfma_f64(a, cur.im[r], f[it][1]);
+          }
+        }
+    };
+#pragma unroll 1
+    for (int t = 0; t + 1 < KT; t += 2) {
+      step2(t, p2[0], p2[1]);
+      step2(t + 1, p2[1], p2[0]);
+    }
+    if (KT & 1) {
+      step2(KT - 1, p2[0], p2[1]);
+      p2[0] = p2[1];
+    }
+    // diagonal of f^sp in tile (jt, jt): element (g + 4 r, c) with g + 4 r == c
+    double d_re = 0.0, d_im = 0.0;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+      if (it == jt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (g + 4 * r == c) {
+            d_re = f[it][0][r];
+            d_im = f[it][1][r];
+          }
+    if (gam == G) {
+      d_re = wave_sum(d_re);
+      d_im = wave_sum(d_im);
+      // one-body term: both spins' traces, gathered through LDS below
+      if (lane == 0) {
+        sD[(wave * 16) * 2] = d_re;
+        sD[(wave * 16) * 2 + 1] = d_im;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w = 0; w < NWV; ++w) {
+          e1_re += sD[(w * 16) * 2];
+          e1_im += sD[(w * 16) * 2 + 1];
+        }
+      }
+      break;
+    }
+    // stage f^sp[:, jt] in LDS for the transpose, and the diagonal partials
+    double* Fs = sF + (size_t)sp * NT * (NT + 1) * 2;
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + g + 4 * r, j = 16 * jt + c;
+        Fs[(i * (NT + 1) + j) * 2] = f[it][0][r];
+        Fs[(i * (NT + 1) + j) * 2 + 1] = f[it][1][r];
+      }
+    if ((c & 3) == g) {  // the lane group holding row c of the diagonal tile
+      double* d = sD + ((size_t)(gam & 15) * NWV * 16 + wave * 16 + c) * 2;
+      d[0] = d_re;
+      d[1] = d_im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NTC; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + g + 4 * r, j = 16 * jt + c;
+        const double tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const double ar = f[it][0][r], ai = f[it][1][r];
+        ex_re += ar * tr_ - ai * ti_;
+        ex_im += ar * ti_ + ai * tr_;
+      }
+    // every 16 vectors: wavefront 0 reduces the staged diagonals to vb_g
+    if (((gam & 15) == 15 || gam == G - 1) && wave == 0) {
+      const int cnt = (gam & 15) + 1, g0 = gam & ~15;
+      const int gl = lane & 15, part = (lane >> 4) & 1;
+      double v = 0.0;
+      if (lane < 32 && gl < cnt)
+        for (int q = 0; q < NWV * 16; ++q) v += sD[((size_t)gl * NWV * 16 + q) * 2 + part];
+      const double vi = __shfl_down(v, 16, 64);
+      if (lane < 16 && gl < cnt) {
+        vb2_re += v * v - vi * vi;
+        vb2_im += 2.0 * v * vi;
+        double* o = vb + ((size_t)s * G + g0 + gl) * 2;
+        o[0] = v;
+        o[1] = vi;
+      }
+    }
+  }
+  // totals: ex from every lane of every wavefront, vb^2 from wavefront 0
+  ex_re = wave_sum(ex_re);
+  ex_im = wave_sum(ex_im);
+  vb2_re = wave_sum(vb2_re);
+  vb2_im = wave_sum(vb2_im);
+  __syncthreads();
+  if (lane == 0) {
+    sD[wave * 4 + 0] = ex_re;
+    sD[wave * 4 + 1] = ex_im;
+    sD[wave * 4 + 2] = vb2_re;
+    sD[wave * 4 + 3] = vb2_im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double xr = 0.0, xi = 0.0;
+    for (int w = 0; w < NWV; ++w) {
+      xr += sD[w * 4 + 0];
+      xi += sD[w * 4 + 1];
+    }
+    const double br = sD[2], bi = sD[3];
+    double* o = ep + (size_t)s * 2;
+    o[0] = active ? e1_re + 0.5 * br - 0.5 * xr : 0.0;
+    o[1] = active ? e1_im + 0.5 * bi - 0.5 * xi : 0.0;
+  }
+  if (!active)
+    for (int q = threadIdx.x; q < 2 * G; q += blockDim.x) vb[(size_t)s * G * 2 + q] = 0.0;
+}
+
+template <int KT, int NTC>
+hipError_t launch_gs(const afqmc_ctx_s* c, int nw, const double* L, const double* phiT,
+                     const double* theta, const double* logov, double* vb, double* ep) {
+  const int n = nw * c->P;
+  const int NT = 16 * NTC, NWV = 2 * NTC;
+  const size_t lds = ((size_t)c->MT * NT + (size_t)2 * NT * (NT + 1) * 2 +
+                      (size_t)16 * NWV * 16 * 2) * sizeof(double);
+  auto kern = k_contract_gs<KT, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(128 * NTC), lds, c->stream, n, c->M, c->N, c->G, c->MT,
+                     L, phiT, theta, logov, vb, ep);
+  return hipGetLastError();
+}
+
 size_t lds_bytes(int MT, int NTC, size_t tsize, bool ct, bool pr) {
   const int NT = 16 * NTC, NWV = 2 * NTC;
   const int syw = pr ? 48 : NT * (ct ? 2 : 1), fr = pr ? 48 : NT;
@@ -498,9 +764,13 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
     AFQMC_G(2, 2) AFQMC_G(3, 2) AFQMC_G(4, 2)
     AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
     AFQMC_G(9, 1) AFQMC_G(10, 1) AFQMC_G(9, 2) AFQMC_G(10, 2)
-    AFQMC_G(3, 3) AFQMC_G(4, 3) AFQMC_G(5, 3) AFQMC_G(6, 3)
-    AFQMC_G(7, 3) AFQMC_G(8, 3) AFQMC_G(9, 3) AFQMC_G(10, 3)
 #undef AFQMC_G
+    // three column tiles (32 < N <= 48): operands streamed, not register-resident
+#define AFQMC_GS(KK) \
+  if (KT == KK && NTC == 3) return launch_gs<KK, 3>(c, nw, L, phiT, theta, logov, vb, ep);
+    AFQMC_GS(3) AFQMC_GS(4) AFQMC_GS(5) AFQMC_GS(6) AFQMC_GS(7) AFQMC_GS(8) AFQMC_GS(9)
+    AFQMC_GS(10)
+#undef AFQMC_GS
   }
   return hipErrorInvalidValue;
 }
