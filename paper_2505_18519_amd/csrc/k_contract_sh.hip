@@ -17,10 +17,13 @@
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
 // brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
 //
-// k_contract_sh: BCP paths per workgroup share each L slab through LDS.  Per
-// path, 2 * NTC wavefronts (NTC = ceil(N/16)); wavefront w = (spin s = w % 2,
-// column tile jt = w / 2) keeps Theta^s[:, jt] as B operands in registers for
-// the whole loop over g, and Phi_T (all column tiles) as the stage-1 B
+// k_contract_sh: BCP paths per workgroup share each L slab through LDS.  Both
+// spins' products f^s = Y Theta^s share the A operand Y, so their B operands
+// are packed side by side: packed column q < 2N is column q mod N of spin
+// q / N, and a path needs NCP = ceil(2N/16) 16-wide column tiles instead of
+// 2 ceil(N/16) (at N = 24 three instead of four).  Per path, NCP wavefronts;
+// wavefront w keeps packed column tile w of Theta as B operands in registers
+// for the whole loop over g, and Phi_T (all column tiles) as the stage-1 B
 // operands.  Stage 1 (Y_g^T = L_g Phi_T) is split over the path's wavefronts by
 // row tile, its A operands read from the shared slab.  Y_g^T is rounded to the
 // operand form once, as stage 1 leaves it, and stored in LDS in the accumulator
@@ -154,14 +157,17 @@ constexpr int BFL = 8;  // vectors per flush of the staged diagonals
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
-template <int KT, int NTC, int FM>
-__global__ void __launch_bounds__(128 * NTC * BCP)
+// FULL: N = 16 NTC (every column tile full, NCP = 2 NTC), so the packed
+// columns are the two spins' tiles in order and no column or row is padding.
+template <int KT, int NTC, int NCP, int FM, bool FULL>
+__global__ void __launch_bounds__(64 * NCP * BCP)
 k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
                const void* __restrict__ Lop_lo, const double* __restrict__ phiT,
                const double* __restrict__ theta,
                const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   constexpr int MT = 16 * KT;
-  constexpr int NWV = 2 * NTC;                 // wavefronts per path
+  constexpr int NWV = NCP;                     // wavefronts per path
+  constexpr int PW = 16 * NCP + 1;             // row length of the staged f (packed columns)
   constexpr int NWT = NWV * BCP;               // wavefronts per workgroup
   constexpr int NT = 16 * NTC;
   constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
@@ -185,15 +191,20 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   extern __shared__ double smem[];
   V* sL = reinterpret_cast<V*>(smem);                                      // [NB][NP][SV]
   V4* sY = reinterpret_cast<V4*>(sL + NB * NP * SV);                       // [BCP][NB][NP][YT]
-  float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][2][NT][NT+1][2]
-  double* sD = reinterpret_cast<double*>(sF + BCP * 2 * NT * (NT + 1) * 2);  // [BCP][BFL][NWV*16][2]
+  float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][NT][PW][2]
+  double* sD = reinterpret_cast<double*>(sF + BCP * NT * PW * 2);          // [BCP][BFL][NWV*16][2]
   double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
   double* sT = sE + BCP * NWV * 2;                                         // [NWT][4]
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const int pw = wave / NWV, wv = wave % NWV;  // path of the workgroup, wavefront of the path
-  const int sp = wv & 1, jt = wv >> 1;
+  // this lane's packed column: spin sp, column n of f^sp (q >= 2N: padding)
+  const int q = 16 * wv + c;
+  const int NN = FULL ? 16 * NTC : N;
+  const bool qok = FULL || q < 2 * N;
+  const int sp = FULL ? (wv >= NTC ? 1 : 0) : (q >= N ? 1 : 0);
+  const int n = FULL ? 16 * (wv - sp * NTC) + c : q - sp * N;
   const int s = blockIdx.x * BCP + pw;
   const bool valid = s < n_samples;            // every wavefront takes part in the barriers
   const int sc = valid ? s : n_samples - 1;
@@ -239,11 +250,10 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
         const double x = phiT[((size_t)sc * M + mc) * N + min(n, N - 1)];
         v[ct][j] = (float)keep_if(x, okm && n < N);
       }
-      const int n = 16 * jt + c;
       const double2 x2 = *reinterpret_cast<const double2*>(
           theta + ((((size_t)sc * 2 + sp) * M + mc) * N + min(n, N - 1)) * 2);
-      w[0][j] = (float)keep_if(x2.x, okm && n < N);
-      w[1][j] = (float)keep_if(x2.y, okm && n < N);
+      w[0][j] = (float)keep_if(x2.x, okm && qok);
+      w[1][j] = (float)keep_if(x2.y, okm && qok);
     }
 #pragma unroll
     for (int ct = 0; ct < NTC; ++ct) bT[ct][t] = Fm::make(v[ct]);
@@ -254,7 +264,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   __syncthreads();
 
   V4* Yp = sY + pw * NB * NP * YT;
-  float* Fp = sF + (size_t)pw * 2 * NT * (NT + 1) * 2;
+  float* Fp = sF + (size_t)pw * NT * PW * 2;
   double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
   for (int gam = 0; gam <= G; ++gam) {
@@ -297,7 +307,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     __syncthreads();
     // single buffers: every stage-1 read of this slab is done, the next one can load
     if (NB == 1 && gam < G) copy_slab(gam + 1, 0);
-    // stage 2: f^sp[it][jt], A[c][KV g + j] = Y^T[KB t + KV g + j][16it + c]: the
+    // stage 2: packed f[it][wv], A[c][KV g + j] = Y^T[KB t + KV g + j][16it + c]: the
     // 4-row group (KB t + KV g) / 4, and for BF16 the next one too
     fx4 f[NTC][2];
 #pragma unroll
@@ -321,17 +331,29 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
           f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
         }
     }
-    // diagonal of f^sp in tile (jt, jt): element (4g + r, c) with 4g + r == c
+    // diagonal of f^sp: the lane's element in row n of its packed column
     double d_re = 0.0, d_im = 0.0;
+    if constexpr (FULL) {  // tile (it, it) of spin sp: element (4g + r, c) with 4g + r == c
+      const int jd = wv - sp * NTC;
 #pragma unroll
-    for (int it = 0; it < NTC; ++it)
-      if (it == jt)
+      for (int it = 0; it < NTC; ++it)
+        if (it == jd)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * g + r == c) {
+              d_re = (double)f[it][0][r];
+              d_im = (double)f[it][1][r];
+            }
+    } else {
+#pragma unroll
+      for (int it = 0; it < NTC; ++it)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (4 * g + r == c) {
+          if (qok && 16 * it + 4 * g + r == n) {
             d_re = (double)f[it][0][r];
             d_im = (double)f[it][1][r];
           }
+    }
     if (gam == G) {  // h1': the path's one-body traces through LDS
       d_re = wave_sum(d_re);
       d_im = wave_sum(d_im);
@@ -348,17 +370,16 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
       }
       break;
     }
-    // stage f^sp[:, jt] for the transpose, and the diagonal partials
-    float* Fs = Fp + (size_t)sp * NT * (NT + 1) * 2;
+    // stage the packed f[:, q] for the transpose, and the diagonal partials
 #pragma unroll
     for (int it = 0; it < NTC; ++it)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
-        Fs[(i * (NT + 1) + j) * 2] = f[it][0][r];
-        Fs[(i * (NT + 1) + j) * 2 + 1] = f[it][1][r];
+        const int i = 16 * it + 4 * g + r;
+        Fp[(i * PW + q) * 2] = f[it][0][r];
+        Fp[(i * PW + q) * 2 + 1] = f[it][1][r];
       }
-    if (g == (c >> 2)) {
+    if (g == ((n & 15) >> 2)) {  // the lane group holding row n (0 for padding columns)
       double* d = Dp + ((size_t)(gam % BFL) * NWV * 16 + wv * 16 + c) * 2;
       d[0] = d_re;
       d[1] = d_im;
@@ -367,13 +388,16 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     __syncthreads();
     // this lane's share of tr(f f) for the vector: its eight FP32 products of
     // FP32 entries summed in FP32, the sum over lanes and vectors in FP64
+    // f^sp_{i n} f^sp_{n i}: the partner sits in row n, packed column sp N + i
     float xr = 0.f, xi = 0.f;
 #pragma unroll
     for (int it = 0; it < NTC; ++it)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * g + r, j = 16 * jt + c;
-        const float tr_ = Fs[(j * (NT + 1) + i) * 2], ti_ = Fs[(j * (NT + 1) + i) * 2 + 1];
+        const int i = 16 * it + 4 * g + r;
+        const bool ok = FULL || (qok && i < N);
+        const int src = ok ? (n * PW + sp * NN + i) * 2 : 0;
+        const float tr_ = ok ? Fp[src] : 0.f, ti_ = ok ? Fp[src + 1] : 0.f;
         const float ar = f[it][0][r], ai = f[it][1][r];
         xr = fmaf(ar, tr_, xr);
         xr = fmaf(-ai, ti_, xr);
@@ -428,28 +452,28 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 
 // buffers x parts x bytes per entry = 2 x 1 x 2 (BF16), 1 x 2 x 2 (split BF16)
 // or 1 x 1 x 4 (FP32), over MT x MTP entries (MTP: k padded to whole blocks)
-size_t lds_bytes_s(int KT, int NTC, int FM) {
-  const int MT = 16 * KT, NT = 16 * NTC, NWV = 2 * NTC;
+size_t lds_bytes_s(int KT, int NTC, int NCP, int FM) {
+  const int MT = 16 * KT, NT = 16 * NTC, NWV = NCP;
   const int KB = FM == FM_FP32 ? 16 : 32, MTP = (MT + KB - 1) / KB * KB;
   size_t b = (size_t)4 * MT * MTP;                    // slabs
   b += (size_t)BCP * (MTP / 4) * NT * 16;             // Y^T tiles
-  b += (size_t)BCP * 2 * NT * (NT + 1) * 2 * 4;       // f (FP32)
+  b += (size_t)BCP * NT * (16 * NCP + 1) * 2 * 4;     // packed f (FP32)
   b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
   b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
   return b;
 }
 
-template <int KT, int NTC, int FM>
+template <int KT, int NTC, int NCP, int FM, bool FULL>
 hipError_t launch_sh(const afqmc_ctx_s* c, int nw, const void* L, const void* L_lo,
                       const double* phiT, const double* theta, const double* logov, double* vb,
                       double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes_s(KT, NTC, FM);
-  auto kern = k_contract_sh<KT, NTC, FM>;
+  const size_t lds = lds_bytes_s(KT, NTC, NCP, FM);
+  auto kern = k_contract_sh<KT, NTC, NCP, FM, FULL>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((n + BCP - 1) / BCP), dim3(128 * NTC * BCP), lds, c->stream, n,
+  hipLaunchKernelGGL(kern, dim3((n + BCP - 1) / BCP), dim3(64 * NCP * BCP), lds, c->stream, n,
                      c->M, c->N, c->G, L, L_lo, phiT, theta, logov, vb, ep);
   return hipGetLastError();
 }
@@ -458,14 +482,18 @@ template <int FM>
 hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const void* L, const void* L_lo,
                       const double* phiT, const double* theta, const double* logov, double* vb,
                       double* ep) {
-  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
-#define AFQMC_BS(KK, NC)    \
-  if (KT == KK && NTC == NC) \
-    return launch_sh<KK, NC, FM>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
-  AFQMC_BS(1, 1) AFQMC_BS(2, 1) AFQMC_BS(3, 1) AFQMC_BS(4, 1)
-  AFQMC_BS(5, 1) AFQMC_BS(6, 1) AFQMC_BS(7, 1) AFQMC_BS(8, 1)
-  AFQMC_BS(2, 2) AFQMC_BS(3, 2) AFQMC_BS(4, 2)
-  AFQMC_BS(5, 2) AFQMC_BS(6, 2) AFQMC_BS(7, 2) AFQMC_BS(8, 2)
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16, NCP = (2 * c->N + 15) / 16;
+  const bool full = c->N == 16 * NTC;
+#define AFQMC_BS(KK, NC, NP, FL)                           \
+  if (KT == KK && NTC == NC && NCP == NP && full == FL) \
+    return launch_sh<KK, NC, NP, FM, FL>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
+#define AFQMC_BS1(KK) AFQMC_BS(KK, 1, 1, false) AFQMC_BS(KK, 1, 2, false) AFQMC_BS(KK, 1, 2, true)
+#define AFQMC_BS2(KK) AFQMC_BS(KK, 2, 3, false) AFQMC_BS(KK, 2, 4, false) AFQMC_BS(KK, 2, 4, true)
+  AFQMC_BS1(1) AFQMC_BS1(2) AFQMC_BS1(3) AFQMC_BS1(4)
+  AFQMC_BS1(5) AFQMC_BS1(6) AFQMC_BS1(7) AFQMC_BS1(8)
+  AFQMC_BS2(2) AFQMC_BS2(3) AFQMC_BS2(4) AFQMC_BS2(5) AFQMC_BS2(6) AFQMC_BS2(7) AFQMC_BS2(8)
+#undef AFQMC_BS2
+#undef AFQMC_BS1
 #undef AFQMC_BS
   return hipErrorInvalidValue;
 }
