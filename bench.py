@@ -430,19 +430,26 @@ def mixed_study(args):
 
 def fixed_error_study(args):
     """Walker-steps/s at fixed energy error on the FP64 workload's system (M=64,
-    N=16, 256 vectors, K=64, 512 walkers x 8 paths, tau = 0.005), every form in
-    the stabilised form (STABLE): the FP64 random-walk form, which fixes the
-    error eps, and the mixed-precision forms (FP32, split-BF16 and BF16
-    contraction products with FP32 trial series and propagation and complex64
-    walkers) and the learned proposal (BF16 network trained on the GPU during
-    the warm-up, then frozen; FP32 products).  Each form runs n_seeds
-    independent runs of warmup + steps steps; a run's energy is its mixed
-    estimate over the measured steps; sigma is the spread of those energies
-    over the seeds (sample standard deviation); eps is the FP64 random-walk
-    form's sigma; a form's time to eps is T (sigma / eps)^2 with T the wall
-    time of one run's measured steps, and its walker-steps/s at fixed error is
-    walkers x measured steps / time to eps.  Mean energies are compared with
-    the FP64 form's within their combined errors."""
+    N=16, 256 vectors, K=64, 512 walkers x 8 paths, tau = 0.005), every run in
+    the stabilised form (STABLE), n_seeds independent runs of warmup + steps
+    steps per configuration; a run's energy is its mixed estimate over the
+    measured steps and sigma is the spread of those energies over the seeds.
+
+    The energy depends on the Metropolis sweeps per step: with few sweeps the
+    paths lag the walkers and the estimate is biased (the paper's one sweep
+    assumes the chains re-equilibrate quickly).  So each form is run at a
+    range of sweeps: the FP64 random walk (step 0.3; its one-sweep sigma is
+    the error eps), the mixed-precision random walks at one sweep, and the
+    learned proposal (BF16 network trained on the GPU during the warm-up, then
+    frozen; FP32 contraction products).  E_inf, the converged energy, is the
+    mean of the two most-swept configurations of the two samplers, which must
+    agree.  eps is the statistical error of one run, sigma pooled over every
+    configuration.  A configuration reaches eps if its bias |E - E_inf| is
+    below eps; its time to eps is then T (sigma^2 / (eps^2 - bias^2)) with T
+    the wall time of one run's measured steps, and its walker-steps/s at
+    fixed error is walkers x measured steps / time to eps.  The line's value
+    is the best configuration's rate; configurations that never reach eps
+    report none."""
     import torch
     import afqmc_inputs as ai
     from paper_2505_18519_amd import afqmc as A
@@ -453,7 +460,7 @@ def fixed_error_study(args):
     n_seeds, n_eq, n_meas = args.seeds, args.warmup, args.steps
     s_train = 0.5
 
-    def one(form, seed):
+    def one(form, ns, seed):
         prec = {"fp64": A.PREC_FP64, "fp32": A.PREC_FP32, "bf16x3": A.PREC_BF16X3,
                 "bf16": A.PREC_BF16, "learned": A.PREC_FP32}[form]
         common = dict(n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=STABLE["xbar_cap"],
@@ -473,7 +480,8 @@ def fixed_error_study(args):
         est = torch.zeros(n_eq + n_meas, 2, dtype=torch.float64, device="cuda")
         ref = D.EnergyReference(ctx)
         for i in range(n_eq):
-            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_qr=run.n_qr, n_pc=1)
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=ns, n_qr=run.n_qr,
+                   n_pc=1)
             ref.update(i, est)
         if form == "learned":  # freeze: network moves only from here on
             trained = A.afqmc_mlp_get_params(ctx)
@@ -486,7 +494,8 @@ def fixed_error_study(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(n_eq, n_eq + n_meas):
-            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_qr=run.n_qr, n_pc=1)
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=ns, n_qr=run.n_qr,
+                   n_pc=1)
             ref.update(i, est)
             nacc += st.nacc
         torch.cuda.synchronize()
@@ -495,53 +504,88 @@ def fixed_error_study(args):
         e = est[n_eq:].cpu().numpy()
         en = float(e[:, 0].sum() / e[:, 1].sum())
         return {"energy": en, "seconds": dt, "reblocked": reblock(e[:, 0] / e[:, 1]),
-                "acceptance": float(nacc.sum().item()) / (n_meas * nw * P),
+                "acceptance": float(nacc.sum().item()) / (n_meas * nw * P * ns),
                 "finite": bool(np.all(np.isfinite(e)))}
 
-    forms = ["fp64", "fp32", "bf16x3", "bf16", "learned"]
+    plan = [("fp64", ns) for ns in args.fe_sweeps_rw] + \
+           [("fp32", 1), ("bf16x3", 1), ("bf16", 1)] + \
+           [("learned", ns) for ns in args.fe_sweeps_learned]
     res = {}
-    for form in forms:
+    for form, ns in plan:
         runs = []
         for k in range(n_seeds):
-            r = one(form, 7001 + 97 * k)
+            r = one(form, ns, 7001 + 97 * k)
             runs.append(r)
-            print(f"{form} seed {k}: E = {r['energy']:.4f} (reblocked +- {r['reblocked']:.4f}), "
-                  f"{1e3 * r['seconds'] / n_meas:.2f} ms/step, acceptance {r['acceptance']:.3f}",
-                  file=sys.stderr, flush=True)
+            print(f"{form} sweeps {ns} seed {k}: E = {r['energy']:.4f} (reblocked +- "
+                  f"{r['reblocked']:.4f}), {1e3 * r['seconds'] / n_meas:.2f} ms/step, "
+                  f"acceptance {r['acceptance']:.3f}", file=sys.stderr, flush=True)
         en = np.array([r["energy"] for r in runs])
         T = float(np.mean([r["seconds"] for r in runs]))
-        res[form] = {"energies": en.tolist(), "energy": float(en.mean()),
-                     "sigma_run": float(en.std(ddof=1)),
-                     "error_of_mean": float(en.std(ddof=1) / np.sqrt(n_seeds)),
-                     "reblocked_sigma_run_mean": float(np.mean([r["reblocked"] for r in runs])),
-                     "seconds_per_run": T, "ms_per_step": 1e3 * T / n_meas,
-                     "walker_steps_per_s": nw * n_meas / T,
-                     "acceptance": float(np.mean([r["acceptance"] for r in runs])),
-                     "finite": all(r["finite"] for r in runs)}
-    eps = res["fp64"]["sigma_run"]
-    for form in forms:
-        d = res[form]
-        d["time_to_eps_s"] = d["seconds_per_run"] * (d["sigma_run"] / eps) ** 2
-        d["walker_steps_per_s_at_eps"] = nw * n_meas / d["time_to_eps_s"]
-        d["vs_fp64_at_eps"] = d["walker_steps_per_s_at_eps"] / res["fp64"]["walker_steps_per_s_at_eps"]
-        diff = d["energy"] - res["fp64"]["energy"]
-        comb = float(np.hypot(d["error_of_mean"], res["fp64"]["error_of_mean"]))
-        d["energy_difference_vs_fp64"] = diff
-        d["combined_error"] = comb
-        d["agrees_within_3_sigma"] = bool(abs(diff) <= 3 * comb)
-    best = max((f for f in forms if f != "fp64"), key=lambda f: res[f]["walker_steps_per_s_at_eps"])
+        res[f"{form}-sweeps{ns}"] = {
+            "form": form, "sweeps": ns, "energies": en.tolist(), "energy": float(en.mean()),
+            "sigma_run": float(en.std(ddof=1)),
+            "error_of_mean": float(en.std(ddof=1) / np.sqrt(n_seeds)),
+            "reblocked_sigma_run_mean": float(np.mean([r["reblocked"] for r in runs])),
+            "seconds_per_run": T, "ms_per_step": 1e3 * T / n_meas,
+            "walker_steps_per_s": nw * n_meas / T,
+            "acceptance": float(np.mean([r["acceptance"] for r in runs])),
+            "finite": all(r["finite"] for r in runs)}
+    rw_top = f"fp64-sweeps{max(args.fe_sweeps_rw)}"
+    ln_top = f"learned-sweeps{max(args.fe_sweeps_learned)}"
+    a, b = res[rw_top], res[ln_top]
+    e_inf = 0.5 * (a["energy"] + b["energy"])
+    e_inf_err = 0.5 * float(np.hypot(a["error_of_mean"], b["error_of_mean"]))
+    samplers_agree = bool(abs(a["energy"] - b["energy"])
+                          <= 3 * np.hypot(a["error_of_mean"], b["error_of_mean"]))
+    # the statistical error of one run: the seed-to-seed spread pooled over every
+    # configuration (a few seeds per configuration make each spread alone a poor
+    # estimate; reblocking single runs understates it, see below)
+    pooled_var = float(np.mean([d["sigma_run"] ** 2 for d in res.values()]))
+    sigma = float(np.sqrt(pooled_var))
+    eps = sigma
+    best = None
+    for key, d in res.items():
+        bias = d["energy"] - e_inf
+        d["bias_vs_converged"] = bias
+        d["reaches_eps"] = bool(abs(bias) < eps)
+        if d["reaches_eps"]:
+            d["time_to_eps_s"] = d["seconds_per_run"] * sigma ** 2 / (eps ** 2 - bias ** 2)
+            d["walker_steps_per_s_at_eps"] = nw * n_meas / d["time_to_eps_s"]
+            if best is None or d["walker_steps_per_s_at_eps"] > res[best]["walker_steps_per_s_at_eps"]:
+                best = key
+        else:
+            d["time_to_eps_s"] = None
+            d["walker_steps_per_s_at_eps"] = None
+    per_form = {}
+    for key, d in res.items():
+        f = d["form"]
+        if d["walker_steps_per_s_at_eps"] is not None and (
+                f not in per_form or d["walker_steps_per_s_at_eps"] > per_form[f][1]):
+            per_form[f] = (key, d["walker_steps_per_s_at_eps"])
     out = {
-        "metric": METRIC, "value": res[best]["walker_steps_per_s_at_eps"], "unit": "walker-steps/s",
+        "metric": METRIC,
+        "value": res[best]["walker_steps_per_s_at_eps"] if best else None,
+        "unit": "walker-steps/s",
         "n_gpus": 1, "steps": n_meas, "warmup": n_eq,
-        "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "mixed (see forms)", "data": "synthetic",
+        "ms_per_step": res[best]["ms_per_step"] if best else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed (see configurations)", "data": "synthetic",
         "config": {"workload": f"fixed-error-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
                                f"-W{nw}-P{P}-dtau{run.dtau}", "walkers": nw, "paths": P,
-                   "seeds_per_form": n_seeds, "rw_step": RW_STEP_FP64,
+                   "seeds_per_configuration": n_seeds, "rw_step": RW_STEP_FP64,
                    "network_train_step": s_train, "L_scale": L_SCALE, **STABLE},
-        "value_form": best,
-        "eps": eps,
-        "forms": res,
+        "value_configuration": best,
+        "eps": eps, "eps_is": "the statistical error of one run (seed-to-seed spread pooled over "
+                              "every configuration); a configuration reaches it if its bias "
+                              "against the converged energy is smaller",
+        "sigma_run_pooled": sigma,
+        "reblocked_over_pooled": float(np.sqrt(np.mean([d["reblocked_sigma_run_mean"] ** 2
+                                                          for d in res.values()])) / sigma),
+        "converged_energy": e_inf, "converged_energy_error": e_inf_err,
+        "converged_from": [rw_top, ln_top], "samplers_agree_within_3_sigma": samplers_agree,
+        "best_per_form": {f: {"configuration": k, "walker_steps_per_s_at_eps": v}
+                          for f, (k, v) in per_form.items()},
+        "configurations": res,
     }
     print(json.dumps(out))
 
@@ -657,8 +701,12 @@ def main():
     ap.add_argument("--workload", default="fp64",
                     choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "mixed-study",
                                                  "fixed-error"])
-    ap.add_argument("--seeds", type=int, default=6,
-                    help="independent runs per form (fixed-error workload)")
+    ap.add_argument("--seeds", type=int, default=4,
+                    help="independent runs per configuration (fixed-error workload)")
+    ap.add_argument("--fe-sweeps-rw", type=int, nargs="+", default=[1, 2, 4, 8, 16, 32],
+                    help="sweeps per step of the FP64 random walk (fixed-error workload)")
+    ap.add_argument("--fe-sweeps-learned", type=int, nargs="+", default=[1, 2, 4, 8],
+                    help="sweeps per step of the learned proposal (fixed-error workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (the plain copy kernel that "
                          "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and exit")
