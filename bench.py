@@ -54,8 +54,8 @@ WORKLOADS = {
 # the plain-copy calibration (profiles/traffic_k_contract_*.md), valid while the
 # kernel source is the one measured: workload -> (source file, sha256 prefix, bytes)
 TRAFFIC = {
-    "fp64": ("k_contract.hip", "e96e7653420b4e6b", 454536192),
-    "fp64-prior": ("k_contract.hip", "e96e7653420b4e6b", 454536192),
+    "fp64": ("k_contract.hip", "911cdc519ab8f700", 454536192),
+    "fp64-prior": ("k_contract.hip", "911cdc519ab8f700", 454536192),
 }
 
 # Proposal of each per-step workload: the default FP64 leg runs the random walk

@@ -218,6 +218,14 @@ afqmc_status afqmc_set_numeric_check(afqmc_ctx ctx, int32_t on);
  * unchanged). */
 afqmc_status afqmc_set_eloc_cap(afqmc_ctx ctx, double center, double half_width);
 
+/* Tile strategy of the FP64 Cholesky contraction (Sec. III.A, Eq. local-obs)
+ * for real trials on the workgroup-per-path kernels (M > 64 or N > 16):
+ * variant 0 (default) keeps Phi_T and Theta in registers across the vectors
+ * (N <= 32), variant 1 streams them from L2 one k tile ahead of the products;
+ * N > 32 always streams.  Same results to rounding.  Other contexts ignore it.
+ * AFQMC_E_INVALID for a variant other than 0 or 1. */
+afqmc_status afqmc_set_contraction_variant(afqmc_ctx ctx, int32_t variant);
+
 /* Initial paths y ~ p_T (stream INIT of the counter layout below). */
 afqmc_status afqmc_sample_prior(afqmc_ctx ctx, int32_t nw, uint64_t seed, double* y);
 
@@ -562,8 +570,10 @@ afqmc_status afqmc_batch_run(afqmc_batch b, int32_t n_cycles);
  * done to steps[i] (HOST uint64). */
 afqmc_status afqmc_batch_estimates(afqmc_batch b, double* out, uint64_t* steps);
 /* The tuner's choices (HOST arrays [n_systems], each may be NULL): kernel
- * family (0 register-resident, 1 workgroup-per-path), branch, the measured
- * time of one step of the system alone (ms), and the number of branches. */
+ * family (0 register-resident, 1 workgroup-per-path, 2 workgroup-per-path
+ * with the FP64 contraction's operands streamed, afqmc_set_contraction_variant),
+ * branch, the measured time of one step of the system alone (ms), and the
+ * number of branches. */
 afqmc_status afqmc_batch_plan(afqmc_batch b, int32_t* family, int32_t* branch, double* step_ms,
                               int32_t* n_branches);
 const char* afqmc_batch_last_error(afqmc_batch b);

@@ -64,6 +64,7 @@ EXPORTS = {
     "afqmc_numeric_flags": (c_int, [c_void_p, c_int32, c_void_p, POINTER(c_int32)]),
     "afqmc_set_numeric_check": (c_int, [c_void_p, c_int32]),
     "afqmc_set_eloc_cap": (c_int, [c_void_p, c_double, c_double]),
+    "afqmc_set_contraction_variant": (c_int, [c_void_p, c_int32]),
     "afqmc_trial_build": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
     "afqmc_overlap": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "afqmc_green": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -283,6 +284,12 @@ def afqmc_numeric_flags(ctx, nw):
 
 def afqmc_set_numeric_check(ctx, on):
     ctx._call("afqmc_set_numeric_check", 1 if on else 0)
+
+
+def afqmc_set_contraction_variant(ctx, variant):
+    """FP64 contraction of real trials on the workgroup-per-path kernels:
+    0 register-resident operands, 1 operands streamed from L2."""
+    ctx._call("afqmc_set_contraction_variant", int(variant))
 
 
 def afqmc_set_eloc_cap(ctx, center, half_width):

@@ -522,6 +522,13 @@ afqmc_status afqmc_set_eloc_cap(afqmc_ctx c, double center, double half_width) {
   return AFQMC_OK;
 }
 
+afqmc_status afqmc_set_contraction_variant(afqmc_ctx c, int32_t variant) {
+  if (c == nullptr) return AFQMC_E_INVALID;
+  if (variant != 0 && variant != 1) return fail(c, AFQMC_E_INVALID, "variant must be 0 or 1");
+  c->contract_variant = variant;
+  return AFQMC_OK;
+}
+
 afqmc_status afqmc_sample_prior(afqmc_ctx c, int32_t nw, uint64_t seed, double* y) {
   CHECK_CTX(c);
   CHECK_NW(c, nw);

@@ -22,8 +22,9 @@
 //    advances the streams without host updates;
 //  * the autotuner times, per system, the kernel families that apply to its
 //    (M, N) (register-resident wavefront-per-path kernels for M <= 64,
-//    N <= 16; workgroup-per-path kernels for any size) and, for the batch,
-//    S in {1, 2, 4}, and keeps the fastest.
+//    N <= 16; workgroup-per-path kernels for any size, with the FP64
+//    contraction's operands in registers or streamed from L2 for N <= 32) and,
+//    for the batch, S in {1, 2, 4}, and keeps the fastest.
 #include <algorithm>
 #include <chrono>
 #include <new>
@@ -62,10 +63,13 @@ struct sys_state {
          *ref = nullptr, *est = nullptr;
   int* nacc = nullptr;
   uint64_t* dstep = nullptr;
-  int family = 1;  // 0 register-resident kernels, 1 workgroup-per-path kernels
+  // 0 register-resident kernels, 1 workgroup-per-path kernels, 2 the same with the
+  // FP64 contraction's operands streamed (contract_variant 1)
+  int family = 1;
   int branch = 0;
   double ms = 0.0;  // measured time of one step alone
   bool can_small = false;
+  bool can_stream = false;  // FP64 real trial with N <= 32 (past that it always streams)
 };
 
 }  // namespace
@@ -223,12 +227,14 @@ afqmc_status tune(afqmc_batch_s* b) {
   // 1. kernel family per system, from one eager step of each candidate (after
   //    a first untimed step that settles clocks and caches)
   for (auto& sys : b->s) {
-    const int fams[2] = {0, 1};
+    const int fams[3] = {0, 1, 2};
     double best = 1e300;
     int best_f = 1;
     for (int f : fams) {
       if (f == 0 && !sys.can_small) continue;
+      if (f == 2 && !sys.can_stream) continue;
       sys.c->small = (f == 0);
+      sys.c->contract_variant = (f == 2) ? 1 : 0;
       for (int rep = 0; rep < 2; ++rep) {
         BHIP(b, hipEventRecord(t0, b->stream), "event");
         afqmc_status r = one_step(b, sys, b->stream, false, true);
@@ -244,6 +250,7 @@ afqmc_status tune(afqmc_batch_s* b) {
     }
     sys.family = best_f;
     sys.c->small = (best_f == 0);
+    sys.c->contract_variant = (best_f == 2) ? 1 : 0;
     sys.ms = best;
   }
   // 2. number of parallel branches, from a replay of the whole captured cycle
@@ -310,6 +317,7 @@ afqmc_status build(afqmc_batch_s* b, const afqmc_system* systems, const int32_t*
     sys.P = sd.P;
     sys.seed = b->opt.seed + (uint64_t)i;
     sys.can_small = sys.c->small;
+    sys.can_stream = sd.precision == AFQMC_PREC_FP64 && !sys.c->ctrial && sd.N <= 32;
     sys.family = sys.c->small ? 0 : 1;
     const size_t nw = sys.nw, M = sys.M, N = sys.N, P = sys.P, K = sys.K, G = sys.G;
     const size_t tsz = (size_t)sys.c->tsz;  // doubles per trial determinant (complex: 2 M N)

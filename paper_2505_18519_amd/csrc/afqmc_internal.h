@@ -19,6 +19,10 @@ struct afqmc_ctx_s {
   // Re E_L clipped to [ecap_center - ecap_half, ecap_center + ecap_half] when ecap_half > 0
   double ecap_center = 0, ecap_half = 0;
   int n_taylor = 10, weight_mode = 0, proposal = 0, precision = 0;
+  // FP64 contraction of real trials on the workgroup-per-path kernels: 0 keeps
+  // Phi_T and Theta in registers (k_contract_g, N <= 32), 1 streams them from
+  // L2 (k_contract_gs; always for 32 < N)
+  int contract_variant = 0;
 
   // device copies owned by the context
   double* d_h1 = nullptr;    // [M][M]

@@ -747,6 +747,17 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
     return hipErrorInvalidValue;
   }
   if constexpr (sizeof(T) == 8) {  // real trials with FP32 products run k_contract_sh
+    // operands streamed from L2: three column tiles always, fewer when asked for
+    if (NTC == 3 || c->contract_variant == 1) {
+#define AFQMC_GS(KK, NC) \
+  if (KT == KK && NTC == NC) return launch_gs<KK, NC>(c, nw, L, phiT, theta, logov, vb, ep);
+#define AFQMC_GSK(KK) AFQMC_GS(KK, 1) AFQMC_GS(KK, 2) AFQMC_GS(KK, 3)
+      AFQMC_GSK(1) AFQMC_GSK(2) AFQMC_GSK(3) AFQMC_GSK(4) AFQMC_GSK(5)
+      AFQMC_GSK(6) AFQMC_GSK(7) AFQMC_GSK(8) AFQMC_GSK(9) AFQMC_GSK(10)
+#undef AFQMC_GSK
+#undef AFQMC_GS
+      return hipErrorInvalidValue;
+    }
     // 16 < N <= 24: vectors in pairs (2N rows in three tiles; measured at M = 96,
     // N = 24: 86.9 -> 82.3 ms); the kernel spills at KT = 8, which keeps one vector
     // at a time
@@ -765,12 +776,6 @@ hipError_t dispatch(const afqmc_ctx_s* c, int nw, const T* L, const double* phiT
     AFQMC_G(5, 2) AFQMC_G(6, 2) AFQMC_G(7, 2) AFQMC_G(8, 2)
     AFQMC_G(9, 1) AFQMC_G(10, 1) AFQMC_G(9, 2) AFQMC_G(10, 2)
 #undef AFQMC_G
-    // three column tiles (32 < N <= 48): operands streamed, not register-resident
-#define AFQMC_GS(KK) \
-  if (KT == KK && NTC == 3) return launch_gs<KK, 3>(c, nw, L, phiT, theta, logov, vb, ep);
-    AFQMC_GS(3) AFQMC_GS(4) AFQMC_GS(5) AFQMC_GS(6) AFQMC_GS(7) AFQMC_GS(8) AFQMC_GS(9)
-    AFQMC_GS(10)
-#undef AFQMC_GS
   }
   return hipErrorInvalidValue;
 }

@@ -594,6 +594,40 @@ def test_stabilised_trajectory_matches_oracle(name):
     assert np.abs(gw - ost.w).max() <= TOL * np.abs(ost.w).max()
 
 
+@pytest.mark.parametrize("case", ["gauss-M72-N20-ragged", "gauss-M96-N24", "gauss-M128-N32",
+                                  "gauss-M150-N20", "gauss-M70-N1", "gauss-M32-N32"])
+def test_streamed_contraction_variant(case):
+    """The FP64 contraction with its operands streamed from L2
+    (afqmc_set_contraction_variant 1; the batch tuner's third family) against
+    the oracle's per-path vb, E_p and walker estimates, at the shapes the
+    register-resident kernel serves by default."""
+    _say("streamed contraction", case)
+    from paper_2505_18519_amd import afqmc as A
+    fac, P, nw = CASES[case]
+    s = fac()
+    ctx = make_ctx(s, P, nw)
+    A.afqmc_set_contraction_variant(ctx, 1)
+    rng, phi, y = state(s, P, nw, 31)
+    phiT = O.trial_det(s, y)
+    ell, theta = O.green(phiT, phi)
+    vb, ep = O.sample_contraction(s, phiT, theta, ell)
+    xbar, eloc = O.walker_estimates(vb, ep, ell, 0.01)
+    d_vb = torch.zeros(nw, P, s.n_chol, dtype=torch.complex128, device="cuda")
+    d_ep = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    d_el = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    d_xb = torch.zeros(nw, s.n_chol, dtype=torch.complex128, device="cuda")
+    A.afqmc_force_bias(ctx, nw, dev(phiT), dev(theta), dev(ell), d_xb, d_vb)
+    A.afqmc_local_energy(ctx, nw, dev(phiT), dev(theta), dev(ell), d_el, d_ep, None)
+    torch.cuda.synchronize()
+    assert rel(host(d_vb), vb) <= TOL
+    assert np.abs(host(d_ep) - ep).max() <= TOL * max(np.abs(ep).max(), 1.0)
+    assert np.abs(host(d_el) - eloc).max() <= TOL * max(np.abs(eloc).max(), 1.0)
+    for w in range(nw):
+        assert rel(host(d_xb)[w], xbar[w]) <= TOL
+    with pytest.raises(A.AfqmcError):
+        A.afqmc_set_contraction_variant(ctx, 2)
+
+
 MIXED_TOL = 1e-4
 MIXED = {"fp32": (1, MIXED_TOL), "bf16x3": (3, MIXED_TOL), "bf16": (2, BF16_TOL)}
 # FP32-product trial series and walker propagation (mixed-precision contexts):
