@@ -144,14 +144,15 @@ struct Form {
 };
 
 // ---------------------------------------------------------------------------
-// BCP paths per workgroup sharing each L slab: the slab of vector g + 1 goes
+// BCP paths per workgroup sharing each L slab (two; four when a path has
+// three wavefronts, so that the twelve wavefronts put three on every SIMD
+// instead of two on some and one on others): the slab of vector g + 1 goes
 // from global memory straight into LDS (global_load_lds) during vector g,
 // already in A-operand order ([row tile][k tile][lane][4]: one 8-byte LDS read
 // per product, consecutive lanes on consecutive words), so every L byte crosses
 // L2 once per workgroup instead of once per path.  f is staged for the
 // transpose in FP32 (its products are FP32) and the diagonals flush every BFL
 // vectors.
-constexpr int BCP = 2;  // paths per workgroup
 constexpr int BFL = 8;  // vectors per flush of the staged diagonals
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
@@ -159,7 +160,7 @@ typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
 // FULL: N = 16 NTC (every column tile full, NCP = 2 NTC), so the packed
 // columns are the two spins' tiles in order and no column or row is padding.
-template <int KT, int NTC, int NCP, int FM, bool FULL>
+template <int KT, int NTC, int NCP, int FM, bool FULL, int BCP>
 __global__ void __launch_bounds__(64 * NCP * BCP)
 k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
                const void* __restrict__ Lop_lo, const double* __restrict__ phiT,
@@ -452,7 +453,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 
 // buffers x parts x bytes per entry = 2 x 1 x 2 (BF16), 1 x 2 x 2 (split BF16)
 // or 1 x 1 x 4 (FP32), over MT x MTP entries (MTP: k padded to whole blocks)
-size_t lds_bytes_s(int KT, int NTC, int NCP, int FM) {
+size_t lds_bytes_s(int KT, int NTC, int NCP, int FM, int BCP) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = NCP;
   const int KB = FM == FM_FP32 ? 16 : 32, MTP = (MT + KB - 1) / KB * KB;
   size_t b = (size_t)4 * MT * MTP;                    // slabs
@@ -463,13 +464,13 @@ size_t lds_bytes_s(int KT, int NTC, int NCP, int FM) {
   return b;
 }
 
-template <int KT, int NTC, int NCP, int FM, bool FULL>
+template <int KT, int NTC, int NCP, int FM, bool FULL, int BCP>
 hipError_t launch_sh(const afqmc_ctx_s* c, int nw, const void* L, const void* L_lo,
                       const double* phiT, const double* theta, const double* logov, double* vb,
                       double* ep) {
   const int n = nw * c->P;
-  const size_t lds = lds_bytes_s(KT, NTC, NCP, FM);
-  auto kern = k_contract_sh<KT, NTC, NCP, FM, FULL>;
+  const size_t lds = lds_bytes_s(KT, NTC, NCP, FM, BCP);
+  auto kern = k_contract_sh<KT, NTC, NCP, FM, FULL, BCP>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -486,7 +487,7 @@ hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const void* L, const void* L
   const bool full = c->N == 16 * NTC;
 #define AFQMC_BS(KK, NC, NP, FL)                           \
   if (KT == KK && NTC == NC && NCP == NP && full == FL) \
-    return launch_sh<KK, NC, NP, FM, FL>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
+    return launch_sh<KK, NC, NP, FM, FL, NP == 3 ? 4 : 2>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
 #define AFQMC_BS1(KK) AFQMC_BS(KK, 1, 1, false) AFQMC_BS(KK, 1, 2, false) AFQMC_BS(KK, 1, 2, true)
 #define AFQMC_BS2(KK) AFQMC_BS(KK, 2, 3, false) AFQMC_BS(KK, 2, 4, false) AFQMC_BS(KK, 2, 4, true)
   AFQMC_BS1(1) AFQMC_BS1(2) AFQMC_BS1(3) AFQMC_BS1(4)
