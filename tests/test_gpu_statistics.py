@@ -74,3 +74,45 @@ def test_gpu_and_oracle_energies_agree_within_error_bars(mode):
          f"(one run: sigma {math.sqrt(pooled):.4f}); ED {e0:.5f}, phaseless and time-step "
          f"bias {g.mean() - e0:+.4f}")
     assert abs(g.mean() - o.mean()) < 3 * err
+
+
+def test_m64_stabilised_runs_agree_with_the_oracle_reference():
+    """The FP64 M = 64 workload (N = 16, 256 vectors, K = 64, 64 walkers x 8
+    paths, tau = 0.005, 2000 steps, random walk of step 0.3) in the stabilised
+    local-energy form: 16 independent GPU runs against the oracle's runs stored
+    by tests/golden/make_stat_reference.py (same form, same E_T schedule, other
+    seeds).  Each run's mixed estimate over steps 500..1999 is one sample; the
+    difference of the means must lie within 3 combined standard errors, the
+    standard errors from the seed-to-seed spreads."""
+    from paper_2505_18519_amd import afqmc as A
+    from paper_2505_18519_amd import driver as D
+    ref = json.load(open(os.path.join(GOLDEN, "stat_m64_local.json")))
+    o = np.array([r["energy"] for r in ref["runs"]])
+    assert len(o) >= 2
+    s, run = ai.workload(1)
+    nw, P, dtau, n_steps, m0 = ref["walkers"], ref["paths"], ref["dtau"], ref["steps"], \
+        ref["measured_from"]
+    assert (s.M, s.N, s.n_chol, s.K, dtau) == (64, 16, 256, 64, run.dtau)
+    g = []
+    for k in range(16):
+        seed = 6001 + k
+        ctx = A.Context(s, P, dtau, max_walkers=nw, weight_mode=A.WEIGHT_LOCAL,
+                        proposal=A.PROPOSAL_RW, rw_step=ref["rw_step"], xbar_cap=ref["xbar_cap"])
+        st = D.init_walkers(ctx, s.phi0, nw, seed)
+        er = D.EnergyReference(ctx, width=ref["eloc_cap_half_width"])
+        est = torch.zeros(n_steps, 2, dtype=torch.float64, device="cuda")
+        for i in range(n_steps):
+            D.step(ctx, st, seed, i, est[i], e_shift=er.e_shift, n_sweep=1, n_qr=ref["n_qr"],
+                   n_pc=1)
+            er.update(i, est)
+        e = est.cpu().numpy()[m0:]
+        g.append(e[:, 0].sum() / e[:, 1].sum())
+        ctx.close()
+        _say(f"GPU run {k}: E = {g[-1]:.4f}")
+    g = np.array(g)
+    err = math.hypot(g.std(ddof=1) / math.sqrt(len(g)), o.std(ddof=1) / math.sqrt(len(o)))
+    _say(f"M=64 stabilised: GPU {g.mean():.4f} +- {g.std(ddof=1) / math.sqrt(len(g)):.4f} "
+         f"(sigma per run {g.std(ddof=1):.4f}), oracle {o.mean():.4f} +- "
+         f"{o.std(ddof=1) / math.sqrt(len(o)):.4f} ({len(o)} runs); difference "
+         f"{g.mean() - o.mean():+.4f} +- {err:.4f}")
+    assert abs(g.mean() - o.mean()) < 3 * err
