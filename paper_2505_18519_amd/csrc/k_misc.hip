@@ -1,86 +1,67 @@
 // Set-up kernels (h1', e^{-tau h1/2}), counter-based random streams, the
 // mixed-estimator sums and walker re-orthonormalisation.
 #include <algorithm>
+#include <vector>
 
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
 namespace {
 
-// h1' = h1 + 1/2 sum_g L_g L_g into slab G of the padded L array
-__global__ void k_h1_eff(int M, int MT, int G, const double* __restrict__ h1,
-                         const double* __restrict__ L, double* __restrict__ Lpad) {
+// h1' = h1 + 1/2 sum_g L_g L_g into slab G of the padded L array, the sum over g
+// split into GS chunks of consecutive vectors (one grid row each) and the
+// chunks' partial sums added in chunk order
+__global__ void k_h1_part(int M, int G, int GS, const double* __restrict__ L,
+                          double* __restrict__ part) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * M) return;
-  const int i = e / M, j = e % M;
+  const int i = e / M, j = e % M, q = blockIdx.y;
+  const int g0 = (int)((long)G * q / GS), g1 = (int)((long)G * (q + 1) / GS);
   double acc = 0.0;
-  for (int gm = 0; gm < G; ++gm) {
+  for (int gm = g0; gm < g1; ++gm) {
     const double* Lg = L + (size_t)gm * M * M;
     double t = 0.0;
     for (int k = 0; k < M; ++k) t += Lg[i * M + k] * Lg[k * M + j];
     acc += t;
   }
-  Lpad[(size_t)G * MT * MT + i * MT + j] = h1[i * M + j] + 0.5 * acc;
+  part[(size_t)q * M * M + e] = acc;
+}
+
+__global__ void k_h1_fin(int M, int MT, int G, int GS, const double* __restrict__ h1,
+                         const double* __restrict__ part, double* __restrict__ Lpad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  double acc = 0.0;
+  for (int q = 0; q < GS; ++q) acc += part[(size_t)q * M * M + e];
+  const int i = e / M, j = e % M;
+  Lpad[(size_t)G * MT * MT + i * MT + j] = h1[e] + 0.5 * acc;
 }
 
 // exp(X), X = -tau h1 / 2, by scaling and squaring of a 24-term Taylor series
-// (|X / 2^s|_1 <= 1/4).  One workgroup; three M x M work matrices in global memory.
-__global__ void __launch_bounds__(256)
-k_expm_half(int M, double dtau, const double* __restrict__ h1, double* __restrict__ X,
-            double* __restrict__ T, double* __restrict__ T2, double* __restrict__ E) {
-  __shared__ double s_norm;
-  __shared__ int s_sq;
-  const int tid = threadIdx.x;
-  const int MM = M * M;
-  if (tid == 0) {
-    double nrm = 0.0;
-    for (int j = 0; j < M; ++j) {
-      double cs = 0.0;
-      for (int i = 0; i < M; ++i) cs += fabs(h1[i * M + j]);
-      nrm = fmax(nrm, cs);
-    }
-    nrm *= 0.5 * dtau;
-    int sq = 0;
-    while (nrm > 0.25 && sq < 64) {
-      nrm *= 0.5;
-      ++sq;
-    }
-    s_norm = nrm;
-    s_sq = sq;
-  }
-  __syncthreads();
-  const double scale = -0.5 * dtau * ldexp(1.0, -s_sq);
-  for (int e = tid; e < MM; e += 256) {
-    X[e] = scale * h1[e];
-    T[e] = ((e / M) == (e % M)) ? 1.0 : 0.0;
-    E[e] = T[e];
-  }
-  __syncthreads();
-  for (int j = 1; j <= 24; ++j) {
-    for (int e = tid; e < MM; e += 256) {
-      const int r = e / M, cc = e % M;
-      double acc = 0.0;
-      for (int k = 0; k < M; ++k) acc += X[r * M + k] * T[k * M + cc];
-      T2[e] = acc / (double)j;
-    }
-    __syncthreads();
-    for (int e = tid; e < MM; e += 256) {
-      T[e] = T2[e];
-      E[e] += T2[e];
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < s_sq; ++q) {
-    for (int e = tid; e < MM; e += 256) {
-      const int r = e / M, cc = e % M;
-      double acc = 0.0;
-      for (int k = 0; k < M; ++k) acc += E[r * M + k] * E[k * M + cc];
-      T2[e] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < MM; e += 256) E[e] = T2[e];
-    __syncthreads();
-  }
+// (|X / 2^s|_1 <= 1/4, s chosen on the host): one launch per term and per
+// squaring, one thread per entry, each entry's sum over k in ascending k.
+__global__ void k_expm_init(int M, double scale, const double* __restrict__ h1,
+                            double* __restrict__ X, double* __restrict__ T,
+                            double* __restrict__ E) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  X[e] = scale * h1[e];
+  const double id = ((e / M) == (e % M)) ? 1.0 : 0.0;
+  T[e] = id;
+  E[e] = id;
+}
+
+// Tn = A B * f; with E given, E += Tn
+__global__ void k_mm_f64(int M, const double* __restrict__ A, const double* __restrict__ B,
+                         double f, double* __restrict__ Tn, double* __restrict__ E) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int r = e / M, cc = e % M;
+  double acc = 0.0;
+  for (int k = 0; k < M; ++k) acc += A[r * M + k] * B[k * M + cc];
+  const double v = acc * f;
+  Tn[e] = v;
+  if (E != nullptr) E[e] += v;
 }
 
 __global__ void k_philox_normal(uint64_t seed, uint64_t step, const uint64_t* __restrict__ dstep,
@@ -287,16 +268,58 @@ __global__ void k_zero_int(int n, int* __restrict__ p) {
 }  // namespace
 
 hipError_t launch_setup(afqmc_ctx_s* c) {
-  const int MM = c->M * c->M;
-  hipLaunchKernelGGL(k_h1_eff, dim3((MM + 255) / 256), dim3(256), 0, c->stream, c->M, c->MT, c->G,
-                     c->d_h1, c->d_Lraw, c->d_Lpad);
-  AFQMC_LAUNCH_CHECK();
+  const int M = c->M, MM = M * M;
+  const int GS = std::max(1, std::min(c->G, 64));
+  const dim3 eg((MM + 255) / 256);
   double* tmp = nullptr;
-  hipError_t e = hipMalloc(&tmp, 3 * (size_t)MM * sizeof(double));
+  hipError_t e = hipMalloc(&tmp, (size_t)std::max(GS, 5) * MM * sizeof(double));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_expm_half, dim3(1), dim3(256), 0, c->stream, c->M, c->dtau, c->d_h1, tmp,
-                     tmp + MM, tmp + 2 * MM, c->d_Eh);
-  e = hipGetLastError();
+  hipLaunchKernelGGL(k_h1_part, dim3(eg.x, GS), dim3(256), 0, c->stream, M, c->G, GS, c->d_Lraw,
+                     tmp);
+  if ((e = hipGetLastError()) == hipSuccess) {
+    hipLaunchKernelGGL(k_h1_fin, eg, dim3(256), 0, c->stream, M, c->MT, c->G, GS, c->d_h1, tmp,
+                       c->d_Lpad);
+    e = hipGetLastError();
+  }
+  // the squarings of exp(-tau h1 / 2): 1-norm of tau h1 / 2 halved until <= 1/4
+  std::vector<double> h1((size_t)MM);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(h1.data(), c->d_h1, (size_t)MM * sizeof(double), hipMemcpyDeviceToHost);
+  int sq = 0;
+  if (e == hipSuccess) {
+    double nrm = 0.0;
+    for (int j = 0; j < M; ++j) {
+      double cs = 0.0;
+      for (int i = 0; i < M; ++i) cs += fabs(h1[(size_t)i * M + j]);
+      nrm = std::max(nrm, cs);
+    }
+    nrm *= 0.5 * c->dtau;
+    while (nrm > 0.25 && sq < 64) {
+      nrm *= 0.5;
+      ++sq;
+    }
+  }
+  double *X = tmp, *T = tmp + MM, *T2 = tmp + 2 * MM, *E = tmp + 3 * MM, *E2 = tmp + 4 * MM;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_expm_init, eg, dim3(256), 0, c->stream, M, -0.5 * c->dtau * ldexp(1.0, -sq),
+                       c->d_h1, X, T, E);
+    e = hipGetLastError();
+  }
+  for (int j = 1; j <= 24 && e == hipSuccess; ++j) {
+    hipLaunchKernelGGL(k_mm_f64, eg, dim3(256), 0, c->stream, M, X, T, 1.0 / (double)j, T2, E);
+    e = hipGetLastError();
+    std::swap(T, T2);
+  }
+  for (int q = 0; q < sq && e == hipSuccess; ++q) {
+    hipLaunchKernelGGL(k_mm_f64, eg, dim3(256), 0, c->stream, M, E, E, 1.0, E2,
+                       (double*)nullptr);
+    e = hipGetLastError();
+    std::swap(E, E2);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_Eh, E, (size_t)MM * sizeof(double), hipMemcpyDeviceToDevice,
+                       c->stream);
   hipError_t e2 = hipStreamSynchronize(c->stream);
   const hipError_t e3 = hipFree(tmp);
   return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);

@@ -3,7 +3,8 @@ sides): the tiny Ising workload (M=8, N=2, 16 vectors, K=4, 64 walkers x 8
 paths, tau = 0.01, one sweep per step, comb every step) run on the GPU and by
 the oracle gives mixed-estimator energies (Eq. mixed_estimator) that agree
 within 3 sigma, with the hybrid weight and with the local-energy formalism
-(Sec. III.A).  Each run's mean over its measured steps is one sample; sigma
+(Sec. III.A); so does the FP64 M = 64 workload in the stabilised local-energy
+form against the oracle's stored runs.  Each run's mean over its measured steps is one sample; sigma
 comes from the pooled spread of these means over independent seeds (16 GPU
 runs, 4 oracle runs), since the population's correlation time can exceed what
 blocking a 300-step series resolves.  The phaseless bias of the Jastrow trial
