@@ -187,10 +187,12 @@ def reblock(x):
 
 def learned_study(args):
     """Learned-proposal workload (M=96, N=24, 384 vectors, K=128, 2048 walkers x
-    4 paths): the learned/mixed form (BF16 network trained during the warm-up
-    on the random-walk moves, then frozen; FP32-product contraction) against
-    the plain FP64 random-walk form, both whole AFQMC steps from the same
-    walkers and seeds.  Energy errors by reblocking over the timed steps."""
+    4 paths), stabilised form (STABLE): the learned/mixed form (BF16 network
+    trained during the warm-up on the random-walk moves, then frozen;
+    FP32-product contraction) against the plain FP64 random-walk form, both
+    whole AFQMC steps from the same walkers and seeds.  Step throughput and
+    acceptance; the energies at fixed error come from the fixed-error
+    workload (independent seeds), not from these short runs."""
     import torch
     import afqmc_inputs as ai
     from paper_2505_18519_amd import afqmc as A
@@ -198,12 +200,13 @@ def learned_study(args):
 
     sys_, run = ai.workload(4)
     nw, P, seed = run.W, run.P, 2004
-    xbar_cap, n_pc, w_cap = 1.0, 1, 4.0
+    xbar_cap, n_pc = STABLE["xbar_cap"], STABLE["comb_every"]
     s_train, rw_step, n_sweep_eq = 0.5, 0.3, 2
 
     def leg(kind):
         prec = A.PREC_FP32 if kind == "learned" else A.PREC_FP64
-        common = dict(n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap, precision=prec)
+        common = dict(n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=xbar_cap, precision=prec,
+                      weight_mode=A.WEIGHT_LOCAL)
         if kind == "learned":
             ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=s_train,
                             **common)
@@ -215,19 +218,17 @@ def learned_study(args):
             ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_RW, rw_step=rw_step, **common)
         st = D.init_walkers(ctx, sys_.phi0, nw, seed)
         est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
-        e_shift = 0.0
+        ref = D.EnergyReference(ctx)
         for i in range(args.warmup):
-            D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=n_sweep_eq, n_qr=run.n_qr,
-                   n_pc=n_pc, w_cap=w_cap)
-            if i == 0:
-                torch.cuda.synchronize()
-                e0 = est[0].cpu().numpy()
-                e_shift = float(e0[0] / e0[1])
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=n_sweep_eq,
+                   n_qr=run.n_qr, n_pc=n_pc)
+            ref.update(i, est)
         if kind == "learned":          # freeze: network moves only from here on
             trained = A.afqmc_mlp_get_params(ctx)
             ctx.close()
             ctx = A.Context(sys_, P, run.dtau, proposal=A.PROPOSAL_LEARNED, rw_step=0.0, **common)
             A.afqmc_mlp_init(ctx, A.PREC_BF16, trained)
+            ref.attach(ctx)
         nacc = torch.zeros(nw, dtype=torch.int64, device="cuda")
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
@@ -235,20 +236,21 @@ def learned_study(args):
         t0 = time.perf_counter()
         for k in range(args.steps):
             i = args.warmup + k
-            D.step(ctx, st, seed, i, est[i], e_shift=e_shift, n_sweep=1, n_qr=run.n_qr,
-                   contract_events=evs[k], n_pc=n_pc, w_cap=w_cap)
+            D.step(ctx, st, seed, i, est[i], e_shift=ref.e_shift, n_sweep=1, n_qr=run.n_qr,
+                   contract_events=evs[k], n_pc=n_pc)
+            ref.update(i, est)
             nacc += st.nacc
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         e = est.cpu().numpy()[args.warmup:]
         en = e[:, 0] / e[:, 1]
         ctx.close()
-        print(f"{kind}: {1e3 * dt / args.steps:.2f} ms/step, E = {en.mean():.5f} +- "
-              f"{reblock(en):.5f}", file=sys.stderr, flush=True)
+        print(f"{kind}: {1e3 * dt / args.steps:.2f} ms/step, E = {en.mean():.5f}",
+              file=sys.stderr, flush=True)
         return {"walker_steps_per_s": nw * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
                 "contraction_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
                 "acceptance": float(nacc.sum().item()) / (args.steps * nw * P),
-                "energy": float(en.mean()), "energy_err": reblock(en),
+                "energy_timed_steps": float(en.mean()),
                 "finite": bool(np.all(np.isfinite(en)))}
 
     L = leg("learned")
@@ -256,10 +258,6 @@ def learned_study(args):
     if not (L["finite"] and R["finite"]):
         print("non-finite energy in the learned study", L, R, file=sys.stderr)
         sys.exit(1)
-    # throughput at equal energy error: steps needed scale with err^2 * steps
-    var_l = L["energy_err"] ** 2 * args.steps
-    var_r = R["energy_err"] ** 2 * args.steps
-    equal_error_ratio = (L["walker_steps_per_s"] / R["walker_steps_per_s"]) * (var_r / var_l)
     flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
     achieved = flops / (L["contraction_ms"] * 1e-3) / 1e12
     out = {
@@ -274,14 +272,14 @@ def learned_study(args):
         "config": {"workload": f"learned-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}"
                                f"-W{nw}-P{P}-dtau{run.dtau}",
                    "network_train_step": s_train, "warmup_sweeps_per_step": n_sweep_eq,
-                   "xbar_cap": xbar_cap, "comb_every": n_pc, "weight_cap": w_cap},
+                   "L_scale": L_SCALE, **STABLE},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
                      "kernel": "k_contract_sh, FP32 products (+ k_combine) in afqmc_local_energy",
                      "ms_per_launch": L["contraction_ms"], "flops_per_launch": flops},
         "learned_mixed": L,
         "random_walk_fp64": R,
-        "equal_error_throughput_ratio": equal_error_ratio,
+        "step_throughput_ratio": L["walker_steps_per_s"] / R["walker_steps_per_s"],
     }
     print(json.dumps(out))
 
@@ -301,18 +299,20 @@ def scan_study(args):
     nw, seed = run.W, 2001
     rows = []
     for P, ns in [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (8, 2), (8, 4)]:
-        ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=1.0)
+        ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw,
+                        xbar_cap=STABLE["xbar_cap"], weight_mode=A.WEIGHT_LOCAL,
+                        proposal=A.PROPOSAL_RW, rw_step=RW_STEP_FP64)
         st = D.init_walkers(ctx, sys_.phi0, nw, seed)
         est = torch.zeros(2, dtype=torch.float64, device="cuda")
         for i in range(args.warmup):
-            D.step(ctx, st, seed, i, est, n_sweep=ns, n_qr=run.n_qr, n_pc=1, w_cap=4.0)
+            D.step(ctx, st, seed, i, est, n_sweep=ns, n_qr=run.n_qr, n_pc=1)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
             D.step(ctx, st, seed, args.warmup + k, est, n_sweep=ns, n_qr=run.n_qr,
-                   contract_events=evs[k], n_pc=1, w_cap=4.0)
+                   contract_events=evs[k], n_pc=1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         cms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
@@ -332,98 +332,16 @@ def scan_study(args):
         "ms_per_step": ref["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"scan-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}-K{sys_.K}-W{nw}",
-                   "walkers": nw},
+                   "walkers": nw, "proposal": "random walk", "rw_step": RW_STEP_FP64,
+                   "L_scale": L_SCALE, "weights": STABLE["weights"],
+                   "xbar_cap": STABLE["xbar_cap"], "comb_every": 1,
+                   "eloc_cap": "none (E_T is not tracked in this cost scan)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
                      "kernel": "k_contract (+ k_combine) in afqmc_local_energy, P = 8",
                      "ms_per_launch": ref["contraction_ms"], "flops_per_launch": flops},
         "scan": rows,
         "linear_fit_ms_per_step_vs_P": {"slope_ms": float(slope), "intercept_ms": float(icept)},
-    }
-    print(json.dumps(out))
-
-
-def mixed_study(args):
-    """The mixed-precision forms at fixed energy error on the FP64 workload's
-    system (M=64, N=16, 256 vectors, K=64, 512 walkers x 8 paths) with the
-    random-walk proposal (step 0.3), where long runs are stable: the FP32,
-    split-BF16 and BF16 contractions and the all-FP64 form run the same steps
-    from the same walkers and seeds; energies reblocked over the timed steps, their
-    difference against the combined error bar, and the throughput of the
-    mixed form at the FP64 form's energy error.  (The mixed workload's own
-    system, M=128 with K=128, loses its path-sign average within a few tens
-    of steps, so its energies carry no usable error bar.)"""
-    import torch
-    import afqmc_inputs as ai
-    from paper_2505_18519_amd import afqmc as A
-    from paper_2505_18519_amd import driver as D
-
-    sys_, run = ai.workload(1)
-    nw, P, seed = run.W, run.P, 2002
-
-    def leg(prec):
-        ctx = A.Context(sys_, P, run.dtau, n_taylor=run.n_taylor, max_walkers=nw, xbar_cap=1.0,
-                        precision=prec, proposal=A.PROPOSAL_RW, rw_step=0.3)
-        st = D.init_walkers(ctx, sys_.phi0, nw, seed)
-        est = torch.zeros(args.warmup + args.steps, 2, dtype=torch.float64, device="cuda")
-        for i in range(args.warmup):
-            D.step(ctx, st, seed, i, est[i], n_qr=run.n_qr, n_pc=1, w_cap=4.0)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            i = args.warmup + k
-            D.step(ctx, st, seed, i, est[i], n_qr=run.n_qr, contract_events=evs[k], n_pc=1,
-                   w_cap=4.0)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        e = est.cpu().numpy()[args.warmup:]
-        en = e[:, 0] / e[:, 1]
-        ctx.close()
-        print(f"precision {prec}: {1e3 * dt / args.steps:.2f} ms/step, E = {en.mean():.6f} +- "
-              f"{reblock(en):.6f}", file=sys.stderr, flush=True)
-        return {"walker_steps_per_s": nw * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
-                "contraction_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
-                "energy": float(en.mean()), "energy_err": reblock(en),
-                "max_step_energy_difference": None, "series": en}
-
-    F32 = leg(A.PREC_FP32)
-    B3 = leg(A.PREC_BF16X3)
-    B1 = leg(A.PREC_BF16)
-    F64 = leg(A.PREC_FP64)
-
-    def versus_fp64(d):
-        d["max_step_energy_difference"] = float(np.max(np.abs(d["series"] - F64["series"])))
-        d["energy_difference"] = d["energy"] - F64["energy"]
-        d["combined_error"] = float(np.hypot(d["energy_err"], F64["energy_err"]))
-        d["equal_error_throughput_ratio"] = (d["walker_steps_per_s"] / F64["walker_steps_per_s"]) * (
-            (F64["energy_err"] ** 2) / max(d["energy_err"] ** 2, 1e-300))
-
-    for d in (F32, B3, B1):
-        versus_fp64(d)
-    for d in (F32, B3, B1, F64):
-        del d["series"]
-    F64["max_step_energy_difference"] = F32["max_step_energy_difference"]
-    comb = F32["combined_error"]
-    ratio = F32["equal_error_throughput_ratio"]
-    flops = contraction_flops(sys_.M, sys_.N, sys_.n_chol) * nw * P
-    achieved = flops / (F32["contraction_ms"] * 1e-3) / 1e12
-    out = {
-        "metric": METRIC, "value": F32["walker_steps_per_s"], "unit": "walker-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": F32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32-contraction/f64", "data": "synthetic",
-        "config": {"workload": f"mixed-vs-fp64-gauss-M{sys_.M}-N{sys_.N}-G{sys_.n_chol}"
-                               f"-K{sys_.K}-W{nw}-P{P}-dtau{run.dtau}-rw0.3", "walkers": nw,
-                   "paths": P},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "kernel": "k_contract_sh, FP32 products (+ k_combine) in afqmc_local_energy",
-                     "ms_per_launch": F32["contraction_ms"], "flops_per_launch": flops},
-        "fp32_products": F32, "bf16x3_products": B3, "bf16_products": B1, "fp64": F64,
-        "energy_difference": F32["energy"] - F64["energy"], "combined_error": comb,
-        "equal_error_throughput_ratio": ratio,
     }
     print(json.dumps(out))
 
@@ -539,7 +457,7 @@ def fixed_error_study(args):
                           <= 3 * np.hypot(a["error_of_mean"], b["error_of_mean"]))
     # the statistical error of one run: the seed-to-seed spread pooled over every
     # configuration (a few seeds per configuration make each spread alone a poor
-    # estimate; reblocking single runs understates it, see below)
+    # estimate; reblocking single runs understates it: reblocked_over_pooled)
     pooled_var = float(np.mean([d["sigma_run"] ** 2 for d in res.values()]))
     sigma = float(np.sqrt(pooled_var))
     eps = sigma
@@ -603,13 +521,16 @@ def uneven_study(args):
     from paper_2505_18519_amd import driver as D
 
     systems, runs = ai.workload(3)
-    specs = [(s, r.P, r.dtau, dict(xbar_cap=1.0)) for s, r in zip(systems, runs)]
+    # local-energy weights with the force-bias cap (STABLE without the E_L cap: the
+    # replayed graph fixes every kernel argument, so E_T cannot move during the run)
+    specs = [(s, r.P, r.dtau, dict(xbar_cap=STABLE["xbar_cap"], weight_mode=A.WEIGHT_LOCAL))
+             for s, r in zip(systems, runs)]
     walkers = [r.W for r in runs]
     total_w = sum(walkers)
     flops = sum(contraction_flops(s.M, s.N, s.n_chol) * r.W * r.P for s, r in zip(systems, runs))
     seed = 2003
     t_build = time.perf_counter()
-    b = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=4.0,
+    b = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=0.0,
                 max_branches=4, autotune=True, history=64)
     print(f"uneven batch built and tuned in {time.perf_counter() - t_build:.1f} s, cycle "
           f"{b.cycle} steps", file=sys.stderr, flush=True)
@@ -636,7 +557,7 @@ def uneven_study(args):
     # agreement: a batch with each system's default kernel family (no tuner)
     # and each system alone through the per-system calls, same seeds, 20 steps
     n_check = 20
-    bv = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=4.0,
+    bv = A.Batch(specs, walkers, seed=seed, n_sweep=1, n_qr=10, n_pc=1, w_cap=0.0,
                  max_branches=4, autotune=False, history=64)
     bv.run(n_check // bv.cycle)
     vsums, _ = bv.estimates()
@@ -649,7 +570,7 @@ def uneven_study(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(n_check):
-            D.step(ctx, st, seed + i, k, est[k], n_pc=1, w_cap=4.0)
+            D.step(ctx, st, seed + i, k, est[k], n_pc=1)
         torch.cuda.synchronize()
         seq_ms += 1e3 * (time.perf_counter() - t1) / n_check
         ref = est.cpu().numpy()
@@ -674,7 +595,9 @@ def uneven_study(args):
                    "M_range": [min(s.M for s in systems), max(s.M for s in systems)],
                    "walkers": total_w, "paths": 4, "cycle_steps": b.cycle,
                    "branches": nb, "families": [int(f) for f in fam],
-                   "L_scale": L_SCALE, "xbar_cap": 1.0, "comb_every": 1, "weight_cap": 4.0},
+                   "L_scale": L_SCALE, "weights": "local energy", "xbar_cap": STABLE["xbar_cap"],
+                   "eloc_cap": "none (the replayed graph fixes E_T)", "comb_every": 1,
+                   "comb_weights_reset_to": 1.0, "weight_cap": 0.0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
                      "kernel": "all systems' contractions per whole step (a lower bound on the "
@@ -699,8 +622,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fp64",
-                    choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "mixed-study",
-                                                 "fixed-error"])
+                    choices=sorted(WORKLOADS) + ["learned", "uneven", "scan", "fixed-error"])
     ap.add_argument("--seeds", type=int, default=4,
                     help="independent runs per configuration (fixed-error workload)")
     ap.add_argument("--fe-sweeps-rw", type=int, nargs="+", default=[1, 2, 4, 8, 16, 32],
@@ -750,9 +672,6 @@ def main():
         return
     if args.workload == "scan":
         scan_study(args)
-        return
-    if args.workload == "mixed-study":
-        mixed_study(args)
         return
     if args.workload == "fixed-error":
         fixed_error_study(args)
