@@ -62,7 +62,8 @@ void free_ctx(afqmc_ctx_s* c) {
   auto& m = c->mlp;
   void* ptrs[] = {c->d_h1,  c->d_Lraw, c->d_Lpad,  c->d_Eh,   c->d_phi0, c->d_A,   c->d_Lpad32,
                   c->d_Lbf, c->d_Lbf_lo, c->d_F,    c->d_phi0c, m.master,  m.mom1,   m.mom2,
-                  m.w1t,    m.w2t,     m.w3t,       m.w2c,      m.w3c,     m.tstep,  m.scal};
+                  m.w1t,    m.w2t,     m.w3t,       m.w2c,      m.w3c,     m.tstep,  m.scal,
+                  c->d_Adiag};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -415,6 +416,26 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
       free_ctx(c);
       delete c;
       return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
+    }
+  }
+  if (!slices) {  // diagonal generators: keep only their diagonals for the row-scaling build
+    bool diag = K > 0;
+    for (int k = 0; k < K && diag; ++k)
+      for (int i = 0; i < M && diag; ++i)
+        for (int j = 0; j < M; ++j)
+          if (i != j && sys->A[((size_t)k * M + i) * M + j] != 0.0) {
+            diag = false;
+            break;
+          }
+    if (diag) {
+      std::vector<double> d((size_t)K * M);
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < M; ++i) d[(size_t)k * M + i] = sys->A[((size_t)k * M + i) * M + i];
+      if ((e = dev_copy(&c->d_Adiag, d.data(), d.size())) != hipSuccess) {
+        free_ctx(c);
+        delete c;
+        return e == hipErrorOutOfMemory ? AFQMC_E_NOMEM : AFQMC_E_DEVICE;
+      }
     }
   }
   if ((e = launch_setup(c)) == hipSuccess && c->precision == AFQMC_PREC_FP32) {

@@ -31,6 +31,9 @@ struct afqmc_ctx_s {
   double* d_Eh = nullptr;    // [M][M] = exp(-tau h1 / 2)
   double* d_phi0 = nullptr;  // [M][N]
   double* d_A = nullptr;      // [K][M][M] trial generators (dense)
+  // every generator diagonal (the Ising pair operators): their diagonals, [K][M];
+  // the trial build is then the row scaling exp(c sum_k y_k A_k[i][i]) of Phi_0
+  double* d_Adiag = nullptr;
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad: A-operand order, row-major with ctrial
   unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad, A-operand order (BF16 contractions)
   unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf, same order (split BF16)

@@ -1,6 +1,8 @@
 // Sampled trial determinants Phi_T(y) = exp(c sum_k y_k A_k) Phi_0 (Sec. II.C,
 // Eq. trial_decomp; Sec. III.A, Eq. Metropolis_sampled_trial), FP64 matrix cores.
 //
+// k_trial_diag: generators that are all diagonal (the Ising pair operators)
+//   give a diagonal U, and exp(U) Phi_0 is a row scaling of Phi_0.
 // k_ubuild: U_s = c sum_k y_{s,k} A_k for every path s, one product
 //   (paths x K) by (K x M^2) with the generators streamed once per 16 paths.
 // k_trial_taylor: one wavefront per path holds its U in registers as MFMA A
@@ -105,6 +107,27 @@ k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
         const int s = s0 + 16 * pt + g + 4 * r, e = e0 + 16 * et + c;
         if (s < S && e < MM) U[(size_t)s * MM + e] = coupling * acc[pt][et][r];
       }
+}
+
+// Diagonal generators (the Ising pair operators): U is diagonal, so exp(U) Phi_0
+// scales row i of Phi_0 by exp(c sum_k y_k A_k[i][i]); one thread per entry.
+__global__ void k_trial_diag(int n_samples, int M, int N, int K, double coupling,
+                             const double* __restrict__ y, const double* __restrict__ Adiag,
+                             const double* __restrict__ phi0, double* __restrict__ phiT) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_samples * M * N) return;
+  const int n = (int)(idx % N), i = (int)((idx / N) % M);
+  const size_t s = idx / ((size_t)M * N);
+  double u = 0.0;
+  for (int k = 0; k < K; ++k) u = fma(y[s * K + k], Adiag[(size_t)k * M + i], u);
+  phiT[idx] = exp(coupling * u) * phi0[(size_t)i * N + n];
+}
+
+hipError_t launch_trial_diag(const afqmc_ctx_s* c, int n, const double* y, double* phiT) {
+  const size_t total = (size_t)n * c->M * c->N;
+  hipLaunchKernelGGL(k_trial_diag, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
+                     n, c->M, c->N, c->K, c->coupling, y, c->d_Adiag, c->d_phi0, phiT);
+  return hipGetLastError();
 }
 
 // the dropped tail may be at most this fraction of max|sum|
@@ -250,6 +273,7 @@ hipError_t launch_mt(const afqmc_ctx_s* c, int n, const double* U, double* phiT)
 hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
                               double* ubuf) {
   if (n_samples <= 0) return hipSuccess;
+  if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
   hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
@@ -444,6 +468,7 @@ hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const doubl
                                 double* ubuf) {
   if (n_samples <= 0) return hipSuccess;
   if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
+  if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
   const int MM = c->M * c->M;
   dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
   hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
