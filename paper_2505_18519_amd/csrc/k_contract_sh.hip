@@ -28,9 +28,12 @@
 // row tile, its A operands read from the shared slab.  Y_g^T is rounded to the
 // operand form once, as stage 1 leaves it, and stored in LDS in the accumulator
 // layout, which is stage 2's A-operand layout (rows 4g .. 4g+3 of a column in
-// one lane); f is transposed through LDS for tr(f f).  Each lane's eight
-// products of FP32 entries of f for tr(f f) are summed in FP32 per vector;
-// the traces, the sums over lanes, vb_g^2 and the sums over g are FP64.
+// one lane; in BF16 the two 4-row groups of one operand side by side, so that
+// an operand is one 16-byte read); f is transposed through LDS for tr(f f), as
+// separate real and imaginary planes whose rows start on 16-byte boundaries.
+// Each lane's eight products of FP32 entries of f for tr(f f) are summed in
+// FP32 per vector; the traces, the sums over lanes, vb_g^2 and the sums over g
+// are FP64.
 
 #include <type_traits>
 
@@ -80,7 +83,7 @@ struct Form {
   static constexpr bool X3 = FM == FM_BF16X3;
   static constexpr bool F32 = FM == FM_FP32;
   static constexpr int NP = X3 ? 2 : 1;             // parts: hi (and lo)
-  static constexpr int NB = FM == FM_BF16 ? 2 : 1;  // slab and Y^T buffers
+  static constexpr int NB = FM == FM_BF16 ? 2 : 1;  // slab buffers (shared slabs)
   static constexpr int KV = F32 ? 4 : 8;            // k values per lane and block
   static constexpr int KB = 4 * KV;                 // k per block
   typedef typename std::conditional<F32, fx4, sx8>::type V;
@@ -144,16 +147,24 @@ struct Form {
 };
 
 // ---------------------------------------------------------------------------
-// BCP paths per workgroup sharing each L slab (two; four when a path has
-// three wavefronts, so that the twelve wavefronts put three on every SIMD
-// instead of two on some and one on others): the slab of vector g + 1 goes
-// from global memory straight into LDS (global_load_lds) during vector g,
-// already in A-operand order ([row tile][k tile][lane][4]: one 8-byte LDS read
-// per product, consecutive lanes on consecutive words), so every L byte crosses
-// L2 once per workgroup instead of once per path.  f is staged for the
-// transpose in FP32 (its products are FP32) and the diagonals flush every BFL
-// vectors.
+// BCP paths per workgroup sharing each L slab: the slab goes from global memory
+// straight into LDS (global_load_lds), already in A-operand order
+// ([row tile][k tile][lane][operand]: consecutive lanes on consecutive words),
+// so every L byte crosses L2 once per workgroup instead of once per path.
+// Double-buffered slabs load the slab of vector g + 1 during the whole of
+// vector g; single buffers load it from the barrier after stage 1 on.  f is
+// staged for the transpose in FP32 (its products are FP32); the diagonals are
+// staged in FP32 and flush every BFL vectors, four lanes per sum.
 constexpr int BFL = 8;  // vectors per flush of the staged diagonals
+
+// Paths per workgroup.  Four when a path has three wavefronts (twelve
+// wavefronts put three on every SIMD instead of two on some and one on
+// others).  Plain BF16 with four wavefronts per path (N = 25 .. 32): one, with
+// a single slab buffer (about 64 KB of LDS), so that two independent
+// workgroups share a CU and one's matrix-core phase overlaps the other's
+// conversion, transpose and trace phase; two per workgroup would share the
+// slab but run every phase of all eight wavefronts in step.  Otherwise two.
+constexpr int bcp_for(int fm, int ncp) { return ncp == 3 ? 4 : (fm == FM_BF16 && ncp == 4) ? 1 : 2; }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
@@ -161,14 +172,14 @@ typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 // FULL: N = 16 NTC (every column tile full, NCP = 2 NTC), so the packed
 // columns are the two spins' tiles in order and no column or row is padding.
 template <int KT, int NTC, int NCP, int FM, bool FULL, int BCP>
-__global__ void __launch_bounds__(64 * NCP * BCP)
+__global__ void __launch_bounds__(64 * NCP * BCP) __attribute__((amdgpu_waves_per_eu(2)))
 k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
                const void* __restrict__ Lop_lo, const double* __restrict__ phiT,
                const double* __restrict__ theta,
                const double* __restrict__ logov, double* __restrict__ vb, double* __restrict__ ep) {
   constexpr int MT = 16 * KT;
   constexpr int NWV = NCP;                     // wavefronts per path
-  constexpr int PW = 16 * NCP + 1;             // row length of the staged f (packed columns)
+  constexpr int PW = 16 * NCP + 4;             // row length of the staged f (packed columns; 16-byte rows)
   constexpr int NWT = NWV * BCP;               // wavefronts per workgroup
   constexpr int NT = 16 * NTC;
   constexpr int S1MAX = (KT + NWV - 1) / NWV;  // stage-1 row tiles per wavefront
@@ -183,18 +194,19 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   constexpr int NU = SV * (int)sizeof(V) / 16; // 16-byte units per slab part
   constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
   constexpr int YT = (MTP / 4) * NT;           // 4-row groups (V4) of one Y^T tile part
-  // plain BF16: slabs and Y^T tiles double-buffered (the next slab loads during
-  // the whole vector); split BF16 (hi and lo of each) and FP32 (twice the
-  // bytes): single buffers, the next slab loading from the barrier after stage 1
-  // on, so that LDS still fits
-  constexpr int NB = Fm::NB;                   // buffers
+  // plain BF16 shared by several paths: slabs double-buffered (the next slab
+  // loads during the whole vector); one path, split BF16 (hi and lo) and FP32
+  // (twice the bytes): a single buffer, the next slab loading from the barrier
+  // after stage 1 on.  The Y^T tile is single: it is rewritten only after the
+  // barrier that follows every stage-2 read of it.
+  constexpr int NB = BCP == 1 ? 1 : Fm::NB;    // slab buffers
   constexpr int NP = Fm::NP;                   // parts (hi, lo)
   extern __shared__ double smem[];
   V* sL = reinterpret_cast<V*>(smem);                                      // [NB][NP][SV]
-  V4* sY = reinterpret_cast<V4*>(sL + NB * NP * SV);                       // [BCP][NB][NP][YT]
-  float* sF = reinterpret_cast<float*>(sY + BCP * NB * NP * YT);           // [BCP][NT][PW][2]
-  double* sD = reinterpret_cast<double*>(sF + BCP * NT * PW * 2);          // [BCP][BFL][NWV*16][2]
-  double* sE = sD + BCP * BFL * NWV * 16 * 2;                              // [BCP][NWV][2]
+  V4* sY = reinterpret_cast<V4*>(sL + NB * NP * SV);                       // [BCP][NP][YT]
+  float* sF = reinterpret_cast<float*>(sY + BCP * NP * YT);           // [BCP][re, im][NT][PW]
+  float* sD = sF + BCP * 2 * NT * PW;                                   // [BCP][BFL][re, im][NWV*16]
+  double* sE = reinterpret_cast<double*>(sD + BCP * BFL * 2 * NWV * 16);  // [BCP][NWV][2]
   double* sT = sE + BCP * NWV * 2;                                         // [NWT][4]
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -211,6 +223,14 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   const int sc = valid ? s : n_samples - 1;
   const bool active = valid && !__builtin_isinf(logov[2 * sc]);
 
+  // Y^T tile index of 4-row group grp, column col: BF16 keeps groups 2p and 2p + 1 of a
+  // column side by side (one stage-2 operand is one 16-byte read)
+  auto yidx = [&](int grp, int col) {
+    if constexpr (Fm::F32)
+      return grp * NT + col;
+    else
+      return ((grp >> 1) * NT + col) * 2 + (grp & 1);
+  };
   auto copy_slab = [&](int slab, int buf) {
 #pragma unroll
     for (int part = 0; part < NP; ++part) {
@@ -225,7 +245,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   };
   copy_slab(0, 0);
   if (MTP > MT) {  // the Y^T rows of a padded k block are never written: zero them once
-    for (int q = threadIdx.x; q < BCP * NB * NP * ((MTP - MT) / 4) * NT; q += blockDim.x) {
+    for (int q = threadIdx.x; q < BCP * NP * ((MTP - MT) / 4) * NT; q += blockDim.x) {
       const int per = ((MTP - MT) / 4) * NT;
       const int tile = q / per, e = q % per;
       V4 z;
@@ -264,9 +284,9 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
-  V4* Yp = sY + pw * NB * NP * YT;
-  float* Fp = sF + (size_t)pw * NT * PW * 2;
-  double* Dp = sD + (size_t)pw * BFL * NWV * 16 * 2;
+  V4* Yp = sY + pw * NP * YT;
+  float* Fp = sF + (size_t)pw * 2 * NT * PW;
+  float* Dp = sD + (size_t)pw * BFL * 2 * NWV * 16;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
   for (int gam = 0; gam <= G; ++gam) {
     const int b = NB == 2 ? (gam & 1) : 0;
@@ -280,7 +300,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
-      if (active && tp < KT)
+      if (tp < KT)  // an inactive path's operands are zero
 #pragma unroll
         for (int t = 0; t < KBN; ++t) {
           Op a;
@@ -292,7 +312,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     }
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
     if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
-    V4* Yb = Yp + b * NP * YT;
+    V4* Yb = Yp;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -302,7 +322,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
           const fx4 v = y1[q][ct];
           const typename Fm::Op4 yv = Fm::make4(v[0], v[1], v[2], v[3]);
 #pragma unroll
-          for (int part = 0; part < NP; ++part) Yb[part * YT + (4 * tp + g) * NT + 16 * ct + c] = yv.p[part];
+          for (int part = 0; part < NP; ++part) Yb[part * YT + yidx(4 * tp + g, 16 * ct + c)] = yv.p[part];
         }
     }
     __syncthreads();
@@ -313,7 +333,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     fx4 f[NTC][2];
 #pragma unroll
     for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
-    if (active) {
+    {
 #pragma unroll
       for (int t = 0; t < KBN; ++t)
 #pragma unroll
@@ -322,28 +342,28 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
           const int grp = (KB * t + KV * g) / 4;
 #pragma unroll
           for (int part = 0; part < NP; ++part) {
-            const V4* yg = Yb + part * YT + grp * NT + 16 * it + c;
+            const V4* yg = Yb + part * YT + yidx(grp, 16 * it + c);
             if constexpr (Fm::F32)
               a.p[part] = yg[0];
             else
-              a.p[part] = Fm::join(yg[0], yg[NT]);
+              a.p[part] = *reinterpret_cast<const V*>(yg);  // groups grp, grp + 1: one 16-byte read
           }
           f[it][0] = Fm::mma(a, th[0][t], f[it][0]);
           f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
         }
     }
     // diagonal of f^sp: the lane's element in row n of its packed column
-    double d_re = 0.0, d_im = 0.0;
+    float d_re = 0.f, d_im = 0.f;
     if constexpr (FULL) {  // tile (it, it) of spin sp: element (4g + r, c) with 4g + r == c
-      const int jd = wv - sp * NTC;
+      const int jd = __builtin_amdgcn_readfirstlane(wv - sp * NTC);  // the same on every lane
 #pragma unroll
       for (int it = 0; it < NTC; ++it)
         if (it == jd)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             if (4 * g + r == c) {
-              d_re = (double)f[it][0][r];
-              d_im = (double)f[it][1][r];
+              d_re = f[it][0][r];
+              d_im = f[it][1][r];
             }
     } else {
 #pragma unroll
@@ -351,16 +371,15 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (qok && 16 * it + 4 * g + r == n) {
-            d_re = (double)f[it][0][r];
-            d_im = (double)f[it][1][r];
+            d_re = f[it][0][r];
+            d_im = f[it][1][r];
           }
     }
     if (gam == G) {  // h1': the path's one-body traces through LDS
-      d_re = wave_sum(d_re);
-      d_im = wave_sum(d_im);
+      const double t_re = wave_sum((double)d_re), t_im = wave_sum((double)d_im);
       if (lane == 0) {
-        sE[wave * 2] = d_re;
-        sE[wave * 2 + 1] = d_im;
+        sE[wave * 2] = t_re;
+        sE[wave * 2 + 1] = t_im;
       }
       __syncthreads();
       if (wv == 0 && lane == 0) {
@@ -377,13 +396,13 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * it + 4 * g + r;
-        Fp[(i * PW + q) * 2] = f[it][0][r];
-        Fp[(i * PW + q) * 2 + 1] = f[it][1][r];
+        Fp[i * PW + q] = f[it][0][r];
+        Fp[(NT + i) * PW + q] = f[it][1][r];
       }
     if (g == ((n & 15) >> 2)) {  // the lane group holding row n (0 for padding columns)
-      double* d = Dp + ((size_t)(gam % BFL) * NWV * 16 + wv * 16 + c) * 2;
+      float* d = Dp + (gam % BFL) * 2 * NWV * 16 + wv * 16 + c;
       d[0] = d_re;
-      d[1] = d_im;
+      d[NWV * 16] = d_im;
     }
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
     __syncthreads();
@@ -392,30 +411,58 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     // f^sp_{i n} f^sp_{n i}: the partner sits in row n, packed column sp N + i
     float xr = 0.f, xi = 0.f;
 #pragma unroll
-    for (int it = 0; it < NTC; ++it)
+    for (int it = 0; it < NTC; ++it) {
+      float pr[4], pi[4];  // f^sp_{n i}, i = 16 it + 4 g + r
+      if constexpr (FULL) {  // four consecutive packed columns: one 16-byte read per plane
+        const int src = n * PW + sp * NN + 16 * it + 4 * g;
+        const fx4 a = *reinterpret_cast<const fx4*>(Fp + src);
+        const fx4 b = *reinterpret_cast<const fx4*>(Fp + NT * PW + src);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pr[r] = a[r];
+          pi[r] = b[r];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + 4 * g + r;
+          const bool ok = qok && i < N;
+          const int src = ok ? n * PW + sp * NN + i : 0;
+          pr[r] = ok ? Fp[src] : 0.f;
+          pi[r] = ok ? Fp[NT * PW + src] : 0.f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * g + r;
-        const bool ok = FULL || (qok && i < N);
-        const int src = ok ? (n * PW + sp * NN + i) * 2 : 0;
-        const float tr_ = ok ? Fp[src] : 0.f, ti_ = ok ? Fp[src + 1] : 0.f;
         const float ar = f[it][0][r], ai = f[it][1][r];
-        xr = fmaf(ar, tr_, xr);
-        xr = fmaf(-ai, ti_, xr);
-        xi = fmaf(ar, ti_, xi);
-        xi = fmaf(ai, tr_, xi);
+        xr = fmaf(ar, pr[r], xr);
+        xr = fmaf(-ai, pi[r], xr);
+        xi = fmaf(ar, pi[r], xi);
+        xi = fmaf(ai, pr[r], xi);
       }
+    }
     ex_re += (double)xr;
     ex_im += (double)xi;
     // every BFL vectors: wavefront 0 of each path reduces its staged diagonals to vb_g
+    // four lanes per sum (vector gl, part re/im), NWV * 4 staged values each, summed in FP64
     if ((gam % BFL == BFL - 1 || gam == G - 1) && wv == 0 && valid) {
+      static_assert(BFL * 2 * 4 == 64, "one lane quad per staged vector and part");
+      constexpr int QN = NWV * 16, QL = QN / 4;
       const int cnt = gam % BFL + 1, g0 = gam - gam % BFL;
-      const int gl = lane % BFL, part = (lane / BFL) & 1;
+      const int gl = lane >> 3, part = (lane >> 2) & 1, qq = lane & 3;
       double v = 0.0;
-      if (lane < 2 * BFL && gl < cnt)
-        for (int q = 0; q < NWV * 16; ++q) v += Dp[((size_t)gl * NWV * 16 + q) * 2 + part];
-      const double vi = __shfl_down(v, BFL, 64);
-      if (lane < BFL && gl < cnt) {
+      if (gl < cnt) {
+        const fx4* src = reinterpret_cast<const fx4*>(Dp + (gl * 2 + part) * QN + qq * QL);
+#pragma unroll
+        for (int e = 0; e < QL / 4; ++e) {
+          const fx4 x = src[e];
+          v += ((double)x[0] + (double)x[1]) + ((double)x[2] + (double)x[3]);
+        }
+      }
+      v += dpp_f64<0xB1>(v);  // quad sum
+      v += dpp_f64<0x4E>(v);
+      const double vi = __shfl_down(v, 4, 64);
+      if ((lane & 7) == 0 && gl < cnt) {
         vb2_re += v * v - vi * vi;
         vb2_im += 2.0 * v * vi;
         double* o = vb + ((size_t)s * G + g0 + gl) * 2;
@@ -451,15 +498,17 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     for (int q = lane; q < 2 * G; q += 64) vb[(size_t)s * G * 2 + q] = 0.0;
 }
 
-// buffers x parts x bytes per entry = 2 x 1 x 2 (BF16), 1 x 2 x 2 (split BF16)
-// or 1 x 1 x 4 (FP32), over MT x MTP entries (MTP: k padded to whole blocks)
+// slabs: buffers x parts x bytes per entry = 2 x 1 x 2 (BF16 shared; 1 x 1 x 2
+// for one path), 1 x 2 x 2 (split BF16) or 1 x 1 x 4 (FP32), over MT x MTP
+// entries (MTP: k padded to whole blocks); Y^T tiles: parts x bytes per 4-row
+// group = 1 x 8 (BF16), 2 x 8 (split BF16), 1 x 16 (FP32)
 size_t lds_bytes_s(int KT, int NTC, int NCP, int FM, int BCP) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = NCP;
   const int KB = FM == FM_FP32 ? 16 : 32, MTP = (MT + KB - 1) / KB * KB;
-  size_t b = (size_t)4 * MT * MTP;                    // slabs
-  b += (size_t)BCP * (MTP / 4) * NT * 16;             // Y^T tiles
-  b += (size_t)BCP * NT * (16 * NCP + 1) * 2 * 4;     // packed f (FP32)
-  b += (size_t)BCP * BFL * NWV * 16 * 2 * 8;          // staged diagonals
+  size_t b = (size_t)(BCP == 1 && FM == FM_BF16 ? 2 : 4) * MT * MTP;  // slabs
+  b += (size_t)BCP * (MTP / 4) * NT * (FM == FM_FP32 ? 16 : FM == FM_BF16X3 ? 16 : 8);  // Y^T tiles
+  b += (size_t)BCP * NT * (16 * NCP + 4) * 2 * 4;     // packed f (FP32)
+  b += (size_t)BCP * BFL * NWV * 16 * 2 * 4;          // staged diagonals (FP32)
   b += (size_t)BCP * NWV * 2 * 8 + (size_t)BCP * NWV * 4 * 8;
   return b;
 }
@@ -487,7 +536,7 @@ hipError_t dispatch_s(const afqmc_ctx_s* c, int nw, const void* L, const void* L
   const bool full = c->N == 16 * NTC;
 #define AFQMC_BS(KK, NC, NP, FL)                           \
   if (KT == KK && NTC == NC && NCP == NP && full == FL) \
-    return launch_sh<KK, NC, NP, FM, FL, NP == 3 ? 4 : 2>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
+    return launch_sh<KK, NC, NP, FM, FL, bcp_for(FM, NP)>(c, nw, L, L_lo, phiT, theta, logov, vb, ep);
 #define AFQMC_BS1(KK) AFQMC_BS(KK, 1, 1, false) AFQMC_BS(KK, 1, 2, false) AFQMC_BS(KK, 1, 2, true)
 #define AFQMC_BS2(KK) AFQMC_BS(KK, 2, 3, false) AFQMC_BS(KK, 2, 4, false) AFQMC_BS(KK, 2, 4, true)
   AFQMC_BS1(1) AFQMC_BS1(2) AFQMC_BS1(3) AFQMC_BS1(4)
