@@ -147,7 +147,7 @@ struct Form {
 };
 
 // ---------------------------------------------------------------------------
-// BCP paths per workgroup sharing each L slab: the slab goes from global memory
+// BCP > 1 paths per workgroup sharing each L slab: the slab goes from global memory
 // straight into LDS (global_load_lds), already in A-operand order
 // ([row tile][k tile][lane][operand]: consecutive lanes on consecutive words),
 // so every L byte crosses L2 once per workgroup instead of once per path.
@@ -159,11 +159,14 @@ constexpr int BFL = 8;  // vectors per flush of the staged diagonals
 
 // Paths per workgroup.  Four when a path has three wavefronts (twelve
 // wavefronts put three on every SIMD instead of two on some and one on
-// others).  Plain BF16 with four wavefronts per path (N = 25 .. 32): one, with
-// a single slab buffer (about 64 KB of LDS), so that two independent
-// workgroups share a CU and one's matrix-core phase overlaps the other's
-// conversion, transpose and trace phase; two per workgroup would share the
-// slab but run every phase of all eight wavefronts in step.  Otherwise two.
+// others).  Plain BF16 with four wavefronts per path (N = 25 .. 32): one path,
+// with no slab in LDS: each wavefront loads its own stage-1 A operands of
+// vector g + 1 from global memory (L2) into registers during vector g, a whole
+// vector ahead of their use, and two independent workgroups (about 30 KB of
+// LDS each) share a CU, so that one's matrix-core phase overlaps the other's
+// conversion, transpose and trace phase.  Two paths per workgroup would share
+// the slab through LDS but run every phase of all eight wavefronts in step.
+// Otherwise two.
 constexpr int bcp_for(int fm, int ncp) { return ncp == 3 ? 4 : (fm == FM_BF16 && ncp == 4) ? 1 : 2; }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
@@ -194,12 +197,15 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   constexpr int NU = SV * (int)sizeof(V) / 16; // 16-byte units per slab part
   constexpr int NCH = (NU + 63) / 64;          // 1 KB chunks per slab (the last may be partial)
   constexpr int YT = (MTP / 4) * NT;           // 4-row groups (V4) of one Y^T tile part
-  // plain BF16 shared by several paths: slabs double-buffered (the next slab
-  // loads during the whole vector); one path, split BF16 (hi and lo) and FP32
-  // (twice the bytes): a single buffer, the next slab loading from the barrier
-  // after stage 1 on.  The Y^T tile is single: it is rewritten only after the
-  // barrier that follows every stage-2 read of it.
-  constexpr int NB = BCP == 1 ? 1 : Fm::NB;    // slab buffers
+  // Slabs in LDS when several paths share them: plain BF16 double-buffered (the
+  // next slab loads during the whole vector), split BF16 (hi and lo) and FP32
+  // (twice the bytes) single, the next slab loading from the barrier after
+  // stage 1 on.  One path per workgroup (DIRECT): no slab in LDS; each
+  // wavefront loads its stage-1 A operands of vector g + 1 from global memory
+  // into registers during vector g.  The Y^T tile is single: it is rewritten
+  // only after the barrier that follows every stage-2 read of it.
+  constexpr bool DIRECT = BCP == 1;
+  constexpr int NB = DIRECT ? 0 : Fm::NB;      // slab buffers
   constexpr int NP = Fm::NP;                   // parts (hi, lo)
   extern __shared__ double smem[];
   V* sL = reinterpret_cast<V*>(smem);                                      // [NB][NP][SV]
@@ -243,7 +249,26 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
                                            (lds_ptr_t)(dst + k * 1024), 16, 0, 0);
     }
   };
-  copy_slab(0, 0);
+  Op an[DIRECT ? S1MAX : 1][DIRECT ? KBN : 1];  // direct form: the next vector's A operands
+  auto load_ops = [&](int slab) {
+    if constexpr (DIRECT) {
+#pragma unroll
+      for (int q = 0; q < S1MAX; ++q) {
+        const int tp = wv + NWV * q;
+        if (tp < KT)
+#pragma unroll
+          for (int t = 0; t < KBN; ++t)
+#pragma unroll
+            for (int part = 0; part < NP; ++part)
+              an[q][t].p[part] = reinterpret_cast<const V*>(
+                  part ? Lop_lo : Lop)[(size_t)slab * SV + (tp * KBN + t) * 64 + lane];
+      }
+    }
+  };
+  if constexpr (DIRECT)
+    load_ops(0);
+  else
+    copy_slab(0, 0);
   if (MTP > MT) {  // the Y^T rows of a padded k block are never written: zero them once
     for (int q = threadIdx.x; q < BCP * NP * ((MTP - MT) / 4) * NT; q += blockDim.x) {
       const int per = ((MTP - MT) / 4) * NT;
@@ -281,7 +306,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) th[ri][t] = Fm::make(w[ri]);
   }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
+  if constexpr (!DIRECT) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
   V4* Yp = sY + pw * NP * YT;
@@ -304,26 +329,50 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 #pragma unroll
         for (int t = 0; t < KBN; ++t) {
           Op a;
+          if constexpr (DIRECT)
+            a = an[q][t];
+          else
 #pragma unroll
-          for (int part = 0; part < NP; ++part) a.p[part] = Ls[part * SV + (tp * KBN + t) * 64 + lane];
+            for (int part = 0; part < NP; ++part) a.p[part] = Ls[part * SV + (tp * KBN + t) * 64 + lane];
 #pragma unroll
           for (int ct = 0; ct < NTC; ++ct) y1[q][ct] = Fm::mma(a, bT[ct][t], y1[q][ct]);
         }
     }
+    if (DIRECT && gam < G) load_ops(gam + 1);
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
     if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
     V4* Yb = Yp;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
-      if (tp < KT)
+      if (tp < KT) {
+        if constexpr (!Fm::F32 && NTC == 2) {
+          // lanes of rows g and g ^ 1 (16 apart) trade tiles: row 2h keeps tile 0 and takes
+          // its row 2h + 1 partner's tile 0 (the next 4-row group of the same column); row
+          // 2h + 1 takes row 2h's tile 1; each lane then stores one whole BF16 operand, the
+          // 4-row groups 4 tp + 2h and 4 tp + 2h + 1 of column 16 (g & 1) + c
+          const fx4 v0 = y1[q][0], v1 = y1[q][1];
+          const typename Fm::Op4 a = Fm::make4(v0[0], v0[1], v0[2], v0[3]);
+          const typename Fm::Op4 b = Fm::make4(v1[0], v1[1], v1[2], v1[3]);
+          V* Yv = reinterpret_cast<V*>(Yb);
 #pragma unroll
-        for (int ct = 0; ct < NTC; ++ct) {
-          const fx4 v = y1[q][ct];
-          const typename Fm::Op4 yv = Fm::make4(v[0], v[1], v[2], v[3]);
+          for (int part = 0; part < NP; ++part) {
+            const uint2 x = __builtin_bit_cast(uint2, a.p[part]), y = __builtin_bit_cast(uint2, b.p[part]);
+            const auto s0 = __builtin_amdgcn_permlane16_swap(x.x, y.x, false, false);
+            const auto s1 = __builtin_amdgcn_permlane16_swap(x.y, y.y, false, false);
+            const uint4 w = {s0[0], s1[0], s0[1], s1[1]};
+            Yv[part * (YT / 2) + (2 * tp + (g >> 1)) * NT + 16 * (g & 1) + c] = __builtin_bit_cast(V, w);
+          }
+        } else {
 #pragma unroll
-          for (int part = 0; part < NP; ++part) Yb[part * YT + yidx(4 * tp + g, 16 * ct + c)] = yv.p[part];
+          for (int ct = 0; ct < NTC; ++ct) {
+            const fx4 v = y1[q][ct];
+            const typename Fm::Op4 yv = Fm::make4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int part = 0; part < NP; ++part) Yb[part * YT + yidx(4 * tp + g, 16 * ct + c)] = yv.p[part];
+          }
         }
+      }
     }
     __syncthreads();
     // single buffers: every stage-1 read of this slab is done, the next one can load
@@ -404,7 +453,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
       d[0] = d_re;
       d[NWV * 16] = d_im;
     }
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
+    if constexpr (!DIRECT) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of the next slab landed
     __syncthreads();
     // this lane's share of tr(f f) for the vector: its eight FP32 products of
     // FP32 entries summed in FP32, the sum over lanes and vectors in FP64
@@ -505,7 +554,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
 size_t lds_bytes_s(int KT, int NTC, int NCP, int FM, int BCP) {
   const int MT = 16 * KT, NT = 16 * NTC, NWV = NCP;
   const int KB = FM == FM_FP32 ? 16 : 32, MTP = (MT + KB - 1) / KB * KB;
-  size_t b = (size_t)(BCP == 1 && FM == FM_BF16 ? 2 : 4) * MT * MTP;  // slabs
+  size_t b = BCP == 1 ? 0 : (size_t)4 * MT * MTP;  // slabs (none with one path per workgroup)
   b += (size_t)BCP * (MTP / 4) * NT * (FM == FM_FP32 ? 16 : FM == FM_BF16X3 ? 16 : 8);  // Y^T tiles
   b += (size_t)BCP * NT * (16 * NCP + 4) * 2 * 4;     // packed f (FP32)
   b += (size_t)BCP * BFL * NWV * 16 * 2 * 4;          // staged diagonals (FP32)
