@@ -16,105 +16,141 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // V build: with c = xi - xbar, R = sum_g Re(c_g) L_g and Q = sum_g Im(c_g) L_g,
-// V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the FP64
-// matrix cores: each wavefront takes VB_WT tiles of 16 walkers (both Re c and
-// Im c as A operands) and VB_ET tiles of 16 matrix entries, so every L entry it
-// loads feeds the products of 16 VB_WT walkers; L is read once per 16 VB_WT
-// walkers, and the four wavefronts of a workgroup share their L entries.  Row w of
-// xi starts at w * xs and of xbar at w * xbs; xbar may be null (c = xi): the
-// trial slices use this with the generators A_k and their block of y, the
-// back-propagation with a walker's recorded fields.  XB = false (no xbar):
-// Q = 0 and only the R products run.
-// With T = float (mixed-precision contexts with real trials) the products run
-// on v_mfma_f32_16x16x4f32: c and L rounded to FP32, FP32 accumulation over g.
-constexpr int VB_WT = 2;  // walker tiles per wavefront
-constexpr int VB_ET = 2;  // entry tiles per wavefront
+// V = sqrt(tau) (-Q + i R).  A (walkers x G) by (G x M^2) product on the matrix
+// cores, tiled through LDS: a workgroup of four wavefronts takes VB_W = 64
+// walkers by VB_E matrix entries (64 in FP64, 128 in FP32) and walks G in
+// chunks of VB_KC vectors.  Each chunk's c (real and imaginary planes) and L
+// entries are read from global memory once per workgroup, converted to T,
+// and staged in double-buffered LDS while the previous chunk's products run;
+// wavefront (wh, eh) holds 2 walker tiles by VB_E / 32 entry tiles of R and Q
+// accumulators, so one staged c value feeds VB_E / 32 products and one L value
+// four.  Row w of xi starts at w * xs and of xbar at w * xbs; xbar may be null
+// (c = xi): the trial slices use this with the generators A_k and their block
+// of y, the back-propagation with a walker's recorded fields.  XB = false (no
+// xbar): Q = 0 and only the R products run.  With T = float (mixed-precision
+// contexts with real trials) c and L are rounded to FP32 and the products run
+// on v_mfma_f32_16x16x4f32 with FP32 accumulation over g.
+constexpr int VB_W = 64;   // walkers per workgroup
+constexpr int VB_KC = 16;  // vectors per staged chunk
+// LDS rows are padded by 16 values, so that the two k rows one 32-lane half of
+// a wavefront reads (g = 0, 1) fall on different banks
+template <typename T>
+struct VbShape {
+  static constexpr int ET = sizeof(T) == 4 ? 4 : 2;  // entry tiles per wavefront
+  static constexpr int E = 32 * ET;                   // entries per workgroup
+  static constexpr int SAW = VB_W + 16, SBE = E + 16; // padded LDS rows of c and L
+};
 template <typename T, bool XB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+size_t vb_lds_bytes() {
+  typedef VbShape<T> S;
+  return (size_t)2 * VB_KC * ((XB ? 2 : 1) * S::SAW + S::SBE) * sizeof(T);
+}
+template <typename T, bool XB>
+__global__ void __launch_bounds__(256)
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
   typedef ::MM<T> mm;  // (the parameter MM is the number of matrix entries)
   typedef typename mm::acc_t acc_t;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int ET = VbShape<T>::ET, E = VbShape<T>::E, SAW = VbShape<T>::SAW, SBE = VbShape<T>::SBE;
+  constexpr int NA = XB ? 2 : 1;                    // c planes (re, im)
+  constexpr int CA = NA * VB_KC * SAW;              // staged c values per chunk
+  constexpr int CH = CA + VB_KC * SBE;              // staged values per chunk
+  extern __shared__ double smem[];
+  T* sbuf = reinterpret_cast<T*>(smem);             // [2][ c: [NA][VB_KC][SAW], L: [VB_KC][SBE] ]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c = lane & 15;
-  const int w0 = (blockIdx.y * 4 + wave) * 16 * VB_WT;
-  const int e0 = blockIdx.x * 16 * VB_ET;
-  if (w0 >= nw) return;
-  acc_t ar[VB_WT][VB_ET], ai[VB_WT][VB_ET];
+  const int wh = wave >> 1, eh = wave & 1;          // walker half, entry half
+  const int wb = blockIdx.y * VB_W, eb = blockIdx.x * E;
+  // global -> register staging: thread (j, w) takes walker w's AV consecutive
+  // vectors AV j .. AV j + AV - 1 of the chunk (consecutive lanes on consecutive
+  // walkers, so the LDS stores are conflict-free), and BV L entries, e fastest
+  constexpr int AV = VB_KC * VB_W / 256;            // (walker, k) pairs per thread
+  constexpr int BV = VB_KC * E / 256;               // L entries per thread
+  static_assert(VB_KC * VB_W % 256 == 0 && VB_KC * E % 256 == 0, "whole chunks per thread");
+  const int wl = tid % VB_W, kj = AV * (tid / VB_W);
+  T ra[NA][AV], rb[BV];
+  auto gload = [&](int k0) {
 #pragma unroll
-  for (int wt = 0; wt < VB_WT; ++wt)
-#pragma unroll
-    for (int et = 0; et < VB_ET; ++et) ar[wt][et] = ai[wt][et] = mm::zero();
-  int wa[VB_WT];
-  bool wok[VB_WT];
-#pragma unroll
-  for (int wt = 0; wt < VB_WT; ++wt) {
-    wa[wt] = min(w0 + 16 * wt + c, nw - 1);
-    wok[wt] = (w0 + 16 * wt + c) < nw;
-  }
-  int ec[VB_ET];
-  bool eok[VB_ET];
-#pragma unroll
-  for (int et = 0; et < VB_ET; ++et) {
-    const int e = e0 + 16 * et + c;
-    eok[et] = e < MM;
-    ec[et] = min(e, MM - 1);
-  }
-  // batches of KB k-steps, double-buffered: the loads of batch i+1 (clamped
-  // in range, masked after the load) are issued before the MFMAs of batch i
-  constexpr int KB = 4;
-  T cr[2][KB][VB_WT], ci[2][KB][VB_WT], b[2][KB][VB_ET];
-  auto load = [&](int k0, int buf) {
-#pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      const int k = k0 + 4 * q + g;
-      const int kc = min(k, G - 1);
-#pragma unroll
-      for (int wt = 0; wt < VB_WT; ++wt) {
-        const bool ok = wok[wt] && k < G;
-        const double x = xi[(size_t)wa[wt] * xs + kc];
-        const double br = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2] : 0.0;
-        const double bi = XB ? xbar[((size_t)wa[wt] * xbs + kc) * 2 + 1] : 0.0;
-        cr[buf][q][wt] = (T)keep_if(x - br, ok);
-        ci[buf][q][wt] = (T)keep_if(-bi, ok);
-      }
-#pragma unroll
-      for (int et = 0; et < VB_ET; ++et) {
-        const double v = L[(size_t)kc * MM + ec[et]];
-        b[buf][q][et] = (T)keep_if(v, k < G && eok[et]);
+    for (int i = 0; i < AV; ++i) {
+      const int k = k0 + kj + i, w = wb + wl;
+      const bool ok = k < G && w < nw;
+      const int kc = min(k, G - 1), wc = min(w, nw - 1);
+      const double x = xi[(size_t)wc * xs + kc];
+      if constexpr (XB) {
+        const double br = xbar[((size_t)wc * xbs + kc) * 2], bi = xbar[((size_t)wc * xbs + kc) * 2 + 1];
+        ra[0][i] = (T)keep_if(x - br, ok);
+        ra[1][i] = (T)keep_if(-bi, ok);
+      } else {
+        ra[0][i] = (T)keep_if(x, ok);
       }
     }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      const int q = tid + 256 * i, k = k0 + q / E, e = eb + q % E;
+      const bool ok = k < G && e < MM;
+      rb[i] = (T)keep_if(L[(size_t)min(k, G - 1) * MM + min(e, MM - 1)], ok);
+    }
   };
-  auto compute = [&](int buf) {
+  auto sstore = [&](int buf) {
+    T* sa = sbuf + buf * CH;
+    T* sb = sa + CA;
 #pragma unroll
-    for (int q = 0; q < KB; ++q)
+    for (int i = 0; i < AV; ++i)
 #pragma unroll
-      for (int wt = 0; wt < VB_WT; ++wt)
+      for (int p = 0; p < NA; ++p) sa[(p * VB_KC + kj + i) * SAW + wl] = ra[p][i];
 #pragma unroll
-        for (int et = 0; et < VB_ET; ++et) {
-          ar[wt][et] = mm::fma(cr[buf][q][wt], b[buf][q][et], ar[wt][et]);
-          if (XB) ai[wt][et] = mm::fma(ci[buf][q][wt], b[buf][q][et], ai[wt][et]);
-        }
+    for (int i = 0; i < BV; ++i) {
+      const int q = tid + 256 * i;
+      sb[(q / E) * SBE + q % E] = rb[i];
+    }
   };
-  load(0, 0);
-  for (int k0 = 0; k0 < G; k0 += 8 * KB) {
-    if (k0 + 4 * KB < G) load(k0 + 4 * KB, 1);
-    compute(0);
-    if (k0 + 4 * KB >= G) break;
-    if (k0 + 8 * KB < G) load(k0 + 8 * KB, 0);
-    compute(1);
+  acc_t acc[NA][2][ET];
+#pragma unroll
+  for (int p = 0; p < NA; ++p)
+#pragma unroll
+    for (int wt = 0; wt < 2; ++wt)
+#pragma unroll
+      for (int et = 0; et < ET; ++et) acc[p][wt][et] = mm::zero();
+  const int nch = (G + VB_KC - 1) / VB_KC;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) gload((ch + 1) * VB_KC);
+    const T* sa = sbuf + (ch & 1) * CH;
+    const T* sb = sa + CA;
+#pragma unroll
+    for (int ks = 0; ks < VB_KC / 4; ++ks) {
+      const int k = 4 * ks + g;
+      T a[NA][2], b[ET];
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int wt = 0; wt < 2; ++wt) a[p][wt] = sa[(p * VB_KC + k) * SAW + 32 * wh + 16 * wt + c];
+#pragma unroll
+      for (int et = 0; et < ET; ++et) b[et] = sb[k * SBE + (E / 2) * eh + 16 * et + c];
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int wt = 0; wt < 2; ++wt)
+#pragma unroll
+          for (int et = 0; et < ET; ++et) acc[p][wt][et] = mm::fma(a[p][wt], b[et], acc[p][wt][et]);
+    }
+    // the other buffer was last read in the previous chunk, before its barrier
+    if (ch + 1 < nch) sstore((ch + 1) & 1);
+    __syncthreads();
   }
 #pragma unroll
-  for (int wt = 0; wt < VB_WT; ++wt)
+  for (int wt = 0; wt < 2; ++wt)
 #pragma unroll
-    for (int et = 0; et < VB_ET; ++et)
+    for (int et = 0; et < ET; ++et)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int w = w0 + 16 * wt + mm::row(g, r), e = e0 + 16 * et + c;
+        const int w = wb + 32 * wh + 16 * wt + mm::row(g, r), e = eb + (E / 2) * eh + 16 * et + c;
         if (w < nw && e < MM) {
-          double* o = vmat + ((size_t)w * MM + e) * 2;
-          o[0] = -sqrt_tau * (double)ai[wt][et][r];
-          o[1] = sqrt_tau * (double)ar[wt][et][r];
+          const double re = -sqrt_tau * (XB ? (double)acc[NA - 1][wt][et][r] : 0.0);
+          const double im = sqrt_tau * (double)acc[0][wt][et][r];
+          *reinterpret_cast<double2*>(vmat + ((size_t)w * MM + e) * 2) = double2{re, im};
         }
       }
 }
@@ -311,6 +347,20 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
 // reduced-precision walker propagation: mixed-precision contexts with real trials
 bool prop_f32(const afqmc_ctx_s* c) { return c->precision != AFQMC_PREC_FP64 && !c->ctrial; }
 
+template <typename T, bool XB>
+hipError_t vb_launch(const afqmc_ctx_s* c, int n, int G, int MM, int xs, int xbs, double sqrt_s,
+                     const double* L, const double* xi, const double* xbar, double* vmat) {
+  const size_t lds = vb_lds_bytes<T, XB>();
+  auto kern = k_vbuild<T, XB>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((MM + VbShape<T>::E - 1) / VbShape<T>::E, (n + VB_W - 1) / VB_W);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lds, c->stream, n, G, MM, xs, xbs, sqrt_s, L, xi, xbar,
+                     vmat);
+  return hipGetLastError();
+}
+
 template <int MT>
 hipError_t launch_taylor_mt(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
   if (prop_f32(c))
@@ -328,15 +378,11 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
                          double* vmat) {
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (nw + 64 * VB_WT - 1) / (64 * VB_WT)),
-      block(256);
   if (prop_f32(c))
-    hipLaunchKernelGGL((k_vbuild<float, true>), grid, block, 0, c->stream, nw, c->G, MM, c->G,
-                       c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
-  else
-    hipLaunchKernelGGL((k_vbuild<double, true>), grid, block, 0, c->stream, nw, c->G, MM, c->G,
-                       c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar, vmat);
-  return hipGetLastError();
+    return vb_launch<float, true>(c, nw, c->G, MM, c->G, c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar,
+                                  vmat);
+  return vb_launch<double, true>(c, nw, c->G, MM, c->G, c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar,
+                                 vmat);
 }
 
 hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
@@ -579,12 +625,7 @@ hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double 
                              const double* xbar, int xbs) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  dim3 grid((MM + 16 * VB_ET - 1) / (16 * VB_ET), (n + 64 * VB_WT - 1) / (64 * VB_WT));
   if (xbar != nullptr)
-    hipLaunchKernelGGL((k_vbuild<double, true>), grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs,
-                       sqrt_s, Lgen, y, xbar, vmat);
-  else
-    hipLaunchKernelGGL((k_vbuild<double, false>), grid, dim3(256), 0, c->stream, n, G, MM, xs, xbs,
-                       sqrt_s, Lgen, y, xbar, vmat);
-  return hipGetLastError();
+    return vb_launch<double, true>(c, n, G, MM, xs, xbs, sqrt_s, Lgen, y, xbar, vmat);
+  return vb_launch<double, false>(c, n, G, MM, xs, xbs, sqrt_s, Lgen, y, xbar, vmat);
 }
