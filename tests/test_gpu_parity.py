@@ -67,6 +67,9 @@ CASES = {
     "gauss-M72-N20-ragged": (lambda: ai.small_gaussian(M=72, N=20, n_chol=40, K=16, seed=7), 3, 3),
     "gauss-M96-N24": (lambda: ai.small_gaussian(M=96, N=24, n_chol=48, K=32, seed=8), 4, 2),
     "gauss-M128-N32": (lambda: ai.small_gaussian(M=128, N=32, n_chol=32, K=32, seed=9), 2, 2),
+    # five row tiles (a padded 32-wide k block in BF16) by four packed column tiles
+    # with ragged columns: the reduced-precision contraction's one-path form
+    "gauss-M80-N27-ragged": (lambda: ai.small_gaussian(M=80, N=27, n_chol=20, K=12, seed=19), 3, 3),
     # past M = 128 and N = 32 (the uneven batches' largest systems): nine and ten
     # row tiles, three column tiles, ragged
     "gauss-M136-N34": (lambda: ai.small_gaussian(M=136, N=34, n_chol=24, K=40, seed=16), 2, 2),
@@ -678,7 +681,7 @@ def test_mixed_precision_trial_and_propagation(case):
 @pytest.mark.parametrize("case", ["tiny-ising-M8", "gauss-M3-N1", "gauss-M20-N5-ragged",
                                   "gauss-M32-N32", "gauss-M48-N11", "cfg-M64-N16-G256",
                                   "gauss-M70-N1", "gauss-M72-N20-ragged", "gauss-M96-N24",
-                                  "gauss-M128-N32"])
+                                  "gauss-M128-N32", "gauss-M80-N27-ragged"])
 def test_mixed_precision_contraction(case, prec):
     """FP32, split-BF16 and BF16 matrix-core contractions (FP64 traces and
     sums) against the FP64 oracle: per-path vb and E_p, per-walker force bias
