@@ -174,6 +174,7 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
                                const double* src, int src_ws, double* dst);
 // vmat[w] = i sqrt_s sum_k (y[w * xs + k] - xbar[w * xbs + k]) Lgen_k  (k < G;
 // xbar complex, may be null)
+hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U);
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
                              const double* Lgen, const double* y, double* vmat,
                              const double* xbar = nullptr, int xbs = 0);

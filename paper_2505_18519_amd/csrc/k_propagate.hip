@@ -29,7 +29,9 @@ namespace {
 // of y, the back-propagation with a walker's recorded fields.  XB = false (no
 // xbar): Q = 0 and only the R products run.  With T = float (mixed-precision
 // contexts with real trials) c and L are rounded to FP32 and the products run
-// on v_mfma_f32_16x16x4f32 with FP32 accumulation over g.
+// on v_mfma_f32_16x16x4f32 with FP32 accumulation over g.  RO (real output,
+// with XB = false): the trial generators' U[s] = c sum_k y[s][k] A_k, stored
+// as one real FP64 entry per (row, entry), scaled by sqrt_tau = c.
 constexpr int VB_W = 64;   // walkers per workgroup
 constexpr int VB_KC = 16;  // vectors per staged chunk
 // LDS rows are padded by 16 values, so that the two k rows one 32-lane half of
@@ -45,7 +47,7 @@ size_t vb_lds_bytes() {
   typedef VbShape<T> S;
   return (size_t)2 * VB_KC * ((XB ? 2 : 1) * S::SAW + S::SBE) * sizeof(T);
 }
-template <typename T, bool XB>
+template <typename T, bool XB, bool RO = false>
 __global__ void __launch_bounds__(256)
 k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* __restrict__ L,
          const double* __restrict__ xi, const double* __restrict__ xbar, double* __restrict__ vmat) {
@@ -147,7 +149,9 @@ k_vbuild(int nw, int G, int MM, int xs, int xbs, double sqrt_tau, const double* 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int w = wb + 32 * wh + 16 * wt + mm::row(g, r), e = eb + (E / 2) * eh + 16 * et + c;
-        if (w < nw && e < MM) {
+        if (RO) {
+          if (w < nw && e < MM) vmat[(size_t)w * MM + e] = sqrt_tau * (double)acc[0][wt][et][r];
+        } else if (w < nw && e < MM) {
           const double re = -sqrt_tau * (XB ? (double)acc[NA - 1][wt][et][r] : 0.0);
           const double im = sqrt_tau * (double)acc[0][wt][et][r];
           *reinterpret_cast<double2*>(vmat + ((size_t)w * MM + e) * 2) = double2{re, im};
@@ -347,11 +351,12 @@ k_weight(int nw, int P, int G, double dtau, double e_shift, int weight_mode,
 // reduced-precision walker propagation: mixed-precision contexts with real trials
 bool prop_f32(const afqmc_ctx_s* c) { return c->precision != AFQMC_PREC_FP64 && !c->ctrial; }
 
-template <typename T, bool XB>
+template <typename T, bool XB, bool RO = false>
 hipError_t vb_launch(const afqmc_ctx_s* c, int n, int G, int MM, int xs, int xbs, double sqrt_s,
                      const double* L, const double* xi, const double* xbar, double* vmat) {
   const size_t lds = vb_lds_bytes<T, XB>();
-  auto kern = k_vbuild<T, XB>;
+  static_assert(!RO || !XB, "real output: no xbar");
+  auto kern = k_vbuild<T, XB, RO>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -618,6 +623,18 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
   if (prop_f32(c))
     return taylor_g_dispatch<float>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
   return taylor_g_dispatch<double>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
+}
+
+// U[s] = c sum_k y[s][k] A_k for n rows of y (the trial generators' product, Sec. II.C
+// Eq. trial_decomp): FP32 products in mixed-precision contexts, whose trial series
+// rounds U to FP32 anyway, FP64 otherwise
+hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U) {
+  if (n <= 0) return hipSuccess;
+  const int MM = c->M * c->M;
+  if (c->precision != AFQMC_PREC_FP64)
+    return vb_launch<float, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr,
+                                         U);
+  return vb_launch<double, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr, U);
 }
 
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,

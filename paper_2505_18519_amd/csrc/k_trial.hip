@@ -3,8 +3,9 @@
 //
 // k_trial_diag: generators that are all diagonal (the Ising pair operators)
 //   give a diagonal U, and exp(U) Phi_0 is a row scaling of Phi_0.
-// k_ubuild: U_s = c sum_k y_{s,k} A_k for every path s, one product
-//   (paths x K) by (K x M^2) with the generators streamed once per 16 paths.
+// U_s = c sum_k y_{s,k} A_k for every path s: one product (paths x K) by
+//   (K x M^2) on the LDS-tiled kernel of the V build (launch_ubuild), with FP32
+//   products in mixed-precision contexts (their series rounds U to FP32).
 // k_trial_taylor: one wavefront per path holds its U in registers as MFMA A
 //   operands and runs the Taylor series sum_j U^j Phi_0 / j!.  With the k
 //   index of the product visited as 16 t + 4 r + g, the accumulator of one
@@ -27,87 +28,6 @@ namespace {
 
 constexpr int TB_WAVES = 4;
 constexpr int MAX_TERMS = 128;
-
-// U[s][e] = c sum_k y[s][k] A[k][e]; block = 4 wavefronts x UB_PT * 16 paths, 64 entries.
-// Each wavefront keeps UB_PT path tiles x 4 entry tiles of accumulators, so every
-// generator entry it loads feeds UB_PT products and every y entry four.
-constexpr int UB_PT = 2;
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_ubuild(int S, int K, int MM, double coupling, const double* __restrict__ y,
-         const double* __restrict__ A, double* __restrict__ U) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, c = lane & 15;
-  const int s0 = (blockIdx.y * 4 + wave) * 16 * UB_PT;
-  const int e0 = blockIdx.x * 64;
-  if (s0 >= S) return;
-  dx4 acc[UB_PT][4];
-#pragma unroll
-  for (int pt = 0; pt < UB_PT; ++pt)
-#pragma unroll
-    for (int et = 0; et < 4; ++et) acc[pt][et] = dx4_zero();
-  int sa[UB_PT];
-  bool sok[UB_PT];
-#pragma unroll
-  for (int pt = 0; pt < UB_PT; ++pt) {
-    sa[pt] = min(s0 + 16 * pt + c, S - 1);
-    sok[pt] = (s0 + 16 * pt + c) < S;
-  }
-  int ec[4];
-  bool eok[4];
-#pragma unroll
-  for (int et = 0; et < 4; ++et) {
-    const int e = e0 + 16 * et + c;
-    eok[et] = e < MM;
-    ec[et] = min(e, MM - 1);
-  }
-  // batches of KB k-steps, double-buffered (loads of batch i+1 before the
-  // MFMAs of batch i), loads clamped in range and masked after the load
-  constexpr int KB = 4;
-  double a[2][KB][UB_PT], b[2][KB][4];
-  auto load = [&](int k0, int buf) {
-#pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      const int k = k0 + 4 * q + g;
-      const int kc = min(k, K - 1);
-#pragma unroll
-      for (int pt = 0; pt < UB_PT; ++pt) {
-        const double ya = y[(size_t)sa[pt] * K + kc];
-        a[buf][q][pt] = keep_if(ya, sok[pt] && k < K);
-      }
-#pragma unroll
-      for (int et = 0; et < 4; ++et) {
-        const double v = A[(size_t)kc * MM + ec[et]];
-        b[buf][q][et] = keep_if(v, k < K && eok[et]);
-      }
-    }
-  };
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < KB; ++q)
-#pragma unroll
-      for (int pt = 0; pt < UB_PT; ++pt)
-#pragma unroll
-        for (int et = 0; et < 4; ++et)
-          acc[pt][et] = mfma_f64(a[buf][q][pt], b[buf][q][et], acc[pt][et]);
-  };
-  load(0, 0);
-  for (int k0 = 0; k0 < K; k0 += 8 * KB) {
-    if (k0 + 4 * KB < K) load(k0 + 4 * KB, 1);
-    compute(0);
-    if (k0 + 4 * KB >= K) break;
-    if (k0 + 8 * KB < K) load(k0 + 8 * KB, 0);
-    compute(1);
-  }
-#pragma unroll
-  for (int pt = 0; pt < UB_PT; ++pt)
-#pragma unroll
-    for (int et = 0; et < 4; ++et)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int s = s0 + 16 * pt + g + 4 * r, e = e0 + 16 * et + c;
-        if (s < S && e < MM) U[(size_t)s * MM + e] = coupling * acc[pt][et][r];
-      }
-}
 
 // Diagonal generators (the Ising pair operators): U is diagonal, so exp(U) Phi_0
 // scales row i of Phi_0 by exp(c sum_k y_k A_k[i][i]); one thread per entry.
@@ -274,11 +194,10 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
                               double* ubuf) {
   if (n_samples <= 0) return hipSuccess;
   if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
-  const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
-  hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
-                     c->d_A, ubuf);
-  AFQMC_LAUNCH_CHECK();
+  {
+    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf);
+    if (e != hipSuccess) return e;
+  }
   switch (c->MT) {
     case 16: return launch_mt<16>(c, n_samples, ubuf, phiT);
     case 32: return launch_mt<32>(c, n_samples, ubuf, phiT);
@@ -469,11 +388,10 @@ hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const doubl
   if (n_samples <= 0) return hipSuccess;
   if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
   if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
-  const int MM = c->M * c->M;
-  dim3 grid((MM + 63) / 64, (n_samples + 64 * UB_PT - 1) / (64 * UB_PT));
-  hipLaunchKernelGGL(k_ubuild, grid, dim3(256), 0, c->stream, n_samples, c->K, MM, c->coupling, y,
-                     c->d_A, ubuf);
-  AFQMC_LAUNCH_CHECK();
+  {
+    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf);
+    if (e != hipSuccess) return e;
+  }
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
 #define AFQMC_T(KM, NC) \
   if (KT <= KM && NTC == NC) return launch_tg<KM, NC>(c, n_samples, ubuf, phiT);
