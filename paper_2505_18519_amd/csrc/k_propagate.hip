@@ -626,14 +626,10 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
 }
 
 // U[s] = c sum_k y[s][k] A_k for n rows of y (the trial generators' product, Sec. II.C
-// Eq. trial_decomp): FP32 products in mixed-precision contexts, whose trial series
-// rounds U to FP32 anyway, FP64 otherwise
+// Eq. trial_decomp), FP64 products in every context
 hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
-  if (c->precision != AFQMC_PREC_FP64)
-    return vb_launch<float, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr,
-                                         U);
   return vb_launch<double, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr, U);
 }
 

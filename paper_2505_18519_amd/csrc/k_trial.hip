@@ -3,9 +3,8 @@
 //
 // k_trial_diag: generators that are all diagonal (the Ising pair operators)
 //   give a diagonal U, and exp(U) Phi_0 is a row scaling of Phi_0.
-// U_s = c sum_k y_{s,k} A_k for every path s: one product (paths x K) by
-//   (K x M^2) on the LDS-tiled kernel of the V build (launch_ubuild), with FP32
-//   products in mixed-precision contexts (their series rounds U to FP32).
+// U_s = c sum_k y_{s,k} A_k for every path s: one FP64 product (paths x K) by
+//   (K x M^2) on the LDS-tiled kernel of the V build (launch_ubuild).
 // k_trial_taylor: one wavefront per path holds its U in registers as MFMA A
 //   operands and runs the Taylor series sum_j U^j Phi_0 / j!.  With the k
 //   index of the product visited as 16 t + 4 r + g, the accumulator of one
