@@ -17,7 +17,8 @@
 // (three products; the dropped a_lo b_lo is below 2^-16 relative), which
 // brings the contraction close to FP32 accuracy.  Plain BF16 takes a_hi b_hi.
 //
-// k_contract_sh: BCP paths per workgroup share each L slab through LDS.  Both
+// k_contract_sh: BCP paths per workgroup share each L slab through LDS (one
+// path per workgroup: each wavefront loads its own slab operands).  Both
 // spins' products f^s = Y Theta^s share the A operand Y, so their B operands
 // are packed side by side: packed column q < 2N is column q mod N of spin
 // q / N, and a path needs NCP = ceil(2N/16) 16-wide column tiles instead of
@@ -309,7 +310,7 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
   if constexpr (!DIRECT) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks of slab 0 are in LDS
   __syncthreads();
 
-  V4* Yp = sY + pw * NP * YT;
+  V4* Yb = sY + pw * NP * YT;  // the path's Y^T tile
   float* Fp = sF + (size_t)pw * 2 * NT * PW;
   float* Dp = sD + (size_t)pw * BFL * 2 * NWV * 16;
   double ex_re = 0.0, ex_im = 0.0, vb2_re = 0.0, vb2_im = 0.0, e1_re = 0.0, e1_im = 0.0;
@@ -341,7 +342,6 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     if (DIRECT && gam < G) load_ops(gam + 1);
     // buffer b ^ 1 was last read in stage 1 of the previous vector, before its barriers
     if (NB == 2 && gam < G) copy_slab(gam + 1, b ^ 1);
-    V4* Yb = Yp;
 #pragma unroll
     for (int q = 0; q < S1MAX; ++q) {
       const int tp = wv + NWV * q;
@@ -382,25 +382,23 @@ k_contract_sh(int n_samples, int M, int N, int G, const void* __restrict__ Lop,
     fx4 f[NTC][2];
 #pragma unroll
     for (int it = 0; it < NTC; ++it) f[it][0] = f[it][1] = fx4_zero();
-    {
 #pragma unroll
-      for (int t = 0; t < KBN; ++t)
+    for (int t = 0; t < KBN; ++t)
 #pragma unroll
-        for (int it = 0; it < NTC; ++it) {
-          Op a;
-          const int grp = (KB * t + KV * g) / 4;
+      for (int it = 0; it < NTC; ++it) {
+        Op a;
+        const int grp = (KB * t + KV * g) / 4;
 #pragma unroll
-          for (int part = 0; part < NP; ++part) {
-            const V4* yg = Yb + part * YT + yidx(grp, 16 * it + c);
-            if constexpr (Fm::F32)
-              a.p[part] = yg[0];
-            else
-              a.p[part] = *reinterpret_cast<const V*>(yg);  // groups grp, grp + 1: one 16-byte read
-          }
-          f[it][0] = Fm::mma(a, th[0][t], f[it][0]);
-          f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
+        for (int part = 0; part < NP; ++part) {
+          const V4* yg = Yb + part * YT + yidx(grp, 16 * it + c);
+          if constexpr (Fm::F32)
+            a.p[part] = yg[0];
+          else
+            a.p[part] = *reinterpret_cast<const V*>(yg);  // groups grp, grp + 1: one 16-byte read
         }
-    }
+        f[it][0] = Fm::mma(a, th[0][t], f[it][0]);
+        f[it][1] = Fm::mma(a, th[1][t], f[it][1]);
+      }
     // diagonal of f^sp: the lane's element in row n of its packed column
     float d_re = 0.f, d_im = 0.f;
     if constexpr (FULL) {  // tile (it, it) of spin sp: element (4g + r, c) with 4g + r == c
