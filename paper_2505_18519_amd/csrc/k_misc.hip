@@ -412,22 +412,31 @@ hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Re-orthonormalisation for larger systems (M <= 160, N <= 40): modified
-// Gram-Schmidt applied twice, one workgroup of QW wavefronts (64 QW >= M) per
-// walker and spin, thread = orbital row, the columns in LDS, inner products
-// reduced across the workgroup in LDS.
+// Re-orthonormalisation for larger systems (M <= 160, N <= 40): classical
+// Gram-Schmidt applied twice (each column projected against all the previous
+// ones at once, then again), one workgroup of QW wavefronts (64 QW >= M) per
+// walker and spin, thread = orbital row, the columns in LDS.  The j inner
+// products h = Q_{<j}^H v of column j are summed by lane k of each wavefront
+// over that wavefront's 64 rows and the wavefronts' partial sums added through
+// LDS: three barriers per pass instead of one workgroup reduction per inner
+// product.  The rows in LDS are padded by one complex entry, so that the
+// threads' reads along their own rows fall on different banks.
 namespace {
 
 template <int QW>
 __global__ void __launch_bounds__(64 * QW)
 k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict__ logshift) {
   constexpr int QRG_T = 64 * QW;
-  extern __shared__ double sq[];  // [M][N] complex
+  extern __shared__ double sq[];           // [M][RS]: row m, N complex entries and a pad
+  __shared__ double s_v[QRG_T][2];         // the column being orthogonalised
+  __shared__ double s_hp[QW][64][2];       // per-wavefront partial inner products
+  __shared__ double s_h[64][2];            // h = Q_{<j}^H v
   __shared__ double s_red[QW][2];
   const int w = blockIdx.x, sp = blockIdx.y;
   const int m = threadIdx.x, wave = m >> 6, lane = m & 63;
+  const int RS = 2 * N + 2;  // LDS row stride (doubles)
   double* base = phi + ((size_t)(w * 2 + sp) * M) * N * 2;
-  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) sq[q] = base[q];
+  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) sq[(q / (2 * N)) * RS + q % (2 * N)] = base[q];
   __syncthreads();
   auto block_sum2 = [&](double& a, double& b) {
     a = wave_sum(a);
@@ -447,18 +456,53 @@ k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict
     __syncthreads();
   };
   double shift = 0.0;
-  double* row = sq + (size_t)m * N * 2;
+  double* row = sq + (size_t)m * RS;
   const bool own = m < M;
+  const int r0 = 64 * wave, r1 = min(r0 + 64, M);  // this wavefront's rows
   for (int j = 0; j < N; ++j) {
     cplx v = own ? cmk(row[2 * j], row[2 * j + 1]) : cmk(0.0, 0.0);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int k = 0; k < j; ++k) {
-        const cplx qk = own ? cmk(row[2 * k], row[2 * k + 1]) : cmk(0.0, 0.0);
-        double hr = qk.re * v.re + qk.im * v.im;
-        double hi = qk.re * v.im - qk.im * v.re;
-        block_sum2(hr, hi);
-        v = cfms(v, cmk(hr, hi), qk);
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      s_v[m][0] = v.re;
+      s_v[m][1] = v.im;
+      __syncthreads();
+      if (lane < j) {  // sum over this wavefront's rows of conj(q_mk) v_m, k = lane
+        double hr[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
+        int mm = r0;
+        for (; mm + 4 <= r1; mm += 4)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double* q = sq + (size_t)(mm + u) * RS + 2 * lane;
+            const double vr = s_v[mm + u][0], vi = s_v[mm + u][1];
+            hr[u] += q[0] * vr + q[1] * vi;
+            hi[u] += q[0] * vi - q[1] * vr;
+          }
+        for (; mm < r1; ++mm) {
+          const double* q = sq + (size_t)mm * RS + 2 * lane;
+          const double vr = s_v[mm][0], vi = s_v[mm][1];
+          hr[0] += q[0] * vr + q[1] * vi;
+          hi[0] += q[0] * vi - q[1] * vr;
+        }
+        s_hp[wave][lane][0] = (hr[0] + hr[1]) + (hr[2] + hr[3]);
+        s_hp[wave][lane][1] = (hi[0] + hi[1]) + (hi[2] + hi[3]);
       }
+      __syncthreads();
+      if (m < j) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+          if (64 * q < M) {
+            a += s_hp[q][m][0];
+            b += s_hp[q][m][1];
+          }
+        }
+        s_h[m][0] = a;
+        s_h[m][1] = b;
+      }
+      __syncthreads();
+      if (own)
+        for (int k = 0; k < j; ++k)
+          v = cfms(v, cmk(s_h[k][0], s_h[k][1]), cmk(row[2 * k], row[2 * k + 1]));
+    }
     double n2 = cabs2(v), dummy = 0.0;
     block_sum2(n2, dummy);
     const double nrm = sqrt(n2);
@@ -469,7 +513,7 @@ k_qr_g(int nw, int P, int M, int N, double* __restrict__ phi, double* __restrict
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) base[q] = sq[q];
+  for (int q = threadIdx.x; q < M * N * 2; q += QRG_T) base[q] = sq[(q / (2 * N)) * RS + q % (2 * N)];
   if (m == 0) logshift[(size_t)w * 2 + sp] = shift;
 }
 
@@ -487,7 +531,7 @@ namespace {
 
 template <int QW>
 hipError_t launch_qr_gw(const afqmc_ctx_s* c, int nw, double* phi, double* shift) {
-  const size_t lds = (size_t)c->M * c->N * 2 * sizeof(double);
+  const size_t lds = (size_t)c->M * (2 * c->N + 2) * sizeof(double);
   auto kern = k_qr_g<QW>;
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
