@@ -1103,11 +1103,13 @@ afqmc_status afqmc_population_control(afqmc_ctx c, int32_t nw, void* phi, double
                 {y, L.pc_y, S * c->K},
                 {phiT, L.pc_phiT, S * c->tsz},
                 {static_cast<double*>(logov), L.pc_logov, S * 2}};
-  for (auto& pt : parts) {
-    double* tmp = ws_ptr<double>(c, pt.off);
-    HIPCALL(c, launch_gather(c, nw, pt.row, par, pt.state, tmp), "gather");
-    HIPCALL(c, launch_copy(c, (size_t)nw * pt.row, tmp, pt.state), "gather copy");
+  GatherParts set{};
+  for (int p = 0; p < GatherParts::NPART; ++p) {
+    set.state[p] = parts[p].state;
+    set.tmp[p] = ws_ptr<double>(c, parts[p].off);
+    set.row[p] = parts[p].row;
   }
+  HIPCALL(c, launch_gather_parts(c, nw, par, set), "gather");
   return AFQMC_OK;
 }
 

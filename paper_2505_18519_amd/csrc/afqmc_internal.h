@@ -202,6 +202,16 @@ hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize
 hipError_t launch_gather(const afqmc_ctx_s* c, int nw, size_t row, const int* parent,
                          const double* src, double* dst);
 hipError_t launch_copy(const afqmc_ctx_s* c, size_t n, const double* src, double* dst);
+// the comb's walker arrays (row of row[p] doubles per walker), gathered by parent
+// into their scratch copies tmp[p] and written back, in two launches
+struct GatherParts {
+  static constexpr int NPART = 4;
+  double* state[NPART];
+  double* tmp[NPART];
+  size_t row[NPART];
+  int nchunk[NPART];  // set by the launcher
+};
+hipError_t launch_gather_parts(const afqmc_ctx_s* c, int nw, const int* parent, GatherParts set);
 
 // learned proposal network (k_mlp.hip); n = feature rows, Sp = n rounded up to 16
 hipError_t launch_mlp_setparams(const afqmc_ctx_s* c, const double* src);

@@ -96,7 +96,51 @@ __global__ void k_gather_rows(int nw, size_t row, int nchunk, const int* __restr
     dst[base_d + q] = src[base_s + q];
 }
 
+// The comb's four walker arrays in two launches: part p = blockIdx.y gathers
+// rows of set.row[p] doubles into its scratch copy (as k_gather_rows), then
+// k_copy_parts writes the scratch copies back over the arrays.
+__global__ void k_gather_parts(int nw, GatherParts set, const int* __restrict__ parent) {
+  const int p = blockIdx.y;
+  const int nchunk = set.nchunk[p];
+  const int j = blockIdx.x / nchunk, ch = blockIdx.x % nchunk;
+  if (j >= nw) return;  // the grid is sized for the widest part
+  const int pj = parent[j];
+  if (pj < 0 || pj >= nw) return;  // a parent out of range copies nothing
+  const size_t row = set.row[p];
+  const double* src = set.state[p] + (size_t)pj * row;
+  double* dst = set.tmp[p] + (size_t)j * row;
+  for (size_t q = (size_t)ch * blockDim.x + threadIdx.x; q < row; q += (size_t)nchunk * blockDim.x)
+    dst[q] = src[q];
+}
+
+__global__ void k_copy_parts(int nw, GatherParts set) {
+  const int p = blockIdx.y;
+  const size_t n = (size_t)nw * set.row[p];
+  const double* src = set.tmp[p];
+  double* dst = set.state[p];
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    dst[q] = src[q];
+}
+
 }  // namespace
+
+hipError_t launch_gather_parts(const afqmc_ctx_s* c, int nw, const int* parent, GatherParts set) {
+  if (nw <= 0) return hipSuccess;
+  int wide = 1;
+  size_t most = 0;
+  for (int p = 0; p < GatherParts::NPART; ++p) {
+    set.nchunk[p] = (int)std::max<size_t>(1, std::min<size_t>((set.row[p] + 255) / 256, 64));
+    wide = std::max(wide, set.nchunk[p]);
+    most = std::max(most, (size_t)nw * set.row[p]);
+  }
+  hipLaunchKernelGGL(k_gather_parts, dim3((unsigned)(wide * nw), GatherParts::NPART), dim3(256), 0,
+                     c->stream, nw, set, parent);
+  AFQMC_LAUNCH_CHECK();
+  const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((most + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_copy_parts, dim3(blocks, GatherParts::NPART), dim3(256), 0, c->stream, nw, set);
+  return hipGetLastError();
+}
 
 hipError_t launch_comb(const afqmc_ctx_s* c, int nw, double w_cap, int normalize, double* w,
                        double* C, double* tot, int* parent, uint64_t seed, uint64_t step) {
