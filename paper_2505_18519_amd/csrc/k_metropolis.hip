@@ -39,8 +39,10 @@ __global__ void k_proposal(int nw, int P, int K, int hidden_kind, int proposal, 
   ytry[idx] = v;
 }
 
-// accept / reject per path; one 64-lane workgroup per walker, lanes over paths
-__global__ void __launch_bounds__(64)
+// accept / reject per path; one workgroup of 256 threads per walker: the
+// lanes of wavefront 0 decide, one per path, and every thread copies the
+// accepted paths' rows over one flattened index
+__global__ void __launch_bounds__(256)
 k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __restrict__ y,
          double* __restrict__ phiT, double* __restrict__ logov, const double* __restrict__ ytry,
          const double* __restrict__ phiTtry, const double* __restrict__ ltry,
@@ -48,14 +50,16 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
          int sweep, int flip_k, const double* __restrict__ lextra, int M,
          double* __restrict__ gd_cur, const double* __restrict__ gd_try, int* __restrict__ mask) {
   __shared__ int s_acc[64];
+  __shared__ int s_list[64];  // the accepted paths of the chunk, in order
+  __shared__ int s_nacc;
   if (dstep != nullptr) step = *dstep;
   const int w = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid;  // lanes of wavefront 0 decide, one per path
   int count = 0;
   for (int p0 = 0; p0 < P; p0 += 64) {
     const int p = p0 + lane;
     int acc = 0;
-    if (p < P) {
+    if (tid < 64 && p < P) {
       const size_t wp = (size_t)w * P + p;
       const double lo = logov[wp * 2], ln = ltry[wp * 2];
       double la = ln - lo;
@@ -79,22 +83,37 @@ k_accept(int nw, int P, int K, int MN, int hidden_kind, int proposal, double* __
       }
       if (mask != nullptr) mask[wp] = acc;
     }
-    s_acc[lane] = acc;
+    if (tid < 64) s_acc[lane] = acc;
     __syncthreads();
-    // copy accepted paths (y and Phi_T) cooperatively
-    const int np = min(64, P - p0);
-    for (int q = 0; q < np; ++q) {
-      if (!s_acc[q]) continue;
-      const size_t wp = (size_t)w * P + p0 + q;
-      for (int k = lane; k < K; k += 64) y[wp * K + k] = ytry[wp * K + k];
-      for (int e = lane; e < MN; e += 64) phiT[wp * MN + e] = phiTtry[wp * MN + e];
-      if (gd_cur != nullptr)
-        for (int e = lane; e < M; e += 64) gd_cur[wp * M + e] = gd_try[wp * M + e];
-      ++count;
+    if (tid == 0) {  // compact list of the accepted paths
+      const int np = min(64, P - p0);
+      int n = 0;
+      for (int q = 0; q < np; ++q)
+        if (s_acc[q]) s_list[n++] = q;
+      s_nacc = n;
     }
     __syncthreads();
+    // copy the accepted paths' y and Phi_T (and Green's-function diagonals) with
+    // every thread of the workgroup over one flattened index
+    const int na = s_nacc;
+    count += na;
+    const size_t wp0 = (size_t)w * P + p0;
+    for (size_t e = tid; e < (size_t)na * MN; e += blockDim.x) {
+      const size_t wp = wp0 + s_list[e / MN];
+      phiT[wp * MN + e % MN] = phiTtry[wp * MN + e % MN];
+    }
+    for (size_t e = tid; e < (size_t)na * K; e += blockDim.x) {
+      const size_t wp = wp0 + s_list[e / K];
+      y[wp * K + e % K] = ytry[wp * K + e % K];
+    }
+    if (gd_cur != nullptr)
+      for (size_t e = tid; e < (size_t)na * M; e += blockDim.x) {
+        const size_t wp = wp0 + s_list[e / M];
+        gd_cur[wp * M + e % M] = gd_try[wp * M + e % M];
+      }
+    __syncthreads();
   }
-  if (lane == 0 && nacc != nullptr) nacc[w] += count;
+  if (tid == 0 && nacc != nullptr) nacc[w] += count;
 }
 
 // W <- W max(0, cos(arg sum_p S'_p - arg ref)), or the half-plane rule; a
@@ -155,7 +174,7 @@ hipError_t launch_accept(const afqmc_ctx_s* c, int nw, double* y, double* phiT, 
                          uint64_t seed, uint64_t step, int sweep, int flip_k, int proposal,
                          const double* lextra, double* gd_cur, const double* gd_try, int* mask) {
   if (nw <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_accept, dim3(nw), dim3(64), 0, c->stream, nw, c->P, c->K, c->tsz,
+  hipLaunchKernelGGL(k_accept, dim3(nw), dim3(256), 0, c->stream, nw, c->P, c->K, c->tsz,
                      c->hidden_kind, proposal, y, phiT, logov, ytry, phiTtry, ltry, nacc, seed,
                      step, c->dstep, sweep, flip_k, lextra, c->M, gd_cur, gd_try, mask);
   return hipGetLastError();
