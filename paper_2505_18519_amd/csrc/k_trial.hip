@@ -353,8 +353,216 @@ hipError_t launch_tgt(const afqmc_ctx_s* c, int n, const double* U, double* phiT
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// BF16 contexts (real trials, M <= 128, N <= 32; the split-BF16 contexts keep
+// FP32 products, whose contraction stays near FP32 accuracy): the same series
+// with split-BF16 products on v_mfma_f32_16x16x32_bf16.  One workgroup
+// per path, one wavefront per 16-row tile of U; wavefront tp keeps its rows of
+// U / s as A operands (lane (g, c): row 16 tp + c, k = 32 t + 8 g + j, as BF16
+// hi = bf16(u) and lo = bf16(u - hi)); the iterate X (MT x NT) sits in LDS
+// transposed, X^T[n][m], as hi and lo planes whose rows are padded by 16
+// bytes, so a B operand (8 consecutive m of column n) is one 16-byte read per
+// part without bank conflicts.  Each product is hi hi + hi lo + lo hi with
+// FP32 accumulation (the dropped lo lo is below 2^-16 relative); the term is
+// rounded to hi and lo once as it leaves the accumulators, the running sum is
+// kept in FP64, and the series stops when the tail bound is below 2^-20 of the
+// largest sum entry (the products themselves carry about 2^-17).  One barrier
+// per term.
+typedef short tsx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 tbfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 tbfx2 __attribute__((ext_vector_type(2)));
+typedef float tfx2 __attribute__((ext_vector_type(2)));
+// two floats -> two bfloat16 (round to nearest even), low and high halves of a word
+__device__ __forceinline__ unsigned tpk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(tfx2{a, b}, tbfx2));
+}
+__device__ __forceinline__ float tbf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float tbf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <int KTMAX, int NTC>
+__global__ void __launch_bounds__(64 * KTMAX)
+k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict__ U,
+                  const double* __restrict__ phi0, double* __restrict__ phiT) {
+  constexpr int NT = 16 * NTC;
+  constexpr int KBM = (16 * KTMAX + 31) / 32;  // k blocks of 32 at most
+  const int KB = (MT + 31) / 32;                // k blocks (the last may be padding)
+  const int XS = 32 * KB + 8;                   // LDS row of X^T (bf16 entries)
+  extern __shared__ double smem[];
+  unsigned short* sX = reinterpret_cast<unsigned short*>(smem);  // [2 buffers][2 parts][NT][XS]
+  double* sred = smem + (4 * NT * XS * 2 + 7) / 8;               // [KTMAX][2]
+  const int s = blockIdx.x;
+  const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  if (s >= n_samples) return;
+  const double* Us = U + (size_t)s * M * M;
+  auto xt = [&](int buf, int part, int n, int m) -> unsigned short* {
+    return sX + ((size_t)(buf * 2 + part) * NT + n) * XS + m;
+  };
+
+  // rows of U: ua[t][j] = U[16 tp + c][32 t + 8 g + j]
+  float ua[KBM][8];
+  double rs = 0.0;
+  const int row = 16 * tp + c;
+#pragma unroll
+  for (int t = 0; t < KBM; ++t)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = 32 * t + 8 * g + j;
+      const double u = (t < KB && row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
+      ua[t][j] = (float)u;
+      rs += fabs(u);
+    }
+  rs += __shfl_xor(rs, 16, 64);
+  rs += __shfl_xor(rs, 32, 64);
+  rs = wave_max_full(rs);
+  if (lane == 0) sred[tp * 2] = rs;
+  // both buffers zero (the padding rows past MT and columns past N stay zero),
+  // then Phi_0 into buffer 0
+  for (int q = threadIdx.x; q < 4 * NT * XS; q += blockDim.x) sX[q] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
+    const int m = q / NT, n = q % NT;
+    const float x = (float)((m < M && n < N) ? phi0[m * N + n] : 0.0);
+    const unsigned h = tpk_bf16(x, 0.f);
+    *xt(0, 0, n, m) = (unsigned short)(h & 0xffffu);
+    *xt(0, 1, n, m) = (unsigned short)(tpk_bf16(x - tbf_lo(h), 0.f) & 0xffffu);
+  }
+  double rownorm = 0.0;
+  for (int w = 0; w < MT / 16; ++w) rownorm = fmax(rownorm, sred[w * 2]);
+  int nstage = 1;
+  if (rownorm > 16.0 && rownorm < 16.0 * 4096.0) nstage = (int)ceil(rownorm / 16.0);
+  const double rn = rownorm / nstage;
+  tsx8 ah[KBM], al[KBM];  // A operands: hi and lo of U / nstage
+  {
+    const float inv = (float)(1.0 / nstage);
+#pragma unroll
+    for (int t = 0; t < KBM; ++t) {
+      unsigned hw[4], lw[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float a = ua[t][2 * q] * inv, b = ua[t][2 * q + 1] * inv;
+        hw[q] = tpk_bf16(a, b);
+        lw[q] = tpk_bf16(a - tbf_lo(hw[q]), b - tbf_hi(hw[q]));
+      }
+      ah[t] = __builtin_bit_cast(tsx8, uint4{hw[0], hw[1], hw[2], hw[3]});
+      al[t] = __builtin_bit_cast(tsx8, uint4{lw[0], lw[1], lw[2], lw[3]});
+    }
+  }
+  // running sum (rows 16 tp + 4 g + r, column 16 ct + c), FP64
+  double sm[NTC][4];
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + 4 * g + r, n = 16 * ct + c;
+      sm[ct][r] = (m < M && n < N) ? phi0[m * N + n] : 0.0;
+    }
+  // store four consecutive rows of one column (this lane's accumulator values) as hi and lo
+  auto put = [&](int buf, int ct, const float (&v)[4]) {
+    const unsigned h01 = tpk_bf16(v[0], v[1]), h23 = tpk_bf16(v[2], v[3]);
+    const unsigned l01 = tpk_bf16(v[0] - tbf_lo(h01), v[1] - tbf_hi(h01));
+    const unsigned l23 = tpk_bf16(v[2] - tbf_lo(h23), v[3] - tbf_hi(h23));
+    const int n = 16 * ct + c, m = 16 * tp + 4 * g;
+    *reinterpret_cast<uint2*>(xt(buf, 0, n, m)) = uint2{h01, h23};
+    *reinterpret_cast<uint2*>(xt(buf, 1, n, m)) = uint2{l01, l23};
+  };
+  __syncthreads();
+
+  int cur = 0;
+  for (int st = 0; st < nstage; ++st) {
+    if (st > 0) {  // the stage starts from the previous stage's sum
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = (float)sm[ct][r];
+        put(cur, ct, v);
+      }
+      __syncthreads();
+    }
+    for (int j = 1; j <= MAX_TERMS; ++j) {
+      fx4 acc[NTC];
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) acc[ct] = fx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < KBM; ++t)
+        if (t < KB)
+#pragma unroll
+          for (int ct = 0; ct < NTC; ++ct) {
+            const int n = 16 * ct + c, m = 32 * t + 8 * g;
+            const tsx8 bh = *reinterpret_cast<const tsx8*>(xt(cur, 0, n, m));
+            const tsx8 bl = *reinterpret_cast<const tsx8*>(xt(cur, 1, n, m));
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(tbfx8, ah[t]),
+                                                              __builtin_bit_cast(tbfx8, bh), acc[ct], 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(tbfx8, ah[t]),
+                                                              __builtin_bit_cast(tbfx8, bl), acc[ct], 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(tbfx8, al[t]),
+                                                              __builtin_bit_cast(tbfx8, bh), acc[ct], 0, 0, 0);
+          }
+      const float invj = (float)(1.0 / (double)j);
+      double tmax = 0.0, smax = 0.0;
+#pragma unroll
+      for (int ct = 0; ct < NTC; ++ct) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = acc[ct][r] * invj;
+          sm[ct][r] += (double)v[r];
+          tmax = fmax(tmax, fabs((double)v[r]));
+          smax = fmax(smax, fabs(sm[ct][r]));
+        }
+        put(cur ^ 1, ct, v);
+      }
+      const bool check = (j & 1) == 0;
+      if (check) {
+        tmax = wave_max_full(tmax);
+        smax = wave_max_full(smax);
+        if (lane == 0) {
+          sred[tp * 2] = tmax;
+          sred[tp * 2 + 1] = smax;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+      if (check) {
+        double tm = 0.0, sx = 0.0;
+        for (int w = 0; w < MT / 16; ++w) {
+          tm = fmax(tm, sred[w * 2]);
+          sx = fmax(sx, sred[w * 2 + 1]);
+        }
+        const double nxt = (double)(j + 2);
+        if (nxt > rn && tm * (rn / (double)(j + 1)) <= 0x1.0p-20 * sx * (1.0 - rn / nxt)) break;
+      }
+    }
+  }
+  double* out = phiT + (size_t)s * M * N;
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + 4 * g + r, n = 16 * ct + c;
+      if (m < M && n < N) out[m * N + n] = sm[ct][r];
+    }
+}
+
+template <int KTMAX, int NTC>
+hipError_t launch_tgx(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+  const int NT = 16 * NTC, XS = 32 * ((c->MT + 31) / 32) + 8;
+  const size_t lds = ((size_t)4 * NT * XS * 2 + 7) / 8 * 8 + (size_t)2 * KTMAX * sizeof(double);
+  auto kern = k_trial_taylor_x3<KTMAX, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(64 * (c->MT / 16)), lds, c->stream, n, c->M, c->N, c->MT,
+                     U, c->d_phi0, phiT);
+  return hipGetLastError();
+}
+
 template <int KTMAX, int NTC>
 hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+  if constexpr (KTMAX <= 8 && NTC <= 2) {
+    if (c->precision == AFQMC_PREC_BF16) return launch_tgx<KTMAX, NTC>(c, n, U, phiT);
+  }
   return c->precision != AFQMC_PREC_FP64 ? launch_tgt<float, KTMAX, NTC>(c, n, U, phiT)
                                          : launch_tgt<double, KTMAX, NTC>(c, n, U, phiT);
 }

@@ -441,8 +441,9 @@ def test_full_size_sampled_walkers(name):
     pick = np.array([0, 1, nw // 3, nw - 1])
     phiT_o = O.trial_det(s, y[pick])
     e_tr = rel(host(dphiT)[pick], phiT_o)
-    # mixed-precision contexts build the trial and propagate with FP32 products:
-    # the later checks start from the GPU's own trial determinants, against
+    # mixed-precision contexts build the trial with FP32 (BF16 contexts: split-
+    # BF16) products and propagate with FP32 products: the later checks start
+    # from the GPU's own trial determinants, against
     # which the FP64 LU, log-det and Theta still hold to the FP64 bound
     phiT_g = host(dphiT)[pick]
     eloc, xbar, ep, vb, ell = O.local_energy(s, phi[pick], phiT_g, run.dtau)
@@ -462,7 +463,8 @@ def test_full_size_sampled_walkers(name):
     if prec == 0:
         assert e_tr <= TOL and e_phi <= TOL and e_w <= TOL
     else:
-        assert e_tr <= MIXED_TRIAL_TOL and e_phi <= MIXED_PROP_TOL and e_w <= MIXED_TOL
+        trial_tol = BF16_TRIAL_TOL if prec == 2 else MIXED_TRIAL_TOL
+        assert e_tr <= trial_tol and e_phi <= MIXED_PROP_TOL and e_w <= MIXED_TOL
 
 
 def test_population_control_matches_oracle_comb():
@@ -675,6 +677,32 @@ def test_mixed_precision_trial_and_propagation(case):
     _say(f"  errors vs FP64 oracle: Phi_T {e_tr:.2e}  phi' {e_phi:.2e}  W {e_w:.2e}")
     assert e_tr <= MIXED_TRIAL_TOL and e_phi <= MIXED_PROP_TOL and e_w <= MIXED_TOL
     assert max(e_tr, e_phi) > 1e-12     # the FP32 products are really in use
+
+
+# BF16 contexts past M = 64 or N = 16 build the trial on split-BF16 products
+# (FP32 accumulation, the running sum in FP64)
+BF16_TRIAL_TOL = 2e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16"])
+@pytest.mark.parametrize("case", ["gauss-M32-N32", "gauss-M70-N1", "gauss-M72-N20-ragged",
+                                  "gauss-M80-N27-ragged", "gauss-M96-N24", "gauss-M128-N32"])
+def test_bf16_contexts_build_the_trial_on_split_bf16_products(case, prec):
+    """Phi_T(y) of a BF16 context within 2e-5 normwise of the
+    FP64 oracle, and further from it than FP32 products would be (so the
+    split-BF16 series is the one that ran)."""
+    _say("bf16 trial", case, prec)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    ctx = A.Context(s, P, 0.01, max_walkers=nw, precision=MIXED[prec][0])
+    rng, phi, y = state(s, P, nw, 3)
+    dphiT = torch.zeros(nw, P, s.M, s.N, dtype=torch.float64, device="cuda")
+    A.afqmc_trial_build(ctx, nw, dev(y), dphiT)
+    torch.cuda.synchronize()
+    phiT_o = O.trial_det(s, y)
+    e_tr = max(rel(host(dphiT)[w], phiT_o[w]) for w in range(nw))
+    _say(f"  Phi_T vs FP64 oracle: {e_tr:.2e}")
+    assert 5e-7 < e_tr <= BF16_TRIAL_TOL  # FP32 products stay below 3e-7 on these shapes
 
 
 @pytest.mark.parametrize("prec", list(MIXED))
