@@ -626,10 +626,15 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
 }
 
 // U[s] = c sum_k y[s][k] A_k for n rows of y (the trial generators' product, Sec. II.C
-// Eq. trial_decomp), FP64 products in every context
+// Eq. trial_decomp), stored as FP64.  FP64 products, except for BF16 contexts on the
+// workgroup-per-path kernels: their trial series rounds U to split BF16 (about 2^-17)
+// as it loads it, so U's FP32 products (about 2^-24 per term) change nothing it keeps.
 hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
+  if (c->precision == AFQMC_PREC_BF16 && !c->small)
+    return vb_launch<float, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr,
+                                         U);
   return vb_launch<double, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr, U);
 }
 
