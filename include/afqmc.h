@@ -87,8 +87,8 @@ enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1, AFQMC_PROPOSAL_LEARNED =
  * other step of the path stay FP64.  Contexts other than FP64 also build the
  * trial series and propagate the walkers with FP32 products; BF16 contexts
  * on the workgroup-per-path kernels (M > 64 or N > 16) build U on FP32 and the
- * trial series on split-bfloat16 products instead (Phi_T within about 2e-5 of
- * FP64).
+ * trial series on split-bfloat16 products, and propagate the walkers on
+ * split-bfloat16 products (Phi_T within about 2e-5, phi' about 1e-5 of FP64).
  * BF16 and BF16X3 need the real trial family (AFQMC_E_UNSUPPORTED otherwise).  The proposal network's own
  * precision is set separately (afqmc_mlp_init: FP32 or BF16). */
 enum {

@@ -95,6 +95,43 @@ struct MM<float> {
 };
 
 // ---------------------------------------------------------------------------
+// split bfloat16: x carried as hi = bf16(x) and lo = bf16(x - hi), a product as
+// hi hi + hi lo + lo hi on v_mfma_f32_16x16x32_bf16.  That product's lane
+// (g, c) supplies A[c][8 g + j] and B[8 g + j][c] (j < 8, one 16-byte operand
+// each) and holds D[4 g + r][c] in element r, the FP32 layout above.
+typedef short tsx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 tbfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 tbfx2 __attribute__((ext_vector_type(2)));
+typedef float tfx2 __attribute__((ext_vector_type(2)));
+// two floats -> two bfloat16 (round to nearest even), low and high halves of a word
+__device__ __forceinline__ unsigned tpk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(tfx2{a, b}, tbfx2));
+}
+__device__ __forceinline__ float tbf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float tbf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ fx4 mfma_bf16x32(tsx8 a, tsx8 b, fx4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(tbfx8, a),
+                                                 __builtin_bit_cast(tbfx8, b), acc, 0, 0, 0);
+}
+// eight values -> their split (hi, lo) operands
+__device__ __forceinline__ void split8(const float (&v)[8], tsx8& hi, tsx8& lo) {
+  unsigned hw[4], lw[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hw[q] = tpk_bf16(v[2 * q], v[2 * q + 1]);
+    lw[q] = tpk_bf16(v[2 * q] - tbf_lo(hw[q]), v[2 * q + 1] - tbf_hi(hw[q]));
+  }
+  hi = __builtin_bit_cast(tsx8, uint4{hw[0], hw[1], hw[2], hw[3]});
+  lo = __builtin_bit_cast(tsx8, uint4{lw[0], lw[1], lw[2], lw[3]});
+}
+// acc += a b in split form (three products)
+__device__ __forceinline__ fx4 mfma_x3(tsx8 ah, tsx8 al, tsx8 bh, tsx8 bl, fx4 acc) {
+  acc = mfma_bf16x32(ah, bh, acc);
+  acc = mfma_bf16x32(ah, bl, acc);
+  return mfma_bf16x32(al, bh, acc);
+}
+
+// ---------------------------------------------------------------------------
 // wave-wide reductions (64 lanes)
 
 __device__ __forceinline__ double wave_sum(double v) {

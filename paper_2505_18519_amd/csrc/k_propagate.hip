@@ -573,6 +573,183 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// The walker step e^{-tau h1/2} T_n(V) e^{-tau h1/2} phi for BF16 contexts on
+// the workgroup kernels (real trials, M <= 128, N <= 32) with split-BF16
+// products on v_mfma_f32_16x16x32_bf16 (FP32 accumulation within each product).
+// One workgroup per (walker, spin), one wavefront per 16-row tile.  Wavefront
+// tp keeps its rows of V_re and -V_im as split A operands (lane (g, c): row
+// 16 tp + c, k = 32 t + 8 g + j); the operands of e^{-tau h1/2} are read from
+// L2 and split at its two uses.  The iterate sits in LDS transposed, Y^T[part]
+// [n][m] with the parts Re hi, Re lo, Im hi, Im lo and rows padded by 16 bytes
+// (a B operand, 8 consecutive m of column n, is one 16-byte read), in two
+// buffers so that each Horner step takes one barrier; X = e^{-tau h1/2} phi
+// stays in registers in the accumulator layout.  The imaginary part is
+// accumulated as V_re Y_im - (-V_im) Y_re.
+template <int KTMAX, int NTC>
+__global__ void __launch_bounds__(64 * KTMAX)
+k_taylor_x3(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
+            const double* __restrict__ Eh, double* __restrict__ phi) {
+  constexpr int NT = 16 * NTC;
+  constexpr int KBM = (16 * KTMAX + 31) / 32;  // k blocks of 32 at most
+  const int KB = (MT + 31) / 32;                // k blocks (the last may be padding)
+  const int XS = 32 * KB + 8;                   // LDS row of Y^T (bf16 entries)
+  extern __shared__ double smem[];
+  unsigned short* sY = reinterpret_cast<unsigned short*>(smem);  // [2 buffers][4 parts][NT][XS]
+  const int w = blockIdx.x, sp = blockIdx.y;
+  const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int row = 16 * tp + c;
+  const double* V = vmat + (size_t)w * M * M * 2;
+  double* ph = phi + ((size_t)w * 2 + sp) * M * N * 2;
+  auto yt = [&](int buf, int part, int n, int m) -> unsigned short* {
+    return sY + ((size_t)(buf * 4 + part) * NT + n) * XS + m;
+  };
+
+  tsx8 vrh[KBM], vrl[KBM], vih[KBM], vil[KBM];  // V_re and -V_im, hi and lo
+#pragma unroll
+  for (int t = 0; t < KBM; ++t) {
+    float re[8], nim[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = 32 * t + 8 * g + j;
+      const bool ok = t < KB && row < M && col < M;
+      // clamped, unconditional loads masked afterwards: all in flight together
+      const double2 v = *reinterpret_cast<const double2*>(
+          V + ((size_t)min(row, M - 1) * M + min(col, M - 1)) * 2);
+      re[j] = (float)keep_if(v.x, ok);
+      nim[j] = (float)keep_if(-v.y, ok);
+    }
+    split8(re, vrh[t], vrl[t]);
+    split8(nim, vih[t], vil[t]);
+  }
+  // both buffers zero (rows past MT are read as padding and never written),
+  // then phi into buffer 0
+  for (int q = threadIdx.x; q < NT * XS; q += blockDim.x)
+    reinterpret_cast<uint4*>(sY)[q] = uint4{0u, 0u, 0u, 0u};
+  __syncthreads();
+  for (int q = threadIdx.x; q < MT * NT; q += blockDim.x) {
+    const int m = q / NT, n = q % NT;
+    const bool ok = m < M && n < N;
+    const double2 v = *reinterpret_cast<const double2*>(
+        ph + ((size_t)min(m, M - 1) * N + min(n, N - 1)) * 2);
+    const float re = (float)keep_if(v.x, ok), im = (float)keep_if(v.y, ok);
+    const unsigned hr = tpk_bf16(re, 0.f), hi = tpk_bf16(im, 0.f);
+    *yt(0, 0, n, m) = (unsigned short)(hr & 0xffffu);
+    *yt(0, 1, n, m) = (unsigned short)(tpk_bf16(re - tbf_lo(hr), 0.f) & 0xffffu);
+    *yt(0, 2, n, m) = (unsigned short)(hi & 0xffffu);
+    *yt(0, 3, n, m) = (unsigned short)(tpk_bf16(im - tbf_lo(hi), 0.f) & 0xffffu);
+  }
+  __syncthreads();
+  // o = e^{-tau h1/2} Y (this wavefront's rows) from buffer buf
+  auto apply_e = [&](int buf, fx4 (&o)[NTC][2]) {
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) o[ct][0] = o[ct][1] = MM<float>::zero();
+#pragma unroll
+    for (int t = 0; t < KBM; ++t)
+      if (t < KB) {
+        float e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int col = 32 * t + 8 * g + j;
+          e[j] = (float)keep_if(Eh[min(row, M - 1) * M + min(col, M - 1)], row < M && col < M);
+        }
+        tsx8 eh, el;
+        split8(e, eh, el);
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct) {
+          const int n = 16 * ct + c, m = 32 * t + 8 * g;
+          const tsx8 rh = *reinterpret_cast<const tsx8*>(yt(buf, 0, n, m));
+          const tsx8 rl = *reinterpret_cast<const tsx8*>(yt(buf, 1, n, m));
+          const tsx8 ih = *reinterpret_cast<const tsx8*>(yt(buf, 2, n, m));
+          const tsx8 il = *reinterpret_cast<const tsx8*>(yt(buf, 3, n, m));
+          o[ct][0] = mfma_x3(eh, el, rh, rl, o[ct][0]);
+          o[ct][1] = mfma_x3(eh, el, ih, il, o[ct][1]);
+        }
+      }
+  };
+  // four consecutive rows of one column (this lane's accumulator values) as hi
+  // and lo into parts (part, part + 1) of buffer buf
+  auto put = [&](int buf, int part, int ct, const fx4& v) {
+    const unsigned h01 = tpk_bf16(v[0], v[1]), h23 = tpk_bf16(v[2], v[3]);
+    const unsigned l01 = tpk_bf16(v[0] - tbf_lo(h01), v[1] - tbf_hi(h01));
+    const unsigned l23 = tpk_bf16(v[2] - tbf_lo(h23), v[3] - tbf_hi(h23));
+    const int n = 16 * ct + c, m = 16 * tp + 4 * g;
+    *reinterpret_cast<uint2*>(yt(buf, part, n, m)) = uint2{h01, h23};
+    *reinterpret_cast<uint2*>(yt(buf, part + 1, n, m)) = uint2{l01, l23};
+  };
+  fx4 x[NTC][2];
+  apply_e(0, x);
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct) {
+    put(1, 0, ct, x[ct][0]);
+    put(1, 2, ct, x[ct][1]);
+  }
+  __syncthreads();
+  int cur = 1;
+  // Horner: Y <- X + V Y / j for j = n .. 1; each step reads buffer cur and
+  // writes the other, which every wavefront finished reading before the last
+  // barrier
+  for (int j = n_taylor; j >= 1; --j) {
+    fx4 are[NTC], aim1[NTC], aim2[NTC];
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) are[ct] = aim1[ct] = aim2[ct] = MM<float>::zero();
+#pragma unroll
+    for (int t = 0; t < KBM; ++t)
+      if (t < KB)
+#pragma unroll
+        for (int ct = 0; ct < NTC; ++ct) {
+          const int n = 16 * ct + c, m = 32 * t + 8 * g;
+          const tsx8 rh = *reinterpret_cast<const tsx8*>(yt(cur, 0, n, m));
+          const tsx8 rl = *reinterpret_cast<const tsx8*>(yt(cur, 1, n, m));
+          const tsx8 ih = *reinterpret_cast<const tsx8*>(yt(cur, 2, n, m));
+          const tsx8 il = *reinterpret_cast<const tsx8*>(yt(cur, 3, n, m));
+          are[ct] = mfma_x3(vrh[t], vrl[t], rh, rl, are[ct]);
+          are[ct] = mfma_x3(vih[t], vil[t], ih, il, are[ct]);
+          aim1[ct] = mfma_x3(vrh[t], vrl[t], ih, il, aim1[ct]);
+          aim2[ct] = mfma_x3(vih[t], vil[t], rh, rl, aim2[ct]);
+        }
+    const float invj = (float)(1.0 / (double)j);
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) {
+      fx4 yr, yi;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        yr[r] = x[ct][0][r] + are[ct][r] * invj;
+        yi[r] = x[ct][1][r] + (aim1[ct][r] - aim2[ct][r]) * invj;
+      }
+      put(cur ^ 1, 0, ct, yr);
+      put(cur ^ 1, 2, ct, yi);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  fx4 o[NTC][2];
+  apply_e(cur, o);
+#pragma unroll
+  for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * tp + 4 * g + r, n = 16 * ct + c;
+      if (m < M && n < N)
+        *reinterpret_cast<double2*>(ph + ((size_t)m * N + n) * 2) =
+            double2{(double)o[ct][0][r], (double)o[ct][1][r]};
+    }
+}
+
+template <int KTMAX, int NTC>
+hipError_t launch_taylor_x3(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+  const int NT = 16 * NTC, XS = 32 * ((c->MT + 31) / 32) + 8;
+  const size_t lds = (size_t)8 * NT * XS * sizeof(unsigned short);
+  auto kern = k_taylor_x3<KTMAX, NTC>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nw, 2), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N,
+                     c->MT, c->n_taylor, vmat, c->d_Eh, phi);
+  return hipGetLastError();
+}
+
 constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename T, int KTMAX, int NTC>
@@ -620,6 +797,16 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
 }
 
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+  if (nw <= 0) return hipSuccess;
+  if (c->precision == AFQMC_PREC_BF16 && !c->ctrial) {
+    // split-BF16 products (BF16 contexts take M <= 128, N <= 32)
+    const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_X(KM, NC) \
+  if (KT <= KM && NTC == NC) return launch_taylor_x3<KM, NC>(c, nw, vmat, phi);
+    AFQMC_X(4, 1) AFQMC_X(6, 1) AFQMC_X(8, 1)
+    AFQMC_X(4, 2) AFQMC_X(6, 2) AFQMC_X(8, 2)
+#undef AFQMC_X
+  }
   if (prop_f32(c))
     return taylor_g_dispatch<float>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
   return taylor_g_dispatch<double>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);

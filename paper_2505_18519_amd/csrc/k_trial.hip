@@ -368,17 +368,6 @@ hipError_t launch_tgt(const afqmc_ctx_s* c, int n, const double* U, double* phiT
 // kept in FP64, and the series stops when the tail bound is below 2^-20 of the
 // largest sum entry (the products themselves carry about 2^-17).  One barrier
 // per term.
-typedef short tsx8 __attribute__((ext_vector_type(8)));
-typedef __bf16 tbfx8 __attribute__((ext_vector_type(8)));
-typedef __bf16 tbfx2 __attribute__((ext_vector_type(2)));
-typedef float tfx2 __attribute__((ext_vector_type(2)));
-// two floats -> two bfloat16 (round to nearest even), low and high halves of a word
-__device__ __forceinline__ unsigned tpk_bf16(float a, float b) {
-  return __builtin_bit_cast(unsigned, __builtin_convertvector(tfx2{a, b}, tbfx2));
-}
-__device__ __forceinline__ float tbf_lo(unsigned w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float tbf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
-
 template <int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict__ U,

@@ -464,7 +464,8 @@ def test_full_size_sampled_walkers(name):
         assert e_tr <= TOL and e_phi <= TOL and e_w <= TOL
     else:
         trial_tol = BF16_TRIAL_TOL if prec == 2 else MIXED_TRIAL_TOL
-        assert e_tr <= trial_tol and e_phi <= MIXED_PROP_TOL and e_w <= MIXED_TOL
+        prop_tol = BF16_PROP_TOL if prec == 2 else MIXED_PROP_TOL
+        assert e_tr <= trial_tol and e_phi <= prop_tol and e_w <= MIXED_TOL
 
 
 def test_population_control_matches_oracle_comb():
@@ -703,6 +704,43 @@ def test_bf16_contexts_build_the_trial_on_split_bf16_products(case, prec):
     e_tr = max(rel(host(dphiT)[w], phiT_o[w]) for w in range(nw))
     _say(f"  Phi_T vs FP64 oracle: {e_tr:.2e}")
     assert 5e-7 < e_tr <= BF16_TRIAL_TOL  # FP32 products stay below 3e-7 on these shapes
+
+
+# ... and propagate the walkers on split-BF16 products
+BF16_PROP_TOL = 5e-5
+
+
+@pytest.mark.parametrize("case", ["gauss-M32-N32", "gauss-M70-N1", "gauss-M72-N20-ragged",
+                                  "gauss-M80-N27-ragged", "gauss-M96-N24", "gauss-M128-N32"])
+def test_bf16_contexts_propagate_on_split_bf16_products(case):
+    """The move of a BF16 context (V build on FP32 products, T_n(V) and the
+    one-body factors on split-BF16 products) from the oracle's trial and
+    x-bar: phi' within 5e-5 normwise of the FP64 oracle and further from it
+    than FP32 products would be; the log-overlaps of the GPU's phi' to the
+    FP64 bound against the oracle's LU of the same matrices; the weights
+    within 1e-4."""
+    _say("bf16 propagation", case)
+    s, P, nw = CASES[case][0](), CASES[case][1], CASES[case][2]
+    from paper_2505_18519_amd import afqmc as A
+    dtau = 0.01
+    ctx = A.Context(s, P, dtau, max_walkers=nw, precision=A.PREC_BF16)
+    rng, phi, y = state(s, P, nw, 3)
+    phiT = O.trial_det(s, y)
+    eloc, xbar, ep, vb, ell = O.local_energy(s, phi, phiT, dtau)
+    xi = rng.normal(size=(nw, s.n_chol))
+    w0 = rng.uniform(0.5, 1.5, size=nw)
+    phin, wn, ref, elln = O.propagate(s, phi, xi, xbar, phiT, ell, w0, dtau, 10, -1.3)
+    dphi, dw = dev(phi), dev(w0)
+    dref = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+    dln = torch.zeros(nw, P, dtype=torch.complex128, device="cuda")
+    A.afqmc_propagate(ctx, nw, dphi, dev(xi), dev(xbar), dev(phiT), dev(ell), -1.3, dw, dref,
+                      dln)
+    torch.cuda.synchronize()
+    e_phi = max(rel(host(dphi)[w], phin[w]) for w in range(nw))
+    check_logov(host(dln), O.log_overlap(phiT, host(dphi)))
+    e_w = np.abs(host(dw) - wn).max() / np.abs(wn).max()
+    _say(f"  errors vs FP64 oracle: phi' {e_phi:.2e}  W {e_w:.2e}")
+    assert 4e-7 < e_phi <= BF16_PROP_TOL and e_w <= MIXED_TOL
 
 
 @pytest.mark.parametrize("prec", list(MIXED))
