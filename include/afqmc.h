@@ -86,9 +86,10 @@ enum { AFQMC_PROPOSAL_PRIOR = 0, AFQMC_PROPOSAL_RW = 1, AFQMC_PROPOSAL_LEARNED =
  * accuracy).  In every form the traces, vb_g^2, the sums over g and every
  * other step of the path stay FP64.  Contexts other than FP64 also build the
  * trial series and propagate the walkers with FP32 products; BF16 contexts
- * on the workgroup-per-path kernels (M > 64 or N > 16) build U on FP32 and the
- * trial series on split-bfloat16 products, and propagate the walkers on
- * split-bfloat16 products (Phi_T within about 2e-5, phi' about 1e-5 of FP64).
+ * on the workgroup-per-path kernels (M > 64 or N > 16) build U, the trial
+ * series, V and the walker propagation on split-bfloat16 products instead
+ * (Phi_T within about 2e-5, phi' about 1e-5 of FP64); their contexts keep
+ * split, transposed copies of L and the generators (4 G M^2 + 4 K M^2 bytes).
  * BF16 and BF16X3 need the real trial family (AFQMC_E_UNSUPPORTED otherwise).  The proposal network's own
  * precision is set separately (afqmc_mlp_init: FP32 or BF16). */
 enum {

@@ -63,7 +63,7 @@ void free_ctx(afqmc_ctx_s* c) {
   void* ptrs[] = {c->d_h1,  c->d_Lraw, c->d_Lpad,  c->d_Eh,   c->d_phi0, c->d_A,   c->d_Lpad32,
                   c->d_Lbf, c->d_Lbf_lo, c->d_F,    c->d_phi0c, m.master,  m.mom1,   m.mom2,
                   m.w1t,    m.w2t,     m.w3t,       m.w2c,      m.w3c,     m.tstep,  m.scal,
-                  c->d_Adiag};
+                  c->d_Adiag, c->d_LTx, c->d_ATx};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
 }
@@ -191,8 +191,14 @@ afqmc_status numeric_check_end(afqmc_ctx_s* c, int nw, const int* f) {
   return n_bad ? numeric_report(c, n_bad, first, h[first]) : AFQMC_OK;
 }
 
-hipError_t do_trial_build(const afqmc_ctx_s* c, int n, const double* y, double* phiT, double* ub) {
-  return c->small ? launch_trial_build(c, n, y, phiT, ub) : launch_trial_build_g(c, n, y, phiT, ub);
+// ub: the workspace's U buffer; the V buffer (idle outside the move) is the U
+// build's scratch
+hipError_t do_trial_build(afqmc_ctx_s* c, const ws_layout& L, const afqmc_ctx_s* cb, int n,
+                          const double* y, double* phiT) {
+  double* ub = ws_ptr<double>(c, L.ubuf);
+  return cb->small ? launch_trial_build(cb, n, y, phiT, ub)
+                   : launch_trial_build_g(cb, n, y, phiT, ub, ws_ptr<void>(c, L.vmat),
+                                          L.ubuf - L.vmat);
 }
 hipError_t do_overlap(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
                       double* logov, double* theta, double* gdiag = nullptr) {
@@ -452,7 +458,8 @@ afqmc_status afqmc_create(const afqmc_system* sys, int device, void* stream, afq
     const bool x3 = c->precision == AFQMC_PREC_BF16X3;
     if ((e = hipMalloc(&c->d_Lbf, n * sizeof(unsigned short))) == hipSuccess &&
         (!x3 || (e = hipMalloc(&c->d_Lbf_lo, n * sizeof(unsigned short))) == hipSuccess) &&
-        (e = launch_to_bf16(c, n, c->d_Lpad, c->d_Lbf, c->d_Lbf_lo)) == hipSuccess)
+        (e = launch_to_bf16(c, n, c->d_Lpad, c->d_Lbf, c->d_Lbf_lo)) == hipSuccess &&
+        (x3 || c->small || (e = launch_lt_split(c)) == hipSuccess))
       e = hipStreamSynchronize(c->stream);
   }
   if (e != hipSuccess) {
@@ -568,7 +575,7 @@ afqmc_status afqmc_trial_build(afqmc_ctx c, int32_t nw, const double* y, double*
   ws_layout L;
   afqmc_status st = need_ws(c, nw, &L);
   if (st != AFQMC_OK) return st;
-  HIPCALL(c, do_trial_build(c, nw * c->P, y, phiT, ws_ptr<double>(c, L.ubuf)), "trial_build");
+  HIPCALL(c, do_trial_build(c, L, c, nw * c->P, y, phiT), "trial_build");
   return AFQMC_OK;
 }
 
@@ -716,7 +723,10 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   double* vmat = ws_ptr<double>(c, L.vmat);
   double* ph;
   PHI_IN(c, nw, phi, &ph);
-  HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat), "vbuild");
+  // the trial build's U buffer is free during the move
+  HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat,
+                           ws_ptr<double>(c, L.ubuf), L.qrshift - L.ubuf),
+          "vbuild");
   HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph), "taylor");
   st = phi_out(c, nw, ph, phi);
   if (st != AFQMC_OK) return st;
@@ -778,7 +788,7 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
       if (hybrid) {  // random-walk move first (stream sweep index 2s), diagonals kept current
         HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, 2 * s, -1, AFQMC_PROPOSAL_RW),
                 "rw proposal");
-        HIPCALL(c, do_trial_build(c, n, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+        HIPCALL(c, do_trial_build(c, L, c, n, ytry, phiTtry),
                 "rw trial build");
         HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr, gdt), "rw overlap");
         if (tr) {  // denoising score matching: q(y | z(y~)) on this move's pairs
@@ -796,7 +806,7 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
       HIPCALL(c, launch_mlp_forward(c, n, Sp, gdc, y, mlF, nullptr, nullptr, nullptr),
               "mlp forward");
       HIPCALL(c, launch_mlp_propose(c, nw, mlF, y, seed, step, sl, ytry, lqf), "mlp propose");
-      HIPCALL(c, do_trial_build(c, n, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+      HIPCALL(c, do_trial_build(c, L, c, n, ytry, phiTtry),
               "proposal trial build");
       HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr, gdt), "proposal overlap");
       HIPCALL(c, launch_mlp_forward(c, n, Sp, gdt, ytry, mlR, nullptr, nullptr, nullptr),
@@ -819,7 +829,7 @@ afqmc_status afqmc_metropolis_x(afqmc_ctx c, int32_t nw, const void* phi, double
     for (int f = 0; f < nflip; ++f) {
       const int flip_k = (c->hidden_kind == AFQMC_HIDDEN_ISING) ? f : -1;
       HIPCALL(c, launch_proposal(c, nw, y, ytry, seed, step, s, flip_k, c->proposal), "proposal");
-      HIPCALL(c, do_trial_build(c, nw * c->P, ytry, phiTtry, ws_ptr<double>(c, L.ubuf)),
+      HIPCALL(c, do_trial_build(c, L, c, nw * c->P, ytry, phiTtry),
               "proposal trial build");
       HIPCALL(c, do_overlap(c, nw, ph, phiTtry, ltry, nullptr), "proposal overlap");
       HIPCALL(c,
@@ -873,7 +883,6 @@ afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32
   double* pb = ws_ptr<double>(c, L.in_pb);
   double* la = ws_ptr<double>(c, L.in_la);
   double* lb = ws_ptr<double>(c, L.in_lb);
-  double* ub = ws_ptr<double>(c, L.ubuf);
   double* ph = static_cast<double*>(phi);
   const size_t MN = (size_t)c->M * c->N;
   auto sub = [&](afqmc_status s2, const afqmc_ctx_s& from) {
@@ -882,8 +891,8 @@ afqmc_status afqmc_init_metropolis(afqmc_ctx c, int32_t nw, uint64_t seed, int32
   };
   HIPCALL(c, launch_sample_prior(&c1, nw, seed, yw, 1), "walker fields");
   HIPCALL(c, launch_sample_prior(&c1, nw, seed, yb, 2), "partner fields");
-  HIPCALL(c, do_trial_build(&c1, nw, yw, pa, ub), "walker trial build");
-  HIPCALL(c, do_trial_build(&c1, nw, yb, pb, ub), "partner trial build");
+  HIPCALL(c, do_trial_build(c, L, &c1, nw, yw, pa), "walker trial build");
+  HIPCALL(c, do_trial_build(c, L, &c1, nw, yb, pb), "partner trial build");
   for (int j = 0; j < n_pair; ++j) {
     HIPCALL(c, launch_as_walker(c, nw, pa, MN, ph), "walker from field");
     HIPCALL(c, do_overlap(&c1, nw, ph, pb, lb, nullptr), "partner overlap");

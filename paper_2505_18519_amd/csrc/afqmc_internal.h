@@ -37,6 +37,15 @@ struct afqmc_ctx_s {
   float* d_Lpad32 = nullptr;  // FP32 copy of d_Lpad: A-operand order, row-major with ctrial
   unsigned short* d_Lbf = nullptr;     // BF16 copy of d_Lpad, A-operand order (BF16 contractions)
   unsigned short* d_Lbf_lo = nullptr;  // BF16 remainder d_Lpad - d_Lbf, same order (split BF16)
+  // BF16 contexts on the workgroup kernels: L split into BF16 hi and lo and
+  // transposed for the V build, [2][M*M][GP] (vectors contiguous, GP = G rounded
+  // up to 32, zero padded)
+  unsigned short* d_LTx = nullptr;
+  int GP = 0;
+  // the same for the trial generators A_k (U build), [2][M*M][KP], unless every
+  // generator is diagonal
+  unsigned short* d_ATx = nullptr;
+  int KP = 0;
   bool small = false;         // M <= 64 and N <= 16: register-resident kernels
   bool c64 = false;           // walkers stored as complex64 (widened in the workspace)
 
@@ -122,8 +131,12 @@ hipError_t launch_contract(const afqmc_ctx_s* c, int nw, const double* phiT, con
 // kernel finds a non-finite result
 hipError_t launch_combine(const afqmc_ctx_s* c, int nw, const double* vb, const double* ep,
                           const double* logov, double* xbar, double* eloc, int* flags);
+// scratch (may be null): device memory free for the call, used by BF16 contexts
+// for their split coefficients when it holds scratch_bytes >= 8 nw GP
 hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
-                         double* vmat);
+                         double* vmat, void* scratch, size_t scratch_bytes);
+// the split, transposed copy of L (d_LTx) of a BF16 context
+hipError_t launch_lt_split(afqmc_ctx_s* c);
 hipError_t launch_taylor(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi);
 hipError_t launch_weight(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
                          const double* logov, const double* logov_new, const double* eloc,
@@ -160,8 +173,10 @@ hipError_t launch_zero_int(const afqmc_ctx_s* c, int n, int* p);
 // complex64 <-> complex128 walker copies, n complex entries
 hipError_t launch_phi_widen(const afqmc_ctx_s* c, size_t n, const float* src, double* dst);
 hipError_t launch_phi_narrow(const afqmc_ctx_s* c, size_t n, const double* src, float* dst);
+// scratch (may be null): device memory free for the call, passed to launch_ubuild
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y,
-                                double* phiT, double* ubuf);
+                                double* phiT, double* ubuf, void* scratch = nullptr,
+                                size_t scratch_bytes = 0);
 hipError_t launch_overlap_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
                             double* logov, double* theta, double* gdiag);
 hipError_t launch_contract_g(const afqmc_ctx_s* c, int nw, const double* phiT, const double* theta,
@@ -174,7 +189,10 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
                                const double* src, int src_ws, double* dst);
 // vmat[w] = i sqrt_s sum_k (y[w * xs + k] - xbar[w * xbs + k]) Lgen_k  (k < G;
 // xbar complex, may be null)
-hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U);
+// scratch (may be null): device memory free for the call (split coefficients of
+// BF16 contexts, 4 n KP bytes)
+hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U, void* scratch,
+                         size_t scratch_bytes);
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
                              const double* Lgen, const double* y, double* vmat,
                              const double* xbar = nullptr, int xbs = 0);

@@ -366,6 +366,207 @@ hipError_t vb_launch(const afqmc_ctx_s* c, int n, int G, int MM, int xs, int xbs
   return hipGetLastError();
 }
 
+// The V and U builds of BF16 contexts on the workgroup kernels, on split-BF16
+// products (v_mfma_f32_16x16x32_bf16, FP32 accumulation): their propagation
+// and trial series split V and U again as they load them.  Both operands
+// arrive split and k-contiguous, so the chunk staging is plain 16-byte copies:
+// L (or the generators A_k) from a transposed split copy [2][M*M][GP] made at
+// context creation, the coefficients from a per-call split [NA planes][2
+// parts][rows][GP] (V: xi - Re xbar and -Im xbar; U: y).  Same workgroup tile
+// as k_vbuild (64 walkers x 128 entries; wavefront (wh, eh) with 2 walker and
+// 4 entry tiles); a chunk is one k block of 32 vectors, staged in LDS as rows
+// of 40 entries (80 bytes), so that each operand (8 consecutive vectors of one
+// walker or entry) is one 16-byte read.  NA = 1 (U) stores a real output.
+constexpr int VX_KC = 32, VX_E = 128, VX_RS = VX_KC + 8;
+template <int NA>
+constexpr int vx_sb0() {  // start of the L planes in a buffer (16-bit units)
+  return NA * 2 * VB_W * VX_RS;
+}
+template <int NA>
+constexpr int vx_ch() {  // 16-bit units per buffer
+  return vx_sb0<NA>() + 2 * VX_E * VX_RS;
+}
+template <int NA>
+__global__ void __launch_bounds__(256)
+k_vbuild_bx(int nw, int GP, int MM, double sqrt_tau, const unsigned short* __restrict__ LT,
+            const unsigned short* __restrict__ cf, double* __restrict__ vmat) {
+  constexpr int VX_SB0 = vx_sb0<NA>(), VX_CH = vx_ch<NA>();
+  extern __shared__ double smem[];
+  unsigned short* sbuf = reinterpret_cast<unsigned short*>(smem);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int wh = wave >> 1, eh = wave & 1;
+  const int wb = blockIdx.y * VB_W, eb = blockIdx.x * VX_E;
+  // staging: 512 NA 16-byte pieces of c and 1024 of L per chunk; piece q of c
+  // is (plane-part q / 256, walker (q % 256) / 4, octet q % 4), piece q of L
+  // is (part q / 512, entry (q % 512) / 4, octet q % 4)
+  uint4 ra[2 * NA], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2 * NA; ++i) {
+      const int q = tid + 256 * i;
+      const int pp = q >> 8, wl = (q & 255) >> 2, ko = q & 3, w = wb + wl;
+      const uint4 v = *reinterpret_cast<const uint4*>(
+          cf + ((size_t)pp * nw + min(w, nw - 1)) * GP + k0 + 8 * ko);
+      ra[i] = w < nw ? v : uint4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      const int part = q >> 9, el = (q & 511) >> 2, ko = q & 3, e = eb + el;
+      const uint4 v = *reinterpret_cast<const uint4*>(
+          LT + ((size_t)part * MM + min(e, MM - 1)) * GP + k0 + 8 * ko);
+      rb[i] = e < MM ? v : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto sstore = [&](int buf) {
+    unsigned short* sa = sbuf + buf * VX_CH;
+    unsigned short* sb = sa + VX_SB0;
+#pragma unroll
+    for (int i = 0; i < 2 * NA; ++i) {
+      const int q = tid + 256 * i;
+      *reinterpret_cast<uint4*>(sa + ((q >> 8) * VB_W + ((q & 255) >> 2)) * VX_RS + 8 * (q & 3)) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      *reinterpret_cast<uint4*>(sb + ((q >> 9) * VX_E + ((q & 511) >> 2)) * VX_RS + 8 * (q & 3)) = rb[i];
+    }
+  };
+  fx4 acc[NA][2][4];
+#pragma unroll
+  for (int p = 0; p < NA; ++p)
+#pragma unroll
+    for (int wt = 0; wt < 2; ++wt)
+#pragma unroll
+      for (int et = 0; et < 4; ++et) acc[p][wt][et] = ::MM<float>::zero();
+  const int nch = GP / VX_KC;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) gload((ch + 1) * VX_KC);
+    const unsigned short* sa = sbuf + (ch & 1) * VX_CH;
+    const unsigned short* sb = sa + VX_SB0;
+    tsx8 ah[NA][2], al[NA][2];
+#pragma unroll
+    for (int p = 0; p < NA; ++p)
+#pragma unroll
+      for (int wt = 0; wt < 2; ++wt) {
+        const int w = 32 * wh + 16 * wt + c;
+        ah[p][wt] = *reinterpret_cast<const tsx8*>(sa + ((p * 2 + 0) * VB_W + w) * VX_RS + 8 * g);
+        al[p][wt] = *reinterpret_cast<const tsx8*>(sa + ((p * 2 + 1) * VB_W + w) * VX_RS + 8 * g);
+      }
+#pragma unroll
+    for (int et = 0; et < 4; ++et) {
+      const int e = 64 * eh + 16 * et + c;
+      const tsx8 bh = *reinterpret_cast<const tsx8*>(sb + e * VX_RS + 8 * g);
+      const tsx8 bl = *reinterpret_cast<const tsx8*>(sb + (VX_E + e) * VX_RS + 8 * g);
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int wt = 0; wt < 2; ++wt)
+          acc[p][wt][et] = mfma_x3(ah[p][wt], al[p][wt], bh, bl, acc[p][wt][et]);
+    }
+    // the other buffer was last read in the previous chunk, before its barrier
+    if (ch + 1 < nch) sstore((ch + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int wt = 0; wt < 2; ++wt)
+#pragma unroll
+    for (int et = 0; et < 4; ++et)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int w = wb + 32 * wh + 16 * wt + 4 * g + r, e = eb + 64 * eh + 16 * et + c;
+        if (w >= nw || e >= MM) continue;
+        if constexpr (NA == 1)
+          vmat[(size_t)w * MM + e] = sqrt_tau * (double)acc[0][wt][et][r];
+        else
+          *reinterpret_cast<double2*>(vmat + ((size_t)w * MM + e) * 2) =
+              double2{-sqrt_tau * (double)acc[1][wt][et][r], sqrt_tau * (double)acc[0][wt][et][r]};
+      }
+}
+
+// split coefficients: thread (w, o) takes row w's vectors 8 o .. 8 o + 7 (zero
+// past G) into cf[plane][part][w][GP]; with xbar the planes xi - Re xbar and
+// -Im xbar (the V build), without it the one plane xi (the U build's y)
+template <bool XB>
+__global__ void __launch_bounds__(256)
+k_vcoef_split(int nw, int G, int GP, const double* __restrict__ xi, const double* __restrict__ xbar,
+              unsigned short* __restrict__ cf) {
+  const int no = GP / 8;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nw * no) return;
+  const int w = q / no, o = q % no;
+  float re[8], nim[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 8 * o + j;
+    const bool ok = k < G;
+    const int kc = min(k, G - 1);
+    const double x = xi[(size_t)w * G + kc];
+    if constexpr (XB) {
+      const double2 b = *reinterpret_cast<const double2*>(xbar + ((size_t)w * G + kc) * 2);
+      re[j] = (float)keep_if(x - b.x, ok);
+      nim[j] = (float)keep_if(-b.y, ok);
+    } else {
+      re[j] = (float)keep_if(x, ok);
+    }
+  }
+  tsx8 h, l;
+  const size_t row = (size_t)w * GP + 8 * o, plane = (size_t)nw * GP;
+  split8(re, h, l);
+  *reinterpret_cast<tsx8*>(cf + row) = h;
+  *reinterpret_cast<tsx8*>(cf + plane + row) = l;
+  if constexpr (XB) {
+    split8(nim, h, l);
+    *reinterpret_cast<tsx8*>(cf + 2 * plane + row) = h;
+    *reinterpret_cast<tsx8*>(cf + 3 * plane + row) = l;
+  }
+}
+
+// coefficient split and split-BF16 product of the V (NA = 2) or U (NA = 1)
+// build; cf holds 4 NA n GP bytes
+template <int NA>
+hipError_t vbx_run(const afqmc_ctx_s* c, int n, int G, int GP, double scale,
+                   const unsigned short* LT, const double* x, const double* xbar,
+                   unsigned short* cf, double* out) {
+  const int MM = c->M * c->M;
+  const size_t nt = (size_t)n * (GP / 8);
+  hipLaunchKernelGGL(k_vcoef_split<NA == 2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                     c->stream, n, G, GP, x, xbar, cf);
+  AFQMC_LAUNCH_CHECK();
+  const size_t lds = (size_t)2 * vx_ch<NA>() * sizeof(unsigned short);
+  hipError_t e = hipFuncSetAttribute((const void*)k_vbuild_bx<NA>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((MM + VX_E - 1) / VX_E, (n + VB_W - 1) / VB_W);
+  hipLaunchKernelGGL(k_vbuild_bx<NA>, grid, dim3(256), lds, c->stream, n, GP, MM, scale, LT, cf,
+                     out);
+  return hipGetLastError();
+}
+
+// L[g][e] -> LT[part][e][g] (split, transposed, zero for g >= G); thread (e, o)
+// takes vectors 8 o .. 8 o + 7 of entry e
+__global__ void __launch_bounds__(256)
+k_lt_split(int G, int GP, int MM, const double* __restrict__ L, unsigned short* __restrict__ LT) {
+  const int no = GP / 8;
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)MM * no) return;
+  const int e = (int)(q / no), o = (int)(q % no);
+  float v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 8 * o + j;
+    v[j] = (float)keep_if(L[(size_t)min(k, G - 1) * MM + e], k < G);
+  }
+  tsx8 h, l;
+  split8(v, h, l);
+  *reinterpret_cast<tsx8*>(LT + (size_t)e * GP + 8 * o) = h;
+  *reinterpret_cast<tsx8*>(LT + ((size_t)MM + e) * GP + 8 * o) = l;
+}
+
 template <int MT>
 hipError_t launch_taylor_mt(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
   if (prop_f32(c))
@@ -379,10 +580,29 @@ hipError_t launch_taylor_mt(const afqmc_ctx_s* c, int nw, const double* vmat, do
 
 }  // namespace
 
+hipError_t launch_lt_split(afqmc_ctx_s* c) {
+  const int MM = c->M * c->M;
+  auto one = [&](int G, const double* src, unsigned short** dst, int* GP) {
+    *GP = (G + VX_KC - 1) / VX_KC * VX_KC;
+    hipError_t e = hipMalloc(dst, (size_t)2 * MM * *GP * sizeof(unsigned short));
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)MM * (*GP / 8);
+    hipLaunchKernelGGL(k_lt_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, G,
+                       *GP, MM, src, *dst);
+    return hipGetLastError();
+  };
+  hipError_t e = one(c->G, c->d_Lraw, &c->d_LTx, &c->GP);
+  if (e == hipSuccess && c->d_Adiag == nullptr) e = one(c->K, c->d_A, &c->d_ATx, &c->KP);
+  return e;
+}
+
 hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
-                         double* vmat) {
+                         double* vmat, void* scratch, size_t scratch_bytes) {
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
+  if (c->d_LTx != nullptr && scratch != nullptr && scratch_bytes >= (size_t)8 * nw * c->GP)
+    return vbx_run<2>(c, nw, c->G, c->GP, sqrt(c->dtau), c->d_LTx, xi, xbar,
+                      static_cast<unsigned short*>(scratch), vmat);
   if (prop_f32(c))
     return vb_launch<float, true>(c, nw, c->G, MM, c->G, c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar,
                                   vmat);
@@ -814,11 +1034,15 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
 
 // U[s] = c sum_k y[s][k] A_k for n rows of y (the trial generators' product, Sec. II.C
 // Eq. trial_decomp), stored as FP64.  FP64 products, except for BF16 contexts on the
-// workgroup-per-path kernels: their trial series rounds U to split BF16 (about 2^-17)
-// as it loads it, so U's FP32 products (about 2^-24 per term) change nothing it keeps.
-hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U) {
+// workgroup-per-path kernels, whose trial series rounds U to split BF16 (about 2^-17)
+// as it loads it: split-BF16 products when scratch (4 n KP bytes) is given, else FP32.
+hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U, void* scratch,
+                         size_t scratch_bytes) {
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
+  if (c->d_ATx != nullptr && scratch != nullptr && scratch_bytes >= (size_t)4 * n * c->KP)
+    return vbx_run<1>(c, n, c->K, c->KP, c->coupling, c->d_ATx, y, nullptr,
+                      static_cast<unsigned short*>(scratch), U);
   if (c->precision == AFQMC_PREC_BF16 && !c->small)
     return vb_launch<float, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr,
                                          U);

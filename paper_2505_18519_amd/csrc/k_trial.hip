@@ -194,7 +194,7 @@ hipError_t launch_trial_build(const afqmc_ctx_s* c, int n_samples, const double*
   if (n_samples <= 0) return hipSuccess;
   if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
   {
-    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf);
+    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf, nullptr, 0);
     if (e != hipSuccess) return e;
   }
   switch (c->MT) {
@@ -580,12 +580,12 @@ hipError_t launch_trial_slices(const afqmc_ctx_s* c, int n, const double* y, dou
 }
 
 hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const double* y, double* phiT,
-                                double* ubuf) {
+                                double* ubuf, void* scratch, size_t scratch_bytes) {
   if (n_samples <= 0) return hipSuccess;
   if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
   if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
   {
-    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf);
+    const hipError_t e = launch_ubuild(c, n_samples, y, ubuf, scratch, scratch_bytes);
     if (e != hipSuccess) return e;
   }
   const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
