@@ -805,10 +805,13 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
 // (a B operand, 8 consecutive m of column n, is one 16-byte read), in two
 // buffers so that each Horner step takes one barrier; X = e^{-tau h1/2} phi
 // stays in registers in the accumulator layout.  The imaginary part is
-// accumulated as V_re Y_im - (-V_im) Y_re.
+// accumulated as V_re Y_im - (-V_im) Y_re.  Workgroup b takes walker
+// 8 (b / 16) + b % 8 and spin (b / 8) % 2: the two spins of a walker are 8
+// launches apart, on the same XCD (workgroups go round-robin over the 8), so
+// the second finds V in that XCD's L2.
 template <int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
-k_taylor_x3(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
+k_taylor_x3(int nw, int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
             const double* __restrict__ Eh, double* __restrict__ phi) {
   constexpr int NT = 16 * NTC;
   constexpr int KBM = (16 * KTMAX + 31) / 32;  // k blocks of 32 at most
@@ -816,7 +819,8 @@ k_taylor_x3(int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
   const int XS = 32 * KB + 8;                   // LDS row of Y^T (bf16 entries)
   extern __shared__ double smem[];
   unsigned short* sY = reinterpret_cast<unsigned short*>(smem);  // [2 buffers][4 parts][NT][XS]
-  const int w = blockIdx.x, sp = blockIdx.y;
+  const int w = 8 * (blockIdx.x >> 4) + (blockIdx.x & 7), sp = (blockIdx.x >> 3) & 1;
+  if (w >= nw) return;  // whole workgroup, before any barrier
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const int row = 16 * tp + c;
@@ -965,8 +969,8 @@ hipError_t launch_taylor_x3(const afqmc_ctx_s* c, int nw, const double* vmat, do
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nw, 2), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N,
-                     c->MT, c->n_taylor, vmat, c->d_Eh, phi);
+  hipLaunchKernelGGL(kern, dim3(16 * ((nw + 7) / 8)), dim3(64 * (c->MT / 16)), lds, c->stream, nw,
+                     c->M, c->N, c->MT, c->n_taylor, vmat, c->d_Eh, phi);
   return hipGetLastError();
 }
 
