@@ -36,7 +36,11 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
   __shared__ double s_res[2][3];
   __shared__ double s_gd[160];  // M <= 160
 
-  const int s = blockIdx.x;
+  // workgroup b takes walker 8 (b / 8P) + b % 8 and its path (b / 8) % P: the
+  // P paths of a walker, which read the same phi, run 8 launches apart on one
+  // XCD (workgroups go round-robin over the 8) and share that XCD's L2
+  const int s = (8 * ((int)blockIdx.x / (8 * P)) + ((int)blockIdx.x & 7)) * P +
+                ((int)blockIdx.x >> 3) % P;
   const int sp = threadIdx.x >> 6;  // spin of this wavefront
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
@@ -369,12 +373,13 @@ template <int NTC>
 hipError_t launch_g(const afqmc_ctx_s* c, int nw, const double* phi, const double* phiT,
                     double* logov, double* theta, double* gdiag) {
   const int n = nw * c->P;
+  const dim3 grid(8 * c->P * ((nw + 7) / 8));  // walkers padded to 8 (see the kernel)
   if (c->ctrial) {
     if (gdiag != nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_overlap_g<NTC, true>), dim3(n), dim3(128), 0, c->stream, n, c->P, c->M,
+    hipLaunchKernelGGL((k_overlap_g<NTC, true>), grid, dim3(128), 0, c->stream, n, c->P, c->M,
                        c->N, phi, phiT, logov, theta, gdiag);
   } else {
-    hipLaunchKernelGGL((k_overlap_g<NTC, false>), dim3(n), dim3(128), 0, c->stream, n, c->P, c->M,
+    hipLaunchKernelGGL((k_overlap_g<NTC, false>), grid, dim3(128), 0, c->stream, n, c->P, c->M,
                        c->N, phi, phiT, logov, theta, gdiag);
   }
   return hipGetLastError();

@@ -646,7 +646,7 @@ namespace {
 
 template <typename T, int KTMAX, int NTC, bool XR>
 __global__ void __launch_bounds__(64 * KTMAX)
-k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restrict__ vmat,
+k_taylor_g(int n, int M, int N, int MT, int n_taylor, int spins, const double* __restrict__ vmat,
            const double* __restrict__ El, const double* __restrict__ Er,
            const double* src, int src_ws, double* dst) {
   typedef MM<T> mm;
@@ -656,7 +656,12 @@ k_taylor_g(int M, int N, int MT, int n_taylor, int spins, const double* __restri
   T* sY = reinterpret_cast<T*>(smem);  // [MT][NT][2] iterate
   T* sX = sY + MT * NT * 2;            // [MT][NT][2] X = Er src (unless XR)
   const int KT = MT / 16;
-  const int w = blockIdx.x, sp = blockIdx.y;
+  // workgroup b takes V block 8 (b / 8S) + b % 8 and its block (b / 8) % S of
+  // S = spins, so that the blocks that share V run 8 launches apart on one XCD
+  // (workgroups go round-robin over the 8) and the later ones read V from its L2
+  const int b = blockIdx.x;
+  const int w = 8 * (b / (8 * spins)) + (b & 7), sp = (b >> 3) % spins;
+  if (w >= n) return;  // whole workgroup, before any barrier
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const double* V = vmat + (size_t)w * M * M * 2;
@@ -987,8 +992,9 @@ hipError_t launch_taylor_g_kt(const afqmc_ctx_s* c, int n, int spins, int n_tayl
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n, spins), dim3(64 * (c->MT / 16)), lds, c->stream, c->M, c->N,
-                     c->MT, n_taylor, spins, vmat, El, Er, src, src_ws, dst);
+  const dim3 grid(8 * spins * ((n + 7) / 8));
+  hipLaunchKernelGGL(kern, grid, dim3(64 * (c->MT / 16)), lds, c->stream, n, c->M, c->N, c->MT,
+                     n_taylor, spins, vmat, El, Er, src, src_ws, dst);
   return hipGetLastError();
 }
 
