@@ -183,6 +183,19 @@ __device__ __forceinline__ double wave_max_full(double v) {
               fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+// the same for a float
+__device__ __forceinline__ float wave_max_full_f32(float v) {
+  v = fmaxf(v, __int_as_float(dpp_i32<0xB1>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i32<0x4E>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i32<0x141>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i32<0x140>(__float_as_int(v))));
+  const int b = __float_as_int(v);
+  return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 0)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+               fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 48))));
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 256-bit counter, 128-bit key.
 

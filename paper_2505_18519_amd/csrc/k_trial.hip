@@ -489,7 +489,10 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
                                                               __builtin_bit_cast(tbfx8, bh), acc[ct], 0, 0, 0);
           }
       const float invj = (float)(1.0 / (double)j);
-      double tmax = 0.0, smax = 0.0;
+      // the stop test (every second term) takes the maxima in FP32: the term
+      // entries are FP32 already and the test is at 2^-20
+      const bool check = (j & 1) == 0;
+      float tmax = 0.f, smax = 0.f;
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct) {
         float v[4];
@@ -497,15 +500,16 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
         for (int r = 0; r < 4; ++r) {
           v[r] = acc[ct][r] * invj;
           sm[ct][r] += (double)v[r];
-          tmax = fmax(tmax, fabs((double)v[r]));
-          smax = fmax(smax, fabs(sm[ct][r]));
+          if (check) {
+            tmax = fmaxf(tmax, fabsf(v[r]));
+            smax = fmaxf(smax, fabsf((float)sm[ct][r]));
+          }
         }
         put(cur ^ 1, ct, v);
       }
-      const bool check = (j & 1) == 0;
       if (check) {
-        tmax = wave_max_full(tmax);
-        smax = wave_max_full(smax);
+        tmax = wave_max_full_f32(tmax);
+        smax = wave_max_full_f32(smax);
         if (lane == 0) {
           sred[tp * 2] = tmax;
           sred[tp * 2 + 1] = smax;
@@ -519,8 +523,10 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
           tm = fmax(tm, sred[w * 2]);
           sx = fmax(sx, sred[w * 2 + 1]);
         }
+        // tail bound tm rn / (j + 1) against 2^-20 sx (1 - rn / nxt), both sides
+        // multiplied by (j + 1) nxt > 0
         const double nxt = (double)(j + 2);
-        if (nxt > rn && tm * (rn / (double)(j + 1)) <= 0x1.0p-20 * sx * (1.0 - rn / nxt)) break;
+        if (nxt > rn && tm * rn * nxt <= 0x1.0p-20 * sx * (nxt - rn) * (double)(j + 1)) break;
       }
     }
   }
