@@ -2,9 +2,11 @@
 // Eqs. walker_prop, importance_function, importance_function_CP; Sec. III.A,
 // Eq. ratio-update-phi for the overlap ratio; App. B step 1).
 //
-//   V = i sqrt(tau) sum_g (xi_g - xbar_g) L_g                      (k_vbuild)
+//   V = i sqrt(tau) sum_g (xi_g - xbar_g) L_g          (k_vbuild; k_vbuild_bx)
 //   phi' = e^{-tau h1/2} T_n(V) e^{-tau h1/2} phi, T_n = sum_{j<=n} V^j/j!
-//                                                                  (k_taylor)
+//                                        (k_taylor, k_taylor_g; k_taylor_x3)
+//   (the _bx and _x3 forms: split-BF16 products, for BF16 contexts on the
+//   workgroup kernels)
 //   l'_p at the unchanged paths (overlap kernel), then per walker
 //   num_r = sum_p exp(l'_p - Re l_p), r = num_r / sum_p S_p,
 //   W <- W |exp(sum_g xi_g xbar_g - xbar_g^2 / 2) r| e^{tau E_T} max(0, cos arg r)

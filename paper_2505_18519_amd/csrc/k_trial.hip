@@ -4,7 +4,8 @@
 // k_trial_diag: generators that are all diagonal (the Ising pair operators)
 //   give a diagonal U, and exp(U) Phi_0 is a row scaling of Phi_0.
 // U_s = c sum_k y_{s,k} A_k for every path s: one FP64 product (paths x K) by
-//   (K x M^2) on the LDS-tiled kernel of the V build (launch_ubuild).
+//   (K x M^2) on the LDS-tiled kernel of the V build (launch_ubuild; split-BF16
+//   products for BF16 contexts on the workgroup kernels).
 // k_trial_taylor: one wavefront per path holds its U in registers as MFMA A
 //   operands and runs the Taylor series sum_j U^j Phi_0 / j!.  With the k
 //   index of the product visited as 16 t + 4 r + g, the accumulator of one
@@ -20,6 +21,8 @@
 // with FP32 products (v_mfma_f32_16x16x4f32: U and the terms rounded to FP32,
 // FP32 accumulation within a product, the running sum kept in FP64) and stop
 // when the tail bound is below 2^-26 max|sum|, a quarter of an FP32 ulp.
+// BF16 contexts on the workgroup kernels run the series on split-BF16 products
+// instead (k_trial_taylor_x3, below) and stop at 2^-20.
 #include "afqmc_internal.h"
 #include "dev_common.h"
 
