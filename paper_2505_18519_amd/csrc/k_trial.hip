@@ -60,12 +60,13 @@ __device__ __forceinline__ constexpr double stop_ratio() {
 
 // Stop test after term j of exp(V) X with r = ||V||_inf: the tail
 // sum_{i>j} V^i X / i! has entries at most tmax * q / (1 - r / (j + 2)),
-// q = r / (j + 1), when j + 2 > r (no bound before that).
+// q = r / (j + 1), when j + 2 > r (no bound before that); tested with both
+// sides multiplied by (j + 1)(j + 2) > 0, so without divisions.
 template <typename T>
 __device__ __forceinline__ bool series_done(double tmax, double smax, double r, int j) {
   const double nxt = (double)(j + 2);
   if (!(nxt > r)) return false;
-  return tmax * (r / (double)(j + 1)) <= stop_ratio<T>() * smax * (1.0 - r / nxt);
+  return tmax * r * nxt <= stop_ratio<T>() * smax * (nxt - r) * (double)(j + 1);
 }
 
 template <typename T, int MT>
@@ -301,7 +302,10 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
             for (int ct = 0; ct < NTC; ++ct)
               acc[ct] = mm::fma(ua[t][r], Tc[(16 * t + mm::row(g, r)) * NT + 16 * ct + c], acc[ct]);
       const T invj = (T)(1.0 / (double)j);
-      double tmax = 0.0, smax = 0.0;
+      // maxima only on the terms that test, in the series' own precision (an
+      // FP32 series' terms and restarts are FP32 already)
+      const bool check = (j & 1) == 0;
+      T tmax = 0, smax = 0;
 #pragma unroll
       for (int ct = 0; ct < NTC; ++ct)
 #pragma unroll
@@ -309,13 +313,19 @@ k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__
           const T v = acc[ct][r] * invj;
           sm[ct][r] += (double)v;
           Tn[(16 * tp + mm::row(g, r)) * NT + 16 * ct + c] = v;
-          tmax = fmax(tmax, fabs((double)v));
-          smax = fmax(smax, fabs(sm[ct][r]));
+          if (check) {
+            tmax = fmax(tmax, fabs(v));
+            smax = fmax(smax, (T)fabs(sm[ct][r]));
+          }
         }
-      const bool check = (j & 1) == 0;
       if (check) {
-        tmax = wave_max_full(tmax);
-        smax = wave_max_full(smax);
+        if constexpr (sizeof(T) == 4) {
+          tmax = wave_max_full_f32(tmax);
+          smax = wave_max_full_f32(smax);
+        } else {
+          tmax = wave_max_full(tmax);
+          smax = wave_max_full(smax);
+        }
         if (lane == 0) {
           sred[tp * 2] = tmax;
           sred[tp * 2 + 1] = smax;
@@ -526,8 +536,8 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
           tm = fmax(tm, sred[w * 2]);
           sx = fmax(sx, sred[w * 2 + 1]);
         }
-        // tail bound tm rn / (j + 1) against 2^-20 sx (1 - rn / nxt), both sides
-        // multiplied by (j + 1) nxt > 0
+        // tail bound tm rn / (j + 1) against 2^-20 sx (1 - rn / nxt), as in
+        // series_done
         const double nxt = (double)(j + 2);
         if (nxt > rn && tm * rn * nxt <= 0x1.0p-20 * sx * (nxt - rn) * (double)(j + 1)) break;
       }
