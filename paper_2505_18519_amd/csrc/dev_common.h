@@ -31,6 +31,16 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
     return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
   }
 }
+// 1 / b = conj(b) / |b|^2, b first scaled by a power of two so that |b|^2
+// neither overflows nor underflows (one real division; b = 0 gives non-finite
+// parts, which the callers never use)
+__device__ __forceinline__ cplx crecip(cplx b) {
+  const double m = fmax(fabs(b.re), fabs(b.im));
+  const int e = (m > 0.0 && isfinite(m)) ? ilogb(m) : 0;
+  const double r = ldexp(b.re, -e), i = ldexp(b.im, -e);
+  const double d = 1.0 / (r * r + i * i);
+  return cplx{ldexp(r * d, -e), ldexp(-i * d, -e)};
+}
 // a - b * c
 __device__ __forceinline__ cplx cfms(cplx a, cplx b, cplx c) {
   return cplx{a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};

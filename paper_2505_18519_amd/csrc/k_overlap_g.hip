@@ -170,7 +170,7 @@ k_overlap_g(int n_samples, int P, int M, int N, const double* __restrict__ phi,
       }
       cplx l = cmk(0.0, 0.0);
       if (!used && !singular) {
-        l = cdiv(a[k], piv);
+        l = cmul(a[k], crecip(piv));  // the pivot's reciprocal: one real division
         a[k] = l;
       }
 #pragma unroll
