@@ -193,6 +193,12 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
 // BF16 contexts, 4 n KP bytes)
 hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U, void* scratch,
                          size_t scratch_bytes);
+// U split into BF16 hi and lo for the split-BF16 trial series, Us [n][2][M][MP]
+// with MP = M rounded up to 32, when ubuild_split_ok (the split generator copy
+// exists and scratch holds 4 n KP bytes)
+bool ubuild_split_ok(const afqmc_ctx_s* c, int n, size_t scratch_bytes);
+hipError_t launch_ubuild_split(const afqmc_ctx_s* c, int n, const double* y, unsigned short* Us,
+                               void* scratch);
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,
                              const double* Lgen, const double* y, double* vmat,
                              const double* xbar = nullptr, int xbs = 0);

@@ -379,6 +379,10 @@ hipError_t vb_launch(const afqmc_ctx_s* c, int n, int G, int MM, int xs, int xbs
 // 4 entry tiles); a chunk is one k block of 32 vectors, staged in LDS as rows
 // of 40 entries (80 bytes), so that each operand (8 consecutive vectors of one
 // walker or entry) is one 16-byte read.  NA = 1 (U) stores a real output.
+// The output rows (M entries) sit MP apart (MP = M, or with SPLIT, for the
+// split-BF16 trial series, M rounded up to 32: the entries past M are zero);
+// SPLIT stores U itself split, [row][hi, lo][M][MP] BF16, half the bytes of
+// FP64 and in the A-operand form the series loads.
 constexpr int VX_KC = 32, VX_E = 128, VX_RS = VX_KC + 8;
 template <int NA>
 constexpr int vx_sb0() {  // start of the L planes in a buffer (16-bit units)
@@ -388,11 +392,13 @@ template <int NA>
 constexpr int vx_ch() {  // 16-bit units per buffer
   return vx_sb0<NA>() + 2 * VX_E * VX_RS;
 }
-template <int NA>
+template <int NA, bool SPLIT>
 __global__ void __launch_bounds__(256)
-k_vbuild_bx(int nw, int GP, int MM, double sqrt_tau, const unsigned short* __restrict__ LT,
-            const unsigned short* __restrict__ cf, double* __restrict__ vmat) {
+k_vbuild_bx(int nw, int GP, int M, int MP, double sqrt_tau, const unsigned short* __restrict__ LT,
+            const unsigned short* __restrict__ cf, void* __restrict__ out) {
+  static_assert(!SPLIT || NA == 1, "split output: real U only");
   constexpr int VX_SB0 = vx_sb0<NA>(), VX_CH = vx_ch<NA>();
+  const int MM = M * M, ET = M * MP;  // entries of L (or A_k) and of an output row
   extern __shared__ double smem[];
   unsigned short* sbuf = reinterpret_cast<unsigned short*>(smem);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -403,6 +409,17 @@ k_vbuild_bx(int nw, int GP, int MM, double sqrt_tau, const unsigned short* __res
   // is (plane-part q / 256, walker (q % 256) / 4, octet q % 4), piece q of L
   // is (part q / 512, entry (q % 512) / 4, octet q % 4)
   uint4 ra[2 * NA], rb[4];
+  // this thread's L pieces: entry eb + (q % 512) / 4 of the output row, at
+  // (row, col) of the M x M matrix; none past column M
+  int lt_off[4];
+  bool lt_ok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = tid + 256 * i, e = eb + ((q & 511) >> 2);
+    const int row = e / MP, col = e - row * MP;
+    lt_ok[i] = e < ET && col < M;
+    lt_off[i] = ((q >> 9) * MM + (lt_ok[i] ? row * M + col : 0)) * GP;
+  }
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 2 * NA; ++i) {
@@ -415,10 +432,8 @@ k_vbuild_bx(int nw, int GP, int MM, double sqrt_tau, const unsigned short* __res
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = tid + 256 * i;
-      const int part = q >> 9, el = (q & 511) >> 2, ko = q & 3, e = eb + el;
-      const uint4 v = *reinterpret_cast<const uint4*>(
-          LT + ((size_t)part * MM + min(e, MM - 1)) * GP + k0 + 8 * ko);
-      rb[i] = e < MM ? v : uint4{0u, 0u, 0u, 0u};
+      const uint4 v = *reinterpret_cast<const uint4*>(LT + lt_off[i] + k0 + 8 * (q & 3));
+      rb[i] = lt_ok[i] ? v : uint4{0u, 0u, 0u, 0u};
     }
   };
   auto sstore = [&](int buf) {
@@ -481,12 +496,19 @@ k_vbuild_bx(int nw, int GP, int MM, double sqrt_tau, const unsigned short* __res
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int w = wb + 32 * wh + 16 * wt + 4 * g + r, e = eb + 64 * eh + 16 * et + c;
-        if (w >= nw || e >= MM) continue;
-        if constexpr (NA == 1)
-          vmat[(size_t)w * MM + e] = sqrt_tau * (double)acc[0][wt][et][r];
-        else
-          *reinterpret_cast<double2*>(vmat + ((size_t)w * MM + e) * 2) =
+        if (w >= nw || e >= ET) continue;
+        if constexpr (SPLIT) {
+          unsigned short* us = static_cast<unsigned short*>(out) + (size_t)w * 2 * ET + e;
+          const float u = (float)(sqrt_tau * (double)acc[0][wt][et][r]);
+          const unsigned h = tpk_bf16(u, 0.f);
+          us[0] = (unsigned short)(h & 0xffffu);
+          us[ET] = (unsigned short)(tpk_bf16(u - tbf_lo(h), 0.f) & 0xffffu);
+        } else if constexpr (NA == 1) {
+          static_cast<double*>(out)[(size_t)w * ET + e] = sqrt_tau * (double)acc[0][wt][et][r];
+        } else {
+          *reinterpret_cast<double2*>(static_cast<double*>(out) + ((size_t)w * ET + e) * 2) =
               double2{-sqrt_tau * (double)acc[1][wt][et][r], sqrt_tau * (double)acc[0][wt][et][r]};
+        }
       }
 }
 
@@ -529,23 +551,23 @@ k_vcoef_split(int nw, int G, int GP, const double* __restrict__ xi, const double
 }
 
 // coefficient split and split-BF16 product of the V (NA = 2) or U (NA = 1)
-// build; cf holds 4 NA n GP bytes
-template <int NA>
-hipError_t vbx_run(const afqmc_ctx_s* c, int n, int G, int GP, double scale,
+// build; cf holds 4 NA n GP bytes; output rows MP apart (MP = M unless SPLIT)
+template <int NA, bool SPLIT>
+hipError_t vbx_run(const afqmc_ctx_s* c, int n, int G, int GP, int MP, double scale,
                    const unsigned short* LT, const double* x, const double* xbar,
-                   unsigned short* cf, double* out) {
-  const int MM = c->M * c->M;
+                   unsigned short* cf, void* out) {
+  const int ET = c->M * MP;
   const size_t nt = (size_t)n * (GP / 8);
   hipLaunchKernelGGL(k_vcoef_split<NA == 2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
                      c->stream, n, G, GP, x, xbar, cf);
   AFQMC_LAUNCH_CHECK();
   const size_t lds = (size_t)2 * vx_ch<NA>() * sizeof(unsigned short);
-  hipError_t e = hipFuncSetAttribute((const void*)k_vbuild_bx<NA>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_vbuild_bx<NA, SPLIT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const dim3 grid((MM + VX_E - 1) / VX_E, (n + VB_W - 1) / VB_W);
-  hipLaunchKernelGGL(k_vbuild_bx<NA>, grid, dim3(256), lds, c->stream, n, GP, MM, scale, LT, cf,
-                     out);
+  const dim3 grid((ET + VX_E - 1) / VX_E, (n + VB_W - 1) / VB_W);
+  hipLaunchKernelGGL((k_vbuild_bx<NA, SPLIT>), grid, dim3(256), lds, c->stream, n, GP, c->M, MP,
+                     scale, LT, cf, out);
   return hipGetLastError();
 }
 
@@ -603,7 +625,7 @@ hipError_t launch_vbuild(const afqmc_ctx_s* c, int nw, const double* xi, const d
   if (nw <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   if (c->d_LTx != nullptr && scratch != nullptr && scratch_bytes >= (size_t)8 * nw * c->GP)
-    return vbx_run<2>(c, nw, c->G, c->GP, sqrt(c->dtau), c->d_LTx, xi, xbar,
+    return vbx_run<2, false>(c, nw, c->G, c->GP, c->M, sqrt(c->dtau), c->d_LTx, xi, xbar,
                       static_cast<unsigned short*>(scratch), vmat);
   if (prop_f32(c))
     return vb_launch<float, true>(c, nw, c->G, MM, c->G, c->G, sqrt(c->dtau), c->d_Lraw, xi, xbar,
@@ -1044,6 +1066,19 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
   return taylor_g_dispatch<double>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
 }
 
+// U split for the split-BF16 trial series of BF16 contexts: Us [n][hi, lo][M][MP]
+// BF16, MP = M rounded up to 32 (zero past column M), from split-BF16 products;
+// scratch holds 4 n KP bytes of split coefficients
+bool ubuild_split_ok(const afqmc_ctx_s* c, int n, size_t scratch_bytes) {
+  return c->d_ATx != nullptr && scratch_bytes >= (size_t)4 * n * c->KP;
+}
+hipError_t launch_ubuild_split(const afqmc_ctx_s* c, int n, const double* y, unsigned short* Us,
+                               void* scratch) {
+  if (n <= 0) return hipSuccess;
+  return vbx_run<1, true>(c, n, c->K, c->KP, (c->M + 31) / 32 * 32, c->coupling, c->d_ATx, y,
+                          nullptr, static_cast<unsigned short*>(scratch), Us);
+}
+
 // U[s] = c sum_k y[s][k] A_k for n rows of y (the trial generators' product, Sec. II.C
 // Eq. trial_decomp), stored as FP64.  FP64 products, except for BF16 contexts on the
 // workgroup-per-path kernels, whose trial series rounds U to split BF16 (about 2^-17)
@@ -1053,7 +1088,7 @@ hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U
   if (n <= 0) return hipSuccess;
   const int MM = c->M * c->M;
   if (c->d_ATx != nullptr && scratch != nullptr && scratch_bytes >= (size_t)4 * n * c->KP)
-    return vbx_run<1>(c, n, c->K, c->KP, c->coupling, c->d_ATx, y, nullptr,
+    return vbx_run<1, false>(c, n, c->K, c->KP, c->M, c->coupling, c->d_ATx, y, nullptr,
                       static_cast<unsigned short*>(scratch), U);
   if (c->precision == AFQMC_PREC_BF16 && !c->small)
     return vb_launch<float, false, true>(c, n, c->K, MM, c->K, 0, c->coupling, c->d_A, y, nullptr,

@@ -384,7 +384,8 @@ hipError_t launch_tgt(const afqmc_ctx_s* c, int n, const double* U, double* phiT
 template <int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict__ U,
-                  const double* __restrict__ phi0, double* __restrict__ phiT) {
+                  const unsigned short* __restrict__ Us, const double* __restrict__ phi0,
+                  double* __restrict__ phiT) {
   constexpr int NT = 16 * NTC;
   constexpr int KBM = (16 * KTMAX + 31) / 32;  // k blocks of 32 at most
   const int KB = (MT + 31) / 32;                // k blocks (the last may be padding)
@@ -396,24 +397,44 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   if (s >= n_samples) return;
-  const double* Us = U + (size_t)s * M * M;
+  const double* Usd = U != nullptr ? U + (size_t)s * M * M : nullptr;
   auto xt = [&](int buf, int part, int n, int m) -> unsigned short* {
     return sX + ((size_t)(buf * 2 + part) * NT + n) * XS + m;
   };
 
-  // rows of U: ua[t][j] = U[16 tp + c][32 t + 8 g + j]
+  // rows of U: ua[t][j] = U[16 tp + c][32 t + 8 g + j], from FP64 U or from U
+  // already split ([hi, lo][M][32 KB] BF16: one 16-byte load per part)
   float ua[KBM][8];
   double rs = 0.0;
   const int row = 16 * tp + c;
+  if (Us != nullptr) {
+    const unsigned short* uh = Us + (size_t)s * 2 * M * (32 * KB);
+    const unsigned short* ul = uh + (size_t)M * (32 * KB);
 #pragma unroll
-  for (int t = 0; t < KBM; ++t)
+    for (int t = 0; t < KBM; ++t) {
+      const bool ok = t < KB && row < M;
+      const size_t o = (size_t)min(row, M - 1) * (32 * KB) + 32 * min(t, KB - 1) + 8 * g;
+      const uint4 h = *reinterpret_cast<const uint4*>(uh + o);
+      const uint4 l = *reinterpret_cast<const uint4*>(ul + o);
+      const unsigned hw[4] = {h.x, h.y, h.z, h.w}, lw[4] = {l.x, l.y, l.z, l.w};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int col = 32 * t + 8 * g + j;
-      const double u = (t < KB && row < M && col < M) ? Us[(size_t)row * M + col] : 0.0;
-      ua[t][j] = (float)u;
-      rs += fabs(u);
+      for (int q = 0; q < 4; ++q) {
+        ua[t][2 * q] = ok ? tbf_lo(hw[q]) + tbf_lo(lw[q]) : 0.f;
+        ua[t][2 * q + 1] = ok ? tbf_hi(hw[q]) + tbf_hi(lw[q]) : 0.f;
+        rs += fabs((double)ua[t][2 * q]) + fabs((double)ua[t][2 * q + 1]);
+      }
     }
+  } else {
+#pragma unroll
+    for (int t = 0; t < KBM; ++t)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int col = 32 * t + 8 * g + j;
+        const double u = (t < KB && row < M && col < M) ? Usd[(size_t)row * M + col] : 0.0;
+        ua[t][j] = (float)u;
+        rs += fabs(u);
+      }
+  }
   rs += __shfl_xor(rs, 16, 64);
   rs += __shfl_xor(rs, 32, 64);
   rs = wave_max_full(rs);
@@ -554,7 +575,8 @@ k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict_
 }
 
 template <int KTMAX, int NTC>
-hipError_t launch_tgx(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
+hipError_t launch_tgx(const afqmc_ctx_s* c, int n, const double* U, const unsigned short* Us,
+                      double* phiT) {
   const int NT = 16 * NTC, XS = 32 * ((c->MT + 31) / 32) + 8;
   const size_t lds = ((size_t)4 * NT * XS * 2 + 7) / 8 * 8 + (size_t)2 * KTMAX * sizeof(double);
   auto kern = k_trial_taylor_x3<KTMAX, NTC>;
@@ -562,14 +584,14 @@ hipError_t launch_tgx(const afqmc_ctx_s* c, int n, const double* U, double* phiT
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(n), dim3(64 * (c->MT / 16)), lds, c->stream, n, c->M, c->N, c->MT,
-                     U, c->d_phi0, phiT);
+                     U, Us, c->d_phi0, phiT);
   return hipGetLastError();
 }
 
 template <int KTMAX, int NTC>
 hipError_t launch_tg(const afqmc_ctx_s* c, int n, const double* U, double* phiT) {
   if constexpr (KTMAX <= 8 && NTC <= 2) {
-    if (c->precision == AFQMC_PREC_BF16) return launch_tgx<KTMAX, NTC>(c, n, U, phiT);
+    if (c->precision == AFQMC_PREC_BF16) return launch_tgx<KTMAX, NTC>(c, n, U, nullptr, phiT);
   }
   return c->precision != AFQMC_PREC_FP64 ? launch_tgt<float, KTMAX, NTC>(c, n, U, phiT)
                                          : launch_tgt<double, KTMAX, NTC>(c, n, U, phiT);
@@ -603,11 +625,23 @@ hipError_t launch_trial_build_g(const afqmc_ctx_s* c, int n_samples, const doubl
   if (n_samples <= 0) return hipSuccess;
   if (c->ctrial) return launch_trial_slices(c, n_samples, y, phiT, ubuf);
   if (c->d_Adiag != nullptr) return launch_trial_diag(c, n_samples, y, phiT);
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+  if (c->precision == AFQMC_PREC_BF16 && KT <= 8 && NTC <= 2 && scratch != nullptr &&
+      ubuild_split_ok(c, n_samples, scratch_bytes)) {
+    // U split once by its own build, in the U buffer (4 n M MP <= 8 n M^2 bytes)
+    unsigned short* Us = reinterpret_cast<unsigned short*>(ubuf);
+    const hipError_t e = launch_ubuild_split(c, n_samples, y, Us, scratch);
+    if (e != hipSuccess) return e;
+#define AFQMC_X(KM, NC) \
+  if (KT <= KM && NTC == NC) return launch_tgx<KM, NC>(c, n_samples, nullptr, Us, phiT);
+    AFQMC_X(4, 1) AFQMC_X(6, 1) AFQMC_X(8, 1)
+    AFQMC_X(4, 2) AFQMC_X(6, 2) AFQMC_X(8, 2)
+#undef AFQMC_X
+  }
   {
     const hipError_t e = launch_ubuild(c, n_samples, y, ubuf, scratch, scratch_bytes);
     if (e != hipSuccess) return e;
   }
-  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
 #define AFQMC_T(KM, NC) \
   if (KT <= KM && NTC == NC) return launch_tg<KM, NC>(c, n_samples, ubuf, phiT);
   AFQMC_T(4, 1) AFQMC_T(6, 1) AFQMC_T(8, 1) AFQMC_T(10, 1)
