@@ -724,10 +724,18 @@ afqmc_status afqmc_propagate(afqmc_ctx c, int32_t nw, void* phi, const double* x
   double* ph;
   PHI_IN(c, nw, phi, &ph);
   // the trial build's U buffer is free during the move
-  HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat,
-                           ws_ptr<double>(c, L.ubuf), L.qrshift - L.ubuf),
-          "vbuild");
-  HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph), "taylor");
+  void* scr = ws_ptr<void>(c, L.ubuf);
+  const size_t scr_bytes = L.qrshift - L.ubuf;
+  if (vbuild_split_ok(c, nw, scr_bytes)) {  // V stored split (8 nw M MP <= 16 nw M^2 bytes)
+    unsigned short* Vs = ws_ptr<unsigned short>(c, L.vmat);
+    HIPCALL(c, launch_vbuild_split(c, nw, xi, static_cast<const double*>(xbar), Vs, scr), "vbuild");
+    HIPCALL(c, launch_taylor_split(c, nw, Vs, ph), "taylor");
+  } else {
+    HIPCALL(c, launch_vbuild(c, nw, xi, static_cast<const double*>(xbar), vmat, scr, scr_bytes),
+            "vbuild");
+    HIPCALL(c, c->small ? launch_taylor(c, nw, vmat, ph) : launch_taylor_g(c, nw, vmat, ph),
+            "taylor");
+  }
   st = phi_out(c, nw, ph, phi);
   if (st != AFQMC_OK) return st;
   if (c->c64) PHI_IN(c, nw, phi, &ph);  // the ratio is that of the stored (rounded) walkers

@@ -197,6 +197,13 @@ hipError_t launch_ubuild(const afqmc_ctx_s* c, int n, const double* y, double* U
 // with MP = M rounded up to 32, when ubuild_split_ok (the split generator copy
 // exists and scratch holds 4 n KP bytes)
 bool ubuild_split_ok(const afqmc_ctx_s* c, int n, size_t scratch_bytes);
+// V split for the split-BF16 propagation, Vs [nw][4][M][MP], and that
+// propagation, when vbuild_split_ok (a BF16 context on the workgroup kernels
+// and scratch of 8 nw GP bytes)
+bool vbuild_split_ok(const afqmc_ctx_s* c, int nw, size_t scratch_bytes);
+hipError_t launch_vbuild_split(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
+                               unsigned short* Vs, void* scratch);
+hipError_t launch_taylor_split(const afqmc_ctx_s* c, int nw, const unsigned short* Vs, double* phi);
 hipError_t launch_ubuild_split(const afqmc_ctx_s* c, int n, const double* y, unsigned short* Us,
                                void* scratch);
 hipError_t launch_vbuild_gen(const afqmc_ctx_s* c, int n, int G, int xs, double sqrt_s,

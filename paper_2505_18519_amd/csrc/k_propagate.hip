@@ -381,8 +381,10 @@ hipError_t vb_launch(const afqmc_ctx_s* c, int n, int G, int MM, int xs, int xbs
 // walker or entry) is one 16-byte read.  NA = 1 (U) stores a real output.
 // The output rows (M entries) sit MP apart (MP = M, or with SPLIT, for the
 // split-BF16 trial series, M rounded up to 32: the entries past M are zero);
-// SPLIT stores U itself split, [row][hi, lo][M][MP] BF16, half the bytes of
-// FP64 and in the A-operand form the series loads.
+// SPLIT stores U itself split, [row][hi, lo][M][MP] BF16, or V as its real
+// part and minus its imaginary part split, [walker][Re hi, Re lo, -Im hi,
+// -Im lo][M][MP]: half the bytes of FP64 and in the A-operand form that the
+// trial series and the propagation load.
 constexpr int VX_KC = 32, VX_E = 128, VX_RS = VX_KC + 8;
 template <int NA>
 constexpr int vx_sb0() {  // start of the L planes in a buffer (16-bit units)
@@ -396,7 +398,7 @@ template <int NA, bool SPLIT>
 __global__ void __launch_bounds__(256)
 k_vbuild_bx(int nw, int GP, int M, int MP, double sqrt_tau, const unsigned short* __restrict__ LT,
             const unsigned short* __restrict__ cf, void* __restrict__ out) {
-  static_assert(!SPLIT || NA == 1, "split output: real U only");
+
   constexpr int VX_SB0 = vx_sb0<NA>(), VX_CH = vx_ch<NA>();
   const int MM = M * M, ET = M * MP;  // entries of L (or A_k) and of an output row
   extern __shared__ double smem[];
@@ -498,11 +500,16 @@ k_vbuild_bx(int nw, int GP, int M, int MP, double sqrt_tau, const unsigned short
         const int w = wb + 32 * wh + 16 * wt + 4 * g + r, e = eb + 64 * eh + 16 * et + c;
         if (w >= nw || e >= ET) continue;
         if constexpr (SPLIT) {
-          unsigned short* us = static_cast<unsigned short*>(out) + (size_t)w * 2 * ET + e;
-          const float u = (float)(sqrt_tau * (double)acc[0][wt][et][r]);
-          const unsigned h = tpk_bf16(u, 0.f);
-          us[0] = (unsigned short)(h & 0xffffu);
-          us[ET] = (unsigned short)(tpk_bf16(u - tbf_lo(h), 0.f) & 0xffffu);
+          // U; or V_re = -sqrt(tau) Q and -V_im = -sqrt(tau) R
+          unsigned short* us = static_cast<unsigned short*>(out) + (size_t)w * 2 * NA * ET + e;
+#pragma unroll
+          for (int p = 0; p < NA; ++p) {
+            const double x = (double)acc[NA - 1 - p][wt][et][r];
+            const float u = (float)(NA == 1 ? sqrt_tau * x : -sqrt_tau * x);
+            const unsigned h = tpk_bf16(u, 0.f);
+            us[(2 * p) * ET] = (unsigned short)(h & 0xffffu);
+            us[(2 * p + 1) * ET] = (unsigned short)(tpk_bf16(u - tbf_lo(h), 0.f) & 0xffffu);
+          }
         } else if constexpr (NA == 1) {
           static_cast<double*>(out)[(size_t)w * ET + e] = sqrt_tau * (double)acc[0][wt][et][r];
         } else {
@@ -841,7 +848,8 @@ k_taylor_g(int n, int M, int N, int MT, int n_taylor, int spins, const double* _
 template <int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
 k_taylor_x3(int nw, int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
-            const double* __restrict__ Eh, double* __restrict__ phi) {
+            const unsigned short* __restrict__ Vs, const double* __restrict__ Eh,
+            double* __restrict__ phi) {
   constexpr int NT = 16 * NTC;
   constexpr int KBM = (16 * KTMAX + 31) / 32;  // k blocks of 32 at most
   const int KB = (MT + 31) / 32;                // k blocks (the last may be padding)
@@ -853,28 +861,47 @@ k_taylor_x3(int nw, int M, int N, int MT, int n_taylor, const double* __restrict
   const int tp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const int row = 16 * tp + c;
-  const double* V = vmat + (size_t)w * M * M * 2;
+  const double* V = vmat != nullptr ? vmat + (size_t)w * M * M * 2 : nullptr;
   double* ph = phi + ((size_t)w * 2 + sp) * M * N * 2;
   auto yt = [&](int buf, int part, int n, int m) -> unsigned short* {
     return sY + ((size_t)(buf * 4 + part) * NT + n) * XS + m;
   };
 
   tsx8 vrh[KBM], vrl[KBM], vih[KBM], vil[KBM];  // V_re and -V_im, hi and lo
+  if (Vs != nullptr) {  // V stored split: [Re hi, Re lo, -Im hi, -Im lo][M][32 KB]
+    const size_t PL = (size_t)M * (32 * KB);
+    const unsigned short* vb = Vs + (size_t)w * 4 * PL;
+    const tsx8 z = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < KBM; ++t) {
-    float re[8], nim[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int col = 32 * t + 8 * g + j;
-      const bool ok = t < KB && row < M && col < M;
-      // clamped, unconditional loads masked afterwards: all in flight together
-      const double2 v = *reinterpret_cast<const double2*>(
-          V + ((size_t)min(row, M - 1) * M + min(col, M - 1)) * 2);
-      re[j] = (float)keep_if(v.x, ok);
-      nim[j] = (float)keep_if(-v.y, ok);
+    for (int t = 0; t < KBM; ++t) {
+      const bool ok = t < KB && row < M;
+      const size_t o = (size_t)min(row, M - 1) * (32 * KB) + 32 * min(t, KB - 1) + 8 * g;
+      const tsx8 a0 = *reinterpret_cast<const tsx8*>(vb + o);
+      const tsx8 a1 = *reinterpret_cast<const tsx8*>(vb + PL + o);
+      const tsx8 a2 = *reinterpret_cast<const tsx8*>(vb + 2 * PL + o);
+      const tsx8 a3 = *reinterpret_cast<const tsx8*>(vb + 3 * PL + o);
+      vrh[t] = ok ? a0 : z;
+      vrl[t] = ok ? a1 : z;
+      vih[t] = ok ? a2 : z;
+      vil[t] = ok ? a3 : z;
     }
-    split8(re, vrh[t], vrl[t]);
-    split8(nim, vih[t], vil[t]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < KBM; ++t) {
+      float re[8], nim[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int col = 32 * t + 8 * g + j;
+        const bool ok = t < KB && row < M && col < M;
+        // clamped, unconditional loads masked afterwards: all in flight together
+        const double2 v = *reinterpret_cast<const double2*>(
+            V + ((size_t)min(row, M - 1) * M + min(col, M - 1)) * 2);
+        re[j] = (float)keep_if(v.x, ok);
+        nim[j] = (float)keep_if(-v.y, ok);
+      }
+      split8(re, vrh[t], vrl[t]);
+      split8(nim, vih[t], vil[t]);
+    }
   }
   // both buffers zero (rows past MT are read as padding and never written),
   // then phi into buffer 0
@@ -991,7 +1018,8 @@ k_taylor_x3(int nw, int M, int N, int MT, int n_taylor, const double* __restrict
 }
 
 template <int KTMAX, int NTC>
-hipError_t launch_taylor_x3(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
+hipError_t launch_taylor_x3(const afqmc_ctx_s* c, int nw, const double* vmat,
+                            const unsigned short* Vs, double* phi) {
   const int NT = 16 * NTC, XS = 32 * ((c->MT + 31) / 32) + 8;
   const size_t lds = (size_t)8 * NT * XS * sizeof(unsigned short);
   auto kern = k_taylor_x3<KTMAX, NTC>;
@@ -999,7 +1027,7 @@ hipError_t launch_taylor_x3(const afqmc_ctx_s* c, int nw, const double* vmat, do
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(16 * ((nw + 7) / 8)), dim3(64 * (c->MT / 16)), lds, c->stream, nw,
-                     c->M, c->N, c->MT, c->n_taylor, vmat, c->d_Eh, phi);
+                     c->M, c->N, c->MT, c->n_taylor, vmat, Vs, c->d_Eh, phi);
   return hipGetLastError();
 }
 
@@ -1050,13 +1078,25 @@ hipError_t launch_taylor_g_gen(const afqmc_ctx_s* c, int n, int spins, int n_tay
   return taylor_g_dispatch<double>(c, n, spins, n_taylor, vmat, El, Er, src, src_ws, dst);
 }
 
+// the split-BF16 propagation from V stored split (launch_vbuild_split)
+hipError_t launch_taylor_split(const afqmc_ctx_s* c, int nw, const unsigned short* Vs, double* phi) {
+  if (nw <= 0) return hipSuccess;
+  const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
+#define AFQMC_X(KM, NC) \
+  if (KT <= KM && NTC == NC) return launch_taylor_x3<KM, NC>(c, nw, nullptr, Vs, phi);
+  AFQMC_X(4, 1) AFQMC_X(6, 1) AFQMC_X(8, 1)
+  AFQMC_X(4, 2) AFQMC_X(6, 2) AFQMC_X(8, 2)
+#undef AFQMC_X
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, double* phi) {
   if (nw <= 0) return hipSuccess;
   if (c->precision == AFQMC_PREC_BF16 && !c->ctrial) {
     // split-BF16 products (BF16 contexts take M <= 128, N <= 32)
     const int KT = c->MT / 16, NTC = (c->N + 15) / 16;
 #define AFQMC_X(KM, NC) \
-  if (KT <= KM && NTC == NC) return launch_taylor_x3<KM, NC>(c, nw, vmat, phi);
+  if (KT <= KM && NTC == NC) return launch_taylor_x3<KM, NC>(c, nw, vmat, nullptr, phi);
     AFQMC_X(4, 1) AFQMC_X(6, 1) AFQMC_X(8, 1)
     AFQMC_X(4, 2) AFQMC_X(6, 2) AFQMC_X(8, 2)
 #undef AFQMC_X
@@ -1064,6 +1104,20 @@ hipError_t launch_taylor_g(const afqmc_ctx_s* c, int nw, const double* vmat, dou
   if (prop_f32(c))
     return taylor_g_dispatch<float>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
   return taylor_g_dispatch<double>(c, nw, 2, c->n_taylor, vmat, c->d_Eh, c->d_Eh, phi, 2, phi);
+}
+
+// V split for the split-BF16 propagation of BF16 contexts: Vs [nw][Re hi, Re lo,
+// -Im hi, -Im lo][M][MP] BF16, MP = M rounded up to 32 (zero past column M);
+// scratch holds 8 nw GP bytes of split coefficients
+bool vbuild_split_ok(const afqmc_ctx_s* c, int nw, size_t scratch_bytes) {
+  return c->d_LTx != nullptr && c->precision == AFQMC_PREC_BF16 && !c->small && !c->ctrial &&
+         c->MT / 16 <= 8 && (c->N + 15) / 16 <= 2 && scratch_bytes >= (size_t)8 * nw * c->GP;
+}
+hipError_t launch_vbuild_split(const afqmc_ctx_s* c, int nw, const double* xi, const double* xbar,
+                               unsigned short* Vs, void* scratch) {
+  if (nw <= 0) return hipSuccess;
+  return vbx_run<2, true>(c, nw, c->G, c->GP, (c->M + 31) / 32 * 32, sqrt(c->dtau), c->d_LTx, xi,
+                          xbar, static_cast<unsigned short*>(scratch), Vs);
 }
 
 // U split for the split-BF16 trial series of BF16 contexts: Us [n][hi, lo][M][MP]
