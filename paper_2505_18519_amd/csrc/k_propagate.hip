@@ -846,7 +846,7 @@ k_taylor_g(int n, int M, int N, int MT, int n_taylor, int spins, const double* _
 // launches apart, on the same XCD (workgroups go round-robin over the 8), so
 // the second finds V in that XCD's L2.
 template <int KTMAX, int NTC>
-__global__ void __launch_bounds__(64 * KTMAX)
+__global__ void __launch_bounds__(64 * KTMAX) __attribute__((amdgpu_waves_per_eu(4)))
 k_taylor_x3(int nw, int M, int N, int MT, int n_taylor, const double* __restrict__ vmat,
             const unsigned short* __restrict__ Vs, const double* __restrict__ Eh,
             double* __restrict__ phi) {

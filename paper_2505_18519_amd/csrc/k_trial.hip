@@ -382,7 +382,7 @@ hipError_t launch_tgt(const afqmc_ctx_s* c, int n, const double* U, double* phiT
 // largest sum entry (the products themselves carry about 2^-17).  One barrier
 // per term.
 template <int KTMAX, int NTC>
-__global__ void __launch_bounds__(64 * KTMAX)
+__global__ void __launch_bounds__(64 * KTMAX) __attribute__((amdgpu_waves_per_eu(6)))
 k_trial_taylor_x3(int n_samples, int M, int N, int MT, const double* __restrict__ U,
                   const unsigned short* __restrict__ Us, const double* __restrict__ phi0,
                   double* __restrict__ phiT) {
