@@ -713,8 +713,8 @@ BF16_PROP_TOL = 5e-5
 @pytest.mark.parametrize("case", ["gauss-M32-N32", "gauss-M70-N1", "gauss-M72-N20-ragged",
                                   "gauss-M80-N27-ragged", "gauss-M96-N24", "gauss-M128-N32"])
 def test_bf16_contexts_propagate_on_split_bf16_products(case):
-    """The move of a BF16 context (V build on FP32 products, T_n(V) and the
-    one-body factors on split-BF16 products) from the oracle's trial and
+    """The move of a BF16 context (V build, T_n(V) and the one-body factors on
+    split-BF16 products, V stored split between them) from the oracle's trial and
     x-bar: phi' within 5e-5 normwise of the FP64 oracle and further from it
     than FP32 products would be; the log-overlaps of the GPU's phi' to the
     FP64 bound against the oracle's LU of the same matrices; the weights
