@@ -218,6 +218,7 @@ namespace {
 
 template <typename T, int KTMAX, int NTC>
 __global__ void __launch_bounds__(64 * KTMAX)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
 k_trial_taylor_g(int n_samples, int M, int N, int MT, const double* __restrict__ U,
                  const double* __restrict__ phi0, double* __restrict__ phiT) {
   typedef MM<T> mm;
